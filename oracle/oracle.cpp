@@ -1,0 +1,158 @@
+// Oracle: a plain, sequential CPU MapReduce used ONLY as test infrastructure.
+//
+// Nothing in the product path may include, link or call this file. It shares
+// no code with the GPU library: tests, the smoke check and the CPU-baseline leg
+// of the benchmark call it through ctypes.
+//
+// What it computes follows the paper's programming model (Section II-A): the
+// map function is applied to every element of the input array and emits
+// intermediate (key, value) pairs; the reduce function is then applied to all
+// pairs that share a key; the result pairs are output in key order (ordering is
+// optional in the paper; it is always done here).
+//
+// The reduce containers are the two the paper names (Section III-A): an
+// ordered associative container (std::map) for arbitrary keys, and a plain
+// array for integer keys in a fixed range (the RGB histogram). No blocking,
+// fusion or reordering is applied: one element at a time, in input order.
+//
+// Readings of points the paper leaves open (the same readings the GPU path
+// implements):
+//   * A word is a maximal run of non-separator bytes. Separators are the six
+//     ASCII whitespace bytes 0x09..0x0D and 0x20. Every other byte (including
+//     NUL and bytes >= 0x80) is a word byte. No case folding.
+//   * Optional record offsets u64[n+1] cut the input into records
+//     [off[i], off[i+1]); a record boundary ends a word. Bytes outside
+//     [off[0], off[n]) are ignored. With no offsets the input is one record.
+//   * Word keys are ordered bytewise as unsigned bytes, a proper prefix first.
+//   * COUNT values are reported as 64-bit here; callers compare against the
+//     32-bit GPU output and flag counts above 2^32-1.
+#include <cstdint>
+#include <cstring>
+#include <map>
+#include <vector>
+
+namespace {
+
+bool is_sep(uint8_t b) { return b == 0x20 || (b >= 0x09 && b <= 0x0D); }
+
+struct WordsResult {
+  std::vector<uint8_t> key_bytes;
+  std::vector<uint64_t> key_offsets;  // n+1
+  std::vector<uint64_t> values;       // n
+};
+
+struct U32Result {
+  std::vector<uint32_t> keys;
+  std::vector<uint64_t> values;
+};
+
+}  // namespace
+
+extern "C" {
+
+// ---------------------------------------------------------------------------
+// Word count (Section II-A model; hash-table container of Section III-A).
+// map: for each word in each record emit (word, 1); reduce: sum per word.
+// Returns an opaque handle, or NULL when the record offsets are malformed
+// (not non-decreasing, or past the end of the input).
+// ---------------------------------------------------------------------------
+void* oracle_words_run(const uint8_t* buf, uint64_t n, const uint64_t* rec_off, uint64_t n_rec) {
+  std::map<std::vector<uint8_t>, uint64_t> m;
+  std::vector<std::pair<uint64_t, uint64_t>> records;
+  if (rec_off == nullptr) {
+    records.push_back({0, n});
+  } else {
+    for (uint64_t r = 0; r < n_rec; ++r) {
+      if (rec_off[r] > rec_off[r + 1] || rec_off[r + 1] > n) return nullptr;
+      records.push_back({rec_off[r], rec_off[r + 1]});
+    }
+  }
+  for (auto& rec : records) {
+    uint64_t i = rec.first, e = rec.second;
+    while (i < e) {
+      while (i < e && is_sep(buf[i])) ++i;          // skip separators
+      uint64_t j = i;
+      while (j < e && !is_sep(buf[j])) ++j;         // one word [i, j)
+      if (j > i) {
+        std::vector<uint8_t> key(buf + i, buf + j);  // map emits (word, 1)
+        m[key] += 1;                                 // reduce: sum
+      }
+      i = j;
+    }
+  }
+  auto* r = new WordsResult();
+  r->key_offsets.push_back(0);
+  for (auto& kv : m) {  // std::map iterates in key order
+    r->key_bytes.insert(r->key_bytes.end(), kv.first.begin(), kv.first.end());
+    r->key_offsets.push_back(r->key_bytes.size());
+    r->values.push_back(kv.second);
+  }
+  return r;
+}
+
+uint64_t oracle_words_n(void* h) { return static_cast<WordsResult*>(h)->values.size(); }
+uint64_t oracle_words_bytes(void* h) { return static_cast<WordsResult*>(h)->key_bytes.size(); }
+
+void oracle_words_copy(void* h, uint8_t* key_bytes, uint64_t* key_offsets, uint64_t* values) {
+  auto* r = static_cast<WordsResult*>(h);
+  if (!r->key_bytes.empty()) std::memcpy(key_bytes, r->key_bytes.data(), r->key_bytes.size());
+  std::memcpy(key_offsets, r->key_offsets.data(), r->key_offsets.size() * sizeof(uint64_t));
+  if (!r->values.empty()) std::memcpy(values, r->values.data(), r->values.size() * sizeof(uint64_t));
+}
+
+void oracle_words_free(void* h) { delete static_cast<WordsResult*>(h); }
+
+// ---------------------------------------------------------------------------
+// Integer keys (Section II-A model; containers of Section III-A).
+// map: element i emits (keys[i], vals[i]) (vals == NULL means value 1);
+// reduce op: 0 = COUNT, 1 = SUM, 2 = MIN, 3 = MAX.
+// ---------------------------------------------------------------------------
+void* oracle_u32_run(const uint32_t* keys, const uint32_t* vals, uint64_t n, int op) {
+  std::map<uint32_t, uint64_t> m;
+  for (uint64_t i = 0; i < n; ++i) {
+    uint64_t v = vals ? vals[i] : 1;
+    auto it = m.find(keys[i]);
+    if (it == m.end()) {
+      m.emplace(keys[i], op == 0 ? 1 : v);
+      continue;
+    }
+    switch (op) {
+      case 0: it->second += 1; break;
+      case 1: it->second += v; break;
+      case 2: if (v < it->second) it->second = v; break;
+      case 3: if (v > it->second) it->second = v; break;
+    }
+  }
+  auto* r = new U32Result();
+  for (auto& kv : m) {
+    r->keys.push_back(kv.first);
+    r->values.push_back(kv.second);
+  }
+  return r;
+}
+
+uint64_t oracle_u32_n(void* h) { return static_cast<U32Result*>(h)->keys.size(); }
+
+void oracle_u32_copy(void* h, uint32_t* keys, uint64_t* values) {
+  auto* r = static_cast<U32Result*>(h);
+  if (!r->keys.empty()) {
+    std::memcpy(keys, r->keys.data(), r->keys.size() * sizeof(uint32_t));
+    std::memcpy(values, r->values.data(), r->values.size() * sizeof(uint64_t));
+  }
+}
+
+void oracle_u32_free(void* h) { delete static_cast<U32Result*>(h); }
+
+// ---------------------------------------------------------------------------
+// RGB histogram (Table of benchmark applications: Histogram, array container).
+// Pixel p has bytes (R, G, B) at 3p, 3p+1, 3p+2; map emits ((c, byte), 1) for
+// each channel c; reduce sums into a 3 x 256 array. A trailing partial pixel
+// is not a pixel; callers reject lengths that are not a multiple of 3.
+// ---------------------------------------------------------------------------
+void oracle_rgb_run(const uint8_t* buf, uint64_t n, uint64_t* bins /* [3*256] */) {
+  for (int i = 0; i < 3 * 256; ++i) bins[i] = 0;
+  for (uint64_t p = 0; p + 3 <= n; p += 3)
+    for (int c = 0; c < 3; ++c) bins[c * 256 + buf[p + c]] += 1;
+}
+
+}  // extern "C"
