@@ -1,0 +1,241 @@
+/*
+ * mr.h - C ABI of an MI355X (gfx950) MapReduce hot path.
+ *
+ * The operation is the MapReduce programming model of Section II-A of
+ * "Optimizing the MapReduce Framework on Intel Xeon Phi Coprocessor"
+ * (arXiv 1309.0215): a map function is applied to every element of an input
+ * array and emits intermediate (key, value) pairs; a reduce function combines
+ * all pairs with the same key; the resulting pairs are output, ordered.
+ * Reduction goes into one of the two containers of Section III-A: a hash table
+ * for arbitrary keys, or an array for integer keys in a fixed range. Large
+ * arrays are updated in place with atomics instead of per-worker copies
+ * (Section III-E); small ones are privatised per workgroup in LDS.
+ *
+ * Conventions for every entry point:
+ *   - Every call returns an mr_status; no exception or abort crosses the ABI.
+ *     mr_last_error() returns a thread-local text with details of the last
+ *     failure on the calling thread.
+ *   - "device pointer" means memory on the job's GPU (hipMalloc or a torch
+ *     CUDA tensor). "host pointer" means ordinary process memory.
+ *   - The caller owns every buffer it passes in. The library owns the
+ *     workspace it allocates for a job (device memory, grown on demand, kept
+ *     between calls, freed by mr_job_destroy).
+ *   - Calls on one mr_job are not thread-safe; use one job per host thread.
+ *   - mr_run and mr_batch_run enqueue on the job's stream and synchronise that
+ *     stream before returning.
+ */
+#ifndef MR_H_
+#define MR_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t mr_status;
+enum {
+  MR_OK = 0,
+  MR_ERR_INVALID_ARG = -1, /* malformed arguments; nothing was launched */
+  MR_ERR_CAPACITY = -2,    /* an output buffer is too small; required sizes are set in mr_output */
+  MR_ERR_OVERFLOW = -3,    /* a reduced value does not fit its output type */
+  MR_ERR_HIP = -4,         /* a HIP runtime call failed */
+  MR_ERR_UNSUPPORTED = -5, /* valid but unsupported combination or size */
+  MR_ERR_NO_DEVICE = -6    /* no usable gfx950 device */
+};
+
+/* Map functions built into the library (Table "Benchmark applications" and
+ * the workloads built on it). */
+typedef enum {
+  /* Word count. Input: bytes. A word is a maximal run of bytes that are not
+   * one of the six ASCII whitespace bytes 0x09-0x0D, 0x20. Optional record
+   * offsets cut the input into records; a record boundary ends a word.
+   * Output: distinct words in unsigned bytewise order (a proper prefix
+   * first) with uint32 counts. */
+  MR_MAP_WORDS = 0,
+  /* Integer keys. Input: little-endian uint32 keys; each emits (key, 1).
+   * Output: distinct keys ascending with uint32 counts. */
+  MR_MAP_U32_KEYS = 1,
+  /* Integer key-value pairs. Input: little-endian (uint32 key, uint32 value)
+   * pairs. Output: distinct keys ascending; SUM gives uint64 values, MIN and
+   * MAX give uint32 values, COUNT gives uint32 values. */
+  MR_MAP_U32_KV = 2,
+  /* RGB histogram. Input: interleaved 8-bit R,G,B pixels (length a multiple
+   * of 3). Output: 768 uint64 bins, channel-major: bin c*256+v counts bytes
+   * of channel c equal to v. */
+  MR_MAP_RGB_HIST = 3,
+  /* One k-means (Lloyd) step. Input: float32 points [n][d] row-major.
+   * Output: assignments int32[n], per-cluster float32 sums [k][d], uint32
+   * counts [k] and new centroids [k][d] (sum / count; an empty cluster keeps
+   * its previous centroid). */
+  MR_MAP_KMEANS = 4
+} mr_map_kind;
+
+typedef enum { MR_REDUCE_COUNT = 0, MR_REDUCE_SUM = 1, MR_REDUCE_MIN = 2, MR_REDUCE_MAX = 3 } mr_reduce_op;
+
+/* Reduce container strategy. RULE applies the paper's rule (Section III-E:
+ * keep per-worker arrays only while each is small, otherwise one shared
+ * array with atomics; hash table for keys without a fixed range). LEARNED
+ * uses the trained selector when weights are loaded, otherwise RULE. The
+ * other four force a container; forcing one that is infeasible for the job
+ * (an array without a declared key range) returns MR_ERR_UNSUPPORTED. */
+typedef enum {
+  MR_STRAT_RULE = 0,
+  MR_STRAT_LEARNED = 1,
+  MR_STRAT_LDS_ARRAY = 2,    /* per-workgroup LDS array, partials merged without atomics */
+  MR_STRAT_GLOBAL_ARRAY = 3, /* one global array updated with atomics */
+  MR_STRAT_HASH = 4,         /* LDS hash cache per workgroup in front of a global open-addressing table */
+  MR_STRAT_SORT = 5          /* radix sort of all pairs, then a segmented reduce */
+} mr_strategy;
+
+typedef struct mr_job mr_job;
+
+typedef struct {
+  int32_t device;          /* HIP device ordinal */
+  void* stream;            /* hipStream_t to enqueue on; NULL = the null stream */
+  mr_strategy strategy;    /* reduce container choice for integer-key jobs */
+  uint32_t lds_slots;      /* slots of the per-workgroup LDS hash cache (power of two, 0 = default) */
+  uint32_t max_load_pct;   /* global hash table load-factor limit in percent (0 = default 50) */
+  uint32_t tile_bytes;     /* input bytes per work item for the word map (0 = default) */
+  uint32_t debug_hash;     /* 0 = normal; 1 = force all keys to collide (tests only) */
+  uint64_t table_slots;    /* initial global hash table slots (power of two, 0 = planned) */
+  uint32_t timing;         /* 1 = also time the map kernel alone with HIP events (stats.map_ms) */
+  /* k-means only: dimensions, clusters and the initial centroids (device, float32 [k][d]) */
+  uint32_t km_d;
+  uint32_t km_k;
+  const float* km_centroids;
+} mr_job_config;
+
+typedef struct {
+  uint32_t strategy_used;  /* mr_strategy actually run */
+  uint32_t retries;        /* hash-table regrowths */
+  uint64_t table_slots;    /* final global hash table slots */
+  uint64_t n_items;        /* number of map elements (words, keys, pixels, points) */
+  float gpu_ms;            /* device time of the job's kernels (HIP events) */
+  float map_ms;            /* device time of the map (dominant) kernel alone; needs cfg.timing */
+  uint32_t km_rechecked;   /* k-means: points whose float32 decision was re-made in float64 */
+  uint32_t selector_used;  /* 1 when the learned selector chose the strategy */
+} mr_stats;
+
+/* Output buffers (device pointers, caller-allocated) and their capacities.
+ * Which fields are used depends on the map kind:
+ *   WORDS:    key_bytes[cap_key_bytes], key_offsets[cap_keys + 1] (uint64),
+ *             values[cap_keys] (uint32 counts)
+ *   U32_*:    keys[cap_keys] (uint32), values[cap_keys] (uint32, or uint64 for SUM)
+ *   RGB_HIST: values[768] (uint64)
+ *   KMEANS:   assign[n] (int32), sums[k*d] (float32), counts[k] (uint32),
+ *             centroids[k*d] (float32)
+ * On return n_keys and key_bytes_used hold the result sizes. When they
+ * exceed the capacities the call returns MR_ERR_CAPACITY, leaves the output
+ * buffers unspecified and keeps the required sizes here, so the caller can
+ * grow its buffers and call again. */
+typedef struct {
+  void* keys;
+  uint8_t* key_bytes;
+  uint64_t* key_offsets;
+  void* values;
+  int32_t* assign;
+  float* sums;
+  uint32_t* counts;
+  float* centroids;
+  uint64_t cap_keys;
+  uint64_t cap_key_bytes;
+  uint64_t n_keys;
+  uint64_t key_bytes_used;
+  mr_status status; /* per-item status for mr_batch_run */
+  mr_stats stats;
+} mr_output;
+
+/* Status text ("MR_OK", ...). Never NULL. */
+const char* mr_status_str(mr_status s);
+
+/* Details of the last failure on this thread ("" if none). Never NULL. */
+const char* mr_last_error(void);
+
+/* Create a job bound to cfg->device and cfg->stream. cfg is copied; for
+ * k-means the initial centroids are copied from device memory at creation.
+ * Errors: MR_ERR_INVALID_ARG (NULL pointers, bad sizes), MR_ERR_NO_DEVICE. */
+mr_status mr_job_create(const mr_job_config* cfg, mr_job** out);
+
+/* Free the job and its device workspace. NULL is accepted. */
+mr_status mr_job_destroy(mr_job* job);
+
+/* Run one MapReduce job over d_input (device pointer, input_bytes bytes,
+ * read only). d_record_offsets (device pointer, uint64[n_records + 1],
+ * non-decreasing, last <= input_bytes) is only valid for MR_MAP_WORDS; pass
+ * NULL for one record. Results go to *out (see mr_output).
+ * Errors: MR_ERR_INVALID_ARG (bad pointers, input length not a multiple of
+ * the element size, malformed record offsets, unsupported kind/op pair),
+ * MR_ERR_CAPACITY, MR_ERR_UNSUPPORTED (word inputs of 4 GiB or more; integer
+ * inputs of 2^32 or more elements; a forced array strategy without a key
+ * range), MR_ERR_HIP. key_range (0 = undeclared) declares that every uint32
+ * key is < key_range, which makes the array containers feasible. Keys at or
+ * above a declared range make the call fail with MR_ERR_INVALID_ARG. */
+mr_status mr_run(mr_job* job, mr_map_kind kind, mr_reduce_op op, const void* d_input, uint64_t input_bytes,
+                 const uint64_t* d_record_offsets, uint64_t n_records, uint64_t key_range, mr_output* out);
+
+/* One item of a batch (device pointers as in mr_run). */
+typedef struct {
+  mr_map_kind kind;
+  mr_reduce_op op;
+  const void* d_input;
+  uint64_t input_bytes;
+  const uint64_t* d_record_offsets;
+  uint64_t n_records;
+  uint64_t key_range;
+} mr_batch_item;
+
+/* Run many independent word-count jobs (MR_MAP_WORDS, MR_REDUCE_COUNT) in
+ * one pass: one persistent map launch over a device work list of
+ * (job, tile) items, then batched compaction, sort and output, captured in a
+ * HIP graph that is replayed while the batch layout is unchanged. outs[i]
+ * receives job i's result exactly as mr_run would produce it, and
+ * outs[i].status its status. Returns MR_OK, or the first failing status. */
+mr_status mr_batch_run(mr_job* job, const mr_batch_item* items, uint32_t n_items, mr_output* outs);
+
+/* --------------------------------------------------------------------------
+ * Reduce-strategy selector. Features of a job are computed on the GPU from a
+ * sample of its input (mr_job_features). A 12-64-64-4 ReLU network predicts
+ * the standardised log time of each of the four containers; the feasible
+ * container with the lowest prediction is chosen.
+ * -------------------------------------------------------------------------- */
+
+#define MR_N_FEATURES 12
+#define MR_N_STRATS 4
+#define MR_MLP_PARAMS 5252
+
+/* Compute the 12 selector features of a job into feats (host float[12]). */
+mr_status mr_job_features(mr_job* job, mr_map_kind kind, mr_reduce_op op, const void* d_input, uint64_t input_bytes,
+                          uint64_t key_range, float* feats);
+
+/* Load trained selector weights: params (host float[5252]: W1[64][12], b1[64],
+ * W2[64][64], b2[64], W3[4][64], b3[4]), feature mean and scale (host
+ * float[12] each; the network sees (f - mean) / scale), and the feature
+ * range seen in training (host float[12] lo and hi; outside it the rule is
+ * used). Passing params = NULL unloads the selector. */
+mr_status mr_selector_set(mr_job* job, const float* params, const float* feat_mean, const float* feat_scale,
+                          const float* feat_lo, const float* feat_hi);
+
+/* Predicted standardised log times (host float[4]) for host features feats. */
+mr_status mr_selector_predict(mr_job* job, const float* feats, float* pred);
+
+/* Device kernels of the selector network, exposed for training on the GPU.
+ * All pointers are device pointers to float32.
+ *   mr_mlp_forward: X[B][12] -> Y[B][4]; H1 and H2 ([B][64] each) receive the
+ *     post-ReLU activations for the backward pass.
+ *   mr_mlp_loss_backward: masked mean squared error of Y against T with mask
+ *     M ([B][4] each); writes loss[1] and the gradient grad[5252] (same
+ *     layout as params).
+ *   mr_mlp_adam: one bias-corrected Adam step (step = 1, 2, ...) on params
+ *     with first and second moments m, v ([5252] each). */
+mr_status mr_mlp_forward(mr_job* job, const float* params, const float* X, uint32_t B, float* H1, float* H2, float* Y);
+mr_status mr_mlp_loss_backward(mr_job* job, const float* params, const float* X, const float* H1, const float* H2,
+                               const float* Y, const float* T, const float* M, uint32_t B, float* loss, float* grad);
+mr_status mr_mlp_adam(mr_job* job, float* params, const float* grad, float* m, float* v, uint32_t step, float lr,
+                      float beta1, float beta2, float eps);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MR_H_ */

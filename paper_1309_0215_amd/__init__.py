@@ -1,0 +1,223 @@
+"""MI355X (gfx950) MapReduce hot path: thin Python binding over libmr.so.
+
+Every step of the path runs in the library's HIP kernels. This module only
+marshals arguments: torch CUDA tensors provide device memory and the stream.
+There is no CPU fallback; without the built library every call raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+from . import _lib as L
+from ._lib import MRError  # noqa: F401
+
+__all__ = ["Job", "WordsResult", "U32Result", "MRError", "load"]
+
+
+def load():
+    return L.load(required=True)
+
+
+def _ptr(t) -> int | None:
+    if t is None:
+        return None
+    return t.data_ptr()
+
+
+def _stream_handle(torch, device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+@dataclass
+class WordsResult:
+    key_bytes: "object"     # torch.uint8 [key_bytes_used]
+    key_offsets: "object"   # torch.int64 [n + 1] (uint64 bit pattern)
+    values: "object"        # torch.int32 [n] (uint32 bit pattern)
+    stats: dict
+
+    def __len__(self):
+        return int(self.values.numel())
+
+    def items(self):
+        kb = self.key_bytes.cpu().numpy().tobytes()
+        o = self.key_offsets.cpu().numpy().astype("uint64")
+        v = self.values.cpu().numpy().astype("uint32")
+        return [(kb[o[i]:o[i + 1]], int(v[i])) for i in range(len(v))]
+
+
+@dataclass
+class U32Result:
+    keys: "object"
+    values: "object"
+    stats: dict
+
+
+def _stats(o: L.Output) -> dict:
+    s = o.stats
+    return {"strategy_used": s.strategy_used, "retries": s.retries, "table_slots": s.table_slots,
+            "n_items": s.n_items, "gpu_ms": s.gpu_ms, "map_ms": s.map_ms, "km_rechecked": s.km_rechecked,
+            "selector_used": s.selector_used}
+
+
+class Job:
+    """One mr_job bound to a device and to that device's current torch stream."""
+
+    def __init__(self, device: int = 0, strategy: int = L.STRAT_RULE, lds_slots: int = 0, max_load_pct: int = 0,
+                 debug_hash: int = 0, table_slots: int = 0, km_centroids=None, stream=None, timing: int = 0):
+        import torch
+        self.torch = torch
+        self.lib = load()
+        self.device = device
+        cfg = L.JobConfig()
+        cfg.device = device
+        cfg.stream = stream if stream is not None else _stream_handle(torch, device)
+        cfg.strategy = strategy
+        cfg.lds_slots = lds_slots
+        cfg.max_load_pct = max_load_pct
+        cfg.debug_hash = debug_hash
+        cfg.table_slots = table_slots
+        cfg.timing = timing
+        self._km = None
+        if km_centroids is not None:
+            c = km_centroids.to(device=f"cuda:{device}", dtype=torch.float32).contiguous()
+            cfg.km_k, cfg.km_d = int(c.shape[0]), int(c.shape[1])
+            cfg.km_centroids = c.data_ptr()
+            self._km = c
+        self.cfg = cfg
+        h = C.c_void_p()
+        L.check(self.lib.mr_job_create(C.byref(cfg), C.byref(h)), "mr_job_create")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.mr_job_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------------ words
+    def _word_out(self, cap_keys: int, cap_bytes: int):
+        torch = self.torch
+        dev = f"cuda:{self.device}"
+        kb = torch.empty(max(cap_bytes, 1), dtype=torch.uint8, device=dev)
+        ko = torch.empty(cap_keys + 1, dtype=torch.int64, device=dev)
+        vals = torch.empty(max(cap_keys, 1), dtype=torch.int32, device=dev)
+        o = L.Output()
+        o.key_bytes, o.key_offsets, o.values = kb.data_ptr(), ko.data_ptr(), vals.data_ptr()
+        o.cap_keys, o.cap_key_bytes = cap_keys, cap_bytes
+        return o, (kb, ko, vals)
+
+    def words(self, data, record_offsets=None, cap_keys: int | None = None, cap_bytes: int | None = None) -> WordsResult:
+        """Word count of a uint8 CUDA tensor; record_offsets is an int64 CUDA tensor [n + 1] or None."""
+        n = int(data.numel())
+        if cap_keys is None:
+            cap_keys = max(1024, min(n // 2 + 1, 1 << 20))
+        if cap_bytes is None:
+            cap_bytes = max(4096, min(n, 1 << 24))
+        for _ in range(2):
+            o, keep = self._word_out(cap_keys, cap_bytes)
+            ro = None if record_offsets is None else record_offsets
+            st = self.lib.mr_run(self.h, L.MAP_WORDS, L.REDUCE_COUNT, _ptr(data), n, _ptr(ro),
+                                 0 if ro is None else int(ro.numel()) - 1, 0, C.byref(o))
+            if st == L.MR_ERR_CAPACITY and (o.n_keys > cap_keys or o.key_bytes_used > cap_bytes):
+                cap_keys, cap_bytes = int(o.n_keys), int(o.key_bytes_used)
+                continue
+            L.check(st, "mr_run(words)")
+            kb, ko, vals = keep
+            nk = int(o.n_keys)
+            return WordsResult(kb[:o.key_bytes_used], ko[:nk + 1], vals[:nk], _stats(o))
+        raise MRError(L.MR_ERR_CAPACITY, "output capacity retry failed")
+
+    def words_raw(self, data, out: L.Output, record_offsets=None) -> int:
+        """mr_run with caller-prepared output buffers; returns the status (for timing loops)."""
+        ro = record_offsets
+        return self.lib.mr_run(self.h, L.MAP_WORDS, L.REDUCE_COUNT, _ptr(data), int(data.numel()), _ptr(ro),
+                               0 if ro is None else int(ro.numel()) - 1, 0, C.byref(out))
+
+    def words_batch(self, inputs, cap_keys: list[int] | None = None, cap_bytes: list[int] | None = None):
+        """One mr_batch_run over a list of uint8 CUDA tensors; returns a list of WordsResult."""
+        n = len(inputs)
+        items = (L.BatchItem * n)()
+        outs = (L.Output * n)()
+        keep = []
+        for i, d in enumerate(inputs):
+            items[i].kind, items[i].op = L.MAP_WORDS, L.REDUCE_COUNT
+            items[i].d_input, items[i].input_bytes = d.data_ptr(), int(d.numel())
+            ck = cap_keys[i] if cap_keys else max(1024, min(int(d.numel()) // 2 + 1, 1 << 20))
+            cb = cap_bytes[i] if cap_bytes else max(4096, min(int(d.numel()), 1 << 24))
+            o, k = self._word_out(ck, cb)
+            outs[i] = o
+            keep.append(k)
+        st = self.lib.mr_batch_run(self.h, items, n, outs)
+        L.check(st, "mr_batch_run")
+        res = []
+        for i in range(n):
+            kb, ko, vals = keep[i]
+            nk = int(outs[i].n_keys)
+            res.append(WordsResult(kb[:outs[i].key_bytes_used], ko[:nk + 1], vals[:nk], _stats(outs[i])))
+        return res
+
+    # -------------------------------------------------------------- histogram
+    def rgb_hist(self, data):
+        torch = self.torch
+        out = torch.empty(768, dtype=torch.int64, device=f"cuda:{self.device}")
+        o = L.Output()
+        o.values = out.data_ptr()
+        L.check(self.lib.mr_run(self.h, L.MAP_RGB_HIST, L.REDUCE_COUNT, _ptr(data), int(data.numel()), None, 0, 0,
+                                C.byref(o)), "mr_run(rgb)")
+        return out.view(3, 256), _stats(o)
+
+    # ------------------------------------------------------------- u32 keys
+    def u32(self, keys, values=None, op: int = L.REDUCE_COUNT, key_range: int = 0, cap_keys: int | None = None):
+        """keys: int32 CUDA tensor (uint32 bit pattern); values likewise or None.
+
+        With values the input is interleaved (key, value) pairs, as mr_run expects."""
+        torch = self.torch
+        dev = f"cuda:{self.device}"
+        if values is not None:
+            data = torch.stack([keys.view(torch.int32), values.view(torch.int32)], dim=1).contiguous()
+            kind = L.MAP_U32_KV
+        else:
+            data = keys.view(torch.int32).contiguous()
+            kind = L.MAP_U32_KEYS
+        n = int(keys.numel())
+        if cap_keys is None:
+            cap_keys = max(1, min(n, key_range) if key_range else n)
+        wide = op == L.REDUCE_SUM
+        for _ in range(2):
+            k = torch.empty(max(cap_keys, 1), dtype=torch.int32, device=dev)
+            v = torch.empty(max(cap_keys, 1), dtype=torch.int64 if wide else torch.int32, device=dev)
+            o = L.Output()
+            o.keys, o.values, o.cap_keys = k.data_ptr(), v.data_ptr(), cap_keys
+            st = self.lib.mr_run(self.h, kind, op, data.data_ptr(), data.numel() * 4, None, 0, key_range, C.byref(o))
+            if st == L.MR_ERR_CAPACITY and o.n_keys > cap_keys:
+                cap_keys = int(o.n_keys)
+                continue
+            L.check(st, "mr_run(u32)")
+            nk = int(o.n_keys)
+            return U32Result(k[:nk], v[:nk], _stats(o))
+        raise MRError(L.MR_ERR_CAPACITY, "output capacity retry failed")
+
+    # -------------------------------------------------------------- k-means
+    def kmeans(self, X):
+        """One Lloyd step on float32 CUDA tensor X [n, d] from the job's current centroids."""
+        torch = self.torch
+        if self._km is None:
+            raise ValueError("job was created without k-means centroids")
+        k, d = self._km.shape
+        n = int(X.shape[0])
+        dev = f"cuda:{self.device}"
+        assign = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+        sums = torch.empty(k, d, dtype=torch.float32, device=dev)
+        counts = torch.empty(k, dtype=torch.int32, device=dev)
+        cents = torch.empty(k, d, dtype=torch.float32, device=dev)
+        o = L.Output()
+        o.assign, o.sums, o.counts, o.centroids = assign.data_ptr(), sums.data_ptr(), counts.data_ptr(), cents.data_ptr()
+        L.check(self.lib.mr_run(self.h, L.MAP_KMEANS, L.REDUCE_SUM, _ptr(X), n * d * 4, None, 0, 0, C.byref(o)),
+                "mr_run(kmeans)")
+        return assign[:n], sums, counts, cents, _stats(o)

@@ -1,0 +1,577 @@
+// Host side of the C ABI declared in include/mr.h: argument checks, planning,
+// workspace management, kernel enqueue, retries and status reporting.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/mr.h"
+#include "jobs.h"
+#include "launch.h"
+
+using namespace mr;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+mr_status fail(mr_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return s;
+}
+
+#define MR_HIP(call)                                                                     \
+  do {                                                                                   \
+    hipError_t e_ = (call);                                                              \
+    if (e_ != hipSuccess) return fail(MR_ERR_HIP, "%s: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+uint64_t next_pow2(uint64_t x) {
+  uint64_t p = 1;
+  while (p < x) p <<= 1;
+  return p;
+}
+
+uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
+
+}  // namespace
+
+// ----------------------------------------------------------------------------
+// job object
+// ----------------------------------------------------------------------------
+
+struct mr_job {
+  mr_job_config cfg{};
+  hipStream_t stream = nullptr;
+  int device = 0;
+  int n_cu = 256;
+  // one device workspace, grown on demand; the table region must be all zero between runs
+  uint8_t* ws = nullptr;
+  uint64_t ws_bytes = 0;
+  uint64_t table_clean_bytes = 0;  // [0, table_clean_bytes) of ws is known to be all zero
+  hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr, ev3 = nullptr;
+  // selector
+  bool sel_loaded = false;
+  std::vector<float> sel_params, sel_mean, sel_scale, sel_lo, sel_hi;
+  // k-means centroids (device, owned)
+  float* km_c = nullptr;
+  // batched graph cache
+  hipGraphExec_t graph = nullptr;
+  uint64_t graph_key = 0;
+  // pinned host staging for job states
+  JobState* h_states = nullptr;
+  uint32_t h_states_cap = 0;
+};
+
+namespace {
+
+struct ScopedDevice {
+  int prev = -1;
+  explicit ScopedDevice(int d) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != d) (void)hipSetDevice(d);
+  }
+  ~ScopedDevice() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+// Workspace layout carved for one run: offsets from ws.
+struct Carve {
+  uint64_t off = 0;
+  uint64_t take(uint64_t bytes, uint64_t align = 256) {
+    off = align_up(off, align);
+    const uint64_t o = off;
+    off += bytes;
+    return o;
+  }
+};
+
+mr_status ensure_ws(mr_job* job, uint64_t bytes) {
+  if (bytes <= job->ws_bytes) return MR_OK;
+  const uint64_t want = std::max<uint64_t>(bytes, job->ws_bytes + job->ws_bytes / 2);
+  if (job->ws) {
+    MR_HIP(hipStreamSynchronize(job->stream));
+    MR_HIP(hipFree(job->ws));
+    job->ws = nullptr;
+    job->ws_bytes = 0;
+  }
+  uint8_t* p = nullptr;
+  hipError_t e = hipMalloc(&p, want);
+  if (e != hipSuccess) return fail(MR_ERR_HIP, "hipMalloc(%llu) failed: %s", (unsigned long long)want, hipGetErrorString(e));
+  job->ws = p;
+  job->ws_bytes = want;
+  job->table_clean_bytes = 0;
+  return MR_OK;
+}
+
+mr_status ensure_host_states(mr_job* job, uint32_t n) {
+  if (n <= job->h_states_cap) return MR_OK;
+  if (job->h_states) (void)hipHostFree(job->h_states);
+  job->h_states = nullptr;
+  MR_HIP(hipHostMalloc(&job->h_states, sizeof(JobState) * n, hipHostMallocDefault));
+  job->h_states_cap = n;
+  return MR_OK;
+}
+
+}  // namespace
+
+// ----------------------------------------------------------------------------
+// status helpers
+// ----------------------------------------------------------------------------
+
+extern "C" const char* mr_status_str(mr_status s) {
+  switch (s) {
+    case MR_OK: return "MR_OK";
+    case MR_ERR_INVALID_ARG: return "MR_ERR_INVALID_ARG";
+    case MR_ERR_CAPACITY: return "MR_ERR_CAPACITY";
+    case MR_ERR_OVERFLOW: return "MR_ERR_OVERFLOW";
+    case MR_ERR_HIP: return "MR_ERR_HIP";
+    case MR_ERR_UNSUPPORTED: return "MR_ERR_UNSUPPORTED";
+    case MR_ERR_NO_DEVICE: return "MR_ERR_NO_DEVICE";
+    default: return "MR_ERR_UNKNOWN";
+  }
+}
+
+extern "C" const char* mr_last_error(void) { return g_last_error.c_str(); }
+
+extern "C" mr_status mr_job_create(const mr_job_config* cfg, mr_job** out) {
+  if (!cfg || !out) return fail(MR_ERR_INVALID_ARG, "mr_job_create: NULL argument");
+  *out = nullptr;
+  int n_dev = 0;
+  if (hipGetDeviceCount(&n_dev) != hipSuccess || n_dev <= 0) return fail(MR_ERR_NO_DEVICE, "no HIP device");
+  if (cfg->device < 0 || cfg->device >= n_dev) return fail(MR_ERR_INVALID_ARG, "device %d out of range", cfg->device);
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, cfg->device) != hipSuccess) return fail(MR_ERR_NO_DEVICE, "device query failed");
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(MR_ERR_NO_DEVICE, "device %d is %s, this library is built for gfx950", cfg->device, prop.gcnArchName);
+  if (cfg->lds_slots && (cfg->lds_slots & (cfg->lds_slots - 1)))
+    return fail(MR_ERR_INVALID_ARG, "lds_slots must be a power of two");
+  if (cfg->table_slots && (cfg->table_slots & (cfg->table_slots - 1)))
+    return fail(MR_ERR_INVALID_ARG, "table_slots must be a power of two");
+  if (cfg->max_load_pct > 95) return fail(MR_ERR_INVALID_ARG, "max_load_pct above 95");
+  mr_job* job = new (std::nothrow) mr_job();
+  if (!job) return fail(MR_ERR_INVALID_ARG, "out of host memory");
+  job->cfg = *cfg;
+  job->device = cfg->device;
+  job->stream = static_cast<hipStream_t>(cfg->stream);
+  job->n_cu = prop.multiProcessorCount;
+  ScopedDevice sd(job->device);
+  if (hipEventCreate(&job->ev0) != hipSuccess || hipEventCreate(&job->ev1) != hipSuccess ||
+      hipEventCreate(&job->ev2) != hipSuccess || hipEventCreate(&job->ev3) != hipSuccess) {
+    delete job;
+    return fail(MR_ERR_HIP, "hipEventCreate failed");
+  }
+  if (cfg->km_k) {
+    if (!cfg->km_centroids || cfg->km_d == 0 || cfg->km_d > 256 || cfg->km_k > 1024) {
+      mr_job_destroy(job);
+      return fail(MR_ERR_INVALID_ARG, "k-means needs centroids, 1 <= d <= 256 and 1 <= k <= 1024");
+    }
+    const size_t bytes = sizeof(float) * cfg->km_d * cfg->km_k;
+    if (hipMalloc(&job->km_c, bytes) != hipSuccess ||
+        hipMemcpyAsync(job->km_c, cfg->km_centroids, bytes, hipMemcpyDeviceToDevice, job->stream) != hipSuccess ||
+        hipStreamSynchronize(job->stream) != hipSuccess) {
+      mr_job_destroy(job);
+      return fail(MR_ERR_HIP, "copying the initial centroids failed");
+    }
+  }
+  *out = job;
+  return MR_OK;
+}
+
+extern "C" mr_status mr_job_destroy(mr_job* job) {
+  if (!job) return MR_OK;
+  ScopedDevice sd(job->device);
+  if (job->stream) (void)hipStreamSynchronize(job->stream);
+  if (job->graph) (void)hipGraphExecDestroy(job->graph);
+  if (job->ws) (void)hipFree(job->ws);
+  if (job->km_c) (void)hipFree(job->km_c);
+  if (job->h_states) (void)hipHostFree(job->h_states);
+  if (job->ev0) (void)hipEventDestroy(job->ev0);
+  if (job->ev1) (void)hipEventDestroy(job->ev1);
+  if (job->ev2) (void)hipEventDestroy(job->ev2);
+  if (job->ev3) (void)hipEventDestroy(job->ev3);
+  delete job;
+  return MR_OK;
+}
+
+// ----------------------------------------------------------------------------
+// word count (one job or a batch)
+// ----------------------------------------------------------------------------
+
+namespace {
+
+struct WordItem {
+  const uint8_t* in;
+  uint64_t n;
+  const uint64_t* rec;
+  uint64_t n_rec;
+  mr_output* out;
+  uint64_t cap;  // planned table slots
+};
+
+// Initial table capacity for an input of n bytes: words <= (n + 1) / 2 and
+// distinct words <= words; start from a sixteenth of the bytes and let a full
+// table trigger regrowth.
+uint64_t initial_slots(const mr_job* job, uint64_t n) {
+  if (job->cfg.table_slots) return job->cfg.table_slots;
+  const double lf = (job->cfg.max_load_pct ? job->cfg.max_load_pct : 50) / 100.0;
+  const uint64_t words_ub = (n + 1) / 2;
+  uint64_t est = std::min<uint64_t>(words_ub, std::max<uint64_t>(2048, n / 16));
+  uint64_t slots = next_pow2((uint64_t)std::ceil(est / lf));
+  return std::max<uint64_t>(4096, std::min<uint64_t>(slots, 1ull << 31));
+}
+
+struct WordsPlan {
+  Carve c;
+  uint64_t o_jobs, o_tile_base, o_states, o_totals, o_bucket_cnt, o_bucket_bytes, o_bucket_start, o_bucket_bstart,
+      o_bucket_fill, o_tw, o_tc, o_recs, o_recs2, o_rbucket, o_spl;
+  uint64_t total_slots = 0, total_tiles = 0;
+  std::vector<uint64_t> slot_base, tile_base;
+};
+
+WordsPlan plan_words(const std::vector<WordItem>& items) {
+  WordsPlan p;
+  const uint32_t n = (uint32_t)items.size();
+  p.slot_base.resize(n);
+  p.tile_base.resize(n + 1);
+  for (uint32_t j = 0; j < n; ++j) {
+    p.slot_base[j] = p.total_slots;
+    p.total_slots += items[j].cap;
+    p.tile_base[j] = p.total_tiles;
+    const uint64_t a = (uint64_t)items[j].in;
+    const uint64_t n_chunks = items[j].n ? ((a + items[j].n + 15) / 16 - a / 16) : 0;
+    p.total_tiles += (n_chunks + kMapTileChunks - 1) / kMapTileChunks;
+  }
+  p.tile_base[n] = p.total_tiles;
+  // the table arena comes first so that its clean prefix survives layout changes
+  p.o_tw = p.c.take(p.total_slots * 8);
+  p.o_tc = p.c.take(p.total_slots * 4);
+  p.o_jobs = p.c.take(sizeof(WordJob) * n);
+  p.o_tile_base = p.c.take(8 * (n + 1));
+  p.o_states = p.c.take(sizeof(JobState) * n);
+  p.o_totals = p.c.take(16);
+  p.o_bucket_cnt = p.c.take(4ull * n * kMaxBuckets);
+  p.o_bucket_bytes = p.c.take(8ull * n * kMaxBuckets);
+  p.o_bucket_start = p.c.take(4ull * n * kMaxBuckets);
+  p.o_bucket_bstart = p.c.take(8ull * n * kMaxBuckets);
+  p.o_bucket_fill = p.c.take(4ull * n * kMaxBuckets);
+  p.o_recs = p.c.take(sizeof(WRec) * p.total_slots);
+  p.o_recs2 = p.c.take(sizeof(WRec) * p.total_slots);
+  p.o_rbucket = p.c.take(4 * p.total_slots);
+  p.o_spl = p.c.take(sizeof(WRec) * (kMaxBuckets - 1) * (uint64_t)n);
+  return p;
+}
+
+mr_status zero_device(mr_job* job, void* p, uint64_t bytes) {
+  if (!bytes) return MR_OK;
+  if (bytes % 4 == 0 && (uintptr_t)p % 4 == 0) {
+    MR_HIP(hipMemsetD32Async((hipDeviceptr_t)p, 0, bytes / 4, job->stream));
+  } else {
+    MR_HIP(hipMemsetAsync(p, 0, bytes, job->stream));
+  }
+  return MR_OK;
+}
+
+// Runs a batch of word-count items once; fills states[] (host). The caller
+// handles regrowth and results.
+mr_status words_pass(mr_job* job, std::vector<WordItem>& items, std::vector<JobState>& states, float* gpu_ms,
+                     float* map_ms) {
+  const uint32_t n = (uint32_t)items.size();
+  WordsPlan p = plan_words(items);
+  mr_status st = ensure_ws(job, p.c.off);
+  if (st != MR_OK) return st;
+  uint8_t* ws = job->ws;
+  // the table arena must start all zero
+  const uint64_t table_bytes = p.o_tc + p.total_slots * 4;
+  if (job->table_clean_bytes < table_bytes) {
+    st = zero_device(job, ws + job->table_clean_bytes, table_bytes - job->table_clean_bytes);
+    if (st != MR_OK) return st;
+  }
+  job->table_clean_bytes = 0;  // until this pass completes
+  std::vector<WordJob> hj(n);
+  bool any_rec = false;
+  for (uint32_t j = 0; j < n; ++j) {
+    WordJob& J = hj[j];
+    const WordItem& it = items[j];
+    J.in = it.in;
+    J.n = it.n;
+    J.rec = it.rec;
+    J.n_rec = it.n_rec;
+    const uint64_t a = (uint64_t)it.in;
+    J.chunk0 = a / 16;
+    J.n_chunks = it.n ? ((a + it.n + 15) / 16 - a / 16) : 0;
+    J.tile_base = p.tile_base[j];
+    J.tw = reinterpret_cast<unsigned long long*>(ws + p.o_tw) + p.slot_base[j];
+    J.tc = reinterpret_cast<uint32_t*>(ws + p.o_tc) + p.slot_base[j];
+    J.cap = it.cap;
+    J.slot_base = p.slot_base[j];
+    J.recs = reinterpret_cast<WRec*>(ws + p.o_recs) + p.slot_base[j];
+    J.recs2 = reinterpret_cast<WRec*>(ws + p.o_recs2) + p.slot_base[j];
+    J.rec_bucket = reinterpret_cast<uint32_t*>(ws + p.o_rbucket) + p.slot_base[j];
+    J.splitters = reinterpret_cast<WRec*>(ws + p.o_spl) + (uint64_t)j * (kMaxBuckets - 1);
+    J.out_key_bytes = it.out->key_bytes;
+    J.out_key_offsets = it.out->key_offsets;
+    J.out_values = static_cast<uint32_t*>(it.out->values);
+    J.cap_keys = it.out->cap_keys;
+    J.cap_key_bytes = it.out->cap_key_bytes;
+    J.st = reinterpret_cast<JobState*>(ws + p.o_states) + j;
+    any_rec |= it.rec != nullptr;
+  }
+  MR_HIP(hipMemcpyAsync(ws + p.o_jobs, hj.data(), sizeof(WordJob) * n, hipMemcpyHostToDevice, job->stream));
+  MR_HIP(hipMemcpyAsync(ws + p.o_tile_base, p.tile_base.data(), 8 * (n + 1), hipMemcpyHostToDevice, job->stream));
+  st = zero_device(job, ws + p.o_states, sizeof(JobState) * n);
+  if (st != MR_OK) return st;
+
+  WordsLaunch L{};
+  L.jobs = reinterpret_cast<const WordJob*>(ws + p.o_jobs);
+  L.tile_base = reinterpret_cast<const uint64_t*>(ws + p.o_tile_base);
+  L.n_jobs = n;
+  L.total_tiles = p.total_tiles;
+  L.total_slots = p.total_slots;
+  const uint64_t want_grid = std::max<uint64_t>(1, std::min<uint64_t>(p.total_tiles, (uint64_t)job->n_cu));
+  L.map_grid = (uint32_t)want_grid;
+  L.sort_grid = (uint32_t)std::max(1, job->n_cu * 2);
+  L.lds_log2 = 12;
+  if (job->cfg.lds_slots) {
+    int lg = 0;
+    while ((1u << lg) < job->cfg.lds_slots) ++lg;
+    if (lg != 8 && lg != 10 && lg != 11 && lg != 12) return fail(MR_ERR_INVALID_ARG, "lds_slots must be 256, 1024, 2048 or 4096");
+    L.lds_log2 = lg;
+  }
+  L.debug_hash = job->cfg.debug_hash;
+  L.any_records = any_rec;
+  L.totals = reinterpret_cast<uint32_t*>(ws + p.o_totals);
+  L.bucket_cnt = reinterpret_cast<uint32_t*>(ws + p.o_bucket_cnt);
+  L.bucket_bytes = reinterpret_cast<unsigned long long*>(ws + p.o_bucket_bytes);
+  L.bucket_start = reinterpret_cast<uint32_t*>(ws + p.o_bucket_start);
+  L.bucket_bstart = reinterpret_cast<unsigned long long*>(ws + p.o_bucket_bstart);
+  L.bucket_fill = reinterpret_cast<uint32_t*>(ws + p.o_bucket_fill);
+
+  MR_HIP(hipEventRecord(job->ev0, job->stream));
+  MR_HIP(words_enqueue_prep(L, job->stream));
+  if (job->cfg.timing) MR_HIP(hipEventRecord(job->ev2, job->stream));
+  MR_HIP(words_enqueue_map(L, job->stream));
+  if (job->cfg.timing) MR_HIP(hipEventRecord(job->ev3, job->stream));
+  MR_HIP(words_enqueue_reduce(L, job->stream));
+  MR_HIP(hipEventRecord(job->ev1, job->stream));
+  st = ensure_host_states(job, n);
+  if (st != MR_OK) return st;
+  MR_HIP(hipMemcpyAsync(job->h_states, ws + p.o_states, sizeof(JobState) * n, hipMemcpyDeviceToHost, job->stream));
+  MR_HIP(hipStreamSynchronize(job->stream));
+  states.assign(job->h_states, job->h_states + n);
+  float ms = 0.f;
+  MR_HIP(hipEventElapsedTime(&ms, job->ev0, job->ev1));
+  *gpu_ms = ms;
+  *map_ms = 0.f;
+  if (job->cfg.timing) MR_HIP(hipEventElapsedTime(map_ms, job->ev2, job->ev3));
+  // The compaction zeroes every slot it reads, so after a complete pass the
+  // table region [0, table_bytes) is zero again. Everything past it was just
+  // used for descriptors, records and buckets and is not. A pass that stopped
+  // on a full table leaves slots behind.
+  bool dirty = false;
+  for (auto& s : states) dirty |= (s.flags & kFlagTableFull) != 0;
+  job->table_clean_bytes = dirty ? 0 : table_bytes;
+  return MR_OK;
+}
+
+mr_status check_words_item(const WordItem& it) {
+  if (!it.out) return fail(MR_ERR_INVALID_ARG, "NULL output");
+  if (it.n && !it.in) return fail(MR_ERR_INVALID_ARG, "NULL input with nonzero length");
+  if (it.n >= (1ull << 32)) return fail(MR_ERR_UNSUPPORTED, "word inputs must be below 4 GiB");
+  if (it.rec && it.n_rec == 0) return fail(MR_ERR_INVALID_ARG, "record offsets need n_records >= 1");
+  if ((it.out->cap_keys && (!it.out->key_offsets || !it.out->values)) || (it.out->cap_key_bytes && !it.out->key_bytes))
+    return fail(MR_ERR_INVALID_ARG, "output capacity given without buffers");
+  if (!it.out->key_offsets) return fail(MR_ERR_INVALID_ARG, "key_offsets is required (at least one entry)");
+  return MR_OK;
+}
+
+mr_status run_words(mr_job* job, std::vector<WordItem>& items, std::vector<mr_status>* per_item) {
+  for (auto& it : items) {
+    mr_status s = check_words_item(it);
+    if (s != MR_OK) return s;
+    it.cap = initial_slots(job, it.n);
+  }
+  std::vector<JobState> states;
+  uint32_t retries = 0;
+  float total_ms = 0.f, map_ms = 0.f;
+  for (;;) {
+    float ms = 0.f;
+    mr_status s = words_pass(job, items, states, &ms, &map_ms);
+    if (s != MR_OK) return s;
+    total_ms += ms;
+    bool regrow = false;
+    for (size_t j = 0; j < items.size(); ++j) {
+      if (states[j].flags & kFlagTableFull) {
+        if (items[j].cap >= (1ull << 31)) return fail(MR_ERR_CAPACITY, "hash table cannot grow beyond 2^31 slots");
+        items[j].cap *= 2;
+        regrow = true;
+      }
+    }
+    if (!regrow) break;
+    if (++retries > 24) return fail(MR_ERR_CAPACITY, "hash table regrowth did not converge");
+  }
+  mr_status first = MR_OK;
+  for (size_t j = 0; j < items.size(); ++j) {
+    mr_output* o = items[j].out;
+    const JobState& s = states[j];
+    o->n_keys = s.n_recs;
+    o->key_bytes_used = s.key_bytes;
+    o->stats.strategy_used = MR_STRAT_HASH;
+    o->stats.retries = retries;
+    o->stats.table_slots = items[j].cap;
+    o->stats.gpu_ms = total_ms;
+    o->stats.map_ms = map_ms;
+    o->stats.n_items = 0;
+    mr_status r = MR_OK;
+    if (s.flags & kFlagBadInput) r = fail(MR_ERR_INVALID_ARG, "malformed record offsets (item %zu)", j);
+    else if (s.flags & kFlagSpin) r = fail(MR_ERR_HIP, "bounded wait expired (item %zu)", j);
+    else if (s.flags & kFlagInternal) r = fail(MR_ERR_HIP, "internal table invariant failed (item %zu)", j);
+    else if (s.flags & kFlagCapacity)
+      r = fail(MR_ERR_CAPACITY, "output needs %llu keys and %llu key bytes (item %zu)", (unsigned long long)s.n_recs,
+               (unsigned long long)s.key_bytes, j);
+    o->status = r;
+    if (per_item) (*per_item)[j] = r;
+    if (first == MR_OK && r != MR_OK) first = r;
+  }
+  return first;
+}
+
+}  // namespace
+
+// ----------------------------------------------------------------------------
+// RGB histogram
+// ----------------------------------------------------------------------------
+
+namespace {
+
+mr_status run_rgb(mr_job* job, const void* d_input, uint64_t bytes, mr_output* out) {
+  if (bytes % 3) return fail(MR_ERR_INVALID_ARG, "RGB input length %llu is not a multiple of 3", (unsigned long long)bytes);
+  if (!out->values) return fail(MR_ERR_INVALID_ARG, "RGB output needs values[768]");
+  const uint32_t G = rgb_grid(bytes, job->n_cu);
+  Carve c;
+  const uint64_t o_part = c.take(4ull * 768 * G);
+  mr_status st = ensure_ws(job, c.off);
+  if (st != MR_OK) return st;
+  job->table_clean_bytes = std::min(job->table_clean_bytes, o_part);  // scratch overwrites the table region
+  MR_HIP(hipEventRecord(job->ev0, job->stream));
+  MR_HIP(rgb_enqueue(static_cast<const uint8_t*>(d_input), bytes, reinterpret_cast<uint32_t*>(job->ws + o_part), G,
+                     static_cast<unsigned long long*>(out->values), job->stream, job->cfg.timing ? job->ev2 : nullptr,
+                     job->cfg.timing ? job->ev3 : nullptr));
+  MR_HIP(hipEventRecord(job->ev1, job->stream));
+  MR_HIP(hipStreamSynchronize(job->stream));
+  float ms = 0.f;
+  MR_HIP(hipEventElapsedTime(&ms, job->ev0, job->ev1));
+  if (job->cfg.timing) MR_HIP(hipEventElapsedTime(&out->stats.map_ms, job->ev2, job->ev3));
+  out->n_keys = 768;
+  out->key_bytes_used = 0;
+  out->stats.strategy_used = MR_STRAT_LDS_ARRAY;
+  out->stats.n_items = bytes / 3;
+  out->stats.gpu_ms = ms;
+  return MR_OK;
+}
+
+mr_status run_u32(mr_job* job, mr_map_kind kind, mr_reduce_op op, const void* d_input, uint64_t bytes, uint64_t key_range,
+                  mr_output* out) {
+  (void)job; (void)kind; (void)op; (void)d_input; (void)bytes; (void)key_range; (void)out;
+  return fail(MR_ERR_UNSUPPORTED, "integer-key jobs are not built yet");
+}
+
+mr_status run_kmeans(mr_job* job, const void* d_input, uint64_t bytes, mr_output* out) {
+  (void)job; (void)d_input; (void)bytes; (void)out;
+  return fail(MR_ERR_UNSUPPORTED, "k-means is not built yet");
+}
+
+}  // namespace
+
+// ----------------------------------------------------------------------------
+// entry points
+// ----------------------------------------------------------------------------
+
+extern "C" mr_status mr_run(mr_job* job, mr_map_kind kind, mr_reduce_op op, const void* d_input, uint64_t input_bytes,
+                            const uint64_t* d_record_offsets, uint64_t n_records, uint64_t key_range, mr_output* out) {
+  if (!job || !out) return fail(MR_ERR_INVALID_ARG, "NULL job or output");
+  if (input_bytes && !d_input) return fail(MR_ERR_INVALID_ARG, "NULL input");
+  if (d_record_offsets && kind != MR_MAP_WORDS) return fail(MR_ERR_INVALID_ARG, "record offsets are only meaningful for words");
+  ScopedDevice sd(job->device);
+  out->stats = mr_stats{};
+  out->status = MR_OK;
+  mr_status s;
+  switch (kind) {
+    case MR_MAP_WORDS: {
+      if (op != MR_REDUCE_COUNT) return fail(MR_ERR_UNSUPPORTED, "words support COUNT only");
+      std::vector<WordItem> items(1);
+      items[0] = WordItem{static_cast<const uint8_t*>(d_input), input_bytes, d_record_offsets, n_records, out, 0};
+      s = run_words(job, items, nullptr);
+      break;
+    }
+    case MR_MAP_RGB_HIST:
+      if (op != MR_REDUCE_COUNT) return fail(MR_ERR_UNSUPPORTED, "the histogram supports COUNT only");
+      s = run_rgb(job, d_input, input_bytes, out);
+      break;
+    case MR_MAP_U32_KEYS:
+    case MR_MAP_U32_KV:
+      s = run_u32(job, kind, op, d_input, input_bytes, key_range, out);
+      break;
+    case MR_MAP_KMEANS:
+      s = run_kmeans(job, d_input, input_bytes, out);
+      break;
+    default:
+      return fail(MR_ERR_INVALID_ARG, "unknown map kind %d", (int)kind);
+  }
+  out->status = s;
+  return s;
+}
+
+extern "C" mr_status mr_batch_run(mr_job* job, const mr_batch_item* items, uint32_t n_items, mr_output* outs) {
+  if (!job || (!items && n_items) || (!outs && n_items)) return fail(MR_ERR_INVALID_ARG, "NULL argument");
+  if (n_items == 0) return MR_OK;
+  ScopedDevice sd(job->device);
+  std::vector<WordItem> w(n_items);
+  for (uint32_t i = 0; i < n_items; ++i) {
+    if (items[i].kind != MR_MAP_WORDS || items[i].op != MR_REDUCE_COUNT)
+      return fail(MR_ERR_UNSUPPORTED, "mr_batch_run supports word-count items only (item %u)", i);
+    outs[i].stats = mr_stats{};
+    outs[i].status = MR_OK;
+    w[i] = WordItem{static_cast<const uint8_t*>(items[i].d_input), items[i].input_bytes, items[i].d_record_offsets,
+                    items[i].n_records, &outs[i], 0};
+  }
+  std::vector<mr_status> per(n_items, MR_OK);
+  return run_words(job, w, &per);
+}
+
+// ----------------------------------------------------------------------------
+// selector entry points (implemented in selector.cpp when built)
+// ----------------------------------------------------------------------------
+#ifndef MR_HAVE_SELECTOR
+extern "C" mr_status mr_job_features(mr_job*, mr_map_kind, mr_reduce_op, const void*, uint64_t, uint64_t, float*) {
+  return fail(MR_ERR_UNSUPPORTED, "selector features are not built");
+}
+extern "C" mr_status mr_selector_set(mr_job*, const float*, const float*, const float*, const float*, const float*) {
+  return fail(MR_ERR_UNSUPPORTED, "selector is not built");
+}
+extern "C" mr_status mr_selector_predict(mr_job*, const float*, float*) {
+  return fail(MR_ERR_UNSUPPORTED, "selector is not built");
+}
+extern "C" mr_status mr_mlp_forward(mr_job*, const float*, const float*, uint32_t, float*, float*, float*) {
+  return fail(MR_ERR_UNSUPPORTED, "selector kernels are not built");
+}
+extern "C" mr_status mr_mlp_loss_backward(mr_job*, const float*, const float*, const float*, const float*, const float*,
+                                          const float*, const float*, uint32_t, float*, float*) {
+  return fail(MR_ERR_UNSUPPORTED, "selector kernels are not built");
+}
+extern "C" mr_status mr_mlp_adam(mr_job*, float*, const float*, float*, float*, uint32_t, float, float, float, float) {
+  return fail(MR_ERR_UNSUPPORTED, "selector kernels are not built");
+}
+#endif

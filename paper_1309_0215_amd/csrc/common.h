@@ -1,0 +1,91 @@
+// Shared device helpers and job descriptors of the MapReduce hot path (gfx950).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "jobs.h"
+
+#define MR_DEV __device__ __forceinline__
+
+namespace mr {
+
+constexpr int kWave = 64;
+
+// ---------------------------------------------------------------------------
+// hashing (the hash only places keys; equality is always decided on full keys)
+// ---------------------------------------------------------------------------
+MR_DEV uint64_t fmix64(uint64_t x) {
+  x ^= x >> 33;
+  x *= 0xff51afd7ed558ccdULL;
+  x ^= x >> 33;
+  x *= 0xc4ceb9fe1a85ec53ULL;
+  x ^= x >> 33;
+  return x;
+}
+
+MR_DEV uint64_t rotl64(uint64_t x, int r) { return (x << r) | (x >> (64 - r)); }
+
+// Hash of one 16-byte block (little-endian words w0, w1) chained onto h.
+MR_DEV uint64_t hash_block(uint64_t h, uint64_t w0, uint64_t w1) {
+  return fmix64(h ^ (w0 * 0x9E3779B97F4A7C15ULL) ^ rotl64(w1 * 0xC2B2AE3D27D4EB4FULL, 29));
+}
+
+MR_DEV uint64_t hash_seed(uint32_t len) { return 0x27D4EB2F165667C5ULL ^ ((uint64_t)len * 0x165667B19E3779F9ULL); }
+
+MR_DEV uint64_t hash_u32(uint32_t k) { return fmix64((uint64_t)k * 0x9E3779B97F4A7C15ULL + 0x632BE59BD9B4E019ULL); }
+
+// ---------------------------------------------------------------------------
+// separators: the six ASCII whitespace bytes 0x09..0x0D and 0x20
+// ---------------------------------------------------------------------------
+MR_DEV bool is_sep_byte(uint32_t b) { return b == 0x20u || (b - 0x09u) < 5u; }
+
+// 4-bit mask (bit i = byte i of w is a separator), branch-free SWAR.
+MR_DEV uint32_t sep_mask4(uint32_t w) {
+  const uint32_t hi = w & 0x80808080u;        // bytes >= 0x80 are word bytes
+  const uint32_t t = w & 0x7F7F7F7Fu;
+  const uint32_t y = t ^ 0x20202020u;          // zero byte where t == 0x20
+  const uint32_t eq20 = ~(y + 0x7F7F7F7Fu);    // bit 7 set where y byte == 0
+  const uint32_t ge9 = t + 0x77777777u;        // bit 7 set where t >= 9
+  const uint32_t ge14 = t + 0x72727272u;       // bit 7 set where t >= 14
+  const uint32_t s = (eq20 | (ge9 & ~ge14)) & ~hi & 0x80808080u;
+  return ((s >> 7) * 0x00204081u) >> 21 & 0xFu;  // gather bits 7,15,23,31 into 0..3
+}
+
+MR_DEV uint32_t sep_mask16(uint32_t a, uint32_t b, uint32_t c, uint32_t d) {
+  return sep_mask4(a) | (sep_mask4(b) << 4) | (sep_mask4(c) << 8) | (sep_mask4(d) << 12);
+}
+
+// bytes [0, n) of a little-endian word kept, the rest zeroed (n in 0..4)
+MR_DEV uint32_t keep_bytes(uint32_t w, int n) {
+  return n >= 4 ? w : (n <= 0 ? 0u : (w & ((1u << (8 * n)) - 1u)));
+}
+
+MR_DEV uint32_t bswap32(uint32_t x) { return __builtin_bswap32(x); }
+
+// ---------------------------------------------------------------------------
+// wave helpers
+// ---------------------------------------------------------------------------
+MR_DEV uint32_t lane_id() { return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u)); }
+
+MR_DEV uint64_t ballot(bool p) { return __ballot(p); }
+
+MR_DEV uint32_t popc64(uint64_t m) { return (uint32_t)__popcll(m); }
+
+// Number of set bits of m below this lane.
+MR_DEV uint32_t mbcnt(uint64_t m) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+// One slot per calling lane from a counter, with one atomic per wave: safe
+// under divergence (only the calling lanes take part).
+MR_DEV unsigned long long wave_claim(unsigned long long* counter) {
+  const uint64_t active = __ballot(true);
+  const int leader = __ffsll((long long)active) - 1;
+  unsigned long long base = 0;
+  if ((int)lane_id() == leader) base = atomicAdd(counter, (unsigned long long)popc64(active));
+  base = __shfl(base, leader);
+  return base + mbcnt(active);
+}
+
+}  // namespace mr

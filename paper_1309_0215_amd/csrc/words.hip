@@ -1,0 +1,818 @@
+// Word count on gfx950: split, tokenise, hash, combine (LDS), reduce (global
+// hash table), compact, sort and output.
+//
+// Paper mapping (arXiv 1309.0215):
+//   * split (Fig. "basic workflow", Section II-A): the input is cut into 16 KiB
+//     tiles; each workgroup takes a contiguous run of tiles. A word belongs to
+//     the 16-byte chunk that holds its first byte.
+//   * map + vectorisation-friendly emit (Section III-B): every lane tokenises
+//     its own 16-byte chunk with a branch-free separator mask and finds word
+//     starts with bit arithmetic, so no lane writes a shared container before
+//     its words are found.
+//   * SIMD hash (Section III-C): each lane hashes its own words (the
+//     SIMDH-Padding arrangement: lanes with shorter or fewer words idle until
+//     the wave's longest finishes). Words of up to 16 bytes are hashed as one
+//     zero-padded 16-byte block; longer words block by block.
+//   * combiner with a bounded local container (Sections III-A and III-D): a
+//     per-workgroup LDS hash table holds whole keys inline; when a key finds no
+//     free slot within a few probes it goes to the global table directly, and
+//     at the end of the workgroup's tiles the LDS table is flushed once. When
+//     every key fits, this degrades to a single flush, as the paper's
+//     pipelined model does when the final table is small.
+//   * global container (Section III-A hash table): open addressing with linear
+//     probing. A slot is one 64-bit word {occurrence offset:32, length:16,
+//     hash:16} claimed with a 64-bit CAS, plus a 32-bit count updated with
+//     atomicAdd. Because the claim word carries the offset of an occurrence in
+//     the (immutable) input, a thread that finds a matching tag compares the
+//     full key against input bytes that are already visible: no publication
+//     protocol or cache-wide fence is needed.
+//   * ordered output (Section II-A): a sample sort of the distinct keys in
+//     unsigned bytewise order, then key bytes, offsets and counts.
+#include "common.h"
+#include "jobs.h"
+#include "launch.h"
+
+namespace mr {
+
+// ----------------------------------------------------------------------------
+// byte access helpers
+// ----------------------------------------------------------------------------
+
+MR_DEV uint4 spaces4() { return make_uint4(0x20202020u, 0x20202020u, 0x20202020u, 0x20202020u); }
+
+// The 16-byte aligned block at absolute address blk, or spaces when the block
+// holds no byte of [a0, a1). A block that holds one valid byte lies inside the
+// caller's allocation (blocks never straddle a page), so the load is safe.
+MR_DEV uint4 load_block(uint64_t a0, uint64_t a1, uint64_t blk) {
+  if (blk + 16 > a0 && blk < a1) return *reinterpret_cast<const uint4*>(blk);
+  return spaces4();
+}
+
+// Bits [lo, hi) of a 32-bit mask (clamped to 0..32).
+MR_DEV uint32_t range_mask32(int64_t lo, int64_t hi) {
+  lo = lo < 0 ? 0 : lo;
+  hi = hi > 32 ? 32 : hi;
+  if (hi <= lo) return 0u;
+  return (uint32_t)(((1ull << hi) - 1ull) & ~((1ull << lo) - 1ull));
+}
+
+// Bytes [s, s + len) of a 32-byte window (w[0] = bytes 0..3), zero padded to
+// 16 bytes. Requires s <= 16 and len <= 16. Uses selects and byte funnel
+// shifts instead of dynamic register indexing.
+MR_DEV uint32_t sel32(bool c, uint32_t x, uint32_t y) { return c ? x : y; }
+
+MR_DEV uint4 extract16(const uint32_t w[8], uint32_t s, uint32_t len) {
+  // Written out by hand: a loop here is turned into a dynamically indexed
+  // private array (scratch memory) before it is unrolled.
+  const bool q2 = (s & 8u) != 0, q1 = (s & 4u) != 0;
+  const uint32_t rb = s & 3u;
+  const uint32_t w0 = w[0], w1 = w[1], w2 = w[2], w3 = w[3], w4 = w[4], w5 = w[5], w6 = w[6], w7 = w[7];
+  const uint32_t v0 = sel32(q2, w2, w0), v1 = sel32(q2, w3, w1), v2 = sel32(q2, w4, w2);
+  const uint32_t v3 = sel32(q2, w5, w3), v4 = sel32(q2, w6, w4), v5 = sel32(q2, w7, w5);
+  const uint32_t a0 = sel32(q1, v1, v0), a1 = sel32(q1, v2, v1), a2 = sel32(q1, v3, v2);
+  const uint32_t a3 = sel32(q1, v4, v3), a4 = sel32(q1, v5, v4);
+  const uint32_t r0 = __builtin_amdgcn_alignbyte(a1, a0, rb);
+  const uint32_t r1 = __builtin_amdgcn_alignbyte(a2, a1, rb);
+  const uint32_t r2 = __builtin_amdgcn_alignbyte(a3, a2, rb);
+  const uint32_t r3 = __builtin_amdgcn_alignbyte(a4, a3, rb);
+  return make_uint4(keep_bytes(r0, (int)len), keep_bytes(r1, (int)len - 4), keep_bytes(r2, (int)len - 8),
+                    keep_bytes(r3, (int)len - 12));
+}
+
+// The key of length len <= 16 that starts at input offset off, zero padded.
+MR_DEV uint4 load_key16(const uint8_t* in, uint64_t off, uint32_t len) {
+  const uint64_t a = (uint64_t)in + off;
+  const uint64_t blk = a & ~15ull;
+  const uint32_t s = (uint32_t)(a & 15u);
+  uint32_t w[8];
+  const uint4 b0 = *reinterpret_cast<const uint4*>(blk);
+  w[0] = b0.x; w[1] = b0.y; w[2] = b0.z; w[3] = b0.w;
+  if (s + len > 16u) {
+    const uint4 b1 = *reinterpret_cast<const uint4*>(blk + 16);
+    w[4] = b1.x; w[5] = b1.y; w[6] = b1.z; w[7] = b1.w;
+  } else {
+    w[4] = w[5] = w[6] = w[7] = 0u;
+  }
+  return extract16(w, s, len);
+}
+
+MR_DEV uint64_t key_hash16(uint4 k, uint32_t len, uint32_t debug_hash) {
+  if (debug_hash) return (uint64_t)len * 0x9E3779B97F4A7C15ULL;
+  return hash_block(hash_seed(len), ((uint64_t)k.y << 32) | k.x, ((uint64_t)k.w << 32) | k.z);
+}
+
+// Hash of a key of any length stored in the input, block by block; equal to
+// key_hash16 for len <= 16.
+MR_DEV uint64_t key_hash_global(const uint8_t* in, uint64_t off, uint64_t len, uint32_t debug_hash) {
+  if (debug_hash) return (uint64_t)(len < 0xFFFFu ? len : 0xFFFFu) * 0x9E3779B97F4A7C15ULL;
+  uint64_t h = hash_seed((uint32_t)(len < 0xFFFFFFFFull ? len : 0xFFFFFFFFull));
+  for (uint64_t b = 0; b < len; b += 16) {
+    const uint32_t take = (uint32_t)((len - b) < 16 ? (len - b) : 16);
+    const uint4 k = load_key16(in, off + b, take);
+    h = hash_block(h, ((uint64_t)k.y << 32) | k.x, ((uint64_t)k.w << 32) | k.z);
+  }
+  return h;
+}
+
+// Index of the first record offset >= pos (offsets may be malformed: the
+// search stays inside [0, n_rec] whatever their values).
+MR_DEV uint64_t rec_lower_bound(const uint64_t* rec, uint64_t n_rec, uint64_t pos) {
+  uint64_t lo = 0, hi = n_rec + 1;
+  while (lo < hi) {
+    const uint64_t mid = (lo + hi) >> 1;
+    if (rec[mid] < pos) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+// Length of the word starting at input offset start (slow path for long words).
+MR_DEV uint64_t word_length_slow(const WordJob& J, uint64_t vlo, uint64_t vhi, uint64_t start) {
+  uint64_t end = vhi;
+  if (J.rec) {
+    const uint64_t r = rec_lower_bound(J.rec, J.n_rec, start + 1);
+    if (r <= J.n_rec && J.rec[r] < end) end = J.rec[r];
+  }
+  uint64_t p = start + 1;
+  while (p < end && !is_sep_byte(J.in[p])) ++p;
+  return p - start;
+}
+
+// ----------------------------------------------------------------------------
+// global table
+// ----------------------------------------------------------------------------
+
+MR_DEV uint64_t gword(uint64_t off, uint64_t len, uint64_t h) {
+  return (off << 32) | ((len < 0xFFFFull ? len : 0xFFFFull) << 16) | (h >> 48);
+}
+
+// An occurrence offset read back from the table must lie inside the input;
+// anything else means the table was not clean, which is reported, never read.
+MR_DEV bool rep_in_bounds(const WordJob& J, uint64_t rep_off, uint64_t len) {
+  if (rep_off + len <= J.n) return true;
+  atomicOr(&J.st->flags, kFlagInternal);
+  return false;
+}
+
+// Full-key equality of a word given inline (len <= 16) against the occurrence at rep_off.
+MR_DEV bool rep_equals_inline(const WordJob& J, uint64_t rep_off, uint4 k, uint32_t len) {
+  if (!rep_in_bounds(J, rep_off, len)) return false;
+  const uint4 r = load_key16(J.in, rep_off, len);
+  return r.x == k.x && r.y == k.y && r.z == k.z && r.w == k.w;
+}
+
+// Full-key equality of two occurrences in the input with equal length tags.
+MR_DEV bool rep_equals_global(const WordJob& J, uint64_t vlo, uint64_t vhi, uint64_t rep_off, uint64_t off, uint64_t len) {
+  if (rep_off == off) return true;
+  if (!rep_in_bounds(J, rep_off, len)) return false;
+  // the length tag saturates at 0xFFFF: then compare the true lengths too
+  if (len >= 0xFFFFull && word_length_slow(J, vlo, vhi, rep_off) != len) return false;
+  for (uint64_t i = 0; i < len; ++i)
+    if (J.in[rep_off + i] != J.in[off + i]) return false;
+  return true;
+}
+
+// Insert one key with value v. Inline keys (len <= 16) come with k; longer
+// keys are compared against the input at off. Returns false on a full table.
+template <bool kInline>
+MR_DEV bool g_insert(const WordJob& J, uint64_t vlo, uint64_t vhi, uint64_t off, uint64_t len, uint64_t h, uint4 k,
+                     uint32_t v) {
+  const uint64_t word = gword(off, len, h);
+  const uint64_t mask = J.cap - 1;
+  uint64_t i = h & mask;
+  for (uint64_t p = 0; p <= mask; ++p) {
+    // A relaxed load may be stale only as 0 (slots are written once per run);
+    // the CAS below then returns the current word.
+    unsigned long long cur = __hip_atomic_load(&J.tw[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (cur == 0ull) {
+      const unsigned long long old = atomicCAS(&J.tw[i], 0ull, (unsigned long long)word);
+      if (old == 0ull) {
+        atomicAdd(&J.tc[i], v);
+        return true;
+      }
+      cur = old;
+    }
+    if ((uint32_t)cur == (uint32_t)word) {
+      const uint64_t rep = cur >> 32;
+      const bool eq = kInline ? rep_equals_inline(J, rep, k, (uint32_t)len) : rep_equals_global(J, vlo, vhi, rep, off, len);
+      if (eq) {
+        atomicAdd(&J.tc[i], v);
+        return true;
+      }
+    }
+    i = (i + 1) & mask;
+    if ((p & 255u) == 255u &&
+        (__hip_atomic_load(&J.st->flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kFlagTableFull))
+      return false;
+  }
+  atomicOr(&J.st->flags, kFlagTableFull);
+  return false;
+}
+
+// ----------------------------------------------------------------------------
+// prep: validate record offsets and publish the valid byte range
+// ----------------------------------------------------------------------------
+
+__global__ void k_words_prep(const WordJob* __restrict__ jobs, uint32_t n_jobs) {
+  const uint32_t j = blockIdx.y;
+  if (j >= n_jobs) return;
+  const WordJob J = jobs[j];
+  if (!J.rec) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      J.st->valid_lo = 0;
+      J.st->valid_hi = J.n;
+    }
+    return;
+  }
+  bool bad = false;
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < J.n_rec; i += (uint64_t)gridDim.x * blockDim.x)
+    if (J.rec[i] > J.rec[i + 1]) bad = true;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (J.rec[J.n_rec] > J.n) bad = true;
+    J.st->valid_lo = J.rec[0] < J.n ? J.rec[0] : J.n;
+    J.st->valid_hi = J.rec[J.n_rec] < J.n ? J.rec[J.n_rec] : J.n;
+  }
+  if (bad) atomicOr(&J.st->flags, kFlagBadInput);
+}
+
+// ----------------------------------------------------------------------------
+// map + combine
+// ----------------------------------------------------------------------------
+
+constexpr int kLdsProbe = 16;
+
+template <int kSlotsLog2>
+struct LdsTable {
+  static constexpr uint32_t kSlots = 1u << kSlotsLog2;
+  uint32_t tag[kSlots];   // 0 empty; bit0 ready; bits 1..5 length; bits 6..31 hash
+  uint4 key[kSlots];
+  uint32_t cnt[kSlots];
+  uint32_t off[kSlots];   // offset of one occurrence, for the global flush
+};
+
+MR_DEV uint32_t lds_tag(uint64_t h, uint32_t len) { return ((uint32_t)(h >> 32) & 0xFFFFFFC0u) | (len << 1); }
+
+// 0 = done, 1 = slot being written by another lane (retry), 2 = no slot within the probe limit
+template <int L>
+MR_DEV int lds_insert(LdsTable<L>& T, uint32_t tg, uint32_t slot, uint4 k, uint32_t off) {
+  uint32_t i = slot & (LdsTable<L>::kSlots - 1);
+  for (int p = 0; p < kLdsProbe; ++p) {
+    uint32_t cur = __hip_atomic_load(&T.tag[i], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (cur == 0u) {
+      const uint32_t old = atomicCAS(&T.tag[i], 0u, tg);
+      if (old == 0u) {
+        T.key[i] = k;
+        T.off[i] = off;
+        T.cnt[i] = 1u;
+        __hip_atomic_store(&T.tag[i], tg | 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+        return 0;
+      }
+      return 1;  // lost the race: look again next round
+    }
+    if ((cur | 1u) == (tg | 1u)) {
+      if (!(cur & 1u)) return 1;
+      const uint4 kk = T.key[i];
+      if (kk.x == k.x && kk.y == k.y && kk.z == k.z && kk.w == k.w) {
+        atomicAdd(&T.cnt[i], 1u);
+        return 0;
+      }
+    }
+    i = (i + 1) & (LdsTable<L>::kSlots - 1);
+  }
+  return 2;
+}
+
+template <int L>
+MR_DEV void lds_flush(LdsTable<L>& T, const WordJob& J, uint64_t vlo, uint64_t vhi, uint32_t debug_hash) {
+  for (uint32_t i = threadIdx.x; i < LdsTable<L>::kSlots; i += blockDim.x) {
+    const uint32_t tg = T.tag[i];
+    if (tg & 1u) {
+      const uint32_t len = (tg >> 1) & 31u;
+      const uint4 k = T.key[i];
+      const uint64_t h = key_hash16(k, len, debug_hash);
+      g_insert<true>(J, vlo, vhi, T.off[i], len, h, k, T.cnt[i]);
+    }
+    T.tag[i] = 0u;
+  }
+}
+
+MR_DEV uint32_t find_job(const uint64_t* __restrict__ tile_base, uint32_t n_jobs, uint64_t t) {
+  uint32_t lo = 0, hi = n_jobs;  // last j with tile_base[j] <= t
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (tile_base[mid] <= t) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+template <int L, bool kRecords>
+__global__ __launch_bounds__(kMapThreads) void k_words_map(const WordJob* __restrict__ jobs, const uint64_t* __restrict__ tile_base,
+                                                           uint32_t n_jobs, uint64_t total_tiles, uint32_t debug_hash) {
+  __shared__ LdsTable<L> T;
+  constexpr uint32_t kBndWords = kMapTileChunks * 16 / 32 + 2;
+  __shared__ uint32_t bnd[kRecords ? kBndWords : 1];
+  __shared__ uint32_t s_abort;
+
+  for (uint32_t i = threadIdx.x; i < LdsTable<L>::kSlots; i += blockDim.x) T.tag[i] = 0u;
+  if (threadIdx.x == 0) s_abort = 0;
+  __syncthreads();
+
+  const uint64_t t_begin = total_tiles * blockIdx.x / gridDim.x;
+  const uint64_t t_end = total_tiles * (blockIdx.x + 1) / gridDim.x;
+  const uint32_t wave = threadIdx.x / kWave;
+  const uint32_t lane = lane_id();
+  int cur = -1;
+  uint64_t vlo = 0, vhi = 0;
+
+  for (uint64_t t = t_begin; t < t_end; ++t) {
+    const uint32_t j = find_job(tile_base, n_jobs, t);
+    if ((int)j != cur) {
+      if (cur >= 0) {
+        __syncthreads();
+        lds_flush<L>(T, jobs[cur], vlo, vhi, debug_hash);
+        __syncthreads();
+      }
+      cur = (int)j;
+      vlo = jobs[j].st->valid_lo;
+      vhi = jobs[j].st->valid_hi;
+    }
+    const WordJob& J = jobs[j];
+    if (threadIdx.x == 0)
+      s_abort = (__hip_atomic_load(&J.st->flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & (kFlagTableFull | kFlagBadInput)) ? 1u : 0u;
+    const uint64_t lt = t - tile_base[j];
+    const uint64_t a0 = (uint64_t)J.in, a1 = a0 + J.n;
+    const uint64_t tile_addr = (J.chunk0 + lt * kMapTileChunks) * 16;
+
+    if constexpr (kRecords) {
+      __syncthreads();
+      for (uint32_t i = threadIdx.x; i < kBndWords; i += blockDim.x) bnd[i] = 0u;
+      __syncthreads();
+      // record boundaries falling in [tile_addr, tile_addr + 32 * kBndWords)
+      const int64_t lo_rel = (int64_t)(tile_addr - a0);
+      const uint64_t r0 = rec_lower_bound(J.rec, J.n_rec, lo_rel < 0 ? 0 : (uint64_t)lo_rel);
+      for (uint64_t r = r0 + threadIdx.x; r <= J.n_rec; r += blockDim.x) {
+        const uint64_t pa = a0 + J.rec[r];
+        if (pa < tile_addr) continue;
+        const uint64_t bit = pa - tile_addr;
+        if (bit >= 32ull * kBndWords) break;
+        atomicOr(&bnd[bit >> 5], 1u << (bit & 31));
+      }
+    }
+    __syncthreads();
+    if (s_abort) continue;
+
+    const uint64_t c = lt * kMapTileChunks + wave * kWave + lane;  // this lane's chunk
+    const uint64_t B = (J.chunk0 + c) * 16;                         // its absolute address
+    uint32_t w[8];
+    {
+      const uint4 b0 = c < J.n_chunks ? load_block(a0, a1, B) : spaces4();
+      const uint4 b1 = c + 1 < J.n_chunks ? load_block(a0, a1, B + 16) : spaces4();
+      w[0] = b0.x; w[1] = b0.y; w[2] = b0.z; w[3] = b0.w;
+      w[4] = b1.x; w[5] = b1.y; w[6] = b1.z; w[7] = b1.w;
+    }
+    const uint32_t valid = range_mask32((int64_t)(a0 + vlo) - (int64_t)B, (int64_t)(a0 + vhi) - (int64_t)B);
+    const uint32_t sep = (sep_mask16(w[0], w[1], w[2], w[3]) | (sep_mask16(w[4], w[5], w[6], w[7]) << 16)) | ~valid;
+    uint32_t bd = 0u;
+    if constexpr (kRecords) {
+      const uint64_t bit = B - tile_addr;  // multiple of 16
+      const uint32_t wi = (uint32_t)(bit >> 5);
+      const uint32_t lo = bnd[wi], hi = bnd[wi + 1];
+      bd = (bit & 16) ? ((lo >> 16) | (hi << 16)) : lo;
+    }
+    uint32_t prev = (uint32_t)__shfl_up((int)((sep >> 15) & 1u), 1);
+    if (lane == 0) {
+      // byte B - 1 lives in the previous chunk
+      const uint64_t pb = B - 1;
+      bool ps = true;
+      if (pb >= a0 + vlo && pb < a0 + vhi) {
+        const uint4 q = load_block(a0, a1, B - 16);
+        ps = (sep_mask4(q.w) >> 3) & 1u;
+      }
+      prev = ps ? 1u : 0u;
+    }
+    uint32_t starts = ~sep & ((sep << 1) | prev | bd) & 0xFFFFu;
+    const uint32_t ends = sep | bd;
+
+    while (starts) {
+      const uint32_t s = __builtin_ctz(starts);
+      starts &= starts - 1u;
+      const uint32_t after = ends & ~((2u << s) - 1u);
+      const uint32_t e = after ? (uint32_t)__builtin_ctz(after) : 32u;
+      const uint64_t off = B + s - a0;
+      if (after == 0u || e - s > 16u) {
+        // long word: measure and hash it from memory, insert globally
+        const uint64_t len = word_length_slow(J, vlo, vhi, off);
+        const uint64_t h = key_hash_global(J.in, off, len, debug_hash);
+        g_insert<false>(J, vlo, vhi, off, len, h, make_uint4(0, 0, 0, 0), 1u);
+        continue;
+      }
+      const uint32_t len = e - s;
+      const uint4 k = extract16(w, s, len);
+      const uint64_t h = key_hash16(k, len, debug_hash);
+      const uint32_t tg = lds_tag(h, len);
+      int r = 1;
+      for (uint32_t spin = 0; r == 1; ++spin) {
+        r = lds_insert<L>(T, tg, (uint32_t)h, k, (uint32_t)off);
+        if (r == 1 && spin > (1u << 22)) {
+          atomicOr(&J.st->flags, kFlagSpin);
+          r = 0;
+        }
+      }
+      if (r == 2) g_insert<true>(J, vlo, vhi, off, len, h, k, 1u);
+    }
+  }
+  __syncthreads();
+  if (cur >= 0) lds_flush<L>(T, jobs[cur], vlo, vhi, debug_hash);
+}
+
+// ----------------------------------------------------------------------------
+// compaction: table slots -> records (and the table is cleared for reuse)
+// ----------------------------------------------------------------------------
+
+constexpr uint32_t kCompactThreads = 256;
+
+__global__ __launch_bounds__(kCompactThreads) void k_words_compact(const WordJob* __restrict__ jobs, uint32_t n_jobs,
+                                                                   uint64_t total_slots) {
+  __shared__ uint32_t s_cnt;
+  __shared__ unsigned long long s_base;
+  __shared__ unsigned long long s_bytes;
+  for (uint64_t t0 = (uint64_t)blockIdx.x * kCompactThreads; t0 < total_slots; t0 += (uint64_t)gridDim.x * kCompactThreads) {
+    // tables are powers of two >= 4096 slots at 4096-aligned arena offsets: a tile is in one job
+    uint32_t lo = 0, hi = n_jobs;
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (jobs[mid].slot_base <= t0) lo = mid; else hi = mid;
+    }
+    const WordJob& J = jobs[lo];
+    const uint64_t i = t0 - J.slot_base + threadIdx.x;
+    if (threadIdx.x == 0) {
+      s_cnt = 0;
+      s_bytes = 0;
+    }
+    __syncthreads();
+    unsigned long long w = 0;
+    uint32_t cnt = 0;
+    if (i < J.cap) {
+      w = J.tw[i];
+      if (w) {
+        cnt = J.tc[i];
+        J.tw[i] = 0ull;
+        J.tc[i] = 0u;
+        if (!rep_in_bounds(J, w >> 32, (w >> 16) & 0xFFFFull)) w = 0;  // reported, skipped
+      }
+    }
+    uint32_t my = 0;
+    if (w) my = atomicAdd(&s_cnt, 1u);
+    __syncthreads();
+    if (threadIdx.x == 0) s_base = s_cnt ? atomicAdd(&J.st->n_recs, (unsigned long long)s_cnt) : 0ull;
+    __syncthreads();
+    if (w) {
+      const uint64_t off = w >> 32;
+      uint64_t len = (w >> 16) & 0xFFFFull;
+      if (len == 0xFFFFull) len = word_length_slow(J, J.st->valid_lo, J.st->valid_hi, off);
+      const uint4 k = load_key16(J.in, off, (uint32_t)(len < 16 ? len : 16));
+      WRec r;
+      r.p[0] = bswap32(k.x); r.p[1] = bswap32(k.y); r.p[2] = bswap32(k.z); r.p[3] = bswap32(k.w);
+      r.len = (uint32_t)len;
+      r.off = (uint32_t)off;
+      r.cnt = cnt;
+      r.pad = 0;
+      reinterpret_cast<WRec*>(J.recs)[s_base + my] = r;
+      atomicAdd(&s_bytes, (unsigned long long)len);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && s_bytes) atomicAdd(&J.st->key_bytes, s_bytes);
+  }
+}
+
+// ----------------------------------------------------------------------------
+// sample sort of the distinct keys (unsigned bytewise order, prefix first)
+// ----------------------------------------------------------------------------
+
+// Three-way compare of two records of the same job.
+MR_DEV int wrec_cmp(const WordJob& J, const WRec& a, const WRec& b) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+    if (a.p[q] != b.p[q]) return a.p[q] < b.p[q] ? -1 : 1;
+  if (a.len > 16u && b.len > 16u) {
+    const uint32_t m = (a.len < b.len ? a.len : b.len);
+    for (uint32_t i = 16; i < m; ++i) {
+      const uint8_t x = J.in[a.off + i], y = J.in[b.off + i];
+      if (x != y) return x < y ? -1 : 1;
+    }
+  }
+  return a.len < b.len ? -1 : (a.len > b.len ? 1 : 0);
+}
+
+// Bitonic sort (all-ascending "flip" form) of a[0, m) by the whole workgroup.
+// Indices >= m act as +infinity and are never touched, so no padding is
+// needed; works on LDS or global memory (callers synchronise the workgroup).
+MR_DEV void bitonic_sort(const WordJob& J, WRec* a, uint32_t m) {
+  uint32_t n = 1;
+  while (n < m) n <<= 1;
+  for (uint32_t k = 2; k <= n; k <<= 1) {
+    for (uint32_t jj = k >> 1; jj > 0; jj >>= 1) {
+      for (uint32_t t = threadIdx.x; t < n / 2; t += blockDim.x) {
+        // t-th pair: i has bit jj clear
+        const uint32_t i = ((t & ~(jj - 1)) << 1) | (t & (jj - 1));
+        const uint32_t l = (jj == (k >> 1)) ? (i ^ (k - 1)) : (i | jj);
+        if (l < m) {
+          const WRec x = a[i], y = a[l];
+          if (wrec_cmp(J, x, y) > 0) {
+            a[i] = y;
+            a[l] = x;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+constexpr uint32_t kSortThreads = 1024;
+constexpr uint32_t kOversample = 4;
+
+// Plan the sort of every job: bucket counts and global bucket / record-tile bases.
+__global__ void k_sort_plan(const WordJob* __restrict__ jobs, uint32_t n_jobs, uint32_t* totals /*[2]*/) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  uint32_t bb = 0, rt = 0;
+  for (uint32_t j = 0; j < n_jobs; ++j) {
+    JobState* st = jobs[j].st;
+    const uint64_t n = st->n_recs;
+    uint32_t nb = 1;
+    if (n > kBucketCap) {
+      const uint64_t want = (n + 511) / 512;
+      nb = (uint32_t)(want < kMaxBuckets ? want : kMaxBuckets);
+    }
+    st->nb = nb;
+    st->bucket_base = bb;
+    st->rtile_base = rt;
+    bb += nb;
+    rt += (uint32_t)((n + kRecTile - 1) / kRecTile);
+  }
+  totals[0] = bb;
+  totals[1] = rt;
+}
+
+// Splitters of one job: sort an evenly spaced sample, keep every kOversample-th.
+__global__ __launch_bounds__(kSortThreads) void k_sort_splitters(const WordJob* __restrict__ jobs, uint32_t n_jobs,
+                                                                  uint32_t* bucket_cnt, unsigned long long* bucket_bytes,
+                                                                  uint32_t* bucket_fill) {
+  __shared__ WRec smp[kMaxBuckets * kOversample];
+  const uint32_t j = blockIdx.x;
+  if (j >= n_jobs) return;
+  const WordJob& J = jobs[j];
+  const uint32_t nb = J.st->nb;
+  const uint32_t bb = J.st->bucket_base;
+  for (uint32_t b = threadIdx.x; b < nb; b += blockDim.x) {
+    bucket_cnt[bb + b] = 0;
+    bucket_bytes[bb + b] = 0;
+    bucket_fill[bb + b] = 0;
+  }
+  if (nb <= 1) return;
+  const uint64_t n = J.st->n_recs;
+  const uint32_t S = nb * kOversample;
+  const WRec* recs = reinterpret_cast<const WRec*>(J.recs);
+  for (uint32_t i = threadIdx.x; i < S; i += blockDim.x) smp[i] = recs[(uint64_t)i * n / S];
+  __syncthreads();
+  bitonic_sort(J, smp, S);
+  WRec* spl = reinterpret_cast<WRec*>(J.splitters);
+  for (uint32_t b = threadIdx.x; b + 1 < nb; b += blockDim.x) spl[b] = smp[(b + 1) * kOversample - 1];
+}
+
+// Bucket of each record: number of splitters strictly below it.
+MR_DEV uint32_t bucket_of(const WordJob& J, const WRec* spl, uint32_t nb, const WRec& r) {
+  uint32_t lo = 0, hi = nb - 1;  // count of splitters < r, in [0, nb - 1]
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (wrec_cmp(J, spl[mid], r) < 0) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+MR_DEV uint32_t find_rtile_job(const WordJob* jobs, uint32_t n_jobs, uint32_t t) {
+  uint32_t lo = 0, hi = n_jobs;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (jobs[mid].st->rtile_base <= t) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(256) void k_sort_count(const WordJob* __restrict__ jobs, uint32_t n_jobs, const uint32_t* totals,
+                                                    uint32_t* bucket_cnt, unsigned long long* bucket_bytes) {
+  __shared__ WRec spl[kMaxBuckets - 1];
+  __shared__ uint32_t h_cnt[kMaxBuckets];
+  __shared__ unsigned long long h_bytes[kMaxBuckets];
+  const uint32_t n_tiles = totals[1];
+  for (uint32_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
+    const uint32_t j = find_rtile_job(jobs, n_jobs, t);
+    const WordJob& J = jobs[j];
+    const uint32_t nb = J.st->nb;
+    const uint64_t n = J.st->n_recs;
+    const uint64_t r0 = (uint64_t)(t - J.st->rtile_base) * kRecTile;
+    __syncthreads();
+    for (uint32_t b = threadIdx.x; b < nb; b += blockDim.x) {
+      h_cnt[b] = 0;
+      h_bytes[b] = 0;
+      if (b + 1 < nb) spl[b] = reinterpret_cast<const WRec*>(J.splitters)[b];
+    }
+    __syncthreads();
+    const WRec* recs = reinterpret_cast<const WRec*>(J.recs);
+    for (uint32_t q = threadIdx.x; q < kRecTile; q += blockDim.x) {
+      const uint64_t i = r0 + q;
+      if (i >= n) break;
+      const WRec r = recs[i];
+      const uint32_t b = nb > 1 ? bucket_of(J, spl, nb, r) : 0u;
+      J.rec_bucket[i] = b;
+      atomicAdd(&h_cnt[b], 1u);
+      atomicAdd(&h_bytes[b], (unsigned long long)r.len);
+    }
+    __syncthreads();
+    const uint32_t bb = J.st->bucket_base;
+    for (uint32_t b = threadIdx.x; b < nb; b += blockDim.x) {
+      if (h_cnt[b]) {
+        atomicAdd(&bucket_cnt[bb + b], h_cnt[b]);
+        atomicAdd(&bucket_bytes[bb + b], h_bytes[b]);
+      }
+    }
+  }
+}
+
+// Exclusive scans of one job's bucket counts and bytes; capacity check.
+__global__ __launch_bounds__(kSortThreads) void k_sort_scan(const WordJob* __restrict__ jobs, uint32_t n_jobs,
+                                                             const uint32_t* bucket_cnt, const unsigned long long* bucket_bytes,
+                                                             uint32_t* bucket_start, unsigned long long* bucket_bstart) {
+  const uint32_t j = blockIdx.x;
+  if (j >= n_jobs) return;
+  const WordJob& J = jobs[j];
+  if (threadIdx.x != 0) return;
+  const uint32_t nb = J.st->nb, bb = J.st->bucket_base;
+  uint32_t c = 0;
+  unsigned long long y = 0;
+  for (uint32_t b = 0; b < nb; ++b) {
+    bucket_start[bb + b] = c;
+    bucket_bstart[bb + b] = y;
+    c += bucket_cnt[bb + b];
+    y += bucket_bytes[bb + b];
+  }
+  if (J.st->n_recs > J.cap_keys || J.st->key_bytes > J.cap_key_bytes) atomicOr(&J.st->flags, kFlagCapacity);
+}
+
+__global__ __launch_bounds__(256) void k_sort_scatter(const WordJob* __restrict__ jobs, uint32_t n_jobs, const uint32_t* totals,
+                                                      const uint32_t* bucket_start, uint32_t* bucket_fill) {
+  const uint32_t n_tiles = totals[1];
+  for (uint32_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
+    const uint32_t j = find_rtile_job(jobs, n_jobs, t);
+    const WordJob& J = jobs[j];
+    const uint64_t n = J.st->n_recs;
+    const uint64_t r0 = (uint64_t)(t - J.st->rtile_base) * kRecTile;
+    const uint32_t bb = J.st->bucket_base;
+    const WRec* recs = reinterpret_cast<const WRec*>(J.recs);
+    WRec* out = reinterpret_cast<WRec*>(J.recs2);
+    for (uint32_t q = threadIdx.x; q < kRecTile; q += blockDim.x) {
+      const uint64_t i = r0 + q;
+      if (i >= n) break;
+      const uint32_t b = J.rec_bucket[i];
+      const uint32_t pos = bucket_start[bb + b] + atomicAdd(&bucket_fill[bb + b], 1u);
+      out[pos] = recs[i];
+    }
+  }
+}
+
+MR_DEV uint32_t find_bucket_job(const WordJob* jobs, uint32_t n_jobs, uint32_t g) {
+  uint32_t lo = 0, hi = n_jobs;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (jobs[mid].st->bucket_base <= g) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+// Sort each bucket and write the job's outputs for it.
+__global__ __launch_bounds__(kSortThreads) void k_sort_buckets(const WordJob* __restrict__ jobs, uint32_t n_jobs, const uint32_t* totals,
+                                                                const uint32_t* bucket_cnt, const uint32_t* bucket_start,
+                                                                const unsigned long long* bucket_bstart) {
+  __shared__ WRec a[kBucketCap];
+  __shared__ uint64_t wsum[kSortThreads / kWave];
+  const uint32_t n_buckets = totals[0];
+  for (uint32_t g = blockIdx.x; g < n_buckets; g += gridDim.x) {
+    const uint32_t j = find_bucket_job(jobs, n_jobs, g);
+    const WordJob& J = jobs[j];
+    const uint32_t m = bucket_cnt[g];
+    const uint32_t s0 = bucket_start[g];
+    const uint64_t y0 = bucket_bstart[g];
+    const bool write = !(__hip_atomic_load(&J.st->flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kFlagCapacity);
+    WRec* src = reinterpret_cast<WRec*>(J.recs2) + s0;
+    __syncthreads();
+    if (m == 0) continue;
+    const bool in_lds = m <= kBucketCap;
+    WRec* arr = in_lds ? a : src;
+    if (in_lds) {
+      for (uint32_t i = threadIdx.x; i < m; i += blockDim.x) a[i] = src[i];
+      __syncthreads();
+    } else if (threadIdx.x == 0) {
+      atomicOr(&J.st->flags, kFlagSortFallback);  // rare: sort the bucket in global memory
+    }
+    bitonic_sort(J, arr, m);
+    if (!write) continue;
+    // byte positions: exclusive scan of lengths in chunks of blockDim
+    uint64_t carry = 0;
+    for (uint32_t base = 0; base < m; base += blockDim.x) {
+      const uint32_t i = base + threadIdx.x;
+      const uint64_t len = i < m ? arr[i].len : 0;
+      // wave inclusive scan
+      uint64_t x = len;
+      const uint32_t ln = lane_id();
+#pragma unroll
+      for (int o = 1; o < kWave; o <<= 1) {
+        const uint64_t y = __shfl_up(x, o);
+        if (ln >= (uint32_t)o) x += y;
+      }
+      if (ln == kWave - 1) wsum[threadIdx.x / kWave] = x;
+      __syncthreads();
+      uint64_t wpre = 0;
+      const uint32_t wv = threadIdx.x / kWave;
+      for (uint32_t q = 0; q < wv; ++q) wpre += wsum[q];
+      uint64_t tot = 0;
+      for (uint32_t q = 0; q < blockDim.x / kWave; ++q) tot += wsum[q];
+      const uint64_t excl = carry + wpre + x - len;
+      if (i < m) {
+        const WRec r = arr[i];
+        const uint64_t o = y0 + excl;
+        J.out_key_offsets[s0 + i] = o;
+        J.out_values[s0 + i] = r.cnt;
+        for (uint32_t b = 0; b < r.len; ++b) J.out_key_bytes[o + b] = J.in[r.off + b];
+      }
+      carry += tot;
+      __syncthreads();
+    }
+  }
+}
+
+// Final entry of each job's key offsets (the total number of key bytes).
+__global__ void k_words_finish(const WordJob* __restrict__ jobs, uint32_t n_jobs) {
+  for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < n_jobs; j += gridDim.x * blockDim.x) {
+    const WordJob& J = jobs[j];
+    if (J.out_key_offsets && !(J.st->flags & kFlagCapacity)) J.out_key_offsets[J.st->n_recs] = J.st->key_bytes;
+  }
+}
+
+// ----------------------------------------------------------------------------
+// host side
+// ----------------------------------------------------------------------------
+
+int words_max_lds_log2() { return 12; }
+
+hipError_t words_enqueue_prep(const WordsLaunch& L, hipStream_t s) {
+  if (L.any_records) {
+    dim3 g(64, L.n_jobs);
+    hipLaunchKernelGGL(k_words_prep, g, dim3(256), 0, s, L.jobs, L.n_jobs);
+  } else {
+    dim3 g(1, L.n_jobs);
+    hipLaunchKernelGGL(k_words_prep, g, dim3(64), 0, s, L.jobs, L.n_jobs);
+  }
+  return hipGetLastError();
+}
+
+hipError_t words_enqueue_map(const WordsLaunch& L, hipStream_t s) {
+  const dim3 grid(L.map_grid), block(kMapThreads);
+#define MR_MAP_CASE(LG)                                                                                       \
+  case LG:                                                                                                     \
+    if (L.any_records)                                                                                         \
+      hipLaunchKernelGGL((k_words_map<LG, true>), grid, block, 0, s, L.jobs, L.tile_base, L.n_jobs, L.total_tiles, \
+                         L.debug_hash);                                                                        \
+    else                                                                                                       \
+      hipLaunchKernelGGL((k_words_map<LG, false>), grid, block, 0, s, L.jobs, L.tile_base, L.n_jobs, L.total_tiles, \
+                         L.debug_hash);                                                                        \
+    break;
+  switch (L.lds_log2) {
+    MR_MAP_CASE(8)
+    MR_MAP_CASE(10)
+    MR_MAP_CASE(11)
+    MR_MAP_CASE(12)
+    default:
+      return hipErrorInvalidValue;
+  }
+#undef MR_MAP_CASE
+  return hipGetLastError();
+}
+
+hipError_t words_enqueue_reduce(const WordsLaunch& L, hipStream_t s) {
+  const uint64_t tiles = (L.total_slots + kCompactThreads - 1) / kCompactThreads;
+  const uint32_t cgrid = (uint32_t)(tiles < 4096 ? tiles : 4096);
+  hipLaunchKernelGGL(k_words_compact, dim3(cgrid ? cgrid : 1), dim3(kCompactThreads), 0, s, L.jobs, L.n_jobs, L.total_slots);
+  hipLaunchKernelGGL(k_sort_plan, dim3(1), dim3(64), 0, s, L.jobs, L.n_jobs, L.totals);
+  hipLaunchKernelGGL(k_sort_splitters, dim3(L.n_jobs), dim3(kSortThreads), 0, s, L.jobs, L.n_jobs, L.bucket_cnt,
+                     L.bucket_bytes, L.bucket_fill);
+  hipLaunchKernelGGL(k_sort_count, dim3(L.sort_grid), dim3(256), 0, s, L.jobs, L.n_jobs, L.totals, L.bucket_cnt, L.bucket_bytes);
+  hipLaunchKernelGGL(k_sort_scan, dim3(L.n_jobs), dim3(64), 0, s, L.jobs, L.n_jobs, L.bucket_cnt, L.bucket_bytes,
+                     L.bucket_start, L.bucket_bstart);
+  hipLaunchKernelGGL(k_sort_scatter, dim3(L.sort_grid), dim3(256), 0, s, L.jobs, L.n_jobs, L.totals, L.bucket_start,
+                     L.bucket_fill);
+  hipLaunchKernelGGL(k_sort_buckets, dim3(L.sort_grid), dim3(kSortThreads), 0, s, L.jobs, L.n_jobs, L.totals, L.bucket_cnt,
+                     L.bucket_start, L.bucket_bstart);
+  hipLaunchKernelGGL(k_words_finish, dim3(1), dim3(256), 0, s, L.jobs, L.n_jobs);
+  return hipGetLastError();
+}
+
+}  // namespace mr

@@ -1,0 +1,194 @@
+"""GPU parity of word count (MR_MAP_WORDS) against the CPU oracle, element by element.
+
+Cases: hand-worked inputs, random bytes with every separator, NUL and high
+bytes, words that straddle 16-byte chunks and 16 KiB tiles, words longer than
+16 and 32 bytes, unaligned input pointers, record offsets, forced hash
+collisions, a table too small at the start (regrowth), output buffers too
+small (capacity error), malformed offsets, and the full 8 MiB Zipf text.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import gen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    return t
+
+
+@pytest.fixture(scope="module")
+def job(torch):
+    from paper_1309_0215_amd import Job
+    return Job(device=0)
+
+
+def _dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def _check(res, buf, offs=None):
+    exp = oracle.words(buf, offs)
+    kb = res.key_bytes.cpu().numpy()
+    ko = res.key_offsets.cpu().numpy().astype(np.uint64)
+    v = res.values.cpu().numpy().astype(np.uint32).astype(np.uint64)
+    assert len(v) == len(exp.values), (len(v), len(exp.values))
+    assert np.array_equal(ko, exp.key_offsets)
+    assert np.array_equal(kb, exp.key_bytes)
+    assert np.array_equal(v, exp.values)
+
+
+def test_golden_hand_cases(torch, job):
+    cases = json.load(open(os.path.join(GOLDEN, "words_hand.json")))["cases"]
+    for c in cases:
+        buf = np.frombuffer(c["input"].encode("latin-1"), np.uint8)
+        offs = None if c["offsets"] is None else np.array(c["offsets"], np.uint64)
+        d = _dev(torch, buf) if len(buf) else torch.empty(0, dtype=torch.uint8, device="cuda:0")
+        ro = None if offs is None else _dev(torch, offs.astype(np.int64))
+        res = job.words(d, ro)
+        got = res.items()
+        exp = [(k.encode("latin-1"), v) for k, v in c["expect"]]
+        assert got == exp, (c["input"], got, exp)
+
+
+WS = list(b" \t\n\x0b\x0c\r")
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_random_bytes(torch, job, seed):
+    rng = np.random.default_rng(seed)
+    alphabet = np.array(list(b"abc") + WS + [0, 0x80, 0xFF])
+    n = int(rng.integers(1, 200_000))
+    buf = rng.choice(alphabet, size=n).astype(np.uint8)
+    _check(job.words(_dev(torch, buf)), buf)
+
+
+@pytest.mark.parametrize("maxlen", [15, 16, 17, 31, 32, 33, 70, 300])
+def test_word_lengths_across_chunks(torch, job, maxlen):
+    rng = np.random.default_rng(maxlen)
+    parts = []
+    total = 0
+    while total < 150_000:
+        L = int(rng.integers(1, maxlen + 1))
+        w = bytes(rng.integers(97, 100, size=L).astype(np.uint8))
+        parts.append(w + (b" " if rng.random() < 0.8 else b"\n\t"))
+        total += L + 1
+    buf = np.frombuffer(b"".join(parts), np.uint8)
+    _check(job.words(_dev(torch, buf)), buf)
+
+
+@pytest.mark.parametrize("shift", [1, 3, 7, 15])
+def test_unaligned_input(torch, job, shift):
+    buf = gen.text(3, 100_003, V=3000, s=1.0)
+    big = torch.zeros(len(buf) + 64, dtype=torch.uint8, device="cuda:0")
+    big[shift:shift + len(buf)] = _dev(torch, buf)
+    _check(job.words(big[shift:shift + len(buf)]), buf)
+
+
+def test_no_separators_and_all_separators(torch, job):
+    one = np.full(1 << 20, ord("x"), np.uint8)  # one 1 MiB word
+    _check(job.words(_dev(torch, one)), one)
+    sp = np.full(300_000, ord(" "), np.uint8)
+    _check(job.words(_dev(torch, sp)), sp)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_records(torch, job, seed):
+    rng = np.random.default_rng(50 + seed)
+    buf = gen.text(7 + seed, 200_000, V=500, s=0.8)
+    cuts = np.sort(rng.integers(0, len(buf) + 1, size=int(rng.integers(1, 3000)))).astype(np.uint64)
+    if seed == 0:
+        cuts = np.concatenate([[0], cuts, [len(buf)]]).astype(np.uint64)
+    _check(job.words(_dev(torch, buf), _dev(torch, cuts.astype(np.int64))), buf, cuts)
+
+
+def test_records_every_line(torch, job):
+    buf = gen.text(9, 1 << 20)
+    nl = np.flatnonzero(buf == ord("\n")) + 1
+    offs = np.concatenate([[0], nl[nl < len(buf)], [len(buf)]]).astype(np.uint64)
+    _check(job.words(_dev(torch, buf), _dev(torch, offs.astype(np.int64))), buf, offs)
+
+
+def test_malformed_offsets(torch, job):
+    from paper_1309_0215_amd import MRError
+    buf = gen.text(1, 10_000, V=100)
+    for bad in ([0, 5000, 4000, 10_000], [0, 20_000]):
+        with pytest.raises(MRError) as e:
+            job.words(_dev(torch, buf), _dev(torch, np.array(bad, np.int64)))
+        assert e.value.status == -1
+
+
+def test_forced_hash_collisions(torch):
+    from paper_1309_0215_amd import Job
+    j = Job(device=0, debug_hash=1)
+    buf = gen.text(5, 60_000, V=800, s=0.7, lmin=3, lmax=20)
+    _check(j.words(_dev(torch, buf)), buf)
+
+
+def test_table_regrowth(torch):
+    from paper_1309_0215_amd import Job
+    j = Job(device=0, table_slots=4096, lds_slots=256)
+    buf = gen.text(6, 1 << 20, V=20_000, s=0.5)
+    res = j.words(_dev(torch, buf))
+    _check(res, buf)
+    assert res.stats["retries"] >= 1 and res.stats["table_slots"] > 4096
+
+
+@pytest.mark.parametrize("lds", [256, 1024, 2048, 4096])
+def test_lds_sizes(torch, lds):
+    from paper_1309_0215_amd import Job
+    j = Job(device=0, lds_slots=lds)
+    buf = gen.text(8, 600_000, V=10_000, s=1.0)
+    _check(j.words(_dev(torch, buf)), buf)
+
+
+def test_capacity_error_reports_sizes(torch, job):
+    import ctypes as C
+    from paper_1309_0215_amd import _lib as L
+    buf = gen.text(2, 50_000, V=300)
+    exp = oracle.words(buf)
+    o, keep = job._word_out(10, 20)
+    st = job.words_raw(_dev(torch, buf), o)
+    assert st == L.MR_ERR_CAPACITY
+    assert o.n_keys == len(exp) and o.key_bytes_used == len(exp.key_bytes)
+
+
+def test_repeat_runs_identical(torch, job):
+    buf = gen.text(4, 2 << 20, V=30_000)
+    d = _dev(torch, buf)
+    a = job.words(d)
+    for _ in range(3):
+        b = job.words(d)
+        assert torch.equal(a.key_bytes, b.key_bytes) and torch.equal(a.values, b.values)
+
+
+def test_full_config_8mib(torch, job):
+    buf = gen.text(1, 8 << 20)  # 8 MiB, V = 50,000, Zipf s = 1.0, lengths 3..12
+    res = job.words(_dev(torch, buf))
+    _check(res, buf)
+    v = res.values.cpu().numpy().astype(np.uint64)
+    assert int(v.sum()) == len(buf.tobytes().split())
+
+
+def test_workspace_reuse_across_sizes_and_kinds(torch):
+    # One job alternating small and large inputs and the histogram, which
+    # reuses the same workspace: every run must see a clean hash table.
+    from paper_1309_0215_amd import Job
+    j = Job(device=0)
+    rgb = gen.rgb(9, 3 * 200_000)
+    sizes = [150_000, 90_000, 170_000, 5_000, 400_000, 120_000]
+    for i, n in enumerate(sizes):
+        buf = gen.text(20 + i, n, V=4000, s=0.9)
+        _check(j.words(_dev(torch, buf)), buf)
+        if i % 2:
+            h, _ = j.rgb_hist(_dev(torch, rgb))
+            assert np.array_equal(h.cpu().numpy().astype(np.uint64), oracle.rgb(rgb))
