@@ -72,6 +72,15 @@ struct mr_job {
   // pinned host staging for job states
   JobState* h_states = nullptr;
   uint32_t h_states_cap = 0;
+  // integer-key containers: persistent and kept clean between runs
+  void* int_dense = nullptr;     // dense counts [R] then values [R] (64-bit)
+  uint64_t int_dense_R = 0;
+  void* int_table = nullptr;     // keys [cap], counts [cap], values [cap] (64-bit), claimed [cap]
+  uint64_t int_table_cap = 0;
+  void* int_small = nullptr;     // flags, counters, side slot
+  void* int_scratch = nullptr;   // partials, sort records, scans
+  uint64_t int_scratch_bytes = 0;
+  uint64_t int_last_distinct = 0;
 };
 
 namespace {
@@ -119,6 +128,10 @@ mr_status ensure_ws(mr_job* job, uint64_t bytes) {
 mr_status ensure_host_states(mr_job* job, uint32_t n) {
   if (n <= job->h_states_cap) return MR_OK;
   if (job->h_states) (void)hipHostFree(job->h_states);
+  if (job->int_dense) (void)hipFree(job->int_dense);
+  if (job->int_table) (void)hipFree(job->int_table);
+  if (job->int_small) (void)hipFree(job->int_small);
+  if (job->int_scratch) (void)hipFree(job->int_scratch);
   job->h_states = nullptr;
   MR_HIP(hipHostMalloc(&job->h_states, sizeof(JobState) * n, hipHostMallocDefault));
   job->h_states_cap = n;
@@ -198,6 +211,10 @@ extern "C" mr_status mr_job_destroy(mr_job* job) {
   if (job->ws) (void)hipFree(job->ws);
   if (job->km_c) (void)hipFree(job->km_c);
   if (job->h_states) (void)hipHostFree(job->h_states);
+  if (job->int_dense) (void)hipFree(job->int_dense);
+  if (job->int_table) (void)hipFree(job->int_table);
+  if (job->int_small) (void)hipFree(job->int_small);
+  if (job->int_scratch) (void)hipFree(job->int_scratch);
   if (job->ev0) (void)hipEventDestroy(job->ev0);
   if (job->ev1) (void)hipEventDestroy(job->ev1);
   if (job->ev2) (void)hipEventDestroy(job->ev2);
@@ -228,9 +245,9 @@ uint64_t initial_slots(const mr_job* job, uint64_t n) {
   if (job->cfg.table_slots) return job->cfg.table_slots;
   const double lf = (job->cfg.max_load_pct ? job->cfg.max_load_pct : 50) / 100.0;
   const uint64_t words_ub = (n + 1) / 2;
-  uint64_t est = std::min<uint64_t>(words_ub, std::max<uint64_t>(2048, n / 16));
+  uint64_t est = std::min<uint64_t>(words_ub, std::max<uint64_t>(2048, n / 64));
   uint64_t slots = next_pow2((uint64_t)std::ceil(est / lf));
-  return std::max<uint64_t>(4096, std::min<uint64_t>(slots, 1ull << 31));
+  return std::max<uint64_t>(4096, std::min<uint64_t>(slots, 1ull << 21));
 }
 
 struct WordsPlan {
@@ -482,10 +499,256 @@ mr_status run_rgb(mr_job* job, const void* d_input, uint64_t bytes, mr_output* o
   return MR_OK;
 }
 
+// ---------------------------------------------------------------------------
+// integer keys
+// ---------------------------------------------------------------------------
+
+constexpr uint64_t kLdsArrayBudget = 64 * 1024;   // LDS bytes a workgroup may give to a private array
+constexpr uint64_t kGlobalArrayMax = 1ull << 27;  // largest declared range for the global array
+
+// Small per-run state block (device): flags, counters, side slot.
+struct IntSmall {
+  uint32_t flags;
+  uint32_t side_cnt;
+  unsigned long long side_val;
+  unsigned long long n_claimed;
+  unsigned long long n_out;
+};
+
+mr_status int_ensure(mr_job* job, void** p, uint64_t* have, uint64_t want, uint64_t elem_bytes, int fill) {
+  if (want <= *have && *p) return MR_OK;
+  MR_HIP(hipStreamSynchronize(job->stream));
+  if (*p) MR_HIP(hipFree(*p));
+  *p = nullptr;
+  *have = 0;
+  const uint64_t bytes = want * elem_bytes + 8;  // + 8: alignment slack of split arrays
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) return fail(MR_ERR_HIP, "hipMalloc(%llu): %s", (unsigned long long)bytes, hipGetErrorString(e));
+  *have = want;
+  if (fill >= 0) MR_HIP(hipMemsetAsync(*p, fill, bytes, job->stream));
+  return MR_OK;
+}
+
+bool int_feasible(mr_strategy s, uint64_t R, uint32_t op) {
+  switch (s) {
+    case MR_STRAT_LDS_ARRAY: return R > 0 && int_lds_array_bytes(R, op) <= kLdsArrayBudget;
+    case MR_STRAT_GLOBAL_ARRAY: return R > 0 && R <= kGlobalArrayMax;
+    case MR_STRAT_HASH:
+    case MR_STRAT_SORT: return true;
+    default: return false;
+  }
+}
+
+// The paper's rule (Section III-E) for integer keys: keep per-worker arrays
+// while each fits the local memory budget, otherwise one shared array with
+// atomics; keys without a fixed range use the hash table. It never picks SORT.
+mr_strategy rule_strategy(uint64_t R, uint32_t op) {
+  if (int_feasible(MR_STRAT_LDS_ARRAY, R, op)) return MR_STRAT_LDS_ARRAY;
+  if (int_feasible(MR_STRAT_GLOBAL_ARRAY, R, op)) return MR_STRAT_GLOBAL_ARRAY;
+  return MR_STRAT_HASH;
+}
+
+mr_status learned_strategy(mr_job* job, mr_map_kind kind, mr_reduce_op op, const void* d_input, uint64_t bytes,
+                           uint64_t R, mr_strategy* s, bool* used);
+
 mr_status run_u32(mr_job* job, mr_map_kind kind, mr_reduce_op op, const void* d_input, uint64_t bytes, uint64_t key_range,
                   mr_output* out) {
-  (void)job; (void)kind; (void)op; (void)d_input; (void)bytes; (void)key_range; (void)out;
-  return fail(MR_ERR_UNSUPPORTED, "integer-key jobs are not built yet");
+  const uint32_t esz = kind == MR_MAP_U32_KV ? 8 : 4;
+  if (bytes % esz) return fail(MR_ERR_INVALID_ARG, "input length %llu is not a multiple of %u", (unsigned long long)bytes, esz);
+  if (kind == MR_MAP_U32_KEYS && op != MR_REDUCE_COUNT) return fail(MR_ERR_UNSUPPORTED, "plain keys support COUNT only");
+  if (op < MR_REDUCE_COUNT || op > MR_REDUCE_MAX) return fail(MR_ERR_INVALID_ARG, "unknown reduce op");
+  const uint64_t n = bytes / esz;
+  if (n >= (1ull << 32)) return fail(MR_ERR_UNSUPPORTED, "integer inputs must have fewer than 2^32 elements");
+  if (key_range > (1ull << 32)) return fail(MR_ERR_INVALID_ARG, "key_range above 2^32");
+  if (out->cap_keys && (!out->keys || !out->values)) return fail(MR_ERR_INVALID_ARG, "output capacity given without buffers");
+  if ((uintptr_t)d_input % 4) return fail(MR_ERR_INVALID_ARG, "integer input must be 4-byte aligned");
+  const uint32_t o = (uint32_t)op;
+
+  mr_strategy strat = job->cfg.strategy;
+  bool sel_used = false;
+  if (strat == MR_STRAT_LEARNED) {
+    mr_status st = learned_strategy(job, kind, op, d_input, bytes, key_range, &strat, &sel_used);
+    if (st != MR_OK) return st;
+  }
+  if (strat == MR_STRAT_RULE) strat = rule_strategy(key_range, o);
+  if (!int_feasible(strat, key_range, o))
+    return fail(MR_ERR_UNSUPPORTED, "strategy %d is infeasible for this job (key_range %llu)", (int)strat,
+                (unsigned long long)key_range);
+
+  uint64_t small_have = job->int_small ? 1 : 0;
+  mr_status st = int_ensure(job, &job->int_small, &small_have, 1, sizeof(IntSmall), 0);
+  if (st != MR_OK) return st;
+  IntSmall* sm = static_cast<IntSmall*>(job->int_small);
+
+  IntLaunch L{};
+  L.in = static_cast<const uint32_t*>(d_input);
+  L.n = n;
+  L.kv = kind == MR_MAP_U32_KV;
+  L.op = o;
+  L.R = key_range;
+  L.debug_hash = job->cfg.debug_hash;
+  L.flags = &sm->flags;
+  L.n_claimed = &sm->n_claimed;
+  L.n_out = &sm->n_out;
+  L.side_cnt = &sm->side_cnt;
+  L.side_val = &sm->side_val;
+  L.out_keys = static_cast<uint32_t*>(out->keys);
+  L.out_vals = out->values;
+  L.cap = out->cap_keys;
+  L.G = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)job->n_cu * 2, (n + 1023) / 1024));
+
+  auto scratch = [&](uint64_t bytes_needed) -> mr_status {
+    return int_ensure(job, &job->int_scratch, &job->int_scratch_bytes, bytes_needed, 1, -1);
+  };
+  uint32_t retries = 0;
+  uint64_t table_cap = 0;
+  MR_HIP(hipMemsetAsync(sm, 0, sizeof(IntSmall), job->stream));
+  MR_HIP(hipEventRecord(job->ev0, job->stream));
+
+  if (strat == MR_STRAT_LDS_ARRAY || strat == MR_STRAT_GLOBAL_ARRAY) {
+    // counts [R] then, 8-byte aligned, values [R]: 12 bytes per key plus alignment
+    st = int_ensure(job, &job->int_dense, &job->int_dense_R, key_range, 12, 0);
+
+    if (st != MR_OK) return st;
+    L.dcnt = static_cast<uint32_t*>(job->int_dense);
+    L.dval = static_cast<uint8_t*>(job->int_dense) + ((4 * job->int_dense_R + 7) & ~7ull);
+    const uint64_t nb = (key_range + 2047) / 2048;
+    Carve c;
+    const uint64_t o_blk = c.take(4 * (nb + 1));
+    uint64_t o_cp = 0, o_vp = 0;
+    if (strat == MR_STRAT_LDS_ARRAY) {
+      o_cp = c.take(4ull * L.G * key_range);
+      o_vp = c.take((o == 1 ? 8ull : 4ull) * L.G * key_range);
+    }
+    st = scratch(c.off);
+    if (st != MR_OK) return st;
+    uint8_t* sc = static_cast<uint8_t*>(job->int_scratch);
+    L.blk = reinterpret_cast<uint32_t*>(sc + o_blk);
+    if (job->cfg.timing) MR_HIP(hipEventRecord(job->ev2, job->stream));
+    if (strat == MR_STRAT_LDS_ARRAY) {
+      L.cnt_part = reinterpret_cast<uint32_t*>(sc + o_cp);
+      L.val_part = sc + o_vp;
+      MR_HIP(int_enqueue_lds_array(L, job->stream));
+    } else {
+      MR_HIP(int_enqueue_global_array(L, job->stream));
+    }
+    if (job->cfg.timing) MR_HIP(hipEventRecord(job->ev3, job->stream));
+    MR_HIP(int_enqueue_dense_out(L, true, job->stream));
+  } else if (strat == MR_STRAT_HASH) {
+    // capacity: distinct <= min(n, range); start from the last job's distinct count when larger inputs repeat
+    const uint64_t bound = std::max<uint64_t>(1, key_range ? std::min<uint64_t>(n, key_range) : n);
+    const double lf = (job->cfg.max_load_pct ? job->cfg.max_load_pct : 50) / 100.0;
+    table_cap = job->cfg.table_slots ? job->cfg.table_slots
+                                     : std::max<uint64_t>(4096, next_pow2((uint64_t)std::ceil(std::min<uint64_t>(bound, 1ull << 24) / lf)));
+    for (;;) {
+      if (table_cap > job->int_table_cap) {
+        // keys start as 0xFFFFFFFF, counts and values as 0
+        MR_HIP(hipStreamSynchronize(job->stream));
+        if (job->int_table) MR_HIP(hipFree(job->int_table));
+        job->int_table = nullptr;
+        job->int_table_cap = 0;
+        const uint64_t bytes_t = table_cap * (4 + 4 + 8 + 4);
+        hipError_t e = hipMalloc(&job->int_table, bytes_t);
+        if (e != hipSuccess) return fail(MR_ERR_HIP, "hipMalloc(table): %s", hipGetErrorString(e));
+        job->int_table_cap = table_cap;
+        MR_HIP(hipMemsetAsync(job->int_table, 0xFF, table_cap * 4, job->stream));
+        MR_HIP(hipMemsetAsync(static_cast<uint8_t*>(job->int_table) + table_cap * 4, 0, table_cap * 16, job->stream));
+      }
+      uint8_t* tb = static_cast<uint8_t*>(job->int_table);
+      const uint64_t C = job->int_table_cap;
+      L.t_keys = reinterpret_cast<uint32_t*>(tb);
+      L.t_cnt = reinterpret_cast<uint32_t*>(tb + 4 * C);
+      L.t_val = tb + 8 * C;
+      L.claimed = reinterpret_cast<uint32_t*>(tb + 16 * C);
+      L.t_cap = table_cap;  // use a prefix of the allocation (kept clean as a whole)
+      if (job->cfg.timing) MR_HIP(hipEventRecord(job->ev2, job->stream));
+      MR_HIP(int_enqueue_hash_map(L, job->stream));
+      if (job->cfg.timing) MR_HIP(hipEventRecord(job->ev3, job->stream));
+      IntSmall hs;
+      MR_HIP(hipMemcpyAsync(&hs, sm, sizeof hs, hipMemcpyDeviceToHost, job->stream));
+      MR_HIP(hipStreamSynchronize(job->stream));
+      const uint64_t nc = hs.n_claimed;
+      // records and sort scratch for nc keys
+      const uint64_t tiles = (nc + 2047) / 2048;
+      const uint64_t hn = 256 * std::max<uint64_t>(tiles, 1);
+      Carve c;
+      const uint64_t o_rk32 = c.take(4 * (nc + 1));
+      const uint64_t o_rk0 = c.take(8 * (nc + 1)), o_rv0 = c.take(8 * (nc + 1));
+      const uint64_t o_rk1 = c.take(8 * (nc + 1)), o_rv1 = c.take(8 * (nc + 1));
+      const uint64_t o_hist = c.take(4 * hn), o_ss = c.take(4 * (hn / 4096 + 2));
+      st = scratch(c.off);
+      if (st != MR_OK) return st;
+      uint8_t* sc = static_cast<uint8_t*>(job->int_scratch);
+      L.rk32 = reinterpret_cast<uint32_t*>(sc + o_rk32);
+      L.rk0 = reinterpret_cast<unsigned long long*>(sc + o_rk0);
+      L.rv0 = reinterpret_cast<unsigned long long*>(sc + o_rv0);
+      L.rk1 = reinterpret_cast<unsigned long long*>(sc + o_rk1);
+      L.rv1 = reinterpret_cast<unsigned long long*>(sc + o_rv1);
+      L.hist = reinterpret_cast<uint32_t*>(sc + o_hist);
+      L.scan_sums = reinterpret_cast<uint32_t*>(sc + o_ss);
+      MR_HIP(int_enqueue_hash_out(L, nc, job->stream));  // gathers and clears the claimed slots
+      if (hs.flags & kFlagTableFull) {
+        if (++retries > 24 || table_cap >= (1ull << 31)) return fail(MR_ERR_CAPACITY, "hash table cannot grow further");
+        table_cap *= 2;
+        MR_HIP(hipMemsetAsync(sm, 0, sizeof(IntSmall), job->stream));
+        continue;
+      }
+      MR_HIP(int_enqueue_hash_sort_out(L, nc, job->stream));
+      break;
+    }
+  } else {  // SORT
+    const uint64_t tiles = (n + 2047) / 2048;
+    const uint64_t hn = 256 * std::max<uint64_t>(tiles, 1);
+    Carve c;
+    const uint64_t o_rk0 = c.take(8 * (n + 1)), o_rv0 = c.take(8 * (n + 1));
+    const uint64_t o_rk1 = c.take(8 * (n + 1)), o_rv1 = c.take(8 * (n + 1));
+    const uint64_t o_hist = c.take(4 * hn), o_ss = c.take(4 * (std::max(hn, n) / 4096 + 2));
+    const uint64_t o_head = c.take(4 * (n + 1)), o_pos = c.take(4 * (n + 1)), o_hpos = c.take(4 * (n + 2));
+    const uint64_t o_ps = c.take(8 * (n / 4096 + 2));
+    st = scratch(c.off);
+    if (st != MR_OK) return st;
+    uint8_t* sc = static_cast<uint8_t*>(job->int_scratch);
+    L.rk0 = reinterpret_cast<unsigned long long*>(sc + o_rk0);
+    L.rv0 = reinterpret_cast<unsigned long long*>(sc + o_rv0);
+    L.rk1 = reinterpret_cast<unsigned long long*>(sc + o_rk1);
+    L.rv1 = reinterpret_cast<unsigned long long*>(sc + o_rv1);
+    L.hist = reinterpret_cast<uint32_t*>(sc + o_hist);
+    L.scan_sums = reinterpret_cast<uint32_t*>(sc + o_ss);
+    L.head = reinterpret_cast<uint32_t*>(sc + o_head);
+    L.pos = reinterpret_cast<uint32_t*>(sc + o_pos);
+    L.hpos = reinterpret_cast<uint32_t*>(sc + o_hpos);
+    L.ps_sums = reinterpret_cast<unsigned long long*>(sc + o_ps);
+    if (job->cfg.timing) MR_HIP(hipEventRecord(job->ev2, job->stream));
+    MR_HIP(int_enqueue_sort(L, job->stream));
+    if (job->cfg.timing) MR_HIP(hipEventRecord(job->ev3, job->stream));
+  }
+  MR_HIP(hipEventRecord(job->ev1, job->stream));
+  IntSmall hs;
+  MR_HIP(hipMemcpyAsync(&hs, sm, sizeof hs, hipMemcpyDeviceToHost, job->stream));
+  MR_HIP(hipStreamSynchronize(job->stream));
+  float ms = 0.f;
+  MR_HIP(hipEventElapsedTime(&ms, job->ev0, job->ev1));
+  out->stats.gpu_ms = ms;
+  if (job->cfg.timing) MR_HIP(hipEventElapsedTime(&out->stats.map_ms, job->ev2, job->ev3));
+  out->stats.strategy_used = strat;
+  out->stats.selector_used = sel_used ? 1u : 0u;
+  out->stats.retries = retries;
+  out->stats.table_slots = table_cap;
+  out->stats.n_items = n;
+  out->n_keys = hs.n_out;
+  out->key_bytes_used = 0;
+  job->int_last_distinct = hs.n_out;
+  if (hs.flags & kFlagBadInput) return fail(MR_ERR_INVALID_ARG, "a key is outside the declared key_range");
+  if (hs.n_out > out->cap_keys) return fail(MR_ERR_CAPACITY, "output needs %llu keys", (unsigned long long)hs.n_out);
+  return MR_OK;
+}
+
+mr_status learned_strategy(mr_job* job, mr_map_kind kind, mr_reduce_op op, const void* d_input, uint64_t bytes,
+                           uint64_t R, mr_strategy* s, bool* used) {
+  (void)job; (void)kind; (void)op; (void)d_input; (void)bytes; (void)R;
+  *s = MR_STRAT_RULE;  // no trained selector is loaded: the rule decides
+  *used = false;
+  return MR_OK;
 }
 
 mr_status run_kmeans(mr_job* job, const void* d_input, uint64_t bytes, mr_output* out) {

@@ -34,4 +34,54 @@ uint32_t rgb_grid(uint64_t n, int n_cu);
 hipError_t rgb_enqueue(const uint8_t* in, uint64_t n, uint32_t* partials, uint32_t G, unsigned long long* out,
                        hipStream_t s, hipEvent_t map0, hipEvent_t map1);
 
+// Integer-key jobs: one launch description shared by the four containers.
+struct IntLaunch {
+  const uint32_t* in;
+  uint64_t n;           // elements
+  uint32_t kv;          // 1 = interleaved (key, value) pairs
+  uint32_t op;          // 0 COUNT, 1 SUM, 2 MIN, 3 MAX
+  uint64_t R;           // declared key range (0 = none)
+  uint32_t G;           // workgroups of the map kernels
+  uint32_t debug_hash;
+  uint32_t* flags;      // device job flags
+  // array containers
+  uint32_t* cnt_part;
+  void* val_part;
+  uint32_t* dcnt;       // dense counts [R]
+  void* dval;           // dense values [R] (64-bit for SUM)
+  uint32_t* blk;        // compaction block counts
+  // hash container
+  uint32_t* t_keys;
+  uint32_t* t_cnt;
+  void* t_val;
+  uint64_t t_cap;
+  uint32_t* claimed;
+  unsigned long long* n_claimed;
+  uint32_t* side_cnt;
+  void* side_val;
+  // sort scratch
+  uint32_t* rk32;
+  unsigned long long *rk0, *rv0, *rk1, *rv1;
+  uint32_t* hist;
+  uint32_t* scan_sums;
+  uint32_t* head;
+  uint32_t* pos;
+  uint32_t* hpos;
+  unsigned long long* ps_sums;
+  // outputs
+  uint32_t* out_keys;
+  void* out_vals;
+  uint64_t cap;
+  unsigned long long* n_out;  // device: number of distinct keys
+};
+
+hipError_t int_enqueue_lds_array(const IntLaunch& L, hipStream_t s);
+hipError_t int_enqueue_global_array(const IntLaunch& L, hipStream_t s);
+hipError_t int_enqueue_dense_out(const IntLaunch& L, bool clear, hipStream_t s);
+hipError_t int_enqueue_hash_map(const IntLaunch& L, hipStream_t s);
+hipError_t int_enqueue_hash_out(const IntLaunch& L, uint64_t n_claimed_host, hipStream_t s);
+hipError_t int_enqueue_hash_sort_out(const IntLaunch& L, uint64_t n, hipStream_t s);
+hipError_t int_enqueue_sort(const IntLaunch& L, hipStream_t s);
+uint32_t int_lds_array_bytes(uint64_t R, uint32_t op);
+
 }  // namespace mr

@@ -638,43 +638,96 @@ __global__ __launch_bounds__(256) void k_sort_count(const WordJob* __restrict__ 
   }
 }
 
-// Exclusive scans of one job's bucket counts and bytes; capacity check.
+// Exclusive scans of one job's bucket counts and bytes (one workgroup per
+// job, chunks of blockDim buckets); capacity check.
 __global__ __launch_bounds__(kSortThreads) void k_sort_scan(const WordJob* __restrict__ jobs, uint32_t n_jobs,
                                                              const uint32_t* bucket_cnt, const unsigned long long* bucket_bytes,
                                                              uint32_t* bucket_start, unsigned long long* bucket_bstart) {
+  __shared__ uint32_t wc[kSortThreads / kWave];
+  __shared__ unsigned long long wb[kSortThreads / kWave];
   const uint32_t j = blockIdx.x;
   if (j >= n_jobs) return;
   const WordJob& J = jobs[j];
-  if (threadIdx.x != 0) return;
   const uint32_t nb = J.st->nb, bb = J.st->bucket_base;
-  uint32_t c = 0;
-  unsigned long long y = 0;
-  for (uint32_t b = 0; b < nb; ++b) {
-    bucket_start[bb + b] = c;
-    bucket_bstart[bb + b] = y;
-    c += bucket_cnt[bb + b];
-    y += bucket_bytes[bb + b];
+  const uint32_t lane = lane_id(), wv = threadIdx.x / kWave, nw = blockDim.x / kWave;
+  uint32_t carry_c = 0;
+  unsigned long long carry_b = 0;
+  for (uint32_t base = 0; base < nb; base += blockDim.x) {
+    const uint32_t b = base + threadIdx.x;
+    const uint32_t c = b < nb ? bucket_cnt[bb + b] : 0u;
+    const unsigned long long y = b < nb ? bucket_bytes[bb + b] : 0ull;
+    uint32_t ic = c;
+    unsigned long long iy = y;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+      const uint32_t tc = __shfl_up(ic, o);
+      const unsigned long long ty = __shfl_up(iy, o);
+      if (lane >= (uint32_t)o) {
+        ic += tc;
+        iy += ty;
+      }
+    }
+    if (lane == kWave - 1) {
+      wc[wv] = ic;
+      wb[wv] = iy;
+    }
+    __syncthreads();
+    uint32_t pc = carry_c, tot_c = 0;
+    unsigned long long py = carry_b, tot_b = 0;
+    for (uint32_t q = 0; q < nw; ++q) {
+      if (q < wv) {
+        pc += wc[q];
+        py += wb[q];
+      }
+      tot_c += wc[q];
+      tot_b += wb[q];
+    }
+    if (b < nb) {
+      bucket_start[bb + b] = pc + ic - c;
+      bucket_bstart[bb + b] = py + iy - y;
+    }
+    carry_c += tot_c;
+    carry_b += tot_b;
+    __syncthreads();
   }
-  if (J.st->n_recs > J.cap_keys || J.st->key_bytes > J.cap_key_bytes) atomicOr(&J.st->flags, kFlagCapacity);
+  if (threadIdx.x == 0 && (J.st->n_recs > J.cap_keys || J.st->key_bytes > J.cap_key_bytes))
+    atomicOr(&J.st->flags, kFlagCapacity);
 }
 
 __global__ __launch_bounds__(256) void k_sort_scatter(const WordJob* __restrict__ jobs, uint32_t n_jobs, const uint32_t* totals,
                                                       const uint32_t* bucket_start, uint32_t* bucket_fill) {
+  // One global reservation per (tile, bucket) instead of one atomic per record.
+  __shared__ uint32_t h_cnt[kMaxBuckets];
+  __shared__ uint32_t h_base[kMaxBuckets];
   const uint32_t n_tiles = totals[1];
   for (uint32_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
     const uint32_t j = find_rtile_job(jobs, n_jobs, t);
     const WordJob& J = jobs[j];
     const uint64_t n = J.st->n_recs;
+    const uint32_t nb = J.st->nb;
     const uint64_t r0 = (uint64_t)(t - J.st->rtile_base) * kRecTile;
     const uint32_t bb = J.st->bucket_base;
     const WRec* recs = reinterpret_cast<const WRec*>(J.recs);
     WRec* out = reinterpret_cast<WRec*>(J.recs2);
-    for (uint32_t q = threadIdx.x; q < kRecTile; q += blockDim.x) {
-      const uint64_t i = r0 + q;
-      if (i >= n) break;
-      const uint32_t b = J.rec_bucket[i];
-      const uint32_t pos = bucket_start[bb + b] + atomicAdd(&bucket_fill[bb + b], 1u);
-      out[pos] = recs[i];
+    __syncthreads();
+    for (uint32_t b = threadIdx.x; b < nb; b += blockDim.x) h_cnt[b] = 0;
+    __syncthreads();
+    constexpr uint32_t kPer = kRecTile / 256;
+    uint32_t bk[kPer], loc[kPer];
+#pragma unroll
+    for (uint32_t q = 0; q < kPer; ++q) {
+      const uint64_t i = r0 + q * 256 + threadIdx.x;
+      bk[q] = i < n ? J.rec_bucket[i] : 0xFFFFFFFFu;
+      loc[q] = bk[q] != 0xFFFFFFFFu ? atomicAdd(&h_cnt[bk[q]], 1u) : 0u;
+    }
+    __syncthreads();
+    for (uint32_t b = threadIdx.x; b < nb; b += blockDim.x)
+      h_base[b] = h_cnt[b] ? bucket_start[bb + b] + atomicAdd(&bucket_fill[bb + b], h_cnt[b]) : 0u;
+    __syncthreads();
+#pragma unroll
+    for (uint32_t q = 0; q < kPer; ++q) {
+      const uint64_t i = r0 + q * 256 + threadIdx.x;
+      if (bk[q] != 0xFFFFFFFFu) out[h_base[bk[q]] + loc[q]] = recs[i];
     }
   }
 }
@@ -741,7 +794,12 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_buckets(const WordJob* __
         const uint64_t o = y0 + excl;
         J.out_key_offsets[s0 + i] = o;
         J.out_values[s0 + i] = r.cnt;
-        for (uint32_t b = 0; b < r.len; ++b) J.out_key_bytes[o + b] = J.in[r.off + b];
+        if (r.len <= 16u) {
+          // the key is the big-endian prefix itself
+          for (uint32_t b = 0; b < r.len; ++b) J.out_key_bytes[o + b] = (uint8_t)(r.p[b >> 2] >> (24 - 8 * (b & 3)));
+        } else {
+          for (uint32_t b = 0; b < r.len; ++b) J.out_key_bytes[o + b] = J.in[r.off + b];
+        }
       }
       carry += tot;
       __syncthreads();
