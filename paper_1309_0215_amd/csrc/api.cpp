@@ -752,8 +752,54 @@ mr_status learned_strategy(mr_job* job, mr_map_kind kind, mr_reduce_op op, const
 }
 
 mr_status run_kmeans(mr_job* job, const void* d_input, uint64_t bytes, mr_output* out) {
-  (void)job; (void)d_input; (void)bytes; (void)out;
-  return fail(MR_ERR_UNSUPPORTED, "k-means is not built yet");
+  const uint32_t k = job->cfg.km_k, d = job->cfg.km_d;
+  if (!job->km_c || !k || !d) return fail(MR_ERR_INVALID_ARG, "the job was created without k-means centroids");
+  if (bytes % (4ull * d)) return fail(MR_ERR_INVALID_ARG, "input length is not a multiple of 4 * d");
+  const uint64_t N = bytes / (4ull * d);
+  if (N >= (1ull << 31)) return fail(MR_ERR_UNSUPPORTED, "k-means inputs must have fewer than 2^31 points");
+  if ((N && !out->assign) || !out->sums || !out->counts || !out->centroids)
+    return fail(MR_ERR_INVALID_ARG, "k-means needs assign, sums, counts and centroids outputs");
+  if ((uintptr_t)d_input % 4) return fail(MR_ERR_INVALID_ARG, "points must be 4-byte aligned");
+  KmLaunch L{};
+  L.X = static_cast<const float*>(d_input);
+  L.N = N;
+  L.C = job->km_c;
+  L.k = k;
+  L.d = d;
+  L.mfma = d == 32 && k == 64 && (uintptr_t)d_input % 16 == 0;
+  L.G = L.mfma ? (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)job->n_cu * 4, (N + 127) / 128)) : 1u;
+  Carve c;
+  const uint64_t o_cn = c.take(4ull * k), o_cmax = c.take(8), o_nr = c.take(8);
+  const uint64_t o_ps = c.take(8ull * L.G * k * d), o_pc = c.take(4ull * L.G * k);
+  mr_status st = ensure_ws(job, c.off);
+  if (st != MR_OK) return st;
+  job->table_clean_bytes = 0;  // this scratch overwrites the word table region
+  uint8_t* ws = job->ws;
+  L.cn = reinterpret_cast<float*>(ws + o_cn);
+  L.cmax = reinterpret_cast<double*>(ws + o_cmax);
+  L.n_recheck = reinterpret_cast<unsigned long long*>(ws + o_nr);
+  L.part_sum = reinterpret_cast<double*>(ws + o_ps);
+  L.part_cnt = reinterpret_cast<uint32_t*>(ws + o_pc);
+  L.assign = out->assign;
+  L.sums = out->sums;
+  L.counts = out->counts;
+  L.cent = out->centroids;
+  MR_HIP(hipMemsetAsync(L.n_recheck, 0, 8, job->stream));
+  MR_HIP(hipEventRecord(job->ev0, job->stream));
+  MR_HIP(km_enqueue(L, job->stream, job->cfg.timing ? job->ev2 : nullptr, job->cfg.timing ? job->ev3 : nullptr));
+  MR_HIP(hipEventRecord(job->ev1, job->stream));
+  unsigned long long nr = 0;
+  MR_HIP(hipMemcpyAsync(&nr, L.n_recheck, 8, hipMemcpyDeviceToHost, job->stream));
+  MR_HIP(hipStreamSynchronize(job->stream));
+  float ms = 0.f;
+  MR_HIP(hipEventElapsedTime(&ms, job->ev0, job->ev1));
+  out->stats.gpu_ms = ms;
+  if (job->cfg.timing) MR_HIP(hipEventElapsedTime(&out->stats.map_ms, job->ev2, job->ev3));
+  out->stats.n_items = N;
+  out->stats.km_rechecked = (uint32_t)nr;
+  out->stats.strategy_used = L.mfma ? 1u : 0u;
+  out->n_keys = k;
+  return MR_OK;
 }
 
 }  // namespace

@@ -1,0 +1,273 @@
+// One k-means (Lloyd) step on gfx950: map = nearest centroid, reduce = per-
+// cluster sum and count (array container over the k clusters).
+//
+// Assignment (d = 32, k = 64): the scores s_j = |c_j|^2 - 2 <x, c_j> come from
+// a dense float32 contraction on the matrix cores (v_mfma_f32_32x32x2f32):
+// A = 32 centroids x 2 dims, B = 2 dims x 32 points, 16 steps cover d = 32,
+// two centroid blocks cover k = 64. Each lane ends with one point's scores for
+// 32 centroids; lanes l and l ^ 32 hold the other 32. The argmin takes the
+// lowest index on equal scores. When the float32 gap between the best and the
+// second best score is within a rounding bound eps(x), the decision is made
+// again in float64 from the direct form sum_t (x_t - c_t)^2.
+//
+// Update: each workgroup adds its points into float32 LDS sums (a few points
+// per cluster between flushes) and flushes them into float64 LDS sums; the
+// per-workgroup float64 partials are added in a fixed order at the end.
+#include "common.h"
+#include "launch.h"
+
+namespace mr {
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kKmThreads = 256;  // 4 waves
+constexpr int kKmFlush = 4;      // wave iterations between float32 -> float64 flushes
+
+// Squared norms of the centroids (rounded to float32) and max |c| (float64).
+__global__ __launch_bounds__(256) void k_km_prep(const float* __restrict__ C, uint32_t k, uint32_t d, float* __restrict__ cn,
+                                                 double* __restrict__ cmax) {
+  __shared__ double m[256];
+  double best = 0.0;
+  for (uint32_t j = threadIdx.x; j < k; j += blockDim.x) {
+    double s = 0.0;
+    for (uint32_t t = 0; t < d; ++t) {
+      const double v = C[(uint64_t)j * d + t];
+      s += v * v;
+    }
+    cn[j] = (float)s;
+    best = s > best ? s : best;
+  }
+  m[threadIdx.x] = best;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double b = 0.0;
+    for (int i = 0; i < 256; ++i) b = m[i] > b ? m[i] : b;
+    *cmax = sqrt(b);
+  }
+}
+
+// float64 direct-form squared distance (the definition of the step).
+MR_DEV double dist64(const float* __restrict__ x, const float* __restrict__ c, uint32_t d) {
+  double s = 0.0;
+  for (uint32_t t = 0; t < d; ++t) {
+    const double q = (double)x[t] - (double)c[t];
+    s += q * q;
+  }
+  return s;
+}
+
+// Assignment + local sums for d = 32, k = 64.
+__global__ __launch_bounds__(kKmThreads) void k_km_mfma(const float* __restrict__ X, uint64_t N, const float* __restrict__ C,
+                                                        const float* __restrict__ cn_g, const double* __restrict__ cmax_g,
+                                                        int32_t* __restrict__ assign, double* __restrict__ part_sum,
+                                                        uint32_t* __restrict__ part_cnt, unsigned long long* __restrict__ n_recheck) {
+  constexpr int D = 32, K = 64;
+  __shared__ float s32[K * D];
+  __shared__ double s64[K * D];
+  __shared__ uint32_t scnt[K];
+  __shared__ float sC[K * D];
+  for (int i = threadIdx.x; i < K * D; i += blockDim.x) {
+    s32[i] = 0.f;
+    s64[i] = 0.0;
+    sC[i] = C[i];
+  }
+  if (threadIdx.x < K) scnt[threadIdx.x] = 0;
+  __syncthreads();
+
+  const uint32_t lane = lane_id();
+  const uint32_t h = lane >> 5;     // which half of the dims (0: 0..15, 1: 16..31)
+  const uint32_t col = lane & 31u;  // point within the 32-point group / centroid row within a block
+  // A operand: centroid values C[blk*32 + col][16h + s]
+  float ca[2][16];
+#pragma unroll
+  for (int b = 0; b < 2; ++b)
+#pragma unroll
+    for (int s = 0; s < 16; ++s) ca[b][s] = sC[(b * 32 + col) * D + 16 * h + s];
+  // this lane's 32 centroid rows: block b, register r -> row 8*(r/4) + 4*h + r%4
+  float cnr[2][16];
+#pragma unroll
+  for (int b = 0; b < 2; ++b)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) cnr[b][r] = cn_g[b * 32 + 8 * (r / 4) + 4 * h + (r % 4)];
+  const float cmax = (float)*cmax_g;
+  const float u = 5.9604645e-08f;                     // 2^-24
+  const float gam = (float)D * u / (1.f - (float)D * u);
+  const float e_c = 8.f * u * cmax * cmax;            // centroid-norm rounding, both scores, x2 margin
+  const float e_x = 8.f * (gam + u) * cmax;           // times |x|: dot products and the subtraction
+
+  const uint32_t waves_total = gridDim.x * (kKmThreads / kWave);
+  const uint32_t wave_g = blockIdx.x * (kKmThreads / kWave) + threadIdx.x / kWave;
+  const uint64_t groups = (N + 31) / 32;
+  const uint64_t iters = (groups + waves_total - 1) / waves_total;  // uniform across the grid
+  unsigned long long rechecks = 0;
+
+  for (uint64_t it = 0; it < iters; ++it) {
+    const uint64_t g = it * waves_total + wave_g;
+    const uint64_t p = g * 32 + col;
+    const bool valid = g < groups && p < N;
+    f32x4 xv[4];
+    if (valid) {
+      const f32x4* src = reinterpret_cast<const f32x4*>(X + p * D + 16 * h);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) xv[q] = __builtin_nontemporal_load(src + q);
+    } else {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) xv[q] = f32x4{0.f, 0.f, 0.f, 0.f};
+    }
+    float xs[16];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      xs[4 * q + 0] = xv[q].x;
+      xs[4 * q + 1] = xv[q].y;
+      xs[4 * q + 2] = xv[q].z;
+      xs[4 * q + 3] = xv[q].w;
+    }
+    f32x16 acc0 = {}, acc1 = {};
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+      acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(ca[0][s], xs[s], acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(ca[1][s], xs[s], acc1, 0, 0, 0);
+    }
+    // |x| for the bound
+    float nx = 0.f;
+#pragma unroll
+    for (int s = 0; s < 16; ++s) nx = fmaf(xs[s], xs[s], nx);
+    nx += __shfl_xor(nx, 32);
+    nx = sqrtf(nx);
+    // best and second best over this lane's 32 rows, lowest index on ties
+    float b1 = INFINITY, b2 = INFINITY;
+    int i1 = 0x7fffffff;
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const float dot = b ? acc1[r] : acc0[r];
+        const float sc = cnr[b][r] - 2.f * dot;
+        const int idx = b * 32 + 8 * (r / 4) + 4 * (int)h + (r % 4);
+        if (sc < b1 || (sc == b1 && idx < i1)) {
+          b2 = b1;
+          b1 = sc;
+          i1 = idx;
+        } else if (sc < b2) {
+          b2 = sc;
+        }
+      }
+    }
+    // combine with the partner lane (other 32 rows of the same point)
+    const float o1 = __shfl_xor(b1, 32), o2 = __shfl_xor(b2, 32);
+    const int oi = __shfl_xor(i1, 32);
+    float best = b1, second;
+    int bi = i1;
+    if (o1 < b1 || (o1 == b1 && oi < i1)) {
+      best = o1;
+      bi = oi;
+      second = fminf(b1, o2);
+    } else {
+      second = fminf(b2, o1);
+    }
+    // near tie: decide in float64 (one lane per point)
+    const float eps = e_c + e_x * nx;
+    if (valid && h == 0 && !(second - best > eps)) {
+      ++rechecks;
+      const float* xp = X + p * D;
+      double bd = INFINITY;
+      int bj = 0;
+      for (int j = 0; j < K; ++j) {
+        const double dj = dist64(xp, sC + j * D, D);
+        if (dj < bd) {
+          bd = dj;
+          bj = j;
+        }
+      }
+      bi = bj;
+    }
+    bi = __shfl(bi, (int)col);  // lane col (h = 0) decided for both halves
+    if (valid) {
+      if (h == 0) assign[p] = bi;
+#pragma unroll
+      for (int s = 0; s < 16; ++s) atomicAdd(&s32[bi * D + 16 * h + s], xs[s]);
+      if (h == 0) atomicAdd(&scnt[bi], 1u);
+    }
+    if ((it + 1) % kKmFlush == 0 || it + 1 == iters) {
+      __syncthreads();
+      for (int i = threadIdx.x; i < K * D; i += blockDim.x) {
+        s64[i] += (double)s32[i];
+        s32[i] = 0.f;
+      }
+      __syncthreads();
+    }
+  }
+  if (rechecks) atomicAdd(n_recheck, rechecks);
+  for (int i = threadIdx.x; i < K * D; i += blockDim.x) part_sum[(uint64_t)blockIdx.x * K * D + i] = s64[i];
+  if (threadIdx.x < K) part_cnt[(uint64_t)blockIdx.x * K + threadIdx.x] = scnt[threadIdx.x];
+}
+
+// Any d, k: float64 direct-form assignment (exact decisions) and float64 sums.
+__global__ __launch_bounds__(256) void k_km_generic(const float* __restrict__ X, uint64_t N, const float* __restrict__ C,
+                                                    uint32_t k, uint32_t d, int32_t* __restrict__ assign,
+                                                    double* __restrict__ part_sum, uint32_t* __restrict__ part_cnt) {
+  // part_sum/part_cnt hold a single partial here, accumulated with atomics
+  for (uint64_t p = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; p < N; p += (uint64_t)gridDim.x * blockDim.x) {
+    const float* xp = X + p * d;
+    double bd = INFINITY;
+    uint32_t bj = 0;
+    for (uint32_t j = 0; j < k; ++j) {
+      const double dj = dist64(xp, C + (uint64_t)j * d, d);
+      if (dj < bd) {
+        bd = dj;
+        bj = j;
+      }
+    }
+    assign[p] = (int32_t)bj;
+    atomicAdd(&part_cnt[bj], 1u);
+    for (uint32_t t = 0; t < d; ++t) atomicAdd(&part_sum[(uint64_t)bj * d + t], (double)xp[t]);
+  }
+}
+
+__global__ void k_km_zero(double* __restrict__ a, uint64_t na, uint32_t* __restrict__ b, uint64_t nb) {
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < na; i += (uint64_t)gridDim.x * blockDim.x) a[i] = 0.0;
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < nb; i += (uint64_t)gridDim.x * blockDim.x) b[i] = 0u;
+}
+
+// Sum the G partials in a fixed order (deterministic), write float32 sums,
+// counts and new centroids (old centroid for an empty cluster).
+__global__ __launch_bounds__(256) void k_km_final(const double* __restrict__ part_sum, const uint32_t* __restrict__ part_cnt,
+                                                  uint32_t G, uint32_t k, uint32_t d, const float* __restrict__ C,
+                                                  float* __restrict__ sums, uint32_t* __restrict__ counts,
+                                                  float* __restrict__ cent) {
+  const uint64_t kd = (uint64_t)k * d;
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < kd; i += (uint64_t)gridDim.x * blockDim.x) {
+    const uint32_t j = (uint32_t)(i / d);
+    double s = 0.0;
+    uint64_t n = 0;
+    for (uint32_t g = 0; g < G; ++g) {
+      s += part_sum[(uint64_t)g * kd + i];
+      n += part_cnt[(uint64_t)g * k + j];
+    }
+    if (sums) sums[i] = (float)s;
+    if (cent) cent[i] = n ? (float)(s / (double)n) : C[i];
+    if (counts && i % d == 0) counts[j] = (uint32_t)n;
+  }
+}
+
+hipError_t km_enqueue(const KmLaunch& L, hipStream_t s, hipEvent_t map0, hipEvent_t map1) {
+  hipLaunchKernelGGL(k_km_prep, dim3(1), dim3(256), 0, s, L.C, L.k, L.d, L.cn, L.cmax);
+  if (map0) (void)hipEventRecord(map0, s);
+  if (L.mfma) {
+    hipLaunchKernelGGL(k_km_mfma, dim3(L.G), dim3(kKmThreads), 0, s, L.X, L.N, L.C, L.cn, L.cmax, L.assign, L.part_sum,
+                       L.part_cnt, L.n_recheck);
+  } else {
+    hipLaunchKernelGGL(k_km_zero, dim3(256), dim3(256), 0, s, L.part_sum, (uint64_t)L.k * L.d, L.part_cnt, (uint64_t)L.k);
+    const uint64_t b = (L.N + 255) / 256;
+    hipLaunchKernelGGL(k_km_generic, dim3((uint32_t)(b ? (b < 4096 ? b : 4096) : 1)), dim3(256), 0, s, L.X, L.N, L.C, L.k,
+                       L.d, L.assign, L.part_sum, L.part_cnt);
+  }
+  if (map1) (void)hipEventRecord(map1, s);
+  const uint64_t kd = (uint64_t)L.k * L.d;
+  hipLaunchKernelGGL(k_km_final, dim3((uint32_t)((kd + 255) / 256)), dim3(256), 0, s, L.part_sum, L.part_cnt,
+                     L.mfma ? L.G : 1u, L.k, L.d, L.C, L.sums, L.counts, L.cent);
+  return hipGetLastError();
+}
+
+}  // namespace mr

@@ -84,4 +84,25 @@ hipError_t int_enqueue_hash_sort_out(const IntLaunch& L, uint64_t n, hipStream_t
 hipError_t int_enqueue_sort(const IntLaunch& L, hipStream_t s);
 uint32_t int_lds_array_bytes(uint64_t R, uint32_t op);
 
+// One k-means step.
+struct KmLaunch {
+  const float* X;       // points [N][d]
+  uint64_t N;
+  const float* C;       // centroids [k][d]
+  uint32_t k, d;
+  float* cn;            // scratch [k]
+  double* cmax;         // scratch [1]
+  uint32_t G;           // workgroups of the assignment kernel
+  bool mfma;            // d == 32, k == 64 and X 16-byte aligned
+  int32_t* assign;      // [N]
+  double* part_sum;     // [G][k][d]
+  uint32_t* part_cnt;   // [G][k]
+  unsigned long long* n_recheck;
+  float* sums;          // [k][d]
+  uint32_t* counts;     // [k]
+  float* cent;          // [k][d]
+};
+
+hipError_t km_enqueue(const KmLaunch& L, hipStream_t s, hipEvent_t map0, hipEvent_t map1);
+
 }  // namespace mr

@@ -1,0 +1,123 @@
+"""GPU parity of one k-means step (MR_MAP_KMEANS) against the float64 oracle.
+
+Tolerances (float32 arithmetic on the GPU, float64 in the oracle):
+* assignment a_i is accepted iff d64(a_i) <= d64_min * (1 + 1e-6) + 1e-12
+  (ties within 1e-6 relative may go either way);
+* counts are exact given the GPU's assignments;
+* sums: |s32 - s64| <= 1e-5 * max(|s64|, sum_i |x_id|) per (cluster, dim),
+  s64 recomputed in float64 with the GPU's assignments;
+* centroids: new centroid = s / n in float64 rounded to float32, same bound
+  divided by n.
+"""
+import numpy as np
+import pytest
+
+import gen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    return t
+
+
+def _run(torch, X, Cn, offset=0):
+    from paper_1309_0215_amd import Job
+    job = Job(device=0, km_centroids=torch.from_numpy(Cn).to("cuda:0"))
+    Xd = torch.from_numpy(X).to("cuda:0")
+    if offset:
+        big = torch.zeros(X.size + offset, dtype=torch.float32, device="cuda:0")
+        big[offset:] = Xd.reshape(-1)
+        Xd = big[offset:].view(X.shape)
+    a, s, c, cent, st = job.kmeans(Xd)
+    return (a.cpu().numpy(), s.cpu().numpy(), c.cpu().numpy().view(np.uint32), cent.cpu().numpy(), st)
+
+
+def _check_assign(X, Cn, a, idx=None):
+    if idx is None:
+        idx = np.arange(len(X))
+    D = oracle.kmeans_distances(X[idx], Cn)
+    dmin = D.min(axis=1)
+    dg = D[np.arange(len(idx)), a[idx]]
+    ok = dg <= dmin * (1 + 1e-6) + 1e-12
+    assert ok.all(), (np.flatnonzero(~ok)[:10], dg[~ok][:5], dmin[~ok][:5])
+    return int((a[idx] != D.argmin(axis=1)).sum())
+
+
+def _check_update(X, Cn, a, s, c, cent):
+    k = len(Cn)
+    S64, n64, newC = oracle.kmeans_update(X, a, Cn)
+    assert np.array_equal(c.astype(np.int64), n64)
+    A = oracle.kmeans_abs_sums(X, a, k)
+    tol = 1e-5 * np.maximum(np.abs(S64), A)
+    assert (np.abs(s.astype(np.float64) - S64) <= tol).all()
+    ctol = tol / np.maximum(n64, 1)[:, None] + 1e-7 * np.abs(newC)
+    assert (np.abs(cent.astype(np.float64) - newC) <= ctol).all()
+
+
+@pytest.mark.parametrize("n", [1, 31, 32, 33, 4097, 50_000])
+def test_mfma_path(torch, n):
+    X, Cn = gen.kmeans(3, n=max(n, 64), d=32, k=64)
+    X = X[:n].copy()
+    a, s, c, cent, st = _run(torch, X, Cn)
+    assert st["strategy_used"] == 1  # matrix-core path
+    _check_assign(X, Cn, a)
+    _check_update(X, Cn, a, s, c, cent)
+
+
+def test_generic_path_any_shape(torch):
+    rng = np.random.default_rng(2)
+    X = rng.standard_normal((3001, 5)).astype(np.float32)
+    Cn = X[:7].copy()
+    a, s, c, cent, st = _run(torch, X, Cn)
+    assert st["strategy_used"] == 0
+    _check_assign(X, Cn, a)
+    _check_update(X, Cn, a, s, c, cent)
+
+
+def test_unaligned_points_use_generic_path(torch):
+    X, Cn = gen.kmeans(4, n=2000, d=32, k=64)
+    a, s, c, cent, st = _run(torch, X, Cn, offset=1)
+    assert st["strategy_used"] == 0
+    _check_assign(X, Cn, a)
+    _check_update(X, Cn, a, s, c, cent)
+
+
+def test_exact_ties_take_lowest_index_and_empty_clusters_keep_centroid(torch):
+    X, Cn = gen.kmeans(5, n=8192, d=32, k=64)
+    Cn = Cn.copy()
+    Cn[10] = Cn[3]          # identical centroids: every point of cluster 3 ties with 10
+    Cn[20] = 1000.0         # far away: an empty cluster
+    a, s, c, cent, st = _run(torch, X, Cn)
+    assert not (a == 10).any() and not (a == 20).any()
+    assert c[20] == 0 and np.array_equal(cent[20], Cn[20])
+    _check_assign(X, Cn, a)
+    _check_update(X, Cn, a, s, c, cent)
+
+
+def test_points_equal_to_centroids(torch):
+    X, Cn = gen.kmeans(6, n=64, d=32, k=64)
+    a, s, c, cent, st = _run(torch, Cn.copy(), Cn)
+    assert np.array_equal(a, np.arange(64))
+
+
+def test_full_config_16m_sampled(torch):
+    X, Cn = gen.kmeans(3)  # 16,777,216 x 32, k = 64, first 64 points
+    a, s, c, cent, st = _run(torch, X, Cn)
+    assert int(c.astype(np.int64).sum()) == len(X)
+    rng = np.random.default_rng(0)
+    idx = rng.choice(len(X), 20_000, replace=False)
+    _check_assign(X, Cn, a, idx)
+    # sums over all points in float64 with the GPU's assignments (bincount per dim)
+    k, d = Cn.shape
+    n64 = np.bincount(a, minlength=k)
+    assert np.array_equal(c.astype(np.int64), n64)
+    for t in range(d):
+        col = X[:, t].astype(np.float64)
+        S = np.bincount(a, weights=col, minlength=k)
+        A = np.bincount(a, weights=np.abs(col), minlength=k)
+        assert (np.abs(s[:, t].astype(np.float64) - S) <= 1e-5 * np.maximum(np.abs(S), A)).all()
+    assert st["km_rechecked"] < len(X) // 100
