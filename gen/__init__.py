@@ -289,6 +289,21 @@ def selector_specs(seed: int = 5, n_jobs: int = 2000, size_lo: int = 1 << 20, si
     return out
 
 
+def _job_input_worker(spec: "JobSpec") -> np.ndarray:
+    return job_input(spec)
+
+
+def job_inputs(specs: list, workers: int | None = None) -> list:
+    """Inputs of many job specs, generated in parallel worker processes."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    w = workers or _threads()
+    if w <= 1 or len(specs) <= 1:
+        return [job_input(s) for s in specs]
+    with cf.ProcessPoolExecutor(w, mp_context=mp.get_context("fork")) as ex:
+        return list(ex.map(_job_input_worker, specs, chunksize=1))
+
+
 def job_input(spec: JobSpec) -> np.ndarray:
     """The input bytes of one job spec."""
     if spec.kind == "words":

@@ -139,8 +139,22 @@ class Job:
         return self.lib.mr_run(self.h, L.MAP_WORDS, L.REDUCE_COUNT, _ptr(data), int(data.numel()), _ptr(ro),
                                0 if ro is None else int(ro.numel()) - 1, 0, C.byref(out))
 
-    def words_batch(self, inputs, cap_keys: list[int] | None = None, cap_bytes: list[int] | None = None):
-        """One mr_batch_run over a list of uint8 CUDA tensors; returns a list of WordsResult."""
+    def words_batch(self, inputs, cap_keys: list[int] | None = None, cap_bytes: list[int] | None = None,
+                    record_offsets: list | None = None, prepared=None):
+        """One mr_batch_run over a list of uint8 CUDA tensors; returns a list of WordsResult.
+
+        `prepared` (from batch_prepare) reuses item and output arrays, so that
+        repeated calls keep the same launch layout and replay the captured graph."""
+        if prepared is not None:
+            items, outs, keep = prepared
+            n = len(keep)
+            L.check(self.lib.mr_batch_run(self.h, items, n, outs), "mr_batch_run")
+            return [WordsResult(keep[i][0][:outs[i].key_bytes_used], keep[i][1][:int(outs[i].n_keys) + 1],
+                                keep[i][2][:int(outs[i].n_keys)], _stats(outs[i])) for i in range(n)]
+        items, outs, keep = self.batch_prepare(inputs, cap_keys, cap_bytes, record_offsets)
+        return self.words_batch(inputs, prepared=(items, outs, keep))
+
+    def batch_prepare(self, inputs, cap_keys=None, cap_bytes=None, record_offsets=None):
         n = len(inputs)
         items = (L.BatchItem * n)()
         outs = (L.Output * n)()
@@ -148,19 +162,15 @@ class Job:
         for i, d in enumerate(inputs):
             items[i].kind, items[i].op = L.MAP_WORDS, L.REDUCE_COUNT
             items[i].d_input, items[i].input_bytes = d.data_ptr(), int(d.numel())
+            if record_offsets is not None and record_offsets[i] is not None:
+                items[i].d_record_offsets = record_offsets[i].data_ptr()
+                items[i].n_records = int(record_offsets[i].numel()) - 1
             ck = cap_keys[i] if cap_keys else max(1024, min(int(d.numel()) // 2 + 1, 1 << 20))
             cb = cap_bytes[i] if cap_bytes else max(4096, min(int(d.numel()), 1 << 24))
             o, k = self._word_out(ck, cb)
             outs[i] = o
             keep.append(k)
-        st = self.lib.mr_batch_run(self.h, items, n, outs)
-        L.check(st, "mr_batch_run")
-        res = []
-        for i in range(n):
-            kb, ko, vals = keep[i]
-            nk = int(outs[i].n_keys)
-            res.append(WordsResult(kb[:outs[i].key_bytes_used], ko[:nk + 1], vals[:nk], _stats(outs[i])))
-        return res
+        return items, outs, keep
 
     # -------------------------------------------------------------- histogram
     def rgb_hist(self, data):

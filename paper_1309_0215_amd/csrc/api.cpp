@@ -66,9 +66,12 @@ struct mr_job {
   std::vector<float> sel_params, sel_mean, sel_scale, sel_lo, sel_hi;
   // k-means centroids (device, owned)
   float* km_c = nullptr;
-  // batched graph cache
+  // batched graph cache: valid while nothing else has written the workspace
   hipGraphExec_t graph = nullptr;
   uint64_t graph_key = 0;
+  bool graph_valid = false;
+  hipStream_t gstream = nullptr;  // non-blocking stream for capture (the caller's may be the null stream)
+  hipEvent_t gev = nullptr;
   // pinned host staging for job states
   JobState* h_states = nullptr;
   uint32_t h_states_cap = 0;
@@ -112,6 +115,7 @@ mr_status ensure_ws(mr_job* job, uint64_t bytes) {
   const uint64_t want = std::max<uint64_t>(bytes, job->ws_bytes + job->ws_bytes / 2);
   if (job->ws) {
     MR_HIP(hipStreamSynchronize(job->stream));
+    if (job->gstream) MR_HIP(hipStreamSynchronize(job->gstream));
     MR_HIP(hipFree(job->ws));
     job->ws = nullptr;
     job->ws_bytes = 0;
@@ -122,6 +126,7 @@ mr_status ensure_ws(mr_job* job, uint64_t bytes) {
   job->ws = p;
   job->ws_bytes = want;
   job->table_clean_bytes = 0;
+  job->graph_valid = false;
   return MR_OK;
 }
 
@@ -182,7 +187,9 @@ extern "C" mr_status mr_job_create(const mr_job_config* cfg, mr_job** out) {
   job->n_cu = prop.multiProcessorCount;
   ScopedDevice sd(job->device);
   if (hipEventCreate(&job->ev0) != hipSuccess || hipEventCreate(&job->ev1) != hipSuccess ||
-      hipEventCreate(&job->ev2) != hipSuccess || hipEventCreate(&job->ev3) != hipSuccess) {
+      hipEventCreate(&job->ev2) != hipSuccess || hipEventCreate(&job->ev3) != hipSuccess ||
+      hipEventCreateWithFlags(&job->gev, hipEventDisableTiming) != hipSuccess ||
+      hipStreamCreateWithFlags(&job->gstream, hipStreamNonBlocking) != hipSuccess) {
     delete job;
     return fail(MR_ERR_HIP, "hipEventCreate failed");
   }
@@ -208,6 +215,9 @@ extern "C" mr_status mr_job_destroy(mr_job* job) {
   ScopedDevice sd(job->device);
   if (job->stream) (void)hipStreamSynchronize(job->stream);
   if (job->graph) (void)hipGraphExecDestroy(job->graph);
+  if (job->gstream) (void)hipStreamSynchronize(job->gstream);
+  if (job->gstream) (void)hipStreamDestroy(job->gstream);
+  if (job->gev) (void)hipEventDestroy(job->gev);
   if (job->ws) (void)hipFree(job->ws);
   if (job->km_c) (void)hipFree(job->km_c);
   if (job->h_states) (void)hipHostFree(job->h_states);
@@ -291,29 +301,85 @@ WordsPlan plan_words(const std::vector<WordItem>& items) {
   return p;
 }
 
-mr_status zero_device(mr_job* job, void* p, uint64_t bytes) {
+mr_status zero_device(hipStream_t s, void* p, uint64_t bytes) {
   if (!bytes) return MR_OK;
   if (bytes % 4 == 0 && (uintptr_t)p % 4 == 0) {
-    MR_HIP(hipMemsetD32Async((hipDeviceptr_t)p, 0, bytes / 4, job->stream));
+    MR_HIP(hipMemsetD32Async((hipDeviceptr_t)p, 0, bytes / 4, s));
   } else {
-    MR_HIP(hipMemsetAsync(p, 0, bytes, job->stream));
+    MR_HIP(hipMemsetAsync(p, 0, bytes, s));
   }
   return MR_OK;
 }
 
 // Runs a batch of word-count items once; fills states[] (host). The caller
 // handles regrowth and results.
+uint64_t fnv_mix(uint64_t h, uint64_t v) {
+  for (int i = 0; i < 8; ++i) {
+    h ^= (v >> (8 * i)) & 0xFF;
+    h *= 0x100000001B3ull;
+  }
+  return h;
+}
+
 mr_status words_pass(mr_job* job, std::vector<WordItem>& items, std::vector<JobState>& states, float* gpu_ms,
-                     float* map_ms) {
+                     float* map_ms, bool use_graph) {
   const uint32_t n = (uint32_t)items.size();
+  // Graphs run on the job's own stream, ordered after the caller's stream.
+  hipStream_t s = job->stream;
+  if (use_graph) {
+    MR_HIP(hipEventRecord(job->gev, job->stream));
+    MR_HIP(hipStreamWaitEvent(job->gstream, job->gev, 0));
+    s = job->gstream;
+  }
   WordsPlan p = plan_words(items);
   mr_status st = ensure_ws(job, p.c.off);
   if (st != MR_OK) return st;
   uint8_t* ws = job->ws;
+  // identity of the launch sequence: a captured graph replays only for the same one
+  uint64_t key = 0xCBF29CE484222325ull;
+  key = fnv_mix(key, (uint64_t)ws);
+  key = fnv_mix(key, n);
+  key = fnv_mix(key, job->cfg.lds_slots);
+  key = fnv_mix(key, job->cfg.debug_hash);
+  for (const WordItem& it : items) {
+    key = fnv_mix(key, (uint64_t)it.in);
+    key = fnv_mix(key, it.n);
+    key = fnv_mix(key, (uint64_t)it.rec);
+    key = fnv_mix(key, it.n_rec);
+    key = fnv_mix(key, it.cap);
+    key = fnv_mix(key, (uint64_t)it.out->key_bytes);
+    key = fnv_mix(key, (uint64_t)it.out->key_offsets);
+    key = fnv_mix(key, (uint64_t)it.out->values);
+    key = fnv_mix(key, it.out->cap_keys);
+    key = fnv_mix(key, it.out->cap_key_bytes);
+  }
+  const uint64_t table_bytes_g = p.o_tc + p.total_slots * 4;
+  if (use_graph && job->graph && job->graph_valid && job->graph_key == key && job->table_clean_bytes >= table_bytes_g) {
+    // replay: descriptors, tile bases and the clean table are still in place
+    job->table_clean_bytes = 0;
+    MR_HIP(hipEventRecord(job->ev0, s));
+    MR_HIP(hipGraphLaunch(job->graph, s));
+    MR_HIP(hipEventRecord(job->ev1, s));
+    st = ensure_host_states(job, n);
+    if (st != MR_OK) return st;
+    MR_HIP(hipMemcpyAsync(job->h_states, ws + p.o_states, sizeof(JobState) * n, hipMemcpyDeviceToHost, s));
+    MR_HIP(hipStreamSynchronize(s));
+    states.assign(job->h_states, job->h_states + n);
+    float ms = 0.f;
+    MR_HIP(hipEventElapsedTime(&ms, job->ev0, job->ev1));
+    *gpu_ms = ms;
+    *map_ms = 0.f;
+    bool dirty = false;
+    for (auto& s : states) dirty |= (s.flags & kFlagTableFull) != 0;
+    job->table_clean_bytes = dirty ? 0 : table_bytes_g;
+    if (dirty) job->graph_valid = false;
+    return MR_OK;
+  }
+  job->graph_valid = false;  // this pass rewrites the descriptors
   // the table arena must start all zero
   const uint64_t table_bytes = p.o_tc + p.total_slots * 4;
   if (job->table_clean_bytes < table_bytes) {
-    st = zero_device(job, ws + job->table_clean_bytes, table_bytes - job->table_clean_bytes);
+    st = zero_device(s, ws + job->table_clean_bytes, table_bytes - job->table_clean_bytes);
     if (st != MR_OK) return st;
   }
   job->table_clean_bytes = 0;  // until this pass completes
@@ -346,10 +412,8 @@ mr_status words_pass(mr_job* job, std::vector<WordItem>& items, std::vector<JobS
     J.st = reinterpret_cast<JobState*>(ws + p.o_states) + j;
     any_rec |= it.rec != nullptr;
   }
-  MR_HIP(hipMemcpyAsync(ws + p.o_jobs, hj.data(), sizeof(WordJob) * n, hipMemcpyHostToDevice, job->stream));
-  MR_HIP(hipMemcpyAsync(ws + p.o_tile_base, p.tile_base.data(), 8 * (n + 1), hipMemcpyHostToDevice, job->stream));
-  st = zero_device(job, ws + p.o_states, sizeof(JobState) * n);
-  if (st != MR_OK) return st;
+  MR_HIP(hipMemcpyAsync(ws + p.o_jobs, hj.data(), sizeof(WordJob) * n, hipMemcpyHostToDevice, s));
+  MR_HIP(hipMemcpyAsync(ws + p.o_tile_base, p.tile_base.data(), 8 * (n + 1), hipMemcpyHostToDevice, s));
 
   WordsLaunch L{};
   L.jobs = reinterpret_cast<const WordJob*>(ws + p.o_jobs);
@@ -376,17 +440,45 @@ mr_status words_pass(mr_job* job, std::vector<WordItem>& items, std::vector<JobS
   L.bucket_bstart = reinterpret_cast<unsigned long long*>(ws + p.o_bucket_bstart);
   L.bucket_fill = reinterpret_cast<uint32_t*>(ws + p.o_bucket_fill);
 
-  MR_HIP(hipEventRecord(job->ev0, job->stream));
-  MR_HIP(words_enqueue_prep(L, job->stream));
-  if (job->cfg.timing) MR_HIP(hipEventRecord(job->ev2, job->stream));
-  MR_HIP(words_enqueue_map(L, job->stream));
-  if (job->cfg.timing) MR_HIP(hipEventRecord(job->ev3, job->stream));
-  MR_HIP(words_enqueue_reduce(L, job->stream));
-  MR_HIP(hipEventRecord(job->ev1, job->stream));
+  L.states = reinterpret_cast<JobState*>(ws + p.o_states);
+  if (use_graph) {
+    // capture the whole sequence (no memset nodes: states are cleared by a kernel)
+    if (job->graph) {
+      MR_HIP(hipGraphExecDestroy(job->graph));
+      job->graph = nullptr;
+    }
+    hipGraph_t g = nullptr;
+    MR_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    hipError_t e = words_enqueue_zero_states(L, s);
+    if (e == hipSuccess) e = words_enqueue_prep(L, s);
+    if (e == hipSuccess) e = words_enqueue_map(L, s);
+    if (e == hipSuccess) e = words_enqueue_reduce(L, s);
+    const hipError_t e2 = hipStreamEndCapture(s, &g);
+    if (e != hipSuccess || e2 != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return fail(MR_ERR_HIP, "graph capture failed: %s", hipGetErrorString(e != hipSuccess ? e : e2));
+    }
+    e = hipGraphInstantiate(&job->graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return fail(MR_ERR_HIP, "graph instantiate failed: %s", hipGetErrorString(e));
+    job->graph_key = key;
+    MR_HIP(hipEventRecord(job->ev0, s));
+    MR_HIP(hipGraphLaunch(job->graph, s));
+    MR_HIP(hipEventRecord(job->ev1, s));
+  } else {
+    MR_HIP(hipEventRecord(job->ev0, s));
+    MR_HIP(words_enqueue_zero_states(L, s));
+    MR_HIP(words_enqueue_prep(L, s));
+    if (job->cfg.timing) MR_HIP(hipEventRecord(job->ev2, s));
+    MR_HIP(words_enqueue_map(L, s));
+    if (job->cfg.timing) MR_HIP(hipEventRecord(job->ev3, s));
+    MR_HIP(words_enqueue_reduce(L, s));
+    MR_HIP(hipEventRecord(job->ev1, s));
+  }
   st = ensure_host_states(job, n);
   if (st != MR_OK) return st;
-  MR_HIP(hipMemcpyAsync(job->h_states, ws + p.o_states, sizeof(JobState) * n, hipMemcpyDeviceToHost, job->stream));
-  MR_HIP(hipStreamSynchronize(job->stream));
+  MR_HIP(hipMemcpyAsync(job->h_states, ws + p.o_states, sizeof(JobState) * n, hipMemcpyDeviceToHost, s));
+  MR_HIP(hipStreamSynchronize(s));
   states.assign(job->h_states, job->h_states + n);
   float ms = 0.f;
   MR_HIP(hipEventElapsedTime(&ms, job->ev0, job->ev1));
@@ -400,6 +492,7 @@ mr_status words_pass(mr_job* job, std::vector<WordItem>& items, std::vector<JobS
   bool dirty = false;
   for (auto& s : states) dirty |= (s.flags & kFlagTableFull) != 0;
   job->table_clean_bytes = dirty ? 0 : table_bytes;
+  job->graph_valid = use_graph && !dirty;
   return MR_OK;
 }
 
@@ -414,7 +507,7 @@ mr_status check_words_item(const WordItem& it) {
   return MR_OK;
 }
 
-mr_status run_words(mr_job* job, std::vector<WordItem>& items, std::vector<mr_status>* per_item) {
+mr_status run_words(mr_job* job, std::vector<WordItem>& items, std::vector<mr_status>* per_item, bool use_graph) {
   for (auto& it : items) {
     mr_status s = check_words_item(it);
     if (s != MR_OK) return s;
@@ -425,7 +518,7 @@ mr_status run_words(mr_job* job, std::vector<WordItem>& items, std::vector<mr_st
   float total_ms = 0.f, map_ms = 0.f;
   for (;;) {
     float ms = 0.f;
-    mr_status s = words_pass(job, items, states, &ms, &map_ms);
+    mr_status s = words_pass(job, items, states, &ms, &map_ms, use_graph);
     if (s != MR_OK) return s;
     total_ms += ms;
     bool regrow = false;
@@ -482,6 +575,7 @@ mr_status run_rgb(mr_job* job, const void* d_input, uint64_t bytes, mr_output* o
   mr_status st = ensure_ws(job, c.off);
   if (st != MR_OK) return st;
   job->table_clean_bytes = std::min(job->table_clean_bytes, o_part);  // scratch overwrites the table region
+  job->graph_valid = false;
   MR_HIP(hipEventRecord(job->ev0, job->stream));
   MR_HIP(rgb_enqueue(static_cast<const uint8_t*>(d_input), bytes, reinterpret_cast<uint32_t*>(job->ws + o_part), G,
                      static_cast<unsigned long long*>(out->values), job->stream, job->cfg.timing ? job->ev2 : nullptr,
@@ -774,6 +868,7 @@ mr_status run_kmeans(mr_job* job, const void* d_input, uint64_t bytes, mr_output
   mr_status st = ensure_ws(job, c.off);
   if (st != MR_OK) return st;
   job->table_clean_bytes = 0;  // this scratch overwrites the word table region
+  job->graph_valid = false;
   uint8_t* ws = job->ws;
   L.cn = reinterpret_cast<float*>(ws + o_cn);
   L.cmax = reinterpret_cast<double*>(ws + o_cmax);
@@ -822,7 +917,7 @@ extern "C" mr_status mr_run(mr_job* job, mr_map_kind kind, mr_reduce_op op, cons
       if (op != MR_REDUCE_COUNT) return fail(MR_ERR_UNSUPPORTED, "words support COUNT only");
       std::vector<WordItem> items(1);
       items[0] = WordItem{static_cast<const uint8_t*>(d_input), input_bytes, d_record_offsets, n_records, out, 0};
-      s = run_words(job, items, nullptr);
+      s = run_words(job, items, nullptr, false);
       break;
     }
     case MR_MAP_RGB_HIST:
@@ -857,7 +952,7 @@ extern "C" mr_status mr_batch_run(mr_job* job, const mr_batch_item* items, uint3
                     items[i].n_records, &outs[i], 0};
   }
   std::vector<mr_status> per(n_items, MR_OK);
-  return run_words(job, w, &per);
+  return run_words(job, w, &per, true);
 }
 
 // ----------------------------------------------------------------------------

@@ -31,6 +31,8 @@ struct JobState {
   uint32_t pad[2];
 };
 
+static_assert(sizeof(JobState) % 8 == 0, "JobState is cleared as 32-bit words");
+
 // One word-count job of a batch (a single mr_run is a batch of one).
 struct WordJob {
   const uint8_t* in;         // input bytes (device)

@@ -24,8 +24,10 @@ struct WordsLaunch {
   uint32_t* bucket_start;
   unsigned long long* bucket_bstart;
   uint32_t* bucket_fill;
+  JobState* states;           // device [n_jobs]
 };
 
+hipError_t words_enqueue_zero_states(const WordsLaunch& L, hipStream_t s);
 hipError_t words_enqueue_prep(const WordsLaunch& L, hipStream_t s);
 hipError_t words_enqueue_map(const WordsLaunch& L, hipStream_t s);
 hipError_t words_enqueue_reduce(const WordsLaunch& L, hipStream_t s);

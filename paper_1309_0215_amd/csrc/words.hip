@@ -346,15 +346,18 @@ __global__ __launch_bounds__(kMapThreads) void k_words_map(const WordJob* __rest
       __syncthreads();
       for (uint32_t i = threadIdx.x; i < kBndWords; i += blockDim.x) bnd[i] = 0u;
       __syncthreads();
-      // record boundaries falling in [tile_addr, tile_addr + 32 * kBndWords)
-      const int64_t lo_rel = (int64_t)(tile_addr - a0);
-      const uint64_t r0 = rec_lower_bound(J.rec, J.n_rec, lo_rel < 0 ? 0 : (uint64_t)lo_rel);
-      for (uint64_t r = r0 + threadIdx.x; r <= J.n_rec; r += blockDim.x) {
-        const uint64_t pa = a0 + J.rec[r];
-        if (pa < tile_addr) continue;
-        const uint64_t bit = pa - tile_addr;
-        if (bit >= 32ull * kBndWords) break;
-        atomicOr(&bnd[bit >> 5], 1u << (bit & 31));
+      // record boundaries falling in [tile_addr, tile_addr + 32 * kBndWords);
+      // in a batch that mixes jobs with and without records, the latter keep an empty bitmap
+      if (J.rec) {
+        const int64_t lo_rel = (int64_t)(tile_addr - a0);
+        const uint64_t r0 = rec_lower_bound(J.rec, J.n_rec, lo_rel < 0 ? 0 : (uint64_t)lo_rel);
+        for (uint64_t r = r0 + threadIdx.x; r <= J.n_rec; r += blockDim.x) {
+          const uint64_t pa = a0 + J.rec[r];
+          if (pa < tile_addr) continue;
+          const uint64_t bit = pa - tile_addr;
+          if (bit >= 32ull * kBndWords) break;
+          atomicOr(&bnd[bit >> 5], 1u << (bit & 31));
+        }
       }
     }
     __syncthreads();
@@ -820,6 +823,17 @@ __global__ void k_words_finish(const WordJob* __restrict__ jobs, uint32_t n_jobs
 // ----------------------------------------------------------------------------
 
 int words_max_lds_log2() { return 12; }
+
+__global__ void k_zero_states(JobState* st, uint32_t n) {
+  uint32_t* p = reinterpret_cast<uint32_t*>(st);
+  const uint32_t words = n * (uint32_t)(sizeof(JobState) / 4);
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < words; i += gridDim.x * blockDim.x) p[i] = 0u;
+}
+
+hipError_t words_enqueue_zero_states(const WordsLaunch& L, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_states, dim3(1), dim3(256), 0, s, L.states, L.n_jobs);
+  return hipGetLastError();
+}
 
 hipError_t words_enqueue_prep(const WordsLaunch& L, hipStream_t s) {
   if (L.any_records) {

@@ -1,0 +1,99 @@
+"""GPU parity of batched word count (mr_batch_run, one graph-captured pass over many jobs).
+
+Every job of a batch must equal the CPU oracle and be byte-identical to the
+same job run alone with mr_run; replays of the captured graph must keep
+giving the same outputs, also after other runs used the job's workspace.
+"""
+import numpy as np
+import pytest
+
+import gen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    return t
+
+
+def _dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def _same(a, b):
+    return (np.array_equal(a.key_bytes.cpu().numpy(), b.key_bytes.cpu().numpy())
+            and np.array_equal(a.key_offsets.cpu().numpy(), b.key_offsets.cpu().numpy())
+            and np.array_equal(a.values.cpu().numpy(), b.values.cpu().numpy()))
+
+
+def _oracle_equal(res, buf, offs=None):
+    exp = oracle.words(buf, offs)
+    return (np.array_equal(res.key_bytes.cpu().numpy(), exp.key_bytes)
+            and np.array_equal(res.key_offsets.cpu().numpy().astype(np.uint64), exp.key_offsets)
+            and np.array_equal(res.values.cpu().numpy().astype(np.uint32).astype(np.uint64), exp.values))
+
+
+def _small_batch():
+    specs = gen.batched_specs(seed=40, n_jobs=24, size_lo=1 << 10, size_hi=512 << 10, v_lo=100, v_hi=20_000)
+    bufs = [gen.job_input(s) for s in specs]
+    bufs[3] = np.zeros(0, np.uint8)                     # an empty job
+    bufs[7] = np.frombuffer(b"the cat the", np.uint8)   # the hand-worked case
+    return bufs
+
+
+def test_small_batch_matches_oracle_and_replays(torch):
+    from paper_1309_0215_amd import Job
+    bufs = _small_batch()
+    dev = [_dev(torch, b) if len(b) else torch.empty(0, dtype=torch.uint8, device="cuda:0") for b in bufs]
+    rng = np.random.default_rng(1)
+    offs = [None] * len(bufs)
+    for i in (1, 5, 11):
+        n = len(bufs[i])
+        o = np.concatenate([[0], np.sort(rng.integers(0, n + 1, 50)), [n]]).astype(np.int64)
+        offs[i] = o
+    offs_dev = [None if o is None else _dev(torch, o) for o in offs]
+    job = Job(device=0)
+    prep = job.batch_prepare(dev, record_offsets=offs_dev)
+    first = job.words_batch(dev, prepared=prep)
+    for i, b in enumerate(bufs):
+        assert _oracle_equal(first[i], b, None if offs[i] is None else offs[i].astype(np.uint64)), i
+    for _ in range(3):  # graph replays
+        again = job.words_batch(dev, prepared=prep)
+        for i in range(len(bufs)):
+            assert _same(first[i], again[i]), i
+    # another run on the same job rewrites the workspace; the batch must recapture
+    single = job.words(dev[0])
+    assert _same(single, first[0])
+    again = job.words_batch(dev, prepared=prep)
+    for i in range(len(bufs)):
+        assert _same(first[i], again[i]), i
+
+
+def test_batch_regrowth(torch):
+    from paper_1309_0215_amd import Job
+    bufs = [gen.text(60 + i, 300_000, V=30_000, s=0.4) for i in range(4)]
+    dev = [_dev(torch, b) for b in bufs]
+    job = Job(device=0, table_slots=4096)
+    res = job.words_batch(dev)
+    for i, b in enumerate(bufs):
+        assert _oracle_equal(res[i], b), i
+    assert res[0].stats["retries"] >= 1
+
+
+def test_full_batched_config_matches_per_job_runs(torch):
+    from paper_1309_0215_amd import Job
+    specs = gen.batched_specs()  # 256 jobs, 64 KiB..16 MiB, vocab 1K..1M, s in [0.6, 1.4]
+    bufs = gen.job_inputs(specs)
+    dev = [_dev(torch, b) for b in bufs]
+    job = Job(device=0)
+    batched = job.words_batch(dev)
+    alone = Job(device=0)
+    for i in range(len(dev)):
+        r = alone.words(dev[i])
+        assert _same(batched[i], r), i
+    order = np.argsort([len(b) for b in bufs])
+    for i in list(order[:6]) + list(order[-3:]) + [int(order[len(order) // 2])]:
+        assert _oracle_equal(batched[i], bufs[i]), i
