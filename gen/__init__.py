@@ -293,14 +293,21 @@ def _job_input_worker(spec: "JobSpec") -> np.ndarray:
     return job_input(spec)
 
 
-def job_inputs(specs: list, workers: int | None = None) -> list:
-    """Inputs of many job specs, generated in parallel worker processes."""
+def job_pool(workers: int | None = None):
+    """A process pool for job_inputs (fresh interpreters: safe in a process that uses a GPU)."""
     import concurrent.futures as cf
     import multiprocessing as mp
+    return cf.ProcessPoolExecutor(workers or _threads(), mp_context=mp.get_context("spawn"))
+
+
+def job_inputs(specs: list, workers: int | None = None, pool=None) -> list:
+    """Inputs of many job specs, generated in parallel worker processes."""
+    if pool is not None:
+        return list(pool.map(_job_input_worker, specs, chunksize=1))
     w = workers or _threads()
     if w <= 1 or len(specs) <= 1:
         return [job_input(s) for s in specs]
-    with cf.ProcessPoolExecutor(w, mp_context=mp.get_context("fork")) as ex:
+    with job_pool(w) as ex:
         return list(ex.map(_job_input_worker, specs, chunksize=1))
 
 

@@ -84,6 +84,11 @@ struct mr_job {
   void* int_scratch = nullptr;   // partials, sort records, scans
   uint64_t int_scratch_bytes = 0;
   uint64_t int_last_distinct = 0;
+  // selector scratch (device): features, inputs, outputs, parameters; MLP training scratch
+  void* sel_dev = nullptr;
+  uint64_t sel_dev_floats = 0;
+  void* mlp_dev = nullptr;
+  uint64_t mlp_dev_floats = 0;
 };
 
 namespace {
@@ -137,6 +142,8 @@ mr_status ensure_host_states(mr_job* job, uint32_t n) {
   if (job->int_table) (void)hipFree(job->int_table);
   if (job->int_small) (void)hipFree(job->int_small);
   if (job->int_scratch) (void)hipFree(job->int_scratch);
+  if (job->sel_dev) (void)hipFree(job->sel_dev);
+  if (job->mlp_dev) (void)hipFree(job->mlp_dev);
   job->h_states = nullptr;
   MR_HIP(hipHostMalloc(&job->h_states, sizeof(JobState) * n, hipHostMallocDefault));
   job->h_states_cap = n;
@@ -225,6 +232,8 @@ extern "C" mr_status mr_job_destroy(mr_job* job) {
   if (job->int_table) (void)hipFree(job->int_table);
   if (job->int_small) (void)hipFree(job->int_small);
   if (job->int_scratch) (void)hipFree(job->int_scratch);
+  if (job->sel_dev) (void)hipFree(job->sel_dev);
+  if (job->mlp_dev) (void)hipFree(job->mlp_dev);
   if (job->ev0) (void)hipEventDestroy(job->ev0);
   if (job->ev1) (void)hipEventDestroy(job->ev1);
   if (job->ev2) (void)hipEventDestroy(job->ev2);
@@ -837,13 +846,6 @@ mr_status run_u32(mr_job* job, mr_map_kind kind, mr_reduce_op op, const void* d_
   return MR_OK;
 }
 
-mr_status learned_strategy(mr_job* job, mr_map_kind kind, mr_reduce_op op, const void* d_input, uint64_t bytes,
-                           uint64_t R, mr_strategy* s, bool* used) {
-  (void)job; (void)kind; (void)op; (void)d_input; (void)bytes; (void)R;
-  *s = MR_STRAT_RULE;  // no trained selector is loaded: the rule decides
-  *used = false;
-  return MR_OK;
-}
 
 mr_status run_kmeans(mr_job* job, const void* d_input, uint64_t bytes, mr_output* out) {
   const uint32_t k = job->cfg.km_k, d = job->cfg.km_d;
@@ -956,26 +958,144 @@ extern "C" mr_status mr_batch_run(mr_job* job, const mr_batch_item* items, uint3
 }
 
 // ----------------------------------------------------------------------------
-// selector entry points (implemented in selector.cpp when built)
+// reduce-strategy selector
 // ----------------------------------------------------------------------------
-#ifndef MR_HAVE_SELECTOR
-extern "C" mr_status mr_job_features(mr_job*, mr_map_kind, mr_reduce_op, const void*, uint64_t, uint64_t, float*) {
-  return fail(MR_ERR_UNSUPPORTED, "selector features are not built");
+
+namespace {
+
+mr_status sel_scratch(mr_job* job, uint64_t floats) {
+  return int_ensure(job, &job->sel_dev, &job->sel_dev_floats, floats, 4, -1);
 }
-extern "C" mr_status mr_selector_set(mr_job*, const float*, const float*, const float*, const float*, const float*) {
-  return fail(MR_ERR_UNSUPPORTED, "selector is not built");
+
+int feature_kind(mr_map_kind kind) {
+  switch (kind) {
+    case MR_MAP_WORDS: return 0;
+    case MR_MAP_U32_KEYS: return 1;
+    case MR_MAP_U32_KV: return 2;
+    default: return -1;
+  }
 }
-extern "C" mr_status mr_selector_predict(mr_job*, const float*, float*) {
-  return fail(MR_ERR_UNSUPPORTED, "selector is not built");
+
+}  // namespace
+
+extern "C" mr_status mr_job_features(mr_job* job, mr_map_kind kind, mr_reduce_op op, const void* d_input,
+                                     uint64_t input_bytes, uint64_t key_range, float* feats) {
+  if (!job || !feats || (input_bytes && !d_input)) return fail(MR_ERR_INVALID_ARG, "NULL argument");
+  const int fk = feature_kind(kind);
+  if (fk < 0) return fail(MR_ERR_UNSUPPORTED, "features exist for word and integer-key jobs");
+  if (fk > 0 && (uintptr_t)d_input % 4) return fail(MR_ERR_INVALID_ARG, "integer input must be 4-byte aligned");
+  ScopedDevice sd(job->device);
+  mr_status st = sel_scratch(job, 64);
+  if (st != MR_OK) return st;
+  float* d = static_cast<float*>(job->sel_dev);
+  MR_HIP(features_enqueue(static_cast<const uint8_t*>(d_input), input_bytes, fk, (int)op, key_range,
+                          (uint32_t)kLdsArrayBudget, d, job->stream));
+  MR_HIP(hipMemcpyAsync(feats, d, 4 * MR_N_FEATURES, hipMemcpyDeviceToHost, job->stream));
+  MR_HIP(hipStreamSynchronize(job->stream));
+  return MR_OK;
 }
-extern "C" mr_status mr_mlp_forward(mr_job*, const float*, const float*, uint32_t, float*, float*, float*) {
-  return fail(MR_ERR_UNSUPPORTED, "selector kernels are not built");
+
+extern "C" mr_status mr_selector_set(mr_job* job, const float* params, const float* feat_mean, const float* feat_scale,
+                                     const float* feat_lo, const float* feat_hi) {
+  if (!job) return fail(MR_ERR_INVALID_ARG, "NULL job");
+  if (!params) {
+    job->sel_loaded = false;
+    return MR_OK;
+  }
+  if (!feat_mean || !feat_scale || !feat_lo || !feat_hi) return fail(MR_ERR_INVALID_ARG, "NULL normalisation");
+  for (int i = 0; i < MR_N_FEATURES; ++i)
+    if (!(feat_scale[i] > 0.f)) return fail(MR_ERR_INVALID_ARG, "feature scale %d must be positive", i);
+  ScopedDevice sd(job->device);
+  job->sel_params.assign(params, params + MR_MLP_PARAMS);
+  job->sel_mean.assign(feat_mean, feat_mean + MR_N_FEATURES);
+  job->sel_scale.assign(feat_scale, feat_scale + MR_N_FEATURES);
+  job->sel_lo.assign(feat_lo, feat_lo + MR_N_FEATURES);
+  job->sel_hi.assign(feat_hi, feat_hi + MR_N_FEATURES);
+  mr_status st = sel_scratch(job, 64 + MR_MLP_PARAMS);
+  if (st != MR_OK) return st;
+  MR_HIP(hipMemcpyAsync(static_cast<float*>(job->sel_dev) + 64, params, 4 * MR_MLP_PARAMS, hipMemcpyHostToDevice,
+                        job->stream));
+  MR_HIP(hipStreamSynchronize(job->stream));
+  job->sel_loaded = true;
+  return MR_OK;
 }
-extern "C" mr_status mr_mlp_loss_backward(mr_job*, const float*, const float*, const float*, const float*, const float*,
-                                          const float*, const float*, uint32_t, float*, float*) {
-  return fail(MR_ERR_UNSUPPORTED, "selector kernels are not built");
+
+// Network output for host features, computed by the forward kernel (batch of one).
+extern "C" mr_status mr_selector_predict(mr_job* job, const float* feats, float* pred) {
+  if (!job || !feats || !pred) return fail(MR_ERR_INVALID_ARG, "NULL argument");
+  if (!job->sel_loaded) return fail(MR_ERR_INVALID_ARG, "no selector weights are loaded");
+  ScopedDevice sd(job->device);
+  float x[16];
+  for (int i = 0; i < MR_N_FEATURES; ++i) x[i] = (feats[i] - job->sel_mean[i]) / job->sel_scale[i];
+  float* d = static_cast<float*>(job->sel_dev);
+  MR_HIP(hipMemcpyAsync(d + 16, x, 4 * MR_N_FEATURES, hipMemcpyHostToDevice, job->stream));
+  MR_HIP(mlp_forward_enqueue(d + 64, d + 16, 1, nullptr, nullptr, d + 32, job->stream));
+  MR_HIP(hipMemcpyAsync(pred, d + 32, 4 * MR_N_STRATS, hipMemcpyDeviceToHost, job->stream));
+  MR_HIP(hipStreamSynchronize(job->stream));
+  return MR_OK;
 }
-extern "C" mr_status mr_mlp_adam(mr_job*, float*, const float*, float*, float*, uint32_t, float, float, float, float) {
-  return fail(MR_ERR_UNSUPPORTED, "selector kernels are not built");
+
+namespace {
+
+mr_status learned_strategy(mr_job* job, mr_map_kind kind, mr_reduce_op op, const void* d_input, uint64_t bytes,
+                           uint64_t R, mr_strategy* s, bool* used) {
+  *s = MR_STRAT_RULE;
+  *used = false;
+  if (!job->sel_loaded) return MR_OK;  // no weights: the rule decides
+  float f[MR_N_FEATURES];
+  mr_status st = mr_job_features(job, kind, op, d_input, bytes, R, f);
+  if (st != MR_OK) return st;
+  for (int i = 0; i < MR_N_FEATURES; ++i)
+    if (f[i] < job->sel_lo[i] || f[i] > job->sel_hi[i]) return MR_OK;  // outside the training range
+  float pred[MR_N_STRATS];
+  st = mr_selector_predict(job, f, pred);
+  if (st != MR_OK) return st;
+  static const mr_strategy order[MR_N_STRATS] = {MR_STRAT_LDS_ARRAY, MR_STRAT_GLOBAL_ARRAY, MR_STRAT_HASH, MR_STRAT_SORT};
+  int best = -1;
+  for (int i = 0; i < MR_N_STRATS; ++i)
+    if (int_feasible(order[i], R, (uint32_t)op) && (best < 0 || pred[i] < pred[best])) best = i;
+  if (best < 0) return MR_OK;
+  *s = order[best];
+  *used = true;
+  return MR_OK;
 }
-#endif
+
+mr_status mlp_scratch(mr_job* job, uint32_t B) {
+  const uint64_t need = (uint64_t)B * (4 + 64 + 64) + 64;
+  return int_ensure(job, &job->mlp_dev, &job->mlp_dev_floats, need, 4, -1);
+}
+
+}  // namespace
+
+extern "C" mr_status mr_mlp_forward(mr_job* job, const float* params, const float* X, uint32_t B, float* H1, float* H2,
+                                    float* Y) {
+  if (!job || !params || (B && (!X || !Y))) return fail(MR_ERR_INVALID_ARG, "NULL argument");
+  ScopedDevice sd(job->device);
+  MR_HIP(mlp_forward_enqueue(params, X, B, H1, H2, Y, job->stream));
+  return MR_OK;
+}
+
+extern "C" mr_status mr_mlp_loss_backward(mr_job* job, const float* params, const float* X, const float* H1,
+                                          const float* H2, const float* Y, const float* T, const float* M, uint32_t B,
+                                          float* loss, float* grad) {
+  if (!job || !params || !loss || !grad || (B && (!X || !H1 || !H2 || !Y || !T || !M)))
+    return fail(MR_ERR_INVALID_ARG, "NULL argument");
+  ScopedDevice sd(job->device);
+  mr_status st = mlp_scratch(job, B);
+  if (st != MR_OK) return st;
+  float* d = static_cast<float*>(job->mlp_dev);
+  float* dY = d;
+  float* dZ1 = d + 4ull * B;
+  float* dZ2 = dZ1 + 64ull * B;
+  MR_HIP(mlp_backward_enqueue(params, X, H1, H2, Y, T, M, B, dY, dZ1, dZ2, loss, grad, job->stream));
+  return MR_OK;
+}
+
+extern "C" mr_status mr_mlp_adam(mr_job* job, float* params, const float* grad, float* m, float* v, uint32_t step, float lr,
+                                 float beta1, float beta2, float eps) {
+  if (!job || !params || !grad || !m || !v) return fail(MR_ERR_INVALID_ARG, "NULL argument");
+  if (step == 0) return fail(MR_ERR_INVALID_ARG, "Adam steps count from 1");
+  ScopedDevice sd(job->device);
+  MR_HIP(adam_enqueue(params, grad, m, v, step, lr, beta1, beta2, eps, job->stream));
+  return MR_OK;
+}

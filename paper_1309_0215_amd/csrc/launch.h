@@ -107,4 +107,14 @@ struct KmLaunch {
 
 hipError_t km_enqueue(const KmLaunch& L, hipStream_t s, hipEvent_t map0, hipEvent_t map1);
 
+// Selector: features of a job and the network kernels.
+hipError_t features_enqueue(const uint8_t* in, uint64_t bytes, int kind, int op, uint64_t key_range, uint32_t lds_budget,
+                            float* feats, hipStream_t s);
+hipError_t mlp_forward_enqueue(const float* P, const float* X, uint32_t B, float* H1, float* H2, float* Y, hipStream_t s);
+hipError_t mlp_backward_enqueue(const float* P, const float* X, const float* H1, const float* H2, const float* Y,
+                                const float* T, const float* M, uint32_t B, float* dY, float* dZ1, float* dZ2, float* loss,
+                                float* G, hipStream_t s);
+hipError_t adam_enqueue(float* P, const float* G, float* m, float* v, uint32_t step, float lr, float b1, float b2, float eps,
+                        hipStream_t s);
+
 }  // namespace mr

@@ -1,0 +1,361 @@
+// Learned reduce-strategy selector on gfx950: job features from a sample of
+// the input, and the kernels of a 12-64-64-4 ReLU network (forward, masked
+// mean-squared-error backward, Adam). The paper's framework decides which
+// technique to apply from properties of the job (Sections III-B, III-E); here
+// the decision among the four reduce containers is learned from measured
+// times, with the paper-style rule as the fallback and the yardstick.
+#include "common.h"
+#include "launch.h"
+
+namespace mr {
+
+// ----------------------------------------------------------------------------
+// features
+// ----------------------------------------------------------------------------
+constexpr int kFeatThreads = 1024;
+constexpr uint32_t kHllLog = 11;                    // 2048 registers
+constexpr uint32_t kHllM = 1u << kHllLog;
+constexpr uint32_t kFeatSlots = 8192;               // exact counts of sampled keys
+constexpr uint32_t kWindows = 32;
+constexpr uint32_t kWindowBytes = 4096;
+
+MR_DEV void hll_add(uint32_t* reg, uint64_t h) {
+  const uint32_t idx = (uint32_t)(h >> (64 - kHllLog));
+  const uint64_t rest = (h << kHllLog) | (1ull << (kHllLog - 1));  // guard bit bounds the rank
+  const uint32_t rank = (uint32_t)__clzll((long long)rest) + 1;
+  atomicMax(&reg[idx], rank);
+}
+
+MR_DEV float hll_estimate(const uint32_t* reg, float* red) {
+  // sum of 2^-M and zero registers, by the whole block
+  float s = 0.f;
+  float z = 0.f;
+  for (uint32_t i = threadIdx.x; i < kHllM; i += blockDim.x) {
+    s += exp2f(-(float)reg[i]);
+    z += reg[i] == 0 ? 1.f : 0.f;
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    s += __shfl_xor(s, o);
+    z += __shfl_xor(z, o);
+  }
+  __syncthreads();
+  if (lane_id() == 0) {
+    red[2 * (threadIdx.x / kWave)] = s;
+    red[2 * (threadIdx.x / kWave) + 1] = z;
+  }
+  __syncthreads();
+  float S = 0.f, Z = 0.f;
+  for (uint32_t w = 0; w < blockDim.x / kWave; ++w) {
+    S += red[2 * w];
+    Z += red[2 * w + 1];
+  }
+  __syncthreads();
+  const float m = (float)kHllM;
+  const float alpha = 0.7213f / (1.f + 1.079f / m);
+  float E = alpha * m * m / S;
+  if (E <= 2.5f * m && Z > 0.f) E = m * logf(m / Z);  // small-range correction (linear counting)
+  return E;
+}
+
+MR_DEV void feat_insert(uint32_t* tk, uint32_t* tc, uint32_t key) {
+  uint32_t s = (uint32_t)hash_u32(key) & (kFeatSlots - 1);
+  for (int p = 0; p < 32; ++p) {
+    uint32_t cur = tk[s];
+    if (cur == 0xFFFFFFFFu) cur = atomicCAS(&tk[s], 0xFFFFFFFFu, key);
+    if (cur == 0xFFFFFFFFu || cur == key) {
+      atomicAdd(&tc[s], 1u);
+      return;
+    }
+    s = (s + 1) & (kFeatSlots - 1);
+  }
+}
+
+// kind: 0 words, 1 u32 keys, 2 u32 (key, value) pairs. One workgroup.
+__global__ __launch_bounds__(kFeatThreads) void k_features(const uint8_t* __restrict__ in, uint64_t bytes, int kind, int op,
+                                                           uint64_t key_range, uint32_t lds_budget, float* __restrict__ feats) {
+  __shared__ uint32_t hll_all[kHllM];
+  __shared__ uint32_t hll_half[kHllM];
+  __shared__ uint32_t tk[kFeatSlots];
+  __shared__ uint32_t tc[kFeatSlots];
+  __shared__ float red[2 * kFeatThreads / kWave];
+  __shared__ unsigned long long s_n, s_len, s_len2;
+  __shared__ uint32_t top[64];
+  __shared__ uint32_t s_best, s_bidx;
+  for (uint32_t i = threadIdx.x; i < kHllM; i += blockDim.x) hll_all[i] = hll_half[i] = 0;
+  for (uint32_t i = threadIdx.x; i < kFeatSlots; i += blockDim.x) {
+    tk[i] = 0xFFFFFFFFu;
+    tc[i] = 0;
+  }
+  if (threadIdx.x == 0) s_n = s_len = s_len2 = 0;
+  __syncthreads();
+  const uint64_t esz = kind == 0 ? 1 : (kind == 1 ? 4 : 8);
+  const uint64_t n_elem = bytes / esz;
+  // windows: the whole input when small, else kWindows evenly spaced windows
+  const uint64_t wel = kWindowBytes / esz;
+  const bool whole = n_elem <= (uint64_t)kWindows * wel;
+  const uint32_t nwin = whole ? 1u : kWindows;
+  unsigned long long my_n = 0, my_len = 0, my_len2 = 0;
+  for (uint32_t w = 0; w < nwin; ++w) {
+    const uint64_t e0 = whole ? 0 : (n_elem - wel) * w / (kWindows - 1);
+    const uint64_t e1 = whole ? n_elem : e0 + wel;
+    const bool half = w < (nwin + 1) / 2 || whole;
+    if (kind == 0) {
+      // words starting inside the window (a word may run past it)
+      for (uint64_t p = e0 + threadIdx.x; p < e1; p += blockDim.x) {
+        const bool start = !is_sep_byte(in[p]) && (p == 0 || is_sep_byte(in[p - 1]));
+        if (!start) continue;
+        uint32_t h = 2166136261u;
+        uint64_t q = p;
+        while (q < bytes && !is_sep_byte(in[q]) && q - p < 256) {
+          h = (h ^ in[q]) * 16777619u;
+          ++q;
+        }
+        const uint64_t len = q - p;
+        const uint64_t hh = hash_u32(h ^ (uint32_t)(len * 0x9E3779B9u));
+        hll_add(hll_all, hh);
+        if (half && !whole) hll_add(hll_half, hh);
+        if (whole && (p & 1)) hll_add(hll_half, hh);
+        feat_insert(tk, tc, (uint32_t)hh);
+        ++my_n;
+        my_len += len;
+        my_len2 += len * len;
+      }
+    } else {
+      for (uint64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+        const uint32_t k = reinterpret_cast<const uint32_t*>(in)[e * (esz / 4)];
+        const uint64_t hh = hash_u32(k);
+        hll_add(hll_all, hh);
+        if (half && !whole) hll_add(hll_half, hh);
+        if (whole && (e & 1)) hll_add(hll_half, hh);
+        feat_insert(tk, tc, k);
+        ++my_n;
+      }
+    }
+  }
+  atomicAdd(&s_n, my_n);
+  atomicAdd(&s_len, my_len);
+  atomicAdd(&s_len2, my_len2);
+  __syncthreads();
+  const float D_all = hll_estimate(hll_all, red);
+  const float D_half = hll_estimate(hll_half, red);
+  // the 64 largest counts (repeated block argmax; the table is small)
+  for (int r = 0; r < 64; ++r) {
+    if (threadIdx.x == 0) {
+      s_best = 0;
+      s_bidx = 0xFFFFFFFFu;
+    }
+    __syncthreads();
+    uint32_t b = 0, bi = 0xFFFFFFFFu;
+    for (uint32_t i = threadIdx.x; i < kFeatSlots; i += blockDim.x)
+      if (tc[i] > b) {
+        b = tc[i];
+        bi = i;
+      }
+    if (b) atomicMax(&s_best, b);
+    __syncthreads();
+    if (b && b == s_best) atomicMin(&s_bidx, bi);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      top[r] = s_best;
+      if (s_bidx != 0xFFFFFFFFu) tc[s_bidx] = 0;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  const float n_s = (float)(s_n ? s_n : 1ull);
+  // elements in the whole input (words: scaled from the sample's word density)
+  const float sample_bytes = whole ? (float)bytes : (float)kWindows * (float)kWindowBytes;
+  const float T = kind == 0 ? n_s * (float)bytes / fmaxf(sample_bytes, 1.f) : (float)n_elem;
+  // growth exponent of distinct keys with sample size (Heaps' law), from half vs all
+  float beta = (D_half > 0.f && D_all > D_half) ? log2f(D_all / D_half) : 0.f;
+  beta = fminf(fmaxf(beta, 0.f), 1.f);
+  float D_est = fmaxf(D_all, 1.f) * powf(fmaxf(T / n_s, 1.f), beta);
+  D_est = fminf(D_est, fmaxf(T, 1.f));
+  if (key_range) D_est = fminf(D_est, (float)key_range);
+  // Zipf exponent: least-squares slope of log count against log rank over the top counts
+  float sx = 0, sy = 0, sxx = 0, sxy = 0, m = 0, top64 = 0;
+  for (int r = 0; r < 64; ++r) {
+    top64 += (float)top[r];
+    if (top[r] > 0) {
+      const float x = logf((float)(r + 1)), y = logf((float)top[r]);
+      sx += x; sy += y; sxx += x * x; sxy += x * y; m += 1.f;
+    }
+  }
+  const float den = m * sxx - sx * sx;
+  const float zipf = (m >= 2.f && den > 0.f) ? -(m * sxy - sx * sy) / den : 0.f;
+  const float mean_len = kind == 0 ? (float)s_len / n_s : (float)esz;
+  const float var_len = kind == 0 ? fmaxf((float)s_len2 / n_s - mean_len * mean_len, 0.f) : 0.f;
+  feats[0] = log2f(fmaxf((float)bytes, 1.f));
+  feats[1] = kind == 0 ? 1.f : 0.f;
+  feats[2] = kind == 0 ? 0.f : 1.f;
+  feats[3] = op == 1 ? 1.f : 0.f;
+  feats[4] = log2f(fmaxf(D_est, 1.f));
+  feats[5] = zipf;
+  feats[6] = (float)top[0] / n_s;
+  feats[7] = top64 / n_s;
+  feats[8] = mean_len;
+  feats[9] = sqrtf(var_len);
+  feats[10] = key_range ? log2f((float)key_range) : 0.f;
+  feats[11] = log2f(fmaxf(D_est * 32.f, 1.f) / (float)lds_budget);  // table bytes at load 1/2, 16-byte slots
+}
+
+hipError_t features_enqueue(const uint8_t* in, uint64_t bytes, int kind, int op, uint64_t key_range, uint32_t lds_budget,
+                            float* feats, hipStream_t s) {
+  hipLaunchKernelGGL(k_features, dim3(1), dim3(kFeatThreads), 0, s, in, bytes, kind, op, key_range, lds_budget, feats);
+  return hipGetLastError();
+}
+
+// ----------------------------------------------------------------------------
+// MLP 12 -> 64 -> 64 -> 4 (float32), parameter layout W1[64][12] b1 W2[64][64] b2 W3[4][64] b3
+// ----------------------------------------------------------------------------
+constexpr int kIn = 12, kH = 64, kOut = 4;
+constexpr int oW1 = 0, ob1 = oW1 + kH * kIn, oW2 = ob1 + kH, ob2 = oW2 + kH * kH, oW3 = ob2 + kH, ob3 = oW3 + kOut * kH;
+constexpr int kParams = ob3 + kOut;
+static_assert(kParams == 5252, "parameter count");
+
+// One workgroup of 64 threads per sample.
+__global__ __launch_bounds__(64) void k_mlp_fwd(const float* __restrict__ P, const float* __restrict__ X, uint32_t B,
+                                                float* __restrict__ H1, float* __restrict__ H2, float* __restrict__ Y) {
+  __shared__ float x[kIn], h1[kH], h2[kH];
+  for (uint32_t b = blockIdx.x; b < B; b += gridDim.x) {
+    const int j = threadIdx.x;
+    if (j < kIn) x[j] = X[(uint64_t)b * kIn + j];
+    __syncthreads();
+    float z = P[ob1 + j];
+    for (int i = 0; i < kIn; ++i) z = fmaf(P[oW1 + j * kIn + i], x[i], z);
+    h1[j] = fmaxf(z, 0.f);
+    __syncthreads();
+    z = P[ob2 + j];
+    for (int i = 0; i < kH; ++i) z = fmaf(P[oW2 + j * kH + i], h1[i], z);
+    h2[j] = fmaxf(z, 0.f);
+    __syncthreads();
+    if (H1) H1[(uint64_t)b * kH + j] = h1[j];
+    if (H2) H2[(uint64_t)b * kH + j] = h2[j];
+    if (j < kOut) {
+      float y = P[ob3 + j];
+      for (int i = 0; i < kH; ++i) y = fmaf(P[oW3 + j * kH + i], h2[i], y);
+      Y[(uint64_t)b * kOut + j] = y;
+    }
+    __syncthreads();
+  }
+}
+
+// loss = sum M (Y - T)^2 / max(sum M, 1); dY = 2 M (Y - T) / max(sum M, 1). One workgroup.
+__global__ __launch_bounds__(256) void k_mlp_dy(const float* __restrict__ Y, const float* __restrict__ T,
+                                                const float* __restrict__ M, uint32_t B, float* __restrict__ dY,
+                                                float* __restrict__ loss) {
+  __shared__ float r1[256 / kWave], r2[256 / kWave];
+  float sm = 0.f, sl = 0.f;
+  for (uint32_t i = threadIdx.x; i < B * kOut; i += blockDim.x) {
+    const float d = Y[i] - T[i];
+    sm += M[i];
+    sl += M[i] * d * d;
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    sm += __shfl_xor(sm, o);
+    sl += __shfl_xor(sl, o);
+  }
+  if (lane_id() == 0) {
+    r1[threadIdx.x / kWave] = sm;
+    r2[threadIdx.x / kWave] = sl;
+  }
+  __syncthreads();
+  float SM = 0.f, SL = 0.f;
+  for (int w = 0; w < 256 / kWave; ++w) {
+    SM += r1[w];
+    SL += r2[w];
+  }
+  const float den = fmaxf(SM, 1.f);
+  if (threadIdx.x == 0) *loss = SL / den;
+  for (uint32_t i = threadIdx.x; i < B * kOut; i += blockDim.x) dY[i] = 2.f * M[i] * (Y[i] - T[i]) / den;
+}
+
+// dZ2 = (dY W3) * [H2 > 0], dZ1 = (dZ2 W2) * [H1 > 0]; one workgroup of 64 per sample.
+__global__ __launch_bounds__(64) void k_mlp_dz(const float* __restrict__ P, const float* __restrict__ H1,
+                                               const float* __restrict__ H2, const float* __restrict__ dY, uint32_t B,
+                                               float* __restrict__ dZ1, float* __restrict__ dZ2) {
+  __shared__ float dz2[kH], dy[kOut];
+  for (uint32_t b = blockIdx.x; b < B; b += gridDim.x) {
+    const int j = threadIdx.x;
+    if (j < kOut) dy[j] = dY[(uint64_t)b * kOut + j];
+    __syncthreads();
+    float g = 0.f;
+    for (int o = 0; o < kOut; ++o) g = fmaf(dy[o], P[oW3 + o * kH + j], g);
+    const float d2 = H2[(uint64_t)b * kH + j] > 0.f ? g : 0.f;
+    dz2[j] = d2;
+    dZ2[(uint64_t)b * kH + j] = d2;
+    __syncthreads();
+    g = 0.f;
+    for (int i = 0; i < kH; ++i) g = fmaf(dz2[i], P[oW2 + i * kH + j], g);
+    dZ1[(uint64_t)b * kH + j] = H1[(uint64_t)b * kH + j] > 0.f ? g : 0.f;
+    __syncthreads();
+  }
+}
+
+// One thread per parameter: the sum over the batch of its chain-rule term.
+__global__ __launch_bounds__(256) void k_mlp_grad(const float* __restrict__ X, const float* __restrict__ H1,
+                                                  const float* __restrict__ H2, const float* __restrict__ dY,
+                                                  const float* __restrict__ dZ1, const float* __restrict__ dZ2, uint32_t B,
+                                                  float* __restrict__ G) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= kParams) return;
+  float s = 0.f;
+  if (p < ob1) {  // W1[j][i] = sum_b dZ1[b][j] X[b][i]
+    const int j = p / kIn, i = p % kIn;
+    for (uint32_t b = 0; b < B; ++b) s = fmaf(dZ1[(uint64_t)b * kH + j], X[(uint64_t)b * kIn + i], s);
+  } else if (p < oW2) {
+    const int j = p - ob1;
+    for (uint32_t b = 0; b < B; ++b) s += dZ1[(uint64_t)b * kH + j];
+  } else if (p < ob2) {
+    const int j = (p - oW2) / kH, i = (p - oW2) % kH;
+    for (uint32_t b = 0; b < B; ++b) s = fmaf(dZ2[(uint64_t)b * kH + j], H1[(uint64_t)b * kH + i], s);
+  } else if (p < oW3) {
+    const int j = p - ob2;
+    for (uint32_t b = 0; b < B; ++b) s += dZ2[(uint64_t)b * kH + j];
+  } else if (p < ob3) {
+    const int o = (p - oW3) / kH, i = (p - oW3) % kH;
+    for (uint32_t b = 0; b < B; ++b) s = fmaf(dY[(uint64_t)b * kOut + o], H2[(uint64_t)b * kH + i], s);
+  } else {
+    const int o = p - ob3;
+    for (uint32_t b = 0; b < B; ++b) s += dY[(uint64_t)b * kOut + o];
+  }
+  G[p] = s;
+}
+
+__global__ __launch_bounds__(256) void k_adam(float* __restrict__ P, const float* __restrict__ G, float* __restrict__ m,
+                                              float* __restrict__ v, uint32_t step, float lr, float b1, float b2, float eps) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= kParams) return;
+  const float g = G[p];
+  const float mm = b1 * m[p] + (1.f - b1) * g;
+  const float vv = b2 * v[p] + (1.f - b2) * g * g;
+  m[p] = mm;
+  v[p] = vv;
+  const float mh = mm / (1.f - powf(b1, (float)step));
+  const float vh = vv / (1.f - powf(b2, (float)step));
+  P[p] -= lr * mh / (sqrtf(vh) + eps);
+}
+
+hipError_t mlp_forward_enqueue(const float* P, const float* X, uint32_t B, float* H1, float* H2, float* Y, hipStream_t s) {
+  const uint32_t g = B < 4096 ? (B ? B : 1) : 4096;
+  hipLaunchKernelGGL(k_mlp_fwd, dim3(g), dim3(64), 0, s, P, X, B, H1, H2, Y);
+  return hipGetLastError();
+}
+
+hipError_t mlp_backward_enqueue(const float* P, const float* X, const float* H1, const float* H2, const float* Y,
+                                const float* T, const float* M, uint32_t B, float* dY, float* dZ1, float* dZ2, float* loss,
+                                float* G, hipStream_t s) {
+  hipLaunchKernelGGL(k_mlp_dy, dim3(1), dim3(256), 0, s, Y, T, M, B, dY, loss);
+  const uint32_t g = B < 4096 ? (B ? B : 1) : 4096;
+  hipLaunchKernelGGL(k_mlp_dz, dim3(g), dim3(64), 0, s, P, H1, H2, dY, B, dZ1, dZ2);
+  hipLaunchKernelGGL(k_mlp_grad, dim3((kParams + 255) / 256), dim3(256), 0, s, X, H1, H2, dY, dZ1, dZ2, B, G);
+  return hipGetLastError();
+}
+
+hipError_t adam_enqueue(float* P, const float* G, float* m, float* v, uint32_t step, float lr, float b1, float b2, float eps,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(k_adam, dim3((kParams + 255) / 256), dim3(256), 0, s, P, G, m, v, step, lr, b1, b2, eps);
+  return hipGetLastError();
+}
+
+}  // namespace mr
