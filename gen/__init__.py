@@ -294,21 +294,29 @@ def _job_input_worker(spec: "JobSpec") -> np.ndarray:
 
 
 def job_pool(workers: int | None = None):
-    """A process pool for job_inputs (fresh interpreters: safe in a process that uses a GPU)."""
+    """A warmed-up process pool for job_inputs.
+
+    Create it before the process touches a GPU: all workers are started here
+    and no process is started later, so a GPU-initialised process never forks
+    or execs."""
     import concurrent.futures as cf
     import multiprocessing as mp
-    return cf.ProcessPoolExecutor(workers or _threads(), mp_context=mp.get_context("spawn"))
+    import time as _time
+    w = workers or _threads()
+    pool = cf.ProcessPoolExecutor(w, mp_context=mp.get_context("spawn"))
+    list(pool.map(_time.sleep, [0.5] * w))  # one task per worker starts every worker now
+    return pool
 
 
 def job_inputs(specs: list, workers: int | None = None, pool=None) -> list:
-    """Inputs of many job specs, generated in parallel worker processes."""
+    """Inputs of many job specs: in `pool` (see job_pool) if given, else in threads."""
     if pool is not None:
         return list(pool.map(_job_input_worker, specs, chunksize=1))
     w = workers or _threads()
     if w <= 1 or len(specs) <= 1:
         return [job_input(s) for s in specs]
-    with job_pool(w) as ex:
-        return list(ex.map(_job_input_worker, specs, chunksize=1))
+    with _cf.ThreadPoolExecutor(w) as ex:
+        return list(ex.map(job_input, specs))
 
 
 def job_input(spec: JobSpec) -> np.ndarray:

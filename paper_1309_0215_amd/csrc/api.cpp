@@ -93,9 +93,15 @@ struct mr_job {
 
 namespace {
 
+// Every entry point selects the job's device and starts from a clear HIP
+// error state, so that an error left behind by other code in the process is
+// not reported as a failure of this call (kernel launches are checked with
+// hipGetLastError).
 struct ScopedDevice {
   int prev = -1;
+  hipError_t stale = hipSuccess;
   explicit ScopedDevice(int d) {
+    stale = hipGetLastError();
     if (hipGetDevice(&prev) != hipSuccess) prev = -1;
     if (prev != d) (void)hipSetDevice(d);
   }
@@ -138,12 +144,6 @@ mr_status ensure_ws(mr_job* job, uint64_t bytes) {
 mr_status ensure_host_states(mr_job* job, uint32_t n) {
   if (n <= job->h_states_cap) return MR_OK;
   if (job->h_states) (void)hipHostFree(job->h_states);
-  if (job->int_dense) (void)hipFree(job->int_dense);
-  if (job->int_table) (void)hipFree(job->int_table);
-  if (job->int_small) (void)hipFree(job->int_small);
-  if (job->int_scratch) (void)hipFree(job->int_scratch);
-  if (job->sel_dev) (void)hipFree(job->sel_dev);
-  if (job->mlp_dev) (void)hipFree(job->mlp_dev);
   job->h_states = nullptr;
   MR_HIP(hipHostMalloc(&job->h_states, sizeof(JobState) * n, hipHostMallocDefault));
   job->h_states_cap = n;
@@ -616,6 +616,8 @@ struct IntSmall {
   unsigned long long side_val;
   unsigned long long n_claimed;
   unsigned long long n_out;
+  int32_t choice;  // learned container choice (-1: use the rule)
+  int32_t pad;
 };
 
 mr_status int_ensure(mr_job* job, void** p, uint64_t* have, uint64_t want, uint64_t elem_bytes, int fill) {
@@ -705,7 +707,15 @@ mr_status run_u32(mr_job* job, mr_map_kind kind, mr_reduce_op op, const void* d_
   };
   uint32_t retries = 0;
   uint64_t table_cap = 0;
-  MR_HIP(hipMemsetAsync(sm, 0, sizeof(IntSmall), job->stream));
+  {
+    const hipError_t e = hipMemsetAsync(sm, 0, sizeof(IntSmall), job->stream);
+    if (e != hipSuccess) {
+      hipPointerAttribute_t at{};
+      const hipError_t ea = hipPointerGetAttributes(&at, sm);
+      return fail(MR_ERR_HIP, "hipMemsetAsync(state %p, %zu) on stream %p: %s (pointer query: %s, type %d)", (void*)sm,
+                  sizeof(IntSmall), (void*)job->stream, hipGetErrorString(e), hipGetErrorString(ea), (int)at.type);
+    }
+  }
   MR_HIP(hipEventRecord(job->ev0, job->stream));
 
   if (strat == MR_STRAT_LDS_ARRAY || strat == MR_STRAT_GLOBAL_ARRAY) {
@@ -963,6 +973,13 @@ extern "C" mr_status mr_batch_run(mr_job* job, const mr_batch_item* items, uint3
 
 namespace {
 
+// Selector scratch (device floats): [0, 16) features, [16, 32) network input,
+// [32, 48) network output, [64, 128) normalisation (mean, scale, lo, hi at
+// +0, +16, +32, +48), [128, 128 + 5252) parameters.
+constexpr uint64_t kSelNorm = 64;
+constexpr uint64_t kSelParams = 128;
+constexpr uint64_t kSelFloats = kSelParams + MR_MLP_PARAMS;
+
 mr_status sel_scratch(mr_job* job, uint64_t floats) {
   return int_ensure(job, &job->sel_dev, &job->sel_dev_floats, floats, 4, -1);
 }
@@ -985,7 +1002,7 @@ extern "C" mr_status mr_job_features(mr_job* job, mr_map_kind kind, mr_reduce_op
   if (fk < 0) return fail(MR_ERR_UNSUPPORTED, "features exist for word and integer-key jobs");
   if (fk > 0 && (uintptr_t)d_input % 4) return fail(MR_ERR_INVALID_ARG, "integer input must be 4-byte aligned");
   ScopedDevice sd(job->device);
-  mr_status st = sel_scratch(job, 64);
+  mr_status st = sel_scratch(job, kSelFloats);
   if (st != MR_OK) return st;
   float* d = static_cast<float*>(job->sel_dev);
   MR_HIP(features_enqueue(static_cast<const uint8_t*>(d_input), input_bytes, fk, (int)op, key_range,
@@ -1011,10 +1028,14 @@ extern "C" mr_status mr_selector_set(mr_job* job, const float* params, const flo
   job->sel_scale.assign(feat_scale, feat_scale + MR_N_FEATURES);
   job->sel_lo.assign(feat_lo, feat_lo + MR_N_FEATURES);
   job->sel_hi.assign(feat_hi, feat_hi + MR_N_FEATURES);
-  mr_status st = sel_scratch(job, 64 + MR_MLP_PARAMS);
+  mr_status st = sel_scratch(job, kSelFloats);
   if (st != MR_OK) return st;
-  MR_HIP(hipMemcpyAsync(static_cast<float*>(job->sel_dev) + 64, params, 4 * MR_MLP_PARAMS, hipMemcpyHostToDevice,
-                        job->stream));
+  float* dv = static_cast<float*>(job->sel_dev);
+  MR_HIP(hipMemcpyAsync(dv + kSelParams, params, 4 * MR_MLP_PARAMS, hipMemcpyHostToDevice, job->stream));
+  MR_HIP(hipMemcpyAsync(dv + kSelNorm, feat_mean, 4 * MR_N_FEATURES, hipMemcpyHostToDevice, job->stream));
+  MR_HIP(hipMemcpyAsync(dv + kSelNorm + 16, feat_scale, 4 * MR_N_FEATURES, hipMemcpyHostToDevice, job->stream));
+  MR_HIP(hipMemcpyAsync(dv + kSelNorm + 32, feat_lo, 4 * MR_N_FEATURES, hipMemcpyHostToDevice, job->stream));
+  MR_HIP(hipMemcpyAsync(dv + kSelNorm + 48, feat_hi, 4 * MR_N_FEATURES, hipMemcpyHostToDevice, job->stream));
   MR_HIP(hipStreamSynchronize(job->stream));
   job->sel_loaded = true;
   return MR_OK;
@@ -1029,7 +1050,7 @@ extern "C" mr_status mr_selector_predict(mr_job* job, const float* feats, float*
   for (int i = 0; i < MR_N_FEATURES; ++i) x[i] = (feats[i] - job->sel_mean[i]) / job->sel_scale[i];
   float* d = static_cast<float*>(job->sel_dev);
   MR_HIP(hipMemcpyAsync(d + 16, x, 4 * MR_N_FEATURES, hipMemcpyHostToDevice, job->stream));
-  MR_HIP(mlp_forward_enqueue(d + 64, d + 16, 1, nullptr, nullptr, d + 32, job->stream));
+  MR_HIP(mlp_forward_enqueue(d + kSelParams, d + 16, 1, nullptr, nullptr, d + 32, job->stream));
   MR_HIP(hipMemcpyAsync(pred, d + 32, 4 * MR_N_STRATS, hipMemcpyDeviceToHost, job->stream));
   MR_HIP(hipStreamSynchronize(job->stream));
   return MR_OK;
@@ -1037,26 +1058,34 @@ extern "C" mr_status mr_selector_predict(mr_job* job, const float* feats, float*
 
 namespace {
 
+// Features, normalisation, network and argmin over the feasible containers
+// all run on the device; the choice comes back in the job's small state block.
 mr_status learned_strategy(mr_job* job, mr_map_kind kind, mr_reduce_op op, const void* d_input, uint64_t bytes,
                            uint64_t R, mr_strategy* s, bool* used) {
   *s = MR_STRAT_RULE;
   *used = false;
   if (!job->sel_loaded) return MR_OK;  // no weights: the rule decides
-  float f[MR_N_FEATURES];
-  mr_status st = mr_job_features(job, kind, op, d_input, bytes, R, f);
-  if (st != MR_OK) return st;
-  for (int i = 0; i < MR_N_FEATURES; ++i)
-    if (f[i] < job->sel_lo[i] || f[i] > job->sel_hi[i]) return MR_OK;  // outside the training range
-  float pred[MR_N_STRATS];
-  st = mr_selector_predict(job, f, pred);
-  if (st != MR_OK) return st;
+  const int fk = feature_kind(kind);
+  if (fk < 0) return MR_OK;
   static const mr_strategy order[MR_N_STRATS] = {MR_STRAT_LDS_ARRAY, MR_STRAT_GLOBAL_ARRAY, MR_STRAT_HASH, MR_STRAT_SORT};
-  int best = -1;
+  uint32_t feas = 0;
   for (int i = 0; i < MR_N_STRATS; ++i)
-    if (int_feasible(order[i], R, (uint32_t)op) && (best < 0 || pred[i] < pred[best])) best = i;
-  if (best < 0) return MR_OK;
-  *s = order[best];
-  *used = true;
+    if (int_feasible(order[i], R, (uint32_t)op)) feas |= 1u << i;
+  uint64_t small_have = job->int_small ? 1 : 0;
+  mr_status st = int_ensure(job, &job->int_small, &small_have, 1, sizeof(IntSmall), 0);
+  if (st != MR_OK) return st;
+  IntSmall* sm = static_cast<IntSmall*>(job->int_small);
+  float* d = static_cast<float*>(job->sel_dev);
+  MR_HIP(features_enqueue(static_cast<const uint8_t*>(d_input), bytes, fk, (int)op, R, (uint32_t)kLdsArrayBudget, d,
+                          job->stream));
+  MR_HIP(select_enqueue(d, d + kSelNorm, d + kSelParams, feas, reinterpret_cast<int32_t*>(&sm->choice), job->stream));
+  IntSmall hs;
+  MR_HIP(hipMemcpyAsync(&hs, sm, sizeof hs, hipMemcpyDeviceToHost, job->stream));
+  MR_HIP(hipStreamSynchronize(job->stream));
+  if (hs.choice >= 0 && hs.choice < MR_N_STRATS) {
+    *s = order[hs.choice];
+    *used = true;
+  }
   return MR_OK;
 }
 

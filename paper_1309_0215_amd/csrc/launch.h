@@ -111,6 +111,8 @@ hipError_t km_enqueue(const KmLaunch& L, hipStream_t s, hipEvent_t map0, hipEven
 hipError_t features_enqueue(const uint8_t* in, uint64_t bytes, int kind, int op, uint64_t key_range, uint32_t lds_budget,
                             float* feats, hipStream_t s);
 hipError_t mlp_forward_enqueue(const float* P, const float* X, uint32_t B, float* H1, float* H2, float* Y, hipStream_t s);
+hipError_t select_enqueue(const float* feats, const float* norm, const float* P, uint32_t feas, int32_t* choice,
+                          hipStream_t s);
 hipError_t mlp_backward_enqueue(const float* P, const float* X, const float* H1, const float* H2, const float* Y,
                                 const float* T, const float* M, uint32_t B, float* dY, float* dZ1, float* dZ2, float* loss,
                                 float* G, hipStream_t s);

@@ -336,6 +336,50 @@ __global__ __launch_bounds__(256) void k_adam(float* __restrict__ P, const float
   P[p] -= lr * mh / (sqrtf(vh) + eps);
 }
 
+// Choose a container for one job: normalise its features, run the network,
+// take the lowest output among the feasible containers (bit i of feas).
+// Features outside [lo, hi] (the training range) give -1: the rule decides.
+__global__ __launch_bounds__(64) void k_select(const float* __restrict__ feats, const float* __restrict__ norm,
+                                               const float* __restrict__ P, uint32_t feas, int32_t* __restrict__ choice) {
+  __shared__ float x[kIn], h1[kH], h2[kH], y[kOut];
+  __shared__ int inside;
+  const int j = threadIdx.x;
+  if (j == 0) inside = 1;
+  __syncthreads();
+  if (j < kIn) {
+    const float f = feats[j];
+    if (!(f >= norm[32 + j] && f <= norm[48 + j])) inside = 0;
+    x[j] = (f - norm[j]) / norm[16 + j];
+  }
+  __syncthreads();
+  float z = P[ob1 + j];
+  for (int i = 0; i < kIn; ++i) z = fmaf(P[oW1 + j * kIn + i], x[i], z);
+  h1[j] = fmaxf(z, 0.f);
+  __syncthreads();
+  z = P[ob2 + j];
+  for (int i = 0; i < kH; ++i) z = fmaf(P[oW2 + j * kH + i], h1[i], z);
+  h2[j] = fmaxf(z, 0.f);
+  __syncthreads();
+  if (j < kOut) {
+    float v = P[ob3 + j];
+    for (int i = 0; i < kH; ++i) v = fmaf(P[oW3 + j * kH + i], h2[i], v);
+    y[j] = v;
+  }
+  __syncthreads();
+  if (j == 0) {
+    int best = -1;
+    for (int o = 0; o < kOut; ++o)
+      if (((feas >> o) & 1u) && (best < 0 || y[o] < y[best])) best = o;
+    *choice = inside ? best : -1;
+  }
+}
+
+hipError_t select_enqueue(const float* feats, const float* norm, const float* P, uint32_t feas, int32_t* choice,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(k_select, dim3(1), dim3(64), 0, s, feats, norm, P, feas, choice);
+  return hipGetLastError();
+}
+
 hipError_t mlp_forward_enqueue(const float* P, const float* X, uint32_t B, float* H1, float* H2, float* Y, hipStream_t s) {
   const uint32_t g = B < 4096 ? (B ? B : 1) : 4096;
   hipLaunchKernelGGL(k_mlp_fwd, dim3(g), dim3(64), 0, s, P, X, B, H1, H2, Y);

@@ -53,6 +53,10 @@ def rule_choice(spec) -> int:
     return 2
 
 
+def _nbytes(d) -> int:
+    return int(d.numel()) * int(d.element_size())
+
+
 class Runner:
     """One library job per container (strategy fixed at creation), on torch's current stream."""
 
@@ -69,7 +73,7 @@ class Runner:
         kind = L.MAP_WORDS if spec.kind == "words" else (L.MAP_U32_KV if spec.op == "sum" else L.MAP_U32_KEYS)
         op = L.REDUCE_SUM if spec.op == "sum" else L.REDUCE_COUNT
         R = spec.card if (spec.kind == "u32" and spec.declare_range) else 0
-        L.check(self.lib.mr_job_features(self.rule.h, kind, op, d.data_ptr(), int(d.numel()), R,
+        L.check(self.lib.mr_job_features(self.rule.h, kind, op, d.data_ptr(), _nbytes(d), R,
                                          f.ctypes.data_as(C.c_void_p)), "mr_job_features")
         return f
 
@@ -81,13 +85,13 @@ class Runner:
             kind = L.MAP_U32_KV if spec.op == "sum" else L.MAP_U32_KEYS
             op = L.REDUCE_SUM if spec.op == "sum" else L.REDUCE_COUNT
             R = spec.card if spec.declare_range else 0
-            st = self.lib.mr_run(job.h, kind, op, d.data_ptr(), int(d.numel()), None, 0, R, C.byref(out))
+            st = self.lib.mr_run(job.h, kind, op, d.data_ptr(), _nbytes(d), None, 0, R, C.byref(out))
         return st, out.stats.gpu_ms
 
     def outputs(self, spec, d):
         """Output buffers sized for the job."""
         torch = self.torch
-        n = int(d.numel())
+        n = _nbytes(d)
         o = L.Output()
         if spec.kind == "words":
             cap = min(n // 2 + 1, spec.card + 16)
@@ -308,6 +312,7 @@ def main(argv=None):
     args = ap.parse_args(argv)
     os.makedirs(args.out, exist_ok=True)
     log = lambda *a: print(*a, file=sys.stderr, flush=True)  # noqa: E731
+    pool = gen.job_pool()  # before any GPU use: no process is started after that
     specs = _specs(args.n_jobs, args.size_hi_mib)
     train_idx, test_idx = split(specs, args.n_train)
     feas = np.array([feasible(s) for s in specs])
@@ -317,7 +322,6 @@ def main(argv=None):
     test_dev = {}
     chunk = 64
     t0 = time.time()
-    pool = gen.job_pool()
     test_set = set(test_idx.tolist())
     for c0 in range(0, len(specs), chunk):
         ids = list(range(c0, min(len(specs), c0 + chunk)))

@@ -139,3 +139,23 @@ def test_large_zipf(torch, strat):
     R = 1 << 16 if strat != "lds_array" else 4096
     keys, vals = gen.u32_keys(21, 4_000_000, R, 1.0, with_values=True)
     _check(_run(torch, _job(STRATS[strat]), keys, vals, "sum", R), keys, vals, "sum")
+
+
+def test_mixed_kinds_on_one_job(torch):
+    # One job alternating integer keys, word count, histogram and k-means:
+    # every kind keeps its own buffers valid across the others' runs.
+    from paper_1309_0215_amd import Job
+    j = Job(device=0, strategy=4, km_centroids=torch.from_numpy(gen.kmeans(3, n=64)[1]).cuda())
+    keys, vals = gen.u32_keys(12, 100_000, 5000, 1.0, with_values=True)
+    txt = gen.text(13, 200_000, V=3000)
+    rgb = gen.rgb(14, 3 * 10_000)
+    X, _ = gen.kmeans(3, n=5000)
+    for rep in range(3):
+        _check(_run(torch, j, keys, vals, "sum", 0), keys, vals, "sum")
+        w = j.words(torch.from_numpy(txt).cuda())
+        assert w.items() == oracle.words(txt).items()
+        _check(_run(torch, j, keys, None, "count", 0), keys, None, "count")
+        h, _ = j.rgb_hist(torch.from_numpy(rgb).cuda())
+        assert np.array_equal(h.cpu().numpy().astype(np.uint64), oracle.rgb(rgb))
+        a, s, c, cent, st = j.kmeans(torch.from_numpy(X).cuda())
+        assert int(c.sum()) == len(X)
