@@ -79,6 +79,104 @@ def bench_words(torch, size, steps, warmup, seed=1):
             "hbm_frac": gbs / HBM_PEAK_GBS, "map_kernel_GBps": size / (map_ms * 1e-3) / 1e9}
 
 
+def bench_kmeans(torch, steps, warmup):
+    import gen
+    from paper_1309_0215_amd import Job
+    X, C0 = gen.kmeans(3)  # 16,777,216 x 32 float32, k = 64
+    Xd = torch.from_numpy(X).to("cuda:0")
+    job = Job(device=0, km_centroids=torch.from_numpy(C0).to("cuda:0"), timing=1)
+    ms, outs = time_steps(lambda: job.kmeans(Xd)[4], steps, warmup, torch)
+    map_ms = sum(o["map_ms"] for o in outs) / len(outs)
+    n, d, k = X.shape[0], X.shape[1], C0.shape[0]
+    flops = 2.0 * n * k * d
+    res = {"bytes": X.nbytes, "points": n, "ms_per_step": ms, "map_ms": map_ms, "GBps": X.nbytes / (ms * 1e-3) / 1e9,
+           "hbm_frac": X.nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+           "assign_kernel_TFLOPs": flops / (map_ms * 1e-3) / 1e12,
+           "fp32_frac": flops / (map_ms * 1e-3) / 1e12 / 157.3, "rechecked": outs[-1]["km_rechecked"]}
+    del Xd
+    return res
+
+
+def bench_batched(torch, reps=3):
+    """256 word-count jobs: one graph-replayed mr_batch_run vs 256 separate mr_run calls."""
+    import gen
+    from paper_1309_0215_amd import Job, _lib as L
+    specs = gen.batched_specs()
+    bufs = gen.job_inputs(specs)
+    dev = [torch.from_numpy(b).to("cuda:0") for b in bufs]
+    total = sum(len(b) for b in bufs)
+    plain = Job(device=0)
+    first = [plain.words(d) for d in dev]
+    outs = [plain._word_out(len(r) + 16, int(r.key_bytes.numel()) + 64) for r in first]
+
+    def run_plain():
+        for d, (o, _) in zip(dev, outs):
+            L.check(plain.words_raw(d, o), "words")
+
+    batch = Job(device=0)
+    prep = batch.batch_prepare(dev, cap_keys=[len(r) + 16 for r in first],
+                               cap_bytes=[int(r.key_bytes.numel()) + 64 for r in first])
+    res_b = batch.words_batch(dev, prepared=prep)
+    same = all(torch.equal(a.key_bytes, b.key_bytes) and torch.equal(a.values, b.values)
+               for a, b in zip(first, res_b))
+    ms_p, _ = time_steps(run_plain, reps, 1, torch)
+    ms_b, _ = time_steps(lambda: batch.words_batch(dev, prepared=prep), reps, 1, torch)
+    return {"jobs": len(dev), "bytes": total, "plain_ms": ms_p, "batched_ms": ms_b,
+            "plain_jobs_per_s": len(dev) / (ms_p * 1e-3), "batched_jobs_per_s": len(dev) / (ms_b * 1e-3),
+            "batched_GBps": total / (ms_b * 1e-3) / 1e9, "speedup": ms_p / ms_b, "outputs_identical": bool(same)}
+
+
+def bench_selector(torch, n_jobs=200):
+    """Held-out selector jobs: plain per-job rule vs learned vs batched word jobs + learned."""
+    import gen
+    from paper_1309_0215_amd import Job, _lib as L, selector as S
+    specs_all = S._specs(2000, 16)
+    _, test = S.split(specs_all, 1500)
+    specs = [specs_all[i] for i in test[:n_jobs]]
+    bufs = gen.job_inputs(specs)
+    dev = []
+    for s, b in zip(specs, bufs):
+        d = torch.from_numpy(b).to("cuda:0")
+        dev.append(d.view(torch.int32) if s.kind == "u32" else d)
+    runner = S.Runner(torch)
+    model = S.load_model(runner.learned)
+    outs = [runner.outputs(s, d) for s, d in zip(specs, dev)]
+    words = [i for i, s in enumerate(specs) if s.kind == "words"]
+    ints = [i for i, s in enumerate(specs) if s.kind == "u32"]
+
+    def plain():
+        for s, d, (o, _) in zip(specs, dev, outs):
+            L.check(runner.run(runner.rule, s, d, o)[0], "rule")
+
+    def learned():
+        for s, d, (o, _) in zip(specs, dev, outs):
+            L.check(runner.run(runner.learned if s.kind == "u32" else runner.rule, s, d, o)[0], "learned")
+
+    bjob = Job(device=0)
+    prep = bjob.batch_prepare([dev[i] for i in words])
+
+    def batched_learned():
+        bjob.words_batch([dev[i] for i in words], prepared=prep)
+        for i in ints:
+            L.check(runner.run(runner.learned, specs[i], dev[i], outs[i][0])[0], "learned")
+
+    ms_plain, _ = time_steps(plain, 2, 1, torch)
+    ms_learn, _ = time_steps(learned, 2, 1, torch)
+    ms_bl, _ = time_steps(batched_learned, 2, 1, torch)
+    rep = model.get("meta", {}).get("report", {})
+    return {"jobs": len(specs), "word_jobs": len(words), "int_jobs": len(ints),
+            "bytes": int(sum(len(b) for b in bufs)),
+            "plain_rule_jobs_per_s": len(specs) / (ms_plain * 1e-3),
+            "learned_jobs_per_s": len(specs) / (ms_learn * 1e-3),
+            "batched_learned_jobs_per_s": len(specs) / (ms_bl * 1e-3),
+            "speedup_batched_learned_vs_plain": ms_plain / ms_bl,
+            "heldout_regret_learned_mean": rep.get("regret_learned_mean"),
+            "heldout_regret_rule_mean": rep.get("regret_rule_mean"),
+            "heldout_regret_learned_p95": rep.get("regret_learned_p95"),
+            "heldout_regret_rule_p95": rep.get("regret_rule_p95"),
+            "trained_on": "1,500 of 2,000 seeded jobs, sizes 1-16 MiB (measured by the runtime on this GPU model)"}
+
+
 def cpu_baseline_rgb(buf):
     import oracle
     oracle.rgb(buf[:3 * 1024])  # load
@@ -99,7 +197,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--apps", default="rgb,words8,words512")
+    ap.add_argument("--apps", default="rgb,words8,words512,kmeans,batched,selector")
     ap.add_argument("--no-cpu", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -121,6 +219,20 @@ def main():
         w = bench_words(torch, 512 << 20, max(3, args.steps // 4), 2)
         per_app["word_count_512MiB"] = w
         log(f"words 512 MiB: {w['GBps']:.1f} GB/s, map {w['map_kernel_GBps']:.1f} GB/s")
+
+    if "kmeans" in apps:
+        km = bench_kmeans(torch, max(3, args.steps // 2), 2)
+        per_app["kmeans_step_16M_d32_k64"] = km
+        log(f"kmeans: {km['GBps']:.1f} GB/s, assign {km['assign_kernel_TFLOPs']:.1f} TFLOP/s")
+    if "batched" in apps:
+        bt = bench_batched(torch)
+        per_app["batched_word_count_256_jobs"] = bt
+        log(f"batched: {bt['batched_jobs_per_s']:.0f} jobs/s vs plain {bt['plain_jobs_per_s']:.0f} jobs/s")
+    if "selector" in apps:
+        sl = bench_selector(torch)
+        per_app["selector_heldout_jobs"] = sl
+        log(f"selector: batched+learned {sl['batched_learned_jobs_per_s']:.0f} jobs/s vs plain rule "
+            f"{sl['plain_rule_jobs_per_s']:.0f} jobs/s")
 
     cpu = None
     if not args.no_cpu:

@@ -80,7 +80,6 @@ __global__ __launch_bounds__(kFeatThreads) void k_features(const uint8_t* __rest
   __shared__ float red[2 * kFeatThreads / kWave];
   __shared__ unsigned long long s_n, s_len, s_len2;
   __shared__ uint32_t top[64];
-  __shared__ uint32_t s_best, s_bidx;
   for (uint32_t i = threadIdx.x; i < kHllM; i += blockDim.x) hll_all[i] = hll_half[i] = 0;
   for (uint32_t i = threadIdx.x; i < kFeatSlots; i += blockDim.x) {
     tk[i] = 0xFFFFFFFFu;
@@ -138,26 +137,75 @@ __global__ __launch_bounds__(kFeatThreads) void k_features(const uint8_t* __rest
   __syncthreads();
   const float D_all = hll_estimate(hll_all, red);
   const float D_half = hll_estimate(hll_half, red);
-  // the 64 largest counts (repeated block argmax; the table is small)
-  for (int r = 0; r < 64; ++r) {
-    if (threadIdx.x == 0) {
-      s_best = 0;
-      s_bidx = 0xFFFFFFFFu;
+  // The 64 largest counts, exactly: radix-select the 64th largest value v64
+  // with two histogram passes over the count bits (counts stay below 2^17:
+  // the sample holds at most 64 Ki elements), then collect the counts above
+  // v64, sort them, and pad with v64 (ties) or zeros (fewer than 64 keys).
+  {
+    __shared__ uint32_t hist[512];
+    __shared__ uint32_t s_b1, s_above, s_v64, s_ngt;
+    __shared__ uint32_t gt[64];
+    for (uint32_t i = threadIdx.x; i < 512; i += blockDim.x) hist[i] = 0;
+    if (threadIdx.x == 0) s_ngt = 0;
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < kFeatSlots; i += blockDim.x) {
+      const uint32_t c = tc[i];
+      if (c) atomicAdd(&hist[min(c >> 9, 255u)], 1u);
     }
     __syncthreads();
-    uint32_t b = 0, bi = 0xFFFFFFFFu;
-    for (uint32_t i = threadIdx.x; i < kFeatSlots; i += blockDim.x)
-      if (tc[i] > b) {
-        b = tc[i];
-        bi = i;
+    if (threadIdx.x == 0) {
+      uint32_t acc = 0;
+      int b = 255;
+      for (; b >= 0; --b) {
+        if (acc + hist[b] >= 64) break;
+        acc += hist[b];
       }
-    if (b) atomicMax(&s_best, b);
+      s_b1 = b >= 0 ? (uint32_t)b : 0xFFFFFFFFu;  // none: fewer than 64 nonzero counts
+      s_above = acc;
+    }
     __syncthreads();
-    if (b && b == s_best) atomicMin(&s_bidx, bi);
+    const uint32_t b1 = s_b1;
+    if (b1 != 0xFFFFFFFFu) {
+      for (uint32_t i = threadIdx.x; i < 512; i += blockDim.x) hist[i] = 0;
+      __syncthreads();
+      for (uint32_t i = threadIdx.x; i < kFeatSlots; i += blockDim.x) {
+        const uint32_t c = tc[i];
+        if (c && min(c >> 9, 255u) == b1) atomicAdd(&hist[c & 511u], 1u);
+      }
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        uint32_t acc = s_above, lo = 511;
+        for (;; --lo) {
+          if (acc + hist[lo] >= 64 || lo == 0) break;
+          acc += hist[lo];
+        }
+        s_v64 = (b1 << 9) | lo;
+      }
+    } else if (threadIdx.x == 0) {
+      s_v64 = 0;
+    }
+    __syncthreads();
+    const uint32_t v64 = s_v64;
+    for (uint32_t i = threadIdx.x; i < kFeatSlots; i += blockDim.x) {
+      const uint32_t c = tc[i];
+      if (c > v64) {
+        const uint32_t q = atomicAdd(&s_ngt, 1u);
+        if (q < 64) gt[q] = c;
+      }
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
-      top[r] = s_best;
-      if (s_bidx != 0xFFFFFFFFu) tc[s_bidx] = 0;
+      const uint32_t n = min(s_ngt, 64u);
+      for (uint32_t a = 1; a < n; ++a) {  // insertion sort, descending
+        const uint32_t x = gt[a];
+        uint32_t b = a;
+        while (b > 0 && gt[b - 1] < x) {
+          gt[b] = gt[b - 1];
+          --b;
+        }
+        gt[b] = x;
+      }
+      for (uint32_t r = 0; r < 64; ++r) top[r] = r < n ? gt[r] : v64;
     }
     __syncthreads();
   }
