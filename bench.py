@@ -177,6 +177,16 @@ def bench_selector(torch, n_jobs=200):
             "trained_on": "1,500 of 2,000 seeded jobs, sizes 1-16 MiB (measured by the runtime on this GPU model)"}
 
 
+def bench_copy(torch, steps=5):
+    """A plain 1 GiB device-to-device copy: the reference whose HBM counters scale the kernels' counters."""
+    n = 1 << 30
+    x = torch.empty(n, dtype=torch.uint8, device="cuda:0").fill_(1)
+    y = torch.empty_like(x)
+    ms, _ = time_steps(lambda: y.copy_(x), steps, 1, torch)
+    del x, y
+    return {"bytes_read": n, "bytes_written": n, "ms_per_copy": ms, "GBps_read_plus_write": 2 * n / (ms * 1e-3) / 1e9}
+
+
 def cpu_baseline_rgb(buf):
     import oracle
     oracle.rgb(buf[:3 * 1024])  # load
@@ -185,7 +195,7 @@ def cpu_baseline_rgb(buf):
     while True:
         oracle.rgb(buf)
         reps += 1
-        if time.perf_counter() - t0 > 5.0 or reps >= 8:
+        if time.perf_counter() - t0 > 12.0 or reps >= 16:
             break
     dt = (time.perf_counter() - t0) / reps
     return {"value": len(buf) / dt / 1e9, "unit": "GB/s", "cores": 1, "kind": "oracle",
@@ -233,6 +243,11 @@ def main():
         per_app["selector_heldout_jobs"] = sl
         log(f"selector: batched+learned {sl['batched_learned_jobs_per_s']:.0f} jobs/s vs plain rule "
             f"{sl['plain_rule_jobs_per_s']:.0f} jobs/s")
+
+    if "copy" in apps:
+        cp = bench_copy(torch)
+        per_app["copy_1GiB"] = cp
+        log(f"copy: {cp['GBps_read_plus_write']:.1f} GB/s read+write")
 
     cpu = None
     if not args.no_cpu:

@@ -16,11 +16,23 @@ namespace mr {
 typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
 
 constexpr int kHistThreads = 512;
-constexpr int kHistReplicas = 4;
+constexpr int kHistReplicas = 8;
 constexpr int kHistBins = 768;
+// Replica stride in words: 776 = 768 + 8 puts bin b of neighbouring replicas
+// in different LDS banks (with 768 every replica's bin b shares one bank).
+constexpr int kHistStride = 776;
+// channel phase advance (bytes mod 3) for a step of T and 2T vectors of 16 bytes
+constexpr uint32_t kPhaseT = (16u * kHistThreads) % 3u;
+constexpr uint32_t kPhase2T = (32u * kHistThreads) % 3u;
 
-MR_DEV void count16(uint32_t* __restrict__ h, uint32_t b0, uint32_t b1, uint32_t b2, u32x4_t v) {
-  // byte q of the 16 has channel (phase + q) mod 3; b0, b1, b2 are the bin bases of q mod 3 = 0, 1, 2
+MR_DEV uint32_t add_mod3(uint32_t a, uint32_t b) {
+  const uint32_t s = a + b;
+  return s >= 3u ? s - 3u : s;
+}
+
+MR_DEV void count16(uint32_t* __restrict__ h, uint32_t ph, u32x4_t v) {
+  // byte q of the 16 has channel (ph + q) mod 3
+  const uint32_t b0 = ph * 256u, b1 = add_mod3(ph, 1u) * 256u, b2 = add_mod3(ph, 2u) * 256u;
   const uint32_t w[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
   for (int q = 0; q < 16; ++q) {
@@ -33,11 +45,11 @@ MR_DEV void count16(uint32_t* __restrict__ h, uint32_t b0, uint32_t b1, uint32_t
 // Each workgroup counts bytes [lo, hi) of the input (offsets relative to in).
 __global__ __launch_bounds__(kHistThreads) void k_rgb_partial(const uint8_t* __restrict__ in, uint64_t n,
                                                               uint32_t* __restrict__ partials, uint32_t G) {
-  __shared__ uint32_t h[kHistReplicas * kHistBins];
-  for (int i = threadIdx.x; i < kHistReplicas * kHistBins; i += blockDim.x) h[i] = 0u;
+  __shared__ uint32_t h[kHistReplicas * kHistStride];
+  for (int i = threadIdx.x; i < kHistReplicas * kHistStride; i += kHistThreads) h[i] = 0u;
   __syncthreads();
   const uint64_t lo = n * blockIdx.x / G, hi = n * (blockIdx.x + 1) / G;
-  uint32_t* hr = h + (threadIdx.x % kHistReplicas) * kHistBins;
+  uint32_t* hr = h + (threadIdx.x % kHistReplicas) * kHistStride;
   // aligned body [a_lo, a_hi) in absolute addresses
   const uint64_t base = (uint64_t)in;
   const uint64_t a_lo = (base + lo + 15) & ~15ull;
@@ -45,39 +57,30 @@ __global__ __launch_bounds__(kHistThreads) void k_rgb_partial(const uint8_t* __r
   if (a_lo < a_hi) {
     const u32x4_t* p = reinterpret_cast<const u32x4_t*>(a_lo);
     const uint64_t nv = (a_hi - a_lo) / 16;
-    const uint64_t o0 = a_lo - base;  // byte offset of vector 0
     uint64_t i = threadIdx.x;
+    uint32_t ph = (uint32_t)((a_lo - base + 16 * i) % 3);  // channel of the first byte of vector i
     // two loads in flight per lane
-    for (; i + blockDim.x < nv; i += 2 * (uint64_t)blockDim.x) {
+    for (; i + kHistThreads < nv; i += 2 * kHistThreads) {
       const u32x4_t v0 = __builtin_nontemporal_load(p + i);
-      const u32x4_t v1 = __builtin_nontemporal_load(p + i + blockDim.x);
-      {
-        const uint32_t ph = (uint32_t)((o0 + 16 * i) % 3);
-        count16(hr, ph * 256u, ((ph + 1) % 3) * 256u, ((ph + 2) % 3) * 256u, v0);
-      }
-      {
-        const uint32_t ph = (uint32_t)((o0 + 16 * (i + blockDim.x)) % 3);
-        count16(hr, ph * 256u, ((ph + 1) % 3) * 256u, ((ph + 2) % 3) * 256u, v1);
-      }
+      const u32x4_t v1 = __builtin_nontemporal_load(p + i + kHistThreads);
+      count16(hr, ph, v0);
+      count16(hr, add_mod3(ph, kPhaseT), v1);
+      ph = add_mod3(ph, kPhase2T);
     }
-    for (; i < nv; i += blockDim.x) {
-      const u32x4_t v0 = __builtin_nontemporal_load(p + i);
-      const uint32_t ph = (uint32_t)((o0 + 16 * i) % 3);
-      count16(hr, ph * 256u, ((ph + 1) % 3) * 256u, ((ph + 2) % 3) * 256u, v0);
-    }
+    if (i < nv) count16(hr, ph, __builtin_nontemporal_load(p + i));
   }
   // head and tail bytes outside the aligned body
   {
     const uint64_t head_end = a_lo < a_hi ? a_lo - base : hi;
-    for (uint64_t o = lo + threadIdx.x; o < head_end; o += blockDim.x) atomicAdd(&hr[(o % 3) * 256 + in[o]], 1u);
+    for (uint64_t o = lo + threadIdx.x; o < head_end; o += kHistThreads) atomicAdd(&hr[(o % 3) * 256 + in[o]], 1u);
     if (a_lo < a_hi)
-      for (uint64_t o = (a_hi - base) + threadIdx.x; o < hi; o += blockDim.x) atomicAdd(&hr[(o % 3) * 256 + in[o]], 1u);
+      for (uint64_t o = (a_hi - base) + threadIdx.x; o < hi; o += kHistThreads) atomicAdd(&hr[(o % 3) * 256 + in[o]], 1u);
   }
   __syncthreads();
-  for (int b = threadIdx.x; b < kHistBins; b += blockDim.x) {
+  for (int b = threadIdx.x; b < kHistBins; b += kHistThreads) {
     uint32_t s = 0;
 #pragma unroll
-    for (int r = 0; r < kHistReplicas; ++r) s += h[r * kHistBins + b];
+    for (int r = 0; r < kHistReplicas; ++r) s += h[r * kHistStride + b];
     partials[(uint64_t)b * G + blockIdx.x] = s;
   }
 }
@@ -100,8 +103,9 @@ __global__ __launch_bounds__(256) void k_rgb_reduce(const uint32_t* __restrict__
 }
 
 uint32_t rgb_grid(uint64_t n, int n_cu) {
-  // enough workgroups to fill the chip; each must count fewer than 2^32 bytes
-  uint64_t g = (uint64_t)n_cu * 4;
+  // 16 workgroups per CU (measured best for 512 threads and 8 replicas);
+  // each must count fewer than 2^32 bytes
+  uint64_t g = (uint64_t)n_cu * 16;
   while (n / g >= (1ull << 31)) g *= 2;
   if (g > n / 64 + 1) g = n / 64 + 1;
   return (uint32_t)(g ? g : 1);

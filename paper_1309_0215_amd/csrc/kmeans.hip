@@ -22,7 +22,7 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kKmThreads = 256;  // 4 waves
-constexpr int kKmFlush = 4;      // wave iterations between float32 -> float64 flushes
+constexpr int kKmFlush = 8;      // wave iterations between float32 -> float64 flushes
 
 // Squared norms of the centroids (rounded to float32) and max |c| (float64).
 __global__ __launch_bounds__(256) void k_km_prep(const float* __restrict__ C, uint32_t k, uint32_t d, float* __restrict__ cn,
@@ -50,6 +50,7 @@ __global__ __launch_bounds__(256) void k_km_prep(const float* __restrict__ C, ui
 // float64 direct-form squared distance (the definition of the step).
 MR_DEV double dist64(const float* __restrict__ x, const float* __restrict__ c, uint32_t d) {
   double s = 0.0;
+#pragma unroll 1
   for (uint32_t t = 0; t < d; ++t) {
     const double q = (double)x[t] - (double)c[t];
     s += q * q;
@@ -58,17 +59,39 @@ MR_DEV double dist64(const float* __restrict__ x, const float* __restrict__ c, u
 }
 
 // Assignment + local sums for d = 32, k = 64.
-__global__ __launch_bounds__(kKmThreads) void k_km_mfma(const float* __restrict__ X, uint64_t N, const float* __restrict__ C,
+constexpr int kSumStride = 33;  // padded row of the LDS sums: lanes of one cluster row hit distinct banks
+
+MR_DEV void load_group(const float* __restrict__ X, uint64_t N, uint64_t g, uint64_t groups, uint32_t col, uint32_t h,
+                       float (&xs)[16]) {
+  const uint64_t p = g * 32 + col;
+  if (g < groups && p < N) {
+    typedef float f32x4l __attribute__((ext_vector_type(4)));
+    const f32x4l* src = reinterpret_cast<const f32x4l*>(X + p * 32 + 16 * h);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const f32x4l v = __builtin_nontemporal_load(src + q);
+      xs[4 * q + 0] = v.x;
+      xs[4 * q + 1] = v.y;
+      xs[4 * q + 2] = v.z;
+      xs[4 * q + 3] = v.w;
+    }
+  } else {
+#pragma unroll
+    for (int s = 0; s < 16; ++s) xs[s] = 0.f;
+  }
+}
+
+__global__ __launch_bounds__(kKmThreads) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_km_mfma(const float* __restrict__ X, uint64_t N, const float* __restrict__ C,
                                                         const float* __restrict__ cn_g, const double* __restrict__ cmax_g,
                                                         int32_t* __restrict__ assign, double* __restrict__ part_sum,
                                                         uint32_t* __restrict__ part_cnt, unsigned long long* __restrict__ n_recheck) {
   constexpr int D = 32, K = 64;
-  __shared__ float s32[K * D];
+  __shared__ float s32[K * kSumStride];
   __shared__ double s64[K * D];
   __shared__ uint32_t scnt[K];
   __shared__ float sC[K * D];
+  for (int i = threadIdx.x; i < K * kSumStride; i += blockDim.x) s32[i] = 0.f;
   for (int i = threadIdx.x; i < K * D; i += blockDim.x) {
-    s32[i] = 0.f;
     s64[i] = 0.0;
     sC[i] = C[i];
   }
@@ -78,18 +101,14 @@ __global__ __launch_bounds__(kKmThreads) void k_km_mfma(const float* __restrict_
   const uint32_t lane = lane_id();
   const uint32_t h = lane >> 5;     // which half of the dims (0: 0..15, 1: 16..31)
   const uint32_t col = lane & 31u;  // point within the 32-point group / centroid row within a block
-  // A operand: centroid values C[blk*32 + col][16h + s]
-  float ca[2][16];
-#pragma unroll
-  for (int b = 0; b < 2; ++b)
-#pragma unroll
-    for (int s = 0; s < 16; ++s) ca[b][s] = sC[(b * 32 + col) * D + 16 * h + s];
-  // this lane's 32 centroid rows: block b, register r -> row 8*(r/4) + 4*h + r%4
-  float cnr[2][16];
-#pragma unroll
-  for (int b = 0; b < 2; ++b)
-#pragma unroll
-    for (int r = 0; r < 16; ++r) cnr[b][r] = cn_g[b * 32 + 8 * (r / 4) + 4 * h + (r % 4)];
+  // A operands (centroid values C[blk*32 + col][16h + s]) and the centroid
+  // norms are read from LDS each iteration instead of held in registers,
+  // which keeps the kernel at several waves per SIMD.
+  __shared__ float sCn[K];
+  if (threadIdx.x < K) sCn[threadIdx.x] = cn_g[threadIdx.x];
+  __syncthreads();
+  const f32x4* ca0 = reinterpret_cast<const f32x4*>(sC + col * D + 16 * h);
+  const f32x4* ca1 = reinterpret_cast<const f32x4*>(sC + (32 + col) * D + 16 * h);
   const float cmax = (float)*cmax_g;
   const float u = 5.9604645e-08f;                     // 2^-24
   const float gam = (float)D * u / (1.f - (float)D * u);
@@ -102,32 +121,26 @@ __global__ __launch_bounds__(kKmThreads) void k_km_mfma(const float* __restrict_
   const uint64_t iters = (groups + waves_total - 1) / waves_total;  // uniform across the grid
   unsigned long long rechecks = 0;
 
+  float xs[16], xn[16];
+  load_group(X, N, wave_g, groups, col, h, xs);
   for (uint64_t it = 0; it < iters; ++it) {
     const uint64_t g = it * waves_total + wave_g;
     const uint64_t p = g * 32 + col;
     const bool valid = g < groups && p < N;
-    f32x4 xv[4];
-    if (valid) {
-      const f32x4* src = reinterpret_cast<const f32x4*>(X + p * D + 16 * h);
-#pragma unroll
-      for (int q = 0; q < 4; ++q) xv[q] = __builtin_nontemporal_load(src + q);
-    } else {
-#pragma unroll
-      for (int q = 0; q < 4; ++q) xv[q] = f32x4{0.f, 0.f, 0.f, 0.f};
-    }
-    float xs[16];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      xs[4 * q + 0] = xv[q].x;
-      xs[4 * q + 1] = xv[q].y;
-      xs[4 * q + 2] = xv[q].z;
-      xs[4 * q + 3] = xv[q].w;
-    }
+    // the next group's loads are in flight while this group is computed
+    load_group(X, N, g + waves_total, groups, col, h, xn);
     f32x16 acc0 = {}, acc1 = {};
 #pragma unroll
-    for (int s = 0; s < 16; ++s) {
-      acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(ca[0][s], xs[s], acc0, 0, 0, 0);
-      acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(ca[1][s], xs[s], acc1, 0, 0, 0);
+    for (int q = 0; q < 4; ++q) {
+      const f32x4 a0 = ca0[q], a1 = ca1[q];
+      acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0.x, xs[4 * q + 0], acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a1.x, xs[4 * q + 0], acc1, 0, 0, 0);
+      acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0.y, xs[4 * q + 1], acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a1.y, xs[4 * q + 1], acc1, 0, 0, 0);
+      acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0.z, xs[4 * q + 2], acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a1.z, xs[4 * q + 2], acc1, 0, 0, 0);
+      acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0.w, xs[4 * q + 3], acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a1.w, xs[4 * q + 3], acc1, 0, 0, 0);
     }
     // |x| for the bound
     float nx = 0.f;
@@ -135,68 +148,113 @@ __global__ __launch_bounds__(kKmThreads) void k_km_mfma(const float* __restrict_
     for (int s = 0; s < 16; ++s) nx = fmaf(xs[s], xs[s], nx);
     nx += __shfl_xor(nx, 32);
     nx = sqrtf(nx);
-    // best and second best over this lane's 32 rows, lowest index on ties
+    // scores of this lane's 32 rows, then best and second best; rows are
+    // visited in increasing index order, so a strict < keeps the lowest index
+    float sc[32];
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 16; ++r)
+        sc[b * 16 + r] = sCn[b * 32 + 8 * (r / 4) + 4 * (int)h + (r % 4)] - 2.f * (b ? acc1[r] : acc0[r]);
     float b1 = INFINITY, b2 = INFINITY;
-    int i1 = 0x7fffffff;
+    int i1 = 0;
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
-        const float dot = b ? acc1[r] : acc0[r];
-        const float sc = cnr[b][r] - 2.f * dot;
         const int idx = b * 32 + 8 * (r / 4) + 4 * (int)h + (r % 4);
-        if (sc < b1 || (sc == b1 && idx < i1)) {
-          b2 = b1;
-          b1 = sc;
-          i1 = idx;
-        } else if (sc < b2) {
-          b2 = sc;
-        }
+        const float v = sc[b * 16 + r];
+        const bool better = v < b1;
+        b2 = better ? b1 : fminf(b2, v);
+        i1 = better ? idx : i1;
+        b1 = better ? v : b1;
       }
     }
     // combine with the partner lane (other 32 rows of the same point)
     const float o1 = __shfl_xor(b1, 32), o2 = __shfl_xor(b2, 32);
     const int oi = __shfl_xor(i1, 32);
-    float best = b1, second;
-    int bi = i1;
-    if (o1 < b1 || (o1 == b1 && oi < i1)) {
-      best = o1;
-      bi = oi;
-      second = fminf(b1, o2);
-    } else {
-      second = fminf(b2, o1);
-    }
-    // near tie: decide in float64 (one lane per point)
+    const bool other = o1 < b1 || (o1 == b1 && oi < i1);
+    const float best = other ? o1 : b1;
+    const float second = other ? fminf(b1, o2) : fminf(b2, o1);
+    int bi = other ? oi : i1;
+    // Near tie: every float32 score is within eps/2 of its exact value, so the
+    // exact argmin is among the rows scoring <= best + eps. Those candidates
+    // (usually two) are decided again in float64 from the direct form; both
+    // lanes of the pair take part, each for its own rows.
     const float eps = e_c + e_x * nx;
-    if (valid && h == 0 && !(second - best > eps)) {
-      ++rechecks;
-      const float* xp = X + p * D;
+    const bool need = valid && !(second - best > eps);
+    if (__any(need)) {
+      uint32_t cand = 0;
+      if (need) {
+        const float thr = best + eps;
+#pragma unroll
+        for (int t = 0; t < 32; ++t) cand |= (sc[t] <= thr ? 1u : 0u) << t;
+      }
+      // the partner's half of the point: this lane then holds all 32 dims
+      float xo[16];
+#pragma unroll
+      for (int s = 0; s < 16; ++s) xo[s] = __shfl_xor(xs[s], 32);
       double bd = INFINITY;
-      int bj = 0;
-      for (int j = 0; j < K; ++j) {
-        const double dj = dist64(xp, sC + j * D, D);
+      int bj = 0x7fffffff;
+#pragma unroll 1
+      while (cand) {  // rows in increasing index order: strict < keeps the lowest index
+        const int bit = __builtin_ctz(cand);
+        cand &= cand - 1u;
+        const int rr = bit & 15;
+        const int idx = (bit >> 4) * 32 + 8 * (rr / 4) + 4 * (int)h + (rr % 4);
+        // own half first, then the partner's (dims 16h.., then 16(1-h)..)
+        const f32x4* c4 = reinterpret_cast<const f32x4*>(sC + idx * D + 16 * h);
+        const f32x4* c4o = reinterpret_cast<const f32x4*>(sC + idx * D + 16 * (1 - h));
+        double dj = 0.0;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const f32x4 c = q < 4 ? c4[q] : c4o[q - 4];
+          const float* xv = q < 4 ? xs + 4 * q : xo + 4 * (q - 4);
+          float x0 = xv[0], x1 = xv[1], x2 = xv[2], x3 = xv[3];
+          // keeps the float64 conversions of x inside this rare loop (hoisted
+          // they would hold 64 more registers for the whole kernel)
+          asm volatile("" : "+v"(x0), "+v"(x1), "+v"(x2), "+v"(x3));
+          double e;
+          e = (double)x0 - (double)c.x; dj = fma(e, e, dj);
+          e = (double)x1 - (double)c.y; dj = fma(e, e, dj);
+          e = (double)x2 - (double)c.z; dj = fma(e, e, dj);
+          e = (double)x3 - (double)c.w; dj = fma(e, e, dj);
+          __builtin_amdgcn_sched_barrier(0);  // one centroid quad in flight at a time
+        }
         if (dj < bd) {
           bd = dj;
-          bj = j;
+          bj = idx;
         }
       }
-      bi = bj;
+      const double obd = __shfl_xor(bd, 32);
+      const int obj = __shfl_xor(bj, 32);
+      if (obd < bd || (obd == bd && obj < bj)) {
+        bd = obd;
+        bj = obj;
+      }
+      if (need) {
+        bi = bj;
+        if (h == 0) ++rechecks;
+      }
     }
     bi = __shfl(bi, (int)col);  // lane col (h = 0) decided for both halves
     if (valid) {
       if (h == 0) assign[p] = bi;
 #pragma unroll
-      for (int s = 0; s < 16; ++s) atomicAdd(&s32[bi * D + 16 * h + s], xs[s]);
+      for (int s = 0; s < 16; ++s) atomicAdd(&s32[bi * kSumStride + 16 * h + s], xs[s]);
       if (h == 0) atomicAdd(&scnt[bi], 1u);
     }
     if ((it + 1) % kKmFlush == 0 || it + 1 == iters) {
       __syncthreads();
       for (int i = threadIdx.x; i < K * D; i += blockDim.x) {
-        s64[i] += (double)s32[i];
-        s32[i] = 0.f;
+        const int c = i / D, t = i % D;
+        s64[i] += (double)s32[c * kSumStride + t];
+        s32[c * kSumStride + t] = 0.f;
       }
       __syncthreads();
     }
+#pragma unroll
+    for (int s = 0; s < 16; ++s) xs[s] = xn[s];
   }
   if (rechecks) atomicAdd(n_recheck, rechecks);
   for (int i = threadIdx.x; i < K * D; i += blockDim.x) part_sum[(uint64_t)blockIdx.x * K * D + i] = s64[i];
