@@ -5,9 +5,10 @@
 // while they are small). Each workgroup streams a contiguous range of the
 // input with 16-byte non-temporal loads and bumps LDS counters; lanes spread
 // over R replicas of the array to cut same-address conflicts. At the end each
-// workgroup writes its partial array (no atomics), and a second kernel adds
-// the partials bin by bin in 64-bit. Merging partials with global atomics
-// instead would put every workgroup on the same 768 addresses.
+// workgroup writes its partial array as one row (no atomics); a second kernel
+// adds groups of rows in 64-bit and merges the group sums with a few atomics.
+// Merging every workgroup's array with global atomics instead would put all
+// of them on the same 768 addresses.
 #include "common.h"
 #include "launch.h"
 
@@ -77,29 +78,38 @@ __global__ __launch_bounds__(kHistThreads) void k_rgb_partial(const uint8_t* __r
       for (uint64_t o = (a_hi - base) + threadIdx.x; o < hi; o += kHistThreads) atomicAdd(&hr[(o % 3) * 256 + in[o]], 1u);
   }
   __syncthreads();
+  // one contiguous row of 768 counts per workgroup (whole cache lines)
   for (int b = threadIdx.x; b < kHistBins; b += kHistThreads) {
     uint32_t s = 0;
 #pragma unroll
     for (int r = 0; r < kHistReplicas; ++r) s += h[r * kHistStride + b];
-    partials[(uint64_t)b * G + blockIdx.x] = s;
+    partials[(uint64_t)blockIdx.x * kHistBins + b] = s;
   }
 }
 
-__global__ __launch_bounds__(256) void k_rgb_reduce(const uint32_t* __restrict__ partials, uint32_t G,
-                                                    unsigned long long* __restrict__ out) {
-  __shared__ unsigned long long ws[256 / kWave];
-  const uint32_t b = blockIdx.x;
+// Bins are zero before the partial rows are added in.
+__global__ __launch_bounds__(kHistBins) void k_rgb_zero(unsigned long long* __restrict__ out) {
+  out[threadIdx.x] = 0ull;
+}
+
+// Workgroup q adds rows [q G / Q, (q + 1) G / Q) of the partials (thread =
+// bin, so every row is read as one contiguous block) and adds its sums into
+// the output: Q atomics per bin.
+constexpr uint32_t kHistReduceGroups = 64;
+
+__global__ __launch_bounds__(kHistBins) void k_rgb_reduce(const uint32_t* __restrict__ partials, uint32_t G,
+                                                          unsigned long long* __restrict__ out) {
+  const uint32_t b = threadIdx.x;
+  const uint64_t g0 = (uint64_t)G * blockIdx.x / gridDim.x, g1 = (uint64_t)G * (blockIdx.x + 1) / gridDim.x;
   unsigned long long s = 0;
-  for (uint32_t g = threadIdx.x; g < G; g += blockDim.x) s += partials[(uint64_t)b * G + g];
-#pragma unroll
-  for (int o = kWave / 2; o > 0; o >>= 1) s += __shfl_xor(s, o);
-  if (lane_id() == 0) ws[threadIdx.x / kWave] = s;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    unsigned long long t = 0;
-    for (int w = 0; w < 256 / kWave; ++w) t += ws[w];
-    out[b] = t;
+  uint64_t g = g0;
+  for (; g + 4 <= g1; g += 4) {
+    const uint32_t a0 = partials[g * kHistBins + b], a1 = partials[(g + 1) * kHistBins + b];
+    const uint32_t a2 = partials[(g + 2) * kHistBins + b], a3 = partials[(g + 3) * kHistBins + b];
+    s += (unsigned long long)a0 + a1 + a2 + a3;
   }
+  for (; g < g1; ++g) s += partials[g * kHistBins + b];
+  if (s) atomicAdd(&out[b], s);
 }
 
 uint32_t rgb_grid(uint64_t n, int n_cu) {
@@ -116,7 +126,9 @@ hipError_t rgb_enqueue(const uint8_t* in, uint64_t n, uint32_t* partials, uint32
   if (map0) (void)hipEventRecord(map0, s);
   hipLaunchKernelGGL(k_rgb_partial, dim3(G), dim3(kHistThreads), 0, s, in, n, partials, G);
   if (map1) (void)hipEventRecord(map1, s);
-  hipLaunchKernelGGL(k_rgb_reduce, dim3(kHistBins), dim3(256), 0, s, partials, G, out);
+  hipLaunchKernelGGL(k_rgb_zero, dim3(1), dim3(kHistBins), 0, s, out);
+  const uint32_t q = G < kHistReduceGroups ? G : kHistReduceGroups;
+  hipLaunchKernelGGL(k_rgb_reduce, dim3(q), dim3(kHistBins), 0, s, partials, G, out);
   return hipGetLastError();
 }
 

@@ -171,15 +171,23 @@ MR_DEV bool rep_equals_global(const WordJob& J, uint64_t vlo, uint64_t vhi, uint
   return true;
 }
 
+// Longest probe sequence before the table counts as full. At the planned
+// load (half the slots or less) a run of this many occupied slots does not
+// happen with a mixing hash; meeting one means the table is filling up, and
+// probing on would make each insert scan a large part of the table.
+constexpr uint64_t kMaxProbe = 512;
+
 // Insert one key with value v. Inline keys (len <= 16) come with k; longer
 // keys are compared against the input at off. Returns false on a full table.
 template <bool kInline>
 MR_DEV bool g_insert(const WordJob& J, uint64_t vlo, uint64_t vhi, uint64_t off, uint64_t len, uint64_t h, uint4 k,
-                     uint32_t v) {
+                     uint32_t v, uint32_t debug_hash) {
   const uint64_t word = gword(off, len, h);
   const uint64_t mask = J.cap - 1;
+  // (with every key forced onto one hash the whole table is one run)
+  const uint64_t limit = (debug_hash || mask < kMaxProbe) ? mask : kMaxProbe;
   uint64_t i = h & mask;
-  for (uint64_t p = 0; p <= mask; ++p) {
+  for (uint64_t p = 0; p <= limit; ++p) {
     // A relaxed load may be stale only as 0 (slots are written once per run);
     // the CAS below then returns the current word.
     unsigned long long cur = __hip_atomic_load(&J.tw[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -289,7 +297,7 @@ MR_DEV void lds_flush(LdsTable<L>& T, const WordJob& J, uint64_t vlo, uint64_t v
       const uint32_t len = (tg >> 1) & 31u;
       const uint4 k = T.key[i];
       const uint64_t h = key_hash16(k, len, debug_hash);
-      g_insert<true>(J, vlo, vhi, T.off[i], len, h, k, T.cnt[i]);
+      g_insert<true>(J, vlo, vhi, T.off[i], len, h, k, T.cnt[i], debug_hash);
     }
     T.tag[i] = 0u;
   }
@@ -405,7 +413,7 @@ __global__ __launch_bounds__(kMapThreads) void k_words_map(const WordJob* __rest
         // long word: measure and hash it from memory, insert globally
         const uint64_t len = word_length_slow(J, vlo, vhi, off);
         const uint64_t h = key_hash_global(J.in, off, len, debug_hash);
-        g_insert<false>(J, vlo, vhi, off, len, h, make_uint4(0, 0, 0, 0), 1u);
+        g_insert<false>(J, vlo, vhi, off, len, h, make_uint4(0, 0, 0, 0), 1u, debug_hash);
         continue;
       }
       const uint32_t len = e - s;
@@ -420,7 +428,7 @@ __global__ __launch_bounds__(kMapThreads) void k_words_map(const WordJob* __rest
           r = 0;
         }
       }
-      if (r == 2) g_insert<true>(J, vlo, vhi, off, len, h, k, 1u);
+      if (r == 2) g_insert<true>(J, vlo, vhi, off, len, h, k, 1u, debug_hash);
     }
   }
   __syncthreads();

@@ -192,3 +192,19 @@ def test_workspace_reuse_across_sizes_and_kinds(torch):
         if i % 2:
             h, _ = j.rgb_hist(_dev(torch, rgb))
             assert np.array_equal(h.cpu().numpy().astype(np.uint64), oracle.rgb(rgb))
+
+
+def test_repeated_calls_replay_and_follow_content(torch):
+    """The third identical call replays a captured graph; results track the bytes in place."""
+    from paper_1309_0215_amd import Job, WordsResult, _lib as L
+    j = Job(device=0)
+    bufs = [gen.text(40 + i, 300_000, V=3000, s=1.0) for i in range(3)]
+    bufs.append(gen.text(50, 300_000, V=200_000, s=0.3))  # many distinct words: needs a larger table
+    d = _dev(torch, bufs[0])
+    o, keep = j._word_out(200_000, 1 << 21)
+    for i, b in enumerate(bufs + bufs[:2]):
+        d.copy_(_dev(torch, b))
+        L.check(j.words_raw(d, o), "words")
+        kb, ko, vals = keep
+        nk = int(o.n_keys)
+        _check(WordsResult(kb[:o.key_bytes_used], ko[:nk + 1], vals[:nk], {}), b)
