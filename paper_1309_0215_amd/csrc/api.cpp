@@ -266,7 +266,8 @@ struct WordItem {
 // distinct words <= words; start from a sixteenth of the bytes and let a full
 // table trigger regrowth.
 uint64_t initial_slots(const mr_job* job, uint64_t n) {
-  if (job->cfg.table_slots) return job->cfg.table_slots;
+  // (at least 4096 slots: the compaction takes 4096-slot pieces of one table)
+  if (job->cfg.table_slots) return std::max<uint64_t>(4096, job->cfg.table_slots);
   const double lf = (job->cfg.max_load_pct ? job->cfg.max_load_pct : 50) / 100.0;
   const uint64_t words_ub = (n + 1) / 2;
   uint64_t est = std::min<uint64_t>(words_ub, std::max<uint64_t>(2048, n / 64));
@@ -897,7 +898,7 @@ mr_status run_kmeans(mr_job* job, const void* d_input, uint64_t bytes, mr_output
   L.k = k;
   L.d = d;
   L.mfma = d == 32 && k == 64 && (uintptr_t)d_input % 16 == 0;
-  L.G = L.mfma ? (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)job->n_cu * 4, (N + 127) / 128)) : 1u;
+  L.G = L.mfma ? (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)job->n_cu * 3, (N + 127) / 128)) : 1u;
   Carve c;
   const uint64_t o_cn = c.take(4ull * k), o_cmax = c.take(8), o_nr = c.take(8);
   const uint64_t o_ps = c.take(8ull * L.G * k * d), o_pc = c.take(4ull * L.G * k);

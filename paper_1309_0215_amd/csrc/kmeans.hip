@@ -10,8 +10,9 @@
 // second best score is within a rounding bound eps(x), the decision is made
 // again in float64 from the direct form sum_t (x_t - c_t)^2.
 //
-// Update: each workgroup adds its points into float32 LDS sums (a few points
-// per cluster between flushes) and flushes them into float64 LDS sums; the
+// Update: the per-cluster sums are a second contraction on the matrix cores
+// (one-hot assignment x points), accumulated in float32 over at most 16 groups
+// of 32 points per wave and then added into float64 LDS sums; the
 // per-workgroup float64 partials are added in a fixed order at the end.
 #include "common.h"
 #include "launch.h"
@@ -22,7 +23,6 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kKmThreads = 256;  // 4 waves
-constexpr int kKmFlush = 8;      // wave iterations between float32 -> float64 flushes
 
 // Squared norms of the centroids (rounded to float32) and max |c| (float64).
 __global__ __launch_bounds__(256) void k_km_prep(const float* __restrict__ C, uint32_t k, uint32_t d, float* __restrict__ cn,
@@ -59,17 +59,16 @@ MR_DEV double dist64(const float* __restrict__ x, const float* __restrict__ c, u
 }
 
 // Assignment + local sums for d = 32, k = 64.
-constexpr int kSumStride = 33;  // padded row of the LDS sums: lanes of one cluster row hit distinct banks
+constexpr int kKmFlushIters = 16;  // wave iterations between float32 -> float64 flushes of the sums
 
 MR_DEV void load_group(const float* __restrict__ X, uint64_t N, uint64_t g, uint64_t groups, uint32_t col, uint32_t h,
                        float (&xs)[16]) {
   const uint64_t p = g * 32 + col;
   if (g < groups && p < N) {
-    typedef float f32x4l __attribute__((ext_vector_type(4)));
-    const f32x4l* src = reinterpret_cast<const f32x4l*>(X + p * 32 + 16 * h);
+    const f32x4* src = reinterpret_cast<const f32x4*>(X + p * 32 + 16 * h);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const f32x4l v = __builtin_nontemporal_load(src + q);
+      const f32x4 v = __builtin_nontemporal_load(src + q);
       xs[4 * q + 0] = v.x;
       xs[4 * q + 1] = v.y;
       xs[4 * q + 2] = v.z;
@@ -81,32 +80,40 @@ MR_DEV void load_group(const float* __restrict__ X, uint64_t N, uint64_t g, uint
   }
 }
 
-__global__ __launch_bounds__(kKmThreads) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_km_mfma(const float* __restrict__ X, uint64_t N, const float* __restrict__ C,
+// Each wave takes groups of 32 points. Lane (col, h) holds dims 16h..16h+15
+// of point col (B operand of the score contraction) and centroid rows col and
+// 32 + col come from LDS (A operand). After the argmin, the per-cluster sums
+// are a second contraction S[c][d] += sum_p [a_p = c] x[p][d]: the one-hot
+// assignment is the A operand (clusters x points), the points transposed
+// through LDS are the B operand (points x dims), and the float32 sums stay in
+// the accumulators until they are flushed into float64 LDS sums.
+__global__ __launch_bounds__(kKmThreads) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_km_mfma(const float* __restrict__ X, uint64_t N, const float* __restrict__ C,
                                                         const float* __restrict__ cn_g, const double* __restrict__ cmax_g,
                                                         int32_t* __restrict__ assign, double* __restrict__ part_sum,
                                                         uint32_t* __restrict__ part_cnt, unsigned long long* __restrict__ n_recheck) {
-  constexpr int D = 32, K = 64;
-  __shared__ float s32[K * kSumStride];
+  constexpr int D = 32, K = 64, W = kKmThreads / kWave;
   __shared__ double s64[K * D];
   __shared__ uint32_t scnt[K];
   __shared__ float sC[K * D];
-  for (int i = threadIdx.x; i < K * kSumStride; i += blockDim.x) s32[i] = 0.f;
+  __shared__ float sCn[K];
+  // per wave: x transposed, xt[w][d % 16][(d / 16) * 32 + (p % 2) * 16 + p / 2] = x[p][d],
+  // and the assignments, ab[w][(p % 2) * 16 + p / 2] = a_p (-1 for no point)
+  __shared__ float xt[W][16][64];
+  __shared__ int32_t ab[W][32];
   for (int i = threadIdx.x; i < K * D; i += blockDim.x) {
     s64[i] = 0.0;
     sC[i] = C[i];
   }
-  if (threadIdx.x < K) scnt[threadIdx.x] = 0;
+  if (threadIdx.x < K) {
+    scnt[threadIdx.x] = 0;
+    sCn[threadIdx.x] = cn_g[threadIdx.x];
+  }
   __syncthreads();
 
   const uint32_t lane = lane_id();
+  const uint32_t wv = threadIdx.x / kWave;
   const uint32_t h = lane >> 5;     // which half of the dims (0: 0..15, 1: 16..31)
   const uint32_t col = lane & 31u;  // point within the 32-point group / centroid row within a block
-  // A operands (centroid values C[blk*32 + col][16h + s]) and the centroid
-  // norms are read from LDS each iteration instead of held in registers,
-  // which keeps the kernel at several waves per SIMD.
-  __shared__ float sCn[K];
-  if (threadIdx.x < K) sCn[threadIdx.x] = cn_g[threadIdx.x];
-  __syncthreads();
   const f32x4* ca0 = reinterpret_cast<const f32x4*>(sC + col * D + 16 * h);
   const f32x4* ca1 = reinterpret_cast<const f32x4*>(sC + (32 + col) * D + 16 * h);
   const float cmax = (float)*cmax_g;
@@ -115,11 +122,12 @@ __global__ __launch_bounds__(kKmThreads) __attribute__((amdgpu_waves_per_eu(4, 4
   const float e_c = 8.f * u * cmax * cmax;            // centroid-norm rounding, both scores, x2 margin
   const float e_x = 8.f * (gam + u) * cmax;           // times |x|: dot products and the subtraction
 
-  const uint32_t waves_total = gridDim.x * (kKmThreads / kWave);
-  const uint32_t wave_g = blockIdx.x * (kKmThreads / kWave) + threadIdx.x / kWave;
+  const uint32_t waves_total = gridDim.x * W;
+  const uint32_t wave_g = blockIdx.x * W + wv;
   const uint64_t groups = (N + 31) / 32;
   const uint64_t iters = (groups + waves_total - 1) / waves_total;  // uniform across the grid
   unsigned long long rechecks = 0;
+  f32x16 sum0 = {}, sum1 = {};  // cluster rows 0..31 and 32..63 x dims (float32, since the last flush)
 
   float xs[16], xn[16];
   load_group(X, N, wave_g, groups, col, h, xs);
@@ -165,7 +173,7 @@ __global__ __launch_bounds__(kKmThreads) __attribute__((amdgpu_waves_per_eu(4, 4
         const int idx = b * 32 + 8 * (r / 4) + 4 * (int)h + (r % 4);
         const float v = sc[b * 16 + r];
         const bool better = v < b1;
-        b2 = better ? b1 : fminf(b2, v);
+        b2 = better ? b1 : (v < b2 ? v : b2);
         i1 = better ? idx : i1;
         b1 = better ? v : b1;
       }
@@ -175,7 +183,7 @@ __global__ __launch_bounds__(kKmThreads) __attribute__((amdgpu_waves_per_eu(4, 4
     const int oi = __shfl_xor(i1, 32);
     const bool other = o1 < b1 || (o1 == b1 && oi < i1);
     const float best = other ? o1 : b1;
-    const float second = other ? fminf(b1, o2) : fminf(b2, o1);
+    const float second = other ? (b1 < o2 ? b1 : o2) : (b2 < o1 ? b2 : o1);
     int bi = other ? oi : i1;
     // Near tie: every float32 score is within eps/2 of its exact value, so the
     // exact argmin is among the rows scoring <= best + eps. Those candidates
@@ -219,7 +227,6 @@ __global__ __launch_bounds__(kKmThreads) __attribute__((amdgpu_waves_per_eu(4, 4
           e = (double)x1 - (double)c.y; dj = fma(e, e, dj);
           e = (double)x2 - (double)c.z; dj = fma(e, e, dj);
           e = (double)x3 - (double)c.w; dj = fma(e, e, dj);
-          __builtin_amdgcn_sched_barrier(0);  // one centroid quad in flight at a time
         }
         if (dj < bd) {
           bd = dj;
@@ -238,24 +245,54 @@ __global__ __launch_bounds__(kKmThreads) __attribute__((amdgpu_waves_per_eu(4, 4
       }
     }
     bi = __shfl(bi, (int)col);  // lane col (h = 0) decided for both halves
-    if (valid) {
-      if (h == 0) assign[p] = bi;
-#pragma unroll
-      for (int s = 0; s < 16; ++s) atomicAdd(&s32[bi * kSumStride + 16 * h + s], xs[s]);
-      if (h == 0) atomicAdd(&scnt[bi], 1u);
+    if (valid && h == 0) {
+      assign[p] = bi;
+      atomicAdd(&scnt[bi], 1u);
     }
-    if ((it + 1) % kKmFlush == 0 || it + 1 == iters) {
-      __syncthreads();
-      for (int i = threadIdx.x; i < K * D; i += blockDim.x) {
-        const int c = i / D, t = i % D;
-        s64[i] += (double)s32[c * kSumStride + t];
-        s32[c * kSumStride + t] = 0.f;
+    // update: x transposed through LDS, one-hot assignments as the A operand
+#pragma unroll
+    for (int t = 0; t < 16; ++t) xt[wv][t][h * 32 + (col & 1u) * 16 + (col >> 1)] = xs[t];
+    if (h == 0) ab[wv][(col & 1u) * 16 + (col >> 1)] = valid ? bi : -1;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    {
+      // lane (col, h) supplies B[h][col] = x[2s + h][col] and A[col][h] = [a_{2s+h} = blk * 32 + col]
+      const f32x4* xr = reinterpret_cast<const f32x4*>(&xt[wv][col & 15u][(col >> 4) * 32 + h * 16]);
+      const int4* ar = reinterpret_cast<const int4*>(&ab[wv][h * 16]);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const f32x4 xv = xr[q];
+        const int4 av = ar[q];
+        const float xq[4] = {xv.x, xv.y, xv.z, xv.w};
+        const int aq[4] = {av.x, av.y, av.z, av.w};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const float o0 = aq[e] == (int)col ? 1.f : 0.f;
+          const float o1 = aq[e] == (int)(32 + col) ? 1.f : 0.f;
+          sum0 = __builtin_amdgcn_mfma_f32_32x32x2f32(o0, xq[e], sum0, 0, 0, 0);
+          sum1 = __builtin_amdgcn_mfma_f32_32x32x2f32(o1, xq[e], sum1, 0, 0, 0);
+        }
       }
-      __syncthreads();
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if ((it + 1) % kKmFlushIters == 0 || it + 1 == iters) {
+      // D layout: register r of lane (col, h) is cluster 8 (r / 4) + 4 h + r % 4 (+ 32 for sum1), dim col
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int c = 8 * (r / 4) + 4 * (int)h + (r % 4);
+        atomicAdd(&s64[c * D + col], (double)sum0[r]);
+        atomicAdd(&s64[(32 + c) * D + col], (double)sum1[r]);
+      }
+      sum0 = f32x16{};
+      sum1 = f32x16{};
     }
 #pragma unroll
     for (int s = 0; s < 16; ++s) xs[s] = xn[s];
   }
+  __syncthreads();
   if (rechecks) atomicAdd(n_recheck, rechecks);
   for (int i = threadIdx.x; i < K * D; i += blockDim.x) part_sum[(uint64_t)blockIdx.x * K * D + i] = s64[i];
   if (threadIdx.x < K) part_cnt[(uint64_t)blockIdx.x * K + threadIdx.x] = scnt[threadIdx.x];

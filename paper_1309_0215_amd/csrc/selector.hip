@@ -18,6 +18,8 @@ constexpr uint32_t kHllM = 1u << kHllLog;
 constexpr uint32_t kFeatSlots = 8192;               // exact counts of sampled keys
 constexpr uint32_t kWindows = 32;
 constexpr uint32_t kWindowBytes = 4096;
+constexpr uint32_t kSegBlocks = kWindowBytes / 16 + 1;  // aligned 16-byte blocks covering one window
+constexpr uint32_t kStageSegs = 16;                     // windows staged in LDS per round
 
 MR_DEV void hll_add(uint32_t* reg, uint64_t h) {
   const uint32_t idx = (uint32_t)(h >> (64 - kHllLog));
@@ -57,17 +59,25 @@ MR_DEV float hll_estimate(const uint32_t* reg, float* red) {
   return E;
 }
 
-MR_DEV void feat_insert(uint32_t* tk, uint32_t* tc, uint32_t key) {
+MR_DEV void feat_insert(uint32_t* tk, uint32_t* tc, uint32_t key, uint32_t c) {
   uint32_t s = (uint32_t)hash_u32(key) & (kFeatSlots - 1);
   for (int p = 0; p < 32; ++p) {
     uint32_t cur = tk[s];
     if (cur == 0xFFFFFFFFu) cur = atomicCAS(&tk[s], 0xFFFFFFFFu, key);
     if (cur == 0xFFFFFFFFu || cur == key) {
-      atomicAdd(&tc[s], 1u);
+      atomicAdd(&tc[s], c);
       return;
     }
     s = (s + 1) & (kFeatSlots - 1);
   }
+}
+
+// One sampled element: HyperLogLog registers and the exact count table.
+MR_DEV void feat_add(uint32_t* hll_all, uint32_t* hll_half, uint32_t* tk, uint32_t* tc, uint32_t key, uint64_t hh,
+                     bool in_half) {
+  hll_add(hll_all, hh);
+  if (in_half) hll_add(hll_half, hh);
+  feat_insert(tk, tc, key, 1u);
 }
 
 // kind: 0 words, 1 u32 keys, 2 u32 (key, value) pairs. One workgroup.
@@ -80,6 +90,7 @@ __global__ __launch_bounds__(kFeatThreads) void k_features(const uint8_t* __rest
   __shared__ float red[2 * kFeatThreads / kWave];
   __shared__ unsigned long long s_n, s_len, s_len2;
   __shared__ uint32_t top[64];
+  __shared__ uint4 stage[kStageSegs * kSegBlocks];
   for (uint32_t i = threadIdx.x; i < kHllM; i += blockDim.x) hll_all[i] = hll_half[i] = 0;
   for (uint32_t i = threadIdx.x; i < kFeatSlots; i += blockDim.x) {
     tk[i] = 0xFFFFFFFFu;
@@ -89,45 +100,77 @@ __global__ __launch_bounds__(kFeatThreads) void k_features(const uint8_t* __rest
   __syncthreads();
   const uint64_t esz = kind == 0 ? 1 : (kind == 1 ? 4 : 8);
   const uint64_t n_elem = bytes / esz;
-  // windows: the whole input when small, else kWindows evenly spaced windows
+  // segments of wel elements: kWindows evenly spaced windows, or the whole
+  // input in consecutive pieces when it is small
   const uint64_t wel = kWindowBytes / esz;
   const bool whole = n_elem <= (uint64_t)kWindows * wel;
-  const uint32_t nwin = whole ? 1u : kWindows;
+  const uint32_t nseg = whole ? (uint32_t)((n_elem + wel - 1) / wel) : kWindows;
   unsigned long long my_n = 0, my_len = 0, my_len2 = 0;
-  for (uint32_t w = 0; w < nwin; ++w) {
-    const uint64_t e0 = whole ? 0 : (n_elem - wel) * w / (kWindows - 1);
-    const uint64_t e1 = whole ? n_elem : e0 + wel;
-    const bool half = w < (nwin + 1) / 2 || whole;
-    if (kind == 0) {
-      // words starting inside the window (a word may run past it)
-      for (uint64_t p = e0 + threadIdx.x; p < e1; p += blockDim.x) {
-        const bool start = !is_sep_byte(in[p]) && (p == 0 || is_sep_byte(in[p - 1]));
-        if (!start) continue;
-        uint32_t h = 2166136261u;
-        uint64_t q = p;
-        while (q < bytes && !is_sep_byte(in[q]) && q - p < 256) {
-          h = (h ^ in[q]) * 16777619u;
-          ++q;
+  const uint8_t* sb = reinterpret_cast<const uint8_t*>(stage);
+  for (uint32_t r0 = 0; r0 < nseg; r0 += kStageSegs) {
+    const uint32_t ns = (nseg - r0) < kStageSegs ? (nseg - r0) : kStageSegs;
+    __syncthreads();  // the previous round is done with the stage
+    // the 16-byte aligned blocks covering each segment, all loads in flight at once
+    for (uint32_t b = threadIdx.x; b < ns * kSegBlocks; b += blockDim.x) {
+      const uint32_t si = b / kSegBlocks, q = b % kSegBlocks;
+      const uint64_t e0 = whole ? (uint64_t)(r0 + si) * wel : (n_elem - wel) * (r0 + si) / (kWindows - 1);
+      const uint64_t blk = (((uint64_t)in + e0 * esz) & ~15ull) + 16ull * q;
+      uint4 v = make_uint4(0x20202020u, 0x20202020u, 0x20202020u, 0x20202020u);
+      // a block that holds a byte of the input lies inside its allocation
+      if (blk < (uint64_t)in + bytes && blk + 16 > (uint64_t)in) v = *reinterpret_cast<const uint4*>(blk);
+      stage[b] = v;
+    }
+    __syncthreads();
+    for (uint32_t si = 0; si < ns; ++si) {
+      const uint32_t w = r0 + si;
+      const uint64_t e0 = whole ? (uint64_t)w * wel : (n_elem - wel) * w / (kWindows - 1);
+      const uint64_t e1 = whole ? (e0 + wel < n_elem ? e0 + wel : n_elem) : e0 + wel;
+      const bool half_win = w < (kWindows + 1) / 2;
+      const uint64_t lo = ((uint64_t)in + e0 * esz) & ~15ull;
+      const uint8_t* seg = sb + (uint64_t)si * kSegBlocks * 16;
+      // byte p of the input: from the staged span when it holds it
+      auto byte_at = [&](uint64_t p) -> uint32_t {
+        const uint64_t a = (uint64_t)in + p;
+        return (a >= lo && a < lo + kSegBlocks * 16ull) ? seg[a - lo] : in[p];
+      };
+      for (uint64_t eb = e0; eb < e1; eb += blockDim.x) {  // uniform over the workgroup
+        const uint64_t e = eb + threadIdx.x;
+        bool act = false, in_half = false;
+        uint32_t key = 0;
+        uint64_t hh = 0;
+        if (e < e1) {
+          if (kind == 0) {
+            // a word starting at byte e (it may run past the segment)
+            if (!is_sep_byte(byte_at(e)) && (e == 0 || is_sep_byte(byte_at(e - 1)))) {
+              uint32_t hf = 2166136261u;
+              uint64_t q = e;
+              while (q < bytes && q - e < 256) {
+                const uint32_t c = byte_at(q);
+                if (is_sep_byte(c)) break;
+                hf = (hf ^ c) * 16777619u;
+                ++q;
+              }
+              const uint64_t len = q - e;
+              hh = hash_u32(hf ^ (uint32_t)(len * 0x9E3779B9u));
+              key = (uint32_t)hh;
+              act = true;
+              ++my_n;
+              my_len += len;
+              my_len2 += len * len;
+            }
+          } else {
+            const uint64_t a = (uint64_t)in + e * esz;
+            uint32_t k;
+            if (a >= lo && a + 4 <= lo + kSegBlocks * 16ull) k = *reinterpret_cast<const uint32_t*>(seg + (a - lo));
+            else k = *reinterpret_cast<const uint32_t*>(a);
+            hh = hash_u32(k);
+            key = k;
+            act = true;
+            ++my_n;
+          }
+          in_half = whole ? (e & 1) != 0 : half_win;
         }
-        const uint64_t len = q - p;
-        const uint64_t hh = hash_u32(h ^ (uint32_t)(len * 0x9E3779B9u));
-        hll_add(hll_all, hh);
-        if (half && !whole) hll_add(hll_half, hh);
-        if (whole && (p & 1)) hll_add(hll_half, hh);
-        feat_insert(tk, tc, (uint32_t)hh);
-        ++my_n;
-        my_len += len;
-        my_len2 += len * len;
-      }
-    } else {
-      for (uint64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
-        const uint32_t k = reinterpret_cast<const uint32_t*>(in)[e * (esz / 4)];
-        const uint64_t hh = hash_u32(k);
-        hll_add(hll_all, hh);
-        if (half && !whole) hll_add(hll_half, hh);
-        if (whole && (e & 1)) hll_add(hll_half, hh);
-        feat_insert(tk, tc, k);
-        ++my_n;
+        if (act) feat_add(hll_all, hll_half, tk, tc, key, hh, in_half);
       }
     }
   }
@@ -140,28 +183,52 @@ __global__ __launch_bounds__(kFeatThreads) void k_features(const uint8_t* __rest
   // The 64 largest counts, exactly: radix-select the 64th largest value v64
   // with two histogram passes over the count bits (counts stay below 2^17:
   // the sample holds at most 64 Ki elements), then collect the counts above
-  // v64, sort them, and pad with v64 (ties) or zeros (fewer than 64 keys).
+  // v64, order them by rank, and pad with v64 (ties) or zeros (fewer than 64
+  // keys). The bucket walks are wave prefix sums, not a serial loop.
   {
     __shared__ uint32_t hist[512];
     __shared__ uint32_t s_b1, s_above, s_v64, s_ngt;
     __shared__ uint32_t gt[64];
+    const uint32_t lane = lane_id();
     for (uint32_t i = threadIdx.x; i < 512; i += blockDim.x) hist[i] = 0;
-    if (threadIdx.x == 0) s_ngt = 0;
+    if (threadIdx.x == 0) {
+      s_ngt = 0;
+      s_b1 = 0xFFFFFFFFu;  // none: fewer than 64 nonzero counts
+      s_above = 0;
+      s_v64 = 0;
+    }
     __syncthreads();
     for (uint32_t i = threadIdx.x; i < kFeatSlots; i += blockDim.x) {
       const uint32_t c = tc[i];
       if (c) atomicAdd(&hist[min(c >> 9, 255u)], 1u);
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-      uint32_t acc = 0;
-      int b = 255;
-      for (; b >= 0; --b) {
-        if (acc + hist[b] >= 64) break;
-        acc += hist[b];
+    if (threadIdx.x < kWave) {
+      // lane l holds buckets 255 - 4l down to 252 - 4l
+      uint32_t h4[4], sum = 0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        h4[q] = hist[255 - 4 * lane - q];
+        sum += h4[q];
       }
-      s_b1 = b >= 0 ? (uint32_t)b : 0xFFFFFFFFu;  // none: fewer than 64 nonzero counts
-      s_above = acc;
+      uint32_t incl = sum;
+#pragma unroll
+      for (int o = 1; o < kWave; o <<= 1) {
+        const uint32_t y = (uint32_t)__shfl_up((int)incl, o);
+        if (lane >= (uint32_t)o) incl += y;
+      }
+      uint32_t acc = incl - sum;
+      if (acc < 64 && incl >= 64) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          if (acc + h4[q] >= 64) {
+            s_b1 = 255 - 4 * lane - (uint32_t)q;
+            s_above = acc;
+            break;
+          }
+          acc += h4[q];
+        }
+      }
     }
     __syncthreads();
     const uint32_t b1 = s_b1;
@@ -173,16 +240,36 @@ __global__ __launch_bounds__(kFeatThreads) void k_features(const uint8_t* __rest
         if (c && min(c >> 9, 255u) == b1) atomicAdd(&hist[c & 511u], 1u);
       }
       __syncthreads();
-      if (threadIdx.x == 0) {
-        uint32_t acc = s_above, lo = 511;
-        for (;; --lo) {
-          if (acc + hist[lo] >= 64 || lo == 0) break;
-          acc += hist[lo];
+      if (threadIdx.x < kWave) {
+        // lane l holds values 511 - 8l down to 504 - 8l of bucket b1
+        uint32_t h8[8], sum = 0;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          h8[q] = hist[511 - 8 * lane - q];
+          sum += h8[q];
         }
-        s_v64 = (b1 << 9) | lo;
+        uint32_t incl = sum;
+#pragma unroll
+        for (int o = 1; o < kWave; o <<= 1) {
+          const uint32_t y = (uint32_t)__shfl_up((int)incl, o);
+          if (lane >= (uint32_t)o) incl += y;
+        }
+        uint32_t acc = s_above + incl - sum;
+        const bool last = lane == kWave - 1;
+        if ((acc < 64 && acc + sum >= 64) || (last && acc + sum < 64)) {
+          uint32_t lo = 0;
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            const uint32_t v = 511 - 8 * lane - (uint32_t)q;
+            if (acc + h8[q] >= 64 || v == 0) {
+              lo = v;
+              break;
+            }
+            acc += h8[q];
+          }
+          s_v64 = (b1 << 9) | lo;
+        }
       }
-    } else if (threadIdx.x == 0) {
-      s_v64 = 0;
     }
     __syncthreads();
     const uint32_t v64 = s_v64;
@@ -194,20 +281,40 @@ __global__ __launch_bounds__(kFeatThreads) void k_features(const uint8_t* __rest
       }
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-      const uint32_t n = min(s_ngt, 64u);
-      for (uint32_t a = 1; a < n; ++a) {  // insertion sort, descending
-        const uint32_t x = gt[a];
-        uint32_t b = a;
-        while (b > 0 && gt[b - 1] < x) {
-          gt[b] = gt[b - 1];
-          --b;
-        }
-        gt[b] = x;
+    if (threadIdx.x < 64) {
+      // descending order by rank (ties keep their collection order)
+      const uint32_t n = min(s_ngt, 64u), t = threadIdx.x;
+      if (t < n) {
+        const uint32_t x = gt[t];
+        uint32_t rank = 0;
+        for (uint32_t u = 0; u < n; ++u) rank += (gt[u] > x || (gt[u] == x && u < t)) ? 1u : 0u;
+        top[rank] = x;
+      } else {
+        top[t] = v64;
       }
-      for (uint32_t r = 0; r < 64; ++r) top[r] = r < n ? gt[r] : v64;
     }
     __syncthreads();
+  }
+  if (threadIdx.x >= kWave) return;
+  // Zipf exponent: least-squares slope of log count against log rank over the top counts
+  float sx = 0, sy = 0, sxx = 0, sxy = 0, m = 0, top64 = 0;
+  {
+    const uint32_t r = lane_id();
+    const float cnt = (float)top[r];
+    top64 = cnt;
+    if (cnt > 0.f) {
+      const float x = logf((float)(r + 1)), y = logf(cnt);
+      sx = x; sy = y; sxx = x * x; sxy = x * y; m = 1.f;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      sx += __shfl_xor(sx, o);
+      sy += __shfl_xor(sy, o);
+      sxx += __shfl_xor(sxx, o);
+      sxy += __shfl_xor(sxy, o);
+      m += __shfl_xor(m, o);
+      top64 += __shfl_xor(top64, o);
+    }
   }
   if (threadIdx.x != 0) return;
   const float n_s = (float)(s_n ? s_n : 1ull);
@@ -220,15 +327,6 @@ __global__ __launch_bounds__(kFeatThreads) void k_features(const uint8_t* __rest
   float D_est = fmaxf(D_all, 1.f) * powf(fmaxf(T / n_s, 1.f), beta);
   D_est = fminf(D_est, fmaxf(T, 1.f));
   if (key_range) D_est = fminf(D_est, (float)key_range);
-  // Zipf exponent: least-squares slope of log count against log rank over the top counts
-  float sx = 0, sy = 0, sxx = 0, sxy = 0, m = 0, top64 = 0;
-  for (int r = 0; r < 64; ++r) {
-    top64 += (float)top[r];
-    if (top[r] > 0) {
-      const float x = logf((float)(r + 1)), y = logf((float)top[r]);
-      sx += x; sy += y; sxx += x * x; sxy += x * y; m += 1.f;
-    }
-  }
   const float den = m * sxx - sx * sx;
   const float zipf = (m >= 2.f && den > 0.f) ? -(m * sxy - sx * sy) / den : 0.f;
   const float mean_len = kind == 0 ? (float)s_len / n_s : (float)esz;

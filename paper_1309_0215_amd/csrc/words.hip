@@ -246,12 +246,16 @@ __global__ void k_words_prep(const WordJob* __restrict__ jobs, uint32_t n_jobs) 
 // map + combine
 // ----------------------------------------------------------------------------
 
-constexpr int kLdsProbe = 16;
+// Probe groups: 4 consecutive slots whose tags are read with one 16-byte LDS
+// load. A word visits at most kLdsGroups groups before it goes global.
+constexpr int kLdsGroups = 4;
+// Word descriptors a wave lists per round (more words take more rounds).
+constexpr uint32_t kListCap = 256;
 
 template <int kSlotsLog2>
 struct LdsTable {
   static constexpr uint32_t kSlots = 1u << kSlotsLog2;
-  uint32_t tag[kSlots];   // 0 empty; bit0 ready; bits 1..5 length; bits 6..31 hash
+  uint32_t tag[kSlots];   // 0 empty; bit0 ready; bits 1..5 length; bits 6..31 hash (16-byte aligned groups)
   uint4 key[kSlots];
   uint32_t cnt[kSlots];
   uint32_t off[kSlots];   // offset of one occurrence, for the global flush
@@ -259,32 +263,47 @@ struct LdsTable {
 
 MR_DEV uint32_t lds_tag(uint64_t h, uint32_t len) { return ((uint32_t)(h >> 32) & 0xFFFFFFC0u) | (len << 1); }
 
-// 0 = done, 1 = slot being written by another lane (retry), 2 = no slot within the probe limit
+// Bucketed linear probing: a group is searched for the key; a group with an
+// empty slot ends the search (slots fill in order and are never freed, so the
+// key would have been placed there), and the key claims that slot unless the
+// table has reached its fill limit.
+// Returns 0 = counted, 1 = a matching slot is still being written or the
+// claim was lost (retry), 2 = not in the table and not inserted (go global).
 template <int L>
-MR_DEV int lds_insert(LdsTable<L>& T, uint32_t tg, uint32_t slot, uint4 k, uint32_t off) {
-  uint32_t i = slot & (LdsTable<L>::kSlots - 1);
-  for (int p = 0; p < kLdsProbe; ++p) {
-    uint32_t cur = __hip_atomic_load(&T.tag[i], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
-    if (cur == 0u) {
-      const uint32_t old = atomicCAS(&T.tag[i], 0u, tg);
-      if (old == 0u) {
-        T.key[i] = k;
-        T.off[i] = off;
-        T.cnt[i] = 1u;
-        __hip_atomic_store(&T.tag[i], tg | 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
-        return 0;
+MR_DEV int lds_insert(LdsTable<L>& T, uint32_t* used, uint32_t limit, uint32_t tg, uint32_t h, uint4 k, uint32_t off) {
+  constexpr uint32_t kGroupMask = LdsTable<L>::kSlots / 4 - 1;
+  uint32_t g = h & kGroupMask;
+  for (int p = 0; p < kLdsGroups; ++p) {
+    const uint4 t4 = reinterpret_cast<const uint4*>(T.tag)[g];
+    const uint32_t tv[4] = {t4.x, t4.y, t4.z, t4.w};
+    int empty = -1;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const uint32_t cur = tv[q];
+      if (cur == 0u) {
+        if (empty < 0) empty = q;
+      } else if ((cur | 1u) == (tg | 1u)) {
+        if (!(cur & 1u)) return 1;
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");  // key bytes after the ready tag
+        const uint4 kk = T.key[4 * g + q];
+        if (kk.x == k.x && kk.y == k.y && kk.z == k.z && kk.w == k.w) {
+          atomicAdd(&T.cnt[4 * g + q], 1u);
+          return 0;
+        }
       }
-      return 1;  // lost the race: look again next round
     }
-    if ((cur | 1u) == (tg | 1u)) {
-      if (!(cur & 1u)) return 1;
-      const uint4 kk = T.key[i];
-      if (kk.x == k.x && kk.y == k.y && kk.z == k.z && kk.w == k.w) {
-        atomicAdd(&T.cnt[i], 1u);
-        return 0;
-      }
+    if (empty >= 0) {
+      if (*used >= limit) return 2;
+      const uint32_t i = 4 * g + (uint32_t)empty;
+      if (atomicCAS(&T.tag[i], 0u, tg) != 0u) return 1;  // lost the slot: look again
+      T.key[i] = k;
+      T.off[i] = off;
+      T.cnt[i] = 1u;
+      __hip_atomic_store(&T.tag[i], tg | 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+      atomicAdd(used, 1u);
+      return 0;
     }
-    i = (i + 1) & (LdsTable<L>::kSlots - 1);
+    g = (g + 1) & kGroupMask;
   }
   return 2;
 }
@@ -312,16 +331,34 @@ MR_DEV uint32_t find_job(const uint64_t* __restrict__ tile_base, uint32_t n_jobs
   return lo;
 }
 
+// Separator mask of a 16-byte block.
+MR_DEV uint32_t sep16(uint4 b) { return sep_mask16(b.x, b.y, b.z, b.w); }
+
+// One workgroup per run of tiles. For each 16 KiB tile:
+//   1. every lane loads one 16-byte chunk into the LDS copy of the tile (plus
+//      32 bytes after it) and finds the words that start in its chunk;
+//   2. words of up to 16 bytes become descriptors (offset in the tile, length)
+//      in a per-wave list, placed by a wave prefix sum; longer words are
+//      measured, hashed and inserted globally by their lane at once;
+//   3. the wave then takes the list one word per lane (all lanes busy): key
+//      bytes from the LDS copy, hash, LDS table insert, global insert on a miss.
 template <int L, bool kRecords>
 __global__ __launch_bounds__(kMapThreads) void k_words_map(const WordJob* __restrict__ jobs, const uint64_t* __restrict__ tile_base,
                                                            uint32_t n_jobs, uint64_t total_tiles, uint32_t debug_hash) {
   __shared__ LdsTable<L> T;
+  __shared__ uint4 stage[kMapTileChunks + 2];
+  __shared__ uint32_t wlist[kMapThreads / kWave][kListCap];
   constexpr uint32_t kBndWords = kMapTileChunks * 16 / 32 + 2;
   __shared__ uint32_t bnd[kRecords ? kBndWords : 1];
-  __shared__ uint32_t s_abort;
+  __shared__ uint32_t s_abort, s_used;
+  // fill limit of the LDS table: beyond it new words go straight to the global table
+  constexpr uint32_t kLimit = LdsTable<L>::kSlots / 4 * 3;
 
   for (uint32_t i = threadIdx.x; i < LdsTable<L>::kSlots; i += blockDim.x) T.tag[i] = 0u;
-  if (threadIdx.x == 0) s_abort = 0;
+  if (threadIdx.x == 0) {
+    s_abort = 0;
+    s_used = 0;
+  }
   __syncthreads();
 
   const uint64_t t_begin = total_tiles * blockIdx.x / gridDim.x;
@@ -332,11 +369,13 @@ __global__ __launch_bounds__(kMapThreads) void k_words_map(const WordJob* __rest
   uint64_t vlo = 0, vhi = 0;
 
   for (uint64_t t = t_begin; t < t_end; ++t) {
+    // every thread is done with the previous tile (its abort flag, LDS copy and lists)
+    __syncthreads();
     const uint32_t j = find_job(tile_base, n_jobs, t);
     if ((int)j != cur) {
       if (cur >= 0) {
-        __syncthreads();
         lds_flush<L>(T, jobs[cur], vlo, vhi, debug_hash);
+        if (threadIdx.x == 0) s_used = 0;
         __syncthreads();
       }
       cur = (int)j;
@@ -351,7 +390,6 @@ __global__ __launch_bounds__(kMapThreads) void k_words_map(const WordJob* __rest
     const uint64_t tile_addr = (J.chunk0 + lt * kMapTileChunks) * 16;
 
     if constexpr (kRecords) {
-      __syncthreads();
       for (uint32_t i = threadIdx.x; i < kBndWords; i += blockDim.x) bnd[i] = 0u;
       __syncthreads();
       // record boundaries falling in [tile_addr, tile_addr + 32 * kBndWords);
@@ -371,27 +409,18 @@ __global__ __launch_bounds__(kMapThreads) void k_words_map(const WordJob* __rest
     __syncthreads();
     if (s_abort) continue;
 
-    const uint64_t c = lt * kMapTileChunks + wave * kWave + lane;  // this lane's chunk
-    const uint64_t B = (J.chunk0 + c) * 16;                         // its absolute address
-    uint32_t w[8];
-    {
-      const uint4 b0 = c < J.n_chunks ? load_block(a0, a1, B) : spaces4();
-      const uint4 b1 = c + 1 < J.n_chunks ? load_block(a0, a1, B + 16) : spaces4();
-      w[0] = b0.x; w[1] = b0.y; w[2] = b0.z; w[3] = b0.w;
-      w[4] = b1.x; w[5] = b1.y; w[6] = b1.z; w[7] = b1.w;
+    // 1. the tile into LDS; this lane's chunk and the next one as a 32-byte window
+    const uint64_t c = lt * kMapTileChunks + threadIdx.x;  // this lane's chunk
+    const uint64_t B = (J.chunk0 + c) * 16;                 // its absolute address
+    const uint4 b0 = c < J.n_chunks ? load_block(a0, a1, B) : spaces4();
+    stage[threadIdx.x] = b0;
+    if (threadIdx.x < 2) {
+      const uint64_t cx = lt * kMapTileChunks + kMapTileChunks + threadIdx.x;
+      stage[kMapTileChunks + threadIdx.x] = cx < J.n_chunks ? load_block(a0, a1, (J.chunk0 + cx) * 16) : spaces4();
     }
-    const uint32_t valid = range_mask32((int64_t)(a0 + vlo) - (int64_t)B, (int64_t)(a0 + vhi) - (int64_t)B);
-    const uint32_t sep = (sep_mask16(w[0], w[1], w[2], w[3]) | (sep_mask16(w[4], w[5], w[6], w[7]) << 16)) | ~valid;
-    uint32_t bd = 0u;
-    if constexpr (kRecords) {
-      const uint64_t bit = B - tile_addr;  // multiple of 16
-      const uint32_t wi = (uint32_t)(bit >> 5);
-      const uint32_t lo = bnd[wi], hi = bnd[wi + 1];
-      bd = (bit & 16) ? ((lo >> 16) | (hi << 16)) : lo;
-    }
-    uint32_t prev = (uint32_t)__shfl_up((int)((sep >> 15) & 1u), 1);
+    // byte B - 1: the previous lane's chunk, or the previous tile's last chunk
+    uint32_t prev = (uint32_t)__shfl_up((int)((sep16(b0) >> 15) & 1u), 1);
     if (lane == 0) {
-      // byte B - 1 lives in the previous chunk
       const uint64_t pb = B - 1;
       bool ps = true;
       if (pb >= a0 + vlo && pb < a0 + vhi) {
@@ -400,35 +429,80 @@ __global__ __launch_bounds__(kMapThreads) void k_words_map(const WordJob* __rest
       }
       prev = ps ? 1u : 0u;
     }
-    uint32_t starts = ~sep & ((sep << 1) | prev | bd) & 0xFFFFu;
+    __syncthreads();
+    const uint4 b1 = stage[threadIdx.x + 1];
+    const uint32_t valid = range_mask32((int64_t)(a0 + vlo) - (int64_t)B, (int64_t)(a0 + vhi) - (int64_t)B);
+    const uint32_t sep = (sep16(b0) | (sep16(b1) << 16)) | ~valid;
+    uint32_t bd = 0u;
+    if constexpr (kRecords) {
+      const uint64_t bit = B - tile_addr;  // multiple of 16
+      const uint32_t wi = (uint32_t)(bit >> 5);
+      const uint32_t lo = bnd[wi], hi = bnd[wi + 1];
+      bd = (bit & 16) ? ((lo >> 16) | (hi << 16)) : lo;
+    }
+    const uint32_t starts = ~sep & ((sep << 1) | prev | bd) & 0xFFFFu;
     const uint32_t ends = sep | bd;
 
-    while (starts) {
-      const uint32_t s = __builtin_ctz(starts);
-      starts &= starts - 1u;
+    // 2. inline words (end inside the window, at most 16 bytes) are listed;
+    //    longer words are handled here
+    uint32_t inl = 0u;
+    for (uint32_t m = starts; m; m &= m - 1u) {
+      const uint32_t s = __builtin_ctz(m);
       const uint32_t after = ends & ~((2u << s) - 1u);
       const uint32_t e = after ? (uint32_t)__builtin_ctz(after) : 32u;
-      const uint64_t off = B + s - a0;
-      if (after == 0u || e - s > 16u) {
-        // long word: measure and hash it from memory, insert globally
+      if (after != 0u && e - s <= 16u) {
+        inl |= 1u << s;
+      } else {
+        const uint64_t off = B + s - a0;
         const uint64_t len = word_length_slow(J, vlo, vhi, off);
         const uint64_t h = key_hash_global(J.in, off, len, debug_hash);
         g_insert<false>(J, vlo, vhi, off, len, h, make_uint4(0, 0, 0, 0), 1u, debug_hash);
-        continue;
       }
-      const uint32_t len = e - s;
-      const uint4 k = extract16(w, s, len);
-      const uint64_t h = key_hash16(k, len, debug_hash);
-      const uint32_t tg = lds_tag(h, len);
-      int r = 1;
-      for (uint32_t spin = 0; r == 1; ++spin) {
-        r = lds_insert<L>(T, tg, (uint32_t)h, k, (uint32_t)off);
-        if (r == 1 && spin > (1u << 22)) {
-          atomicOr(&J.st->flags, kFlagSpin);
-          r = 0;
+    }
+    const uint32_t n_mine = __builtin_popcount(inl);
+    uint32_t incl = n_mine;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+      const uint32_t y = (uint32_t)__shfl_up((int)incl, o);
+      if (lane >= (uint32_t)o) incl += y;
+    }
+    const uint32_t total = (uint32_t)__shfl((int)incl, kWave - 1);
+    const uint32_t first = incl - n_mine;
+
+    // 3. rounds of up to kListCap words, one word per lane
+    for (uint32_t base = 0; base < total; base += kListCap) {
+      uint32_t p = first;
+      for (uint32_t m = inl; m; m &= m - 1u, ++p) {
+        if (p < base || p >= base + kListCap) continue;
+        const uint32_t s = __builtin_ctz(m);
+        const uint32_t after = ends & ~((2u << s) - 1u);
+        const uint32_t len = (uint32_t)__builtin_ctz(after) - s;
+        wlist[wave][p - base] = ((threadIdx.x * 16u + s) << 5) | len;
+      }
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      const uint32_t nr = (total - base) < kListCap ? (total - base) : kListCap;
+      for (uint32_t i = lane; i < nr; i += kWave) {
+        const uint32_t d = wlist[wave][i];
+        const uint32_t o = d >> 5, len = d & 31u;
+        const uint4 x0 = stage[o >> 4], x1 = stage[(o >> 4) + 1];
+        const uint32_t w[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
+        const uint4 k = extract16(w, o & 15u, len);
+        const uint64_t h = key_hash16(k, len, debug_hash);
+        const uint32_t tg = lds_tag(h, len);
+        const uint64_t off = tile_addr + o - a0;
+        int r = 1;
+        for (uint32_t spin = 0; r == 1; ++spin) {
+          r = lds_insert<L>(T, &s_used, kLimit, tg, (uint32_t)h, k, (uint32_t)off);
+          if (r == 1 && spin > (1u << 22)) {
+            atomicOr(&J.st->flags, kFlagSpin);
+            r = 0;
+          }
         }
+        if (r == 2) g_insert<true>(J, vlo, vhi, off, len, h, k, 1u, debug_hash);
       }
-      if (r == 2) g_insert<true>(J, vlo, vhi, off, len, h, k, 1u, debug_hash);
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      __builtin_amdgcn_wave_barrier();
     }
   }
   __syncthreads();
@@ -440,43 +514,52 @@ __global__ __launch_bounds__(kMapThreads) void k_words_map(const WordJob* __rest
 // ----------------------------------------------------------------------------
 
 constexpr uint32_t kCompactThreads = 256;
+constexpr uint32_t kCompactSlots = 4096;  // slots per work item: one job-counter update each
 
+// The entry of slot i, or 0 (empty, or an occurrence offset outside the
+// input, which is reported and skipped).
+MR_DEV unsigned long long compact_entry(const WordJob& J, uint64_t i) {
+  if (i >= J.cap) return 0ull;
+  const unsigned long long w = J.tw[i];
+  if (w && !rep_in_bounds(J, w >> 32, (w >> 16) & 0xFFFFull)) return 0ull;
+  return w;
+}
+
+// Work item = 4096 slots of one job's table (tables are powers of two >= 4096
+// slots at 4096-aligned arena offsets). Pass 1 counts the entries, one atomic
+// reserves their places, pass 2 writes the records and clears the slots.
 __global__ __launch_bounds__(kCompactThreads) void k_words_compact(const WordJob* __restrict__ jobs, uint32_t n_jobs,
                                                                    uint64_t total_slots) {
-  __shared__ uint32_t s_cnt;
-  __shared__ unsigned long long s_base;
-  __shared__ unsigned long long s_bytes;
-  for (uint64_t t0 = (uint64_t)blockIdx.x * kCompactThreads; t0 < total_slots; t0 += (uint64_t)gridDim.x * kCompactThreads) {
-    // tables are powers of two >= 4096 slots at 4096-aligned arena offsets: a tile is in one job
+  __shared__ uint32_t s_cnt, s_pos;
+  __shared__ unsigned long long s_base, s_bytes;
+  for (uint64_t t0 = (uint64_t)blockIdx.x * kCompactSlots; t0 < total_slots; t0 += (uint64_t)gridDim.x * kCompactSlots) {
     uint32_t lo = 0, hi = n_jobs;
     while (hi - lo > 1) {
       const uint32_t mid = (lo + hi) >> 1;
       if (jobs[mid].slot_base <= t0) lo = mid; else hi = mid;
     }
     const WordJob& J = jobs[lo];
-    const uint64_t i = t0 - J.slot_base + threadIdx.x;
+    const uint64_t i0 = t0 - J.slot_base;
     if (threadIdx.x == 0) {
       s_cnt = 0;
+      s_pos = 0;
       s_bytes = 0;
     }
     __syncthreads();
-    unsigned long long w = 0;
-    uint32_t cnt = 0;
-    if (i < J.cap) {
-      w = J.tw[i];
-      if (w) {
-        cnt = J.tc[i];
-        J.tw[i] = 0ull;
-        J.tc[i] = 0u;
-        if (!rep_in_bounds(J, w >> 32, (w >> 16) & 0xFFFFull)) w = 0;  // reported, skipped
-      }
-    }
-    uint32_t my = 0;
-    if (w) my = atomicAdd(&s_cnt, 1u);
+    uint32_t mine = 0;
+    for (uint32_t q = threadIdx.x; q < kCompactSlots; q += kCompactThreads) mine += compact_entry(J, i0 + q) ? 1u : 0u;
+    if (mine) atomicAdd(&s_cnt, mine);
     __syncthreads();
     if (threadIdx.x == 0) s_base = s_cnt ? atomicAdd(&J.st->n_recs, (unsigned long long)s_cnt) : 0ull;
     __syncthreads();
-    if (w) {
+    unsigned long long bytes = 0;
+    for (uint32_t q = threadIdx.x; q < kCompactSlots; q += kCompactThreads) {
+      const uint64_t i = i0 + q;
+      const unsigned long long w = compact_entry(J, i);
+      if (!w) continue;
+      const uint32_t cnt = J.tc[i];
+      J.tw[i] = 0ull;
+      J.tc[i] = 0u;
       const uint64_t off = w >> 32;
       uint64_t len = (w >> 16) & 0xFFFFull;
       if (len == 0xFFFFull) len = word_length_slow(J, J.st->valid_lo, J.st->valid_hi, off);
@@ -487,9 +570,10 @@ __global__ __launch_bounds__(kCompactThreads) void k_words_compact(const WordJob
       r.off = (uint32_t)off;
       r.cnt = cnt;
       r.pad = 0;
-      reinterpret_cast<WRec*>(J.recs)[s_base + my] = r;
-      atomicAdd(&s_bytes, (unsigned long long)len);
+      reinterpret_cast<WRec*>(J.recs)[s_base + atomicAdd(&s_pos, 1u)] = r;
+      bytes += len;
     }
+    if (bytes) atomicAdd(&s_bytes, bytes);
     __syncthreads();
     if (threadIdx.x == 0 && s_bytes) atomicAdd(&J.st->key_bytes, s_bytes);
   }
@@ -539,6 +623,80 @@ MR_DEV void bitonic_sort(const WordJob& J, WRec* a, uint32_t m) {
   }
 }
 
+// Keys of up to CAP records in LDS as separate arrays (prefix words, length,
+// record index): a compare-exchange reads consecutive words across threads
+// instead of 32-byte records, which keeps LDS accesses free of bank conflicts.
+template <uint32_t CAP>
+struct SoaKeys {
+  uint32_t k[4][CAP];
+  uint32_t len[CAP];
+  uint32_t ix[CAP];  // record index in recs
+};
+
+template <uint32_t CAP>
+MR_DEV void soa_load(SoaKeys<CAP>& S, uint32_t i, const WRec& r, uint32_t ix) {
+  S.k[0][i] = r.p[0];
+  S.k[1][i] = r.p[1];
+  S.k[2][i] = r.p[2];
+  S.k[3][i] = r.p[3];
+  S.len[i] = r.len;
+  S.ix[i] = ix;
+}
+
+// Three-way compare of entries i and l (same order as wrec_cmp).
+template <uint32_t CAP>
+MR_DEV int soa_cmp(const WordJob& J, const WRec* recs, const SoaKeys<CAP>& S, uint32_t i, uint32_t l) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const uint32_t a = S.k[q][i], b = S.k[q][l];
+    if (a != b) return a < b ? -1 : 1;
+  }
+  const uint32_t la = S.len[i], lb = S.len[l];
+  if (la > 16u && lb > 16u) {
+    const uint32_t oa = recs[S.ix[i]].off, ob = recs[S.ix[l]].off;
+    const uint32_t m = la < lb ? la : lb;
+    for (uint32_t t = 16; t < m; ++t) {
+      const uint8_t x = J.in[oa + t], y = J.in[ob + t];
+      if (x != y) return x < y ? -1 : 1;
+    }
+  }
+  return la < lb ? -1 : (la > lb ? 1 : 0);
+}
+
+template <uint32_t CAP>
+MR_DEV void soa_swap(SoaKeys<CAP>& S, uint32_t i, uint32_t l) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const uint32_t t = S.k[q][i];
+    S.k[q][i] = S.k[q][l];
+    S.k[q][l] = t;
+  }
+  uint32_t t = S.len[i];
+  S.len[i] = S.len[l];
+  S.len[l] = t;
+  t = S.ix[i];
+  S.ix[i] = S.ix[l];
+  S.ix[l] = t;
+}
+
+// Bitonic sort (all-ascending "flip" form) of entries [0, m), m <= CAP, by the
+// whole workgroup; indices >= m act as +infinity and are never touched.
+template <uint32_t CAP>
+MR_DEV void soa_bitonic(const WordJob& J, const WRec* recs, SoaKeys<CAP>& S, uint32_t m) {
+  uint32_t n = 1;
+  while (n < m) n <<= 1;
+  for (uint32_t k = 2; k <= n; k <<= 1) {
+    for (uint32_t jj = k >> 1; jj > 0; jj >>= 1) {
+      for (uint32_t t = threadIdx.x; t < n / 2; t += blockDim.x) {
+        const uint32_t i = ((t & ~(jj - 1)) << 1) | (t & (jj - 1));
+        const uint32_t l = (jj == (k >> 1)) ? (i ^ (k - 1)) : (i | jj);
+        if (l < m && soa_cmp(J, recs, S, i, l) > 0) soa_swap(S, i, l);
+      }
+      __syncthreads();
+    }
+  }
+}
+
 constexpr uint32_t kSortThreads = 1024;
 constexpr uint32_t kOversample = 4;
 
@@ -568,7 +726,7 @@ __global__ void k_sort_plan(const WordJob* __restrict__ jobs, uint32_t n_jobs, u
 __global__ __launch_bounds__(kSortThreads) void k_sort_splitters(const WordJob* __restrict__ jobs, uint32_t n_jobs,
                                                                   uint32_t* bucket_cnt, unsigned long long* bucket_bytes,
                                                                   uint32_t* bucket_fill) {
-  __shared__ WRec smp[kMaxBuckets * kOversample];
+  __shared__ SoaKeys<kMaxBuckets * kOversample> smp;
   const uint32_t j = blockIdx.x;
   if (j >= n_jobs) return;
   const WordJob& J = jobs[j];
@@ -583,11 +741,14 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_splitters(const WordJob* 
   const uint64_t n = J.st->n_recs;
   const uint32_t S = nb * kOversample;
   const WRec* recs = reinterpret_cast<const WRec*>(J.recs);
-  for (uint32_t i = threadIdx.x; i < S; i += blockDim.x) smp[i] = recs[(uint64_t)i * n / S];
+  for (uint32_t i = threadIdx.x; i < S; i += blockDim.x) {
+    const uint32_t ix = (uint32_t)((uint64_t)i * n / S);
+    soa_load(smp, i, recs[ix], ix);
+  }
   __syncthreads();
-  bitonic_sort(J, smp, S);
+  soa_bitonic(J, recs, smp, S);
   WRec* spl = reinterpret_cast<WRec*>(J.splitters);
-  for (uint32_t b = threadIdx.x; b + 1 < nb; b += blockDim.x) spl[b] = smp[(b + 1) * kOversample - 1];
+  for (uint32_t b = threadIdx.x; b + 1 < nb; b += blockDim.x) spl[b] = recs[smp.ix[(b + 1) * kOversample - 1]];
 }
 
 // Bucket of each record: number of splitters strictly below it.
@@ -756,7 +917,7 @@ MR_DEV uint32_t find_bucket_job(const WordJob* jobs, uint32_t n_jobs, uint32_t g
 __global__ __launch_bounds__(kSortThreads) void k_sort_buckets(const WordJob* __restrict__ jobs, uint32_t n_jobs, const uint32_t* totals,
                                                                 const uint32_t* bucket_cnt, const uint32_t* bucket_start,
                                                                 const unsigned long long* bucket_bstart) {
-  __shared__ WRec a[kBucketCap];
+  __shared__ SoaKeys<kBucketCap> a;
   __shared__ uint64_t wsum[kSortThreads / kWave];
   const uint32_t n_buckets = totals[0];
   for (uint32_t g = blockIdx.x; g < n_buckets; g += gridDim.x) {
@@ -770,20 +931,20 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_buckets(const WordJob* __
     __syncthreads();
     if (m == 0) continue;
     const bool in_lds = m <= kBucketCap;
-    WRec* arr = in_lds ? a : src;
     if (in_lds) {
-      for (uint32_t i = threadIdx.x; i < m; i += blockDim.x) a[i] = src[i];
+      for (uint32_t i = threadIdx.x; i < m; i += blockDim.x) soa_load(a, i, src[i], i);
       __syncthreads();
-    } else if (threadIdx.x == 0) {
-      atomicOr(&J.st->flags, kFlagSortFallback);  // rare: sort the bucket in global memory
+      soa_bitonic(J, src, a, m);
+    } else {
+      if (threadIdx.x == 0) atomicOr(&J.st->flags, kFlagSortFallback);  // rare: sort the bucket in global memory
+      bitonic_sort(J, src, m);
     }
-    bitonic_sort(J, arr, m);
     if (!write) continue;
     // byte positions: exclusive scan of lengths in chunks of blockDim
     uint64_t carry = 0;
     for (uint32_t base = 0; base < m; base += blockDim.x) {
       const uint32_t i = base + threadIdx.x;
-      const uint64_t len = i < m ? arr[i].len : 0;
+      const uint64_t len = i < m ? (in_lds ? a.len[i] : src[i].len) : 0;
       // wave inclusive scan
       uint64_t x = len;
       const uint32_t ln = lane_id();
@@ -801,13 +962,15 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_buckets(const WordJob* __
       for (uint32_t q = 0; q < blockDim.x / kWave; ++q) tot += wsum[q];
       const uint64_t excl = carry + wpre + x - len;
       if (i < m) {
-        const WRec r = arr[i];
+        const WRec r = src[in_lds ? a.ix[i] : i];
         const uint64_t o = y0 + excl;
         J.out_key_offsets[s0 + i] = o;
         J.out_values[s0 + i] = r.cnt;
         if (r.len <= 16u) {
           // the key is the big-endian prefix itself
-          for (uint32_t b = 0; b < r.len; ++b) J.out_key_bytes[o + b] = (uint8_t)(r.p[b >> 2] >> (24 - 8 * (b & 3)));
+#pragma unroll
+          for (uint32_t b = 0; b < 16u; ++b)
+            if (b < r.len) J.out_key_bytes[o + b] = (uint8_t)(r.p[b >> 2] >> (24 - 8 * (b & 3)));
         } else {
           for (uint32_t b = 0; b < r.len; ++b) J.out_key_bytes[o + b] = J.in[r.off + b];
         }
@@ -878,7 +1041,7 @@ hipError_t words_enqueue_map(const WordsLaunch& L, hipStream_t s) {
 }
 
 hipError_t words_enqueue_reduce(const WordsLaunch& L, hipStream_t s) {
-  const uint64_t tiles = (L.total_slots + kCompactThreads - 1) / kCompactThreads;
+  const uint64_t tiles = (L.total_slots + kCompactSlots - 1) / kCompactSlots;
   const uint32_t cgrid = (uint32_t)(tiles < 4096 ? tiles : 4096);
   hipLaunchKernelGGL(k_words_compact, dim3(cgrid ? cgrid : 1), dim3(kCompactThreads), 0, s, L.jobs, L.n_jobs, L.total_slots);
   hipLaunchKernelGGL(k_sort_plan, dim3(1), dim3(64), 0, s, L.jobs, L.n_jobs, L.totals);
