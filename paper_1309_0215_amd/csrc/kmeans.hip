@@ -326,23 +326,60 @@ __global__ void k_km_zero(double* __restrict__ a, uint64_t na, uint32_t* __restr
 }
 
 // Sum the G partials in a fixed order (deterministic), write float32 sums,
-// counts and new centroids (old centroid for an empty cluster).
-__global__ __launch_bounds__(256) void k_km_final(const double* __restrict__ part_sum, const uint32_t* __restrict__ part_cnt,
-                                                  uint32_t G, uint32_t k, uint32_t d, const float* __restrict__ C,
-                                                  float* __restrict__ sums, uint32_t* __restrict__ counts,
-                                                  float* __restrict__ cent) {
+// counts and new centroids (old centroid for an empty cluster). Workgroup =
+// 64 consecutive (cluster, dim) entries x 16 waves; wave w adds partials
+// g = w, w + 16, ... (loads unrolled, in flight together), then the 16 wave
+// sums are added in wave order. The same split for every launch keeps the
+// result bit-identical from run to run.
+constexpr int kFinalWaves = 16;
+
+__global__ __launch_bounds__(kFinalWaves * kWave) void k_km_final(const double* __restrict__ part_sum,
+                                                                  const uint32_t* __restrict__ part_cnt, uint32_t G,
+                                                                  uint32_t k, uint32_t d, const float* __restrict__ C,
+                                                                  float* __restrict__ sums, uint32_t* __restrict__ counts,
+                                                                  float* __restrict__ cent) {
+  __shared__ double ws[kFinalWaves][kWave];
+  __shared__ unsigned long long wn[kFinalWaves][kWave];
   const uint64_t kd = (uint64_t)k * d;
-  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < kd; i += (uint64_t)gridDim.x * blockDim.x) {
+  const uint32_t w = threadIdx.x / kWave, lane = lane_id();
+  const uint64_t i = (uint64_t)blockIdx.x * kWave + lane;
+  double s = 0.0;
+  unsigned long long n = 0;
+  if (i < kd) {
     const uint32_t j = (uint32_t)(i / d);
-    double s = 0.0;
-    uint64_t n = 0;
-    for (uint32_t g = 0; g < G; ++g) {
+    uint32_t g = w;
+    for (; g + 3 * kFinalWaves < G; g += 4 * kFinalWaves) {
+      const double a0 = part_sum[(uint64_t)g * kd + i], a1 = part_sum[(uint64_t)(g + kFinalWaves) * kd + i];
+      const double a2 = part_sum[(uint64_t)(g + 2 * kFinalWaves) * kd + i];
+      const double a3 = part_sum[(uint64_t)(g + 3 * kFinalWaves) * kd + i];
+      const uint32_t c0 = part_cnt[(uint64_t)g * k + j], c1 = part_cnt[(uint64_t)(g + kFinalWaves) * k + j];
+      const uint32_t c2 = part_cnt[(uint64_t)(g + 2 * kFinalWaves) * k + j];
+      const uint32_t c3 = part_cnt[(uint64_t)(g + 3 * kFinalWaves) * k + j];
+      s += a0;
+      s += a1;
+      s += a2;
+      s += a3;
+      n += (unsigned long long)c0 + c1 + c2 + c3;
+    }
+    for (; g < G; g += kFinalWaves) {
       s += part_sum[(uint64_t)g * kd + i];
       n += part_cnt[(uint64_t)g * k + j];
     }
-    if (sums) sums[i] = (float)s;
-    if (cent) cent[i] = n ? (float)(s / (double)n) : C[i];
-    if (counts && i % d == 0) counts[j] = (uint32_t)n;
+  }
+  ws[w][lane] = s;
+  wn[w][lane] = n;
+  __syncthreads();
+  if (w == 0 && i < kd) {
+    double t = 0.0;
+    unsigned long long c = 0;
+    for (int q = 0; q < kFinalWaves; ++q) {
+      t += ws[q][lane];
+      c += wn[q][lane];
+    }
+    const uint32_t j = (uint32_t)(i / d);
+    if (sums) sums[i] = (float)t;
+    if (cent) cent[i] = c ? (float)(t / (double)c) : C[i];
+    if (counts && i % d == 0) counts[j] = (uint32_t)c;
   }
 }
 
@@ -360,7 +397,7 @@ hipError_t km_enqueue(const KmLaunch& L, hipStream_t s, hipEvent_t map0, hipEven
   }
   if (map1) (void)hipEventRecord(map1, s);
   const uint64_t kd = (uint64_t)L.k * L.d;
-  hipLaunchKernelGGL(k_km_final, dim3((uint32_t)((kd + 255) / 256)), dim3(256), 0, s, L.part_sum, L.part_cnt,
+  hipLaunchKernelGGL(k_km_final, dim3((uint32_t)((kd + kWave - 1) / kWave)), dim3(kFinalWaves * kWave), 0, s, L.part_sum, L.part_cnt,
                      L.mfma ? L.G : 1u, L.k, L.d, L.C, L.sums, L.counts, L.cent);
   return hipGetLastError();
 }
