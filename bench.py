@@ -182,6 +182,30 @@ def bench_selector(torch, n_jobs=200):
             "trained_on": "1,500 of 2,000 seeded jobs, sizes 1-16 MiB (measured by the runtime on this GPU model)"}
 
 
+def bench_hist16m(torch, steps=5):
+    """The paper's Histogram: 2^28 uint32 keys over 2^24 possible keys, COUNT.
+
+    The rule picks the global array (one array, atomics); the hash table and
+    the sort are timed on the same input for comparison."""
+    import gen
+    from paper_1309_0215_amd import Job
+    n, R = 1 << 28, 1 << 24
+    keys = gen.uniform_keys(20, n, R)
+    kt = torch.from_numpy(keys.view("int32")).to("cuda:0")
+    del keys
+    res = {"elements": n, "key_range": R, "bytes": 4 * n}
+    for name, strat in (("rule", 0), ("hash", 4), ("sort", 5)):
+        job = Job(device=0, strategy=strat, timing=1)
+        ms, outs = time_steps(lambda: job.u32(kt, key_range=R).stats, steps, 1, torch)
+        map_ms = sum(o["map_ms"] for o in outs) / len(outs)
+        res[name] = {"strategy_used": int(outs[-1]["strategy_used"]), "ms_per_step": ms,
+                     "GBps": 4 * n / (ms * 1e-3) / 1e9, "elements_per_s": n / (ms * 1e-3),
+                     "map_ms": map_ms, "map_kernel_GBps": 4 * n / (map_ms * 1e-3) / 1e9}
+        del job
+    del kt
+    return res
+
+
 def bench_copy(torch, steps=5):
     """A plain 1 GiB device-to-device copy: the reference whose HBM counters scale the kernels' counters."""
     n = 1 << 30
@@ -241,7 +265,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--apps", default="rgb,words8,words512,kmeans,batched,selector")
+    ap.add_argument("--apps", default="rgb,words8,words512,kmeans,hist16m,batched,selector")
     ap.add_argument("--no-cpu", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -278,6 +302,11 @@ def main():
         log(f"selector: batched+learned {sl['batched_learned_jobs_per_s']:.0f} jobs/s vs plain rule "
             f"{sl['plain_rule_jobs_per_s']:.0f} jobs/s")
 
+    if "hist16m" in apps:
+        h = bench_hist16m(torch)
+        per_app["histogram_2p24_keys_2p28_elements"] = h
+        log(f"histogram 2^24 keys: rule {h['rule']['GBps']:.1f} GB/s, hash {h['hash']['GBps']:.1f} GB/s, "
+            f"sort {h['sort']['GBps']:.1f} GB/s")
     if "copy" in apps:
         cp = bench_copy(torch)
         per_app["copy_1GiB"] = cp

@@ -41,6 +41,7 @@ _STREAM_KM_CENTRES = 6
 _STREAM_KM_POINTS = 7
 _STREAM_U32 = 8
 _STREAM_JOBS = 9
+_STREAM_UNIFORM = 10
 
 
 def _rng(seed: int, stream: int, chunk: int = 0) -> np.random.Generator:
@@ -229,6 +230,21 @@ def u32_keys(seed: int, n: int, C: int, s: float, with_values: bool = False,
     with _cf.ThreadPoolExecutor(_threads()) as ex:
         list(ex.map(work, range(nch)))
     return keys, vals
+
+
+def uniform_keys(seed: int, n: int, C: int) -> np.ndarray:
+    """n uint32 keys drawn uniformly from [0, C) (the large-range histogram input)."""
+    keys = np.empty(n, np.uint32)
+    nch = (n + CHUNK - 1) // CHUNK
+
+    def work(c):
+        lo = c * CHUNK
+        hi = min(n, lo + CHUNK)
+        keys[lo:hi] = _rng(seed, _STREAM_UNIFORM, c).integers(0, C, size=hi - lo, dtype=np.uint32)
+
+    with _cf.ThreadPoolExecutor(_threads()) as ex:
+        list(ex.map(work, range(nch)))
+    return keys
 
 
 def interleave_kv(keys: np.ndarray, vals: np.ndarray) -> np.ndarray:

@@ -758,6 +758,16 @@ mr_status run_u32(mr_job* job, mr_map_kind kind, mr_reduce_op op, const void* d_
       o_cp = c.take(4ull * L.G * key_range);
       o_vp = c.take((o == 1 ? 8ull : 4ull) * L.G * key_range);
     }
+    // a large array counted by key-range partitions instead of atomics
+    const PartPlan pp = part_plan(n, key_range);
+    const bool parts = strat == MR_STRAT_GLOBAL_ARRAY && o == MR_REDUCE_COUNT && pp.usable;
+    uint64_t o_ph = 0, o_ps = 0, o_pt = 0, o_pk = 0;
+    if (parts) {
+      o_ph = c.take(4 * pp.H);
+      o_ps = c.take(4ull * pp.sb + 4);
+      o_pt = c.take(8);
+      o_pk = c.take(2 * n);
+    }
     st = scratch(c.off);
     if (st != MR_OK) return st;
     uint8_t* sc = static_cast<uint8_t*>(job->int_scratch);
@@ -767,6 +777,10 @@ mr_status run_u32(mr_job* job, mr_map_kind kind, mr_reduce_op op, const void* d_
       L.cnt_part = reinterpret_cast<uint32_t*>(sc + o_cp);
       L.val_part = sc + o_vp;
       MR_HIP(int_enqueue_lds_array(L, job->stream));
+    } else if (parts) {
+      MR_HIP(int_enqueue_global_array_parts(L, pp, reinterpret_cast<uint32_t*>(sc + o_ph), reinterpret_cast<uint32_t*>(sc + o_ps),
+                                            reinterpret_cast<unsigned long long*>(sc + o_pt),
+                                            reinterpret_cast<uint16_t*>(sc + o_pk), job->stream));
     } else {
       MR_HIP(int_enqueue_global_array(L, job->stream));
     }

@@ -190,6 +190,161 @@ __global__ __launch_bounds__(256) void k_global_array(IntIn in, uint32_t R, uint
 }
 
 // ----------------------------------------------------------------------------
+// global array over a large range, filled by key-range partitions (COUNT)
+//
+// Device-scope atomics run far below the load rate, so a large array is not
+// updated element by element. Instead: count the elements of every 2^14-key
+// range per tile, scan, scatter each element's low 14 bits into its range's
+// segment, then one workgroup per range counts its segment in an LDS array
+// and writes the range's counts once. Every array entry is written exactly
+// once; no global atomics on the array.
+// ----------------------------------------------------------------------------
+constexpr uint32_t kPartBits = 15;
+constexpr uint32_t kPartKeys = 1u << kPartBits;  // keys per range: LDS counters of one workgroup (128 KB)
+constexpr uint32_t kMaxParts = 2048;             // ranges (key range up to 2^26)
+constexpr uint32_t kPartTile = 32768;            // elements per tile of the count and scatter passes
+constexpr uint32_t kPartThreads = 1024;
+
+// Element i of a tile: keys are read 4 at a time (one 16-byte load) when the
+// input is plain keys; pairs are read one by one.
+template <typename F>
+MR_DEV void for_tile_keys(const IntIn& in, uint64_t base, F&& f) {
+  if (!in.kv && ((uintptr_t)in.p & 15u) == 0) {
+    const uint64_t end = base + kPartTile < in.n ? base + kPartTile : in.n;
+    const uint64_t nv = end > base ? (end - base) / 4 : 0;  // whole vectors
+    const uint4* v = reinterpret_cast<const uint4*>(in.p + base);
+    for (uint64_t q = threadIdx.x; q < nv; q += blockDim.x) {
+      const uint4 x = v[q];
+      f(x.x);
+      f(x.y);
+      f(x.z);
+      f(x.w);
+    }
+    for (uint64_t i = base + nv * 4 + threadIdx.x; i < end; i += blockDim.x) f(in.p[i]);
+  } else {
+    for (uint32_t q = threadIdx.x; q < kPartTile; q += blockDim.x) {
+      const uint64_t i = base + q;
+      if (i >= in.n) break;
+      uint32_t k, v;
+      load_elem(in, i, k, v);
+      f(k);
+    }
+  }
+}
+
+__global__ __launch_bounds__(kPartThreads) void k_part_count(IntIn in, uint64_t R, uint32_t P, uint32_t n_tiles,
+                                                             uint32_t* __restrict__ hist /* [P][n_tiles] */,
+                                                             uint32_t* __restrict__ flags) {
+  __shared__ uint32_t h[kMaxParts];
+  for (uint32_t p = threadIdx.x; p < P; p += blockDim.x) h[p] = 0;
+  __syncthreads();
+  bool bad = false;
+  for_tile_keys(in, (uint64_t)blockIdx.x * kPartTile, [&](uint32_t k) {
+    if (k < R) atomicAdd(&h[k >> kPartBits], 1u);
+    else bad = true;
+  });
+  __syncthreads();
+  for (uint32_t p = threadIdx.x; p < P; p += blockDim.x) hist[(uint64_t)p * n_tiles + blockIdx.x] = h[p];
+  if (bad) atomicOr(flags, kFlagBadInput);
+}
+
+// Each tile is ordered by range in LDS first; then each wave writes whole
+// runs (one range's elements of the tile) as contiguous 2-byte entries.
+__global__ __launch_bounds__(kPartThreads) void k_part_scatter(IntIn in, uint64_t R, uint32_t P, uint32_t n_tiles,
+                                                               const uint32_t* __restrict__ offs /* scanned hist */,
+                                                               const unsigned long long* __restrict__ total,
+                                                               uint16_t* __restrict__ part) {
+  __shared__ uint32_t lbase[kMaxParts + 1];  // start of each range's run in the staged tile (and the end)
+  __shared__ uint32_t lpos[kMaxParts];       // next free place of each range's run
+  __shared__ uint16_t sk[kPartTile];         // staged low bits, ordered by range
+  __shared__ uint32_t wsum[kPartThreads / kWave];
+  const uint32_t t = blockIdx.x;
+  // this tile's count of range p, from the scanned counts (range-major, tile-minor)
+  auto tile_count = [&](uint32_t p) -> uint32_t {
+    const uint64_t at = (uint64_t)p * n_tiles + t;
+    const uint64_t next = at + 1 < (uint64_t)P * n_tiles ? (uint64_t)offs[at + 1] : *total;
+    return (uint32_t)(next - offs[at]);
+  };
+  // exclusive scan of the tile's range counts (P <= 2048: 2 per thread)
+  constexpr uint32_t kPer = kMaxParts / kPartThreads;
+  uint32_t c[kPer], sum = 0;
+#pragma unroll
+  for (uint32_t q = 0; q < kPer; ++q) {
+    const uint32_t p = threadIdx.x * kPer + q;
+    c[q] = p < P ? tile_count(p) : 0u;
+    sum += c[q];
+  }
+  const uint32_t lane = lane_id(), wv = threadIdx.x / kWave;
+  uint32_t incl = sum;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const uint32_t y = (uint32_t)__shfl_up((int)incl, o);
+    if (lane >= (uint32_t)o) incl += y;
+  }
+  if (lane == kWave - 1) wsum[wv] = incl;
+  __syncthreads();
+  uint32_t pre = 0, m = 0;
+  for (uint32_t w = 0; w < kPartThreads / kWave; ++w) {
+    if (w < wv) pre += wsum[w];
+    m += wsum[w];
+  }
+  uint32_t run = pre + incl - sum;
+#pragma unroll
+  for (uint32_t q = 0; q < kPer; ++q) {
+    const uint32_t p = threadIdx.x * kPer + q;
+    if (p < P) {
+      lbase[p] = run;
+      lpos[p] = run;
+    }
+    run += c[q];
+  }
+  if (threadIdx.x == 0) lbase[P] = m;
+  __syncthreads();
+  for_tile_keys(in, (uint64_t)t * kPartTile, [&](uint32_t k) {
+    if (k < R) sk[atomicAdd(&lpos[k >> kPartBits], 1u)] = (uint16_t)(k & (kPartKeys - 1));
+  });
+  __syncthreads();
+  for (uint32_t p = wv; p < P; p += kPartThreads / kWave) {
+    const uint32_t b0 = lbase[p], b1 = lbase[p + 1];
+    uint16_t* dst = part + offs[(uint64_t)p * n_tiles + t];
+    for (uint32_t j = b0 + lane; j < b1; j += kWave) dst[j - b0] = sk[j];
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_part_fill(const uint16_t* __restrict__ part, const uint32_t* __restrict__ offs,
+                                                    const unsigned long long* __restrict__ total, uint32_t P,
+                                                    uint32_t n_tiles, uint64_t R, uint32_t* __restrict__ dcnt) {
+  __shared__ uint32_t c[kPartKeys];
+  const uint32_t p = blockIdx.x;
+  for (uint32_t i = threadIdx.x; i < kPartKeys; i += blockDim.x) c[i] = 0;
+  __syncthreads();
+  const uint64_t start = offs[(uint64_t)p * n_tiles];
+  const uint64_t end = p + 1 < P ? offs[(uint64_t)(p + 1) * n_tiles] : *total;
+  // 8 entries per 16-byte load over the aligned middle, single entries at the ends
+  const uint64_t a0 = (start + 7) & ~7ull, a1 = end & ~7ull;
+  if (a0 < a1) {
+    const uint4* v = reinterpret_cast<const uint4*>(part + a0);
+    for (uint64_t q = threadIdx.x; q < (a1 - a0) / 8; q += blockDim.x) {
+      const uint4 x = v[q];
+      const uint32_t w[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        atomicAdd(&c[w[e] & 0xFFFFu], 1u);
+        atomicAdd(&c[w[e] >> 16], 1u);
+      }
+    }
+    for (uint64_t j = start + threadIdx.x; j < a0; j += blockDim.x) atomicAdd(&c[part[j]], 1u);
+    for (uint64_t j = a1 + threadIdx.x; j < end; j += blockDim.x) atomicAdd(&c[part[j]], 1u);
+  } else {
+    for (uint64_t j = start + threadIdx.x; j < end; j += blockDim.x) atomicAdd(&c[part[j]], 1u);
+  }
+  __syncthreads();
+  const uint64_t key0 = (uint64_t)p * kPartKeys;
+  const uint64_t nk = R - key0 < kPartKeys ? R - key0 : kPartKeys;
+  for (uint32_t i = threadIdx.x; i < nk; i += blockDim.x) dcnt[key0 + i] = c[i];
+}
+
+// ----------------------------------------------------------------------------
 // ordered compaction of dense arrays: keys with count > 0, ascending
 // ----------------------------------------------------------------------------
 constexpr uint32_t kCompTile = 2048;  // keys per block (256 threads x 8)
@@ -742,6 +897,29 @@ hipError_t int_enqueue_global_array(const IntLaunch& L, hipStream_t s) {
     case 2: hipLaunchKernelGGL(k_global_array<2>, dim3(g), dim3(256), 0, s, in, L.R, L.dcnt, L.dval, L.flags); break;
     case 3: hipLaunchKernelGGL(k_global_array<3>, dim3(g), dim3(256), 0, s, in, L.R, L.dcnt, L.dval, L.flags); break;
   }
+  return hipGetLastError();
+}
+
+// Layout of the partitioned fill's scratch for n elements over range R.
+PartPlan part_plan(uint64_t n, uint64_t R) {
+  PartPlan pp{};
+  pp.P = (uint32_t)((R + kPartKeys - 1) / kPartKeys);
+  pp.n_tiles = (uint32_t)((n + kPartTile - 1) / kPartTile);
+  pp.H = (uint64_t)pp.P * pp.n_tiles;
+  pp.sb = (uint32_t)((pp.H + kScanTile - 1) / kScanTile);
+  pp.usable = R > kPartKeys && pp.P <= kMaxParts && n >= (1ull << 20) && n < (1ull << 32);
+  return pp;
+}
+
+hipError_t int_enqueue_global_array_parts(const IntLaunch& L, const PartPlan& pp, uint32_t* hist, uint32_t* scan_sums,
+                                          unsigned long long* total, uint16_t* part, hipStream_t s) {
+  const IntIn in{L.in, L.n, L.kv};
+  hipLaunchKernelGGL(k_part_count, dim3(pp.n_tiles), dim3(kPartThreads), 0, s, in, L.R, pp.P, pp.n_tiles, hist, L.flags);
+  hipLaunchKernelGGL(k_scan_blocks, dim3(pp.sb), dim3(256), 0, s, hist, pp.H, scan_sums);
+  hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, s, scan_sums, pp.sb, total);
+  hipLaunchKernelGGL(k_scan_apply, dim3(pp.sb), dim3(256), 0, s, hist, pp.H, scan_sums);
+  hipLaunchKernelGGL(k_part_scatter, dim3(pp.n_tiles), dim3(kPartThreads), 0, s, in, L.R, pp.P, pp.n_tiles, hist, total, part);
+  hipLaunchKernelGGL(k_part_fill, dim3(pp.P), dim3(1024), 0, s, part, hist, total, pp.P, pp.n_tiles, L.R, L.dcnt);
   return hipGetLastError();
 }
 

@@ -1,0 +1,93 @@
+"""GPU parity of the large-range histogram (the paper's Histogram workload:
+2^24 possible keys, 2^28 uint32 input elements, reduced into one global array
+with atomics instead of per-worker local arrays, Section III-E).
+
+* 2^22 elements over 2^24 keys: every output (key, count) against the CPU
+  oracle, with the rule's container (global array) and with the hash table
+  and the sort forced.
+* The full 2^28 elements: the oracle's counts for 4096 sampled keys (the
+  oracle run on the elements holding those keys), the count total, and the
+  ordering and range of the output keys.
+"""
+import numpy as np
+import pytest
+
+import gen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+R = 1 << 24
+GLOBAL_ARRAY, HASH, SORT = 3, 4, 5
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    return t
+
+
+def _run(torch, strategy, keys):
+    from paper_1309_0215_amd import Job
+    kt = torch.from_numpy(keys.view(np.int32)).to("cuda:0")
+    res = Job(device=0, strategy=strategy).u32(kt, key_range=R)
+    del kt
+    return res
+
+
+@pytest.mark.parametrize("strategy", [0, HASH, SORT])
+def test_2p22_elements_every_key(torch, strategy):
+    keys = gen.uniform_keys(21, 1 << 22, R)
+    res = _run(torch, strategy, keys)
+    assert res.stats["strategy_used"] == (GLOBAL_ARRAY if strategy == 0 else strategy)
+    ek, ev = oracle.u32(keys)
+    assert np.array_equal(res.keys.cpu().numpy().view(np.uint32), ek)
+    assert np.array_equal(res.values.cpu().numpy().view(np.uint32).astype(np.uint64), ev)
+
+
+def test_full_2p28_elements_sampled():
+    import torch
+    n = 1 << 28
+    keys = gen.uniform_keys(22, n, R)
+    res = _run(torch, 0, keys)
+    assert res.stats["strategy_used"] == GLOBAL_ARRAY
+    gk = res.keys.cpu().numpy().view(np.uint32)
+    gv = res.values.cpu().numpy().view(np.uint32).astype(np.uint64)
+    assert int(gv.sum()) == n
+    assert np.all(gk[1:] > gk[:-1]) and int(gk[-1]) < R and np.all(gv > 0)
+    # the oracle on the elements whose key is one of 4096 sampled keys
+    sample = np.random.default_rng(23).choice(R, size=4096, replace=False).astype(np.uint32)
+    member = np.zeros(R, bool)
+    member[sample] = True
+    ek, ev = oracle.u32(keys[member[keys]])
+    pos = np.searchsorted(gk, ek)
+    assert np.all(pos < len(gk)) and np.array_equal(gk[pos], ek)
+    assert np.array_equal(gv[pos], ev)
+    # sampled keys the oracle did not see do not appear in the output either
+    absent = np.setdiff1d(sample, ek)
+    p2 = np.searchsorted(gk, absent)
+    assert not np.any((p2 < len(gk)) & (gk[np.minimum(p2, len(gk) - 1)] == absent))
+
+
+def test_key_outside_the_range_is_rejected(torch):
+    from paper_1309_0215_amd import Job, MRError
+    keys = gen.uniform_keys(24, 1 << 21, R)
+    keys[123457] = R  # one key at the declared range
+    kt = torch.from_numpy(keys.view(np.int32)).to("cuda:0")
+    with pytest.raises(MRError) as e:
+        Job(device=0).u32(kt, key_range=R)
+    assert e.value.status == -1
+
+
+def test_pairs_count_and_ragged_range(torch):
+    """(key, value) pairs with COUNT, and a range that is not a multiple of 2^14."""
+    from paper_1309_0215_amd import Job
+    Rr = (1 << 20) + 12345
+    keys = gen.uniform_keys(25, (1 << 20) + 77, Rr)
+    vals = np.arange(len(keys), dtype=np.uint32)
+    d = lambda a: torch.from_numpy(a.view(np.int32)).to("cuda:0")  # noqa: E731
+    res = Job(device=0).u32(d(keys), d(vals), op=0, key_range=Rr)
+    assert res.stats["strategy_used"] == GLOBAL_ARRAY
+    ek, ev = oracle.u32(keys)
+    assert np.array_equal(res.keys.cpu().numpy().view(np.uint32), ek)
+    assert np.array_equal(res.values.cpu().numpy().view(np.uint32).astype(np.uint64), ev)
