@@ -1017,7 +1017,9 @@ namespace {
 // +0, +16, +32, +48), [128, 128 + 5252) parameters.
 constexpr uint64_t kSelNorm = 64;
 constexpr uint64_t kSelParams = 128;
-constexpr uint64_t kSelFloats = kSelParams + MR_MLP_PARAMS;
+constexpr uint64_t kSelState = (kSelParams + MR_MLP_PARAMS + 63) / 64 * 64;  // feature sampling state (floats offset)
+
+uint64_t sel_floats() { return kSelState + (feature_state_bytes() + 3) / 4; }
 
 mr_status sel_scratch(mr_job* job, uint64_t floats) {
   return int_ensure(job, &job->sel_dev, &job->sel_dev_floats, floats, 4, -1);
@@ -1041,11 +1043,11 @@ extern "C" mr_status mr_job_features(mr_job* job, mr_map_kind kind, mr_reduce_op
   if (fk < 0) return fail(MR_ERR_UNSUPPORTED, "features exist for word and integer-key jobs");
   if (fk > 0 && (uintptr_t)d_input % 4) return fail(MR_ERR_INVALID_ARG, "integer input must be 4-byte aligned");
   ScopedDevice sd(job->device);
-  mr_status st = sel_scratch(job, kSelFloats);
+  mr_status st = sel_scratch(job, sel_floats());
   if (st != MR_OK) return st;
   float* d = static_cast<float*>(job->sel_dev);
   MR_HIP(features_enqueue(static_cast<const uint8_t*>(d_input), input_bytes, fk, (int)op, key_range,
-                          (uint32_t)kLdsArrayBudget, d, job->stream));
+                          (uint32_t)kLdsArrayBudget, d, d + kSelState, job->stream));
   MR_HIP(hipMemcpyAsync(feats, d, 4 * MR_N_FEATURES, hipMemcpyDeviceToHost, job->stream));
   MR_HIP(hipStreamSynchronize(job->stream));
   return MR_OK;
@@ -1067,7 +1069,7 @@ extern "C" mr_status mr_selector_set(mr_job* job, const float* params, const flo
   job->sel_scale.assign(feat_scale, feat_scale + MR_N_FEATURES);
   job->sel_lo.assign(feat_lo, feat_lo + MR_N_FEATURES);
   job->sel_hi.assign(feat_hi, feat_hi + MR_N_FEATURES);
-  mr_status st = sel_scratch(job, kSelFloats);
+  mr_status st = sel_scratch(job, sel_floats());
   if (st != MR_OK) return st;
   float* dv = static_cast<float*>(job->sel_dev);
   MR_HIP(hipMemcpyAsync(dv + kSelParams, params, 4 * MR_MLP_PARAMS, hipMemcpyHostToDevice, job->stream));
@@ -1116,7 +1118,7 @@ mr_status learned_strategy(mr_job* job, mr_map_kind kind, mr_reduce_op op, const
   IntSmall* sm = static_cast<IntSmall*>(job->int_small);
   float* d = static_cast<float*>(job->sel_dev);
   MR_HIP(features_enqueue(static_cast<const uint8_t*>(d_input), bytes, fk, (int)op, R, (uint32_t)kLdsArrayBudget, d,
-                          job->stream));
+                          d + kSelState, job->stream));
   MR_HIP(select_enqueue(d, d + kSelNorm, d + kSelParams, feas, reinterpret_cast<int32_t*>(&sm->choice), job->stream));
   IntSmall hs;
   MR_HIP(hipMemcpyAsync(&hs, sm, sizeof hs, hipMemcpyDeviceToHost, job->stream));

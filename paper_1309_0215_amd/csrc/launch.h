@@ -119,8 +119,11 @@ struct KmLaunch {
 hipError_t km_enqueue(const KmLaunch& L, hipStream_t s, hipEvent_t map0, hipEvent_t map1);
 
 // Selector: features of a job and the network kernels.
+// Selector features: one sampling workgroup per window writes its window's
+// results into the state, and a finishing workgroup merges them.
+uint64_t feature_state_bytes();
 hipError_t features_enqueue(const uint8_t* in, uint64_t bytes, int kind, int op, uint64_t key_range, uint32_t lds_budget,
-                            float* feats, hipStream_t s);
+                            float* feats, void* state, hipStream_t s);
 hipError_t mlp_forward_enqueue(const float* P, const float* X, uint32_t B, float* H1, float* H2, float* Y, hipStream_t s);
 hipError_t select_enqueue(const float* feats, const float* norm, const float* P, uint32_t feas, int32_t* choice,
                           hipStream_t s);

@@ -15,7 +15,6 @@ namespace mr {
 constexpr int kFeatThreads = 1024;
 constexpr uint32_t kHllLog = 11;                    // 2048 registers
 constexpr uint32_t kHllM = 1u << kHllLog;
-constexpr uint32_t kFeatSlots = 8192;               // exact counts of sampled keys
 constexpr uint32_t kWindows = 32;
 constexpr uint32_t kWindowBytes = 4096;
 constexpr uint32_t kSegBlocks = kWindowBytes / 16 + 1;  // aligned 16-byte blocks covering one window
@@ -59,127 +58,51 @@ MR_DEV float hll_estimate(const uint32_t* reg, float* red) {
   return E;
 }
 
-MR_DEV void feat_insert(uint32_t* tk, uint32_t* tc, uint32_t key, uint32_t c) {
-  uint32_t s = (uint32_t)hash_u32(key) & (kFeatSlots - 1);
+// hist[bin] += 1 for every active lane, one atomic per distinct bin of the
+// wave (the bins of neighbouring slots are mostly equal; same-address LDS
+// atomics from many lanes would run one after another).
+MR_DEV void wave_hist_add(uint32_t* hist, uint32_t bin, bool act) {
+  while (true) {
+    const uint64_t m = __ballot(act);
+    if (!m) return;
+    const uint32_t lb = (uint32_t)__shfl((int)bin, (int)(__ffsll((unsigned long long)m) - 1));
+    const uint64_t eq = __ballot(act && bin == lb);
+    if (act && bin == lb) {
+      if (__popcll(eq & ((1ull << lane_id()) - 1)) == 0) atomicAdd(&hist[lb], (uint32_t)__popcll(eq));
+      act = false;
+    }
+  }
+}
+
+// Count c more of key in an exact count table of `slots` slots (a power of
+// two). At most half of the slots are claimed (used counts the claims): a key
+// without a slot by then is not counted, and the probe runs stay short.
+MR_DEV void feat_insert(uint32_t* tk, uint32_t* tc, uint32_t slots, uint32_t* used, uint32_t key, uint32_t c) {
+  uint32_t s = (uint32_t)hash_u32(key) & (slots - 1);
   for (int p = 0; p < 32; ++p) {
     uint32_t cur = tk[s];
-    if (cur == 0xFFFFFFFFu) cur = atomicCAS(&tk[s], 0xFFFFFFFFu, key);
-    if (cur == 0xFFFFFFFFu || cur == key) {
+    if (cur == 0xFFFFFFFFu) {
+      if (*used >= slots / 2) return;
+      cur = atomicCAS(&tk[s], 0xFFFFFFFFu, key);
+      if (cur == 0xFFFFFFFFu) {
+        atomicAdd(used, 1u);
+        atomicAdd(&tc[s], c);
+        return;
+      }
+    }
+    if (cur == key) {
       atomicAdd(&tc[s], c);
       return;
     }
-    s = (s + 1) & (kFeatSlots - 1);
+    s = (s + 1) & (slots - 1);
   }
 }
 
-// One sampled element: HyperLogLog registers and the exact count table.
-MR_DEV void feat_add(uint32_t* hll_all, uint32_t* hll_half, uint32_t* tk, uint32_t* tc, uint32_t key, uint64_t hh,
-                     bool in_half) {
-  hll_add(hll_all, hh);
-  if (in_half) hll_add(hll_half, hh);
-  feat_insert(tk, tc, key, 1u);
-}
-
-// kind: 0 words, 1 u32 keys, 2 u32 (key, value) pairs. One workgroup.
-__global__ __launch_bounds__(kFeatThreads) void k_features(const uint8_t* __restrict__ in, uint64_t bytes, int kind, int op,
-                                                           uint64_t key_range, uint32_t lds_budget, float* __restrict__ feats) {
-  __shared__ uint32_t hll_all[kHllM];
-  __shared__ uint32_t hll_half[kHllM];
-  __shared__ uint32_t tk[kFeatSlots];
-  __shared__ uint32_t tc[kFeatSlots];
-  __shared__ float red[2 * kFeatThreads / kWave];
-  __shared__ unsigned long long s_n, s_len, s_len2;
-  __shared__ uint32_t top[64];
-  __shared__ uint4 stage[kStageSegs * kSegBlocks];
-  for (uint32_t i = threadIdx.x; i < kHllM; i += blockDim.x) hll_all[i] = hll_half[i] = 0;
-  for (uint32_t i = threadIdx.x; i < kFeatSlots; i += blockDim.x) {
-    tk[i] = 0xFFFFFFFFu;
-    tc[i] = 0;
-  }
-  if (threadIdx.x == 0) s_n = s_len = s_len2 = 0;
-  __syncthreads();
-  const uint64_t esz = kind == 0 ? 1 : (kind == 1 ? 4 : 8);
-  const uint64_t n_elem = bytes / esz;
-  // segments of wel elements: kWindows evenly spaced windows, or the whole
-  // input in consecutive pieces when it is small
-  const uint64_t wel = kWindowBytes / esz;
-  const bool whole = n_elem <= (uint64_t)kWindows * wel;
-  const uint32_t nseg = whole ? (uint32_t)((n_elem + wel - 1) / wel) : kWindows;
-  unsigned long long my_n = 0, my_len = 0, my_len2 = 0;
-  const uint8_t* sb = reinterpret_cast<const uint8_t*>(stage);
-  for (uint32_t r0 = 0; r0 < nseg; r0 += kStageSegs) {
-    const uint32_t ns = (nseg - r0) < kStageSegs ? (nseg - r0) : kStageSegs;
-    __syncthreads();  // the previous round is done with the stage
-    // the 16-byte aligned blocks covering each segment, all loads in flight at once
-    for (uint32_t b = threadIdx.x; b < ns * kSegBlocks; b += blockDim.x) {
-      const uint32_t si = b / kSegBlocks, q = b % kSegBlocks;
-      const uint64_t e0 = whole ? (uint64_t)(r0 + si) * wel : (n_elem - wel) * (r0 + si) / (kWindows - 1);
-      const uint64_t blk = (((uint64_t)in + e0 * esz) & ~15ull) + 16ull * q;
-      uint4 v = make_uint4(0x20202020u, 0x20202020u, 0x20202020u, 0x20202020u);
-      // a block that holds a byte of the input lies inside its allocation
-      if (blk < (uint64_t)in + bytes && blk + 16 > (uint64_t)in) v = *reinterpret_cast<const uint4*>(blk);
-      stage[b] = v;
-    }
-    __syncthreads();
-    for (uint32_t si = 0; si < ns; ++si) {
-      const uint32_t w = r0 + si;
-      const uint64_t e0 = whole ? (uint64_t)w * wel : (n_elem - wel) * w / (kWindows - 1);
-      const uint64_t e1 = whole ? (e0 + wel < n_elem ? e0 + wel : n_elem) : e0 + wel;
-      const bool half_win = w < (kWindows + 1) / 2;
-      const uint64_t lo = ((uint64_t)in + e0 * esz) & ~15ull;
-      const uint8_t* seg = sb + (uint64_t)si * kSegBlocks * 16;
-      // byte p of the input: from the staged span when it holds it
-      auto byte_at = [&](uint64_t p) -> uint32_t {
-        const uint64_t a = (uint64_t)in + p;
-        return (a >= lo && a < lo + kSegBlocks * 16ull) ? seg[a - lo] : in[p];
-      };
-      for (uint64_t eb = e0; eb < e1; eb += blockDim.x) {  // uniform over the workgroup
-        const uint64_t e = eb + threadIdx.x;
-        bool act = false, in_half = false;
-        uint32_t key = 0;
-        uint64_t hh = 0;
-        if (e < e1) {
-          if (kind == 0) {
-            // a word starting at byte e (it may run past the segment)
-            if (!is_sep_byte(byte_at(e)) && (e == 0 || is_sep_byte(byte_at(e - 1)))) {
-              uint32_t hf = 2166136261u;
-              uint64_t q = e;
-              while (q < bytes && q - e < 256) {
-                const uint32_t c = byte_at(q);
-                if (is_sep_byte(c)) break;
-                hf = (hf ^ c) * 16777619u;
-                ++q;
-              }
-              const uint64_t len = q - e;
-              hh = hash_u32(hf ^ (uint32_t)(len * 0x9E3779B9u));
-              key = (uint32_t)hh;
-              act = true;
-              ++my_n;
-              my_len += len;
-              my_len2 += len * len;
-            }
-          } else {
-            const uint64_t a = (uint64_t)in + e * esz;
-            uint32_t k;
-            if (a >= lo && a + 4 <= lo + kSegBlocks * 16ull) k = *reinterpret_cast<const uint32_t*>(seg + (a - lo));
-            else k = *reinterpret_cast<const uint32_t*>(a);
-            hh = hash_u32(k);
-            key = k;
-            act = true;
-            ++my_n;
-          }
-          in_half = whole ? (e & 1) != 0 : half_win;
-        }
-        if (act) feat_add(hll_all, hll_half, tk, tc, key, hh, in_half);
-      }
-    }
-  }
-  atomicAdd(&s_n, my_n);
-  atomicAdd(&s_len, my_len);
-  atomicAdd(&s_len2, my_len2);
-  __syncthreads();
-  const float D_all = hll_estimate(hll_all, red);
-  const float D_half = hll_estimate(hll_half, red);
+// The 64 largest of the n counts tc[0, n) (LDS), in descending order, into
+// top[64] (LDS), padded as described below. Called by the whole workgroup;
+// n is a multiple of blockDim.x. (counts stay below 2^17: the sample holds
+// at most 64 Ki elements)
+MR_DEV void top64_of(const uint32_t* tc, uint32_t n, uint32_t* top) {
   // The 64 largest counts, exactly: radix-select the 64th largest value v64
   // with two histogram passes over the count bits (counts stay below 2^17:
   // the sample holds at most 64 Ki elements), then collect the counts above
@@ -198,9 +121,9 @@ __global__ __launch_bounds__(kFeatThreads) void k_features(const uint8_t* __rest
       s_v64 = 0;
     }
     __syncthreads();
-    for (uint32_t i = threadIdx.x; i < kFeatSlots; i += blockDim.x) {
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
       const uint32_t c = tc[i];
-      if (c) atomicAdd(&hist[min(c >> 9, 255u)], 1u);
+      wave_hist_add(hist, min(c >> 9, 255u), c != 0);
     }
     __syncthreads();
     if (threadIdx.x < kWave) {
@@ -235,9 +158,9 @@ __global__ __launch_bounds__(kFeatThreads) void k_features(const uint8_t* __rest
     if (b1 != 0xFFFFFFFFu) {
       for (uint32_t i = threadIdx.x; i < 512; i += blockDim.x) hist[i] = 0;
       __syncthreads();
-      for (uint32_t i = threadIdx.x; i < kFeatSlots; i += blockDim.x) {
+      for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
         const uint32_t c = tc[i];
-        if (c && min(c >> 9, 255u) == b1) atomicAdd(&hist[c & 511u], 1u);
+        wave_hist_add(hist, c & 511u, c && min(c >> 9, 255u) == b1);
       }
       __syncthreads();
       if (threadIdx.x < kWave) {
@@ -273,11 +196,19 @@ __global__ __launch_bounds__(kFeatThreads) void k_features(const uint8_t* __rest
     }
     __syncthreads();
     const uint32_t v64 = s_v64;
-    for (uint32_t i = threadIdx.x; i < kFeatSlots; i += blockDim.x) {
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
       const uint32_t c = tc[i];
-      if (c > v64) {
-        const uint32_t q = atomicAdd(&s_ngt, 1u);
-        if (q < 64) gt[q] = c;
+      // one place reservation per wave
+      const uint64_t m = __ballot(c > v64);
+      if (m) {
+        const uint32_t lane = lane_id();
+        uint32_t base = 0;
+        if (lane == (uint32_t)(__ffsll((unsigned long long)m) - 1)) base = atomicAdd(&s_ngt, (uint32_t)__popcll(m));
+        base = (uint32_t)__shfl((int)base, (int)(__ffsll((unsigned long long)m) - 1));
+        if (c > v64) {
+          const uint32_t q = base + (uint32_t)__popcll(m & ((1ull << lane) - 1));
+          if (q < 64) gt[q] = c;
+        }
       }
     }
     __syncthreads();
@@ -295,6 +226,267 @@ __global__ __launch_bounds__(kFeatThreads) void k_features(const uint8_t* __rest
     }
     __syncthreads();
   }
+}
+
+constexpr int kSampThreads = 256;
+constexpr uint32_t kLocalSlots = 2048;  // distinct keys of one window (at most 2048 elements)
+
+// Per-window results written by the sampling workgroups (every field is
+// rewritten on each call, so nothing needs clearing).
+struct FeatWindow {
+  uint8_t hll_all[kHllM];
+  uint8_t hll_half[kHllM];
+  uint32_t key[kLocalSlots];
+  uint32_t cnt[kLocalSlots];
+  uint32_t n_keys;
+  uint32_t pad;
+  unsigned long long n, len, len2;
+};
+
+// Geometry of the sample: kWindows evenly spaced windows of wel elements, or
+// the whole input in consecutive pieces of wel elements when it is small.
+struct Sample {
+  uint64_t esz, n_elem, wel;
+  bool whole;
+  uint32_t nseg;
+};
+
+MR_DEV Sample sample_of(uint64_t bytes, int kind) {
+  Sample S;
+  S.esz = kind == 0 ? 1 : (kind == 1 ? 4 : 8);
+  S.n_elem = bytes / S.esz;
+  S.wel = kWindowBytes / S.esz;
+  S.whole = S.n_elem <= (uint64_t)kWindows * S.wel;
+  S.nseg = S.whole ? (uint32_t)((S.n_elem + S.wel - 1) / S.wel) : kWindows;
+  return S;
+}
+
+// One workgroup per segment: its elements into LDS registers and counts,
+// written out as the window's registers, (key, count) list and sums.
+__global__ __launch_bounds__(kSampThreads) void k_feat_sample(const uint8_t* __restrict__ in, uint64_t bytes, int kind,
+                                                               FeatWindow* __restrict__ win) {
+  __shared__ uint32_t hll_all[kHllM];
+  __shared__ uint32_t hll_half[kHllM];
+  __shared__ uint32_t tk[kLocalSlots];
+  __shared__ uint32_t tc[kLocalSlots];
+  __shared__ uint4 stage[kSegBlocks];
+  __shared__ unsigned long long s_n, s_len, s_len2;
+  __shared__ uint32_t s_keys;
+  const Sample S = sample_of(bytes, kind);
+  const uint32_t w = blockIdx.x;
+  if (w >= S.nseg) return;
+  for (uint32_t i = threadIdx.x; i < kHllM; i += blockDim.x) hll_all[i] = hll_half[i] = 0;
+  for (uint32_t i = threadIdx.x; i < kLocalSlots; i += blockDim.x) {
+    tk[i] = 0xFFFFFFFFu;
+    tc[i] = 0;
+  }
+  if (threadIdx.x == 0) {
+    s_n = s_len = s_len2 = 0;
+    s_keys = 0;
+  }
+  const uint64_t esz = S.esz;
+  const uint64_t e0 = S.whole ? (uint64_t)w * S.wel : (S.n_elem - S.wel) * w / (kWindows - 1);
+  const uint64_t e1 = S.whole ? (e0 + S.wel < S.n_elem ? e0 + S.wel : S.n_elem) : e0 + S.wel;
+  const bool half_win = w < (kWindows + 1) / 2;
+  const uint64_t lo = ((uint64_t)in + e0 * esz) & ~15ull;
+  // the 16-byte aligned blocks covering the segment, all loads in flight at once
+  for (uint32_t q = threadIdx.x; q < kSegBlocks; q += blockDim.x) {
+    const uint64_t blk = lo + 16ull * q;
+    uint4 v = make_uint4(0x20202020u, 0x20202020u, 0x20202020u, 0x20202020u);
+    // a block that holds a byte of the input lies inside its allocation
+    if (blk < (uint64_t)in + bytes && blk + 16 > (uint64_t)in) v = *reinterpret_cast<const uint4*>(blk);
+    stage[q] = v;
+  }
+  __syncthreads();
+  const uint8_t* seg = reinterpret_cast<const uint8_t*>(stage);
+  // byte p of the input: from the staged span when it holds it
+  auto byte_at = [&](uint64_t p) -> uint32_t {
+    const uint64_t a = (uint64_t)in + p;
+    return (a >= lo && a < lo + kSegBlocks * 16ull) ? seg[a - lo] : in[p];
+  };
+  unsigned long long my_n = 0, my_len = 0, my_len2 = 0;
+  for (uint64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+    bool act = false;
+    uint32_t key = 0;
+    uint64_t hh = 0;
+    if (kind == 0) {
+      // a word starting at byte e (it may run past the segment)
+      if (!is_sep_byte(byte_at(e)) && (e == 0 || is_sep_byte(byte_at(e - 1)))) {
+        uint32_t hf = 2166136261u;
+        uint64_t q = e;
+        while (q < bytes && q - e < 256) {
+          const uint32_t c = byte_at(q);
+          if (is_sep_byte(c)) break;
+          hf = (hf ^ c) * 16777619u;
+          ++q;
+        }
+        const uint64_t len = q - e;
+        hh = hash_u32(hf ^ (uint32_t)(len * 0x9E3779B9u));
+        key = (uint32_t)hh;
+        act = true;
+        ++my_n;
+        my_len += len;
+        my_len2 += len * len;
+      }
+    } else {
+      const uint64_t a = (uint64_t)in + e * esz;
+      const uint32_t k = *reinterpret_cast<const uint32_t*>(seg + (a - lo));
+      hh = hash_u32(k);
+      key = k;
+      act = true;
+      ++my_n;
+    }
+    if (act) {
+      hll_add(hll_all, hh);
+      if (S.whole ? (e & 1) != 0 : half_win) hll_add(hll_half, hh);
+      uint32_t sl = (uint32_t)hash_u32(key) & (kLocalSlots - 1);
+      for (uint32_t p = 0; p < kLocalSlots; ++p) {
+        uint32_t cur = tk[sl];
+        if (cur == 0xFFFFFFFFu) cur = atomicCAS(&tk[sl], 0xFFFFFFFFu, key);
+        if (cur == 0xFFFFFFFFu || cur == key) {
+          atomicAdd(&tc[sl], 1u);
+          break;
+        }
+        sl = (sl + 1) & (kLocalSlots - 1);
+      }
+    }
+  }
+  if (my_n) atomicAdd(&s_n, my_n);
+  if (my_len) atomicAdd(&s_len, my_len);
+  if (my_len2) atomicAdd(&s_len2, my_len2);
+  __syncthreads();
+  FeatWindow& W = win[w];
+  for (uint32_t i = threadIdx.x; i < kHllM; i += blockDim.x) {
+    W.hll_all[i] = (uint8_t)hll_all[i];
+    W.hll_half[i] = (uint8_t)hll_half[i];
+  }
+  for (uint32_t i = threadIdx.x; i < kLocalSlots; i += blockDim.x) {
+    if (tc[i]) {
+      const uint32_t at = atomicAdd(&s_keys, 1u);
+      W.key[at] = tk[i];
+      W.cnt[at] = tc[i];
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    W.n_keys = s_keys;
+    W.n = s_n;
+    W.len = s_len;
+    W.len2 = s_len2;
+  }
+}
+
+constexpr uint32_t kMergeParts = 16;     // key partitions merged by separate workgroups
+constexpr uint32_t kMergeSlots = 4096;   // count table of one partition
+
+// Exact counts of the sampled keys, one workgroup per hash partition of the
+// keys (every occurrence of a key lands in the same partition): the windows'
+// (key, count) lists into an LDS table, then the partition's 64 largest
+// counts into cand[partition][64].
+__global__ __launch_bounds__(kFeatThreads) void k_feat_merge(uint64_t bytes, int kind, const FeatWindow* __restrict__ win,
+                                                              uint32_t* __restrict__ cand) {
+  __shared__ uint32_t tk[kMergeSlots];
+  __shared__ uint32_t tc[kMergeSlots];
+  __shared__ uint32_t s_first[kWindows + 1];  // first entry of each window in the concatenated lists
+  __shared__ uint32_t s_used;                 // claimed slots of the count table
+  __shared__ uint32_t top[64];
+  const Sample S = sample_of(bytes, kind);
+  for (uint32_t i = threadIdx.x; i < kMergeSlots; i += blockDim.x) {
+    tk[i] = 0xFFFFFFFFu;
+    tc[i] = 0;
+  }
+  if (threadIdx.x == 0) {
+    s_used = 0;
+    uint32_t acc = 0;
+    for (uint32_t w = 0; w < S.nseg; ++w) {
+      s_first[w] = acc;
+      acc += win[w].n_keys;
+    }
+    s_first[S.nseg] = acc;
+  }
+  __syncthreads();
+  const uint32_t total = s_first[S.nseg];
+  auto entry = [&](uint32_t i, uint32_t& k, uint32_t& c) {
+    uint32_t lo = 0, hi = S.nseg;  // last window w with s_first[w] <= i
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (s_first[mid] <= i) lo = mid; else hi = mid;
+    }
+    k = win[lo].key[i - s_first[lo]];
+    c = win[lo].cnt[i - s_first[lo]];
+  };
+  // 8 entries per thread loaded together (their loads in flight at once), then inserted
+  for (uint32_t i0 = 0; i0 < total; i0 += 8 * blockDim.x) {
+    uint32_t k[8], c[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const uint32_t i = i0 + u * blockDim.x + threadIdx.x;
+      k[u] = 0;
+      c[u] = 0;
+      if (i < total) entry(i, k[u], c[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (c[u] && (uint32_t)(hash_u32(k[u]) >> 60) == blockIdx.x) feat_insert(tk, tc, kMergeSlots, &s_used, k[u], c[u]);
+  }
+  __syncthreads();
+  top64_of(tc, kMergeSlots, top);
+  if (threadIdx.x < 64) cand[blockIdx.x * 64 + threadIdx.x] = top[threadIdx.x];
+}
+
+// Merges the windows' registers and sums and the partitions' largest counts,
+// then estimates, top-64 counts and the 12 features. One workgroup.
+__global__ __launch_bounds__(kFeatThreads) void k_feat_final(const uint8_t* __restrict__ in, uint64_t bytes, int kind, int op,
+                                                              uint64_t key_range, uint32_t lds_budget,
+                                                              const FeatWindow* __restrict__ win,
+                                                              const uint32_t* __restrict__ cand, float* __restrict__ feats) {
+  __shared__ uint32_t hll_all[kHllM];
+  __shared__ uint32_t hll_half[kHllM];
+  __shared__ uint32_t tc[kMergeParts * 64];  // the partitions' 64 largest counts
+  __shared__ float red[2 * kFeatThreads / kWave];
+  __shared__ unsigned long long s_n, s_len, s_len2;
+  __shared__ uint32_t top[64];
+  const Sample S = sample_of(bytes, kind);
+  const uint64_t esz = S.esz, n_elem = S.n_elem;
+  const bool whole = S.whole;
+  for (uint32_t i = threadIdx.x; i < kMergeParts * 64; i += blockDim.x) tc[i] = cand[i];
+  // register maxima: thread t takes word t of the two register arrays (4
+  // registers a word) across the windows, loads of 8 windows in flight
+  static_assert(2 * kHllM / 4 <= kFeatThreads, "one register word per thread");
+  if (threadIdx.x < 2 * kHllM / 4) {
+    const uint32_t t = threadIdx.x, half = t >= kHllM / 4, q = t % (kHllM / 4);
+    uint32_t m[4] = {0, 0, 0, 0};
+    for (uint32_t w0 = 0; w0 < S.nseg; w0 += 8) {
+      uint32_t v[8];
+#pragma unroll
+      for (uint32_t u = 0; u < 8; ++u) {
+        const uint32_t w = w0 + u;
+        v[u] = w < S.nseg ? reinterpret_cast<const uint32_t*>(half ? win[w].hll_half : win[w].hll_all)[q] : 0u;
+      }
+#pragma unroll
+      for (uint32_t u = 0; u < 8; ++u)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) m[b] = max(m[b], (v[u] >> (8 * b)) & 0xFFu);
+    }
+    uint32_t* dst = half ? hll_half : hll_all;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) dst[4 * q + b] = m[b];
+  }
+  if (threadIdx.x == 0) {
+    unsigned long long n = 0, l = 0, l2 = 0;
+    for (uint32_t w = 0; w < S.nseg; ++w) {
+      n += win[w].n;
+      l += win[w].len;
+      l2 += win[w].len2;
+    }
+    s_n = n;
+    s_len = l;
+    s_len2 = l2;
+  }
+  __syncthreads();
+  const float D_all = hll_estimate(hll_all, red);
+  const float D_half = hll_estimate(hll_half, red);
+  top64_of(tc, kMergeParts * 64, top);
   if (threadIdx.x >= kWave) return;
   // Zipf exponent: least-squares slope of log count against log rank over the top counts
   float sx = 0, sy = 0, sxx = 0, sxy = 0, m = 0, top64 = 0;
@@ -345,9 +537,19 @@ __global__ __launch_bounds__(kFeatThreads) void k_features(const uint8_t* __rest
   feats[11] = log2f(fmaxf(D_est * 32.f, 1.f) / (float)lds_budget);  // table bytes at load 1/2, 16-byte slots
 }
 
+uint64_t feature_state_bytes() { return sizeof(FeatWindow) * kWindows + 4ull * kMergeParts * 64; }
+
 hipError_t features_enqueue(const uint8_t* in, uint64_t bytes, int kind, int op, uint64_t key_range, uint32_t lds_budget,
-                            float* feats, hipStream_t s) {
-  hipLaunchKernelGGL(k_features, dim3(1), dim3(kFeatThreads), 0, s, in, bytes, kind, op, key_range, lds_budget, feats);
+                            float* feats, void* state, hipStream_t s) {
+  FeatWindow* win = static_cast<FeatWindow*>(state);
+  const uint64_t esz = kind == 0 ? 1 : (kind == 1 ? 4 : 8);
+  const uint64_t n_elem = bytes / esz, wel = kWindowBytes / esz;
+  const uint32_t nseg = n_elem <= (uint64_t)kWindows * wel ? (uint32_t)((n_elem + wel - 1) / wel) : kWindows;
+  uint32_t* cand = reinterpret_cast<uint32_t*>(win + kWindows);
+  if (nseg) hipLaunchKernelGGL(k_feat_sample, dim3(nseg), dim3(kSampThreads), 0, s, in, bytes, kind, win);
+  hipLaunchKernelGGL(k_feat_merge, dim3(kMergeParts), dim3(kFeatThreads), 0, s, bytes, kind, win, cand);
+  hipLaunchKernelGGL(k_feat_final, dim3(1), dim3(kFeatThreads), 0, s, in, bytes, kind, op, key_range, lds_budget, win, cand,
+                     feats);
   return hipGetLastError();
 }
 

@@ -368,7 +368,24 @@ __global__ __launch_bounds__(kMapThreads) void k_words_map(const WordJob* __rest
   int cur = -1;
   uint64_t vlo = 0, vhi = 0;
 
+  // This lane's chunk of tile t (and, for thread 0, the chunk before the
+  // tile): loaded one tile ahead, so that the loads of the next tile are in
+  // flight while the current one is processed.
+  auto load_tile = [&](uint64_t t, uint4& mine, uint4& before) {
+    const uint32_t jn = find_job(tile_base, n_jobs, t);
+    const WordJob& Jn = jobs[jn];
+    const uint64_t an0 = (uint64_t)Jn.in, an1 = an0 + Jn.n;
+    const uint64_t cn = (t - tile_base[jn]) * kMapTileChunks + threadIdx.x;
+    const uint64_t Bn = (Jn.chunk0 + cn) * 16;
+    mine = cn < Jn.n_chunks ? load_block(an0, an1, Bn) : spaces4();
+    if (threadIdx.x == 0) before = load_block(an0, an1, Bn - 16);
+  };
+  uint4 nx_mine = spaces4(), nx_before = spaces4();
+  if (t_begin < t_end) load_tile(t_begin, nx_mine, nx_before);
+
   for (uint64_t t = t_begin; t < t_end; ++t) {
+    const uint4 b0 = nx_mine, pre_chunk = nx_before;
+    if (t + 1 < t_end) load_tile(t + 1, nx_mine, nx_before);
     // every thread is done with the previous tile (its abort flag, LDS copy and lists)
     __syncthreads();
     const uint32_t j = find_job(tile_base, n_jobs, t);
@@ -412,25 +429,22 @@ __global__ __launch_bounds__(kMapThreads) void k_words_map(const WordJob* __rest
     // 1. the tile into LDS; this lane's chunk and the next one as a 32-byte window
     const uint64_t c = lt * kMapTileChunks + threadIdx.x;  // this lane's chunk
     const uint64_t B = (J.chunk0 + c) * 16;                 // its absolute address
-    const uint4 b0 = c < J.n_chunks ? load_block(a0, a1, B) : spaces4();
     stage[threadIdx.x] = b0;
     if (threadIdx.x < 2) {
       const uint64_t cx = lt * kMapTileChunks + kMapTileChunks + threadIdx.x;
       stage[kMapTileChunks + threadIdx.x] = cx < J.n_chunks ? load_block(a0, a1, (J.chunk0 + cx) * 16) : spaces4();
     }
-    // byte B - 1: the previous lane's chunk, or the previous tile's last chunk
-    uint32_t prev = (uint32_t)__shfl_up((int)((sep16(b0) >> 15) & 1u), 1);
-    if (lane == 0) {
-      const uint64_t pb = B - 1;
-      bool ps = true;
-      if (pb >= a0 + vlo && pb < a0 + vhi) {
-        const uint4 q = load_block(a0, a1, B - 16);
-        ps = (sep_mask4(q.w) >> 3) & 1u;
-      }
-      prev = ps ? 1u : 0u;
-    }
     __syncthreads();
     const uint4 b1 = stage[threadIdx.x + 1];
+    // byte B - 1: last byte of the previous chunk (a separator outside the valid range)
+    uint32_t prev = 1u;
+    {
+      const uint64_t pb = B - 1;
+      if (pb >= a0 + vlo && pb < a0 + vhi) {
+        const uint4 q = threadIdx.x ? stage[threadIdx.x - 1] : pre_chunk;
+        prev = (sep_mask4(q.w) >> 3) & 1u;
+      }
+    }
     const uint32_t valid = range_mask32((int64_t)(a0 + vlo) - (int64_t)B, (int64_t)(a0 + vhi) - (int64_t)B);
     const uint32_t sep = (sep16(b0) | (sep16(b1) << 16)) | ~valid;
     uint32_t bd = 0u;
