@@ -18,7 +18,6 @@ constexpr uint32_t kHllM = 1u << kHllLog;
 constexpr uint32_t kWindows = 32;
 constexpr uint32_t kWindowBytes = 4096;
 constexpr uint32_t kSegBlocks = kWindowBytes / 16 + 1;  // aligned 16-byte blocks covering one window
-constexpr uint32_t kStageSegs = 16;                     // windows staged in LDS per round
 
 MR_DEV void hll_add(uint32_t* reg, uint64_t h) {
   const uint32_t idx = (uint32_t)(h >> (64 - kHllLog));
