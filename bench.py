@@ -206,6 +206,23 @@ def bench_hist16m(torch, steps=5):
     return res
 
 
+def bench_bloom(torch, steps=10):
+    """The paper's Bloom Filter build: 30 million k-mers (k = 20) of synthetic
+    DNA, 7 hash positions each, into one array of 300 million bits."""
+    import gen
+    from paper_1309_0215_amd import Job
+    n, m, k, h = 30_000_019, 300_000_000, 20, 7
+    d = torch.from_numpy(gen.dna(20, n)).to("cuda:0")
+    job = Job(device=0, bloom_k=k, bloom_hashes=h)
+    ms, outs = time_steps(lambda: job.bloom(d, m)[1], steps, 2, torch)
+    kmers = int(outs[-1]["n_items"])
+    algo = n + m // 8  # input read once, filter written once
+    del d, job
+    return {"bytes": n, "bits": m, "k": k, "hashes": h, "kmers": kmers, "ms_per_step": ms,
+            "kmers_per_s": kmers / (ms * 1e-3), "input_GBps": n / (ms * 1e-3) / 1e9,
+            "algorithmic_GBps": algo / (ms * 1e-3) / 1e9}
+
+
 def bench_copy(torch, steps=5):
     """A plain 1 GiB device-to-device copy: the reference whose HBM counters scale the kernels' counters."""
     n = 1 << 30
@@ -265,7 +282,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--apps", default="rgb,words8,words512,kmeans,hist16m,batched,selector")
+    ap.add_argument("--apps", default="rgb,words8,words512,kmeans,hist16m,bloom,batched,selector")
     ap.add_argument("--no-cpu", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -307,6 +324,10 @@ def main():
         per_app["histogram_2p24_keys_2p28_elements"] = h
         log(f"histogram 2^24 keys: rule {h['rule']['GBps']:.1f} GB/s, hash {h['hash']['GBps']:.1f} GB/s, "
             f"sort {h['sort']['GBps']:.1f} GB/s")
+    if "bloom" in apps:
+        bl = bench_bloom(torch)
+        per_app["bloom_filter_30M_kmers_300M_bits"] = bl
+        log(f"bloom: {bl['ms_per_step']:.3f} ms, {bl['kmers_per_s'] / 1e9:.2f} G k-mers/s")
     if "copy" in apps:
         cp = bench_copy(torch)
         per_app["copy_1GiB"] = cp

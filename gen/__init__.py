@@ -21,6 +21,9 @@ Input recipes (the paper names the workloads but ships none of its data):
   component uniform, stored as float32.
 * u32 keys: Zipf ranks over C distinct keys mapped through a seeded
   bijection onto [0, C); optional u32 values.
+* dna: bases A, C, G, T uniform and independent; each position starts a run
+  of 'N' (an unknown base, as in assembled chromosomes) with probability
+  n_rate, of length uniform in [1, 200], cut at the end of its chunk.
 """
 from __future__ import annotations
 
@@ -42,6 +45,7 @@ _STREAM_KM_POINTS = 7
 _STREAM_U32 = 8
 _STREAM_JOBS = 9
 _STREAM_UNIFORM = 10
+_STREAM_DNA = 11
 
 
 def _rng(seed: int, stream: int, chunk: int = 0) -> np.random.Generator:
@@ -245,6 +249,30 @@ def uniform_keys(seed: int, n: int, C: int) -> np.ndarray:
     with _cf.ThreadPoolExecutor(_threads()) as ex:
         list(ex.map(work, range(nch)))
     return keys
+
+
+def _dna_chunk(seed: int, c: int, n: int, n_rate: float) -> np.ndarray:
+    rng = _rng(seed, _STREAM_DNA, c)
+    out = np.frombuffer(b"ACGT", np.uint8)[rng.integers(0, 4, size=n, dtype=np.uint8)]
+    starts = np.flatnonzero(rng.random(n) < n_rate)
+    lens = rng.integers(1, 201, size=len(starts))
+    for a, ln in zip(starts, lens):
+        out[a:a + ln] = ord("N")
+    return out
+
+
+def dna(seed: int, n: int, n_rate: float = 1e-5) -> np.ndarray:
+    """n DNA bytes (uint8): uniform A/C/G/T with occasional runs of N."""
+    out = np.empty(n, np.uint8)
+    chunks = [(c, c * CHUNK, min(n, (c + 1) * CHUNK)) for c in range((n + CHUNK - 1) // CHUNK)]
+
+    def work(t):
+        c, lo, hi = t
+        out[lo:hi] = _dna_chunk(seed, c, hi - lo, n_rate)
+
+    with _cf.ThreadPoolExecutor(_threads()) as ex:
+        list(ex.map(work, chunks))
+    return out
 
 
 def interleave_kv(keys: np.ndarray, vals: np.ndarray) -> np.ndarray:

@@ -69,7 +69,19 @@ typedef enum {
    * Output: assignments int32[n], per-cluster float32 sums [k][d], uint32
    * counts [k] and new centroids [k][d] (sum / count; an empty cluster keeps
    * its previous centroid). */
-  MR_MAP_KMEANS = 4
+  MR_MAP_KMEANS = 4,
+  /* Bloom filter build (benchmark application "Bloom Filter"). Input: DNA
+   * bytes. Every k-mer (bloom_k consecutive bytes, all of them A, C, G or T;
+   * a k-mer holding any other byte emits nothing) is packed two bits per
+   * base (A 0, C 1, G 2, T 3, first base in the highest bits) into v, and
+   * x = fmix64(v), the 64-bit finaliser of MurmurHash3. It sets the
+   * bloom_hashes bits g_i * m / 2^32 (integer division), i = 0, 1, ...,
+   * where g_i = (low32(x) + i * (high32(x) | 1)) mod 2^32 and m = key_range,
+   * the filter size in bits (1 <= m <= 2^29). Reduce: bitwise OR (op must be
+   * MR_REDUCE_COUNT, the only op accepted). Output: values = uint32
+   * words[ceil(m / 32)], bit b of the filter in bit b % 32 of word b / 32;
+   * cap_keys is the capacity in words and n_keys the words written. */
+  MR_MAP_BLOOM = 5
 } mr_map_kind;
 
 typedef enum { MR_REDUCE_COUNT = 0, MR_REDUCE_SUM = 1, MR_REDUCE_MIN = 2, MR_REDUCE_MAX = 3 } mr_reduce_op;
@@ -105,6 +117,9 @@ typedef struct {
   uint32_t km_d;
   uint32_t km_k;
   const float* km_centroids;
+  /* Bloom filter only: k-mer length (1..32, 0 = 20) and hash count (1..8, 0 = 7) */
+  uint32_t bloom_k;
+  uint32_t bloom_hashes;
 } mr_job_config;
 
 typedef struct {
@@ -126,6 +141,7 @@ typedef struct {
  *   RGB_HIST: values[768] (uint64)
  *   KMEANS:   assign[n] (int32), sums[k*d] (float32), counts[k] (uint32),
  *             centroids[k*d] (float32)
+ *   BLOOM:    values[cap_keys] (uint32 filter words)
  * On return n_keys and key_bytes_used hold the result sizes. When they
  * exceed the capacities the call returns MR_ERR_CAPACITY, leaves the output
  * buffers unspecified and keeps the required sizes here, so the caller can
@@ -169,9 +185,11 @@ mr_status mr_job_destroy(mr_job* job);
  * the element size, malformed record offsets, unsupported kind/op pair),
  * MR_ERR_CAPACITY, MR_ERR_UNSUPPORTED (word inputs of 4 GiB or more; integer
  * inputs of 2^32 or more elements; a forced array strategy without a key
- * range), MR_ERR_HIP. key_range (0 = undeclared) declares that every uint32
+ * range; a Bloom filter of more than 2^29 bits or with more than 2^32
+ * positions), MR_ERR_HIP. key_range (0 = undeclared) declares that every uint32
  * key is < key_range, which makes the array containers feasible. Keys at or
- * above a declared range make the call fail with MR_ERR_INVALID_ARG. */
+ * above a declared range make the call fail with MR_ERR_INVALID_ARG. For
+ * MR_MAP_BLOOM, key_range is the filter size m in bits (required). */
 mr_status mr_run(mr_job* job, mr_map_kind kind, mr_reduce_op op, const void* d_input, uint64_t input_bytes,
                  const uint64_t* d_record_offsets, uint64_t n_records, uint64_t key_range, mr_output* out);
 

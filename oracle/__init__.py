@@ -4,7 +4,8 @@ Only the tests, the smoke check and the benchmark's CPU-baseline leg may
 import this package. The GPU library never imports, links or calls it, and
 it shares no code with the GPU library.
 
-* Word count, integer-key reduce and the RGB histogram run in a small C++
+* Word count, integer-key reduce, the RGB histogram and the Bloom filter
+  build run in a small C++
   library (oracle.cpp, built with g++) that follows the paper's programming
   model (Section II-A): map every input element, reduce all pairs with equal
   keys, output in key order.
@@ -57,6 +58,10 @@ def _load():
         lib.oracle_u32_copy.argtypes = [P, P, P]
         lib.oracle_u32_free.argtypes = [P]
         lib.oracle_rgb_run.argtypes = [P, U64, P]
+        lib.oracle_fmix64.restype = U64
+        lib.oracle_fmix64.argtypes = [U64]
+        lib.oracle_bloom_run.restype = U64
+        lib.oracle_bloom_run.argtypes = [P, U64, C.c_uint32, C.c_uint32, U64, P]
         _lib = lib
     return _lib
 
@@ -148,6 +153,24 @@ def rgb(buf: np.ndarray) -> np.ndarray:
     bins = np.zeros(768, np.uint64)
     lib.oracle_rgb_run(_ptr(buf), len(buf), _ptr(bins))
     return bins.reshape(3, 256)
+
+
+# ----------------------------------------------------------------------------
+# Bloom filter build
+# ----------------------------------------------------------------------------
+
+def fmix64(x: int) -> int:
+    """MurmurHash3's 64-bit finaliser, as the oracle computes it."""
+    return int(_load().oracle_fmix64(int(x) & 0xFFFFFFFFFFFFFFFF))
+
+
+def bloom(buf: np.ndarray, m: int, k: int = 20, h: int = 7) -> tuple[np.ndarray, int]:
+    """Bloom filter of the valid k-mers of DNA bytes `buf`: (uint32 words[ceil(m/32)], k-mers inserted)."""
+    lib = _load()
+    buf = np.ascontiguousarray(buf, dtype=np.uint8)
+    words = np.zeros((m + 31) // 32, np.uint32)
+    n = lib.oracle_bloom_run(_ptr(buf), len(buf), k, h, m, _ptr(words))
+    return words, int(n)
 
 
 # ----------------------------------------------------------------------------

@@ -155,4 +155,69 @@ void oracle_rgb_run(const uint8_t* buf, uint64_t n, uint64_t* bins /* [3*256] */
     for (int c = 0; c < 3; ++c) bins[c * 256 + buf[p + c]] += 1;
 }
 
+// ---------------------------------------------------------------------------
+// Bloom filter build (Table of benchmark applications: Bloom Filter, large
+// array container; Section III-E). map: each k-mer of the DNA input, taken
+// only when all of its k bytes are A, C, G or T, emits h bit positions;
+// reduce: OR into one array of m bits. Readings (the paper names the
+// application but not its hashing):
+//   v     = k-mer packed two bits per base, A 0, C 1, G 2, T 3, first base
+//           in the most significant position
+//   x     = fmix64(v), the 64-bit finaliser of MurmurHash3
+//   g_i   = (low32(x) + i * (high32(x) | 1)) mod 2^32, i = 0 .. h-1
+//           (double hashing, Kirsch and Mitzenmacher)
+//   pos_i = floor(g_i * m / 2^32)
+// Every k-mer is recomputed from its k bytes; nothing is rolled or reused.
+// ---------------------------------------------------------------------------
+uint64_t oracle_fmix64(uint64_t x) {
+  // MurmurHash3's fmix64: xor-shift by 33, multiply, xor-shift, multiply, xor-shift
+  x ^= x >> 33;
+  x *= 0xff51afd7ed558ccdULL;
+  x ^= x >> 33;
+  x *= 0xc4ceb9fe1a85ec53ULL;
+  x ^= x >> 33;
+  return x;
+}
+
+static int dna_code(uint8_t b) {
+  switch (b) {
+    case 'A': return 0;
+    case 'C': return 1;
+    case 'G': return 2;
+    case 'T': return 3;
+    default: return -1;
+  }
+}
+
+// words: ceil(m / 32) uint32, cleared here; bit b lives in bit b % 32 of word b / 32.
+// Returns the number of k-mers that emitted positions.
+uint64_t oracle_bloom_run(const uint8_t* buf, uint64_t n, uint32_t k, uint32_t h, uint64_t m, uint32_t* words) {
+  const uint64_t n_words = (m + 31) / 32;
+  for (uint64_t w = 0; w < n_words; ++w) words[w] = 0;
+  uint64_t emitted = 0;
+  for (uint64_t s = 0; s + k <= n; ++s) {
+    uint64_t v = 0;
+    bool valid = true;
+    for (uint32_t q = 0; q < k; ++q) {
+      const int c = dna_code(buf[s + q]);
+      if (c < 0) {
+        valid = false;
+        break;
+      }
+      v = v * 4 + (uint64_t)c;
+    }
+    if (!valid) continue;
+    ++emitted;
+    const uint64_t x = oracle_fmix64(v);
+    const uint32_t a = (uint32_t)(x & 0xffffffffu);
+    const uint32_t b = (uint32_t)(x >> 32) | 1u;
+    for (uint32_t i = 0; i < h; ++i) {
+      const uint32_t g = a + i * b;  // mod 2^32 by unsigned wrap-around
+      const uint64_t pos = ((uint64_t)g * m) >> 32;
+      words[pos / 32] |= 1u << (pos % 32);
+    }
+  }
+  return emitted;
+}
+
 }  // extern "C"

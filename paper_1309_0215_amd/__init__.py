@@ -64,7 +64,8 @@ class Job:
     """One mr_job bound to a device and to that device's current torch stream."""
 
     def __init__(self, device: int = 0, strategy: int = L.STRAT_RULE, lds_slots: int = 0, max_load_pct: int = 0,
-                 debug_hash: int = 0, table_slots: int = 0, km_centroids=None, stream=None, timing: int = 0):
+                 debug_hash: int = 0, table_slots: int = 0, km_centroids=None, stream=None, timing: int = 0,
+                 bloom_k: int = 0, bloom_hashes: int = 0):
         import torch
         self.torch = torch
         self.lib = load()
@@ -78,6 +79,8 @@ class Job:
         cfg.debug_hash = debug_hash
         cfg.table_slots = table_slots
         cfg.timing = timing
+        cfg.bloom_k = bloom_k
+        cfg.bloom_hashes = bloom_hashes
         self._km = None
         if km_centroids is not None:
             c = km_centroids.to(device=f"cuda:{device}", dtype=torch.float32).contiguous()
@@ -231,3 +234,18 @@ class Job:
         L.check(self.lib.mr_run(self.h, L.MAP_KMEANS, L.REDUCE_SUM, _ptr(X), n * d * 4, None, 0, 0, C.byref(o)),
                 "mr_run(kmeans)")
         return assign[:n], sums, counts, cents, _stats(o)
+
+    # ---------------------------------------------------------- Bloom filter
+    def bloom(self, data, m: int):
+        """Bloom filter of the k-mers of uint8 CUDA tensor data (DNA bytes) with m bits.
+
+        Returns the filter as an int32 tensor of ceil(m / 32) words (bit b in
+        bit b % 32 of word b / 32) and the stats."""
+        torch = self.torch
+        n_words = (int(m) + 31) // 32
+        words = torch.empty(max(n_words, 1), dtype=torch.int32, device=f"cuda:{self.device}")
+        o = L.Output()
+        o.values, o.cap_keys = words.data_ptr(), n_words
+        L.check(self.lib.mr_run(self.h, L.MAP_BLOOM, L.REDUCE_COUNT, _ptr(data), int(data.numel()), None, 0, int(m),
+                                C.byref(o)), "mr_run(bloom)")
+        return words[:n_words], _stats(o)

@@ -15,7 +15,7 @@ MR_ERR_HIP = -4
 MR_ERR_UNSUPPORTED = -5
 MR_ERR_NO_DEVICE = -6
 
-MAP_WORDS, MAP_U32_KEYS, MAP_U32_KV, MAP_RGB_HIST, MAP_KMEANS = range(5)
+MAP_WORDS, MAP_U32_KEYS, MAP_U32_KV, MAP_RGB_HIST, MAP_KMEANS, MAP_BLOOM = range(6)
 REDUCE_COUNT, REDUCE_SUM, REDUCE_MIN, REDUCE_MAX = range(4)
 STRAT_RULE, STRAT_LEARNED, STRAT_LDS_ARRAY, STRAT_GLOBAL_ARRAY, STRAT_HASH, STRAT_SORT = range(6)
 
@@ -44,6 +44,8 @@ class JobConfig(C.Structure):
         ("km_d", C.c_uint32),
         ("km_k", C.c_uint32),
         ("km_centroids", C.c_void_p),
+        ("bloom_k", C.c_uint32),
+        ("bloom_hashes", C.c_uint32),
     ]
 
 

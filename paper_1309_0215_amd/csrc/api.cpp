@@ -948,6 +948,42 @@ mr_status run_kmeans(mr_job* job, const void* d_input, uint64_t bytes, mr_output
   return MR_OK;
 }
 
+mr_status run_bloom(mr_job* job, mr_reduce_op op, const void* d_input, uint64_t bytes, uint64_t m, mr_output* out) {
+  if (op != MR_REDUCE_COUNT) return fail(MR_ERR_UNSUPPORTED, "the Bloom filter takes MR_REDUCE_COUNT (bitwise OR)");
+  const uint32_t k = job->cfg.bloom_k ? job->cfg.bloom_k : 20u;
+  const uint32_t h = job->cfg.bloom_hashes ? job->cfg.bloom_hashes : 7u;
+  if (k > 32 || h > 8) return fail(MR_ERR_INVALID_ARG, "Bloom filter k-mer length %u (1..32) or hash count %u (1..8)", k, h);
+  if (m == 0) return fail(MR_ERR_INVALID_ARG, "the Bloom filter needs its size in bits as key_range");
+  if (m > (1ull << 29)) return fail(MR_ERR_UNSUPPORTED, "Bloom filters of more than 2^29 bits are not supported");
+  const BloomPlan b = bloom_plan(bytes, k, h, m);
+  if (!b.ok) return fail(MR_ERR_UNSUPPORTED, "Bloom filter input too large (%llu positions)", (unsigned long long)b.max_entries);
+  out->n_keys = b.n_words;
+  out->key_bytes_used = 0;
+  if (!out->values) return fail(MR_ERR_INVALID_ARG, "the Bloom filter needs values (uint32 words)");
+  if (out->cap_keys < b.n_words)
+    return fail(MR_ERR_CAPACITY, "the Bloom filter needs %llu words", (unsigned long long)b.n_words);
+  Carve c;
+  const uint64_t o_hist = c.take(4ull * std::max<uint64_t>(b.H, 1)), o_sums = c.take(4ull * scan_sums_count(b.H));
+  const uint64_t o_tot = c.take(8), o_part = c.take(4ull * std::max<uint64_t>(b.max_entries, 1));
+  mr_status st = ensure_ws(job, c.off);
+  if (st != MR_OK) return st;
+  job->table_clean_bytes = 0;  // this scratch overwrites the word table region
+  job->graph_valid = false;
+  uint8_t* ws = job->ws;
+  MR_HIP(hipEventRecord(job->ev0, job->stream));
+  MR_HIP(bloom_enqueue(static_cast<const uint8_t*>(d_input), bytes, k, h, m, b, reinterpret_cast<uint32_t*>(ws + o_hist),
+                       reinterpret_cast<uint32_t*>(ws + o_sums), reinterpret_cast<unsigned long long*>(ws + o_tot),
+                       reinterpret_cast<uint32_t*>(ws + o_part), static_cast<uint32_t*>(out->values), job->stream));
+  MR_HIP(hipEventRecord(job->ev1, job->stream));
+  MR_HIP(hipStreamSynchronize(job->stream));
+  float ms = 0.f;
+  MR_HIP(hipEventElapsedTime(&ms, job->ev0, job->ev1));
+  out->stats.gpu_ms = ms;
+  out->stats.n_items = b.n_kmers;
+  out->stats.strategy_used = MR_STRAT_GLOBAL_ARRAY;
+  return MR_OK;
+}
+
 }  // namespace
 
 // ----------------------------------------------------------------------------
@@ -981,6 +1017,9 @@ extern "C" mr_status mr_run(mr_job* job, mr_map_kind kind, mr_reduce_op op, cons
       break;
     case MR_MAP_KMEANS:
       s = run_kmeans(job, d_input, input_bytes, out);
+      break;
+    case MR_MAP_BLOOM:
+      s = run_bloom(job, op, d_input, input_bytes, key_range, out);
       break;
     default:
       return fail(MR_ERR_INVALID_ARG, "unknown map kind %d", (int)kind);

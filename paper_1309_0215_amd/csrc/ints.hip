@@ -900,6 +900,17 @@ hipError_t int_enqueue_global_array(const IntLaunch& L, hipStream_t s) {
   return hipGetLastError();
 }
 
+// Exclusive scan of a[0, n) in place; the sum of all entries into *total.
+hipError_t scan_exclusive_u32(uint32_t* a, uint64_t n, uint32_t* sums, unsigned long long* total, hipStream_t s) {
+  const uint32_t sb = (uint32_t)((n + kScanTile - 1) / kScanTile);
+  hipLaunchKernelGGL(k_scan_blocks, dim3(sb ? sb : 1), dim3(256), 0, s, a, n, sums);
+  hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, s, sums, sb ? sb : 1, total);
+  hipLaunchKernelGGL(k_scan_apply, dim3(sb ? sb : 1), dim3(256), 0, s, a, n, sums);
+  return hipGetLastError();
+}
+
+uint64_t scan_sums_count(uint64_t n) { return (n + kScanTile - 1) / kScanTile + 1; }
+
 // Layout of the partitioned fill's scratch for n elements over range R.
 PartPlan part_plan(uint64_t n, uint64_t R) {
   PartPlan pp{};

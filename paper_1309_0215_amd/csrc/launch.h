@@ -78,6 +78,24 @@ struct IntLaunch {
 };
 
 hipError_t int_enqueue_lds_array(const IntLaunch& L, hipStream_t s);
+// device-wide exclusive scan of uint32 counts (sums: scan_sums_count(n) entries)
+hipError_t scan_exclusive_u32(uint32_t* a, uint64_t n, uint32_t* sums, unsigned long long* total, hipStream_t s);
+uint64_t scan_sums_count(uint64_t n);
+
+// Bloom filter build: plan and enqueue (see bloom.hip)
+struct BloomPlan {
+  uint64_t n_kmers;      // k-mers of the input
+  uint64_t n_words;      // uint32 words of the m-bit filter
+  uint32_t P;            // position ranges of 2^18 bits
+  uint32_t n_tiles;      // tiles of the count and scatter passes
+  uint64_t H;            // P * n_tiles range counts
+  uint64_t max_entries;  // positions emitted at most (n_kmers * h)
+  bool ok;               // parameters and sizes within the kernels' limits
+};
+BloomPlan bloom_plan(uint64_t n_bytes, uint32_t k, uint32_t h, uint64_t m);
+hipError_t bloom_enqueue(const uint8_t* in, uint64_t n_bytes, uint32_t k, uint32_t h, uint64_t m, const BloomPlan& b,
+                         uint32_t* hist, uint32_t* scan_sums, unsigned long long* total, uint32_t* part, uint32_t* words,
+                         hipStream_t s);
 // global array filled by key-range partitions (COUNT): plan and enqueue
 struct PartPlan {
   uint32_t P;        // key ranges of 2^15 keys
