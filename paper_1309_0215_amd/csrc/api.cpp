@@ -964,7 +964,7 @@ mr_status run_bloom(mr_job* job, mr_reduce_op op, const void* d_input, uint64_t 
     return fail(MR_ERR_CAPACITY, "the Bloom filter needs %llu words", (unsigned long long)b.n_words);
   Carve c;
   const uint64_t o_hist = c.take(4ull * std::max<uint64_t>(b.H, 1)), o_sums = c.take(4ull * scan_sums_count(b.H));
-  const uint64_t o_tot = c.take(8), o_part = c.take(4ull * std::max<uint64_t>(b.max_entries, 1));
+  const uint64_t o_tot = c.take(8), o_part = c.take(4ull * b.part_words);
   mr_status st = ensure_ws(job, c.off);
   if (st != MR_OK) return st;
   job->table_clean_bytes = 0;  // this scratch overwrites the word table region

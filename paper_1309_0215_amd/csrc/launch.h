@@ -90,6 +90,7 @@ struct BloomPlan {
   uint32_t n_tiles;      // tiles of the count and scatter passes
   uint64_t H;            // P * n_tiles range counts
   uint64_t max_entries;  // positions emitted at most (n_kmers * h)
+  uint64_t part_words;   // uint32 words of the position buffer
   bool ok;               // parameters and sizes within the kernels' limits
 };
 BloomPlan bloom_plan(uint64_t n_bytes, uint32_t k, uint32_t h, uint64_t m);

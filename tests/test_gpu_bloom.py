@@ -47,11 +47,11 @@ def _check(torch, s, m, k=20, h=7):
     (100_000, 1_000_003, 20, 7, 1),
     (2048 + 19, 4096, 20, 7, 2),          # exactly one tile of k-mers plus the k - 1 bytes
     (2048 + 20, 4096, 20, 7, 3),          # one k-mer into a second tile
-    (333_333, (1 << 18) * 3 + 17, 31, 8, 4),
+    (333_333, (1 << 19) * 3 + 17, 31, 8, 4),
     (333_333, 300_001, 32, 3, 5),
     (50_001, 77, 1, 1, 6),
     (250_000, 5_000_000, 12, 5, 7),
-    (1_000_000, 1 << 29, 20, 7, 8),      # the largest filter: 2048 ranges
+    (1_000_000, 1 << 29, 20, 7, 8),      # the largest filter
 ])
 def test_small_inputs_every_word(torch, n, m, k, h, seed):
     s = gen.dna(seed, n, n_rate=1e-3)
