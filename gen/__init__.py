@@ -21,6 +21,15 @@ Input recipes (the paper names the workloads but ships none of its data):
   component uniform, stored as float32.
 * u32 keys: Zipf ranks over C distinct keys mapped through a seeded
   bijection onto [0, C); optional u32 values.
+* html: n_files files of synthetic HTML. URL vocabulary of V distinct URLs
+  ("http://" + 5-14 lowercase letters + ".com/" + 1-40 bytes of
+  [a-z0-9/_-] + ".html"); every link picks a URL by a finite Zipf(s) law
+  over a seeded permutation and a file uniformly; each file's filler is a
+  slice of a pool of words and tags (including near-misses such as
+  <A HREF="x">, <a href='x'> and <a href=x>, never the exact link marker),
+  cut at random points where its links <a href="URL">w</a> are inserted.
+  File sizes are uniform in [mean/2, 3 mean/2]. The planted (file, URL id)
+  pairs are returned with the bytes.
 * dna: bases A, C, G, T uniform and independent; each position starts a run
   of 'N' (an unknown base, as in assembled chromosomes) with probability
   n_rate, of length uniform in [1, 200], cut at the end of its chunk.
@@ -46,6 +55,7 @@ _STREAM_U32 = 8
 _STREAM_JOBS = 9
 _STREAM_UNIFORM = 10
 _STREAM_DNA = 11
+_STREAM_HTML = 12
 
 
 def _rng(seed: int, stream: int, chunk: int = 0) -> np.random.Generator:
@@ -249,6 +259,76 @@ def uniform_keys(seed: int, n: int, C: int) -> np.ndarray:
     with _cf.ThreadPoolExecutor(_threads()) as ex:
         list(ex.map(work, range(nch)))
     return keys
+
+
+_HTML_TAGS = [b"<p>", b"</p>", b"<div class=\"c\">", b"</div>", b"<b>", b"</b>", b"<a name=\"n\">", b"</a>",
+              b"<img src=\"i.png\">", b"\n", b"<li>", b"<A HREF=\"X\">", b"<a href='y'>", b"<a href=z>",
+              b"<a  href=\"w\">"]
+
+
+@dataclass
+class Html:
+    buf: np.ndarray        # uint8 bytes of all files
+    rec: np.ndarray        # uint64 file offsets [n_files + 1]
+    urls: list             # URL vocabulary (bytes)
+    link_file: np.ndarray  # uint32 file of each planted link
+    link_url: np.ndarray   # uint32 URL id of each planted link
+
+
+def html(seed: int, n_files: int = 78_355, n_links: int = 307_921, size: int = 1 << 30, V: int = 100_000,
+         s: float = 1.0) -> Html:
+    """Synthetic HTML files with planted links (see the module docstring)."""
+    rng = _rng(seed, _STREAM_HTML)
+    letters = np.frombuffer(b"abcdefghijklmnopqrstuvwxyz", np.uint8)
+    path_chars = np.frombuffer(b"abcdefghijklmnopqrstuvwxyz0123456789/_-", np.uint8)
+    urls, seen = [], set()
+    while len(urls) < V:
+        host = letters[rng.integers(0, 26, size=int(rng.integers(5, 15)))].tobytes()
+        path = path_chars[rng.integers(0, len(path_chars), size=int(rng.integers(1, 41)))].tobytes()
+        u = b"http://" + host + b".com/" + path + b".html"
+        if u not in seen:
+            seen.add(u)
+            urls.append(u)
+    perm = rng.permutation(V)
+    link_url = perm[zipf_ranks(rng, V, s, n_links) - 1].astype(np.uint32)
+    link_file = np.sort(rng.integers(0, n_files, size=n_links)).astype(np.uint32)
+    # filler pool: words and tags
+    n_tok = max(1 << 16, size // 5)
+    pool_tokens = []
+    vocab = [letters[rng.integers(0, 26, size=int(rng.integers(2, 11)))].tobytes() + b" " for _ in range(4096)]
+    kinds = rng.random(n_tok // 16 + 1)
+    tok_ids = rng.integers(0, 4096, size=n_tok // 16 + 1)
+    tag_ids = rng.integers(0, len(_HTML_TAGS), size=n_tok // 16 + 1)
+    for kd, w, t in zip(kinds, tok_ids, tag_ids):
+        pool_tokens.append(_HTML_TAGS[t] if kd < 0.25 else vocab[w])
+    pool = np.frombuffer(b"".join(pool_tokens), np.uint8)
+    mean = size / n_files
+    sizes = rng.integers(int(mean // 2), int(mean * 3 // 2) + 1, size=n_files)
+    starts = rng.integers(0, max(1, len(pool) - int(sizes.max()) - 1), size=n_files)
+    first = np.searchsorted(link_file, np.arange(n_files + 1))
+    parts, rec = [], [0]
+    total = 0
+    for f in range(n_files):
+        ln = int(sizes[f])
+        body = pool[starts[f]:starts[f] + ln]
+        lo, hi = first[f], first[f + 1]
+        if hi > lo:
+            cuts = np.sort(rng.integers(0, ln + 1, size=hi - lo))
+            prev = 0
+            for c, li in zip(cuts, range(lo, hi)):
+                parts.append(body[prev:c])
+                parts.append(np.frombuffer(b'<a href="' + urls[link_url[li]] + b'">w</a>', np.uint8))
+                total += int(c) - prev
+                prev = int(c)
+                total += len(parts[-1])
+            parts.append(body[prev:])
+            total += ln - prev
+        else:
+            parts.append(body)
+            total += ln
+        rec.append(total)
+    buf = np.concatenate(parts) if parts else np.zeros(0, np.uint8)
+    return Html(buf, np.array(rec, np.uint64), urls, link_file, link_url)
 
 
 def _dna_chunk(seed: int, c: int, n: int, n_rate: float) -> np.ndarray:

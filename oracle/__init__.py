@@ -4,8 +4,8 @@ Only the tests, the smoke check and the benchmark's CPU-baseline leg may
 import this package. The GPU library never imports, links or calls it, and
 it shares no code with the GPU library.
 
-* Word count, integer-key reduce, the RGB histogram and the Bloom filter
-  build run in a small C++
+* Word count, integer-key reduce, the RGB histogram, the Reverse Index and
+  the Bloom filter build run in a small C++
   library (oracle.cpp, built with g++) that follows the paper's programming
   model (Section II-A): map every input element, reduce all pairs with equal
   keys, output in key order.
@@ -58,6 +58,13 @@ def _load():
         lib.oracle_u32_copy.argtypes = [P, P, P]
         lib.oracle_u32_free.argtypes = [P]
         lib.oracle_rgb_run.argtypes = [P, U64, P]
+        lib.oracle_links_run.restype = P
+        lib.oracle_links_run.argtypes = [P, U64, P, U64]
+        for f in ("oracle_links_n", "oracle_links_bytes", "oracle_links_ids"):
+            getattr(lib, f).restype = U64
+            getattr(lib, f).argtypes = [P]
+        lib.oracle_links_copy.argtypes = [P, P, P, P, P, P]
+        lib.oracle_links_free.argtypes = [P]
         lib.oracle_fmix64.restype = U64
         lib.oracle_fmix64.argtypes = [U64]
         lib.oracle_bloom_run.restype = U64
@@ -153,6 +160,51 @@ def rgb(buf: np.ndarray) -> np.ndarray:
     bins = np.zeros(768, np.uint64)
     lib.oracle_rgb_run(_ptr(buf), len(buf), _ptr(bins))
     return bins.reshape(3, 256)
+
+
+# ----------------------------------------------------------------------------
+# Reverse Index
+# ----------------------------------------------------------------------------
+
+class LinksResult:
+    """Sorted distinct URLs: key_bytes, key_offsets (n+1), counts (links per
+    URL), list_offsets (n+1) and ids (files holding each URL, ascending)."""
+
+    def __init__(self, key_bytes, key_offsets, counts, list_offsets, ids):
+        self.key_bytes, self.key_offsets, self.counts = key_bytes, key_offsets, counts
+        self.list_offsets, self.ids = list_offsets, ids
+
+    def __len__(self):
+        return len(self.counts)
+
+    def items(self):
+        kb = self.key_bytes.tobytes()
+        o, lo = self.key_offsets, self.list_offsets
+        return [(kb[o[i]:o[i + 1]], int(self.counts[i]), self.ids[lo[i]:lo[i + 1]].tolist())
+                for i in range(len(self.counts))]
+
+
+def links(buf: np.ndarray, record_offsets: np.ndarray | None = None) -> LinksResult:
+    """Reverse index of the links in `buf` (uint8), records = files. Raises ValueError on malformed offsets."""
+    lib = _load()
+    buf = np.ascontiguousarray(buf, dtype=np.uint8)
+    n_rec = 0
+    if record_offsets is not None:
+        record_offsets = np.ascontiguousarray(record_offsets, dtype=np.uint64)
+        n_rec = len(record_offsets) - 1
+        if n_rec < 0:
+            raise ValueError("record offsets need at least one entry")
+    h = lib.oracle_links_run(_ptr(buf), len(buf), _ptr(record_offsets), n_rec)
+    if not h:
+        raise ValueError("malformed record offsets")
+    try:
+        n, nb, ni = lib.oracle_links_n(h), lib.oracle_links_bytes(h), lib.oracle_links_ids(h)
+        kb, ko, c = np.empty(nb, np.uint8), np.empty(n + 1, np.uint64), np.empty(n, np.uint64)
+        lo, ids = np.empty(n + 1, np.uint64), np.empty(ni, np.uint32)
+        lib.oracle_links_copy(h, _ptr(kb), _ptr(ko), _ptr(c), _ptr(lo), _ptr(ids))
+    finally:
+        lib.oracle_links_free(h)
+    return LinksResult(kb, ko, c, lo, ids)
 
 
 # ----------------------------------------------------------------------------

@@ -29,6 +29,7 @@
 #include <cstdint>
 #include <cstring>
 #include <map>
+#include <string>
 #include <vector>
 
 namespace {
@@ -219,5 +220,82 @@ uint64_t oracle_bloom_run(const uint8_t* buf, uint64_t n, uint32_t k, uint32_t h
   }
   return emitted;
 }
+
+// ---------------------------------------------------------------------------
+// Reverse Index (Table of benchmark applications: Reverse Index, hash table
+// container). Records are files, numbered from 0. map: every link emits
+// (URL, file); reduce: per URL, the number of links and the ascending list of
+// distinct files that hold one. Reading of "link" (the paper does not define
+// it): the nine bytes <a href=" followed by 1 to 4095 bytes other than a
+// double quote and then a double quote, all inside one record; the URL is the
+// bytes between the quotes. Matching is exact (case and spacing included).
+// Output in unsigned bytewise URL order, a proper prefix first.
+// ---------------------------------------------------------------------------
+struct LinksResult {
+  std::vector<uint8_t> key_bytes;
+  std::vector<uint64_t> key_offsets;   // n+1
+  std::vector<uint64_t> counts;        // links per URL
+  std::vector<uint64_t> list_offsets;  // n+1
+  std::vector<uint32_t> ids;           // files, ascending within each URL
+};
+
+void* oracle_links_run(const uint8_t* buf, uint64_t n, const uint64_t* rec_off, uint64_t n_rec) {
+  static const uint8_t kMarker[9] = {'<', 'a', ' ', 'h', 'r', 'e', 'f', '=', '"'};
+  const uint64_t kMaxUrl = 4095;
+  uint64_t one[2] = {0, n};
+  if (!rec_off) {
+    rec_off = one;
+    n_rec = 1;
+  }
+  for (uint64_t r = 0; r < n_rec; ++r)
+    if (rec_off[r] > rec_off[r + 1] || rec_off[r + 1] > n) return nullptr;
+  struct Entry {
+    uint64_t count = 0;
+    std::vector<uint32_t> files;  // appended in file order, so ascending
+  };
+  std::map<std::string, Entry> index;
+  for (uint64_t r = 0; r < n_rec; ++r) {
+    const uint64_t lo = rec_off[r], hi = rec_off[r + 1];
+    for (uint64_t p = lo; p + 9 <= hi; ++p) {
+      if (std::memcmp(buf + p, kMarker, 9) != 0) continue;
+      const uint64_t u = p + 9;
+      uint64_t q = u;
+      while (q < hi && buf[q] != '"' && q - u <= kMaxUrl) ++q;
+      if (q >= hi || buf[q] != '"') continue;  // no closing quote in the record (or URL too long)
+      const uint64_t len = q - u;
+      if (len < 1 || len > kMaxUrl) continue;
+      Entry& e = index[std::string(reinterpret_cast<const char*>(buf + u), len)];
+      e.count += 1;
+      if (e.files.empty() || e.files.back() != (uint32_t)r) e.files.push_back((uint32_t)r);
+    }
+  }
+  auto* res = new LinksResult();
+  res->key_offsets.push_back(0);
+  res->list_offsets.push_back(0);
+  for (auto& kv : index) {  // std::string compares as unsigned bytes (char_traits<char>::compare uses memcmp)
+    res->key_bytes.insert(res->key_bytes.end(), kv.first.begin(), kv.first.end());
+    res->key_offsets.push_back(res->key_bytes.size());
+    res->counts.push_back(kv.second.count);
+    res->ids.insert(res->ids.end(), kv.second.files.begin(), kv.second.files.end());
+    res->list_offsets.push_back(res->ids.size());
+  }
+  return res;
+}
+
+uint64_t oracle_links_n(void* h) { return static_cast<LinksResult*>(h)->counts.size(); }
+uint64_t oracle_links_bytes(void* h) { return static_cast<LinksResult*>(h)->key_bytes.size(); }
+uint64_t oracle_links_ids(void* h) { return static_cast<LinksResult*>(h)->ids.size(); }
+
+void oracle_links_copy(void* h, uint8_t* key_bytes, uint64_t* key_offsets, uint64_t* counts, uint64_t* list_offsets,
+                       uint32_t* ids) {
+  auto* r = static_cast<LinksResult*>(h);
+  if (!r->key_bytes.empty()) std::memcpy(key_bytes, r->key_bytes.data(), r->key_bytes.size());
+  std::memcpy(key_offsets, r->key_offsets.data(), r->key_offsets.size() * sizeof(uint64_t));
+  if (!r->counts.empty()) std::memcpy(counts, r->counts.data(), r->counts.size() * sizeof(uint64_t));
+  std::memcpy(list_offsets, r->list_offsets.data(), r->list_offsets.size() * sizeof(uint64_t));
+  if (!r->ids.empty()) std::memcpy(ids, r->ids.data(), r->ids.size() * sizeof(uint32_t));
+}
+
+void oracle_links_free(void* h) { delete static_cast<LinksResult*>(h); }
 
 }  // extern "C"
