@@ -223,6 +223,24 @@ def bench_bloom(torch, steps=10):
             "algorithmic_GBps": algo / (ms * 1e-3) / 1e9}
 
 
+def bench_links(torch, steps=5):
+    """The paper's Reverse Index: 78,355 synthetic HTML files, 307,921 links, 1 GiB."""
+    import gen
+    from paper_1309_0215_amd import Job
+    h = gen.html(3)
+    n = len(h.buf)
+    d = torch.from_numpy(h.buf).to("cuda:0")
+    r = torch.from_numpy(h.rec.view("int64")).to("cuda:0")
+    job = Job(device=0)
+    first = job.links(d, r)  # sizes the outputs
+    caps = dict(cap_keys=len(first), cap_bytes=int(first.key_bytes.numel()), cap_ids=int(first.list_ids.numel()))
+    ms, outs = time_steps(lambda: job.links(d, r, **caps).stats, steps, 1, torch)
+    del d, r, job
+    return {"bytes": n, "files": len(h.rec) - 1, "links": int(outs[-1]["n_items"]), "urls": len(first),
+            "list_entries": int(first.list_ids.numel()), "ms_per_step": ms, "GBps": n / (ms * 1e-3) / 1e9,
+            "links_per_s": int(outs[-1]["n_items"]) / (ms * 1e-3)}
+
+
 def bench_copy(torch, steps=5):
     """A plain 1 GiB device-to-device copy: the reference whose HBM counters scale the kernels' counters."""
     n = 1 << 30
@@ -282,7 +300,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--apps", default="rgb,words8,words512,kmeans,hist16m,bloom,batched,selector")
+    ap.add_argument("--apps", default="rgb,words8,words512,kmeans,hist16m,bloom,links,batched,selector")
     ap.add_argument("--no-cpu", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -328,6 +346,10 @@ def main():
         bl = bench_bloom(torch)
         per_app["bloom_filter_30M_kmers_300M_bits"] = bl
         log(f"bloom: {bl['ms_per_step']:.3f} ms, {bl['kmers_per_s'] / 1e9:.2f} G k-mers/s")
+    if "links" in apps:
+        li = bench_links(torch)
+        per_app["reverse_index_78355_files_1GiB"] = li
+        log(f"reverse index: {li['ms_per_step']:.3f} ms, {li['GBps']:.1f} GB/s")
     if "copy" in apps:
         cp = bench_copy(torch)
         per_app["copy_1GiB"] = cp

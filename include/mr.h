@@ -81,7 +81,19 @@ typedef enum {
    * MR_REDUCE_COUNT, the only op accepted). Output: values = uint32
    * words[ceil(m / 32)], bit b of the filter in bit b % 32 of word b / 32;
    * cap_keys is the capacity in words and n_keys the words written. */
-  MR_MAP_BLOOM = 5
+  MR_MAP_BLOOM = 5,
+  /* Reverse Index (benchmark application "Reverse Index"). Input: bytes cut
+   * into files by the record offsets (without offsets, one file); file i is
+   * record i. A link is the nine bytes <a href=" followed by a URL of 1 to
+   * 4095 bytes other than a double quote and then a double quote, all inside
+   * one file; every start position is tried, so links may overlap (a quote
+   * can close one URL and end the next marker). Matching is exact: case and
+   * spacing included. Output: distinct URLs in unsigned bytewise order (a
+   * proper prefix first) in key_bytes / key_offsets as for MR_MAP_WORDS;
+   * values[i] = number of links to URL i (uint32); list_ids[list_offsets[i]
+   * .. list_offsets[i + 1]) = the distinct files linking to URL i,
+   * ascending (uint32). op must be MR_REDUCE_COUNT. */
+  MR_MAP_LINKS = 6
 } mr_map_kind;
 
 typedef enum { MR_REDUCE_COUNT = 0, MR_REDUCE_SUM = 1, MR_REDUCE_MIN = 2, MR_REDUCE_MAX = 3 } mr_reduce_op;
@@ -142,10 +154,14 @@ typedef struct {
  *   KMEANS:   assign[n] (int32), sums[k*d] (float32), counts[k] (uint32),
  *             centroids[k*d] (float32)
  *   BLOOM:    values[cap_keys] (uint32 filter words)
+ *   LINKS:    as WORDS, plus list_offsets[cap_keys + 1] (uint64, required)
+ *             and list_ids[cap_list_ids] (uint32)
  * On return n_keys and key_bytes_used hold the result sizes. When they
  * exceed the capacities the call returns MR_ERR_CAPACITY, leaves the output
  * buffers unspecified and keeps the required sizes here, so the caller can
- * grow its buffers and call again. */
+ * grow its buffers and call again. For LINKS, n_list_ids is the exact list
+ * size once the URL outputs fit, and an upper bound (the number of links)
+ * when they do not. */
 typedef struct {
   void* keys;
   uint8_t* key_bytes;
@@ -161,6 +177,11 @@ typedef struct {
   uint64_t key_bytes_used;
   mr_status status; /* per-item status for mr_batch_run */
   mr_stats stats;
+  /* LINKS only */
+  uint64_t* list_offsets;
+  uint32_t* list_ids;
+  uint64_t cap_list_ids;
+  uint64_t n_list_ids;
 } mr_output;
 
 /* Status text ("MR_OK", ...). Never NULL. */
@@ -179,8 +200,8 @@ mr_status mr_job_destroy(mr_job* job);
 
 /* Run one MapReduce job over d_input (device pointer, input_bytes bytes,
  * read only). d_record_offsets (device pointer, uint64[n_records + 1],
- * non-decreasing, last <= input_bytes) is only valid for MR_MAP_WORDS; pass
- * NULL for one record. Results go to *out (see mr_output).
+ * non-decreasing, last <= input_bytes) is only valid for MR_MAP_WORDS and
+ * MR_MAP_LINKS; pass NULL for one record. Results go to *out (see mr_output).
  * Errors: MR_ERR_INVALID_ARG (bad pointers, input length not a multiple of
  * the element size, malformed record offsets, unsupported kind/op pair),
  * MR_ERR_CAPACITY, MR_ERR_UNSUPPORTED (word inputs of 4 GiB or more; integer

@@ -60,6 +60,29 @@ def _stats(o: L.Output) -> dict:
             "selector_used": s.selector_used}
 
 
+@dataclass
+class LinksResult:
+    """Reverse index on the device: URLs (key_bytes, key_offsets), link counts,
+    and the file lists (list_ids[list_offsets[i]:list_offsets[i + 1]])."""
+    key_bytes: object
+    key_offsets: object
+    counts: object
+    list_offsets: object
+    list_ids: object
+    stats: dict
+
+    def __len__(self):
+        return int(self.counts.numel())
+
+    def items(self):
+        kb = self.key_bytes.cpu().numpy().tobytes()
+        o = self.key_offsets.cpu().numpy()
+        c = self.counts.cpu().numpy().view("uint32")
+        lo = self.list_offsets.cpu().numpy()
+        ids = self.list_ids.cpu().numpy().view("uint32")
+        return [(kb[o[i]:o[i + 1]], int(c[i]), ids[lo[i]:lo[i + 1]].tolist()) for i in range(len(c))]
+
+
 class Job:
     """One mr_job bound to a device and to that device's current torch stream."""
 
@@ -234,6 +257,37 @@ class Job:
         L.check(self.lib.mr_run(self.h, L.MAP_KMEANS, L.REDUCE_SUM, _ptr(X), n * d * 4, None, 0, 0, C.byref(o)),
                 "mr_run(kmeans)")
         return assign[:n], sums, counts, cents, _stats(o)
+
+    # ---------------------------------------------------------- Reverse Index
+    def links(self, data, record_offsets=None, cap_keys: int | None = None, cap_bytes: int | None = None,
+              cap_ids: int | None = None) -> "LinksResult":
+        """Reverse index of uint8 CUDA tensor data; record_offsets (uint64 CUDA tensor) cut it into files."""
+        torch = self.torch
+        dev = f"cuda:{self.device}"
+        n = int(data.numel())
+        ro = record_offsets
+        n_rec = int(ro.numel()) - 1 if ro is not None else 0
+        ck = cap_keys if cap_keys is not None else max(16, n // 64)
+        cb = cap_bytes if cap_bytes is not None else max(64, n // 8)
+        ci = cap_ids if cap_ids is not None else max(16, n // 64)
+        for _ in range(3):
+            kb = torch.empty(max(cb, 1), dtype=torch.uint8, device=dev)
+            ko = torch.empty(ck + 1, dtype=torch.int64, device=dev)
+            v = torch.empty(max(ck, 1), dtype=torch.int32, device=dev)
+            lo = torch.empty(ck + 1, dtype=torch.int64, device=dev)
+            ids = torch.empty(max(ci, 1), dtype=torch.int32, device=dev)
+            o = L.Output()
+            o.key_bytes, o.key_offsets, o.values, o.cap_keys, o.cap_key_bytes = (kb.data_ptr(), ko.data_ptr(), v.data_ptr(),
+                                                                                ck, cb)
+            o.list_offsets, o.list_ids, o.cap_list_ids = lo.data_ptr(), ids.data_ptr(), ci
+            st = self.lib.mr_run(self.h, L.MAP_LINKS, L.REDUCE_COUNT, _ptr(data), n, _ptr(ro), n_rec, 0, C.byref(o))
+            if st == L.MR_ERR_CAPACITY:
+                ck, cb, ci = max(ck, int(o.n_keys)), max(cb, int(o.key_bytes_used)), max(ci, int(o.n_list_ids))
+                continue
+            L.check(st, "mr_run(links)")
+            nk, ni = int(o.n_keys), int(o.n_list_ids)
+            return LinksResult(kb[:int(o.key_bytes_used)], ko[:nk + 1], v[:nk], lo[:nk + 1], ids[:ni], _stats(o))
+        raise MRError(L.MR_ERR_CAPACITY, "output capacity retry failed")
 
     # ---------------------------------------------------------- Bloom filter
     def bloom(self, data, m: int):

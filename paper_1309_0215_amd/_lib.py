@@ -15,7 +15,7 @@ MR_ERR_HIP = -4
 MR_ERR_UNSUPPORTED = -5
 MR_ERR_NO_DEVICE = -6
 
-MAP_WORDS, MAP_U32_KEYS, MAP_U32_KV, MAP_RGB_HIST, MAP_KMEANS, MAP_BLOOM = range(6)
+MAP_WORDS, MAP_U32_KEYS, MAP_U32_KV, MAP_RGB_HIST, MAP_KMEANS, MAP_BLOOM, MAP_LINKS = range(7)
 REDUCE_COUNT, REDUCE_SUM, REDUCE_MIN, REDUCE_MAX = range(4)
 STRAT_RULE, STRAT_LEARNED, STRAT_LDS_ARRAY, STRAT_GLOBAL_ARRAY, STRAT_HASH, STRAT_SORT = range(6)
 
@@ -78,6 +78,10 @@ class Output(C.Structure):
         ("key_bytes_used", C.c_uint64),
         ("status", C.c_int32),
         ("stats", Stats),
+        ("list_offsets", C.c_void_p),
+        ("list_ids", C.c_void_p),
+        ("cap_list_ids", C.c_uint64),
+        ("n_list_ids", C.c_uint64),
     ]
 
 

@@ -94,6 +94,10 @@ struct mr_job {
   uint64_t sel_dev_floats = 0;
   void* mlp_dev = nullptr;
   uint64_t mlp_dev_floats = 0;
+  // Reverse Index: marker list and pairs (sized by link_cap), then the sort scratch
+  void* link_dev = nullptr;
+  uint64_t link_dev_bytes = 0;
+  uint64_t link_cap = 0;
 };
 
 namespace {
@@ -239,6 +243,7 @@ extern "C" mr_status mr_job_destroy(mr_job* job) {
   if (job->int_scratch) (void)hipFree(job->int_scratch);
   if (job->sel_dev) (void)hipFree(job->sel_dev);
   if (job->mlp_dev) (void)hipFree(job->mlp_dev);
+  if (job->link_dev) (void)hipFree(job->link_dev);
   if (job->ev0) (void)hipEventDestroy(job->ev0);
   if (job->ev1) (void)hipEventDestroy(job->ev1);
   if (job->ev2) (void)hipEventDestroy(job->ev2);
@@ -252,6 +257,16 @@ extern "C" mr_status mr_job_destroy(mr_job* job) {
 // ----------------------------------------------------------------------------
 
 namespace {
+
+// Device buffers of the Reverse Index map (one job).
+struct LinkBufs {
+  uint32_t* marks;
+  unsigned long long* n_marks;
+  uint64_t cap;
+  uint32_t* pair_slot;
+  uint32_t* pair_file;
+  uint32_t* slot_rank;  // set by the pass: output rank of each table slot
+};
 
 struct WordItem {
   const uint8_t* in;
@@ -278,12 +293,12 @@ uint64_t initial_slots(const mr_job* job, uint64_t n) {
 struct WordsPlan {
   Carve c;
   uint64_t o_jobs, o_tile_base, o_states, o_totals, o_bucket_cnt, o_bucket_bytes, o_bucket_start, o_bucket_bstart,
-      o_bucket_fill, o_tw, o_tc, o_recs, o_recs2, o_rbucket, o_spl;
+      o_bucket_fill, o_tw, o_tc, o_recs, o_recs2, o_rbucket, o_spl, o_slot_rank = 0;
   uint64_t total_slots = 0, total_tiles = 0;
   std::vector<uint64_t> slot_base, tile_base;
 };
 
-WordsPlan plan_words(const std::vector<WordItem>& items) {
+WordsPlan plan_words(const std::vector<WordItem>& items, bool slot_ranks) {
   WordsPlan p;
   const uint32_t n = (uint32_t)items.size();
   p.slot_base.resize(n);
@@ -313,6 +328,7 @@ WordsPlan plan_words(const std::vector<WordItem>& items) {
   p.o_recs2 = p.c.take(sizeof(WRec) * p.total_slots);
   p.o_rbucket = p.c.take(4 * p.total_slots);
   p.o_spl = p.c.take(sizeof(WRec) * (kMaxBuckets - 1) * (uint64_t)n);
+  if (slot_ranks) p.o_slot_rank = p.c.take(4 * p.total_slots);
   return p;
 }
 
@@ -342,9 +358,9 @@ uint64_t fnv_mix(uint64_t h, uint64_t v) {
 }
 
 mr_status words_pass(mr_job* job, std::vector<WordItem>& items, std::vector<JobState>& states, float* gpu_ms,
-                     float* map_ms, GraphMode mode) {
+                     float* map_ms, GraphMode mode, LinkBufs* lb) {
   const uint32_t n = (uint32_t)items.size();
-  WordsPlan p = plan_words(items);
+  WordsPlan p = plan_words(items, lb != nullptr);
   mr_status st = ensure_ws(job, p.c.off);
   if (st != MR_OK) return st;
   uint8_t* ws = job->ws;
@@ -354,6 +370,7 @@ mr_status words_pass(mr_job* job, std::vector<WordItem>& items, std::vector<JobS
   key = fnv_mix(key, n);
   key = fnv_mix(key, job->cfg.lds_slots);
   key = fnv_mix(key, job->cfg.debug_hash);
+  key = fnv_mix(key, lb ? (uint64_t)lb->marks ^ lb->cap : 0ull);
   for (const WordItem& it : items) {
     key = fnv_mix(key, (uint64_t)it.in);
     key = fnv_mix(key, it.n);
@@ -435,6 +452,7 @@ mr_status words_pass(mr_job* job, std::vector<WordItem>& items, std::vector<JobS
     J.cap_keys = it.out->cap_keys;
     J.cap_key_bytes = it.out->cap_key_bytes;
     J.st = reinterpret_cast<JobState*>(ws + p.o_states) + j;
+    J.slot_rank = lb ? reinterpret_cast<uint32_t*>(ws + p.o_slot_rank) + p.slot_base[j] : nullptr;
     any_rec |= it.rec != nullptr;
   }
   MR_HIP(hipMemcpyAsync(ws + p.o_jobs, hj.data(), sizeof(WordJob) * n, hipMemcpyHostToDevice, s));
@@ -466,6 +484,16 @@ mr_status words_pass(mr_job* job, std::vector<WordItem>& items, std::vector<JobS
   L.bucket_fill = reinterpret_cast<uint32_t*>(ws + p.o_bucket_fill);
 
   L.states = reinterpret_cast<JobState*>(ws + p.o_states);
+  if (lb) {
+    L.links = true;
+    L.link_grid = (uint32_t)std::max(1, job->n_cu * 8);
+    L.link_marks = lb->marks;
+    L.link_n = lb->n_marks;
+    L.link_cap = lb->cap;
+    L.link_pair_slot = lb->pair_slot;
+    L.link_pair_file = lb->pair_file;
+    lb->slot_rank = reinterpret_cast<uint32_t*>(ws + p.o_slot_rank);
+  }
   if (use_graph) {
     // capture the whole sequence (no memset nodes: states are cleared by a kernel)
     if (job->graph) {
@@ -532,7 +560,8 @@ mr_status check_words_item(const WordItem& it) {
   return MR_OK;
 }
 
-mr_status run_words(mr_job* job, std::vector<WordItem>& items, std::vector<mr_status>* per_item, GraphMode use_graph) {
+mr_status run_words(mr_job* job, std::vector<WordItem>& items, std::vector<mr_status>* per_item, GraphMode use_graph,
+                    LinkBufs* lb = nullptr) {
   for (auto& it : items) {
     mr_status s = check_words_item(it);
     if (s != MR_OK) return s;
@@ -546,7 +575,7 @@ mr_status run_words(mr_job* job, std::vector<WordItem>& items, std::vector<mr_st
   float total_ms = 0.f, map_ms = 0.f;
   for (;;) {
     float ms = 0.f;
-    mr_status s = words_pass(job, items, states, &ms, &map_ms, use_graph);
+    mr_status s = words_pass(job, items, states, &ms, &map_ms, use_graph, lb);
     if (s != MR_OK) return s;
     total_ms += ms;
     bool regrow = false;
@@ -590,6 +619,131 @@ mr_status run_words(mr_job* job, std::vector<WordItem>& items, std::vector<mr_st
     if (first == MR_OK && r != MR_OK) first = r;
   }
   return first;
+}
+
+// ----------------------------------------------------------------------------
+// Reverse Index: the word pass with the link map, then the file lists
+// ----------------------------------------------------------------------------
+
+uint32_t bits_for(uint64_t n) {  // smallest b with 2^b >= n
+  uint32_t b = 0;
+  while (b < 64 && (1ull << b) < n) ++b;
+  return b;
+}
+
+mr_status ensure_link_dev(mr_job* job, uint64_t bytes) {
+  if (bytes <= job->link_dev_bytes) return MR_OK;
+  MR_HIP(hipStreamSynchronize(job->stream));
+  if (job->link_dev) MR_HIP(hipFree(job->link_dev));
+  job->link_dev = nullptr;
+  job->link_dev_bytes = 0;
+  MR_HIP(hipMalloc(&job->link_dev, bytes));
+  job->link_dev_bytes = bytes;
+  return MR_OK;
+}
+
+mr_status run_links(mr_job* job, mr_reduce_op op, const void* d_input, uint64_t bytes, const uint64_t* rec, uint64_t n_rec,
+                    mr_output* out) {
+  if (op != MR_REDUCE_COUNT) return fail(MR_ERR_UNSUPPORTED, "the Reverse Index takes MR_REDUCE_COUNT");
+  if (!out->list_offsets) return fail(MR_ERR_INVALID_ARG, "list_offsets is required (at least one entry)");
+  if (out->cap_list_ids && !out->list_ids) return fail(MR_ERR_INVALID_ARG, "cap_list_ids given without list_ids");
+  if (rec && n_rec >= (1ull << 32)) return fail(MR_ERR_UNSUPPORTED, "at most 2^32 - 1 files");
+  // marker list: one per 512 input bytes to start with, grown to the count found
+  uint64_t cap = std::max<uint64_t>(4096, std::max<uint64_t>(job->link_cap, bytes / 512));
+  std::vector<WordItem> items(1);
+  mr_status st = MR_OK;
+  unsigned long long n_marks = 0;
+  Carve c;
+  uint64_t o_marks = 0, o_n = 0, o_slot = 0, o_file = 0;
+  LinkBufs lb{};
+  for (int attempt = 0;; ++attempt) {
+    c = Carve{};
+    o_n = c.take(8);
+    o_marks = c.take(4 * cap);
+    o_slot = c.take(4 * cap);
+    o_file = c.take(4 * cap);
+    st = ensure_link_dev(job, c.off);
+    if (st != MR_OK) return st;
+    uint8_t* d = static_cast<uint8_t*>(job->link_dev);
+    lb = LinkBufs{reinterpret_cast<uint32_t*>(d + o_marks), reinterpret_cast<unsigned long long*>(d + o_n), cap,
+                  reinterpret_cast<uint32_t*>(d + o_slot), reinterpret_cast<uint32_t*>(d + o_file), nullptr};
+    items[0] = WordItem{static_cast<const uint8_t*>(d_input), bytes, rec, n_rec, out, 0};
+    st = run_words(job, items, nullptr, GraphMode::kNever, &lb);
+    if (st != MR_OK && st != MR_ERR_CAPACITY) return st;
+    MR_HIP(hipMemcpy(&n_marks, lb.n_marks, 8, hipMemcpyDeviceToHost));
+    if (n_marks <= cap) break;
+    if (attempt >= 2) return fail(MR_ERR_HIP, "marker list did not converge");
+    cap = next_pow2(n_marks);
+  }
+  job->link_cap = cap;
+  out->stats.n_items = 0;
+  if (st == MR_ERR_CAPACITY) {  // the URL outputs did not fit: report an upper bound of the list size
+    out->n_list_ids = n_marks;
+    return st;
+  }
+  // file lists
+  const uint64_t n = n_marks, nk = out->n_keys;
+  const uint32_t fb = bits_for(rec ? n_rec : 1), rb = bits_for(nk + 1);
+  const int sort_bits = (int)std::max<uint32_t>(8, (fb + rb + 7) / 8 * 8);
+  const uint64_t hw = links_hist_words(n);
+  Carve c2 = c;
+  const uint64_t o_k0 = c2.take(8 * n), o_v0 = c2.take(8 * n), o_k1 = c2.take(8 * n), o_v1 = c2.take(8 * n);
+  const uint64_t o_hist = c2.take(4 * std::max<uint64_t>(hw, 1));
+  const uint64_t o_sums = c2.take(4 * std::max(scan_sums_count(hw), scan_sums_count(n)));
+  const uint64_t o_head = c2.take(4 * std::max<uint64_t>(n, 1)), o_tot = c2.take(8), o_val = c2.take(8), o_fl = c2.take(8);
+  const uint64_t o_first = c2.take(4 * (nk + 1));
+  if (c2.off > job->link_dev_bytes) {
+    // keep the pairs: grow into a new buffer and copy the map's part across
+    void* nd = nullptr;
+    MR_HIP(hipMalloc(&nd, c2.off));
+    MR_HIP(hipMemcpyAsync(nd, job->link_dev, c.off, hipMemcpyDeviceToDevice, job->stream));
+    MR_HIP(hipStreamSynchronize(job->stream));
+    MR_HIP(hipFree(job->link_dev));
+    job->link_dev = nd;
+    job->link_dev_bytes = c2.off;
+  }
+  uint8_t* d = static_cast<uint8_t*>(job->link_dev);
+  LinksPost P{};
+  P.pair_slot = reinterpret_cast<const uint32_t*>(d + o_slot);
+  P.pair_file = reinterpret_cast<const uint32_t*>(d + o_file);
+  P.n = n;
+  P.slot_rank = lb.slot_rank;
+  P.n_keys = nk;
+  P.file_bits = (int)fb;
+  P.sort_bits = sort_bits;
+  P.k0 = reinterpret_cast<unsigned long long*>(d + o_k0);
+  P.v0 = reinterpret_cast<unsigned long long*>(d + o_v0);
+  P.k1 = reinterpret_cast<unsigned long long*>(d + o_k1);
+  P.v1 = reinterpret_cast<unsigned long long*>(d + o_v1);
+  P.hist = reinterpret_cast<uint32_t*>(d + o_hist);
+  P.scan_sums = reinterpret_cast<uint32_t*>(d + o_sums);
+  P.head = reinterpret_cast<uint32_t*>(d + o_head);
+  P.total = reinterpret_cast<unsigned long long*>(d + o_tot);
+  P.n_valid = reinterpret_cast<unsigned long long*>(d + o_val);
+  P.flags = reinterpret_cast<uint32_t*>(d + o_fl);
+  P.first = reinterpret_cast<uint32_t*>(d + o_first);
+  MR_HIP(hipMemsetAsync(P.flags, 0, 4, job->stream));
+  MR_HIP(hipEventRecord(job->ev0, job->stream));
+  bool in1 = false;
+  MR_HIP(links_enqueue_rank_sort(P, &in1, job->stream));
+  unsigned long long tv[2] = {0, 0};
+  uint32_t flags = 0;
+  MR_HIP(hipMemcpyAsync(&tv[0], P.total, 8, hipMemcpyDeviceToHost, job->stream));
+  MR_HIP(hipMemcpyAsync(&tv[1], P.n_valid, 8, hipMemcpyDeviceToHost, job->stream));
+  MR_HIP(hipMemcpyAsync(&flags, P.flags, 4, hipMemcpyDeviceToHost, job->stream));
+  MR_HIP(hipStreamSynchronize(job->stream));
+  if (flags) return fail(MR_ERR_HIP, "internal error: a link's URL is missing from the sorted URLs");
+  out->n_list_ids = tv[0];
+  out->stats.n_items = tv[1];
+  if (tv[0] > out->cap_list_ids)
+    return fail(MR_ERR_CAPACITY, "the file lists need %llu entries", (unsigned long long)tv[0]);
+  MR_HIP(links_enqueue_write(P, in1, out->list_ids, out->list_offsets, static_cast<uint32_t*>(out->values), job->stream));
+  MR_HIP(hipEventRecord(job->ev1, job->stream));
+  MR_HIP(hipStreamSynchronize(job->stream));
+  float ms = 0.f;
+  MR_HIP(hipEventElapsedTime(&ms, job->ev0, job->ev1));
+  out->stats.gpu_ms += ms;
+  return MR_OK;
 }
 
 }  // namespace
@@ -994,7 +1148,8 @@ extern "C" mr_status mr_run(mr_job* job, mr_map_kind kind, mr_reduce_op op, cons
                             const uint64_t* d_record_offsets, uint64_t n_records, uint64_t key_range, mr_output* out) {
   if (!job || !out) return fail(MR_ERR_INVALID_ARG, "NULL job or output");
   if (input_bytes && !d_input) return fail(MR_ERR_INVALID_ARG, "NULL input");
-  if (d_record_offsets && kind != MR_MAP_WORDS) return fail(MR_ERR_INVALID_ARG, "record offsets are only meaningful for words");
+  if (d_record_offsets && kind != MR_MAP_WORDS && kind != MR_MAP_LINKS)
+    return fail(MR_ERR_INVALID_ARG, "record offsets are only meaningful for words and links");
   ScopedDevice sd(job->device);
   out->stats = mr_stats{};
   out->status = MR_OK;
@@ -1020,6 +1175,9 @@ extern "C" mr_status mr_run(mr_job* job, mr_map_kind kind, mr_reduce_op op, cons
       break;
     case MR_MAP_BLOOM:
       s = run_bloom(job, op, d_input, input_bytes, key_range, out);
+      break;
+    case MR_MAP_LINKS:
+      s = run_links(job, op, d_input, input_bytes, d_record_offsets, n_records, out);
       break;
     default:
       return fail(MR_ERR_INVALID_ARG, "unknown map kind %d", (int)kind);

@@ -56,6 +56,7 @@ struct WordJob {
   uint64_t cap_keys;
   uint64_t cap_key_bytes;
   JobState* st;
+  uint32_t* slot_rank;       // [cap] output rank of the key in each table slot, or NULL
 };
 
 // Compacted table entry of a word, ordered by (p, len) then tail bytes.

@@ -25,12 +25,45 @@ struct WordsLaunch {
   unsigned long long* bucket_bstart;
   uint32_t* bucket_fill;
   JobState* states;           // device [n_jobs]
+  // Reverse Index map instead of the word map (one job)
+  bool links;
+  uint32_t link_grid;
+  uint32_t* link_marks;       // device [link_cap] marker offsets
+  unsigned long long* link_n; // device: markers found
+  uint64_t link_cap;
+  uint32_t* link_pair_slot;          // device [link_cap] table slot of the link's URL (all ones: no link)
+  uint32_t* link_pair_file;          // device [link_cap] record of the link
 };
 
 hipError_t words_enqueue_zero_states(const WordsLaunch& L, hipStream_t s);
 hipError_t words_enqueue_prep(const WordsLaunch& L, hipStream_t s);
 hipError_t words_enqueue_map(const WordsLaunch& L, hipStream_t s);
 hipError_t words_enqueue_reduce(const WordsLaunch& L, hipStream_t s);
+
+// Reverse Index file lists from the pairs and the sorted URLs (links.hip)
+struct LinksPost {
+  const uint32_t* pair_slot;    // table slot of each link's URL (all ones: no link)
+  const uint32_t* pair_file;
+  uint64_t n;                   // pairs (markers)
+  const uint32_t* slot_rank;    // output rank of the URL in each table slot
+  uint64_t n_keys;              // distinct URLs
+  int file_bits;                // bits of a record index
+  int sort_bits;                // rank bits + file bits, a multiple of 8
+  unsigned long long *k0, *v0, *k1, *v1;  // [n] each
+  uint32_t* hist;               // radix histogram
+  uint32_t* scan_sums;
+  uint32_t* head;               // [n]
+  unsigned long long* total;    // device: distinct (URL, file) pairs
+  unsigned long long* n_valid;  // device: links
+  uint32_t* flags;              // device: internal errors
+  uint32_t* first;              // [n_keys + 1] first sorted pair of each rank
+};
+hipError_t links_enqueue_rank_sort(const LinksPost& P, bool* sorted_in_1, hipStream_t s);
+hipError_t links_enqueue_write(const LinksPost& P, bool sorted_in_1, uint32_t* ids, uint64_t* list_off, uint32_t* counts,
+                               hipStream_t s);
+uint64_t links_hist_words(uint64_t n);
+hipError_t radix_sort64(unsigned long long* k0, unsigned long long* v0, unsigned long long* k1, unsigned long long* v1,
+                        uint64_t n, int bits, uint32_t* hist, uint32_t* scan_sums, bool* result_in_1, hipStream_t s);
 
 uint32_t rgb_grid(uint64_t n, int n_cu);
 hipError_t rgb_enqueue(const uint8_t* in, uint64_t n, uint32_t* partials, uint32_t G, unsigned long long* out,

@@ -96,6 +96,20 @@ MR_DEV uint4 load_key16(const uint8_t* in, uint64_t off, uint32_t len) {
   return extract16(w, s, len);
 }
 
+// Three-way unsigned bytewise compare of in[oa + s, oa + m) and in[ob + s, ob + m),
+// 16 bytes per step.
+MR_DEV int input_cmp(const uint8_t* in, uint64_t oa, uint64_t ob, uint64_t s, uint64_t m) {
+  for (uint64_t b = s; b < m; b += 16) {
+    const uint32_t take = (uint32_t)((m - b) < 16 ? (m - b) : 16);
+    const uint4 x = load_key16(in, oa + b, take), y = load_key16(in, ob + b, take);
+    if (x.x != y.x) return bswap32(x.x) < bswap32(y.x) ? -1 : 1;
+    if (x.y != y.y) return bswap32(x.y) < bswap32(y.y) ? -1 : 1;
+    if (x.z != y.z) return bswap32(x.z) < bswap32(y.z) ? -1 : 1;
+    if (x.w != y.w) return bswap32(x.w) < bswap32(y.w) ? -1 : 1;
+  }
+  return 0;
+}
+
 MR_DEV uint64_t key_hash16(uint4 k, uint32_t len, uint32_t debug_hash) {
   if (debug_hash) return (uint64_t)len * 0x9E3779B97F4A7C15ULL;
   return hash_block(hash_seed(len), ((uint64_t)k.y << 32) | k.x, ((uint64_t)k.w << 32) | k.z);
@@ -166,9 +180,7 @@ MR_DEV bool rep_equals_global(const WordJob& J, uint64_t vlo, uint64_t vhi, uint
   if (!rep_in_bounds(J, rep_off, len)) return false;
   // the length tag saturates at 0xFFFF: then compare the true lengths too
   if (len >= 0xFFFFull && word_length_slow(J, vlo, vhi, rep_off) != len) return false;
-  for (uint64_t i = 0; i < len; ++i)
-    if (J.in[rep_off + i] != J.in[off + i]) return false;
-  return true;
+  return input_cmp(J.in, rep_off, off, 0, len) == 0;
 }
 
 // Longest probe sequence before the table counts as full. At the planned
@@ -178,10 +190,12 @@ MR_DEV bool rep_equals_global(const WordJob& J, uint64_t vlo, uint64_t vhi, uint
 constexpr uint64_t kMaxProbe = 512;
 
 // Insert one key with value v. Inline keys (len <= 16) come with k; longer
-// keys are compared against the input at off. Returns false on a full table.
+// keys are compared against the input at off. Returns false on a full table;
+// otherwise the key's slot goes to *slot_out when it is given. v = 0 claims
+// or finds the slot without touching its count.
 template <bool kInline>
 MR_DEV bool g_insert(const WordJob& J, uint64_t vlo, uint64_t vhi, uint64_t off, uint64_t len, uint64_t h, uint4 k,
-                     uint32_t v, uint32_t debug_hash) {
+                     uint32_t v, uint32_t debug_hash, uint64_t* slot_out = nullptr) {
   const uint64_t word = gword(off, len, h);
   const uint64_t mask = J.cap - 1;
   // (with every key forced onto one hash the whole table is one run)
@@ -194,7 +208,8 @@ MR_DEV bool g_insert(const WordJob& J, uint64_t vlo, uint64_t vhi, uint64_t off,
     if (cur == 0ull) {
       const unsigned long long old = atomicCAS(&J.tw[i], 0ull, (unsigned long long)word);
       if (old == 0ull) {
-        atomicAdd(&J.tc[i], v);
+        if (v) atomicAdd(&J.tc[i], v);
+        if (slot_out) *slot_out = i;
         return true;
       }
       cur = old;
@@ -203,7 +218,8 @@ MR_DEV bool g_insert(const WordJob& J, uint64_t vlo, uint64_t vhi, uint64_t off,
       const uint64_t rep = cur >> 32;
       const bool eq = kInline ? rep_equals_inline(J, rep, k, (uint32_t)len) : rep_equals_global(J, vlo, vhi, rep, off, len);
       if (eq) {
-        atomicAdd(&J.tc[i], v);
+        if (v) atomicAdd(&J.tc[i], v);
+        if (slot_out) *slot_out = i;
         return true;
       }
     }
@@ -583,7 +599,7 @@ __global__ __launch_bounds__(kCompactThreads) void k_words_compact(const WordJob
       r.len = (uint32_t)len;
       r.off = (uint32_t)off;
       r.cnt = cnt;
-      r.pad = 0;
+      r.pad = (uint32_t)i;  // the table slot, for callers that map slots to output ranks
       reinterpret_cast<WRec*>(J.recs)[s_base + atomicAdd(&s_pos, 1u)] = r;
       bytes += len;
     }
@@ -603,11 +619,8 @@ MR_DEV int wrec_cmp(const WordJob& J, const WRec& a, const WRec& b) {
   for (int q = 0; q < 4; ++q)
     if (a.p[q] != b.p[q]) return a.p[q] < b.p[q] ? -1 : 1;
   if (a.len > 16u && b.len > 16u) {
-    const uint32_t m = (a.len < b.len ? a.len : b.len);
-    for (uint32_t i = 16; i < m; ++i) {
-      const uint8_t x = J.in[a.off + i], y = J.in[b.off + i];
-      if (x != y) return x < y ? -1 : 1;
-    }
+    const int c = input_cmp(J.in, a.off, b.off, 16, a.len < b.len ? a.len : b.len);
+    if (c) return c;
   }
   return a.len < b.len ? -1 : (a.len > b.len ? 1 : 0);
 }
@@ -667,12 +680,8 @@ MR_DEV int soa_cmp(const WordJob& J, const WRec* recs, const SoaKeys<CAP>& S, ui
   }
   const uint32_t la = S.len[i], lb = S.len[l];
   if (la > 16u && lb > 16u) {
-    const uint32_t oa = recs[S.ix[i]].off, ob = recs[S.ix[l]].off;
-    const uint32_t m = la < lb ? la : lb;
-    for (uint32_t t = 16; t < m; ++t) {
-      const uint8_t x = J.in[oa + t], y = J.in[ob + t];
-      if (x != y) return x < y ? -1 : 1;
-    }
+    const int c = input_cmp(J.in, recs[S.ix[i]].off, recs[S.ix[l]].off, 16, la < lb ? la : lb);
+    if (c) return c;
   }
   return la < lb ? -1 : (la > lb ? 1 : 0);
 }
@@ -980,13 +989,21 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_buckets(const WordJob* __
         const uint64_t o = y0 + excl;
         J.out_key_offsets[s0 + i] = o;
         J.out_values[s0 + i] = r.cnt;
+        if (J.slot_rank) J.slot_rank[r.pad] = (uint32_t)(s0 + i);
         if (r.len <= 16u) {
           // the key is the big-endian prefix itself
 #pragma unroll
           for (uint32_t b = 0; b < 16u; ++b)
             if (b < r.len) J.out_key_bytes[o + b] = (uint8_t)(r.p[b >> 2] >> (24 - 8 * (b & 3)));
         } else {
-          for (uint32_t b = 0; b < r.len; ++b) J.out_key_bytes[o + b] = J.in[r.off + b];
+          for (uint32_t b0 = 0; b0 < r.len; b0 += 16) {  // 16 bytes loaded per step
+            const uint32_t take = r.len - b0 < 16u ? r.len - b0 : 16u;
+            const uint4 k = load_key16(J.in, r.off + b0, take);
+            const uint32_t w[4] = {k.x, k.y, k.z, k.w};
+#pragma unroll
+            for (uint32_t b = 0; b < 16u; ++b)
+              if (b < take) J.out_key_bytes[o + b0 + b] = (uint8_t)(w[b >> 2] >> (8 * (b & 3)));
+          }
         }
       }
       carry += tot;
@@ -1008,6 +1025,153 @@ __global__ void k_words_finish(const WordJob* __restrict__ jobs, uint32_t n_jobs
 // ----------------------------------------------------------------------------
 
 int words_max_lds_log2() { return 12; }
+
+// ----------------------------------------------------------------------------
+// links: the map of the Reverse Index (Table of benchmark applications). A
+// link is the nine bytes <a href=" followed by a URL of 1..4095 bytes other
+// than a double quote and then a double quote, all inside one record (file).
+// Every start position is tried, so links may overlap. Each URL goes into
+// the job's global table (the same table, compaction and sort as words) and
+// (table slot, record) into a pair list, from which the link counts and the
+// file lists are built: counting in the table would serialise the many links
+// of a popular URL on one atomic.
+// ----------------------------------------------------------------------------
+
+constexpr uint32_t kLinkMaxUrl = 4095;
+constexpr uint32_t kLinkFindThreads = 256;
+constexpr uint32_t kLinkGroup = 64;   // input bytes per lane per step (four 16-byte chunks)
+constexpr uint32_t kLinkBuf = 4096;   // marker offsets staged per workgroup
+constexpr uint32_t kLinkStepMax = kLinkFindThreads * (kLinkGroup / 9 + 1);  // markers one step can add
+constexpr uint32_t kMarkW0 = 0x6820613Cu;  // '<' 'a' ' ' 'h'
+constexpr uint32_t kMarkW1 = 0x3D666572u;  // 'r' 'e' 'f' '='
+constexpr uint32_t kMarkW2 = 0x22u;        // '"'
+
+// Bit i set when byte i of the 16-byte block may equal c (a superset of the
+// true positions: each one is checked afterwards).
+MR_DEV uint32_t byte_candidates16(uint4 b, uint32_t c) {
+  const uint32_t rep = c * 0x01010101u;
+  uint32_t m = 0;
+  const uint32_t w[4] = {b.x, b.y, b.z, b.w};
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const uint32_t t = w[q] ^ rep;
+    const uint32_t z = (t - 0x01010101u) & ~t & 0x80808080u;
+    m |= (((z >> 7) & 1u) | ((z >> 14) & 2u) | ((z >> 21) & 4u) | ((z >> 28) & 8u)) << (4 * q);
+  }
+  return m;
+}
+
+__global__ void k_links_zero(unsigned long long* n_marks) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *n_marks = 0ull;
+}
+
+// Input offsets of every marker inside the valid byte range of job 0. Marks
+// past mark_cap are counted but not stored (the caller grows the list and
+// runs again).
+__global__ __launch_bounds__(kLinkFindThreads) void k_links_find(const WordJob* __restrict__ jobs, uint32_t* __restrict__ marks,
+                                                                 unsigned long long* __restrict__ n_marks, uint64_t mark_cap) {
+  __shared__ uint32_t buf[kLinkBuf];
+  __shared__ uint32_t cnt;
+  __shared__ unsigned long long base;
+  const WordJob J = jobs[0];
+  const uint64_t a_in = (uint64_t)J.in;
+  const uint64_t a0 = a_in + J.st->valid_lo, a1 = a_in + J.st->valid_hi;
+  const uint64_t g0 = a0 / kLinkGroup, g1 = (a1 + kLinkGroup - 1) / kLinkGroup;
+  if (threadIdx.x == 0) cnt = 0;
+  __syncthreads();
+  auto flush = [&]() {
+    if (threadIdx.x == 0) base = cnt ? atomicAdd(n_marks, (unsigned long long)cnt) : 0ull;
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < cnt; i += blockDim.x)
+      if (base + i < mark_cap) marks[base + i] = buf[i];
+    __syncthreads();
+    if (threadIdx.x == 0) cnt = 0;
+    __syncthreads();
+  };
+  // the step base is the same for every lane of the workgroup, so all lanes meet every barrier
+  for (uint64_t step = g0 + (uint64_t)blockIdx.x * blockDim.x; step < g1; step += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t g = step + threadIdx.x;
+    if (g < g1) {
+      const uint64_t ga = g * kLinkGroup;
+      uint4 blk[5];
+#pragma unroll
+      for (int c = 0; c < 5; ++c) blk[c] = load_block(a0, a1, ga + 16ull * c);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        uint32_t cand = byte_candidates16(blk[c], '<');
+        if (!cand) continue;
+        const uint32_t w[8] = {blk[c].x, blk[c].y, blk[c].z, blk[c].w, blk[c + 1].x, blk[c + 1].y, blk[c + 1].z, blk[c + 1].w};
+        while (cand) {
+          const uint32_t sb = __builtin_ctz(cand);
+          cand &= cand - 1;
+          const uint64_t pa = ga + 16ull * c + sb;
+          if (pa < a0 || pa + 9 > a1) continue;
+          const uint4 k = extract16(w, sb, 9);
+          if (k.x == kMarkW0 && k.y == kMarkW1 && k.z == kMarkW2) buf[atomicAdd(&cnt, 1u)] = (uint32_t)(pa - a_in);
+        }
+      }
+    }
+    __syncthreads();
+    if (cnt > kLinkBuf - kLinkStepMax) flush();
+  }
+  __syncthreads();
+  flush();
+}
+
+// One lane per marker: the record, the closing quote, the table insert and
+// the (URL, record) pair: the URL's table slot, or all ones when the marker
+// starts no link (or the table is full and the pass will be repeated).
+__global__ __launch_bounds__(256) void k_links_insert(const WordJob* __restrict__ jobs, const uint32_t* __restrict__ marks,
+                                                      const unsigned long long* __restrict__ n_marks, uint64_t mark_cap,
+                                                      uint32_t* __restrict__ pair_slot, uint32_t* __restrict__ pair_file,
+                                                      uint32_t debug_hash) {
+  const WordJob J = jobs[0];
+  const uint64_t nm = *n_marks < mark_cap ? *n_marks : mark_cap;
+  const uint64_t vlo = J.st->valid_lo, vhi = J.st->valid_hi;
+  const uint64_t a_in = (uint64_t)J.in;
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < nm; i += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t p = marks[i];
+    uint64_t rend = vhi;
+    uint32_t file = 0;
+    bool ok = true;
+    if (J.rec) {
+      const uint64_t r = rec_lower_bound(J.rec, J.n_rec, p + 1);  // first record start above p
+      ok = r >= 1 && r <= J.n_rec;
+      if (ok) {
+        file = (uint32_t)(r - 1);
+        rend = J.rec[r] < vhi ? J.rec[r] : vhi;
+      }
+    }
+    const uint64_t u = p + 9;
+    ok = ok && u <= rend;
+    uint64_t q = ~0ull;
+    if (ok) {
+      const uint64_t lim = (u + kLinkMaxUrl + 1) < rend ? (u + kLinkMaxUrl + 1) : rend;  // the quote lies in [u, lim)
+      for (uint64_t blk = (a_in + u) & ~15ull; blk < a_in + lim && q == ~0ull; blk += 16) {
+        const uint4 b = *reinterpret_cast<const uint4*>(blk);  // overlaps [in + u, in + lim), inside the input
+        uint32_t m = byte_candidates16(b, '"');
+        while (m) {
+          const uint32_t sb = __builtin_ctz(m);
+          m &= m - 1;
+          const uint64_t at = blk + sb;
+          if (at < a_in + u || at >= a_in + lim) continue;
+          if (((sb < 4 ? b.x : sb < 8 ? b.y : sb < 12 ? b.z : b.w) >> (8 * (sb & 3)) & 0xFFu) != 0x22u) continue;
+          q = at - a_in;
+          break;
+        }
+      }
+    }
+    const uint64_t len = q != ~0ull ? q - u : 0ull;
+    uint64_t slot = ~0ull;
+    if (ok && len >= 1 && len <= kLinkMaxUrl) {
+      const uint64_t h = key_hash_global(J.in, u, len, debug_hash);
+      if (len <= 16) g_insert<true>(J, vlo, vhi, u, len, h, load_key16(J.in, u, (uint32_t)len), 0u, debug_hash, &slot);
+      else g_insert<false>(J, vlo, vhi, u, len, h, make_uint4(0, 0, 0, 0), 0u, debug_hash, &slot);
+    }
+    pair_slot[i] = slot != ~0ull ? (uint32_t)slot : ~0u;
+    pair_file[i] = file;
+  }
+}
 
 __global__ void k_zero_states(JobState* st, uint32_t n) {
   uint32_t* p = reinterpret_cast<uint32_t*>(st);
@@ -1032,6 +1196,14 @@ hipError_t words_enqueue_prep(const WordsLaunch& L, hipStream_t s) {
 }
 
 hipError_t words_enqueue_map(const WordsLaunch& L, hipStream_t s) {
+  if (L.links) {
+    hipLaunchKernelGGL(k_links_zero, dim3(1), dim3(64), 0, s, L.link_n);
+    hipLaunchKernelGGL(k_links_find, dim3(L.link_grid), dim3(kLinkFindThreads), 0, s, L.jobs, L.link_marks, L.link_n,
+                       L.link_cap);
+    hipLaunchKernelGGL(k_links_insert, dim3(L.link_grid), dim3(256), 0, s, L.jobs, L.link_marks, L.link_n, L.link_cap,
+                       L.link_pair_slot, L.link_pair_file, L.debug_hash);
+    return hipGetLastError();
+  }
   const dim3 grid(L.map_grid), block(kMapThreads);
 #define MR_MAP_CASE(LG)                                                                                       \
   case LG:                                                                                                     \
