@@ -49,7 +49,7 @@ struct LinksPost {
   uint64_t n_keys;              // distinct URLs
   int file_bits;                // bits of a record index
   int sort_bits;                // rank bits + file bits, a multiple of 8
-  unsigned long long *k0, *v0, *k1, *v1;  // [n] each
+  unsigned long long *k0, *v0, *k1, *v1;  // [n] each: sort keys, unused values, and their second buffers
   uint32_t* hist;               // radix histogram
   uint32_t* scan_sums;
   uint32_t* head;               // [n]

@@ -28,36 +28,28 @@ __global__ void k_links_init(unsigned long long* total, unsigned long long* n_va
 // Sort key of each pair: (output rank of its URL) << file_bits | record; all
 // ones for a marker that starts no link (those sort last).
 __global__ __launch_bounds__(kLinksThreads) void k_links_rank(LinksPost P) {
-  const uint32_t lane = lane_id();
-  for (uint64_t base = blockIdx.x * (uint64_t)blockDim.x; base < P.n; base += (uint64_t)gridDim.x * blockDim.x) {
-    const uint64_t i = base + threadIdx.x;
-    bool valid = false;
-    if (i < P.n) {
-      const uint32_t slot = P.pair_slot[i];
-      unsigned long long key = ~0ull;
-      if (slot != ~0u) {
-        const uint32_t rank = P.slot_rank[slot];
-        if (rank < P.n_keys) {
-          key = ((unsigned long long)rank << P.file_bits) | P.pair_file[i];
-          valid = true;
-        } else {
-          atomicOr(P.flags, kFlagInternal);  // every URL of the table has an output rank
-        }
-      }
-      P.k0[i] = key;
-      P.v0[i] = 0ull;
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < P.n; i += (uint64_t)gridDim.x * blockDim.x) {
+    const uint32_t slot = P.pair_slot[i];
+    unsigned long long key = ~0ull;
+    if (slot != ~0u) {
+      const uint32_t rank = P.slot_rank[slot];
+      if (rank < P.n_keys) key = ((unsigned long long)rank << P.file_bits) | P.pair_file[i];
+      else atomicOr(P.flags, kFlagInternal);  // every URL of the table has an output rank
     }
-    const unsigned long long b = __ballot(valid);
-    if (lane == 0 && b) atomicAdd(P.n_valid, (unsigned long long)__popcll(b));
+    P.k0[i] = key;
+    P.v0[i] = 0ull;  // the sort carries values; these are not used
   }
 }
 
-// head[i] = 1 for the first of each run of equal valid keys.
+// head[i] = 1 for the first of each run of equal valid keys; the last valid
+// key writes the number of links (valid keys come first).
 __global__ __launch_bounds__(kLinksThreads) void k_links_heads(const unsigned long long* __restrict__ k, uint64_t n,
-                                                               uint32_t* __restrict__ head) {
+                                                               uint32_t* __restrict__ head,
+                                                               unsigned long long* __restrict__ n_valid) {
   for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
     const unsigned long long x = k[i];
     head[i] = (x != ~0ull && (i == 0 || x != k[i - 1])) ? 1u : 0u;
+    if (x != ~0ull && (i + 1 == n || k[i + 1] == ~0ull)) *n_valid = i + 1;
   }
 }
 
@@ -111,7 +103,7 @@ hipError_t links_enqueue_rank_sort(const LinksPost& P, bool* sorted_in_1, hipStr
   hipError_t e = radix_sort64(P.k0, P.v0, P.k1, P.v1, P.n, P.sort_bits, P.hist, P.scan_sums, sorted_in_1, s);
   if (e != hipSuccess) return e;
   const unsigned long long* k = *sorted_in_1 ? P.k1 : P.k0;
-  hipLaunchKernelGGL(k_links_heads, dim3(links_grid(P.n)), dim3(kLinksThreads), 0, s, k, P.n, P.head);
+  hipLaunchKernelGGL(k_links_heads, dim3(links_grid(P.n)), dim3(kLinksThreads), 0, s, k, P.n, P.head, P.n_valid);
   return scan_exclusive_u32(P.head, P.n, P.scan_sums, P.total, s);
 }
 

@@ -1093,7 +1093,7 @@ __global__ __launch_bounds__(kLinkFindThreads) void k_links_find(const WordJob* 
     const uint64_t g = step + threadIdx.x;
     if (g < g1) {
       const uint64_t ga = g * kLinkGroup;
-      uint4 blk[5];
+      uint4 blk[5];  // the group and the block after it (for markers that cross the group's end)
 #pragma unroll
       for (int c = 0; c < 5; ++c) blk[c] = load_block(a0, a1, ga + 16ull * c);
 #pragma unroll
