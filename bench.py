@@ -124,11 +124,22 @@ def bench_batched(torch, reps=3):
     res_b = batch.words_batch(dev, prepared=prep)
     same = all(torch.equal(a.key_bytes, b.key_bytes) and torch.equal(a.values, b.values)
                for a, b in zip(first, res_b))
+    # the same batch with the autotuned launch parameters (tile share, LDS cache, load limit)
+    tuned = Job(device=0)
+    tuned.load_tuning()
+    prep_t = tuned.batch_prepare(dev, cap_keys=[len(r) + 16 for r in first],
+                                 cap_bytes=[int(r.key_bytes.numel()) + 64 for r in first])
+    res_t = tuned.words_batch(dev, prepared=prep_t)
+    same = same and all(torch.equal(a.key_bytes, b.key_bytes) and torch.equal(a.values, b.values)
+                        for a, b in zip(first, res_t))
     ms_p, _ = time_steps(run_plain, reps, 1, torch)
     ms_b, _ = time_steps(lambda: batch.words_batch(dev, prepared=prep), reps, 1, torch)
-    return {"jobs": len(dev), "bytes": total, "plain_ms": ms_p, "batched_ms": ms_b,
+    ms_t, _ = time_steps(lambda: tuned.words_batch(dev, prepared=prep_t), reps, 1, torch)
+    return {"jobs": len(dev), "bytes": total, "plain_ms": ms_p, "batched_ms": ms_b, "batched_tuned_ms": ms_t,
             "plain_jobs_per_s": len(dev) / (ms_p * 1e-3), "batched_jobs_per_s": len(dev) / (ms_b * 1e-3),
-            "batched_GBps": total / (ms_b * 1e-3) / 1e9, "speedup": ms_p / ms_b, "outputs_identical": bool(same)}
+            "batched_tuned_jobs_per_s": len(dev) / (ms_t * 1e-3), "batched_GBps": total / (ms_b * 1e-3) / 1e9,
+            "batched_tuned_GBps": total / (ms_t * 1e-3) / 1e9, "speedup": ms_p / ms_b, "speedup_tuned": ms_p / ms_t,
+            "outputs_identical": bool(same)}
 
 
 def bench_selector(torch, n_jobs=200):
@@ -330,7 +341,8 @@ def main():
     if "batched" in apps:
         bt = bench_batched(torch)
         per_app["batched_word_count_256_jobs"] = bt
-        log(f"batched: {bt['batched_jobs_per_s']:.0f} jobs/s vs plain {bt['plain_jobs_per_s']:.0f} jobs/s")
+        log(f"batched: {bt['batched_jobs_per_s']:.0f} jobs/s, tuned {bt['batched_tuned_jobs_per_s']:.0f} jobs/s, "
+            f"vs plain {bt['plain_jobs_per_s']:.0f} jobs/s")
     if "selector" in apps:
         sl = bench_selector(torch)
         per_app["selector_heldout_jobs"] = sl

@@ -274,6 +274,34 @@ mr_status mr_mlp_loss_backward(mr_job* job, const float* params, const float* X,
 mr_status mr_mlp_adam(mr_job* job, float* params, const float* grad, float* m, float* v, uint32_t step, float lr,
                       float beta1, float beta2, float eps);
 
+/* --------------------------------------------------------------------------
+ * Tuned launch parameters (the batched workload's tile, load-factor and
+ * privatisation thresholds). An entry covers the jobs of one map kind whose
+ * input size lies in [bytes_lo, bytes_hi); the first matching entry is used.
+ * The word map's LDS slots and grid follow the bytes one launch covers (a
+ * batch's total); each job's table load follows its own size. A nonzero field of
+ * mr_job_config still wins over an entry, and an entry's zero field keeps
+ * the built-in default. The project's autotuner times candidate settings
+ * with this runtime and keeps the fastest per size bucket; outputs do not
+ * depend on these parameters.
+ * -------------------------------------------------------------------------- */
+typedef struct {
+  mr_map_kind kind;         /* MR_MAP_WORDS, MR_MAP_U32_KEYS or MR_MAP_U32_KV */
+  uint64_t bytes_lo;        /* input sizes [bytes_lo, bytes_hi) */
+  uint64_t bytes_hi;
+  uint32_t lds_slots;       /* word map: LDS hash cache slots per workgroup (256, 1024, 2048 or 4096) */
+  uint32_t max_load_pct;    /* global hash table load limit in percent (1..95) */
+  uint32_t map_grid_pct;    /* word map: workgroups as a percentage of the CUs (1..100); fewer workgroups
+                               take more 16 KiB tiles each and flush fewer LDS caches */
+  uint32_t lds_array_bytes; /* uint32 jobs under the rule: LDS bytes a key range may take as
+                               per-workgroup arrays (1..65536); larger ranges use the global array */
+} mr_tune_entry;
+
+/* Replace the job's tuned entries with entries[0, n) (copied). n = 0 clears
+ * them. Errors: MR_ERR_INVALID_ARG for an unsupported kind, an empty size
+ * range or a field outside its range (nothing is changed then). */
+mr_status mr_tune_set(mr_job* job, const mr_tune_entry* entries, uint32_t n);
+
 #ifdef __cplusplus
 }
 #endif

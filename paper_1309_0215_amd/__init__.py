@@ -60,6 +60,23 @@ def _stats(o: L.Output) -> dict:
             "selector_used": s.selector_used}
 
 
+TUNE_KINDS = {"words": L.MAP_WORDS, "u32": L.MAP_U32_KEYS, "u32_kv": L.MAP_U32_KV}
+TUNE_FIELDS = ("lds_slots", "max_load_pct", "map_grid_pct", "lds_array_bytes")
+
+
+def tune_entries(entries):
+    """mr_tune_entry array from dicts with keys kind ("words", "u32" or
+    "u32_kv"), bytes_lo, bytes_hi and any of TUNE_FIELDS (missing = 0, the
+    default)."""
+    arr = (L.TuneEntry * max(1, len(entries)))()
+    for i, e in enumerate(entries):
+        arr[i].kind = TUNE_KINDS[e["kind"]]
+        arr[i].bytes_lo, arr[i].bytes_hi = int(e["bytes_lo"]), int(e["bytes_hi"])
+        for f in TUNE_FIELDS:
+            setattr(arr[i], f, int(e.get(f, 0)))
+    return arr
+
+
 @dataclass
 class LinksResult:
     """Reverse index on the device: URLs (key_bytes, key_offsets), link counts,
@@ -114,6 +131,17 @@ class Job:
         h = C.c_void_p()
         L.check(self.lib.mr_job_create(C.byref(cfg), C.byref(h)), "mr_job_create")
         self.h = h
+
+    def set_tuning(self, entries):
+        """Tuned launch parameters (see tune_entries); an empty list clears them."""
+        L.check(self.lib.mr_tune_set(self.h, tune_entries(entries), len(entries)), "mr_tune_set")
+
+    def load_tuning(self, path: str | None = None):
+        """Apply the entries of a tuning file written by paper_1309_0215_amd.autotune."""
+        import json
+        from .autotune import TUNING_PATH
+        with open(path or TUNING_PATH) as f:
+            self.set_tuning(json.load(f)["entries"])
 
     def close(self):
         if getattr(self, "h", None):

@@ -26,7 +26,7 @@ MLP_PARAMS = 5252
 EXPORTS = [
     "mr_status_str", "mr_last_error", "mr_job_create", "mr_job_destroy", "mr_run", "mr_batch_run",
     "mr_job_features", "mr_selector_set", "mr_selector_predict", "mr_mlp_forward", "mr_mlp_loss_backward",
-    "mr_mlp_adam",
+    "mr_mlp_adam", "mr_tune_set",
 ]
 
 
@@ -85,6 +85,18 @@ class Output(C.Structure):
     ]
 
 
+class TuneEntry(C.Structure):
+    _fields_ = [
+        ("kind", C.c_int),
+        ("bytes_lo", C.c_uint64),
+        ("bytes_hi", C.c_uint64),
+        ("lds_slots", C.c_uint32),
+        ("max_load_pct", C.c_uint32),
+        ("map_grid_pct", C.c_uint32),
+        ("lds_array_bytes", C.c_uint32),
+    ]
+
+
 class BatchItem(C.Structure):
     _fields_ = [
         ("kind", C.c_int),
@@ -123,6 +135,8 @@ def load(required: bool = True):
     lib.mr_run.argtypes = [P, C.c_int, C.c_int, P, U64, P, U64, U64, C.POINTER(Output)]
     lib.mr_batch_run.restype = I32
     lib.mr_batch_run.argtypes = [P, C.POINTER(BatchItem), U32, C.POINTER(Output)]
+    lib.mr_tune_set.restype = I32
+    lib.mr_tune_set.argtypes = [P, C.POINTER(TuneEntry), U32]
     if hasattr(lib, "mr_job_features"):
         lib.mr_job_features.restype = I32
         lib.mr_job_features.argtypes = [P, C.c_int, C.c_int, P, U64, U64, P]

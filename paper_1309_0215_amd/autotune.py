@@ -1,0 +1,177 @@
+"""Autotuner of the runtime's launch parameters (the batched workload's tile,
+load-factor and privatisation thresholds).
+
+For each input-size bucket the tuner runs seeded synthetic jobs under every
+candidate setting, times them with the runtime's own device timers, checks
+that every setting gives the same outputs as the defaults, and keeps the
+setting with the least total time when it saves at least 3% over the
+defaults (otherwise the bucket keeps them). The result is a list of mr_tune_entry
+records (see mr_tune_set in include/mr.h) saved as JSON with the device
+name, the ROCm version and every measurement.
+
+Word jobs tune three parameters:
+* lds_slots: the per-workgroup LDS hash cache (privatisation capacity);
+* map_grid_pct: map workgroups as a share of the CUs, i.e. how many 16 KiB
+  tiles each workgroup takes (each workgroup flushes its cache once);
+* max_load_pct: the global table's load limit, hence its size.
+Buckets below 64 MiB are tuned on single jobs of the batched recipe (sizes
+log-uniform within the bucket, vocabularies 1 K-1 M, Zipf s in [0.6, 1.4]);
+the two largest on whole batches of such jobs, since a batch is looked up by
+the bytes its launch covers.
+
+uint32 jobs tune max_load_pct (hash table, no declared range) and
+lds_array_bytes (the rule's limit for per-workgroup arrays, ranges of 6,000
+and 12,000 keys).
+"""
+from __future__ import annotations
+
+import itertools
+import json
+import os
+import time
+
+import numpy as np
+
+TUNING_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_mi355x.json")
+
+KiB, MiB = 1 << 10, 1 << 20
+MIN_GAIN = 0.03  # a setting replaces the defaults only when it saves at least this fraction of the time
+WORD_BUCKETS = [(0, 256 * KiB), (256 * KiB, MiB), (MiB, 4 * MiB), (4 * MiB, 16 * MiB), (16 * MiB, 64 * MiB),
+                (64 * MiB, 256 * MiB), (256 * MiB, 1 << 62)]
+WORD_CANDIDATES = [dict(lds_slots=l, max_load_pct=f, map_grid_pct=g)
+                   for l, f, g in itertools.product((1024, 2048, 4096), (35, 50, 70), (25, 50, 100))]
+U32_BUCKETS = [(0, MiB), (MiB, 16 * MiB), (16 * MiB, 1 << 62)]
+U32_CANDIDATES = [dict(max_load_pct=f, lds_array_bytes=b) for f, b in itertools.product((35, 50, 70),
+                                                                                       (16 * KiB, 32 * KiB, 64 * KiB))]
+
+
+def _word_specs(lo: int, hi: int, seed: int):
+    """Jobs for a word bucket: three single jobs, or, for the two largest
+    buckets, one batch of recipe jobs whose total lies in the bucket."""
+    import gen
+    if lo >= 64 * MiB:
+        target = 1.25 * lo
+        specs, total = [], 0
+        for sp in gen.batched_specs(seed=seed, n_jobs=1024):
+            specs.append(sp)
+            total += sp.size
+            if total >= target:
+                break
+        assert lo <= total < hi
+        return specs, True
+    return gen.batched_specs(seed=seed, n_jobs=3, size_lo=max(lo, 32 * KiB), size_hi=hi), False
+
+
+def _time_words(torch, job, dev, batch: bool, reps: int):
+    """Median device time (ms) of the job list, and its outputs."""
+    ts, res = [], None
+    for _ in range(reps):
+        if batch:
+            r = job.words_batch(dev)
+            t = max(x.stats["gpu_ms"] for x in r)  # every item reports the batch's device time
+        else:
+            r = [job.words(d) for d in dev]
+            t = sum(x.stats["gpu_ms"] for x in r)
+        ts.append(t)
+        res = r
+    return float(np.median(ts)), res
+
+
+def _same_words(a, b, torch) -> bool:
+    return all(torch.equal(x.key_bytes, y.key_bytes) and torch.equal(x.key_offsets, y.key_offsets) and
+               torch.equal(x.values, y.values) for x, y in zip(a, b))
+
+
+def tune_words(torch, seed: int = 11, reps: int = 3, log=print):
+    import gen
+    from . import Job
+    entries, report = [], []
+    for lo, hi in WORD_BUCKETS:
+        specs, batch = _word_specs(lo, hi, seed)
+        dev = [torch.from_numpy(b).to("cuda:0") for b in gen.job_inputs(specs)]
+        total = sum(int(d.numel()) for d in dev)
+        base_job = Job(device=0, timing=1)
+        t0, ref = _time_words(torch, base_job, dev, batch, reps)
+        rows = []
+        for c in WORD_CANDIDATES:
+            job = Job(device=0, timing=1)
+            job.set_tuning([dict(kind="words", bytes_lo=0, bytes_hi=1 << 62, **c)])
+            t, out = _time_words(torch, job, dev, batch, reps)
+            if not _same_words(out, ref, torch):
+                raise RuntimeError(f"outputs differ under {c} in bucket [{lo}, {hi})")
+            rows.append((t, c))
+            job.close()
+        best_t, best = min(rows, key=lambda r: r[0])
+        if best_t > (1 - MIN_GAIN) * t0:
+            best = {}  # within the noise of the defaults: keep them
+        entries.append(dict(kind="words", bytes_lo=lo, bytes_hi=hi, **best))
+        report.append(dict(kind="words", bytes_lo=lo, bytes_hi=hi, batch=batch, jobs=len(dev), bytes=total,
+                           default_ms=t0, best_ms=best_t, best=best,
+                           all=[dict(ms=t, **c) for t, c in rows]))
+        log(f"words [{lo}, {hi}): {len(dev)} jobs, {total / MiB:.1f} MiB, default {t0:.3f} ms, "
+            f"best {best_t:.3f} ms with {best}")
+        del dev
+    return entries, report
+
+
+def tune_u32(torch, seed: int = 12, reps: int = 3, log=print):
+    import gen
+    from . import Job
+    entries, report = [], []
+    for lo, hi in U32_BUCKETS:
+        size = int(min(max(lo * 2, 512 * KiB), 64 * MiB)) // 4
+        jobs = []
+        for card, R in ((100_000, 0), (1_000_000, 0), (6_000, 6_000), (12_000, 12_000)):
+            keys, _ = gen.u32_keys(seed + card, size, card, 1.0)
+            jobs.append((torch.from_numpy(keys.view(np.int32)).to("cuda:0"), R))
+
+        def run(job):
+            ts, outs = [], None
+            for _ in range(reps):
+                rs = [job.u32(k, key_range=R) for k, R in jobs]
+                ts.append(sum(r.stats["gpu_ms"] for r in rs))
+                outs = rs
+            return float(np.median(ts)), outs
+
+        t0, ref = run(Job(device=0, timing=1))
+        rows = []
+        for c in U32_CANDIDATES:
+            job = Job(device=0, timing=1)
+            job.set_tuning([dict(kind="u32", bytes_lo=0, bytes_hi=1 << 62, **c)])
+            t, out = run(job)
+            if not all(torch.equal(a.keys, b.keys) and torch.equal(a.values, b.values) for a, b in zip(out, ref)):
+                raise RuntimeError(f"u32 outputs differ under {c}")
+            rows.append((t, c))
+            job.close()
+        best_t, best = min(rows, key=lambda r: r[0])
+        if best_t > (1 - MIN_GAIN) * t0:
+            best = {}
+        entries.append(dict(kind="u32", bytes_lo=lo, bytes_hi=hi, **best))
+        report.append(dict(kind="u32", bytes_lo=lo, bytes_hi=hi, bytes=4 * size, default_ms=t0, best_ms=best_t,
+                           best=best, all=[dict(ms=t, **c) for t, c in rows]))
+        log(f"u32 [{lo}, {hi}): default {t0:.3f} ms, best {best_t:.3f} ms with {best}")
+    return entries, report
+
+
+def main(argv=None):
+    import argparse
+
+    import torch
+    ap = argparse.ArgumentParser(description="tune the runtime's launch parameters on this GPU")
+    ap.add_argument("--out", default=TUNING_PATH)
+    ap.add_argument("--reps", type=int, default=3)
+    args = ap.parse_args(argv)
+    t0 = time.time()
+    we, wr = tune_words(torch, reps=args.reps)
+    ue, ur = tune_u32(torch, reps=args.reps)
+    props = torch.cuda.get_device_properties(0)
+    doc = {"device": props.name, "arch": getattr(props, "gcnArchName", ""), "rocm": torch.version.hip,
+           "command": "python -m paper_1309_0215_amd.autotune", "seconds": round(time.time() - t0, 1),
+           "entries": we + ue, "measurements": wr + ur}
+    with open(args.out, "w") as f:
+        json.dump(doc, f, indent=1)
+    print(f"wrote {args.out} ({len(doc['entries'])} entries) in {doc['seconds']} s", flush=True)
+
+
+if __name__ == "__main__":
+    main()

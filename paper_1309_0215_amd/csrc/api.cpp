@@ -98,6 +98,8 @@ struct mr_job {
   void* link_dev = nullptr;
   uint64_t link_dev_bytes = 0;
   uint64_t link_cap = 0;
+  // tuned launch parameters by map kind and input size
+  std::vector<mr_tune_entry> tune;
 };
 
 namespace {
@@ -157,6 +159,31 @@ mr_status ensure_host_states(mr_job* job, uint32_t n) {
   MR_HIP(hipHostMalloc(&job->h_states, sizeof(JobState) * n, hipHostMallocDefault));
   job->h_states_cap = n;
   return MR_OK;
+}
+
+// The tuned entry for a job of this kind and input size, or NULL.
+const mr_tune_entry* tune_for(const mr_job* job, mr_map_kind kind, uint64_t bytes) {
+  for (const mr_tune_entry& e : job->tune)
+    if (e.kind == kind && bytes >= e.bytes_lo && bytes < e.bytes_hi) return &e;
+  return nullptr;
+}
+
+// Effective parameters: the job's explicit setting, else the tuned one, else the default.
+uint32_t eff_load_pct(const mr_job* job, mr_map_kind kind, uint64_t bytes) {
+  if (job->cfg.max_load_pct) return job->cfg.max_load_pct;
+  const mr_tune_entry* t = tune_for(job, kind, bytes);
+  return t && t->max_load_pct ? t->max_load_pct : 50u;
+}
+
+uint32_t eff_lds_slots(const mr_job* job, uint64_t bytes) {
+  if (job->cfg.lds_slots) return job->cfg.lds_slots;
+  const mr_tune_entry* t = tune_for(job, MR_MAP_WORDS, bytes);
+  return t && t->lds_slots ? t->lds_slots : 4096u;
+}
+
+uint32_t eff_grid_pct(const mr_job* job, uint64_t bytes) {
+  const mr_tune_entry* t = tune_for(job, MR_MAP_WORDS, bytes);
+  return t && t->map_grid_pct ? t->map_grid_pct : 100u;
 }
 
 }  // namespace
@@ -283,7 +310,7 @@ struct WordItem {
 uint64_t initial_slots(const mr_job* job, uint64_t n) {
   // (at least 4096 slots: the compaction takes 4096-slot pieces of one table)
   if (job->cfg.table_slots) return std::max<uint64_t>(4096, job->cfg.table_slots);
-  const double lf = (job->cfg.max_load_pct ? job->cfg.max_load_pct : 50) / 100.0;
+  const double lf = eff_load_pct(job, MR_MAP_WORDS, n) / 100.0;
   const uint64_t words_ub = (n + 1) / 2;
   uint64_t est = std::min<uint64_t>(words_ub, std::max<uint64_t>(2048, n / 64));
   uint64_t slots = next_pow2((uint64_t)std::ceil(est / lf));
@@ -361,6 +388,16 @@ mr_status words_pass(mr_job* job, std::vector<WordItem>& items, std::vector<JobS
                      float* map_ms, GraphMode mode, LinkBufs* lb) {
   const uint32_t n = (uint32_t)items.size();
   WordsPlan p = plan_words(items, lb != nullptr);
+  // tuned map parameters, looked up by the bytes this launch covers (a
+  // batch by its total; each job's table load factor by its own size)
+  uint64_t size_key = 0;
+  for (const WordItem& it : items) size_key += it.n;
+  const uint32_t lds_slots = eff_lds_slots(job, size_key);
+  int lds_log2 = 0;
+  while ((1u << lds_log2) < lds_slots) ++lds_log2;
+  if (lds_log2 != 8 && lds_log2 != 10 && lds_log2 != 11 && lds_log2 != 12)
+    return fail(MR_ERR_INVALID_ARG, "lds_slots must be 256, 1024, 2048 or 4096");
+  const uint64_t grid_cap = std::max<uint64_t>(1, (uint64_t)job->n_cu * eff_grid_pct(job, size_key) / 100);
   mr_status st = ensure_ws(job, p.c.off);
   if (st != MR_OK) return st;
   uint8_t* ws = job->ws;
@@ -368,7 +405,8 @@ mr_status words_pass(mr_job* job, std::vector<WordItem>& items, std::vector<JobS
   uint64_t key = 0xCBF29CE484222325ull;
   key = fnv_mix(key, (uint64_t)ws);
   key = fnv_mix(key, n);
-  key = fnv_mix(key, job->cfg.lds_slots);
+  key = fnv_mix(key, (uint64_t)lds_log2);
+  key = fnv_mix(key, grid_cap);
   key = fnv_mix(key, job->cfg.debug_hash);
   key = fnv_mix(key, lb ? (uint64_t)lb->marks ^ lb->cap : 0ull);
   for (const WordItem& it : items) {
@@ -464,16 +502,10 @@ mr_status words_pass(mr_job* job, std::vector<WordItem>& items, std::vector<JobS
   L.n_jobs = n;
   L.total_tiles = p.total_tiles;
   L.total_slots = p.total_slots;
-  const uint64_t want_grid = std::max<uint64_t>(1, std::min<uint64_t>(p.total_tiles, (uint64_t)job->n_cu));
+  const uint64_t want_grid = std::max<uint64_t>(1, std::min<uint64_t>(p.total_tiles, grid_cap));
   L.map_grid = (uint32_t)want_grid;
   L.sort_grid = (uint32_t)std::max(1, job->n_cu * 2);
-  L.lds_log2 = 12;
-  if (job->cfg.lds_slots) {
-    int lg = 0;
-    while ((1u << lg) < job->cfg.lds_slots) ++lg;
-    if (lg != 8 && lg != 10 && lg != 11 && lg != 12) return fail(MR_ERR_INVALID_ARG, "lds_slots must be 256, 1024, 2048 or 4096");
-    L.lds_log2 = lg;
-  }
+  L.lds_log2 = lds_log2;
   L.debug_hash = job->cfg.debug_hash;
   L.any_records = any_rec;
   L.totals = reinterpret_cast<uint32_t*>(ws + p.o_totals);
@@ -537,7 +569,8 @@ mr_status words_pass(mr_job* job, std::vector<WordItem>& items, std::vector<JobS
   MR_HIP(hipEventElapsedTime(&ms, job->ev0, job->ev1));
   *gpu_ms = ms;
   *map_ms = 0.f;
-  if (job->cfg.timing) MR_HIP(hipEventElapsedTime(map_ms, job->ev2, job->ev3));
+  // (a graph replays the whole sequence: the map is timed with plain launches only)
+  if (job->cfg.timing && !use_graph) MR_HIP(hipEventElapsedTime(map_ms, job->ev2, job->ev3));
   // The compaction zeroes every slot it reads, so after a complete pass the
   // table region [0, table_bytes) is zero again. Everything past it was just
   // used for descriptors, records and buckets and is not. A pass that stopped
@@ -813,9 +846,15 @@ mr_status int_ensure(mr_job* job, void** p, uint64_t* have, uint64_t want, uint6
   return MR_OK;
 }
 
-bool int_feasible(mr_strategy s, uint64_t R, uint32_t op) {
+// The LDS budget of the rule's per-workgroup arrays: the tuned one, at most the default.
+uint64_t eff_lds_array_bytes(const mr_job* job, mr_map_kind kind, uint64_t bytes) {
+  const mr_tune_entry* t = tune_for(job, kind, bytes);
+  return t && t->lds_array_bytes ? std::min<uint64_t>(t->lds_array_bytes, kLdsArrayBudget) : kLdsArrayBudget;
+}
+
+bool int_feasible(mr_strategy s, uint64_t R, uint32_t op, uint64_t lds_budget = kLdsArrayBudget) {
   switch (s) {
-    case MR_STRAT_LDS_ARRAY: return R > 0 && int_lds_array_bytes(R, op) <= kLdsArrayBudget;
+    case MR_STRAT_LDS_ARRAY: return R > 0 && int_lds_array_bytes(R, op) <= lds_budget;
     case MR_STRAT_GLOBAL_ARRAY: return R > 0 && R <= kGlobalArrayMax;
     case MR_STRAT_HASH:
     case MR_STRAT_SORT: return true;
@@ -826,8 +865,8 @@ bool int_feasible(mr_strategy s, uint64_t R, uint32_t op) {
 // The paper's rule (Section III-E) for integer keys: keep per-worker arrays
 // while each fits the local memory budget, otherwise one shared array with
 // atomics; keys without a fixed range use the hash table. It never picks SORT.
-mr_strategy rule_strategy(uint64_t R, uint32_t op) {
-  if (int_feasible(MR_STRAT_LDS_ARRAY, R, op)) return MR_STRAT_LDS_ARRAY;
+mr_strategy rule_strategy(uint64_t R, uint32_t op, uint64_t lds_budget) {
+  if (int_feasible(MR_STRAT_LDS_ARRAY, R, op, lds_budget)) return MR_STRAT_LDS_ARRAY;
   if (int_feasible(MR_STRAT_GLOBAL_ARRAY, R, op)) return MR_STRAT_GLOBAL_ARRAY;
   return MR_STRAT_HASH;
 }
@@ -854,7 +893,7 @@ mr_status run_u32(mr_job* job, mr_map_kind kind, mr_reduce_op op, const void* d_
     mr_status st = learned_strategy(job, kind, op, d_input, bytes, key_range, &strat, &sel_used);
     if (st != MR_OK) return st;
   }
-  if (strat == MR_STRAT_RULE) strat = rule_strategy(key_range, o);
+  if (strat == MR_STRAT_RULE) strat = rule_strategy(key_range, o, eff_lds_array_bytes(job, kind, bytes));
   if (!int_feasible(strat, key_range, o))
     return fail(MR_ERR_UNSUPPORTED, "strategy %d is infeasible for this job (key_range %llu)", (int)strat,
                 (unsigned long long)key_range);
@@ -943,7 +982,7 @@ mr_status run_u32(mr_job* job, mr_map_kind kind, mr_reduce_op op, const void* d_
   } else if (strat == MR_STRAT_HASH) {
     // capacity: distinct <= min(n, range); start from the last job's distinct count when larger inputs repeat
     const uint64_t bound = std::max<uint64_t>(1, key_range ? std::min<uint64_t>(n, key_range) : n);
-    const double lf = (job->cfg.max_load_pct ? job->cfg.max_load_pct : 50) / 100.0;
+    const double lf = eff_load_pct(job, kind, bytes) / 100.0;
     table_cap = job->cfg.table_slots ? job->cfg.table_slots
                                      : std::max<uint64_t>(4096, next_pow2((uint64_t)std::ceil(std::min<uint64_t>(bound, 1ull << 24) / lf)));
     for (;;) {
@@ -1184,6 +1223,21 @@ extern "C" mr_status mr_run(mr_job* job, mr_map_kind kind, mr_reduce_op op, cons
   }
   out->status = s;
   return s;
+}
+
+extern "C" mr_status mr_tune_set(mr_job* job, const mr_tune_entry* entries, uint32_t n) {
+  if (!job || (n && !entries)) return fail(MR_ERR_INVALID_ARG, "NULL job or entries");
+  for (uint32_t i = 0; i < n; ++i) {
+    const mr_tune_entry& e = entries[i];
+    const bool kind_ok = e.kind == MR_MAP_WORDS || e.kind == MR_MAP_U32_KEYS || e.kind == MR_MAP_U32_KV;
+    const bool lds_ok = e.lds_slots == 0 || e.lds_slots == 256 || e.lds_slots == 1024 || e.lds_slots == 2048 || e.lds_slots == 4096;
+    if (!kind_ok || e.bytes_lo >= e.bytes_hi || !lds_ok || e.max_load_pct > 95 || e.map_grid_pct > 100 ||
+        e.lds_array_bytes > kLdsArrayBudget)
+      return fail(MR_ERR_INVALID_ARG, "tune entry %u is malformed", i);
+  }
+  job->tune.assign(entries, entries + n);
+  job->graph_valid = false;
+  return MR_OK;
 }
 
 extern "C" mr_status mr_batch_run(mr_job* job, const mr_batch_item* items, uint32_t n_items, mr_output* outs) {

@@ -61,6 +61,7 @@ def test_struct_sizes_match_the_header():
     assert C.sizeof(L.Stats) == 4 + 4 + 8 + 8 + 4 + 4 + 4 + 4
     assert C.sizeof(L.Output) == 8 * 8 + 8 * 4 + 8 + C.sizeof(L.Stats) + 8 * 4
     assert C.sizeof(L.BatchItem) == 4 + 4 + 8 + 8 + 8 + 8 + 8
+    assert C.sizeof(L.TuneEntry) == 4 + 4 + 8 + 8 + 4 * 4
 
 
 def test_product_path_does_not_import_the_oracle():
