@@ -320,12 +320,22 @@ uint64_t initial_slots(const mr_job* job, uint64_t n) {
 struct WordsPlan {
   Carve c;
   uint64_t o_jobs, o_tile_base, o_states, o_totals, o_bucket_cnt, o_bucket_bytes, o_bucket_start, o_bucket_bstart,
-      o_bucket_fill, o_tw, o_tc, o_recs, o_recs2, o_rbucket, o_spl, o_slot_rank = 0;
+      o_bucket_fill, o_tw, o_tc, o_recs, o_recs2, o_rbucket, o_spl, o_slot_rank = 0, o_queue = 0, o_qcnt = 0;
+  uint32_t qcap = 0;  // records per flush queue (0: no two-phase flush)
   uint64_t total_slots = 0, total_tiles = 0;
   std::vector<uint64_t> slot_base, tile_base;
 };
 
-WordsPlan plan_words(const std::vector<WordItem>& items, bool slot_ranks) {
+// Records per flush queue for a single job: at most one per LDS cache slot
+// that each of up to n_cu workgroups fills (3/4 of 4096), and at most one per
+// two input bytes, spread over the queues by hash, with slack; a full queue
+// sends its overflow to the global table directly.
+uint32_t flush_queue_cap(uint64_t n, int n_cu) {
+  const uint64_t recs = std::min<uint64_t>((uint64_t)n_cu * 3072, n / 2 + 1);
+  return (uint32_t)(recs * 3 / 2 / kFlushParts + 256);
+}
+
+WordsPlan plan_words(const std::vector<WordItem>& items, bool slot_ranks, uint32_t qcap) {
   WordsPlan p;
   const uint32_t n = (uint32_t)items.size();
   p.slot_base.resize(n);
@@ -356,6 +366,11 @@ WordsPlan plan_words(const std::vector<WordItem>& items, bool slot_ranks) {
   p.o_rbucket = p.c.take(4 * p.total_slots);
   p.o_spl = p.c.take(sizeof(WRec) * (kMaxBuckets - 1) * (uint64_t)n);
   if (slot_ranks) p.o_slot_rank = p.c.take(4 * p.total_slots);
+  if (qcap) {
+    p.qcap = qcap;
+    p.o_queue = p.c.take(32ull * kFlushParts * qcap);
+    p.o_qcnt = p.c.take(4ull * kFlushParts);
+  }
   return p;
 }
 
@@ -387,7 +402,9 @@ uint64_t fnv_mix(uint64_t h, uint64_t v) {
 mr_status words_pass(mr_job* job, std::vector<WordItem>& items, std::vector<JobState>& states, float* gpu_ms,
                      float* map_ms, GraphMode mode, LinkBufs* lb) {
   const uint32_t n = (uint32_t)items.size();
-  WordsPlan p = plan_words(items, lb != nullptr);
+  // single word jobs flush their LDS caches in two phases through partition queues
+  const uint32_t qcap = (n == 1 && !lb) ? flush_queue_cap(items[0].n, job->n_cu) : 0u;
+  WordsPlan p = plan_words(items, lb != nullptr, qcap);
   // tuned map parameters, looked up by the bytes this launch covers (a
   // batch by its total; each job's table load factor by its own size)
   uint64_t size_key = 0;
@@ -491,6 +508,9 @@ mr_status words_pass(mr_job* job, std::vector<WordItem>& items, std::vector<JobS
     J.cap_key_bytes = it.out->cap_key_bytes;
     J.st = reinterpret_cast<JobState*>(ws + p.o_states) + j;
     J.slot_rank = lb ? reinterpret_cast<uint32_t*>(ws + p.o_slot_rank) + p.slot_base[j] : nullptr;
+    J.queue = p.qcap ? ws + p.o_queue : nullptr;
+    J.qcnt = p.qcap ? reinterpret_cast<uint32_t*>(ws + p.o_qcnt) : nullptr;
+    J.qcap = p.qcap;
     any_rec |= it.rec != nullptr;
   }
   MR_HIP(hipMemcpyAsync(ws + p.o_jobs, hj.data(), sizeof(WordJob) * n, hipMemcpyHostToDevice, s));
@@ -506,6 +526,7 @@ mr_status words_pass(mr_job* job, std::vector<WordItem>& items, std::vector<JobS
   L.map_grid = (uint32_t)want_grid;
   L.sort_grid = (uint32_t)std::max(1, job->n_cu * 2);
   L.lds_log2 = lds_log2;
+  L.flush_parts = p.qcap != 0;
   L.debug_hash = job->cfg.debug_hash;
   L.any_records = any_rec;
   L.totals = reinterpret_cast<uint32_t*>(ws + p.o_totals);

@@ -57,7 +57,16 @@ struct WordJob {
   uint64_t cap_key_bytes;
   JobState* st;
   uint32_t* slot_rank;       // [cap] output rank of the key in each table slot, or NULL
+  // partition queues of the two-phase flush (single jobs), or NULL: the LDS
+  // caches are flushed into kFlushParts queues by key hash, and one
+  // workgroup per queue sums them before the global inserts
+  void* queue;               // records [kFlushParts][qcap]
+  uint32_t* qcnt;            // [kFlushParts] records claimed per queue
+  uint32_t qcap;
 };
+
+constexpr uint32_t kFlushParts = 256;  // queues: the top 8 bits of the key hash
+constexpr uint32_t kFlushShift = 56;
 
 // Compacted table entry of a word, ordered by (p, len) then tail bytes.
 struct WRec {

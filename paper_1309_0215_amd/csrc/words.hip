@@ -240,6 +240,8 @@ __global__ void k_words_prep(const WordJob* __restrict__ jobs, uint32_t n_jobs) 
   const uint32_t j = blockIdx.y;
   if (j >= n_jobs) return;
   const WordJob J = jobs[j];
+  if (J.qcnt && blockIdx.x == 0)
+    for (uint32_t p = threadIdx.x; p < kFlushParts; p += blockDim.x) J.qcnt[p] = 0u;
   if (!J.rec) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       J.st->valid_lo = 0;
@@ -286,7 +288,8 @@ MR_DEV uint32_t lds_tag(uint64_t h, uint32_t len) { return ((uint32_t)(h >> 32) 
 // Returns 0 = counted, 1 = a matching slot is still being written or the
 // claim was lost (retry), 2 = not in the table and not inserted (go global).
 template <int L>
-MR_DEV int lds_insert(LdsTable<L>& T, uint32_t* used, uint32_t limit, uint32_t tg, uint32_t h, uint4 k, uint32_t off) {
+MR_DEV int lds_insert(LdsTable<L>& T, uint32_t* used, uint32_t limit, uint32_t tg, uint32_t h, uint4 k, uint32_t off,
+                      uint32_t v = 1u) {
   constexpr uint32_t kGroupMask = LdsTable<L>::kSlots / 4 - 1;
   uint32_t g = h & kGroupMask;
   for (int p = 0; p < kLdsGroups; ++p) {
@@ -303,7 +306,7 @@ MR_DEV int lds_insert(LdsTable<L>& T, uint32_t* used, uint32_t limit, uint32_t t
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");  // key bytes after the ready tag
         const uint4 kk = T.key[4 * g + q];
         if (kk.x == k.x && kk.y == k.y && kk.z == k.z && kk.w == k.w) {
-          atomicAdd(&T.cnt[4 * g + q], 1u);
+          atomicAdd(&T.cnt[4 * g + q], v);
           return 0;
         }
       }
@@ -314,7 +317,7 @@ MR_DEV int lds_insert(LdsTable<L>& T, uint32_t* used, uint32_t limit, uint32_t t
       if (atomicCAS(&T.tag[i], 0u, tg) != 0u) return 1;  // lost the slot: look again
       T.key[i] = k;
       T.off[i] = off;
-      T.cnt[i] = 1u;
+      T.cnt[i] = v;
       __hip_atomic_store(&T.tag[i], tg | 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
       atomicAdd(used, 1u);
       return 0;
@@ -333,6 +336,58 @@ MR_DEV void lds_flush(LdsTable<L>& T, const WordJob& J, uint64_t vlo, uint64_t v
       const uint4 k = T.key[i];
       const uint64_t h = key_hash16(k, len, debug_hash);
       g_insert<true>(J, vlo, vhi, T.off[i], len, h, k, T.cnt[i], debug_hash);
+    }
+    T.tag[i] = 0u;
+  }
+}
+
+// One record of a flush queue: an LDS cache entry (key bytes as loaded,
+// length, offset of an occurrence, count).
+struct FlushRec {
+  uint4 k;
+  uint32_t off, len, cnt, pad;
+};
+
+// Two-phase flush, first phase: the workgroup's cache entries go to the
+// job's queues by the top bits of their hash, with one global reservation per
+// queue; an entry that finds its queue full is inserted globally at once.
+// pc: LDS scratch [2 * kFlushParts]. Called by the whole workgroup.
+template <int L>
+MR_DEV void lds_flush_parts(LdsTable<L>& T, const WordJob& J, uint32_t* pc, uint64_t vlo, uint64_t vhi,
+                            uint32_t debug_hash) {
+  for (uint32_t p = threadIdx.x; p < kFlushParts; p += blockDim.x) pc[p] = 0;
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < LdsTable<L>::kSlots; i += blockDim.x) {
+    const uint32_t tg = T.tag[i];
+    if (tg & 1u) atomicAdd(&pc[key_hash16(T.key[i], (tg >> 1) & 31u, debug_hash) >> kFlushShift], 1u);
+  }
+  __syncthreads();
+  for (uint32_t p = threadIdx.x; p < kFlushParts; p += blockDim.x) {
+    const uint32_t c = pc[p];
+    pc[kFlushParts + p] = c ? atomicAdd(&J.qcnt[p], c) : 0u;
+    pc[p] = 0;
+  }
+  __syncthreads();
+  FlushRec* q = reinterpret_cast<FlushRec*>(J.queue);
+  for (uint32_t i = threadIdx.x; i < LdsTable<L>::kSlots; i += blockDim.x) {
+    const uint32_t tg = T.tag[i];
+    if (tg & 1u) {
+      const uint32_t len = (tg >> 1) & 31u;
+      const uint4 k = T.key[i];
+      const uint64_t h = key_hash16(k, len, debug_hash);
+      const uint32_t p = (uint32_t)(h >> kFlushShift);
+      const uint32_t at = pc[kFlushParts + p] + atomicAdd(&pc[p], 1u);
+      if (at < J.qcap) {
+        FlushRec r;
+        r.k = k;
+        r.off = T.off[i];
+        r.len = len;
+        r.cnt = T.cnt[i];
+        r.pad = 0;
+        q[(uint64_t)p * J.qcap + at] = r;
+      } else {
+        g_insert<true>(J, vlo, vhi, T.off[i], len, h, k, T.cnt[i], debug_hash);
+      }
     }
     T.tag[i] = 0u;
   }
@@ -407,7 +462,8 @@ __global__ __launch_bounds__(kMapThreads) void k_words_map(const WordJob* __rest
     const uint32_t j = find_job(tile_base, n_jobs, t);
     if ((int)j != cur) {
       if (cur >= 0) {
-        lds_flush<L>(T, jobs[cur], vlo, vhi, debug_hash);
+        if (jobs[cur].queue) lds_flush_parts<L>(T, jobs[cur], &wlist[0][0], vlo, vhi, debug_hash);
+        else lds_flush<L>(T, jobs[cur], vlo, vhi, debug_hash);
         if (threadIdx.x == 0) s_used = 0;
         __syncthreads();
       }
@@ -536,7 +592,46 @@ __global__ __launch_bounds__(kMapThreads) void k_words_map(const WordJob* __rest
     }
   }
   __syncthreads();
-  if (cur >= 0) lds_flush<L>(T, jobs[cur], vlo, vhi, debug_hash);
+  if (cur >= 0) {
+    if (jobs[cur].queue) lds_flush_parts<L>(T, jobs[cur], &wlist[0][0], vlo, vhi, debug_hash);
+    else lds_flush<L>(T, jobs[cur], vlo, vhi, debug_hash);
+  }
+}
+
+// Two-phase flush, second phase: one workgroup per queue of job 0 sums the
+// queue's records by key in an LDS table and inserts each key globally once,
+// so the keys that every workgroup caches no longer meet on one global slot
+// from every workgroup. Records that find the LDS table full are inserted
+// globally as they come.
+template <int L>
+__global__ __launch_bounds__(kMapThreads) void k_words_parts(const WordJob* __restrict__ jobs, uint32_t debug_hash) {
+  __shared__ LdsTable<L> T;
+  __shared__ uint32_t s_used;
+  constexpr uint32_t kLimit = LdsTable<L>::kSlots / 4 * 3;
+  const WordJob& J = jobs[0];
+  const uint32_t p = blockIdx.x;
+  for (uint32_t i = threadIdx.x; i < LdsTable<L>::kSlots; i += blockDim.x) T.tag[i] = 0u;
+  if (threadIdx.x == 0) s_used = 0;
+  __syncthreads();
+  const uint64_t vlo = J.st->valid_lo, vhi = J.st->valid_hi;
+  const uint32_t n = J.qcnt[p] < J.qcap ? J.qcnt[p] : J.qcap;
+  const FlushRec* q = reinterpret_cast<const FlushRec*>(J.queue) + (uint64_t)p * J.qcap;
+  for (uint32_t r0 = threadIdx.x; r0 < n; r0 += blockDim.x) {
+    const FlushRec rec = q[r0];
+    const uint64_t h = key_hash16(rec.k, rec.len, debug_hash);
+    const uint32_t tg = lds_tag(h, rec.len);
+    int r = 1;
+    for (uint32_t spin = 0; r == 1; ++spin) {
+      r = lds_insert<L>(T, &s_used, kLimit, tg, (uint32_t)h, rec.k, rec.off, rec.cnt);
+      if (r == 1 && spin > (1u << 22)) {
+        atomicOr(&J.st->flags, kFlagSpin);
+        r = 0;
+      }
+    }
+    if (r == 2) g_insert<true>(J, vlo, vhi, rec.off, rec.len, h, rec.k, rec.cnt, debug_hash);
+  }
+  __syncthreads();
+  lds_flush<L>(T, J, vlo, vhi, debug_hash);
 }
 
 // ----------------------------------------------------------------------------
@@ -544,7 +639,7 @@ __global__ __launch_bounds__(kMapThreads) void k_words_map(const WordJob* __rest
 // ----------------------------------------------------------------------------
 
 constexpr uint32_t kCompactThreads = 256;
-constexpr uint32_t kCompactSlots = 4096;  // slots per work item: one job-counter update each
+constexpr uint32_t kCompactSlots = 1024;  // slots per work item: one job-counter update each
 
 // The entry of slot i, or 0 (empty, or an occurrence offset outside the
 // input, which is reported and skipped).
@@ -555,9 +650,10 @@ MR_DEV unsigned long long compact_entry(const WordJob& J, uint64_t i) {
   return w;
 }
 
-// Work item = 4096 slots of one job's table (tables are powers of two >= 4096
-// slots at 4096-aligned arena offsets). Pass 1 counts the entries, one atomic
-// reserves their places, pass 2 writes the records and clears the slots.
+// Work item = 1024 slots of one job's table (tables are powers of two >= 4096
+// slots at 4096-aligned arena offsets, so no item straddles two tables). Pass
+// 1 counts the entries, one atomic reserves their places, pass 2 writes the
+// records and clears the slots.
 __global__ __launch_bounds__(kCompactThreads) void k_words_compact(const WordJob* __restrict__ jobs, uint32_t n_jobs,
                                                                    uint64_t total_slots) {
   __shared__ uint32_t s_cnt, s_pos;
@@ -1223,6 +1319,7 @@ hipError_t words_enqueue_map(const WordsLaunch& L, hipStream_t s) {
       return hipErrorInvalidValue;
   }
 #undef MR_MAP_CASE
+  if (L.flush_parts) hipLaunchKernelGGL((k_words_parts<12>), dim3(kFlushParts), dim3(kMapThreads), 0, s, L.jobs, L.debug_hash);
   return hipGetLastError();
 }
 
