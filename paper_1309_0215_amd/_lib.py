@@ -119,7 +119,7 @@ def load(required: bool = True):
         return _lib
     if not os.path.exists(LIB_PATH):
         if required:
-            raise RuntimeError(f"{LIB_PATH} is not built: run __graft_entry__.build() or python -m paper_1309_0215_amd.build")
+            raise RuntimeError(f"{LIB_PATH} is not built: run python -m paper_1309_0215_amd.build")
         return None
     lib = C.CDLL(LIB_PATH)
     P, U32, U64, I32, F = C.c_void_p, C.c_uint32, C.c_uint64, C.c_int32, C.c_float

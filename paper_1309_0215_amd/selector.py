@@ -308,7 +308,7 @@ def main(argv=None):
     ap.add_argument("--size-hi-mib", type=int, default=32)
     ap.add_argument("--epochs", type=int, default=500)
     ap.add_argument("--reps", type=int, default=2)
-    ap.add_argument("--out", default="gpurun_out/selector")
+    ap.add_argument("--out", default="selector_out")
     args = ap.parse_args(argv)
     os.makedirs(args.out, exist_ok=True)
     log = lambda *a: print(*a, file=sys.stderr, flush=True)  # noqa: E731
