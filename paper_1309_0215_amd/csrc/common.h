@@ -7,8 +7,35 @@
 #include "jobs.h"
 
 #define MR_DEV __device__ __forceinline__
+// Global address space: a pointer loaded from a descriptor is generic, and
+// generic (flat) accesses count against the LDS wait counter too, so every
+// LDS wait would also wait for outstanding global loads. Casting to the
+// global space makes them global_* instructions.
+#define MR_GLOBAL __attribute__((address_space(1)))
 
 namespace mr {
+
+template <typename T>
+MR_DEV MR_GLOBAL T* gp(T* p) {
+  return (MR_GLOBAL T*)p;
+}
+
+typedef uint32_t gu32x4 __attribute__((ext_vector_type(4)));
+
+// 16-byte global load / store at a 16-byte aligned address.
+MR_DEV uint4 gload16(const void* p) {
+  const gu32x4 v = *gp(reinterpret_cast<const gu32x4*>(p));
+  return make_uint4(v[0], v[1], v[2], v[3]);
+}
+
+MR_DEV void gstore16(void* p, uint4 x) {
+  gu32x4 v;
+  v[0] = x.x;
+  v[1] = x.y;
+  v[2] = x.z;
+  v[3] = x.w;
+  *gp(reinterpret_cast<gu32x4*>(p)) = v;
+}
 
 constexpr int kWave = 64;
 

@@ -44,7 +44,7 @@ MR_DEV uint4 spaces4() { return make_uint4(0x20202020u, 0x20202020u, 0x20202020u
 // holds no byte of [a0, a1). A block that holds one valid byte lies inside the
 // caller's allocation (blocks never straddle a page), so the load is safe.
 MR_DEV uint4 load_block(uint64_t a0, uint64_t a1, uint64_t blk) {
-  if (blk + 16 > a0 && blk < a1) return *reinterpret_cast<const uint4*>(blk);
+  if (blk + 16 > a0 && blk < a1) return gload16(reinterpret_cast<const void*>(blk));
   return spaces4();
 }
 
@@ -85,10 +85,10 @@ MR_DEV uint4 load_key16(const uint8_t* in, uint64_t off, uint32_t len) {
   const uint64_t blk = a & ~15ull;
   const uint32_t s = (uint32_t)(a & 15u);
   uint32_t w[8];
-  const uint4 b0 = *reinterpret_cast<const uint4*>(blk);
+  const uint4 b0 = gload16(reinterpret_cast<const void*>(blk));
   w[0] = b0.x; w[1] = b0.y; w[2] = b0.z; w[3] = b0.w;
   if (s + len > 16u) {
-    const uint4 b1 = *reinterpret_cast<const uint4*>(blk + 16);
+    const uint4 b1 = gload16(reinterpret_cast<const void*>(blk + 16));
     w[4] = b1.x; w[5] = b1.y; w[6] = b1.z; w[7] = b1.w;
   } else {
     w[4] = w[5] = w[6] = w[7] = 0u;
@@ -134,7 +134,7 @@ MR_DEV uint64_t rec_lower_bound(const uint64_t* rec, uint64_t n_rec, uint64_t po
   uint64_t lo = 0, hi = n_rec + 1;
   while (lo < hi) {
     const uint64_t mid = (lo + hi) >> 1;
-    if (rec[mid] < pos) lo = mid + 1; else hi = mid;
+    if (gp(rec)[mid] < pos) lo = mid + 1; else hi = mid;
   }
   return lo;
 }
@@ -144,10 +144,10 @@ MR_DEV uint64_t word_length_slow(const WordJob& J, uint64_t vlo, uint64_t vhi, u
   uint64_t end = vhi;
   if (J.rec) {
     const uint64_t r = rec_lower_bound(J.rec, J.n_rec, start + 1);
-    if (r <= J.n_rec && J.rec[r] < end) end = J.rec[r];
+    if (r <= J.n_rec && gp(J.rec)[r] < end) end = gp(J.rec)[r];
   }
   uint64_t p = start + 1;
-  while (p < end && !is_sep_byte(J.in[p])) ++p;
+  while (p < end && !is_sep_byte(gp(J.in)[p])) ++p;
   return p - start;
 }
 
@@ -163,7 +163,7 @@ MR_DEV uint64_t gword(uint64_t off, uint64_t len, uint64_t h) {
 // anything else means the table was not clean, which is reported, never read.
 MR_DEV bool rep_in_bounds(const WordJob& J, uint64_t rep_off, uint64_t len) {
   if (rep_off + len <= J.n) return true;
-  atomicOr(&J.st->flags, kFlagInternal);
+  __hip_atomic_fetch_or(gp(&J.st->flags), kFlagInternal, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   return false;
 }
 
@@ -204,11 +204,13 @@ MR_DEV bool g_insert(const WordJob& J, uint64_t vlo, uint64_t vhi, uint64_t off,
   for (uint64_t p = 0; p <= limit; ++p) {
     // A relaxed load may be stale only as 0 (slots are written once per run);
     // the CAS below then returns the current word.
-    unsigned long long cur = __hip_atomic_load(&J.tw[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    unsigned long long cur = __hip_atomic_load(gp(&J.tw[i]), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     if (cur == 0ull) {
-      const unsigned long long old = atomicCAS(&J.tw[i], 0ull, (unsigned long long)word);
+      unsigned long long old = 0ull;
+      __hip_atomic_compare_exchange_strong(gp(&J.tw[i]), &old, (unsigned long long)word, __ATOMIC_RELAXED,
+                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       if (old == 0ull) {
-        if (v) atomicAdd(&J.tc[i], v);
+        if (v) __hip_atomic_fetch_add(gp(&J.tc[i]), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (slot_out) *slot_out = i;
         return true;
       }
@@ -218,17 +220,17 @@ MR_DEV bool g_insert(const WordJob& J, uint64_t vlo, uint64_t vhi, uint64_t off,
       const uint64_t rep = cur >> 32;
       const bool eq = kInline ? rep_equals_inline(J, rep, k, (uint32_t)len) : rep_equals_global(J, vlo, vhi, rep, off, len);
       if (eq) {
-        if (v) atomicAdd(&J.tc[i], v);
+        if (v) __hip_atomic_fetch_add(gp(&J.tc[i]), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (slot_out) *slot_out = i;
         return true;
       }
     }
     i = (i + 1) & mask;
     if ((p & 255u) == 255u &&
-        (__hip_atomic_load(&J.st->flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kFlagTableFull))
+        (__hip_atomic_load(gp(&J.st->flags), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kFlagTableFull))
       return false;
   }
-  atomicOr(&J.st->flags, kFlagTableFull);
+  __hip_atomic_fetch_or(gp(&J.st->flags), kFlagTableFull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   return false;
 }
 
@@ -364,7 +366,7 @@ MR_DEV void lds_flush_parts(LdsTable<L>& T, const WordJob& J, uint32_t* pc, uint
   __syncthreads();
   for (uint32_t p = threadIdx.x; p < kFlushParts; p += blockDim.x) {
     const uint32_t c = pc[p];
-    pc[kFlushParts + p] = c ? atomicAdd(&J.qcnt[p], c) : 0u;
+    pc[kFlushParts + p] = c ? __hip_atomic_fetch_add(gp(&J.qcnt[p]), c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
     pc[p] = 0;
   }
   __syncthreads();
@@ -378,13 +380,9 @@ MR_DEV void lds_flush_parts(LdsTable<L>& T, const WordJob& J, uint32_t* pc, uint
       const uint32_t p = (uint32_t)(h >> kFlushShift);
       const uint32_t at = pc[kFlushParts + p] + atomicAdd(&pc[p], 1u);
       if (at < J.qcap) {
-        FlushRec r;
-        r.k = k;
-        r.off = T.off[i];
-        r.len = len;
-        r.cnt = T.cnt[i];
-        r.pad = 0;
-        q[(uint64_t)p * J.qcap + at] = r;
+        FlushRec* dst = &q[(uint64_t)p * J.qcap + at];
+        gstore16(&dst->k, k);
+        gstore16(&dst->off, make_uint4(T.off[i], len, T.cnt[i], 0u));
       } else {
         g_insert<true>(J, vlo, vhi, T.off[i], len, h, k, T.cnt[i], debug_hash);
       }
@@ -468,12 +466,12 @@ __global__ __launch_bounds__(kMapThreads) void k_words_map(const WordJob* __rest
         __syncthreads();
       }
       cur = (int)j;
-      vlo = jobs[j].st->valid_lo;
-      vhi = jobs[j].st->valid_hi;
+      vlo = gp(jobs[j].st)->valid_lo;
+      vhi = gp(jobs[j].st)->valid_hi;
     }
     const WordJob& J = jobs[j];
     if (threadIdx.x == 0)
-      s_abort = (__hip_atomic_load(&J.st->flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & (kFlagTableFull | kFlagBadInput)) ? 1u : 0u;
+      s_abort = (__hip_atomic_load(gp(&J.st->flags), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & (kFlagTableFull | kFlagBadInput)) ? 1u : 0u;
     const uint64_t lt = t - tile_base[j];
     const uint64_t a0 = (uint64_t)J.in, a1 = a0 + J.n;
     const uint64_t tile_addr = (J.chunk0 + lt * kMapTileChunks) * 16;
@@ -487,7 +485,7 @@ __global__ __launch_bounds__(kMapThreads) void k_words_map(const WordJob* __rest
         const int64_t lo_rel = (int64_t)(tile_addr - a0);
         const uint64_t r0 = rec_lower_bound(J.rec, J.n_rec, lo_rel < 0 ? 0 : (uint64_t)lo_rel);
         for (uint64_t r = r0 + threadIdx.x; r <= J.n_rec; r += blockDim.x) {
-          const uint64_t pa = a0 + J.rec[r];
+          const uint64_t pa = a0 + gp(J.rec)[r];
           if (pa < tile_addr) continue;
           const uint64_t bit = pa - tile_addr;
           if (bit >= 32ull * kBndWords) break;
@@ -581,7 +579,7 @@ __global__ __launch_bounds__(kMapThreads) void k_words_map(const WordJob* __rest
         for (uint32_t spin = 0; r == 1; ++spin) {
           r = lds_insert<L>(T, &s_used, kLimit, tg, (uint32_t)h, k, (uint32_t)off);
           if (r == 1 && spin > (1u << 22)) {
-            atomicOr(&J.st->flags, kFlagSpin);
+            __hip_atomic_fetch_or(gp(&J.st->flags), kFlagSpin, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             r = 0;
           }
         }
@@ -613,18 +611,24 @@ __global__ __launch_bounds__(kMapThreads) void k_words_parts(const WordJob* __re
   for (uint32_t i = threadIdx.x; i < LdsTable<L>::kSlots; i += blockDim.x) T.tag[i] = 0u;
   if (threadIdx.x == 0) s_used = 0;
   __syncthreads();
-  const uint64_t vlo = J.st->valid_lo, vhi = J.st->valid_hi;
-  const uint32_t n = J.qcnt[p] < J.qcap ? J.qcnt[p] : J.qcap;
+  const uint64_t vlo = gp(J.st)->valid_lo, vhi = gp(J.st)->valid_hi;
+  const uint32_t qn = *gp(&J.qcnt[p]);
+  const uint32_t n = qn < J.qcap ? qn : J.qcap;
   const FlushRec* q = reinterpret_cast<const FlushRec*>(J.queue) + (uint64_t)p * J.qcap;
   for (uint32_t r0 = threadIdx.x; r0 < n; r0 += blockDim.x) {
-    const FlushRec rec = q[r0];
+    FlushRec rec;
+    rec.k = gload16(&q[r0].k);
+    const uint4 m = gload16(&q[r0].off);
+    rec.off = m.x;
+    rec.len = m.y;
+    rec.cnt = m.z;
     const uint64_t h = key_hash16(rec.k, rec.len, debug_hash);
     const uint32_t tg = lds_tag(h, rec.len);
     int r = 1;
     for (uint32_t spin = 0; r == 1; ++spin) {
       r = lds_insert<L>(T, &s_used, kLimit, tg, (uint32_t)h, rec.k, rec.off, rec.cnt);
       if (r == 1 && spin > (1u << 22)) {
-        atomicOr(&J.st->flags, kFlagSpin);
+        __hip_atomic_fetch_or(gp(&J.st->flags), kFlagSpin, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         r = 0;
       }
     }
