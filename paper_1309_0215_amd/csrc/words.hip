@@ -295,27 +295,28 @@ MR_DEV int lds_insert(LdsTable<L>& T, uint32_t* used, uint32_t limit, uint32_t t
   constexpr uint32_t kGroupMask = LdsTable<L>::kSlots / 4 - 1;
   uint32_t g = h & kGroupMask;
   for (int p = 0; p < kLdsGroups; ++p) {
+    // the group's four tags in one 16-byte read, classified without branches
     const uint4 t4 = reinterpret_cast<const uint4*>(T.tag)[g];
-    const uint32_t tv[4] = {t4.x, t4.y, t4.z, t4.w};
-    int empty = -1;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const uint32_t cur = tv[q];
-      if (cur == 0u) {
-        if (empty < 0) empty = q;
-      } else if ((cur | 1u) == (tg | 1u)) {
-        if (!(cur & 1u)) return 1;
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");  // key bytes after the ready tag
-        const uint4 kk = T.key[4 * g + q];
-        if (kk.x == k.x && kk.y == k.y && kk.z == k.z && kk.w == k.w) {
-          atomicAdd(&T.cnt[4 * g + q], v);
-          return 0;
-        }
+    const uint32_t tq = tg | 1u;
+    const uint32_t match = ((t4.x | 1u) == tq ? 1u : 0u) | ((t4.y | 1u) == tq ? 2u : 0u) |
+                           ((t4.z | 1u) == tq ? 4u : 0u) | ((t4.w | 1u) == tq ? 8u : 0u);
+    const uint32_t ready = (t4.x & 1u) | ((t4.y & 1u) << 1) | ((t4.z & 1u) << 2) | ((t4.w & 1u) << 3);
+    const uint32_t empty = (t4.x == 0u ? 1u : 0u) | (t4.y == 0u ? 2u : 0u) | (t4.z == 0u ? 4u : 0u) |
+                           (t4.w == 0u ? 8u : 0u);
+    // ready slots with the key's tag: compare the whole key with one 16-byte read each
+    for (uint32_t rm = match & ready; rm; rm &= rm - 1u) {
+      const uint32_t i = 4 * g + (uint32_t)__builtin_ctz(rm);
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");  // key bytes after the ready tag
+      const uint4 kk = T.key[i];
+      if (((kk.x ^ k.x) | (kk.y ^ k.y) | (kk.z ^ k.z) | (kk.w ^ k.w)) == 0u) {
+        atomicAdd(&T.cnt[i], v);
+        return 0;
       }
     }
-    if (empty >= 0) {
+    if (match & ~ready) return 1;  // a slot with the key's tag is still being written
+    if (empty) {
       if (*used >= limit) return 2;
-      const uint32_t i = 4 * g + (uint32_t)empty;
+      const uint32_t i = 4 * g + (uint32_t)__builtin_ctz(empty);  // slots fill in order: the first empty one
       if (atomicCAS(&T.tag[i], 0u, tg) != 0u) return 1;  // lost the slot: look again
       T.key[i] = k;
       T.off[i] = off;
