@@ -644,7 +644,9 @@ __global__ __launch_bounds__(kMapThreads) void k_words_parts(const WordJob* __re
 // ----------------------------------------------------------------------------
 
 constexpr uint32_t kCompactThreads = 256;
-constexpr uint32_t kCompactSlots = 1024;  // slots per work item: one job-counter update each
+// slots per work item (one job-counter update each): 1024 for small tables,
+// where more workgroups help, 4096 for large ones, where fewer updates do
+constexpr uint32_t kCompactSmall = 1024, kCompactLarge = 4096;
 
 // The entry of slot i, or 0 (empty, or an occurrence offset outside the
 // input, which is reported and skipped).
@@ -655,15 +657,15 @@ MR_DEV unsigned long long compact_entry(const WordJob& J, uint64_t i) {
   return w;
 }
 
-// Work item = 1024 slots of one job's table (tables are powers of two >= 4096
-// slots at 4096-aligned arena offsets, so no item straddles two tables). Pass
-// 1 counts the entries, one atomic reserves their places, pass 2 writes the
-// records and clears the slots.
+// Work item = `item` slots of one job's table, 1024 or 4096 (tables are
+// powers of two >= 4096 slots at 4096-aligned arena offsets, so no item
+// straddles two tables). Pass 1 counts the entries, one atomic reserves their
+// places, pass 2 writes the records and clears the slots.
 __global__ __launch_bounds__(kCompactThreads) void k_words_compact(const WordJob* __restrict__ jobs, uint32_t n_jobs,
-                                                                   uint64_t total_slots) {
+                                                                   uint64_t total_slots, uint32_t item) {
   __shared__ uint32_t s_cnt, s_pos;
   __shared__ unsigned long long s_base, s_bytes;
-  for (uint64_t t0 = (uint64_t)blockIdx.x * kCompactSlots; t0 < total_slots; t0 += (uint64_t)gridDim.x * kCompactSlots) {
+  for (uint64_t t0 = (uint64_t)blockIdx.x * item; t0 < total_slots; t0 += (uint64_t)gridDim.x * item) {
     uint32_t lo = 0, hi = n_jobs;
     while (hi - lo > 1) {
       const uint32_t mid = (lo + hi) >> 1;
@@ -678,13 +680,13 @@ __global__ __launch_bounds__(kCompactThreads) void k_words_compact(const WordJob
     }
     __syncthreads();
     uint32_t mine = 0;
-    for (uint32_t q = threadIdx.x; q < kCompactSlots; q += kCompactThreads) mine += compact_entry(J, i0 + q) ? 1u : 0u;
+    for (uint32_t q = threadIdx.x; q < item; q += kCompactThreads) mine += compact_entry(J, i0 + q) ? 1u : 0u;
     if (mine) atomicAdd(&s_cnt, mine);
     __syncthreads();
     if (threadIdx.x == 0) s_base = s_cnt ? atomicAdd(&J.st->n_recs, (unsigned long long)s_cnt) : 0ull;
     __syncthreads();
     unsigned long long bytes = 0;
-    for (uint32_t q = threadIdx.x; q < kCompactSlots; q += kCompactThreads) {
+    for (uint32_t q = threadIdx.x; q < item; q += kCompactThreads) {
       const uint64_t i = i0 + q;
       const unsigned long long w = compact_entry(J, i);
       if (!w) continue;
@@ -1329,9 +1331,11 @@ hipError_t words_enqueue_map(const WordsLaunch& L, hipStream_t s) {
 }
 
 hipError_t words_enqueue_reduce(const WordsLaunch& L, hipStream_t s) {
-  const uint64_t tiles = (L.total_slots + kCompactSlots - 1) / kCompactSlots;
+  const uint32_t item = L.total_slots <= (1ull << 20) ? kCompactSmall : kCompactLarge;
+  const uint64_t tiles = (L.total_slots + item - 1) / item;
   const uint32_t cgrid = (uint32_t)(tiles < 4096 ? tiles : 4096);
-  hipLaunchKernelGGL(k_words_compact, dim3(cgrid ? cgrid : 1), dim3(kCompactThreads), 0, s, L.jobs, L.n_jobs, L.total_slots);
+  hipLaunchKernelGGL(k_words_compact, dim3(cgrid ? cgrid : 1), dim3(kCompactThreads), 0, s, L.jobs, L.n_jobs, L.total_slots,
+                     item);
   hipLaunchKernelGGL(k_sort_plan, dim3(1), dim3(64), 0, s, L.jobs, L.n_jobs, L.totals);
   hipLaunchKernelGGL(k_sort_splitters, dim3(L.n_jobs), dim3(kSortThreads), 0, s, L.jobs, L.n_jobs, L.bucket_cnt,
                      L.bucket_bytes, L.bucket_fill);
