@@ -278,8 +278,9 @@ mr_status mr_mlp_adam(mr_job* job, float* params, const float* grad, float* m, f
  * Tuned launch parameters (the batched workload's tile, load-factor and
  * privatisation thresholds). An entry covers the jobs of one map kind whose
  * input size lies in [bytes_lo, bytes_hi); the first matching entry is used.
- * The word map's LDS slots and grid follow the bytes one launch covers (a
- * batch's total); each job's table load follows its own size. A nonzero field of
+ * Word jobs look entries up by the bytes one launch covers: a batch by its
+ * total, for every parameter (the setting the tuner timed on whole
+ * batches), and a single job by its own size. A nonzero field of
  * mr_job_config still wins over an entry, and an entry's zero field keeps
  * the built-in default. The project's autotuner times candidate settings
  * with this runtime and keeps the fastest per size bucket; outputs do not

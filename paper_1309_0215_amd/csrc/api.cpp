@@ -9,6 +9,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "../../include/mr.h"
@@ -72,9 +73,9 @@ struct mr_job {
   bool graph_valid = false;
   uint64_t plain_key = 0;  // launch-sequence identity of the last plain word pass
   // final table size of the last single word job and the input it ran on
-  const uint8_t* hint_in = nullptr;
-  uint64_t hint_n = 0;
-  uint64_t hint_cap = 0;
+  // final table size of recent word jobs by input (address, length): a job
+  // over the same input starts at the size it grew to, in a batch too
+  std::unordered_map<uint64_t, uint64_t> table_hint;
   hipStream_t gstream = nullptr;  // non-blocking stream for capture (the caller's may be the null stream)
   hipEvent_t gev = nullptr;
   // pinned host staging for job states
@@ -307,10 +308,11 @@ struct WordItem {
 // Initial table capacity for an input of n bytes: words <= (n + 1) / 2 and
 // distinct words <= words; start from a sixteenth of the bytes and let a full
 // table trigger regrowth.
-uint64_t initial_slots(const mr_job* job, uint64_t n) {
+// size_key: the input size the tuned load limit is looked up by.
+uint64_t initial_slots(const mr_job* job, uint64_t n, uint64_t size_key) {
   // (at least 4096 slots: the compaction takes 4096-slot pieces of one table)
   if (job->cfg.table_slots) return std::max<uint64_t>(4096, job->cfg.table_slots);
-  const double lf = eff_load_pct(job, MR_MAP_WORDS, n) / 100.0;
+  const double lf = eff_load_pct(job, MR_MAP_WORDS, size_key) / 100.0;
   const uint64_t words_ub = (n + 1) / 2;
   uint64_t est = std::min<uint64_t>(words_ub, std::max<uint64_t>(2048, n / 64));
   uint64_t slots = next_pow2((uint64_t)std::ceil(est / lf));
@@ -398,6 +400,9 @@ uint64_t fnv_mix(uint64_t h, uint64_t v) {
   }
   return h;
 }
+
+// Identity of a job's input for the table-size hints.
+uint64_t input_key(const uint8_t* in, uint64_t n) { return fnv_mix(fnv_mix(0xCBF29CE484222325ull, (uint64_t)in), n); }
 
 mr_status words_pass(mr_job* job, std::vector<WordItem>& items, std::vector<JobState>& states, float* gpu_ms,
                      float* map_ms, GraphMode mode, LinkBufs* lb) {
@@ -616,13 +621,20 @@ mr_status check_words_item(const WordItem& it) {
 
 mr_status run_words(mr_job* job, std::vector<WordItem>& items, std::vector<mr_status>* per_item, GraphMode use_graph,
                     LinkBufs* lb = nullptr) {
+  // a batch takes its tuned parameters, the load limit included, from the
+  // entry for its total size (the setting the tuner timed on whole batches);
+  // a single job from the entry for its own size
+  uint64_t total = 0;
+  for (const auto& it : items) total += it.n;
   for (auto& it : items) {
     mr_status s = check_words_item(it);
     if (s != MR_OK) return s;
-    it.cap = initial_slots(job, it.n);
-    // a single job over the same input as the last one starts at the size that one grew to
-    if (items.size() == 1 && !job->cfg.table_slots && it.in == job->hint_in && it.n == job->hint_n)
-      it.cap = std::max(it.cap, job->hint_cap);
+    it.cap = initial_slots(job, it.n, items.size() > 1 ? total : it.n);
+    // a job over an input seen before starts at the size its table grew to
+    if (!job->cfg.table_slots) {
+      const auto h = job->table_hint.find(input_key(it.in, it.n));
+      if (h != job->table_hint.end()) it.cap = std::max(it.cap, h->second);
+    }
   }
   std::vector<JobState> states;
   uint32_t retries = 0;
@@ -644,11 +656,8 @@ mr_status run_words(mr_job* job, std::vector<WordItem>& items, std::vector<mr_st
     if (!regrow) break;
     if (++retries > 24) return fail(MR_ERR_CAPACITY, "hash table regrowth did not converge");
   }
-  if (items.size() == 1) {
-    job->hint_in = items[0].in;
-    job->hint_n = items[0].n;
-    job->hint_cap = items[0].cap;
-  }
+  if (job->table_hint.size() > 65536) job->table_hint.clear();
+  for (const WordItem& it : items) job->table_hint[input_key(it.in, it.n)] = it.cap;
   mr_status first = MR_OK;
   for (size_t j = 0; j < items.size(); ++j) {
     mr_output* o = items[j].out;
