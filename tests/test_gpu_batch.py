@@ -83,6 +83,26 @@ def test_batch_regrowth(torch):
     assert res[0].stats["retries"] >= 1
 
 
+def test_repeated_batch_starts_at_grown_tables(torch):
+    """A batch whose tables regrow on the first call starts the next call over
+    the same inputs at the grown sizes: no repeated pass, same outputs."""
+    from paper_1309_0215_amd import Job
+    bufs = [gen.text(70 + i, 300_000, V=30_000, s=0.4) for i in range(4)]
+    dev = [_dev(torch, b) for b in bufs]
+    job = Job(device=0)
+    prep = job.batch_prepare(dev)
+    first = job.words_batch(dev, prepared=prep)
+    assert max(r.stats["retries"] for r in first) >= 1
+    kept = [(r.key_bytes.clone(), r.values.clone()) for r in first]
+    for _ in range(2):
+        again = job.words_batch(dev, prepared=prep)
+        assert max(r.stats["retries"] for r in again) == 0
+        for (kb, v), r in zip(kept, again):
+            assert torch.equal(kb, r.key_bytes) and torch.equal(v, r.values)
+    for i, b in enumerate(bufs):
+        assert _oracle_equal(again[i], b), i
+
+
 def test_full_batched_config_matches_per_job_runs(torch):
     from paper_1309_0215_amd import Job
     specs = gen.batched_specs()  # 256 jobs, 64 KiB..16 MiB, vocab 1K..1M, s in [0.6, 1.4]
