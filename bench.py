@@ -47,7 +47,8 @@ def bench_rgb(torch, steps, warmup):
     n = len(buf)
     d = torch.from_numpy(buf).to("cuda:0")
     job = Job(device=0, timing=1)
-    ms, outs = time_steps(lambda: job.rgb_hist(d)[1], steps, warmup, torch)
+    out = torch.empty(768, dtype=torch.int64, device="cuda:0")  # one output buffer: repeated calls replay a graph
+    ms, outs = time_steps(lambda: job.rgb_hist(d, out=out)[1], steps, warmup, torch)
     map_ms = sum(o["map_ms"] for o in outs) / len(outs)
     gpu_ms = sum(o["gpu_ms"] for o in outs) / len(outs)
     gbs = n / (ms * 1e-3) / 1e9

@@ -227,9 +227,17 @@ class Job:
         return items, outs, keep
 
     # -------------------------------------------------------------- histogram
-    def rgb_hist(self, data):
+    def rgb_hist(self, data, out=None):
+        """768 bins (3 x 256, uint64 counts as int64) of interleaved RGB bytes.
+
+        out: optional int64 CUDA tensor of 768 elements to write the bins
+        into; a repeated call on the same input, size and output replays a
+        captured HIP graph."""
         torch = self.torch
-        out = torch.empty(768, dtype=torch.int64, device=f"cuda:{self.device}")
+        if out is None:
+            out = torch.empty(768, dtype=torch.int64, device=f"cuda:{self.device}")
+        elif out.dtype != torch.int64 or out.numel() != 768 or not out.is_contiguous():
+            raise ValueError("out must be a contiguous int64 tensor of 768 elements")
         o = L.Output()
         o.values = out.data_ptr()
         L.check(self.lib.mr_run(self.h, L.MAP_RGB_HIST, L.REDUCE_COUNT, _ptr(data), int(data.numel()), None, 0, 0,

@@ -67,8 +67,14 @@ hipError_t radix_sort64(unsigned long long* k0, unsigned long long* v0, unsigned
                         uint64_t n, int bits, uint32_t* hist, uint32_t* scan_sums, bool* result_in_1, hipStream_t s);
 
 uint32_t rgb_grid(uint64_t n, int n_cu);
+// map0 / map1 (optional) are recorded around k_rgb_partial.
 hipError_t rgb_enqueue(const uint8_t* in, uint64_t n, uint32_t* partials, uint32_t G, unsigned long long* out,
                        hipStream_t s, hipEvent_t map0, hipEvent_t map1);
+// Adds the same sequence to an empty graph g, with event-record nodes for the
+// non-null events: all0, map0, k_rgb_partial, map1, k_rgb_reduce, all1.
+hipError_t rgb_graph_build(hipGraph_t g, const uint8_t* in, uint64_t n, uint32_t* partials, uint32_t G,
+                           unsigned long long* out, hipEvent_t all0, hipEvent_t map0, hipEvent_t map1,
+                           hipEvent_t all1);
 
 // Integer-key jobs: one launch description shared by the four containers.
 struct IntLaunch {
