@@ -213,8 +213,23 @@ MR_DEV void for_tile_keys(const IntIn& in, uint64_t base, F&& f) {
     const uint64_t end = base + kPartTile < in.n ? base + kPartTile : in.n;
     const uint64_t nv = end > base ? (end - base) / 4 : 0;  // whole vectors
     const uint4* v = reinterpret_cast<const uint4*>(in.p + base);
-    for (uint64_t q = threadIdx.x; q < nv; q += blockDim.x) {
-      const uint4 x = v[q];
+    // loads in batches of kTileBatch per lane, issued before any of them is used
+    constexpr uint32_t kTileBatch = 4;
+    uint64_t q = threadIdx.x;
+    for (; q + (kTileBatch - 1) * blockDim.x < nv; q += kTileBatch * blockDim.x) {
+      uint4 x[kTileBatch];
+#pragma unroll
+      for (uint32_t u = 0; u < kTileBatch; ++u) x[u] = gload16(v + q + u * blockDim.x);
+#pragma unroll
+      for (uint32_t u = 0; u < kTileBatch; ++u) {
+        f(x[u].x);
+        f(x[u].y);
+        f(x[u].z);
+        f(x[u].w);
+      }
+    }
+    for (; q < nv; q += blockDim.x) {
+      const uint4 x = gload16(v + q);
       f(x.x);
       f(x.y);
       f(x.z);
@@ -267,11 +282,12 @@ __global__ __launch_bounds__(kPartThreads) void k_part_scatter(IntIn in, uint64_
   };
   // exclusive scan of the tile's range counts (P <= 2048: 2 per thread)
   constexpr uint32_t kPer = kMaxParts / kPartThreads;
-  uint32_t c[kPer], sum = 0;
+  uint32_t c[kPer], gb[kPer], sum = 0;  // this tile's count and global segment start per range
 #pragma unroll
   for (uint32_t q = 0; q < kPer; ++q) {
     const uint32_t p = threadIdx.x * kPer + q;
     c[q] = p < P ? tile_count(p) : 0u;
+    gb[q] = p < P ? offs[(uint64_t)p * n_tiles + t] : 0u;
     sum += c[q];
   }
   const uint32_t lane = lane_id(), wv = threadIdx.x / kWave;
@@ -304,9 +320,17 @@ __global__ __launch_bounds__(kPartThreads) void k_part_scatter(IntIn in, uint64_
     if (k < R) sk[atomicAdd(&lpos[k >> kPartBits], 1u)] = (uint16_t)(k & (kPartKeys - 1));
   });
   __syncthreads();
+  // the run ends are lbase[p + 1]: lpos now holds the global segment starts,
+  // so that the write loop reads no global memory before its stores
+#pragma unroll
+  for (uint32_t q = 0; q < kPer; ++q) {
+    const uint32_t p = threadIdx.x * kPer + q;
+    if (p < P) lpos[p] = gb[q];
+  }
+  __syncthreads();
   for (uint32_t p = wv; p < P; p += kPartThreads / kWave) {
     const uint32_t b0 = lbase[p], b1 = lbase[p + 1];
-    uint16_t* dst = part + offs[(uint64_t)p * n_tiles + t];
+    uint16_t* dst = part + lpos[p];
     for (uint32_t j = b0 + lane; j < b1; j += kWave) dst[j - b0] = sk[j];
   }
 }
@@ -324,15 +348,25 @@ __global__ __launch_bounds__(1024) void k_part_fill(const uint16_t* __restrict__
   const uint64_t a0 = (start + 7) & ~7ull, a1 = end & ~7ull;
   if (a0 < a1) {
     const uint4* v = reinterpret_cast<const uint4*>(part + a0);
-    for (uint64_t q = threadIdx.x; q < (a1 - a0) / 8; q += blockDim.x) {
-      const uint4 x = v[q];
+    const uint64_t nv = (a1 - a0) / 8;
+    auto count8 = [&](const uint4& x) {
       const uint32_t w[4] = {x.x, x.y, x.z, x.w};
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         atomicAdd(&c[w[e] & 0xFFFFu], 1u);
         atomicAdd(&c[w[e] >> 16], 1u);
       }
+    };
+    // loads in batches of four per lane, issued before any of them is used
+    uint64_t q = threadIdx.x;
+    for (; q + 3 * blockDim.x < nv; q += 4 * blockDim.x) {
+      uint4 x[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) x[u] = gload16(v + q + u * blockDim.x);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) count8(x[u]);
     }
+    for (; q < nv; q += blockDim.x) count8(gload16(v + q));
     for (uint64_t j = start + threadIdx.x; j < a0; j += blockDim.x) atomicAdd(&c[part[j]], 1u);
     for (uint64_t j = a1 + threadIdx.x; j < end; j += blockDim.x) atomicAdd(&c[part[j]], 1u);
   } else {
