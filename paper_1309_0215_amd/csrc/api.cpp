@@ -839,10 +839,11 @@ mr_status run_rgb(mr_job* job, const void* d_input, uint64_t bytes, mr_output* o
   job->graph_valid = false;
   uint32_t* partials = reinterpret_cast<uint32_t*>(job->ws + o_part);
   unsigned long long* bins = static_cast<unsigned long long*>(out->values);
-  // The second call with the same launch sequence captures it as a graph
-  // and later ones replay it: one submission, so the events around the
-  // kernels are not spread apart by host launch latency. The partial rows
-  // live in the workspace, whose address is part of the identity.
+  // The second call with the same launch sequence builds it as a graph and
+  // later ones replay it: one submission, so the events around the kernels
+  // are not spread apart by host launch latency. The partial rows live in the
+  // workspace, whose address is part of the identity. A runtime that refuses
+  // the graph leaves the job on plain launches.
   uint64_t key = input_key(static_cast<const uint8_t*>(d_input), bytes);
   key = fnv_mix(key, (uint64_t)bins);
   key = fnv_mix(key, (uint64_t)partials);
@@ -1193,7 +1194,7 @@ mr_status run_kmeans(mr_job* job, const void* d_input, uint64_t bytes, mr_output
   L.mfma = d == 32 && k == 64 && (uintptr_t)d_input % 16 == 0;
   L.G = L.mfma ? (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)job->n_cu * 3, (N + 127) / 128)) : 1u;
   Carve c;
-  const uint64_t o_cn = c.take(4ull * k), o_cmax = c.take(8), o_nr = c.take(8);
+  const uint64_t o_cn = c.take(4ull * k), o_cmax = c.take(8), o_nr = c.take(16);  // rechecks, tiny flag
   const uint64_t o_ps = c.take(8ull * L.G * k * d), o_pc = c.take(4ull * L.G * k);
   mr_status st = ensure_ws(job, c.off);
   if (st != MR_OK) return st;
@@ -1203,19 +1204,28 @@ mr_status run_kmeans(mr_job* job, const void* d_input, uint64_t bytes, mr_output
   L.cn = reinterpret_cast<float*>(ws + o_cn);
   L.cmax = reinterpret_cast<double*>(ws + o_cmax);
   L.n_recheck = reinterpret_cast<unsigned long long*>(ws + o_nr);
+  L.tiny = L.n_recheck + 1;
   L.part_sum = reinterpret_cast<double*>(ws + o_ps);
   L.part_cnt = reinterpret_cast<uint32_t*>(ws + o_pc);
   L.assign = out->assign;
   L.sums = out->sums;
   L.counts = out->counts;
   L.cent = out->centroids;
-  MR_HIP(hipMemsetAsync(L.n_recheck, 0, 8, job->stream));
-  MR_HIP(hipEventRecord(job->ev0, job->stream));
-  MR_HIP(km_enqueue(L, job->stream, job->cfg.timing ? job->ev2 : nullptr, job->cfg.timing ? job->ev3 : nullptr));
-  MR_HIP(hipEventRecord(job->ev1, job->stream));
-  unsigned long long nr = 0;
-  MR_HIP(hipMemcpyAsync(&nr, L.n_recheck, 8, hipMemcpyDeviceToHost, job->stream));
-  MR_HIP(hipStreamSynchronize(job->stream));
+  unsigned long long flags[2] = {0, 0};  // rechecks, tiny
+  for (int pass = 0; pass < 2; ++pass) {
+    MR_HIP(hipMemsetAsync(L.n_recheck, 0, 16, job->stream));
+    MR_HIP(hipEventRecord(job->ev0, job->stream));
+    MR_HIP(km_enqueue(L, job->stream, job->cfg.timing ? job->ev2 : nullptr, job->cfg.timing ? job->ev3 : nullptr));
+    MR_HIP(hipEventRecord(job->ev1, job->stream));
+    MR_HIP(hipMemcpyAsync(flags, L.n_recheck, 16, hipMemcpyDeviceToHost, job->stream));
+    MR_HIP(hipStreamSynchronize(job->stream));
+    // coordinates too small for the matrix-core path's exact split: the
+    // generic kernel redoes the step (it writes every output again)
+    if (!L.mfma || !flags[1]) break;
+    L.mfma = false;
+    L.G = 1;
+  }
+  const unsigned long long nr = flags[0];
   float ms = 0.f;
   MR_HIP(hipEventElapsedTime(&ms, job->ev0, job->ev1));
   out->stats.gpu_ms = ms;

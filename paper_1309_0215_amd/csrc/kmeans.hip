@@ -2,17 +2,25 @@
 // cluster sum and count (array container over the k clusters).
 //
 // Assignment (d = 32, k = 64): the scores s_j = |c_j|^2 - 2 <x, c_j> come from
-// a dense float32 contraction on the matrix cores (v_mfma_f32_32x32x2f32):
-// A = 32 centroids x 2 dims, B = 2 dims x 32 points, 16 steps cover d = 32,
-// two centroid blocks cover k = 64. Each lane ends with one point's scores for
-// 32 centroids; lanes l and l ^ 32 hold the other 32. The argmin takes the
-// lowest index on equal scores. When the float32 gap between the best and the
-// second best score is within a rounding bound eps(x), the decision is made
-// again in float64 from the direct form sum_t (x_t - c_t)^2.
+// a contraction on the matrix cores. Points and centroids are split exactly
+// into three bfloat16 pieces each (x = xh + xm + xl); the six largest of the
+// nine piece products (all but xm.cl, xl.cm, xl.cl, which together stay below
+// 2^-20 |x| |c|) are accumulated in float32 by v_mfma_f32_32x32x16_bf16:
+// A = 32 centroids x 16 dims, B = 16 dims x 32 points, two steps cover
+// d = 32, two centroid blocks cover k = 64. Each lane ends with one point's
+// scores for 32 centroids; lanes l and l ^ 32 hold the other 32. The argmin
+// takes the lowest index on equal scores. When the float32 gap between the
+// best and the second best score is within a rounding bound eps(x) (which
+// covers the dropped products), the decision is made again in float64 from
+// the direct form sum_t (x_t - c_t)^2.
 //
 // Update: the per-cluster sums are a second contraction on the matrix cores
-// (one-hot assignment x points), accumulated in float32 over at most 16 groups
-// of 32 points per wave and then added into float64 LDS sums; the
+// (one-hot assignment x points). Each float32 coordinate is split exactly into
+// three bfloat16 pieces (x = hi + mid + lo), so the one-hot products are
+// exact and the contraction runs on the bfloat16 unit
+// (v_mfma_f32_32x32x16_bf16) with float32 accumulation, as the float32
+// contraction did. The float32 sums stay in the accumulators for at most 16
+// groups of 32 points per wave and are then added into float64 LDS sums; the
 // per-workgroup float64 partials are added in a fixed order at the end.
 #include "common.h"
 #include "launch.h"
@@ -21,23 +29,50 @@ namespace mr {
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+MR_DEV __bf16 bf16_bits(uint32_t hi16) { return __builtin_bit_cast(__bf16, (unsigned short)hi16); }
+
+// x = hi + mid + lo exactly (finite x above the float32 subnormal range):
+// hi keeps the top 8 significant bits, mid the next 8 of the remainder, and
+// the last remainder has at most 8 significant bits left.
+MR_DEV void split_bf16x3(float x, __bf16& hi, __bf16& mid, __bf16& lo) {
+  const uint32_t u0 = __float_as_uint(x);
+  const float r1 = x - __uint_as_float(u0 & 0xFFFF0000u);
+  const uint32_t u1 = __float_as_uint(r1);
+  const float r2 = r1 - __uint_as_float(u1 & 0xFFFF0000u);
+  hi = bf16_bits(u0 >> 16);
+  mid = bf16_bits(u1 >> 16);
+  lo = bf16_bits(__float_as_uint(r2) >> 16);
+}
 
 constexpr int kKmThreads = 256;  // 4 waves
 
-// Squared norms of the centroids (rounded to float32) and max |c| (float64).
+// Nonzero float32 magnitudes below 2^-100 (bit patterns 1 .. kTinyBits - 1):
+// their bfloat16 pieces can fall below the normal range, where the split
+// into pieces is no longer exact, so the matrix-core path is not used.
+constexpr uint32_t kTinyBits = 0x0D800000u;  // 2^-100
+
+// Squared norms of the centroids (rounded to float32) and max |c| (float64);
+// *tiny is set when a centroid has a nonzero coordinate below 2^-100.
 __global__ __launch_bounds__(256) void k_km_prep(const float* __restrict__ C, uint32_t k, uint32_t d, float* __restrict__ cn,
-                                                 double* __restrict__ cmax) {
+                                                 double* __restrict__ cmax, unsigned long long* __restrict__ tiny) {
   __shared__ double m[256];
   double best = 0.0;
+  bool small = false;
   for (uint32_t j = threadIdx.x; j < k; j += blockDim.x) {
     double s = 0.0;
     for (uint32_t t = 0; t < d; ++t) {
-      const double v = C[(uint64_t)j * d + t];
+      const float f = C[(uint64_t)j * d + t];
+      const uint32_t b = __float_as_uint(f) & 0x7FFFFFFFu;
+      small |= b != 0u && b < kTinyBits;
+      const double v = f;
       s += v * v;
     }
     cn[j] = (float)s;
     best = s > best ? s : best;
   }
+  if (small) atomicOr(tiny, 1ull);
   m[threadIdx.x] = best;
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -65,10 +100,11 @@ MR_DEV void load_group(const float* __restrict__ X, uint64_t N, uint64_t g, uint
                        float (&xs)[16]) {
   const uint64_t p = g * 32 + col;
   if (g < groups && p < N) {
-    const f32x4* src = reinterpret_cast<const f32x4*>(X + p * 32 + 16 * h);
+    // dims 8h..8h+7 (xs[0..7]) and 16+8h..16+8h+7 (xs[8..15])
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const f32x4 v = __builtin_nontemporal_load(src + q);
+      const f32x4* src = reinterpret_cast<const f32x4*>(X + p * 32 + 16 * (q / 2) + 8 * h + 4 * (q % 2));
+      const f32x4 v = __builtin_nontemporal_load(src);
       xs[4 * q + 0] = v.x;
       xs[4 * q + 1] = v.y;
       xs[4 * q + 2] = v.z;
@@ -90,19 +126,25 @@ MR_DEV void load_group(const float* __restrict__ X, uint64_t N, uint64_t g, uint
 __global__ __launch_bounds__(kKmThreads) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_km_mfma(const float* __restrict__ X, uint64_t N, const float* __restrict__ C,
                                                         const float* __restrict__ cn_g, const double* __restrict__ cmax_g,
                                                         int32_t* __restrict__ assign, double* __restrict__ part_sum,
-                                                        uint32_t* __restrict__ part_cnt, unsigned long long* __restrict__ n_recheck) {
+                                                        uint32_t* __restrict__ part_cnt, unsigned long long* __restrict__ n_recheck,
+                                                        unsigned long long* __restrict__ tiny) {
   constexpr int D = 32, K = 64, W = kKmThreads / kWave;
   __shared__ double s64[K * D];
   __shared__ uint32_t scnt[K];
   __shared__ float sC[K * D];
   __shared__ float sCn[K];
-  // per wave: x transposed, xt[w][d % 16][(d / 16) * 32 + (p % 2) * 16 + p / 2] = x[p][d],
-  // and the assignments, ab[w][(p % 2) * 16 + p / 2] = a_p (-1 for no point)
-  __shared__ float xt[W][16][64];
+  // centroid pieces: sCp[piece][row][dim] (hi, mid, lo) as A operands
+  __shared__ __bf16 sCp[3][K][D];
+  // per wave: x transposed, xt[w][row(d)][p] = x[p][d] with row(d) =
+  // 16 (d / 16) + 2 (d % 8) + (d / 8) % 2 (the two lanes of a pair write rows
+  // of different parity, hence different banks), and the assignments,
+  // ab[w][p] = a_p (-1 for no point)
+  __shared__ float xt[W][32][32];
   __shared__ int32_t ab[W][32];
   for (int i = threadIdx.x; i < K * D; i += blockDim.x) {
     s64[i] = 0.0;
     sC[i] = C[i];
+    split_bf16x3(C[i], sCp[0][i / D][i % D], sCp[1][i / D][i % D], sCp[2][i / D][i % D]);
   }
   if (threadIdx.x < K) {
     scnt[threadIdx.x] = 0;
@@ -114,19 +156,21 @@ __global__ __launch_bounds__(kKmThreads) __attribute__((amdgpu_waves_per_eu(3, 3
   const uint32_t wv = threadIdx.x / kWave;
   const uint32_t h = lane >> 5;     // which half of the dims (0: 0..15, 1: 16..31)
   const uint32_t col = lane & 31u;  // point within the 32-point group / centroid row within a block
-  const f32x4* ca0 = reinterpret_cast<const f32x4*>(sC + col * D + 16 * h);
-  const f32x4* ca1 = reinterpret_cast<const f32x4*>(sC + (32 + col) * D + 16 * h);
   const float cmax = (float)*cmax_g;
   const float u = 5.9604645e-08f;                     // 2^-24
-  const float gam = (float)D * u / (1.f - (float)D * u);
+  // float32 accumulation of the piece products: 12 instructions of 16 products
+  // each per score, counted as 48 sequential additions (with margin)
+  const float gam = 48.f * u / (1.f - 48.f * u);
+  const float drop = 9.5367432e-07f;                  // 2^-20: the three dropped piece products
   const float e_c = 8.f * u * cmax * cmax;            // centroid-norm rounding, both scores, x2 margin
-  const float e_x = 8.f * (gam + u) * cmax;           // times |x|: dot products and the subtraction
+  const float e_x = 8.f * (gam + u + drop) * cmax;    // times |x|: dot products and the subtraction
 
   const uint32_t waves_total = gridDim.x * W;
   const uint32_t wave_g = blockIdx.x * W + wv;
   const uint64_t groups = (N + 31) / 32;
   const uint64_t iters = (groups + waves_total - 1) / waves_total;  // uniform across the grid
   unsigned long long rechecks = 0;
+  uint32_t tmin = 0xFFFFFFFFu;  // min over this lane's coordinates of (|bits| - 1): zero stays above every tiny value
   f32x16 sum0 = {}, sum1 = {};  // cluster rows 0..31 and 32..63 x dims (float32, since the last flush)
 
   float xs[16], xn[16];
@@ -139,16 +183,38 @@ __global__ __launch_bounds__(kKmThreads) __attribute__((amdgpu_waves_per_eu(3, 3
     load_group(X, N, g + waves_total, groups, col, h, xn);
     f32x16 acc0 = {}, acc1 = {};
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const f32x4 a0 = ca0[q], a1 = ca1[q];
-      acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0.x, xs[4 * q + 0], acc0, 0, 0, 0);
-      acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a1.x, xs[4 * q + 0], acc1, 0, 0, 0);
-      acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0.y, xs[4 * q + 1], acc0, 0, 0, 0);
-      acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a1.y, xs[4 * q + 1], acc1, 0, 0, 0);
-      acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0.z, xs[4 * q + 2], acc0, 0, 0, 0);
-      acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a1.z, xs[4 * q + 2], acc1, 0, 0, 0);
-      acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0.w, xs[4 * q + 3], acc0, 0, 0, 0);
-      acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a1.w, xs[4 * q + 3], acc1, 0, 0, 0);
+    for (int kc = 0; kc < 2; ++kc) {
+      // B: dims 16 kc + 8h + j of point col (xs[8 kc + j]) as three pieces
+      bf16x8 xh, xm, xl;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        __bf16 vh, vm, vl;
+        split_bf16x3(xs[8 * kc + j], vh, vm, vl);
+        xh[j] = vh;
+        xm[j] = vm;
+        xl[j] = vl;
+      }
+#pragma unroll
+      for (int blk = 0; blk < 2; ++blk) {
+        // A: centroid row blk * 32 + col, the same 8 dims
+        const bf16x8 ch = *reinterpret_cast<const bf16x8*>(&sCp[0][blk * 32 + col][16 * kc + 8 * h]);
+        const bf16x8 cm = *reinterpret_cast<const bf16x8*>(&sCp[1][blk * 32 + col][16 * kc + 8 * h]);
+        const bf16x8 cl = *reinterpret_cast<const bf16x8*>(&sCp[2][blk * 32 + col][16 * kc + 8 * h]);
+        f32x16 acc = blk ? acc1 : acc0;
+        // smaller products first
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(cm, xm, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(cl, xh, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ch, xl, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(cm, xh, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ch, xm, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ch, xh, acc, 0, 0, 0);
+        if (blk) acc1 = acc; else acc0 = acc;
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+      const uint32_t b = (__float_as_uint(xs[t]) & 0x7FFFFFFFu) - 1u;
+      tmin = b < tmin ? b : tmin;
     }
     // |x| for the bound
     float nx = 0.f;
@@ -210,13 +276,13 @@ __global__ __launch_bounds__(kKmThreads) __attribute__((amdgpu_waves_per_eu(3, 3
         cand &= cand - 1u;
         const int rr = bit & 15;
         const int idx = (bit >> 4) * 32 + 8 * (rr / 4) + 4 * (int)h + (rr % 4);
-        // own half first, then the partner's (dims 16h.., then 16(1-h)..)
-        const f32x4* c4 = reinterpret_cast<const f32x4*>(sC + idx * D + 16 * h);
-        const f32x4* c4o = reinterpret_cast<const f32x4*>(sC + idx * D + 16 * (1 - h));
+        // own dims first, then the partner's: lane half g holds dims 8g..8g+7
+        // and 16+8g..16+8g+7, in xs order
         double dj = 0.0;
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
-          const f32x4 c = q < 4 ? c4[q] : c4o[q - 4];
+          const uint32_t g = q < 4 ? h : 1u - h;
+          const f32x4 c = *reinterpret_cast<const f32x4*>(sC + idx * D + 16 * ((q % 4) / 2) + 8 * g + 4 * (q % 2));
           const float* xv = q < 4 ? xs + 4 * q : xo + 4 * (q - 4);
           float x0 = xv[0], x1 = xv[1], x2 = xv[2], x3 = xv[3];
           // keeps the float64 conversions of x inside this rare loop (hoisted
@@ -251,28 +317,41 @@ __global__ __launch_bounds__(kKmThreads) __attribute__((amdgpu_waves_per_eu(3, 3
     }
     // update: x transposed through LDS, one-hot assignments as the A operand
 #pragma unroll
-    for (int t = 0; t < 16; ++t) xt[wv][t][h * 32 + (col & 1u) * 16 + (col >> 1)] = xs[t];
-    if (h == 0) ab[wv][(col & 1u) * 16 + (col >> 1)] = valid ? bi : -1;
+    for (int t = 0; t < 16; ++t) xt[wv][16 * (t / 8) + 2 * (t % 8) + h][col] = xs[t];  // xs[t] is dim 16 (t / 8) + 8h + t % 8
+    if (h == 0) ab[wv][col] = valid ? bi : -1;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     {
-      // lane (col, h) supplies B[h][col] = x[2s + h][col] and A[col][h] = [a_{2s+h} = blk * 32 + col]
-      const f32x4* xr = reinterpret_cast<const f32x4*>(&xt[wv][col & 15u][(col >> 4) * 32 + h * 16]);
-      const int4* ar = reinterpret_cast<const int4*>(&ab[wv][h * 16]);
+      // 16 points per instruction: lane (col, h) supplies A[col][8h + j] =
+      // [a_p = blk * 32 + col] and B[8h + j][col] = x[p][col] (as three
+      // pieces) for the points p = 16 kc + 8h + j, j = 0..7
+      const float* xrow = &xt[wv][16 * (col / 16) + 2 * (col % 8) + (col / 8) % 2][0];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const f32x4 xv = xr[q];
-        const int4 av = ar[q];
-        const float xq[4] = {xv.x, xv.y, xv.z, xv.w};
-        const int aq[4] = {av.x, av.y, av.z, av.w};
+      for (int kc = 0; kc < 2; ++kc) {
+        const f32x4 xa = *reinterpret_cast<const f32x4*>(xrow + 16 * kc + 8 * h);
+        const f32x4 xb = *reinterpret_cast<const f32x4*>(xrow + 16 * kc + 8 * h + 4);
+        const int4 aa = *reinterpret_cast<const int4*>(&ab[wv][16 * kc + 8 * h]);
+        const int4 ac = *reinterpret_cast<const int4*>(&ab[wv][16 * kc + 8 * h + 4]);
+        const float xv[8] = {xa.x, xa.y, xa.z, xa.w, xb.x, xb.y, xb.z, xb.w};
+        const int av[8] = {aa.x, aa.y, aa.z, aa.w, ac.x, ac.y, ac.z, ac.w};
+        bf16x8 ph, pm, pl, o0, o1;
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const float o0 = aq[e] == (int)col ? 1.f : 0.f;
-          const float o1 = aq[e] == (int)(32 + col) ? 1.f : 0.f;
-          sum0 = __builtin_amdgcn_mfma_f32_32x32x2f32(o0, xq[e], sum0, 0, 0, 0);
-          sum1 = __builtin_amdgcn_mfma_f32_32x32x2f32(o1, xq[e], sum1, 0, 0, 0);
+        for (int j = 0; j < 8; ++j) {
+          __bf16 vh, vm, vl;
+          split_bf16x3(xv[j], vh, vm, vl);
+          ph[j] = vh;
+          pm[j] = vm;
+          pl[j] = vl;
+          o0[j] = bf16_bits(av[j] == (int)col ? 0x3F80u : 0u);
+          o1[j] = bf16_bits(av[j] == (int)(32 + col) ? 0x3F80u : 0u);
         }
+        sum0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(o0, ph, sum0, 0, 0, 0);
+        sum1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(o1, ph, sum1, 0, 0, 0);
+        sum0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(o0, pm, sum0, 0, 0, 0);
+        sum1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(o1, pm, sum1, 0, 0, 0);
+        sum0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(o0, pl, sum0, 0, 0, 0);
+        sum1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(o1, pl, sum1, 0, 0, 0);
       }
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -294,6 +373,7 @@ __global__ __launch_bounds__(kKmThreads) __attribute__((amdgpu_waves_per_eu(3, 3
   }
   __syncthreads();
   if (rechecks) atomicAdd(n_recheck, rechecks);
+  if (tmin < kTinyBits - 1u) atomicOr(tiny, 1ull);
   for (int i = threadIdx.x; i < K * D; i += blockDim.x) part_sum[(uint64_t)blockIdx.x * K * D + i] = s64[i];
   if (threadIdx.x < K) part_cnt[(uint64_t)blockIdx.x * K + threadIdx.x] = scnt[threadIdx.x];
 }
@@ -384,11 +464,11 @@ __global__ __launch_bounds__(kFinalWaves * kWave) void k_km_final(const double* 
 }
 
 hipError_t km_enqueue(const KmLaunch& L, hipStream_t s, hipEvent_t map0, hipEvent_t map1) {
-  hipLaunchKernelGGL(k_km_prep, dim3(1), dim3(256), 0, s, L.C, L.k, L.d, L.cn, L.cmax);
+  hipLaunchKernelGGL(k_km_prep, dim3(1), dim3(256), 0, s, L.C, L.k, L.d, L.cn, L.cmax, L.tiny);
   if (map0) (void)hipEventRecord(map0, s);
   if (L.mfma) {
     hipLaunchKernelGGL(k_km_mfma, dim3(L.G), dim3(kKmThreads), 0, s, L.X, L.N, L.C, L.cn, L.cmax, L.assign, L.part_sum,
-                       L.part_cnt, L.n_recheck);
+                       L.part_cnt, L.n_recheck, L.tiny);
   } else {
     hipLaunchKernelGGL(k_km_zero, dim3(256), dim3(256), 0, s, L.part_sum, (uint64_t)L.k * L.d, L.part_cnt, (uint64_t)L.k);
     const uint64_t b = (L.N + 255) / 256;

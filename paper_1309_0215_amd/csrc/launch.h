@@ -170,6 +170,7 @@ struct KmLaunch {
   double* part_sum;     // [G][k][d]
   uint32_t* part_cnt;   // [G][k]
   unsigned long long* n_recheck;
+  unsigned long long* tiny;  // set when a coordinate is nonzero and below 2^-100 (the step is then redone generically)
   float* sums;          // [k][d]
   uint32_t* counts;     // [k]
   float* cent;          // [k][d]

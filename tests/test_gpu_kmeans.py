@@ -68,6 +68,38 @@ def test_mfma_path(torch, n):
     _check_update(X, Cn, a, s, c, cent)
 
 
+@pytest.mark.parametrize("scale", [1e-3, 1e3])
+def test_mfma_path_scales(torch, scale):
+    # the near-tie bound scales with |x| and max |c|: small and large coordinates
+    X, Cn = gen.kmeans(7, n=50_000, d=32, k=64)
+    X = (X * scale).astype(np.float32)
+    Cn = (Cn * scale).astype(np.float32)
+    a, s, c, cent, st = _run(torch, X, Cn)
+    assert st["strategy_used"] == 1
+    _check_assign(X, Cn, a)
+    _check_update(X, Cn, a, s, c, cent)
+
+
+def test_tiny_coordinates_redo_the_step_generically(torch):
+    # a nonzero coordinate below 2^-100 (in a point or a centroid) is outside
+    # the exact bfloat16 split of the matrix-core path: the generic kernel
+    # redoes the step
+    X, Cn = gen.kmeans(8, n=4096, d=32, k=64)
+    X = X.copy()
+    X[100:200] *= np.float32(1e-33)
+    a, s, c, cent, st = _run(torch, X, Cn)
+    assert st["strategy_used"] == 0
+    _check_assign(X, Cn, a)
+    _check_update(X, Cn, a, s, c, cent)
+    X, Cn = gen.kmeans(9, n=4096, d=32, k=64)
+    Cn = Cn.copy()
+    Cn[5, 3] = np.float32(1e-35)
+    a, s, c, cent, st = _run(torch, X, Cn)
+    assert st["strategy_used"] == 0
+    _check_assign(X, Cn, a)
+    _check_update(X, Cn, a, s, c, cent)
+
+
 def test_generic_path_any_shape(torch):
     rng = np.random.default_rng(2)
     X = rng.standard_normal((3001, 5)).astype(np.float32)
