@@ -133,7 +133,10 @@ __global__ __launch_bounds__(kKmThreads) __attribute__((amdgpu_waves_per_eu(3, 3
   __shared__ uint32_t scnt[K];
   __shared__ float sC[K * D];
   __shared__ float sCn[K];
-  // centroid pieces: sCp[piece][row][dim] (hi, mid, lo) as A operands
+  // centroid pieces (hi, mid, lo) as A operands: sCp[piece][row][...] holds
+  // the row's four 8-dim chunks, chunk c at position c ^ ((row / 4) % 4), so
+  // that the 16 lanes of one 16-byte read (rows r..r+15) meet 16 different
+  // bank groups
   __shared__ __bf16 sCp[3][K][D];
   // per wave: x transposed, xt[w][row(d)][p] = x[p][d] with row(d) =
   // 16 (d / 16) + 2 (d % 8) + (d / 8) % 2 (the two lanes of a pair write rows
@@ -144,7 +147,8 @@ __global__ __launch_bounds__(kKmThreads) __attribute__((amdgpu_waves_per_eu(3, 3
   for (int i = threadIdx.x; i < K * D; i += blockDim.x) {
     s64[i] = 0.0;
     sC[i] = C[i];
-    split_bf16x3(C[i], sCp[0][i / D][i % D], sCp[1][i / D][i % D], sCp[2][i / D][i % D]);
+    const int r = i / D, e = ((((i % D) / 8) ^ ((r / 4) % 4)) * 8) + i % 8;
+    split_bf16x3(C[i], sCp[0][r][e], sCp[1][r][e], sCp[2][r][e]);
   }
   if (threadIdx.x < K) {
     scnt[threadIdx.x] = 0;
@@ -197,9 +201,10 @@ __global__ __launch_bounds__(kKmThreads) __attribute__((amdgpu_waves_per_eu(3, 3
 #pragma unroll
       for (int blk = 0; blk < 2; ++blk) {
         // A: centroid row blk * 32 + col, the same 8 dims
-        const bf16x8 ch = *reinterpret_cast<const bf16x8*>(&sCp[0][blk * 32 + col][16 * kc + 8 * h]);
-        const bf16x8 cm = *reinterpret_cast<const bf16x8*>(&sCp[1][blk * 32 + col][16 * kc + 8 * h]);
-        const bf16x8 cl = *reinterpret_cast<const bf16x8*>(&sCp[2][blk * 32 + col][16 * kc + 8 * h]);
+        const uint32_t row = blk * 32 + col, pc = ((2 * kc + h) ^ ((row / 4) % 4)) * 8;
+        const bf16x8 ch = *reinterpret_cast<const bf16x8*>(&sCp[0][row][pc]);
+        const bf16x8 cm = *reinterpret_cast<const bf16x8*>(&sCp[1][row][pc]);
+        const bf16x8 cl = *reinterpret_cast<const bf16x8*>(&sCp[2][row][pc]);
         f32x16 acc = blk ? acc1 : acc0;
         // smaller products first
         acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(cm, xm, acc, 0, 0, 0);
