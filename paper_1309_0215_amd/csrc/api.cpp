@@ -83,8 +83,7 @@ struct mr_job {
   // final table size of recent word jobs by input (address, length): a job
   // over the same input starts at the size it grew to, in a batch too
   std::unordered_map<uint64_t, uint64_t> table_hint;
-  hipStream_t gstream = nullptr;  // non-blocking stream for capture (the caller's may be the null stream)
-  hipEvent_t gev = nullptr;
+  hipStream_t gstream = nullptr;  // non-blocking stream for graph capture (the job's may be the null stream)
   // pinned host staging for job states
   JobState* h_states = nullptr;
   uint32_t h_states_cap = 0;
@@ -239,7 +238,6 @@ extern "C" mr_status mr_job_create(const mr_job_config* cfg, mr_job** out) {
   ScopedDevice sd(job->device);
   if (hipEventCreate(&job->ev0) != hipSuccess || hipEventCreate(&job->ev1) != hipSuccess ||
       hipEventCreate(&job->ev2) != hipSuccess || hipEventCreate(&job->ev3) != hipSuccess ||
-      hipEventCreateWithFlags(&job->gev, hipEventDisableTiming) != hipSuccess ||
       hipStreamCreateWithFlags(&job->gstream, hipStreamNonBlocking) != hipSuccess) {
     delete job;
     return fail(MR_ERR_HIP, "hipEventCreate failed");
@@ -271,7 +269,6 @@ extern "C" mr_status mr_job_destroy(mr_job* job) {
     if (e) (void)hipEventDestroy(e);
   if (job->gstream) (void)hipStreamSynchronize(job->gstream);
   if (job->gstream) (void)hipStreamDestroy(job->gstream);
-  if (job->gev) (void)hipEventDestroy(job->gev);
   if (job->ws) (void)hipFree(job->ws);
   if (job->km_c) (void)hipFree(job->km_c);
   if (job->h_states) (void)hipHostFree(job->h_states);
@@ -458,13 +455,11 @@ mr_status words_pass(mr_job* job, std::vector<WordItem>& items, std::vector<JobS
   const bool use_graph = mode == GraphMode::kAlways || (mode == GraphMode::kOnRepeat && !job->cfg.timing &&
                                                        (key == job->plain_key || key == job->graph_key));
   job->plain_key = use_graph ? 0 : key;
-  // Graphs run on the job's own stream, ordered after the caller's stream.
-  hipStream_t s = job->stream;
-  if (use_graph) {
-    MR_HIP(hipEventRecord(job->gev, job->stream));
-    MR_HIP(hipStreamWaitEvent(job->gstream, job->gev, 0));
-    s = job->gstream;
-  }
+  // Everything runs on the job's stream; a graph is only captured on the
+  // capture stream (the job's stream may be the null stream, which cannot
+  // be captured) and is launched on the job's stream, which orders it after
+  // the work before it without an event.
+  const hipStream_t s = job->stream;
   const uint64_t table_bytes_g = p.o_tc + p.total_slots * 4;
   if (use_graph && job->graph && job->graph_valid && job->graph_key == key && job->table_clean_bytes >= table_bytes_g) {
     // replay: descriptors, tile bases and the clean table are still in place
@@ -569,12 +564,13 @@ mr_status words_pass(mr_job* job, std::vector<WordItem>& items, std::vector<JobS
       job->graph = nullptr;
     }
     hipGraph_t g = nullptr;
-    MR_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-    hipError_t e = words_enqueue_zero_states(L, s);
-    if (e == hipSuccess) e = words_enqueue_prep(L, s);
-    if (e == hipSuccess) e = words_enqueue_map(L, s);
-    if (e == hipSuccess) e = words_enqueue_reduce(L, s);
-    const hipError_t e2 = hipStreamEndCapture(s, &g);
+    const hipStream_t cs = job->gstream;
+    MR_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    hipError_t e = words_enqueue_zero_states(L, cs);
+    if (e == hipSuccess) e = words_enqueue_prep(L, cs);
+    if (e == hipSuccess) e = words_enqueue_map(L, cs);
+    if (e == hipSuccess) e = words_enqueue_reduce(L, cs);
+    const hipError_t e2 = hipStreamEndCapture(cs, &g);
     if (e != hipSuccess || e2 != hipSuccess) {
       if (g) (void)hipGraphDestroy(g);
       return fail(MR_ERR_HIP, "graph capture failed: %s", hipGetErrorString(e != hipSuccess ? e : e2));
