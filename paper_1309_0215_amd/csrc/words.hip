@@ -404,62 +404,80 @@ MR_DEV uint32_t find_job(const uint64_t* __restrict__ tile_base, uint32_t n_jobs
 // Separator mask of a 16-byte block.
 MR_DEV uint32_t sep16(uint4 b) { return sep_mask16(b.x, b.y, b.z, b.w); }
 
-// One workgroup per run of tiles. For each 16 KiB tile:
-//   1. every lane loads one 16-byte chunk into the LDS copy of the tile (plus
-//      32 bytes after it) and finds the words that start in its chunk;
-//   2. words of up to 16 bytes become descriptors (offset in the tile, length)
-//      in a per-wave list, placed by a wave prefix sum; longer words are
+// One workgroup per run of tiles; each 16 KiB tile is cut into 16 parts of
+// 1 KiB, and wave w takes part w of every tile of the run. The waves share the
+// LDS hash cache but no barrier between tiles: each moves on to its next part
+// as soon as it is done, so the latency one wave waits on (a global probe, a
+// slow word) is hidden by the others instead of holding the whole workgroup
+// at a barrier. For each part:
+//   1. every lane loads one 16-byte chunk into the wave's LDS copy of the part
+//      (plus 32 bytes after it) and finds the words that start in its chunk;
+//   2. words of up to 16 bytes become descriptors (offset in the part, length)
+//      in the wave's list, placed by a wave prefix sum; longer words are
 //      measured, hashed and inserted globally by their lane at once;
 //   3. the wave then takes the list one word per lane (all lanes busy): key
 //      bytes from the LDS copy, hash, LDS table insert, global insert on a miss.
+// Workgroup barriers remain where the run moves to another job (the cache is
+// flushed into the old job's table) and at the end.
 template <int L, bool kRecords>
 __global__ __launch_bounds__(kMapThreads) void k_words_map(const WordJob* __restrict__ jobs, const uint64_t* __restrict__ tile_base,
                                                            uint32_t n_jobs, uint64_t total_tiles, uint32_t debug_hash) {
+  constexpr uint32_t kWaves = kMapThreads / kWave;
+  constexpr uint32_t kPart = kMapTileChunks / kWaves;  // chunks per wave part (one per lane)
+  static_assert(kPart == kWave, "one chunk per lane");
   __shared__ LdsTable<L> T;
-  __shared__ uint4 stage[kMapTileChunks + 2];
-  __shared__ uint32_t wlist[kMapThreads / kWave][kListCap];
-  constexpr uint32_t kBndWords = kMapTileChunks * 16 / 32 + 2;
-  __shared__ uint32_t bnd[kRecords ? kBndWords : 1];
-  __shared__ uint32_t s_abort, s_used;
+  __shared__ uint4 stage[kWaves][kPart + 2];
+  __shared__ uint32_t wlist[kWaves][kListCap];
+  constexpr uint32_t kBndWords = kPart * 16 / 32 + 2;
+  __shared__ uint32_t bnd[kRecords ? kWaves : 1][kRecords ? kBndWords : 1];
+  __shared__ uint32_t s_used;
   // fill limit of the LDS table: beyond it new words go straight to the global table
   constexpr uint32_t kLimit = LdsTable<L>::kSlots / 4 * 3;
 
   for (uint32_t i = threadIdx.x; i < LdsTable<L>::kSlots; i += blockDim.x) T.tag[i] = 0u;
-  if (threadIdx.x == 0) {
-    s_abort = 0;
-    s_used = 0;
-  }
+  if (threadIdx.x == 0) s_used = 0;
   __syncthreads();
 
   const uint64_t t_begin = total_tiles * blockIdx.x / gridDim.x;
   const uint64_t t_end = total_tiles * (blockIdx.x + 1) / gridDim.x;
   const uint32_t wave = threadIdx.x / kWave;
   const uint32_t lane = lane_id();
+  uint4* const ws = stage[wave];
   int cur = -1;
   uint64_t vlo = 0, vhi = 0;
+  auto wave_sync = [] {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+  };
 
-  // This lane's chunk of tile t (and, for thread 0, the chunk before the
-  // tile): loaded one tile ahead, so that the loads of the next tile are in
-  // flight while the current one is processed.
-  auto load_tile = [&](uint64_t t, uint4& mine, uint4& before) {
+  // This lane's chunk of the wave's part of tile t (lane 0 also the chunk
+  // before the part, lanes 0 and 1 the two after it): loaded one tile ahead,
+  // so that the loads of the next part are in flight while the current one
+  // is processed.
+  auto load_part = [&](uint64_t t, uint4& mine, uint4& extra) {
     const uint32_t jn = find_job(tile_base, n_jobs, t);
     const WordJob& Jn = jobs[jn];
     const uint64_t an0 = (uint64_t)Jn.in, an1 = an0 + Jn.n;
-    const uint64_t cn = (t - tile_base[jn]) * kMapTileChunks + threadIdx.x;
-    const uint64_t Bn = (Jn.chunk0 + cn) * 16;
-    mine = cn < Jn.n_chunks ? load_block(an0, an1, Bn) : spaces4();
-    if (threadIdx.x == 0) before = load_block(an0, an1, Bn - 16);
+    const uint64_t c0 = (t - tile_base[jn]) * kMapTileChunks + wave * kPart;  // the part's first chunk
+    const uint64_t cn = c0 + lane;
+    mine = cn < Jn.n_chunks ? load_block(an0, an1, (Jn.chunk0 + cn) * 16) : spaces4();
+    // lane 0: the chunk before the part (its address is checked against the
+    // input by load_block, also before the first chunk); lanes 1, 2: the two
+    // chunks after the part, where the job has them
+    const uint64_t cx = lane == 0 ? c0 - 1 : c0 + kPart + (lane - 1);
+    const bool ok = lane == 0 || (lane <= 2 && cx < Jn.n_chunks);
+    extra = ok ? load_block(an0, an1, (Jn.chunk0 + cx) * 16) : spaces4();
   };
-  uint4 nx_mine = spaces4(), nx_before = spaces4();
-  if (t_begin < t_end) load_tile(t_begin, nx_mine, nx_before);
+  uint4 nx_mine = spaces4(), nx_extra = spaces4();
+  if (t_begin < t_end) load_part(t_begin, nx_mine, nx_extra);
 
   for (uint64_t t = t_begin; t < t_end; ++t) {
-    const uint4 b0 = nx_mine, pre_chunk = nx_before;
-    if (t + 1 < t_end) load_tile(t + 1, nx_mine, nx_before);
-    // every thread is done with the previous tile (its abort flag, LDS copy and lists)
-    __syncthreads();
+    const uint4 b0 = nx_mine, ex = nx_extra;
+    if (t + 1 < t_end) load_part(t + 1, nx_mine, nx_extra);
     const uint32_t j = find_job(tile_base, n_jobs, t);
     if ((int)j != cur) {
+      // every wave meets this point at the same tile
+      __syncthreads();
       if (cur >= 0) {
         if (jobs[cur].queue) lds_flush_parts<L>(T, jobs[cur], &wlist[0][0], vlo, vhi, debug_hash);
         else lds_flush<L>(T, jobs[cur], vlo, vhi, debug_hash);
@@ -471,48 +489,45 @@ __global__ __launch_bounds__(kMapThreads) void k_words_map(const WordJob* __rest
       vhi = gp(jobs[j].st)->valid_hi;
     }
     const WordJob& J = jobs[j];
-    if (threadIdx.x == 0)
-      s_abort = (__hip_atomic_load(gp(&J.st->flags), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & (kFlagTableFull | kFlagBadInput)) ? 1u : 0u;
+    const bool abort =
+        (__hip_atomic_load(gp(&J.st->flags), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & (kFlagTableFull | kFlagBadInput)) != 0;
+    if (abort) continue;  // uniform over the wave
     const uint64_t lt = t - tile_base[j];
-    const uint64_t a0 = (uint64_t)J.in, a1 = a0 + J.n;
-    const uint64_t tile_addr = (J.chunk0 + lt * kMapTileChunks) * 16;
+    const uint64_t a0 = (uint64_t)J.in;
+    const uint64_t part_addr = (J.chunk0 + lt * kMapTileChunks + wave * kPart) * 16;  // the part's first byte
 
+    // the previous part's list and copy are no longer read by any lane of the wave
+    wave_sync();
     if constexpr (kRecords) {
-      for (uint32_t i = threadIdx.x; i < kBndWords; i += blockDim.x) bnd[i] = 0u;
-      __syncthreads();
-      // record boundaries falling in [tile_addr, tile_addr + 32 * kBndWords);
+      for (uint32_t i = lane; i < kBndWords; i += kWave) bnd[wave][i] = 0u;
+      wave_sync();
+      // record boundaries falling in [part_addr, part_addr + 32 * kBndWords);
       // in a batch that mixes jobs with and without records, the latter keep an empty bitmap
       if (J.rec) {
-        const int64_t lo_rel = (int64_t)(tile_addr - a0);
+        const int64_t lo_rel = (int64_t)(part_addr - a0);
         const uint64_t r0 = rec_lower_bound(J.rec, J.n_rec, lo_rel < 0 ? 0 : (uint64_t)lo_rel);
-        for (uint64_t r = r0 + threadIdx.x; r <= J.n_rec; r += blockDim.x) {
+        for (uint64_t r = r0 + lane; r <= J.n_rec; r += kWave) {
           const uint64_t pa = a0 + gp(J.rec)[r];
-          if (pa < tile_addr) continue;
-          const uint64_t bit = pa - tile_addr;
+          if (pa < part_addr) continue;
+          const uint64_t bit = pa - part_addr;
           if (bit >= 32ull * kBndWords) break;
-          atomicOr(&bnd[bit >> 5], 1u << (bit & 31));
+          atomicOr(&bnd[wave][bit >> 5], 1u << (bit & 31));
         }
       }
     }
-    __syncthreads();
-    if (s_abort) continue;
 
-    // 1. the tile into LDS; this lane's chunk and the next one as a 32-byte window
-    const uint64_t c = lt * kMapTileChunks + threadIdx.x;  // this lane's chunk
-    const uint64_t B = (J.chunk0 + c) * 16;                 // its absolute address
-    stage[threadIdx.x] = b0;
-    if (threadIdx.x < 2) {
-      const uint64_t cx = lt * kMapTileChunks + kMapTileChunks + threadIdx.x;
-      stage[kMapTileChunks + threadIdx.x] = cx < J.n_chunks ? load_block(a0, a1, (J.chunk0 + cx) * 16) : spaces4();
-    }
-    __syncthreads();
-    const uint4 b1 = stage[threadIdx.x + 1];
+    // 1. the part into LDS; this lane's chunk and the next one as a 32-byte window
+    const uint64_t B = part_addr + 16ull * lane;  // this lane's chunk (absolute address)
+    ws[lane] = b0;
+    if (lane == 1 || lane == 2) ws[kPart + lane - 1] = ex;
+    wave_sync();
+    const uint4 b1 = ws[lane + 1];
     // byte B - 1: last byte of the previous chunk (a separator outside the valid range)
     uint32_t prev = 1u;
     {
       const uint64_t pb = B - 1;
       if (pb >= a0 + vlo && pb < a0 + vhi) {
-        const uint4 q = threadIdx.x ? stage[threadIdx.x - 1] : pre_chunk;
+        const uint4 q = lane ? ws[lane - 1] : ex;
         prev = (sep_mask4(q.w) >> 3) & 1u;
       }
     }
@@ -520,9 +535,9 @@ __global__ __launch_bounds__(kMapThreads) void k_words_map(const WordJob* __rest
     const uint32_t sep = (sep16(b0) | (sep16(b1) << 16)) | ~valid;
     uint32_t bd = 0u;
     if constexpr (kRecords) {
-      const uint64_t bit = B - tile_addr;  // multiple of 16
+      const uint64_t bit = B - part_addr;  // multiple of 16
       const uint32_t wi = (uint32_t)(bit >> 5);
-      const uint32_t lo = bnd[wi], hi = bnd[wi + 1];
+      const uint32_t lo = bnd[wave][wi], hi = bnd[wave][wi + 1];
       bd = (bit & 16) ? ((lo >> 16) | (hi << 16)) : lo;
     }
     const uint32_t starts = ~sep & ((sep << 1) | prev | bd) & 0xFFFFu;
@@ -562,20 +577,19 @@ __global__ __launch_bounds__(kMapThreads) void k_words_map(const WordJob* __rest
         const uint32_t s = __builtin_ctz(m);
         const uint32_t after = ends & ~((2u << s) - 1u);
         const uint32_t len = (uint32_t)__builtin_ctz(after) - s;
-        wlist[wave][p - base] = ((threadIdx.x * 16u + s) << 5) | len;
+        wlist[wave][p - base] = ((lane * 16u + s) << 5) | len;
       }
-      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-      __builtin_amdgcn_wave_barrier();
+      wave_sync();
       const uint32_t nr = (total - base) < kListCap ? (total - base) : kListCap;
       for (uint32_t i = lane; i < nr; i += kWave) {
         const uint32_t d = wlist[wave][i];
         const uint32_t o = d >> 5, len = d & 31u;
-        const uint4 x0 = stage[o >> 4], x1 = stage[(o >> 4) + 1];
+        const uint4 x0 = ws[o >> 4], x1 = ws[(o >> 4) + 1];
         const uint32_t w[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
         const uint4 k = extract16(w, o & 15u, len);
         const uint64_t h = key_hash16(k, len, debug_hash);
         const uint32_t tg = lds_tag(h, len);
-        const uint64_t off = tile_addr + o - a0;
+        const uint64_t off = part_addr + o - a0;
         int r = 1;
         for (uint32_t spin = 0; r == 1; ++spin) {
           r = lds_insert<L>(T, &s_used, kLimit, tg, (uint32_t)h, k, (uint32_t)off);
@@ -586,8 +600,7 @@ __global__ __launch_bounds__(kMapThreads) void k_words_map(const WordJob* __rest
         }
         if (r == 2) g_insert<true>(J, vlo, vhi, off, len, h, k, 1u, debug_hash);
       }
-      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-      __builtin_amdgcn_wave_barrier();
+      wave_sync();
     }
   }
   __syncthreads();
