@@ -6,7 +6,7 @@ table, sort), the device time of each is measured, and all containers must
 produce identical outputs. Job features come from the library's feature
 kernel. The 12-64-64-4 network is trained on the GPU with the library's own
 forward, backward and Adam kernels (this module only marshals tensors), and
-is judged against the paper-style rule by regret on held-out jobs.
+is compared with the paper-style rule by regret on held-out jobs.
 
 Readings of the selector set-up (not in the paper): ReLU; the four outputs
 predict standardised log device times (one mean and scale over all
