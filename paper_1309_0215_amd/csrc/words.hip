@@ -836,6 +836,95 @@ MR_DEV void soa_bitonic(const WordJob& J, const WRec* recs, SoaKeys<CAP>& S, uin
   }
 }
 
+// The same sort with one entry per thread in registers, for m <= blockDim.x:
+// compare-exchange stages between lanes of one wave (partner distance < 64)
+// swap through shuffles with no barrier; only the stages with a farther
+// partner go through the LDS arrays (10 of the 55 stages of a 1024-entry
+// sort). The network and the order are those of soa_bitonic; entries past m
+// are +infinity. S holds the input and receives the sorted entries.
+constexpr uint32_t kRegPad = 0xFFFFFFFFu;  // index field of a padding entry
+
+MR_DEV int reg_cmp(const WordJob& J, const WRec* recs, const uint32_t (&a)[6], const uint32_t (&b)[6]) {
+  // a[0..3]: prefix words, a[4]: length, a[5]: record index (kRegPad: padding)
+  if (a[5] == kRegPad || b[5] == kRegPad) return (a[5] == kRegPad ? 1 : 0) - (b[5] == kRegPad ? 1 : 0);
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+    if (a[q] != b[q]) return a[q] < b[q] ? -1 : 1;
+  if (a[4] > 16u && b[4] > 16u) {
+    const int c = input_cmp(J.in, recs[a[5]].off, recs[b[5]].off, 16, a[4] < b[4] ? a[4] : b[4]);
+    if (c) return c;
+  }
+  return a[4] < b[4] ? -1 : (a[4] > b[4] ? 1 : 0);
+}
+
+template <uint32_t CAP>
+MR_DEV void reg_bitonic(const WordJob& J, const WRec* recs, SoaKeys<CAP>& S, uint32_t m) {
+  uint32_t n = 1;
+  while (n < m) n <<= 1;
+  const uint32_t t = threadIdx.x;
+  const bool act = t < n;
+  uint32_t a[6];
+  if (t < m) {
+    a[0] = S.k[0][t];
+    a[1] = S.k[1][t];
+    a[2] = S.k[2][t];
+    a[3] = S.k[3][t];
+    a[4] = S.len[t];
+    a[5] = S.ix[t];
+  } else {
+#pragma unroll
+    for (int q = 0; q < 6; ++q) a[q] = kRegPad;
+  }
+  __syncthreads();  // every entry is read before S is used for exchanges
+  for (uint32_t k = 2; k <= n; k <<= 1) {
+    for (uint32_t jj = k >> 1; jj > 0; jj >>= 1) {
+      const uint32_t x = jj == (k >> 1) ? (k - 1) : jj;  // partner: t ^ x
+      uint32_t b[6];
+      if (x < (uint32_t)kWave) {
+#pragma unroll
+        for (int q = 0; q < 6; ++q) b[q] = (uint32_t)__shfl_xor((int)a[q], (int)x);
+      } else {
+        if (act) {
+          S.k[0][t] = a[0];
+          S.k[1][t] = a[1];
+          S.k[2][t] = a[2];
+          S.k[3][t] = a[3];
+          S.len[t] = a[4];
+          S.ix[t] = a[5];
+        }
+        __syncthreads();
+        if (act) {
+          const uint32_t p = t ^ x;
+          b[0] = S.k[0][p];
+          b[1] = S.k[1][p];
+          b[2] = S.k[2][p];
+          b[3] = S.k[3][p];
+          b[4] = S.len[p];
+          b[5] = S.ix[p];
+        }
+        __syncthreads();
+      }
+      if (act) {
+        // the lower index of the pair keeps the smaller entry
+        const int c = reg_cmp(J, recs, a, b);
+        if ((t & jj) == 0 ? c > 0 : c < 0) {
+#pragma unroll
+          for (int q = 0; q < 6; ++q) a[q] = b[q];
+        }
+      }
+    }
+  }
+  if (t < m) {
+    S.k[0][t] = a[0];
+    S.k[1][t] = a[1];
+    S.k[2][t] = a[2];
+    S.k[3][t] = a[3];
+    S.len[t] = a[4];
+    S.ix[t] = a[5];
+  }
+  __syncthreads();
+}
+
 constexpr uint32_t kSortThreads = 1024;
 constexpr uint32_t kOversample = 4;
 
@@ -885,7 +974,8 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_splitters(const WordJob* 
     soa_load(smp, i, recs[ix], ix);
   }
   __syncthreads();
-  soa_bitonic(J, recs, smp, S);
+  if (S <= blockDim.x) reg_bitonic(J, recs, smp, S);
+  else soa_bitonic(J, recs, smp, S);
   WRec* spl = reinterpret_cast<WRec*>(J.splitters);
   for (uint32_t b = threadIdx.x; b + 1 < nb; b += blockDim.x) spl[b] = recs[smp.ix[(b + 1) * kOversample - 1]];
 }
@@ -1073,7 +1163,8 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_buckets(const WordJob* __
     if (in_lds) {
       for (uint32_t i = threadIdx.x; i < m; i += blockDim.x) soa_load(a, i, src[i], i);
       __syncthreads();
-      soa_bitonic(J, src, a, m);
+      if (m <= blockDim.x) reg_bitonic(J, src, a, m);
+      else soa_bitonic(J, src, a, m);
     } else {
       if (threadIdx.x == 0) atomicOr(&J.st->flags, kFlagSortFallback);  // rare: sort the bucket in global memory
       bitonic_sort(J, src, m);
