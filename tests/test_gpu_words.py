@@ -208,3 +208,35 @@ def test_repeated_calls_replay_and_follow_content(torch):
         kb, ko, vals = keep
         nk = int(o.n_keys)
         _check(WordsResult(kb[:o.key_bytes_used], ko[:nk + 1], vals[:nk], {}), b)
+
+
+def _uneven_parts(seed: int, n_tiles: int) -> np.ndarray:
+    # 16 KiB tiles of sixteen 1 KiB parts: even parts hold words of 17-60
+    # bytes (measured and inserted globally by their own lane), odd parts
+    # short words from a small vocabulary (LDS cache hits), so that the waves
+    # of a workgroup take very different times over the same tiles; words
+    # also run across part and tile boundaries
+    rng = np.random.default_rng(seed)
+    vocab = [bytes(rng.integers(97, 123, size=int(rng.integers(2, 9)), dtype=np.uint8)) for _ in range(300)]
+    out = bytearray()
+    for _ in range(n_tiles * 16):
+        part = bytearray()
+        long_part = (len(out) // 1024) % 2 == 0
+        while len(part) < 1024:
+            if long_part:
+                part += bytes(rng.integers(97, 123, size=int(rng.integers(17, 61)), dtype=np.uint8)) + b" "
+            else:
+                part += vocab[int(rng.integers(0, len(vocab)))] + b" \n"[int(rng.integers(0, 2)):][:1]
+        out += part
+    return np.frombuffer(bytes(out), np.uint8).copy()
+
+
+def test_uneven_parts_alone_and_in_a_batch(torch):
+    from paper_1309_0215_amd import Job
+    bufs = [_uneven_parts(80 + i, n) for i, n in enumerate((3, 17, 40))]
+    job = Job(device=0)
+    for b in bufs:
+        _check(job.words(_dev(torch, b)), b)
+    res = job.words_batch([_dev(torch, b) for b in bufs])
+    for r, b in zip(res, bufs):
+        _check(r, b)
