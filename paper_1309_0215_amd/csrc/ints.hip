@@ -247,19 +247,32 @@ MR_DEV void for_tile_keys(const IntIn& in, uint64_t base, F&& f) {
   }
 }
 
+// Each workgroup counts kPartCountTiles consecutive tiles, one LDS row of
+// range counters per tile, so that the counts of one range over those tiles
+// are stored as one contiguous run (range-major order, as the scan wants):
+// one store per tile and range had cost about ten times the counts' bytes
+// in partial-line writes.
+constexpr uint32_t kPartCountTiles = 8;
+
 __global__ __launch_bounds__(kPartThreads) void k_part_count(IntIn in, uint64_t R, uint32_t P, uint32_t n_tiles,
                                                              uint32_t* __restrict__ hist /* [P][n_tiles] */,
                                                              uint32_t* __restrict__ flags) {
-  __shared__ uint32_t h[kMaxParts];
-  for (uint32_t p = threadIdx.x; p < P; p += blockDim.x) h[p] = 0;
+  __shared__ uint32_t h[kPartCountTiles][kMaxParts];
+  const uint32_t t0 = blockIdx.x * kPartCountTiles;
+  const uint32_t nt = n_tiles - t0 < kPartCountTiles ? n_tiles - t0 : kPartCountTiles;
+  for (uint32_t i = threadIdx.x; i < nt * P; i += blockDim.x) h[i / P][i % P] = 0;
   __syncthreads();
   bool bad = false;
-  for_tile_keys(in, (uint64_t)blockIdx.x * kPartTile, [&](uint32_t k) {
-    if (k < R) atomicAdd(&h[k >> kPartBits], 1u);
-    else bad = true;
-  });
+  for (uint32_t j = 0; j < nt; ++j)
+    for_tile_keys(in, (uint64_t)(t0 + j) * kPartTile, [&](uint32_t k) {
+      if (k < R) atomicAdd(&h[j][k >> kPartBits], 1u);
+      else bad = true;
+    });
   __syncthreads();
-  for (uint32_t p = threadIdx.x; p < P; p += blockDim.x) hist[(uint64_t)p * n_tiles + blockIdx.x] = h[p];
+  for (uint32_t i = threadIdx.x; i < P * nt; i += blockDim.x) {
+    const uint32_t p = i / nt, j = i % nt;
+    hist[(uint64_t)p * n_tiles + t0 + j] = h[j][p];
+  }
   if (bad) atomicOr(flags, kFlagBadInput);
 }
 
@@ -959,7 +972,8 @@ PartPlan part_plan(uint64_t n, uint64_t R) {
 hipError_t int_enqueue_global_array_parts(const IntLaunch& L, const PartPlan& pp, uint32_t* hist, uint32_t* scan_sums,
                                           unsigned long long* total, uint16_t* part, hipStream_t s) {
   const IntIn in{L.in, L.n, L.kv};
-  hipLaunchKernelGGL(k_part_count, dim3(pp.n_tiles), dim3(kPartThreads), 0, s, in, L.R, pp.P, pp.n_tiles, hist, L.flags);
+  hipLaunchKernelGGL(k_part_count, dim3((pp.n_tiles + kPartCountTiles - 1) / kPartCountTiles), dim3(kPartThreads), 0, s, in,
+                     L.R, pp.P, pp.n_tiles, hist, L.flags);
   hipLaunchKernelGGL(k_scan_blocks, dim3(pp.sb), dim3(256), 0, s, hist, pp.H, scan_sums);
   hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, s, scan_sums, pp.sb, total);
   hipLaunchKernelGGL(k_scan_apply, dim3(pp.sb), dim3(256), 0, s, hist, pp.H, scan_sums);
