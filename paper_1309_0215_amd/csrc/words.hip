@@ -967,7 +967,10 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_splitters(const WordJob* 
   }
   if (nb <= 1) return;
   const uint64_t n = J.st->n_recs;
-  const uint32_t S = nb * kOversample;
+  // twice the oversampling while the sample fits the array: the largest
+  // bucket, which sets the bucket sort's time, stays closer to the mean
+  const uint32_t ov = nb * 2 * kOversample <= kMaxBuckets * kOversample ? 2 * kOversample : kOversample;
+  const uint32_t S = nb * ov;
   const WRec* recs = reinterpret_cast<const WRec*>(J.recs);
   for (uint32_t i = threadIdx.x; i < S; i += blockDim.x) {
     const uint32_t ix = (uint32_t)((uint64_t)i * n / S);
@@ -977,7 +980,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_splitters(const WordJob* 
   if (S <= blockDim.x) reg_bitonic(J, recs, smp, S);
   else soa_bitonic(J, recs, smp, S);
   WRec* spl = reinterpret_cast<WRec*>(J.splitters);
-  for (uint32_t b = threadIdx.x; b + 1 < nb; b += blockDim.x) spl[b] = recs[smp.ix[(b + 1) * kOversample - 1]];
+  for (uint32_t b = threadIdx.x; b + 1 < nb; b += blockDim.x) spl[b] = recs[smp.ix[(b + 1) * ov - 1]];
 }
 
 // Bucket of each record: number of splitters strictly below it.
