@@ -581,15 +581,28 @@ __global__ __launch_bounds__(kMapThreads) void k_words_map(const WordJob* __rest
       }
       wave_sync();
       const uint32_t nr = (total - base) < kListCap ? (total - base) : kListCap;
-      for (uint32_t i = lane; i < nr; i += kWave) {
-        const uint32_t d = wlist[wave][i];
-        const uint32_t o = d >> 5, len = d & 31u;
+      // the word at list entry d: key bytes from the wave's copy of the part
+      auto word_at = [&](uint32_t d, uint4& k, uint32_t& len, uint64_t& h, uint64_t& off) {
+        const uint32_t o = d >> 5;
+        len = d & 31u;
         const uint4 x0 = ws[o >> 4], x1 = ws[(o >> 4) + 1];
         const uint32_t w[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
-        const uint4 k = extract16(w, o & 15u, len);
-        const uint64_t h = key_hash16(k, len, debug_hash);
+        k = extract16(w, o & 15u, len);
+        h = key_hash16(k, len, debug_hash);
+        off = part_addr + o - a0;
+      };
+      // LDS inserts; the words the cache cannot take are marked (bit u: entry lane + 64 u)
+      constexpr uint32_t kPerLane = kListCap / kWave;
+      uint32_t missed = 0u;
+#pragma unroll
+      for (uint32_t u = 0; u < kPerLane; ++u) {
+        const uint32_t i = lane + u * kWave;
+        if (i >= nr) break;
+        uint4 k;
+        uint32_t len;
+        uint64_t h, off;
+        word_at(wlist[wave][i], k, len, h, off);
         const uint32_t tg = lds_tag(h, len);
-        const uint64_t off = part_addr + o - a0;
         int r = 1;
         for (uint32_t spin = 0; r == 1; ++spin) {
           r = lds_insert<L>(T, &s_used, kLimit, tg, (uint32_t)h, k, (uint32_t)off);
@@ -598,7 +611,34 @@ __global__ __launch_bounds__(kMapThreads) void k_words_map(const WordJob* __rest
             r = 0;
           }
         }
-        if (r == 2) g_insert<true>(J, vlo, vhi, off, len, h, k, 1u, debug_hash);
+        if (r == 2) missed |= 1u << u;
+      }
+      // The misses of the whole round are packed to the front of the list and
+      // inserted globally one per lane: the wave then waits on one round of
+      // dependent global probes instead of one per list pass.
+      uint32_t md[kPerLane];
+#pragma unroll
+      for (uint32_t u = 0; u < kPerLane; ++u) md[u] = (missed >> u & 1u) ? wlist[wave][lane + u * kWave] : 0u;
+      const uint32_t n_m = __builtin_popcount(missed);
+      uint32_t incl_m = n_m;
+#pragma unroll
+      for (int o = 1; o < kWave; o <<= 1) {
+        const uint32_t y = (uint32_t)__shfl_up((int)incl_m, o);
+        if (lane >= (uint32_t)o) incl_m += y;
+      }
+      const uint32_t total_m = (uint32_t)__shfl((int)incl_m, kWave - 1);
+      wave_sync();  // every lane has read its entries
+      uint32_t at = incl_m - n_m;
+#pragma unroll
+      for (uint32_t u = 0; u < kPerLane; ++u)
+        if (missed >> u & 1u) wlist[wave][at++] = md[u];
+      wave_sync();
+      for (uint32_t i = lane; i < total_m; i += kWave) {
+        uint4 k;
+        uint32_t len;
+        uint64_t h, off;
+        word_at(wlist[wave][i], k, len, h, off);
+        g_insert<true>(J, vlo, vhi, off, len, h, k, 1u, debug_hash);
       }
       wave_sync();
     }
