@@ -245,3 +245,121 @@ def test_regret_arithmetic():
     feas = np.array([[True, True, True, True], [True, False, True, True]])
     r = oracle.regret(t, feas, np.array([1, 2]))
     assert np.allclose(r, [1.0, 0.0])
+
+
+# ----------------------------------------------------------------------------
+# selector network pinned to an independent implementation (torch, float64)
+# ----------------------------------------------------------------------------
+
+def _torch_mlp(theta):
+    """The same 12-64-64-4 ReLU network built from torch.nn layers, float64."""
+    import torch
+    p = oracle.mlp_unpack(theta)
+    net = torch.nn.Sequential(torch.nn.Linear(12, 64), torch.nn.ReLU(), torch.nn.Linear(64, 64), torch.nn.ReLU(),
+                              torch.nn.Linear(64, 4)).double()
+    with torch.no_grad():
+        for layer, (w, b) in zip((net[0], net[2], net[4]), (("W1", "b1"), ("W2", "b2"), ("W3", "b3"))):
+            layer.weight.copy_(torch.from_numpy(p[w]))
+            layer.bias.copy_(torch.from_numpy(p[b]))
+    return net
+
+
+def test_mlp_forward_matches_torch_layers():
+    # Biases are shifted so that about half the hidden pre-activations are
+    # negative: a missing, extra or misplaced ReLU changes the output.
+    import torch
+    rng = np.random.default_rng(11)
+    theta = rng.standard_normal(oracle.MLP_NPARAM) * 0.4
+    X = rng.standard_normal((33, 12))
+    y, (_, z1, _, z2, _) = oracle.mlp_forward(theta, X)
+    assert 0.2 < (z1 < 0).mean() < 0.8 and 0.2 < (z2 < 0).mean() < 0.8
+    ref = _torch_mlp(theta)(torch.from_numpy(X)).detach().numpy()
+    assert np.allclose(y, ref, rtol=1e-12, atol=1e-12)
+
+
+def test_mlp_forward_hand_worked():
+    # One input, weights chosen so that ReLU zeroes a hidden unit in each layer:
+    # z1 = [1*2 - 1, -3*2 + 1] = [1, -5] -> h1 = [1, 0]
+    # z2 = [2*1 + 0.5, -1*1 - 0.25] = [2.5, -1.25] -> h2 = [2.5, 0]
+    # y0 = 4 * 2.5 + 0.1 = 10.1, y3 = -1 * 2.5 + 7 = 4.5
+    p = {n: np.zeros(s) for n, s in oracle.MLP_SHAPES}
+    p["W1"][0, 0], p["b1"][0] = 1.0, -1.0
+    p["W1"][1, 0], p["b1"][1] = -3.0, 1.0
+    p["W2"][0, 0], p["b2"][0] = 2.0, 0.5
+    p["W2"][1, 0], p["b2"][1] = -1.0, -0.25
+    p["W3"][0, 0], p["b3"][0] = 4.0, 0.1
+    p["W3"][3, 0], p["b3"][3] = -1.0, 7.0
+    p["W3"][1, 1] = 100.0  # reads h2[1], which ReLU zeroes
+    p["W2"][0, 1] = 100.0  # reads h1[1], which ReLU zeroes
+    theta = np.concatenate([p[n].ravel() for n, _ in oracle.MLP_SHAPES])
+    x = np.zeros((1, 12))
+    x[0, 0] = 2.0
+    y, _ = oracle.mlp_forward(theta, x)
+    assert np.allclose(y[0], [10.1, 0.0, 0.0, 4.5], rtol=0, atol=1e-12)
+
+
+def test_mlp_loss_hand_worked_masked_mean():
+    # y = b3 = [1, 2, 3, 4] for both rows (zero weights).
+    # Row 0 targets [0, 2, 5, 4], mask [1, 1, 1, 0]: errors 1, 0, 4 (the masked 100 is ignored).
+    # Row 1 targets [1, 0, 3, 4], mask [0, 1, 0, 0]: error 4.
+    # Loss = (1 + 0 + 4 + 4) / 4 = 2.25.
+    theta = np.zeros(oracle.MLP_NPARAM)
+    theta[-4:] = [1.0, 2.0, 3.0, 4.0]
+    X = np.ones((2, 12))
+    T = np.array([[0.0, 2.0, 5.0, 104.0], [1.0, 0.0, 3.0, 4.0]])
+    M = np.array([[1.0, 1.0, 1.0, 0.0], [0.0, 1.0, 0.0, 0.0]])
+    assert oracle.mlp_loss(theta, X, T, M) == 2.25
+    loss, g = oracle.mlp_grad(theta, X, T, M)
+    assert loss == 2.25
+    # dL/db3 = sum_b 2 m (y - t) / sum m = [2*1/4, 2*(0 + 2)/4, 2*(-2)/4, 0] = [0.5, 1.0, -1.0, 0]
+    assert np.allclose(g[-4:], [0.5, 1.0, -1.0, 0.0], rtol=0, atol=1e-15)
+
+
+def test_mlp_gradient_matches_torch_autograd():
+    import torch
+    rng = np.random.default_rng(12)
+    theta = rng.standard_normal(oracle.MLP_NPARAM) * 0.4
+    X = rng.standard_normal((17, 12))
+    T = rng.standard_normal((17, 4))
+    M = (rng.random((17, 4)) < 0.6).astype(np.float64)
+    loss, g = oracle.mlp_grad(theta, X, T, M)
+    net = _torch_mlp(theta)
+    y = net(torch.from_numpy(X))
+    Mt = torch.from_numpy(M)
+    tl = (Mt * (y - torch.from_numpy(T)) ** 2).sum() / Mt.sum()
+    tl.backward()
+    tg = np.concatenate([net[0].weight.grad.numpy().ravel(), net[0].bias.grad.numpy(), net[2].weight.grad.numpy().ravel(),
+                         net[2].bias.grad.numpy(), net[4].weight.grad.numpy().ravel(), net[4].bias.grad.numpy()])
+    assert abs(loss - float(tl.detach())) < 1e-12
+    assert np.allclose(g, tg, rtol=1e-10, atol=1e-12)
+
+
+def test_adam_matches_torch_optim_over_ten_steps():
+    # torch.optim.Adam (bias-corrected, eps added to the corrected root) over
+    # steps t = 1..10 with changing gradients: a wrong bias-correction exponent
+    # or moment update diverges after the first step.
+    import torch
+    rng = np.random.default_rng(13)
+    th = rng.standard_normal(50)
+    m = np.zeros(50)
+    v = np.zeros(50)
+    p = torch.nn.Parameter(torch.from_numpy(th.copy()))
+    opt = torch.optim.Adam([p], lr=3e-2, betas=(0.8, 0.95), eps=1e-6)
+    for t in range(1, 11):
+        g = rng.standard_normal(50) * (1 + t)
+        th, m, v = oracle.adam_step(th, g, m, v, t, lr=3e-2, b1=0.8, b2=0.95, eps=1e-6)
+        opt.zero_grad()
+        p.grad = torch.from_numpy(g.copy())
+        opt.step()
+        assert np.allclose(th, p.detach().numpy(), rtol=1e-12, atol=1e-14), t
+
+
+def test_kmeans_abs_sums_hand_worked():
+    # Points (1, -2), (-3, 4), (5, 0.5) in clusters 1, 1, 0 of three:
+    # cluster 0: |5| + ... = (5, 0.5); cluster 1: (1 + 3, 2 + 4) = (4, 6); cluster 2: empty.
+    X = np.array([[1.0, -2.0], [-3.0, 4.0], [5.0, 0.5]], np.float32)
+    A = oracle.kmeans_abs_sums(X, np.array([1, 1, 0]), 3)
+    assert np.array_equal(A, np.array([[5.0, 0.5], [4.0, 6.0], [0.0, 0.0]]))
+    # and it bounds |S| with equality when all signs agree within a cluster
+    S, _, _ = oracle.kmeans_update(X, np.array([1, 1, 0]), np.zeros((3, 2), np.float32))
+    assert np.all(np.abs(S) <= A) and S[0, 0] == A[0, 0]
