@@ -45,7 +45,8 @@ def test_2p22_elements_every_key(torch, strategy):
     assert np.array_equal(res.values.cpu().numpy().view(np.uint32).astype(np.uint64), ev)
 
 
-def test_full_2p28_elements_sampled():
+def test_full_2p28_elements():
+    """Every one of the 2^24 bins against np.bincount of the 2^28 keys."""
     import torch
     n = 1 << 28
     keys = gen.uniform_keys(22, n, R)
@@ -53,20 +54,11 @@ def test_full_2p28_elements_sampled():
     assert res.stats["strategy_used"] == GLOBAL_ARRAY
     gk = res.keys.cpu().numpy().view(np.uint32)
     gv = res.values.cpu().numpy().view(np.uint32).astype(np.uint64)
+    counts = np.bincount(keys, minlength=R).astype(np.uint64)
+    ek = np.flatnonzero(counts).astype(np.uint32)
+    assert np.array_equal(gk, ek)
+    assert np.array_equal(gv, counts[ek])
     assert int(gv.sum()) == n
-    assert np.all(gk[1:] > gk[:-1]) and int(gk[-1]) < R and np.all(gv > 0)
-    # the oracle on the elements whose key is one of 4096 sampled keys
-    sample = np.random.default_rng(23).choice(R, size=4096, replace=False).astype(np.uint32)
-    member = np.zeros(R, bool)
-    member[sample] = True
-    ek, ev = oracle.u32(keys[member[keys]])
-    pos = np.searchsorted(gk, ek)
-    assert np.all(pos < len(gk)) and np.array_equal(gk[pos], ek)
-    assert np.array_equal(gv[pos], ev)
-    # sampled keys the oracle did not see do not appear in the output either
-    absent = np.setdiff1d(sample, ek)
-    p2 = np.searchsorted(gk, absent)
-    assert not np.any((p2 < len(gk)) & (gk[np.minimum(p2, len(gk) - 1)] == absent))
 
 
 def test_key_outside_the_range_is_rejected(torch):

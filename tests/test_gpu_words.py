@@ -179,6 +179,29 @@ def test_full_config_8mib(torch, job):
     assert int(v.sum()) == len(buf.tobytes().split())
 
 
+def test_full_512mib_against_oracle(torch):
+    """The 512 MiB text the benchmark times (same generator, the paper's scale),
+    launched as the benchmark launches it: fixed output buffers, so the repeat
+    replays the captured graph. Every key of both runs against the oracle."""
+    from paper_1309_0215_amd import Job, _lib as L
+    buf = gen.text(1, 512 << 20)
+    d = _dev(torch, buf)
+    exp = oracle.words(buf)
+    job = Job(device=0)
+    o, (kb, ko, vals) = job._word_out(len(exp) + 16, len(exp.key_bytes) + 64)
+    for rep in range(3):
+        L.check(job.words_raw(d, o), "words")
+        torch.cuda.synchronize()
+        nk = int(o.n_keys)
+        assert nk == len(exp), rep
+        assert np.array_equal(ko[:nk + 1].cpu().numpy().astype(np.uint64), exp.key_offsets), rep
+        assert np.array_equal(kb[:int(o.key_bytes_used)].cpu().numpy(), exp.key_bytes), rep
+        assert np.array_equal(vals[:nk].cpu().numpy().astype(np.uint32).astype(np.uint64), exp.values), rep
+        kb.fill_(0)
+        vals.fill_(0)
+    del d
+
+
 def test_workspace_reuse_across_sizes_and_kinds(torch):
     # One job alternating small and large inputs and the histogram, which
     # reuses the same workspace: every run must see a clean hash table.
