@@ -214,6 +214,22 @@ mr_status mr_job_destroy(mr_job* job);
 mr_status mr_run(mr_job* job, mr_map_kind kind, mr_reduce_op op, const void* d_input, uint64_t input_bytes,
                  const uint64_t* d_record_offsets, uint64_t n_records, uint64_t key_range, mr_output* out);
 
+/* RGB histogram (MR_MAP_RGB_HIST with MR_REDUCE_COUNT) for callers that
+ * cannot allocate device memory: code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation. Same result as mr_run: d_bins
+ * (device, uint64[768], channel-major) receives the 768 bins, overwritten.
+ * It allocates nothing, sets no memory with memset calls and does not
+ * synchronise: the two kernels are enqueued on the job's stream and the bins
+ * are ready when that stream reaches this point.
+ * Scratch: the per-workgroup partial rows go to a library-owned static device
+ * array of 1024 x 768 uint32 (3 MiB), one per GPU, kept until the process
+ * ends. Every call on a GPU shares that GPU's array: calls that overlap on one
+ * GPU (other streams, other jobs, other host threads) race and give wrong
+ * bins; serialise them. Errors: MR_ERR_INVALID_ARG (NULL pointers, length not
+ * a multiple of 3), MR_ERR_UNSUPPORTED (inputs of 2^41 bytes or more, which
+ * the 1024 rows of 32-bit counters cannot hold), MR_ERR_HIP. */
+mr_status mr_rgb_hist_static(mr_job* job, const void* d_input, uint64_t input_bytes, uint64_t* d_bins);
+
 /* One item of a batch (device pointers as in mr_run). */
 typedef struct {
   mr_map_kind kind;

@@ -244,6 +244,17 @@ class Job:
                                 C.byref(o)), "mr_run(rgb)")
         return out.view(3, 256), _stats(o)
 
+    def rgb_hist_static(self, data, out):
+        """mr_rgb_hist_static: the histogram into `out` (contiguous int64 CUDA
+        tensor of 768) with the library's static scratch; enqueued on the job's
+        stream, no allocation and no synchronisation."""
+        torch = self.torch
+        if out.dtype != torch.int64 or out.numel() != 768 or not out.is_contiguous():
+            raise ValueError("out must be a contiguous int64 tensor of 768 elements")
+        L.check(self.lib.mr_rgb_hist_static(self.h, _ptr(data), int(data.numel()), out.data_ptr()),
+                "mr_rgb_hist_static")
+        return out.view(3, 256)
+
     # ------------------------------------------------------------- u32 keys
     def u32(self, keys, values=None, op: int = L.REDUCE_COUNT, key_range: int = 0, cap_keys: int | None = None):
         """keys: int32 CUDA tensor (uint32 bit pattern); values likewise or None.

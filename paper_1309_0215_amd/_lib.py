@@ -26,7 +26,7 @@ MLP_PARAMS = 5252
 EXPORTS = [
     "mr_status_str", "mr_last_error", "mr_job_create", "mr_job_destroy", "mr_run", "mr_batch_run",
     "mr_job_features", "mr_selector_set", "mr_selector_predict", "mr_mlp_forward", "mr_mlp_loss_backward",
-    "mr_mlp_adam", "mr_tune_set",
+    "mr_mlp_adam", "mr_tune_set", "mr_rgb_hist_static",
 ]
 
 
@@ -137,6 +137,8 @@ def load(required: bool = True):
     lib.mr_batch_run.argtypes = [P, C.POINTER(BatchItem), U32, C.POINTER(Output)]
     lib.mr_tune_set.restype = I32
     lib.mr_tune_set.argtypes = [P, C.POINTER(TuneEntry), U32]
+    lib.mr_rgb_hist_static.restype = I32
+    lib.mr_rgb_hist_static.argtypes = [P, P, U64, P]
     if hasattr(lib, "mr_job_features"):
         lib.mr_job_features.restype = I32
         lib.mr_job_features.argtypes = [P, C.c_int, C.c_int, P, U64, U64, P]

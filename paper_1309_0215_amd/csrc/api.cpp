@@ -242,6 +242,11 @@ extern "C" mr_status mr_job_create(const mr_job_config* cfg, mr_job** out) {
     delete job;
     return fail(MR_ERR_HIP, "hipEventCreate failed");
   }
+  // the allocation-free histogram's static scratch: its address on this device, looked up once
+  if (rgb_static_init(job->device) != hipSuccess) {
+    mr_job_destroy(job);
+    return fail(MR_ERR_HIP, "looking up the static histogram scratch on device %d failed", cfg->device);
+  }
   if (cfg->km_k) {
     if (!cfg->km_centroids || cfg->km_d == 0 || cfg->km_d > 256 || cfg->km_k > 1024) {
       mr_job_destroy(job);
@@ -1315,6 +1320,22 @@ extern "C" mr_status mr_run(mr_job* job, mr_map_kind kind, mr_reduce_op op, cons
   }
   out->status = s;
   return s;
+}
+
+extern "C" mr_status mr_rgb_hist_static(mr_job* job, const void* d_input, uint64_t input_bytes, uint64_t* d_bins) {
+  if (!job || !d_bins || (input_bytes && !d_input)) return fail(MR_ERR_INVALID_ARG, "NULL argument");
+  if (input_bytes % 3)
+    return fail(MR_ERR_INVALID_ARG, "RGB input length %llu is not a multiple of 3", (unsigned long long)input_bytes);
+  const uint32_t G = rgb_static_rows(input_bytes, job->n_cu);
+  // each partial row counts fewer than 2^31 bytes in 32-bit counters
+  if (input_bytes / G >= (1ull << 31))
+    return fail(MR_ERR_UNSUPPORTED, "input of %llu bytes exceeds the static scratch (%u rows of 2^31 bytes)",
+                (unsigned long long)input_bytes, kRgbStaticRows);
+  ScopedDevice sd(job->device);
+  const hipError_t e = rgb_static_enqueue(job->device, static_cast<const uint8_t*>(d_input), input_bytes, G,
+                                          reinterpret_cast<unsigned long long*>(d_bins), job->stream);
+  if (e != hipSuccess) return fail(MR_ERR_HIP, "mr_rgb_hist_static: %s", hipGetErrorString(e));
+  return MR_OK;
 }
 
 extern "C" mr_status mr_tune_set(mr_job* job, const mr_tune_entry* entries, uint32_t n) {

@@ -173,6 +173,46 @@ hipError_t rgb_enqueue(const uint8_t* in, uint64_t n, uint32_t* partials, uint32
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Allocation-free variant: the partial rows live in a file-scope device array
+// (one copy per GPU, held until the process ends) instead of a workspace.
+// Host code never passes the array's name to a kernel (on the host it only
+// stands in for the symbol): its device address is looked up once per device
+// with hipGetSymbolAddress and used from then on.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) uint32_t scratch[kRgbStaticRows * kHistBins];
+
+namespace {
+constexpr int kMaxDevices = 64;
+void* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t rgb_static_init(int device) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  if (g_scratch_ptr[device]) return hipSuccess;
+  int prev = -1;
+  hipError_t e = hipGetDevice(&prev);
+  if (e != hipSuccess) return e;
+  if (prev != device && (e = hipSetDevice(device)) != hipSuccess) return e;
+  void* ptr = nullptr;
+  e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e == hipSuccess) g_scratch_ptr[device] = ptr;
+  if (prev != device) (void)hipSetDevice(prev);
+  return e;
+}
+
+uint32_t rgb_static_rows(uint64_t n, int n_cu) {
+  const uint32_t g = rgb_grid(n, n_cu);
+  return g < kRgbStaticRows ? g : kRgbStaticRows;
+}
+
+hipError_t rgb_static_enqueue(int device, const uint8_t* in, uint64_t n, uint32_t G, unsigned long long* out,
+                              hipStream_t s) {
+  if (device < 0 || device >= kMaxDevices || !g_scratch_ptr[device]) return hipErrorNotInitialized;
+  if (G == 0 || G > kRgbStaticRows) return hipErrorInvalidValue;
+  return rgb_enqueue(in, n, static_cast<uint32_t*>(g_scratch_ptr[device]), G, out, s, nullptr, nullptr);
+}
+
 // The same sequence as a graph built node by node: event records around
 // the whole sequence (all0, all1) and around k_rgb_partial (map0, map1, may
 // be null). Built explicitly rather than by stream capture, since event

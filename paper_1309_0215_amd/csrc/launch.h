@@ -66,6 +66,15 @@ uint64_t links_hist_words(uint64_t n);
 hipError_t radix_sort64(unsigned long long* k0, unsigned long long* v0, unsigned long long* k1, unsigned long long* v1,
                         uint64_t n, int bits, uint32_t* hist, uint32_t* scan_sums, bool* result_in_1, hipStream_t s);
 
+// Allocation-free histogram: partial rows in a static device array of
+// kRgbStaticRows rows (3 MiB per GPU). rgb_static_init looks up its address
+// on a device (once); rgb_static_rows is the row count for an input (at most
+// kRgbStaticRows); rgb_static_enqueue launches the two kernels on it.
+constexpr uint32_t kRgbStaticRows = 1024;
+hipError_t rgb_static_init(int device);
+uint32_t rgb_static_rows(uint64_t n, int n_cu);
+hipError_t rgb_static_enqueue(int device, const uint8_t* in, uint64_t n, uint32_t G, unsigned long long* out,
+                              hipStream_t s);
 uint32_t rgb_grid(uint64_t n, int n_cu);
 // map0 / map1 (optional) are recorded around k_rgb_partial.
 hipError_t rgb_enqueue(const uint8_t* in, uint64_t n, uint32_t* partials, uint32_t G, unsigned long long* out,
