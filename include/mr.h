@@ -132,6 +132,12 @@ typedef struct {
   /* Bloom filter only: k-mer length (1..32, 0 = 20) and hash count (1..8, 0 = 7) */
   uint32_t bloom_k;
   uint32_t bloom_hashes;
+  /* Word count: 1 = each wave merges equal words among the 64 it holds
+   * (four leader rounds) before the LDS cache insert, so repeated words take
+   * one atomic (Section II-A combiner at wave level); 0 = off (default:
+   * measured slower on the Zipf text, see the design notes). Outputs do not
+   * depend on it. */
+  uint32_t wave_combine;
 } mr_job_config;
 
 typedef struct {

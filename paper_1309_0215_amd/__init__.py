@@ -105,7 +105,7 @@ class Job:
 
     def __init__(self, device: int = 0, strategy: int = L.STRAT_RULE, lds_slots: int = 0, max_load_pct: int = 0,
                  debug_hash: int = 0, table_slots: int = 0, km_centroids=None, stream=None, timing: int = 0,
-                 bloom_k: int = 0, bloom_hashes: int = 0):
+                 bloom_k: int = 0, bloom_hashes: int = 0, wave_combine: int = 0):
         import torch
         self.torch = torch
         self.lib = load()
@@ -121,6 +121,7 @@ class Job:
         cfg.timing = timing
         cfg.bloom_k = bloom_k
         cfg.bloom_hashes = bloom_hashes
+        cfg.wave_combine = wave_combine
         self._km = None
         if km_centroids is not None:
             c = km_centroids.to(device=f"cuda:{device}", dtype=torch.float32).contiguous()

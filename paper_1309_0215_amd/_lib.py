@@ -46,6 +46,7 @@ class JobConfig(C.Structure):
         ("km_centroids", C.c_void_p),
         ("bloom_k", C.c_uint32),
         ("bloom_hashes", C.c_uint32),
+        ("wave_combine", C.c_uint32),
     ]
 
 

@@ -336,6 +336,8 @@ struct WordsPlan {
   uint64_t o_jobs, o_tile_base, o_states, o_totals, o_bucket_cnt, o_bucket_bytes, o_bucket_start, o_bucket_bstart,
       o_bucket_fill, o_tw, o_tc, o_recs, o_recs2, o_rbucket, o_spl, o_slot_rank = 0, o_queue = 0, o_qcnt = 0;
   uint32_t qcap = 0;  // records per flush queue (0: no two-phase flush)
+  uint64_t o_mq = 0, o_mqfill = 0;
+  uint32_t mq_cap = 0, grid = 1;  // miss sub-queue records; map workgroups
   uint64_t total_slots = 0, total_tiles = 0;
   std::vector<uint64_t> slot_base, tile_base;
 };
@@ -349,7 +351,17 @@ uint32_t flush_queue_cap(uint64_t n, int n_cu) {
   return (uint32_t)(recs * 3 / 2 / kFlushParts + 256);
 }
 
-WordsPlan plan_words(const std::vector<WordItem>& items, bool slot_ranks, uint32_t qcap) {
+// Records per miss sub-queue (one per map workgroup and partition) of a
+// single job: room for half the words of an input of mean word length 8
+// missing the LDS caches, spread evenly, so that a sub-queue rarely fills on
+// text whose cache misses stay below that; a full sub-queue sends its
+// overflow to the global table directly.
+uint32_t miss_queue_cap(uint64_t n, uint32_t grid) {
+  const uint64_t want = n / (16ull * grid * kFlushParts) + 1;
+  return (uint32_t)std::min<uint64_t>(4096, std::max<uint64_t>(16, next_pow2(want)));
+}
+
+WordsPlan plan_words(const std::vector<WordItem>& items, bool slot_ranks, uint32_t qcap, uint64_t grid_cap) {
   WordsPlan p;
   const uint32_t n = (uint32_t)items.size();
   p.slot_base.resize(n);
@@ -363,6 +375,7 @@ WordsPlan plan_words(const std::vector<WordItem>& items, bool slot_ranks, uint32
     p.total_tiles += (n_chunks + kMapTileChunks - 1) / kMapTileChunks;
   }
   p.tile_base[n] = p.total_tiles;
+  p.grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(p.total_tiles, grid_cap));
   // the table arena comes first so that its clean prefix survives layout changes
   p.o_tw = p.c.take(p.total_slots * 8);
   p.o_tc = p.c.take(p.total_slots * 4);
@@ -384,6 +397,9 @@ WordsPlan plan_words(const std::vector<WordItem>& items, bool slot_ranks, uint32
     p.qcap = qcap;
     p.o_queue = p.c.take(32ull * kFlushParts * qcap);
     p.o_qcnt = p.c.take(4ull * kFlushParts);
+    p.mq_cap = miss_queue_cap(items[0].n, p.grid);
+    p.o_mq = p.c.take(32ull * kFlushParts * p.grid * p.mq_cap);
+    p.o_mqfill = p.c.take(4ull * kFlushParts * p.grid);
   }
   return p;
 }
@@ -421,7 +437,6 @@ mr_status words_pass(mr_job* job, std::vector<WordItem>& items, std::vector<JobS
   const uint32_t n = (uint32_t)items.size();
   // single word jobs flush their LDS caches in two phases through partition queues
   const uint32_t qcap = (n == 1 && !lb) ? flush_queue_cap(items[0].n, job->n_cu) : 0u;
-  WordsPlan p = plan_words(items, lb != nullptr, qcap);
   // tuned map parameters, looked up by the bytes this launch covers (a
   // batch by its total; each job's table load factor by its own size)
   uint64_t size_key = 0;
@@ -432,6 +447,7 @@ mr_status words_pass(mr_job* job, std::vector<WordItem>& items, std::vector<JobS
   if (lds_log2 != 8 && lds_log2 != 10 && lds_log2 != 11 && lds_log2 != 12)
     return fail(MR_ERR_INVALID_ARG, "lds_slots must be 256, 1024, 2048 or 4096");
   const uint64_t grid_cap = std::max<uint64_t>(1, (uint64_t)job->n_cu * eff_grid_pct(job, size_key) / 100);
+  WordsPlan p = plan_words(items, lb != nullptr, qcap, grid_cap);
   mr_status st = ensure_ws(job, p.c.off);
   if (st != MR_OK) return st;
   uint8_t* ws = job->ws;
@@ -442,6 +458,7 @@ mr_status words_pass(mr_job* job, std::vector<WordItem>& items, std::vector<JobS
   key = fnv_mix(key, (uint64_t)lds_log2);
   key = fnv_mix(key, grid_cap);
   key = fnv_mix(key, job->cfg.debug_hash);
+  key = fnv_mix(key, job->cfg.wave_combine);
   key = fnv_mix(key, lb ? (uint64_t)lb->marks ^ lb->cap : 0ull);
   for (const WordItem& it : items) {
     key = fnv_mix(key, (uint64_t)it.in);
@@ -526,6 +543,10 @@ mr_status words_pass(mr_job* job, std::vector<WordItem>& items, std::vector<JobS
     J.queue = p.qcap ? ws + p.o_queue : nullptr;
     J.qcnt = p.qcap ? reinterpret_cast<uint32_t*>(ws + p.o_qcnt) : nullptr;
     J.qcap = p.qcap;
+    J.mq_cap = p.mq_cap;
+    J.mq_grid = p.grid;
+    J.mq = p.qcap ? ws + p.o_mq : nullptr;
+    J.mq_fill = p.qcap ? reinterpret_cast<uint32_t*>(ws + p.o_mqfill) : nullptr;
     any_rec |= it.rec != nullptr;
   }
   MR_HIP(hipMemcpyAsync(ws + p.o_jobs, hj.data(), sizeof(WordJob) * n, hipMemcpyHostToDevice, s));
@@ -537,13 +558,13 @@ mr_status words_pass(mr_job* job, std::vector<WordItem>& items, std::vector<JobS
   L.n_jobs = n;
   L.total_tiles = p.total_tiles;
   L.total_slots = p.total_slots;
-  const uint64_t want_grid = std::max<uint64_t>(1, std::min<uint64_t>(p.total_tiles, grid_cap));
-  L.map_grid = (uint32_t)want_grid;
+  L.map_grid = p.grid;
   L.sort_grid = (uint32_t)std::max(1, job->n_cu * 2);
   L.lds_log2 = lds_log2;
   L.flush_parts = p.qcap != 0;
   L.debug_hash = job->cfg.debug_hash;
   L.any_records = any_rec;
+  L.wave_combine = job->cfg.wave_combine != 0;
   L.totals = reinterpret_cast<uint32_t*>(ws + p.o_totals);
   L.bucket_cnt = reinterpret_cast<uint32_t*>(ws + p.o_bucket_cnt);
   L.bucket_bytes = reinterpret_cast<unsigned long long*>(ws + p.o_bucket_bytes);

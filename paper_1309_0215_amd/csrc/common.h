@@ -67,20 +67,33 @@ MR_DEV uint64_t hash_u32(uint32_t k) { return fmix64((uint64_t)k * 0x9E3779B97F4
 // ---------------------------------------------------------------------------
 MR_DEV bool is_sep_byte(uint32_t b) { return b == 0x20u || (b - 0x09u) < 5u; }
 
-// 4-bit mask (bit i = byte i of w is a separator), branch-free SWAR.
-MR_DEV uint32_t sep_mask4(uint32_t w) {
-  const uint32_t hi = w & 0x80808080u;        // bytes >= 0x80 are word bytes
+// Separator flags of a little-endian word: bit 7 of byte i is set when byte i
+// is a separator (branch-free SWAR; bytes >= 0x80 are word bytes, and the
+// 0x7F mask keeps the byte sums below from carrying into the next byte).
+MR_DEV uint32_t sep_flags4(uint32_t w) {
   const uint32_t t = w & 0x7F7F7F7Fu;
-  const uint32_t y = t ^ 0x20202020u;          // zero byte where t == 0x20
-  const uint32_t eq20 = ~(y + 0x7F7F7F7Fu);    // bit 7 set where y byte == 0
-  const uint32_t ge9 = t + 0x77777777u;        // bit 7 set where t >= 9
-  const uint32_t ge14 = t + 0x72727272u;       // bit 7 set where t >= 14
-  const uint32_t s = (eq20 | (ge9 & ~ge14)) & ~hi & 0x80808080u;
-  return ((s >> 7) * 0x00204081u) >> 21 & 0xFu;  // gather bits 7,15,23,31 into 0..3
+  const uint32_t not20 = (t ^ 0x20202020u) + 0x7F7F7F7Fu;  // bit 7: t != 0x20
+  const uint32_t ge9 = t + 0x77777777u;                    // bit 7: t >= 0x09
+  const uint32_t ge14 = t + 0x72727272u;                   // bit 7: t >= 0x0E
+  const uint32_t word = not20 & ~(ge9 & ~ge14);            // bit 7: neither 0x20 nor 0x09..0x0D
+  return ~(word | w) & 0x80808080u;
 }
 
+// Flags of two words (bytes 0..7) gathered into bits 0..7. The flag bits sit
+// at 0, 8, 16, 24 (first word) and 4, 12, 20, 28 (second); multiplying by
+// 1 + 2^7 + 2^14 + 2^21 puts byte i's flag at bit 21 + i, and no two partial
+// products share a bit, so nothing carries.
+MR_DEV uint32_t gather8(uint32_t f0, uint32_t f1) {
+  const uint32_t x = (f0 >> 7) | (f1 >> 3);
+  return (x * 0x00204081u) >> 21 & 0xFFu;
+}
+
+// 4-bit mask (bit i = byte i of w is a separator).
+MR_DEV uint32_t sep_mask4(uint32_t w) { return gather8(sep_flags4(w), 0u) & 0xFu; }
+
+// 16-bit mask of a 16-byte chunk (bit i = byte i is a separator).
 MR_DEV uint32_t sep_mask16(uint32_t a, uint32_t b, uint32_t c, uint32_t d) {
-  return sep_mask4(a) | (sep_mask4(b) << 4) | (sep_mask4(c) << 8) | (sep_mask4(d) << 12);
+  return gather8(sep_flags4(a), sep_flags4(b)) | (gather8(sep_flags4(c), sep_flags4(d)) << 8);
 }
 
 // bytes [0, n) of a little-endian word kept, the rest zeroed (n in 0..4)

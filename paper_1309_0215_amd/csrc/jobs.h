@@ -63,6 +63,16 @@ struct WordJob {
   void* queue;               // records [kFlushParts][qcap]
   uint32_t* qcnt;            // [kFlushParts] records claimed per queue
   uint32_t qcap;
+  // LDS-cache misses of the word map (single jobs), or NULL: map workgroup w
+  // appends the words its cache cannot take to its own sub-queue of
+  // partition p (records [kFlushParts][mq_grid][mq_cap], positions from LDS
+  // counters, no global atomics) and stores the sub-queue's fill in
+  // mq_fill[p * mq_grid + w]; the queue-summing workgroup of partition p then
+  // adds them with the flushed cache entries
+  uint32_t mq_cap;
+  uint32_t mq_grid;
+  void* mq;
+  uint32_t* mq_fill;
 };
 
 constexpr uint32_t kFlushParts = 256;  // queues: the top 8 bits of the key hash
@@ -81,6 +91,6 @@ constexpr uint32_t kMaxBuckets = 1024;     // sort buckets per job
 constexpr uint32_t kBucketCap = 2048;      // records a bucket sorts in LDS
 constexpr uint32_t kRecTile = 1024;        // records per sort work item
 constexpr uint32_t kMapThreads = 1024;     // word map workgroup size
-constexpr uint32_t kMapTileChunks = 1024;  // 16-byte chunks per map tile (16 KiB)
+constexpr uint32_t kMapTileChunks = 992;   // 16-byte chunks a map tile owns (16 waves x 62)
 
 }  // namespace mr

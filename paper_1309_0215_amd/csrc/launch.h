@@ -18,6 +18,7 @@ struct WordsLaunch {
   int lds_log2;
   uint32_t debug_hash;
   bool any_records;
+  bool wave_combine;          // merge equal words of a wave before the LDS cache (the wave-level combiner)
   uint32_t* totals;           // device [2]
   uint32_t* bucket_cnt;       // device [n_jobs * kMaxBuckets]
   unsigned long long* bucket_bytes;

@@ -110,13 +110,35 @@ MR_DEV int input_cmp(const uint8_t* in, uint64_t oa, uint64_t ob, uint64_t s, ui
   return 0;
 }
 
-MR_DEV uint64_t key_hash16(uint4 k, uint32_t len, uint32_t debug_hash) {
-  if (debug_hash) return (uint64_t)len * 0x9E3779B97F4A7C15ULL;
-  return hash_block(hash_seed(len), ((uint64_t)k.y << 32) | k.x, ((uint64_t)k.w << 32) | k.z);
+// Placement hash of an inline key (len <= 16, zero padded): 32 bits from
+// three multiplies. It places the key in the LDS cache, and key_hash16
+// extends it for the global table.
+MR_DEV uint32_t lds_hash32(uint4 k, uint32_t len, uint32_t debug_hash) {
+  if (debug_hash) return len * 0x9E3779B1u;
+  const uint32_t a = (k.x ^ __builtin_amdgcn_alignbit(k.z, k.z, 16)) * 0x9E3779B1u;
+  const uint32_t b = (k.y ^ __builtin_amdgcn_alignbit(k.w, k.w, 16) ^ len) * 0x85EBCA77u;
+  uint32_t h = a ^ __builtin_amdgcn_alignbit(b, b, 15);
+  h ^= h >> 16;
+  h *= 0x7FEB352Du;
+  return h ^ (h >> 15);
 }
 
-// Hash of a key of any length stored in the input, block by block; equal to
-// key_hash16 for len <= 16.
+// Global-table hash of an inline key from its 32-bit placement hash: the low
+// word (the table index) is the placement hash itself; the high word (slot
+// tag and flush queue) is a second mix of it.
+MR_DEV uint64_t hash_from32(uint32_t h) {
+  const uint32_t hi = (h ^ (h >> 15)) * 0x2C1B3C6Du;
+  return ((uint64_t)(hi ^ (hi >> 12)) << 32) | h;
+}
+
+MR_DEV uint64_t key_hash16(uint4 k, uint32_t len, uint32_t debug_hash) {
+  return hash_from32(lds_hash32(k, len, debug_hash));
+}
+
+// Hash of a key of any length stored in the input, block by block: the
+// global-table hash of keys longer than 16 bytes (in the word map) and of
+// every Reverse Index URL. A key always takes the same one of the two hashes
+// (it depends only on the length and the map), so equal keys meet.
 MR_DEV uint64_t key_hash_global(const uint8_t* in, uint64_t off, uint64_t len, uint32_t debug_hash) {
   if (debug_hash) return (uint64_t)(len < 0xFFFFu ? len : 0xFFFFu) * 0x9E3779B97F4A7C15ULL;
   uint64_t h = hash_seed((uint32_t)(len < 0xFFFFFFFFull ? len : 0xFFFFFFFFull));
@@ -281,7 +303,6 @@ struct LdsTable {
   uint32_t off[kSlots];   // offset of one occurrence, for the global flush
 };
 
-MR_DEV uint32_t lds_tag(uint64_t h, uint32_t len) { return ((uint32_t)(h >> 32) & 0xFFFFFFC0u) | (len << 1); }
 
 // Bucketed linear probing: a group is searched for the key; a group with an
 // empty slot ends the search (slots fill in order and are never freed, so the
@@ -289,12 +310,12 @@ MR_DEV uint32_t lds_tag(uint64_t h, uint32_t len) { return ((uint32_t)(h >> 32) 
 // table has reached its fill limit.
 // Returns 0 = counted, 1 = a matching slot is still being written or the
 // claim was lost (retry), 2 = not in the table and not inserted (go global).
-template <int L>
+template <int L, int kGroups = kLdsGroups>
 MR_DEV int lds_insert(LdsTable<L>& T, uint32_t* used, uint32_t limit, uint32_t tg, uint32_t h, uint4 k, uint32_t off,
                       uint32_t v = 1u) {
   constexpr uint32_t kGroupMask = LdsTable<L>::kSlots / 4 - 1;
   uint32_t g = h & kGroupMask;
-  for (int p = 0; p < kLdsGroups; ++p) {
+  for (int p = 0; p < kGroups; ++p) {
     // the group's four tags in one 16-byte read, classified without branches
     const uint4 t4 = reinterpret_cast<const uint4*>(T.tag)[g];
     const uint32_t tq = tg | 1u;
@@ -328,6 +349,36 @@ MR_DEV int lds_insert(LdsTable<L>& T, uint32_t* used, uint32_t limit, uint32_t t
     g = (g + 1) & kGroupMask;
   }
   return 2;
+}
+
+// The map's cache lookup, straight-line code for the whole wave. The map
+// places a key only in its home group (four slots): a key whose group filled
+// up before it came is not cached and goes to the global table, so every
+// lookup is one 16-byte tag read, and the keys that miss are the ones first
+// seen late, the colder ones. Returns 0 = counted (a ready slot holds the
+// key), 2 = not cached (the group is full without it), 3 = undecided (a free
+// slot to claim, a slot still being written, or a tag that matched another
+// key): the caller runs lds_insert on the home group.
+template <int L>
+MR_DEV int lds_probe_home(LdsTable<L>& T, uint32_t tg, uint32_t h, uint4 k, uint32_t v) {
+  constexpr uint32_t kGroupMask = LdsTable<L>::kSlots / 4 - 1;
+  const uint32_t g = h & kGroupMask;
+  const uint4 t4 = reinterpret_cast<const uint4*>(T.tag)[g];
+  const uint32_t tq = tg | 1u;
+  const uint32_t c = t4.x == tq ? 0u : (t4.y == tq ? 1u : (t4.z == tq ? 2u : (t4.w == tq ? 3u : 4u)));
+  const bool pend = t4.x == tg || t4.y == tg || t4.z == tg || t4.w == tg;
+  const bool empty = t4.x == 0u || t4.y == 0u || t4.z == 0u || t4.w == 0u;
+  if (c < 4u) {
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");  // key bytes after the ready tag
+    const uint32_t i = 4u * g + c;
+    const uint4 kk = T.key[i];
+    if (((kk.x ^ k.x) | (kk.y ^ k.y) | (kk.z ^ k.z) | (kk.w ^ k.w)) == 0u) {
+      atomicAdd(&T.cnt[i], v);
+      return 0;
+    }
+    return 3;
+  }
+  return (!pend && !empty) ? 2 : 3;
 }
 
 template <int L>
@@ -404,37 +455,91 @@ MR_DEV uint32_t find_job(const uint64_t* __restrict__ tile_base, uint32_t n_jobs
 // Separator mask of a 16-byte block.
 MR_DEV uint32_t sep16(uint4 b) { return sep_mask16(b.x, b.y, b.z, b.w); }
 
-// One workgroup per run of tiles; each 16 KiB tile is cut into 16 parts of
-// 1 KiB, and wave w takes part w of every tile of the run. The waves share the
-// LDS hash cache but no barrier between tiles: each moves on to its next part
-// as soon as it is done, so the latency one wave waits on (a global probe, a
-// slow word) is hidden by the others instead of holding the whole workgroup
-// at a barrier. For each part:
-//   1. every lane loads one 16-byte chunk into the wave's LDS copy of the part
-//      (plus 32 bytes after it) and finds the words that start in its chunk;
-//   2. words of up to 16 bytes become descriptors (offset in the part, length)
-//      in the wave's list, placed by a wave prefix sum; longer words are
-//      measured, hashed and inserted globally by their lane at once;
-//   3. the wave then takes the list one word per lane (all lanes busy): key
-//      bytes from the LDS copy, hash, LDS table insert, global insert on a miss.
+// Four 32-bit words read at any byte address.
+typedef uint32_t u32x4_u __attribute__((ext_vector_type(4), aligned(1)));
+
+// Lane l receives lane l + 1's value (lane 63 keeps `fill`), and lane l
+// receives lane l - 1's value (lane 0 keeps `fill`): DPP whole-wave shifts.
+MR_DEV uint32_t from_next_lane(uint32_t v, uint32_t fill) {
+  return (uint32_t)__builtin_amdgcn_update_dpp((int)fill, (int)v, 0x130, 0xF, 0xF, false);  // wave_shl:1
+}
+MR_DEV uint32_t from_prev_lane(uint32_t v, uint32_t fill) {
+  return (uint32_t)__builtin_amdgcn_update_dpp((int)fill, (int)v, 0x138, 0xF, 0xF, false);  // wave_shr:1
+}
+
+// Inclusive prefix sum over the 64 lanes with DPP: shifts within rows of 16
+// lanes, then the last lane of row 0 (row 2) is broadcast into row 1 (row 3),
+// and the last lane of row 1 into rows 2 and 3. No LDS traffic.
+MR_DEV uint32_t wave_incl_scan(uint32_t x) {
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xF, 0xF, true);  // row_shr:1
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xF, 0xF, true);  // row_shr:2
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xF, 0xF, true);  // row_shr:4
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xF, 0xF, true);  // row_shr:8
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xA, 0xF, false);  // row_bcast:15
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xC, 0xF, false);  // row_bcast:31
+  return x;
+}
+
+// Wave-level combiner: `rounds` times, the first lane still holding a word
+// is the leader; every lane whose word equals the leader's (same LDS hash,
+// length and bytes) adds its count to the leader and drops out. `v` is this
+// lane's count (0 after it merged into a leader). Uniform control flow.
+MR_DEV void wave_combine_words(bool has, uint32_t h, uint32_t len, uint4 k, uint32_t& v, int rounds) {
+  uint64_t left = __ballot(has);
+  for (int r = 0; r < rounds && left; ++r) {
+    const int ld = __ffsll((long long)left) - 1;
+    auto rl = [ld](uint32_t x) { return (uint32_t)__builtin_amdgcn_readlane((int)x, ld); };
+    const uint32_t lh = rl(h), ll = rl(len), k0 = rl(k.x), k1 = rl(k.y), k2 = rl(k.z), k3 = rl(k.w);
+    const bool same = has && v && h == lh && len == ll && k.x == k0 && k.y == k1 && k.z == k2 && k.w == k3;
+    const uint64_t eq = __ballot(same);
+    if ((int)lane_id() == ld) v = popc64(eq);
+    else if (same) v = 0u;
+    left &= ~eq;
+  }
+}
+
+// Lanes per window and owned chunks: wave w's window of a tile is 64
+// consecutive 16-byte chunks, one per lane. Lane 0 holds the chunk before the
+// owned run (its last byte decides whether the first owned byte starts a
+// word) and lane 63 the chunk after it (words of up to 16 bytes that start in
+// lane 62's chunk end there); lanes 1..62 own their chunks. Windows of
+// neighbouring parts overlap by two chunks.
+constexpr uint32_t kOwnChunks = kWave - 2;
+static_assert(kMapTileChunks == (kMapThreads / kWave) * kOwnChunks, "tile = one owned run per wave");
+
+// One workgroup per run of tiles; wave w takes the w-th run of 62 owned
+// chunks of every tile of the run. The waves share the LDS hash cache but no
+// barrier between tiles: each moves on to its next part as soon as it is
+// done, so the latency one wave waits on (a global probe, a slow word) is
+// hidden by the others instead of holding the whole workgroup at a barrier.
+// For each part:
+//   1. every lane loads one 16-byte chunk of the window (loaded two tiles
+//      ahead) and stores it in the wave's LDS copy; it computes its chunk's
+//      separator mask, and takes the next lane's mask and the previous
+//      lane's last bit with DPP lane shifts;
+//   2. each owning lane appends one descriptor per word start (offset in the
+//      window, length; 31 marks a word longer than 16 bytes) to the wave's
+//      list, placed by a wave prefix sum;
+//   3. the wave takes the list one word per lane (all lanes busy): key bytes
+//      from the LDS copy, LDS hash, optionally the wave combiner, LDS cache
+//      insert; words the cache cannot take are packed and inserted globally,
+//      one per lane.
 // Workgroup barriers remain where the run moves to another job (the cache is
 // flushed into the old job's table) and at the end.
-template <int L, bool kRecords>
+template <int L, bool kRecords, bool kCombine>
 __global__ __launch_bounds__(kMapThreads) void k_words_map(const WordJob* __restrict__ jobs, const uint64_t* __restrict__ tile_base,
                                                            uint32_t n_jobs, uint64_t total_tiles, uint32_t debug_hash) {
   constexpr uint32_t kWaves = kMapThreads / kWave;
-  constexpr uint32_t kPart = kMapTileChunks / kWaves;  // chunks per wave part (one per lane)
-  static_assert(kPart == kWave, "one chunk per lane");
   __shared__ LdsTable<L> T;
-  __shared__ uint4 stage[kWaves][kPart + 2];
+  __shared__ uint4 stage[kWaves][kWave];
   __shared__ uint32_t wlist[kWaves][kListCap];
-  constexpr uint32_t kBndWords = kPart * 16 / 32 + 2;
-  __shared__ uint32_t bnd[kRecords ? kWaves : 1][kRecords ? kBndWords : 1];
+  constexpr uint32_t kBndWords = kWave * 16 / 32;  // boundary bits of the 1 KiB window
+  __shared__ uint32_t bnd[kRecords ? kWaves : 1][kRecords ? kBndWords + 1 : 1];
   __shared__ uint32_t s_used;
-  // fill limit of the LDS table: beyond it new words go straight to the global table
-  constexpr uint32_t kLimit = LdsTable<L>::kSlots / 4 * 3;
+  __shared__ uint32_t s_mfill[kFlushParts];  // this workgroup's miss sub-queue fills
 
   for (uint32_t i = threadIdx.x; i < LdsTable<L>::kSlots; i += blockDim.x) T.tag[i] = 0u;
+  for (uint32_t i = threadIdx.x; i < kFlushParts; i += blockDim.x) s_mfill[i] = 0u;
   if (threadIdx.x == 0) s_used = 0;
   __syncthreads();
 
@@ -450,30 +555,24 @@ __global__ __launch_bounds__(kMapThreads) void k_words_map(const WordJob* __rest
     __builtin_amdgcn_wave_barrier();
   };
 
-  // This lane's chunk of the wave's part of tile t (lane 0 also the chunk
-  // before the part, lanes 0 and 1 the two after it): loaded one tile ahead,
-  // so that the loads of the next part are in flight while the current one
-  // is processed.
-  auto load_part = [&](uint64_t t, uint4& mine, uint4& extra) {
+  // This lane's chunk of the wave's window of tile t: chunk c0 - 1 + lane of
+  // the job, c0 = the first owned chunk (spaces outside the job's input).
+  auto load_part = [&](uint64_t t) -> uint4 {
     const uint32_t jn = find_job(tile_base, n_jobs, t);
     const WordJob& Jn = jobs[jn];
     const uint64_t an0 = (uint64_t)Jn.in, an1 = an0 + Jn.n;
-    const uint64_t c0 = (t - tile_base[jn]) * kMapTileChunks + wave * kPart;  // the part's first chunk
-    const uint64_t cn = c0 + lane;
-    mine = cn < Jn.n_chunks ? load_block(an0, an1, (Jn.chunk0 + cn) * 16) : spaces4();
-    // lane 0: the chunk before the part (its address is checked against the
-    // input by load_block, also before the first chunk); lanes 1, 2: the two
-    // chunks after the part, where the job has them
-    const uint64_t cx = lane == 0 ? c0 - 1 : c0 + kPart + (lane - 1);
-    const bool ok = lane == 0 || (lane <= 2 && cx < Jn.n_chunks);
-    extra = ok ? load_block(an0, an1, (Jn.chunk0 + cx) * 16) : spaces4();
+    const int64_t ci = (int64_t)((t - tile_base[jn]) * kMapTileChunks + wave * kOwnChunks) - 1 + (int64_t)lane;
+    return (ci >= 0 && (uint64_t)ci < Jn.n_chunks) ? load_block(an0, an1, (Jn.chunk0 + (uint64_t)ci) * 16) : spaces4();
   };
-  uint4 nx_mine = spaces4(), nx_extra = spaces4();
-  if (t_begin < t_end) load_part(t_begin, nx_mine, nx_extra);
+  // two tiles in flight ahead of the one being processed
+  uint4 nx1 = spaces4(), nx2 = spaces4();
+  if (t_begin < t_end) nx1 = load_part(t_begin);
+  if (t_begin + 1 < t_end) nx2 = load_part(t_begin + 1);
 
   for (uint64_t t = t_begin; t < t_end; ++t) {
-    const uint4 b0 = nx_mine, ex = nx_extra;
-    if (t + 1 < t_end) load_part(t + 1, nx_mine, nx_extra);
+    const uint4 b0 = nx1;
+    nx1 = nx2;
+    if (t + 2 < t_end) nx2 = load_part(t + 2);
     const uint32_t j = find_job(tile_base, n_jobs, t);
     if ((int)j != cur) {
       // every wave meets this point at the same tile
@@ -494,139 +593,132 @@ __global__ __launch_bounds__(kMapThreads) void k_words_map(const WordJob* __rest
     if (abort) continue;  // uniform over the wave
     const uint64_t lt = t - tile_base[j];
     const uint64_t a0 = (uint64_t)J.in;
-    const uint64_t part_addr = (J.chunk0 + lt * kMapTileChunks + wave * kPart) * 16;  // the part's first byte
+    // absolute address of the window's first byte (lane 0's chunk)
+    const uint64_t win = (J.chunk0 + lt * kMapTileChunks + wave * kOwnChunks - 1) * 16;
+    // input offset of the window's first byte, modulo 2^32 (inputs are below 4 GiB)
+    const uint32_t win_off = (uint32_t)(win - a0);
 
     // the previous part's list and copy are no longer read by any lane of the wave
     wave_sync();
+    uint32_t bd = 0u, bd_next = 0u;
     if constexpr (kRecords) {
-      for (uint32_t i = lane; i < kBndWords; i += kWave) bnd[wave][i] = 0u;
+      for (uint32_t i = lane; i <= kBndWords; i += kWave) bnd[wave][i] = 0u;
       wave_sync();
-      // record boundaries falling in [part_addr, part_addr + 32 * kBndWords);
-      // in a batch that mixes jobs with and without records, the latter keep an empty bitmap
+      // record boundaries falling in the window; in a batch that mixes jobs
+      // with and without records, the latter keep an empty bitmap
       if (J.rec) {
-        const int64_t lo_rel = (int64_t)(part_addr - a0);
+        const int64_t lo_rel = (int64_t)(win - a0);
         const uint64_t r0 = rec_lower_bound(J.rec, J.n_rec, lo_rel < 0 ? 0 : (uint64_t)lo_rel);
         for (uint64_t r = r0 + lane; r <= J.n_rec; r += kWave) {
           const uint64_t pa = a0 + gp(J.rec)[r];
-          if (pa < part_addr) continue;
-          const uint64_t bit = pa - part_addr;
+          if (pa < win) continue;
+          const uint64_t bit = pa - win;
           if (bit >= 32ull * kBndWords) break;
           atomicOr(&bnd[wave][bit >> 5], 1u << (bit & 31));
         }
       }
+      wave_sync();
+      const uint32_t wv = bnd[wave][lane >> 1];
+      bd = (lane & 1u) ? (wv >> 16) : (wv & 0xFFFFu);
+      bd_next = from_next_lane(bd, 0u);
     }
 
-    // 1. the part into LDS; this lane's chunk and the next one as a 32-byte window
-    const uint64_t B = part_addr + 16ull * lane;  // this lane's chunk (absolute address)
+    // 1. the window into LDS; separator masks
     ws[lane] = b0;
-    if (lane == 1 || lane == 2) ws[kPart + lane - 1] = ex;
-    wave_sync();
-    const uint4 b1 = ws[lane + 1];
-    // byte B - 1: last byte of the previous chunk (a separator outside the valid range)
-    uint32_t prev = 1u;
-    {
-      const uint64_t pb = B - 1;
-      if (pb >= a0 + vlo && pb < a0 + vhi) {
-        const uint4 q = lane ? ws[lane - 1] : ex;
-        prev = (sep_mask4(q.w) >> 3) & 1u;
-      }
+    uint32_t sep = sep16(b0);
+    // bytes outside the valid range count as separators (only windows that
+    // reach past it need the per-lane check)
+    if (win < a0 + vlo || win + 16ull * kWave > a0 + vhi) {
+      const uint64_t B = win + 16ull * lane;
+      sep |= ~range_mask32((int64_t)(a0 + vlo) - (int64_t)B, (int64_t)(a0 + vhi) - (int64_t)B) & 0xFFFFu;
     }
-    const uint32_t valid = range_mask32((int64_t)(a0 + vlo) - (int64_t)B, (int64_t)(a0 + vhi) - (int64_t)B);
-    const uint32_t sep = (sep16(b0) | (sep16(b1) << 16)) | ~valid;
-    uint32_t bd = 0u;
-    if constexpr (kRecords) {
-      const uint64_t bit = B - part_addr;  // multiple of 16
-      const uint32_t wi = (uint32_t)(bit >> 5);
-      const uint32_t lo = bnd[wave][wi], hi = bnd[wave][wi + 1];
-      bd = (bit & 16) ? ((lo >> 16) | (hi << 16)) : lo;
-    }
-    const uint32_t starts = ~sep & ((sep << 1) | prev | bd) & 0xFFFFu;
-    const uint32_t ends = sep | bd;
+    const uint32_t sep_next = from_next_lane(sep, 0xFFFFu);
+    const uint32_t prev = from_prev_lane(sep >> 15, 1u);
+    const uint32_t starts = (lane - 1u < kOwnChunks) ? (~sep & ((sep << 1) | prev | bd) & 0xFFFFu) : 0u;
+    const uint32_t ends = sep | (sep_next << 16) | bd | (bd_next << 16);
 
-    // 2. inline words (end inside the window, at most 16 bytes) are listed;
-    //    longer words are handled here
-    uint32_t inl = 0u;
-    for (uint32_t m = starts; m; m &= m - 1u) {
-      const uint32_t s = __builtin_ctz(m);
-      const uint32_t after = ends & ~((2u << s) - 1u);
-      const uint32_t e = after ? (uint32_t)__builtin_ctz(after) : 32u;
-      if (after != 0u && e - s <= 16u) {
-        inl |= 1u << s;
-      } else {
-        const uint64_t off = B + s - a0;
-        const uint64_t len = word_length_slow(J, vlo, vhi, off);
-        const uint64_t h = key_hash_global(J.in, off, len, debug_hash);
-        g_insert<false>(J, vlo, vhi, off, len, h, make_uint4(0, 0, 0, 0), 1u, debug_hash);
-      }
-    }
-    const uint32_t n_mine = __builtin_popcount(inl);
-    uint32_t incl = n_mine;
-#pragma unroll
-    for (int o = 1; o < kWave; o <<= 1) {
-      const uint32_t y = (uint32_t)__shfl_up((int)incl, o);
-      if (lane >= (uint32_t)o) incl += y;
-    }
-    const uint32_t total = (uint32_t)__shfl((int)incl, kWave - 1);
+    // 2. one descriptor per word start, placed by a wave prefix sum
+    const uint32_t n_mine = __builtin_popcount(starts);
+    const uint32_t incl = wave_incl_scan(n_mine);
+    const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, kWave - 1);
     const uint32_t first = incl - n_mine;
+    wave_sync();  // the window copy is complete
 
     // 3. rounds of up to kListCap words, one word per lane
     for (uint32_t base = 0; base < total; base += kListCap) {
       uint32_t p = first;
-      for (uint32_t m = inl; m; m &= m - 1u, ++p) {
+      for (uint32_t m = starts; m; m &= m - 1u, ++p) {
         if (p < base || p >= base + kListCap) continue;
         const uint32_t s = __builtin_ctz(m);
         const uint32_t after = ends & ~((2u << s) - 1u);
-        const uint32_t len = (uint32_t)__builtin_ctz(after) - s;
-        wlist[wave][p - base] = ((lane * 16u + s) << 5) | len;
+        const uint32_t len = after ? (uint32_t)__builtin_ctz(after) - s : 32u;
+        wlist[wave][p - base] = ((lane * 16u + s) << 5) | (len <= 16u ? len : 31u);
       }
       wave_sync();
       const uint32_t nr = (total - base) < kListCap ? (total - base) : kListCap;
-      // the word at list entry d: key bytes from the wave's copy of the part
-      auto word_at = [&](uint32_t d, uint4& k, uint32_t& len, uint64_t& h, uint64_t& off) {
-        const uint32_t o = d >> 5;
+      // the word at list entry d: key bytes from the wave's copy of the window
+      auto key_at = [&](uint32_t d, uint4& k, uint32_t& len, uint32_t& o) {
+        o = (d >> 5) & 0x3FFu;
         len = d & 31u;
-        const uint4 x0 = ws[o >> 4], x1 = ws[(o >> 4) + 1];
-        const uint32_t w[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
-        k = extract16(w, o & 15u, len);
-        h = key_hash16(k, len, debug_hash);
-        off = part_addr + o - a0;
+        // 16 bytes at any byte offset of the copy (LDS reads need no alignment
+        // here); o <= 62 * 16 + 15, so the read ends inside the wave's 1 KiB
+        const u32x4_u x = *reinterpret_cast<const u32x4_u*>(reinterpret_cast<const uint8_t*>(ws) + o);
+        k = make_uint4(keep_bytes(x[0], (int)len), keep_bytes(x[1], (int)len - 4), keep_bytes(x[2], (int)len - 8),
+                       keep_bytes(x[3], (int)len - 12));
       };
       // LDS inserts; the words the cache cannot take are marked (bit u: entry lane + 64 u)
       constexpr uint32_t kPerLane = kListCap / kWave;
       uint32_t missed = 0u;
+      uint32_t vcnt[kPerLane];
 #pragma unroll
       for (uint32_t u = 0; u < kPerLane; ++u) {
+        vcnt[u] = 1u;
         const uint32_t i = lane + u * kWave;
-        if (i >= nr) break;
+        if (base + u * kWave >= total) break;  // uniform: no word left for any lane
+        const bool has = i < nr;
+        const uint32_t d = has ? wlist[wave][i] : 0u;
         uint4 k;
-        uint32_t len;
-        uint64_t h, off;
-        word_at(wlist[wave][i], k, len, h, off);
-        const uint32_t tg = lds_tag(h, len);
-        int r = 1;
-        for (uint32_t spin = 0; r == 1; ++spin) {
-          r = lds_insert<L>(T, &s_used, kLimit, tg, (uint32_t)h, k, (uint32_t)off);
-          if (r == 1 && spin > (1u << 22)) {
-            __hip_atomic_fetch_or(gp(&J.st->flags), kFlagSpin, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            r = 0;
+        uint32_t len, o;
+        key_at(d, k, len, o);
+        const bool inl = has && len <= 16u;
+        if (has && !inl) {
+          // a word longer than 16 bytes: measured, hashed and inserted from the input
+          const uint64_t off = (uint64_t)(win_off + o);
+          const uint64_t wl = word_length_slow(J, vlo, vhi, off);
+          g_insert<false>(J, vlo, vhi, off, wl, key_hash_global(J.in, off, wl, debug_hash), make_uint4(0, 0, 0, 0), 1u,
+                          debug_hash);
+        }
+        const uint32_t h = lds_hash32(k, len, debug_hash);
+        uint32_t v = 1u;
+        if constexpr (kCombine) wave_combine_words(inl, h, len, k, v, 4);
+        const uint32_t tg = (h & 0xFFFFFFC0u) | (len << 1);
+        int r = (inl && v) ? lds_probe_home<L>(T, tg, h, k, v) : 0;
+        if (__ballot(r == 3)) {
+          if (r == 3) {
+            r = 1;
+            for (uint32_t spin = 0; r == 1; ++spin) {
+              r = lds_insert<L, 1>(T, &s_used, LdsTable<L>::kSlots, tg, h, k, win_off + o, v);
+              if (r == 1 && spin > (1u << 22)) {
+                __hip_atomic_fetch_or(gp(&J.st->flags), kFlagSpin, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                r = 0;
+              }
+            }
           }
         }
         if (r == 2) missed |= 1u << u;
+        vcnt[u] = v;
       }
       // The misses of the whole round are packed to the front of the list and
       // inserted globally one per lane: the wave then waits on one round of
-      // dependent global probes instead of one per list pass.
+      // dependent global probes instead of one per list pass. A packed entry
+      // carries its count (above 1 after the combiner) in bits 16 and up.
       uint32_t md[kPerLane];
 #pragma unroll
-      for (uint32_t u = 0; u < kPerLane; ++u) md[u] = (missed >> u & 1u) ? wlist[wave][lane + u * kWave] : 0u;
+      for (uint32_t u = 0; u < kPerLane; ++u)
+        md[u] = (missed >> u & 1u) ? ((wlist[wave][lane + u * kWave] & 0xFFFFu) | (vcnt[u] << 16)) : 0u;
       const uint32_t n_m = __builtin_popcount(missed);
-      uint32_t incl_m = n_m;
-#pragma unroll
-      for (int o = 1; o < kWave; o <<= 1) {
-        const uint32_t y = (uint32_t)__shfl_up((int)incl_m, o);
-        if (lane >= (uint32_t)o) incl_m += y;
-      }
-      const uint32_t total_m = (uint32_t)__shfl((int)incl_m, kWave - 1);
+      const uint32_t incl_m = wave_incl_scan(n_m);
+      const uint32_t total_m = (uint32_t)__builtin_amdgcn_readlane((int)incl_m, kWave - 1);
       wave_sync();  // every lane has read its entries
       uint32_t at = incl_m - n_m;
 #pragma unroll
@@ -635,10 +727,23 @@ __global__ __launch_bounds__(kMapThreads) void k_words_map(const WordJob* __rest
       wave_sync();
       for (uint32_t i = lane; i < total_m; i += kWave) {
         uint4 k;
-        uint32_t len;
-        uint64_t h, off;
-        word_at(wlist[wave][i], k, len, h, off);
-        g_insert<true>(J, vlo, vhi, off, len, h, k, 1u, debug_hash);
+        uint32_t len, o;
+        const uint32_t d = wlist[wave][i];
+        key_at(d, k, len, o);
+        const uint32_t off = win_off + o;
+        const uint64_t h = key_hash16(k, len, debug_hash);
+        if (J.mq) {
+          // into this workgroup's sub-queue of the key's partition
+          const uint32_t q = (uint32_t)(h >> kFlushShift);
+          const uint32_t at = atomicAdd(&s_mfill[q], 1u);
+          if (at < J.mq_cap) {
+            FlushRec* dst = reinterpret_cast<FlushRec*>(J.mq) + ((uint64_t)q * J.mq_grid + blockIdx.x) * J.mq_cap + at;
+            gstore16(&dst->k, k);
+            gstore16(&dst->off, make_uint4(off, len, d >> 16, 0u));
+            continue;
+          }
+        }
+        g_insert<true>(J, vlo, vhi, off, len, h, k, d >> 16, debug_hash);
       }
       wave_sync();
     }
@@ -648,6 +753,14 @@ __global__ __launch_bounds__(kMapThreads) void k_words_map(const WordJob* __rest
     if (jobs[cur].queue) lds_flush_parts<L>(T, jobs[cur], &wlist[0][0], vlo, vhi, debug_hash);
     else lds_flush<L>(T, jobs[cur], vlo, vhi, debug_hash);
   }
+  // the miss sub-queue fills (every workgroup of a single job's map writes
+  // all of its entries, zero or not, so nothing needs clearing before)
+  const WordJob& J0 = jobs[0];
+  if (n_jobs == 1 && J0.mq)
+    for (uint32_t q = threadIdx.x; q < kFlushParts; q += blockDim.x) {
+      const uint32_t f = s_mfill[q];
+      J0.mq_fill[q * J0.mq_grid + blockIdx.x] = f < J0.mq_cap ? f : J0.mq_cap;
+    }
 }
 
 // Two-phase flush, second phase: one workgroup per queue of job 0 sums the
@@ -666,27 +779,34 @@ __global__ __launch_bounds__(kMapThreads) void k_words_parts(const WordJob* __re
   if (threadIdx.x == 0) s_used = 0;
   __syncthreads();
   const uint64_t vlo = gp(J.st)->valid_lo, vhi = gp(J.st)->valid_hi;
-  const uint32_t qn = *gp(&J.qcnt[p]);
-  const uint32_t n = qn < J.qcap ? qn : J.qcap;
-  const FlushRec* q = reinterpret_cast<const FlushRec*>(J.queue) + (uint64_t)p * J.qcap;
-  for (uint32_t r0 = threadIdx.x; r0 < n; r0 += blockDim.x) {
-    FlushRec rec;
-    rec.k = gload16(&q[r0].k);
-    const uint4 m = gload16(&q[r0].off);
-    rec.off = m.x;
-    rec.len = m.y;
-    rec.cnt = m.z;
-    const uint64_t h = key_hash16(rec.k, rec.len, debug_hash);
-    const uint32_t tg = lds_tag(h, rec.len);
+  // one record: summed into the LDS table, or inserted globally when it is full
+  auto consume = [&](const FlushRec* rp) {
+    const uint4 k = gload16(&rp->k);
+    const uint4 m = gload16(&rp->off);
+    const uint32_t h32 = lds_hash32(k, m.y, debug_hash);
+    const uint32_t tg = (h32 & 0xFFFFFFC0u) | (m.y << 1);
     int r = 1;
     for (uint32_t spin = 0; r == 1; ++spin) {
-      r = lds_insert<L>(T, &s_used, kLimit, tg, (uint32_t)h, rec.k, rec.off, rec.cnt);
+      r = lds_insert<L>(T, &s_used, kLimit, tg, h32, k, m.x, m.z);
       if (r == 1 && spin > (1u << 22)) {
         __hip_atomic_fetch_or(gp(&J.st->flags), kFlagSpin, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         r = 0;
       }
     }
-    if (r == 2) g_insert<true>(J, vlo, vhi, rec.off, rec.len, h, rec.k, rec.cnt, debug_hash);
+    if (r == 2) g_insert<true>(J, vlo, vhi, m.x, m.y, hash_from32(h32), k, m.z, debug_hash);
+  };
+  const uint32_t qn = *gp(&J.qcnt[p]);
+  const uint32_t n = qn < J.qcap ? qn : J.qcap;
+  const FlushRec* q = reinterpret_cast<const FlushRec*>(J.queue) + (uint64_t)p * J.qcap;
+  for (uint32_t r0 = threadIdx.x; r0 < n; r0 += blockDim.x) consume(&q[r0]);
+  if (J.mq) {
+    // the map workgroups' miss sub-queues of this partition, one wave per sub-queue
+    const uint32_t lane = lane_id();
+    for (uint32_t w = threadIdx.x / kWave; w < J.mq_grid; w += blockDim.x / kWave) {
+      const uint32_t nm = *gp(&J.mq_fill[p * J.mq_grid + w]);
+      const FlushRec* mq = reinterpret_cast<const FlushRec*>(J.mq) + ((uint64_t)p * J.mq_grid + w) * J.mq_cap;
+      for (uint32_t i = lane; i < nm; i += kWave) consume(&mq[i]);
+    }
   }
   __syncthreads();
   lds_flush<L>(T, J, vlo, vhi, debug_hash);
@@ -1455,14 +1575,17 @@ hipError_t words_enqueue_map(const WordsLaunch& L, hipStream_t s) {
     return hipGetLastError();
   }
   const dim3 grid(L.map_grid), block(kMapThreads);
-#define MR_MAP_CASE(LG)                                                                                       \
-  case LG:                                                                                                     \
-    if (L.any_records)                                                                                         \
-      hipLaunchKernelGGL((k_words_map<LG, true>), grid, block, 0, s, L.jobs, L.tile_base, L.n_jobs, L.total_tiles, \
-                         L.debug_hash);                                                                        \
-    else                                                                                                       \
-      hipLaunchKernelGGL((k_words_map<LG, false>), grid, block, 0, s, L.jobs, L.tile_base, L.n_jobs, L.total_tiles, \
-                         L.debug_hash);                                                                        \
+#define MR_MAP_LAUNCH(LG, REC, CMB) \
+  hipLaunchKernelGGL((k_words_map<LG, REC, CMB>), grid, block, 0, s, L.jobs, L.tile_base, L.n_jobs, L.total_tiles, L.debug_hash)
+#define MR_MAP_CASE(LG)                                                   \
+  case LG:                                                                 \
+    if (L.any_records) {                                                   \
+      if (L.wave_combine) MR_MAP_LAUNCH(LG, true, true);                   \
+      else MR_MAP_LAUNCH(LG, true, false);                                 \
+    } else {                                                               \
+      if (L.wave_combine) MR_MAP_LAUNCH(LG, false, true);                  \
+      else MR_MAP_LAUNCH(LG, false, false);                                \
+    }                                                                      \
     break;
   switch (L.lds_log2) {
     MR_MAP_CASE(8)
@@ -1473,6 +1596,7 @@ hipError_t words_enqueue_map(const WordsLaunch& L, hipStream_t s) {
       return hipErrorInvalidValue;
   }
 #undef MR_MAP_CASE
+#undef MR_MAP_LAUNCH
   if (L.flush_parts) hipLaunchKernelGGL((k_words_parts<12>), dim3(kFlushParts), dim3(kMapThreads), 0, s, L.jobs, L.debug_hash);
   return hipGetLastError();
 }

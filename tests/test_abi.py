@@ -57,7 +57,7 @@ def test_null_arguments_are_rejected_without_a_gpu():
 def test_struct_sizes_match_the_header():
     # sizes computed from the C declarations with the usual x86-64 alignment rules
     from paper_1309_0215_amd import _lib as L
-    assert C.sizeof(L.JobConfig) == 4 + 4 + 8 + 4 * 5 + 4 + 8 + 4 + 4 + 4 + 4 + 8 + 4 + 4
+    assert C.sizeof(L.JobConfig) == 4 + 4 + 8 + 4 * 5 + 4 + 8 + 4 + 4 + 4 + 4 + 8 + 4 + 4 + 4 + 4
     assert C.sizeof(L.Stats) == 4 + 4 + 8 + 8 + 4 + 4 + 4 + 4
     assert C.sizeof(L.Output) == 8 * 8 + 8 * 4 + 8 + C.sizeof(L.Stats) + 8 * 4
     assert C.sizeof(L.BatchItem) == 4 + 4 + 8 + 8 + 8 + 8 + 8

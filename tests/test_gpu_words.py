@@ -263,3 +263,31 @@ def test_uneven_parts_alone_and_in_a_batch(torch):
     res = job.words_batch([_dev(torch, b) for b in bufs])
     for r, b in zip(res, bufs):
         _check(r, b)
+
+
+@pytest.mark.parametrize("combine", [0, 1])
+def test_wave_combiner_and_cache_misses(torch, combine):
+    """The wave-level combiner on and off, on text whose vocabulary is far
+    larger than the LDS caches: most words miss them, so the per-workgroup
+    miss sub-queues overflow and the overflow goes to the global table."""
+    from paper_1309_0215_amd import Job
+    job = Job(device=0, wave_combine=combine)
+    for seed, size, V, s in ((81, 16 << 20, 2_000_000, 0.3), (82, 3 << 20, 50_000, 1.0), (83, 100_003, 300, 1.2)):
+        buf = gen.text(seed, size, V=V, s=s, lmin=1, lmax=16)
+        _check(job.words(_dev(torch, buf)), buf)
+
+
+def test_wave_combiner_records_and_hand_cases(torch):
+    from paper_1309_0215_amd import Job
+    job = Job(device=0, wave_combine=1)
+    cases = json.load(open(os.path.join(GOLDEN, "words_hand.json")))["cases"]
+    for c in cases:
+        buf = np.frombuffer(c["input"].encode("latin-1"), np.uint8)
+        offs = None if c["offsets"] is None else np.array(c["offsets"], np.int64)
+        d = _dev(torch, buf) if len(buf) else torch.empty(0, dtype=torch.uint8, device="cuda:0")
+        got = job.words(d, None if offs is None else _dev(torch, offs)).items()
+        assert got == [(k.encode("latin-1"), v) for k, v in c["expect"]], c["input"]
+    buf = gen.text(84, 1 << 20, V=5000, s=1.0)
+    rng = np.random.default_rng(5)
+    offs = np.concatenate([[0], np.sort(rng.integers(0, len(buf) + 1, 999)), [len(buf)]]).astype(np.int64)
+    _check(job.words(_dev(torch, buf), _dev(torch, offs)), buf, offs.astype(np.uint64))
