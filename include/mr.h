@@ -17,9 +17,13 @@
  *     failure on the calling thread.
  *   - "device pointer" means memory on the job's GPU (hipMalloc or a torch
  *     CUDA tensor). "host pointer" means ordinary process memory.
- *   - The caller owns every buffer it passes in. The library owns the
- *     workspace it allocates for a job (device memory, grown on demand, kept
- *     between calls, freed by mr_job_destroy).
+ *   - The caller owns every buffer it passes in. Device memory the library
+ *     needs beyond the inputs and outputs comes from one of two places:
+ *     a caller workspace given in mr_job_config (the library then never
+ *     allocates device memory; mr_workspace_bytes says how much a call
+ *     needs), or, without one, device memory the library allocates for the
+ *     job (grown on demand, kept between calls, freed by mr_job_destroy).
+ *     stats.device_allocs counts the allocations a call made.
  *   - Calls on one mr_job are not thread-safe; use one job per host thread.
  *   - mr_run and mr_batch_run enqueue on the job's stream and synchronise that
  *     stream before returning.
@@ -138,6 +142,15 @@ typedef struct {
    * measured slower on the Zipf text, see the design notes). Outputs do not
    * depend on it. */
   uint32_t wave_combine;
+  /* Caller workspace: device memory (256-byte aligned) of workspace_bytes
+   * bytes that the job uses for all its device buffers instead of allocating
+   * (NULL = the library allocates). It stays the caller's: it must outlive
+   * the job and must not be used for anything else meanwhile, since the job
+   * keeps state in it between calls (clean tables, graphs, uploaded
+   * weights). A call that needs more fails with MR_ERR_CAPACITY and sets
+   * stats.workspace_needed; create a job with a larger workspace then. */
+  void* workspace;
+  uint64_t workspace_bytes;
 } mr_job_config;
 
 typedef struct {
@@ -149,6 +162,11 @@ typedef struct {
   float map_ms;            /* device time of the map (dominant) kernel alone; needs cfg.timing */
   uint32_t km_rechecked;   /* k-means: points whose float32 decision was re-made in float64 */
   uint32_t selector_used;  /* 1 when the learned selector chose the strategy */
+  uint32_t device_allocs;  /* device allocations (hipMalloc) the library made during this call;
+                              always 0 with a caller workspace */
+  uint32_t sort_spills;    /* words: sort buckets too large for LDS, sorted in global memory instead */
+  uint64_t workspace_needed; /* with a caller workspace that was too small (MR_ERR_CAPACITY): the
+                                bytes the call had reached; 0 otherwise */
 } mr_stats;
 
 /* Output buffers (device pointers, caller-allocated) and their capacities.
@@ -201,8 +219,29 @@ const char* mr_last_error(void);
  * Errors: MR_ERR_INVALID_ARG (NULL pointers, bad sizes), MR_ERR_NO_DEVICE. */
 mr_status mr_job_create(const mr_job_config* cfg, mr_job** out);
 
-/* Free the job and its device workspace. NULL is accepted. */
+/* Free the job and the device memory the library allocated for it (a caller
+ * workspace is left alone). NULL is accepted. */
 mr_status mr_job_destroy(mr_job* job);
+
+/* Workspace bytes an mr_run of `kind` needs for inputs of up to
+ * max_input_bytes bytes (and, for integer keys, declared key range
+ * key_range, 0 = undeclared; for MR_MAP_BLOOM the filter bits), with the
+ * job settings of *cfg (device, strategy, table and tuning fields; its
+ * workspace fields are ignored). A pure host computation: the caller then
+ * allocates that much and passes it in mr_job_config.workspace.
+ * The figure covers the call as planned from the input size (Section II-A:
+ * input array in, ordered pairs out). What the data decides beyond the plan
+ * is not covered: a word or integer hash table that must grow past its
+ * planned size (more distinct keys than one per 64 input bytes, or than the
+ * integer range), a Reverse Index with more than one link per 512 bytes.
+ * Such a call fails with MR_ERR_CAPACITY and stats.workspace_needed. For
+ * mr_batch_run, plan with the batch's total size per job kind, or use the
+ * figure a failed call reports. The entry points of the selector need
+ * 24 KiB plus, for mr_mlp_loss_backward, 528 bytes per example.
+ * Errors: MR_ERR_INVALID_ARG (NULL pointers, unknown kind, invalid cfg),
+ * MR_ERR_NO_DEVICE. */
+mr_status mr_workspace_bytes(const mr_job_config* cfg, mr_map_kind kind, uint64_t max_input_bytes, uint64_t key_range,
+                             uint64_t* out_bytes);
 
 /* Run one MapReduce job over d_input (device pointer, input_bytes bytes,
  * read only). d_record_offsets (device pointer, uint64[n_records + 1],
@@ -277,6 +316,49 @@ mr_status mr_job_features(mr_job* job, mr_map_kind kind, mr_reduce_op op, const 
  * used). Passing params = NULL unloads the selector. */
 mr_status mr_selector_set(mr_job* job, const float* params, const float* feat_mean, const float* feat_scale,
                           const float* feat_lo, const float* feat_hi);
+
+/* Load trained selector weights from a JSON file (path on the host): an
+ * object whose members "params" (5252 numbers), "feat_mean", "feat_scale",
+ * "feat_lo" and "feat_hi" (12 numbers each) are as in mr_selector_set;
+ * other members are ignored. The file the training driver writes
+ * (selector_weights.json) has this form. Errors: MR_ERR_INVALID_ARG (file
+ * missing or unreadable, malformed JSON, a member missing or of the wrong
+ * length, a scale not positive); the job then keeps what it had loaded
+ * before (without weights, MR_STRAT_LEARNED runs the rule). */
+mr_status mr_selector_load(mr_job* job, const char* weights_json);
+
+/* Training settings (zero fields take the defaults in brackets). */
+typedef struct {
+  uint32_t epochs; /* passes over the jobs [500] */
+  uint32_t batch;  /* jobs per Adam step, at most 4096 [64] */
+  float lr;        /* Adam step size [1e-3] */
+  float beta1;     /* [0.9] */
+  float beta2;     /* [0.999] */
+  float eps;       /* [1e-8] */
+  uint64_t seed;   /* initialisation and shuffling (SplitMix64) */
+} mr_train_config;
+
+/* Train the selector on measured timings and load the result into the job.
+ * feats: host float[n][12], each job's mr_job_features; times: host
+ * float[n][4], each container's device time in any unit (read only where
+ * feasible, and positive there); feasible: host uint8[n][4] (nonzero =
+ * the container can run the job). The network learns the standardised log
+ * time of every feasible container (one mean and scale over all of them;
+ * masked mean squared error), from He-uniform initial weights, with
+ * bias-corrected Adam over shuffled batches; forward, backward and Adam run
+ * on the GPU in the kernels mr_mlp_* expose. Features are standardised
+ * (mean, standard deviation; a constant feature keeps scale 1) and the
+ * range seen, widened by a tenth, becomes feat_lo / feat_hi. loss_out (host
+ * float[epochs] or NULL) receives each epoch's mean loss; out_json (path or
+ * NULL) receives the weights in the form mr_selector_load reads. Device
+ * memory for the call: about 80 bytes per job, 1.1 KiB per batch example
+ * and 84 KiB (a workspace region, or a library allocation freed before the
+ * call returns). Errors: MR_ERR_INVALID_ARG (NULL
+ * pointers, n = 0, no feasible container, a feasible time not positive,
+ * batch above 4096, a beta not below 1, out_json not writable),
+ * MR_ERR_CAPACITY (caller workspace too small), MR_ERR_HIP. */
+mr_status mr_selector_train(mr_job* job, const float* feats, const float* times, const uint8_t* feasible, uint32_t n,
+                            const mr_train_config* cfg, float* loss_out, const char* out_json);
 
 /* Predicted standardised log times (host float[4]) for host features feats. */
 mr_status mr_selector_predict(mr_job* job, const float* feats, float* pred);

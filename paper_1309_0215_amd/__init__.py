@@ -12,7 +12,7 @@ from dataclasses import dataclass
 from . import _lib as L
 from ._lib import MRError  # noqa: F401
 
-__all__ = ["Job", "WordsResult", "U32Result", "MRError", "load"]
+__all__ = ["Job", "WordsResult", "U32Result", "MRError", "load", "workspace_bytes"]
 
 
 def load():
@@ -57,7 +57,8 @@ def _stats(o: L.Output) -> dict:
     s = o.stats
     return {"strategy_used": s.strategy_used, "retries": s.retries, "table_slots": s.table_slots,
             "n_items": s.n_items, "gpu_ms": s.gpu_ms, "map_ms": s.map_ms, "km_rechecked": s.km_rechecked,
-            "selector_used": s.selector_used}
+            "selector_used": s.selector_used, "device_allocs": s.device_allocs, "sort_spills": s.sort_spills,
+            "workspace_needed": s.workspace_needed}
 
 
 TUNE_KINDS = {"words": L.MAP_WORDS, "u32": L.MAP_U32_KEYS, "u32_kv": L.MAP_U32_KV}
@@ -100,12 +101,24 @@ class LinksResult:
         return [(kb[o[i]:o[i + 1]], int(c[i]), ids[lo[i]:lo[i + 1]].tolist()) for i in range(len(c))]
 
 
+def workspace_bytes(kind: int, input_bytes: int, key_range: int = 0, device: int = 0, strategy: int = L.STRAT_RULE,
+                    km_k: int = 0, km_d: int = 0, bloom_k: int = 0, bloom_hashes: int = 0) -> int:
+    """mr_workspace_bytes: device bytes an mr_run of `kind` needs for inputs of up to input_bytes."""
+    lib = load()
+    cfg = L.JobConfig()
+    cfg.device, cfg.strategy, cfg.km_k, cfg.km_d = device, strategy, km_k, km_d
+    cfg.bloom_k, cfg.bloom_hashes = bloom_k, bloom_hashes
+    out = C.c_uint64(0)
+    L.check(lib.mr_workspace_bytes(C.byref(cfg), kind, input_bytes, key_range, C.byref(out)), "mr_workspace_bytes")
+    return int(out.value)
+
+
 class Job:
     """One mr_job bound to a device and to that device's current torch stream."""
 
     def __init__(self, device: int = 0, strategy: int = L.STRAT_RULE, lds_slots: int = 0, max_load_pct: int = 0,
                  debug_hash: int = 0, table_slots: int = 0, km_centroids=None, stream=None, timing: int = 0,
-                 bloom_k: int = 0, bloom_hashes: int = 0, wave_combine: int = 0):
+                 bloom_k: int = 0, bloom_hashes: int = 0, wave_combine: int = 0, workspace=None):
         import torch
         self.torch = torch
         self.lib = load()
@@ -122,6 +135,11 @@ class Job:
         cfg.bloom_k = bloom_k
         cfg.bloom_hashes = bloom_hashes
         cfg.wave_combine = wave_combine
+        # a caller workspace (uint8 CUDA tensor): the library then allocates no device memory
+        self._ws = workspace
+        if workspace is not None:
+            cfg.workspace = workspace.data_ptr()
+            cfg.workspace_bytes = int(workspace.numel()) * int(workspace.element_size())
         self._km = None
         if km_centroids is not None:
             c = km_centroids.to(device=f"cuda:{device}", dtype=torch.float32).contiguous()

@@ -26,7 +26,8 @@ MLP_PARAMS = 5252
 EXPORTS = [
     "mr_status_str", "mr_last_error", "mr_job_create", "mr_job_destroy", "mr_run", "mr_batch_run",
     "mr_job_features", "mr_selector_set", "mr_selector_predict", "mr_mlp_forward", "mr_mlp_loss_backward",
-    "mr_mlp_adam", "mr_tune_set", "mr_rgb_hist_static",
+    "mr_mlp_adam", "mr_tune_set", "mr_rgb_hist_static", "mr_workspace_bytes", "mr_selector_load",
+    "mr_selector_train",
 ]
 
 
@@ -47,6 +48,8 @@ class JobConfig(C.Structure):
         ("bloom_k", C.c_uint32),
         ("bloom_hashes", C.c_uint32),
         ("wave_combine", C.c_uint32),
+        ("workspace", C.c_void_p),
+        ("workspace_bytes", C.c_uint64),
     ]
 
 
@@ -60,6 +63,9 @@ class Stats(C.Structure):
         ("map_ms", C.c_float),
         ("km_rechecked", C.c_uint32),
         ("selector_used", C.c_uint32),
+        ("device_allocs", C.c_uint32),
+        ("sort_spills", C.c_uint32),
+        ("workspace_needed", C.c_uint64),
     ]
 
 
@@ -95,6 +101,18 @@ class TuneEntry(C.Structure):
         ("max_load_pct", C.c_uint32),
         ("map_grid_pct", C.c_uint32),
         ("lds_array_bytes", C.c_uint32),
+    ]
+
+
+class TrainConfig(C.Structure):
+    _fields_ = [
+        ("epochs", C.c_uint32),
+        ("batch", C.c_uint32),
+        ("lr", C.c_float),
+        ("beta1", C.c_float),
+        ("beta2", C.c_float),
+        ("eps", C.c_float),
+        ("seed", C.c_uint64),
     ]
 
 
@@ -140,6 +158,12 @@ def load(required: bool = True):
     lib.mr_tune_set.argtypes = [P, C.POINTER(TuneEntry), U32]
     lib.mr_rgb_hist_static.restype = I32
     lib.mr_rgb_hist_static.argtypes = [P, P, U64, P]
+    lib.mr_workspace_bytes.restype = I32
+    lib.mr_workspace_bytes.argtypes = [C.POINTER(JobConfig), C.c_int, U64, U64, C.POINTER(U64)]
+    lib.mr_selector_load.restype = I32
+    lib.mr_selector_load.argtypes = [P, C.c_char_p]
+    lib.mr_selector_train.restype = I32
+    lib.mr_selector_train.argtypes = [P, P, P, P, U32, C.POINTER(TrainConfig), P, C.c_char_p]
     if hasattr(lib, "mr_job_features"):
         lib.mr_job_features.restype = I32
         lib.mr_job_features.argtypes = [P, C.c_int, C.c_int, P, U64, U64, P]

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -38,6 +39,8 @@ mr_status fail(mr_status s, const char* fmt, ...) {
     if (e_ != hipSuccess) return fail(MR_ERR_HIP, "%s: %s", #call, hipGetErrorString(e_)); \
   } while (0)
 
+uint64_t sel_floats();  // floats of the selector region
+
 uint64_t next_pow2(uint64_t x) {
   uint64_t p = 1;
   while (p < x) p <<= 1;
@@ -65,8 +68,11 @@ struct mr_job {
   // selector
   bool sel_loaded = false;
   std::vector<float> sel_params, sel_mean, sel_scale, sel_lo, sel_hi;
-  // k-means centroids (device, owned)
+  // k-means centroids (device; a host copy re-fills them when a caller
+  // workspace region holding them was overwritten)
   float* km_c = nullptr;
+  uint64_t km_c_bytes = 0;
+  std::vector<float> km_host;
   // batched graph cache: valid while nothing else has written the workspace
   hipGraphExec_t graph = nullptr;
   uint64_t graph_key = 0;
@@ -89,24 +95,47 @@ struct mr_job {
   uint32_t h_states_cap = 0;
   // integer-key containers: persistent and kept clean between runs
   void* int_dense = nullptr;     // dense counts [R] then values [R] (64-bit)
-  uint64_t int_dense_R = 0;
+  uint64_t int_dense_R = 0;      // R of the dense layout
+  uint64_t int_dense_bytes = 0;
   void* int_table = nullptr;     // keys [cap], counts [cap], values [cap] (64-bit), claimed [cap]
+  uint64_t int_table_bytes = 0;  // (int_table_cap: the cap of the layout)
   uint64_t int_table_cap = 0;
   void* int_small = nullptr;     // flags, counters, side slot
+  uint64_t int_small_bytes = 0;
   void* int_scratch = nullptr;   // partials, sort records, scans
   uint64_t int_scratch_bytes = 0;
   uint64_t int_last_distinct = 0;
   // selector scratch (device): features, inputs, outputs, parameters; MLP training scratch
   void* sel_dev = nullptr;
-  uint64_t sel_dev_floats = 0;
+  uint64_t sel_dev_bytes = 0;
   void* mlp_dev = nullptr;
-  uint64_t mlp_dev_floats = 0;
+  uint64_t mlp_dev_bytes = 0;
   // Reverse Index: marker list and pairs (sized by link_cap), then the sort scratch
   void* link_dev = nullptr;
   uint64_t link_dev_bytes = 0;
   uint64_t link_cap = 0;
   // tuned launch parameters by map kind and input size
   std::vector<mr_tune_entry> tune;
+  // device memory accounting: hipMalloc calls during the current call and in total
+  uint32_t call_allocs = 0;
+  uint64_t total_allocs = 0;
+  // caller-owned workspace (cfg.workspace): every device buffer of a call is a
+  // region of it, carved in request order from offset 0 (so a call repeating
+  // the previous call's requests finds its regions where they were); the
+  // library then never allocates device memory
+  uint8_t* cws = nullptr;
+  uint64_t cws_bytes = 0;
+  uint64_t cws_off = 0;    // end of the current call's regions
+  uint64_t cws_need = 0;   // bytes the current call needed when it ran out (0: it fit)
+  int cws_family = -1;     // which entry point family the last call was
+  bool cws_prefix = true;  // every region of this call so far matches the last call's
+  struct Region {
+    int id;
+    uint64_t off, bytes;
+    bool operator==(const Region& o) const { return id == o.id && off == o.off && bytes == o.bytes; }
+  };
+  std::vector<Region> cws_prev, cws_cur;
+  bool sel_uploaded = false;  // the selector weights are in the device region
 };
 
 namespace {
@@ -139,23 +168,122 @@ struct Carve {
   }
 };
 
-mr_status ensure_ws(mr_job* job, uint64_t bytes) {
-  if (bytes <= job->ws_bytes) return MR_OK;
-  const uint64_t want = std::max<uint64_t>(bytes, job->ws_bytes + job->ws_bytes / 2);
-  if (job->ws) {
-    MR_HIP(hipStreamSynchronize(job->stream));
-    if (job->gstream) MR_HIP(hipStreamSynchronize(job->gstream));
-    MR_HIP(hipFree(job->ws));
-    job->ws = nullptr;
-    job->ws_bytes = 0;
+// Device regions of a job and the entry-point families that use them.
+enum RegionId { kRegWs = 1, kRegKmC, kRegSmall, kRegDense, kRegTable, kRegScratch, kRegSel, kRegMlp, kRegLink, kRegTrain };
+enum Family { kFamWords = 1, kFamRgb, kFamKmeans, kFamBloom, kFamU32, kFamLinks, kFamFeatures, kFamPredict, kFamMlp, kFamTrain };
+
+// Start of a call of `family`. With a caller workspace the call carves its
+// regions from offset 0; a region keeps its contents from the last call only
+// when that call was of the same family and every region requested up to it
+// had the same place and size (then no other region overlapped it since).
+void arena_begin(mr_job* job, int family) {
+  job->call_allocs = 0;
+  job->cws_need = 0;
+  if (!job->cws) return;
+  job->cws_prev.clear();
+  if (family == job->cws_family) job->cws_prev.swap(job->cws_cur);
+  job->cws_cur.clear();
+  job->cws_off = 0;
+  job->cws_prefix = true;
+  if (family != job->cws_family) {
+    // the workspace was used by another kind of call: nothing in it is known
+    job->table_clean_bytes = 0;
+    job->graph_valid = false;
+    job->sel_uploaded = false;
   }
-  uint8_t* p = nullptr;
-  hipError_t e = hipMalloc(&p, want);
-  if (e != hipSuccess) return fail(MR_ERR_HIP, "hipMalloc(%llu) failed: %s", (unsigned long long)want, hipGetErrorString(e));
-  job->ws = p;
-  job->ws_bytes = want;
-  job->table_clean_bytes = 0;
-  job->graph_valid = false;
+  job->cws_family = family;
+}
+
+// Device memory of region `id`, at least `want` bytes, at *p (size in *have).
+// Library memory: a buffer already large enough is kept (*fresh = false);
+// otherwise it is replaced by `alloc` >= want new bytes (*fresh = true:
+// contents undefined; the old buffer is freed after the job's streams are
+// synchronised). Caller workspace: the next `want` bytes of the workspace
+// (256-byte aligned). A region requested again in the same call is the same
+// one when it is large enough (*fresh = false: contents as this call left
+// them), is extended in place when it is the last one, and is otherwise
+// taken anew after the others. For a first request *fresh tells whether the
+// contents are those the last call left there. A workspace
+// too small fails with MR_ERR_CAPACITY and the bytes needed in cws_need.
+mr_status dev_region(mr_job* job, int id, void** p, uint64_t* have, uint64_t want, uint64_t alloc, bool* fresh) {
+  if (!job->cws) {
+    if (*p && *have >= want) {
+      *fresh = false;
+      return MR_OK;
+    }
+    if (*p) {
+      MR_HIP(hipStreamSynchronize(job->stream));
+      if (job->gstream) MR_HIP(hipStreamSynchronize(job->gstream));
+      MR_HIP(hipFree(*p));
+      *p = nullptr;
+      *have = 0;
+    }
+    alloc = std::max(alloc, want);
+    hipError_t e = hipMalloc(p, alloc);
+    if (e != hipSuccess) return fail(MR_ERR_HIP, "hipMalloc(%llu) failed: %s", (unsigned long long)alloc, hipGetErrorString(e));
+    ++job->call_allocs;
+    ++job->total_allocs;
+    *have = alloc;
+    *fresh = true;
+    return MR_OK;
+  }
+  auto& cur = job->cws_cur;
+  for (size_t i = cur.size(); i-- > 0;) {
+    // a region this call already carved and large enough: the same one again
+    if (cur[i].id == id && cur[i].bytes >= want) {
+      *p = job->cws + cur[i].off;
+      *have = cur[i].bytes;
+      *fresh = false;
+      return MR_OK;
+    }
+    if (cur[i].id == id) break;
+  }
+  if (!cur.empty() && cur.back().id == id) {
+    // the last region again: extend it in place
+    mr_job::Region& r = cur.back();
+    if (r.off + want > job->cws_bytes) {
+      job->cws_need = r.off + want;
+      return fail(MR_ERR_CAPACITY, "the workspace (%llu bytes) is too small: this call needs %llu bytes",
+                  (unsigned long long)job->cws_bytes, (unsigned long long)job->cws_need);
+    }
+    if (want > r.bytes) {
+      r.bytes = want;
+      job->cws_prefix = false;
+    }
+    job->cws_off = r.off + r.bytes;
+    *p = job->cws + r.off;
+    *have = r.bytes;
+    *fresh = !job->cws_prefix;
+    return MR_OK;
+  }
+  const uint64_t o = align_up(job->cws_off, 256);
+  if (o + want > job->cws_bytes) {
+    job->cws_need = o + want;
+    return fail(MR_ERR_CAPACITY, "the workspace (%llu bytes) is too small: this call needs %llu bytes",
+                (unsigned long long)job->cws_bytes, (unsigned long long)job->cws_need);
+  }
+  const mr_job::Region r{id, o, want};
+  const size_t i = cur.size();
+  if (!(job->cws_prefix && i < job->cws_prev.size() && job->cws_prev[i] == r)) job->cws_prefix = false;
+  cur.push_back(r);
+  job->cws_off = o + want;
+  *p = job->cws + o;
+  *have = want;
+  *fresh = !job->cws_prefix;
+  return MR_OK;
+}
+
+mr_status ensure_ws(mr_job* job, uint64_t bytes) {
+  void* p = job->ws;
+  bool fresh = false;
+  mr_status st = dev_region(job, kRegWs, &p, &job->ws_bytes, bytes, std::max<uint64_t>(bytes, job->ws_bytes + job->ws_bytes / 2),
+                            &fresh);
+  if (st != MR_OK) return st;
+  job->ws = static_cast<uint8_t*>(p);
+  if (fresh) {
+    job->table_clean_bytes = 0;
+    job->graph_valid = false;
+  }
   return MR_OK;
 }
 
@@ -229,12 +357,16 @@ extern "C" mr_status mr_job_create(const mr_job_config* cfg, mr_job** out) {
   if (cfg->table_slots && (cfg->table_slots & (cfg->table_slots - 1)))
     return fail(MR_ERR_INVALID_ARG, "table_slots must be a power of two");
   if (cfg->max_load_pct > 95) return fail(MR_ERR_INVALID_ARG, "max_load_pct above 95");
+  if ((cfg->workspace_bytes && !cfg->workspace) || (cfg->workspace && (uintptr_t)cfg->workspace % 256))
+    return fail(MR_ERR_INVALID_ARG, "the workspace must be a 256-byte aligned device pointer with its size");
   mr_job* job = new (std::nothrow) mr_job();
   if (!job) return fail(MR_ERR_INVALID_ARG, "out of host memory");
   job->cfg = *cfg;
   job->device = cfg->device;
   job->stream = static_cast<hipStream_t>(cfg->stream);
   job->n_cu = prop.multiProcessorCount;
+  job->cws = static_cast<uint8_t*>(cfg->workspace);
+  job->cws_bytes = cfg->workspace ? cfg->workspace_bytes : 0;
   ScopedDevice sd(job->device);
   if (hipEventCreate(&job->ev0) != hipSuccess || hipEventCreate(&job->ev1) != hipSuccess ||
       hipEventCreate(&job->ev2) != hipSuccess || hipEventCreate(&job->ev3) != hipSuccess ||
@@ -252,9 +384,10 @@ extern "C" mr_status mr_job_create(const mr_job_config* cfg, mr_job** out) {
       mr_job_destroy(job);
       return fail(MR_ERR_INVALID_ARG, "k-means needs centroids, 1 <= d <= 256 and 1 <= k <= 1024");
     }
-    const size_t bytes = sizeof(float) * cfg->km_d * cfg->km_k;
-    if (hipMalloc(&job->km_c, bytes) != hipSuccess ||
-        hipMemcpyAsync(job->km_c, cfg->km_centroids, bytes, hipMemcpyDeviceToDevice, job->stream) != hipSuccess ||
+    // kept on the host; each run places them in a device region
+    job->km_host.resize((size_t)cfg->km_d * cfg->km_k);
+    if (hipMemcpyAsync(job->km_host.data(), cfg->km_centroids, sizeof(float) * job->km_host.size(), hipMemcpyDeviceToHost,
+                       job->stream) != hipSuccess ||
         hipStreamSynchronize(job->stream) != hipSuccess) {
       mr_job_destroy(job);
       return fail(MR_ERR_HIP, "copying the initial centroids failed");
@@ -274,16 +407,12 @@ extern "C" mr_status mr_job_destroy(mr_job* job) {
     if (e) (void)hipEventDestroy(e);
   if (job->gstream) (void)hipStreamSynchronize(job->gstream);
   if (job->gstream) (void)hipStreamDestroy(job->gstream);
-  if (job->ws) (void)hipFree(job->ws);
-  if (job->km_c) (void)hipFree(job->km_c);
   if (job->h_states) (void)hipHostFree(job->h_states);
-  if (job->int_dense) (void)hipFree(job->int_dense);
-  if (job->int_table) (void)hipFree(job->int_table);
-  if (job->int_small) (void)hipFree(job->int_small);
-  if (job->int_scratch) (void)hipFree(job->int_scratch);
-  if (job->sel_dev) (void)hipFree(job->sel_dev);
-  if (job->mlp_dev) (void)hipFree(job->mlp_dev);
-  if (job->link_dev) (void)hipFree(job->link_dev);
+  if (!job->cws) {  // regions of a caller workspace belong to the caller
+    for (void* p : {(void*)job->ws, (void*)job->km_c, job->int_dense, job->int_table, job->int_small, job->int_scratch,
+                    job->sel_dev, job->mlp_dev, job->link_dev})
+      if (p) (void)hipFree(p);
+  }
   if (job->ev0) (void)hipEventDestroy(job->ev0);
   if (job->ev1) (void)hipEventDestroy(job->ev1);
   if (job->ev2) (void)hipEventDestroy(job->ev2);
@@ -702,6 +831,7 @@ mr_status run_words(mr_job* job, std::vector<WordItem>& items, std::vector<mr_st
     o->stats.gpu_ms = total_ms;
     o->stats.map_ms = map_ms;
     o->stats.n_items = 0;
+    o->stats.sort_spills = s.sort_spills;
     mr_status r = MR_OK;
     if (s.flags & kFlagBadInput) r = fail(MR_ERR_INVALID_ARG, "malformed record offsets (item %zu)", j);
     else if (s.flags & kFlagSpin) r = fail(MR_ERR_HIP, "bounded wait expired (item %zu)", j);
@@ -727,14 +857,8 @@ uint32_t bits_for(uint64_t n) {  // smallest b with 2^b >= n
 }
 
 mr_status ensure_link_dev(mr_job* job, uint64_t bytes) {
-  if (bytes <= job->link_dev_bytes) return MR_OK;
-  MR_HIP(hipStreamSynchronize(job->stream));
-  if (job->link_dev) MR_HIP(hipFree(job->link_dev));
-  job->link_dev = nullptr;
-  job->link_dev_bytes = 0;
-  MR_HIP(hipMalloc(&job->link_dev, bytes));
-  job->link_dev_bytes = bytes;
-  return MR_OK;
+  bool fresh = false;
+  return dev_region(job, kRegLink, &job->link_dev, &job->link_dev_bytes, bytes, bytes, &fresh);
 }
 
 mr_status run_links(mr_job* job, mr_reduce_op op, const void* d_input, uint64_t bytes, const uint64_t* rec, uint64_t n_rec,
@@ -788,14 +912,18 @@ mr_status run_links(mr_job* job, mr_reduce_op op, const void* d_input, uint64_t 
   const uint64_t o_head = c2.take(4 * std::max<uint64_t>(n, 1)), o_tot = c2.take(8), o_val = c2.take(8), o_fl = c2.take(8);
   const uint64_t o_first = c2.take(4 * (nk + 1));
   if (c2.off > job->link_dev_bytes) {
-    // keep the pairs: grow into a new buffer and copy the map's part across
+    // keep the pairs: grow into a new buffer (library memory) or a new region
+    // after the others (caller workspace) and copy the map's part across
     void* nd = nullptr;
-    MR_HIP(hipMalloc(&nd, c2.off));
+    uint64_t nh = 0;
+    bool fresh = false;
+    st = dev_region(job, kRegLink, &nd, &nh, c2.off, c2.off, &fresh);
+    if (st != MR_OK) return st;
     MR_HIP(hipMemcpyAsync(nd, job->link_dev, c.off, hipMemcpyDeviceToDevice, job->stream));
     MR_HIP(hipStreamSynchronize(job->stream));
-    MR_HIP(hipFree(job->link_dev));
+    if (!job->cws) MR_HIP(hipFree(job->link_dev));
     job->link_dev = nd;
-    job->link_dev_bytes = c2.off;
+    job->link_dev_bytes = nh;
   }
   uint8_t* d = static_cast<uint8_t*>(job->link_dev);
   LinksPost P{};
@@ -928,6 +1056,7 @@ mr_status run_rgb(mr_job* job, const void* d_input, uint64_t bytes, mr_output* o
 // ---------------------------------------------------------------------------
 
 constexpr uint64_t kLdsArrayBudget = 64 * 1024;   // LDS bytes a workgroup may give to a private array
+constexpr uint64_t kIntSlotBytes = 4 + 4 + 8 + 4;  // integer hash table: key, count, value, claimed list
 constexpr uint64_t kGlobalArrayMax = 1ull << 27;  // largest declared range for the global array
 
 // Small per-run state block (device): flags, counters, side slot.
@@ -941,17 +1070,14 @@ struct IntSmall {
   int32_t pad;
 };
 
-mr_status int_ensure(mr_job* job, void** p, uint64_t* have, uint64_t want, uint64_t elem_bytes, int fill) {
-  if (want <= *have && *p) return MR_OK;
-  MR_HIP(hipStreamSynchronize(job->stream));
-  if (*p) MR_HIP(hipFree(*p));
-  *p = nullptr;
-  *have = 0;
-  const uint64_t bytes = want * elem_bytes + 8;  // + 8: alignment slack of split arrays
-  hipError_t e = hipMalloc(p, bytes);
-  if (e != hipSuccess) return fail(MR_ERR_HIP, "hipMalloc(%llu): %s", (unsigned long long)bytes, hipGetErrorString(e));
-  *have = want;
-  if (fill >= 0) MR_HIP(hipMemsetAsync(*p, fill, bytes, job->stream));
+// Region `id` of at least `bytes` bytes; a new one is filled with the byte
+// `fill` when fill >= 0. *fresh (optional) tells whether it is new.
+mr_status int_ensure(mr_job* job, int id, void** p, uint64_t* have, uint64_t bytes, int fill, bool* fresh_out = nullptr) {
+  bool fresh = false;
+  mr_status st = dev_region(job, id, p, have, bytes, bytes, &fresh);
+  if (st != MR_OK) return st;
+  if (fresh && fill >= 0) MR_HIP(hipMemsetAsync(*p, fill, bytes, job->stream));
+  if (fresh_out) *fresh_out = fresh;
   return MR_OK;
 }
 
@@ -983,6 +1109,78 @@ mr_strategy rule_strategy(uint64_t R, uint32_t op, uint64_t lds_budget) {
 mr_status learned_strategy(mr_job* job, mr_map_kind kind, mr_reduce_op op, const void* d_input, uint64_t bytes,
                            uint64_t R, mr_strategy* s, bool* used);
 
+// Scratch layouts of the integer-key containers (offsets in the scratch region).
+struct DenseCarve {  // LDS or global array over n elements and range R, G workgroups
+  uint64_t o_blk = 0, o_cp = 0, o_vp = 0, o_ph = 0, o_ps = 0, o_pt = 0, o_pk = 0, bytes = 0;
+  bool parts = false;  // a large COUNT array filled by key-range partitions
+  PartPlan pp;
+};
+DenseCarve dense_carve(mr_strategy strat, uint64_t n, uint64_t R, uint32_t op, uint32_t G) {
+  DenseCarve d;
+  Carve c;
+  const uint64_t nb = (R + 2047) / 2048;
+  d.o_blk = c.take(4 * (nb + 1));
+  if (strat == MR_STRAT_LDS_ARRAY) {
+    d.o_cp = c.take(4ull * G * R);
+    d.o_vp = c.take((op == MR_REDUCE_SUM ? 8ull : 4ull) * G * R);
+  }
+  // a large array counted by key-range partitions instead of atomics
+  d.pp = part_plan(n, R);
+  d.parts = strat == MR_STRAT_GLOBAL_ARRAY && op == MR_REDUCE_COUNT && d.pp.usable;
+  if (d.parts) {
+    d.o_ph = c.take(4 * d.pp.H);
+    d.o_ps = c.take(4ull * d.pp.sb + 4);
+    d.o_pt = c.take(8);
+    d.o_pk = c.take(2 * n);
+  }
+  d.bytes = c.off;
+  return d;
+}
+struct HashCarve {  // output records and radix sort of nc claimed keys
+  uint64_t o_rk32, o_rk0, o_rv0, o_rk1, o_rv1, o_hist, o_ss, bytes;
+};
+HashCarve hash_carve(uint64_t nc) {
+  HashCarve h;
+  Carve c;
+  const uint64_t hn = 256 * std::max<uint64_t>((nc + 2047) / 2048, 1);
+  h.o_rk32 = c.take(4 * (nc + 1));
+  h.o_rk0 = c.take(8 * (nc + 1));
+  h.o_rv0 = c.take(8 * (nc + 1));
+  h.o_rk1 = c.take(8 * (nc + 1));
+  h.o_rv1 = c.take(8 * (nc + 1));
+  h.o_hist = c.take(4 * hn);
+  h.o_ss = c.take(4 * (hn / 4096 + 2));
+  h.bytes = c.off;
+  return h;
+}
+struct SortCarve {  // radix sort of all n pairs and the segmented reduce
+  uint64_t o_rk0, o_rv0, o_rk1, o_rv1, o_hist, o_ss, o_head, o_pos, o_hpos, o_ps, bytes;
+};
+SortCarve sort_carve(uint64_t n) {
+  SortCarve s;
+  Carve c;
+  const uint64_t hn = 256 * std::max<uint64_t>((n + 2047) / 2048, 1);
+  s.o_rk0 = c.take(8 * (n + 1));
+  s.o_rv0 = c.take(8 * (n + 1));
+  s.o_rk1 = c.take(8 * (n + 1));
+  s.o_rv1 = c.take(8 * (n + 1));
+  s.o_hist = c.take(4 * hn);
+  s.o_ss = c.take(4 * (std::max(hn, n) / 4096 + 2));
+  s.o_head = c.take(4 * (n + 1));
+  s.o_pos = c.take(4 * (n + 1));
+  s.o_hpos = c.take(4 * (n + 2));
+  s.o_ps = c.take(8 * (n / 4096 + 2));
+  s.bytes = c.off;
+  return s;
+}
+// Initial slots of the integer hash table for n elements and range R.
+uint64_t int_table_slots(const mr_job* job, mr_map_kind kind, uint64_t bytes, uint64_t n, uint64_t R) {
+  if (job->cfg.table_slots) return job->cfg.table_slots;
+  const uint64_t bound = std::max<uint64_t>(1, R ? std::min<uint64_t>(n, R) : n);
+  const double lf = eff_load_pct(job, kind, bytes) / 100.0;
+  return std::max<uint64_t>(4096, next_pow2((uint64_t)std::ceil(std::min<uint64_t>(bound, 1ull << 24) / lf)));
+}
+
 mr_status run_u32(mr_job* job, mr_map_kind kind, mr_reduce_op op, const void* d_input, uint64_t bytes, uint64_t key_range,
                   mr_output* out) {
   const uint32_t esz = kind == MR_MAP_U32_KV ? 8 : 4;
@@ -1007,8 +1205,7 @@ mr_status run_u32(mr_job* job, mr_map_kind kind, mr_reduce_op op, const void* d_
     return fail(MR_ERR_UNSUPPORTED, "strategy %d is infeasible for this job (key_range %llu)", (int)strat,
                 (unsigned long long)key_range);
 
-  uint64_t small_have = job->int_small ? 1 : 0;
-  mr_status st = int_ensure(job, &job->int_small, &small_have, 1, sizeof(IntSmall), 0);
+  mr_status st = int_ensure(job, kRegSmall, &job->int_small, &job->int_small_bytes, sizeof(IntSmall), 0);
   if (st != MR_OK) return st;
   IntSmall* sm = static_cast<IntSmall*>(job->int_small);
 
@@ -1030,7 +1227,7 @@ mr_status run_u32(mr_job* job, mr_map_kind kind, mr_reduce_op op, const void* d_
   L.G = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)job->n_cu * 2, (n + 1023) / 1024));
 
   auto scratch = [&](uint64_t bytes_needed) -> mr_status {
-    return int_ensure(job, &job->int_scratch, &job->int_scratch_bytes, bytes_needed, 1, -1);
+    return int_ensure(job, kRegScratch, &job->int_scratch, &job->int_scratch_bytes, bytes_needed, -1);
   };
   uint32_t retries = 0;
   uint64_t table_cap = 0;
@@ -1047,30 +1244,20 @@ mr_status run_u32(mr_job* job, mr_map_kind kind, mr_reduce_op op, const void* d_
 
   if (strat == MR_STRAT_LDS_ARRAY || strat == MR_STRAT_GLOBAL_ARRAY) {
     // counts [R] then, 8-byte aligned, values [R]: 12 bytes per key plus alignment
-    st = int_ensure(job, &job->int_dense, &job->int_dense_R, key_range, 12, 0);
-
+    // a new region (or a larger R) starts all zero; the output pass clears what it reads
+    bool dense_fresh = false;
+    st = int_ensure(job, kRegDense, &job->int_dense, &job->int_dense_bytes, key_range * 12 + 8, 0, &dense_fresh);
     if (st != MR_OK) return st;
+    // the layout's R: a kept region was laid out for an R at least this large
+    if (dense_fresh) job->int_dense_R = key_range;
     L.dcnt = static_cast<uint32_t*>(job->int_dense);
     L.dval = static_cast<uint8_t*>(job->int_dense) + ((4 * job->int_dense_R + 7) & ~7ull);
-    const uint64_t nb = (key_range + 2047) / 2048;
-    Carve c;
-    const uint64_t o_blk = c.take(4 * (nb + 1));
-    uint64_t o_cp = 0, o_vp = 0;
-    if (strat == MR_STRAT_LDS_ARRAY) {
-      o_cp = c.take(4ull * L.G * key_range);
-      o_vp = c.take((o == 1 ? 8ull : 4ull) * L.G * key_range);
-    }
-    // a large array counted by key-range partitions instead of atomics
-    const PartPlan pp = part_plan(n, key_range);
-    const bool parts = strat == MR_STRAT_GLOBAL_ARRAY && o == MR_REDUCE_COUNT && pp.usable;
-    uint64_t o_ph = 0, o_ps = 0, o_pt = 0, o_pk = 0;
-    if (parts) {
-      o_ph = c.take(4 * pp.H);
-      o_ps = c.take(4ull * pp.sb + 4);
-      o_pt = c.take(8);
-      o_pk = c.take(2 * n);
-    }
-    st = scratch(c.off);
+    const DenseCarve dc = dense_carve(strat, n, key_range, o, L.G);
+    const PartPlan& pp = dc.pp;
+    const bool parts = dc.parts;
+    const uint64_t o_blk = dc.o_blk, o_cp = dc.o_cp, o_vp = dc.o_vp, o_ph = dc.o_ph, o_ps = dc.o_ps, o_pt = dc.o_pt,
+                   o_pk = dc.o_pk;
+    st = scratch(dc.bytes);
     if (st != MR_OK) return st;
     uint8_t* sc = static_cast<uint8_t*>(job->int_scratch);
     L.blk = reinterpret_cast<uint32_t*>(sc + o_blk);
@@ -1090,23 +1277,20 @@ mr_status run_u32(mr_job* job, mr_map_kind kind, mr_reduce_op op, const void* d_
     MR_HIP(int_enqueue_dense_out(L, true, job->stream));
   } else if (strat == MR_STRAT_HASH) {
     // capacity: distinct <= min(n, range); start from the last job's distinct count when larger inputs repeat
-    const uint64_t bound = std::max<uint64_t>(1, key_range ? std::min<uint64_t>(n, key_range) : n);
-    const double lf = eff_load_pct(job, kind, bytes) / 100.0;
-    table_cap = job->cfg.table_slots ? job->cfg.table_slots
-                                     : std::max<uint64_t>(4096, next_pow2((uint64_t)std::ceil(std::min<uint64_t>(bound, 1ull << 24) / lf)));
+    table_cap = int_table_slots(job, kind, bytes, n, key_range);
     for (;;) {
-      if (table_cap > job->int_table_cap) {
-        // keys start as 0xFFFFFFFF, counts and values as 0
-        MR_HIP(hipStreamSynchronize(job->stream));
-        if (job->int_table) MR_HIP(hipFree(job->int_table));
-        job->int_table = nullptr;
-        job->int_table_cap = 0;
-        const uint64_t bytes_t = table_cap * (4 + 4 + 8 + 4);
-        hipError_t e = hipMalloc(&job->int_table, bytes_t);
-        if (e != hipSuccess) return fail(MR_ERR_HIP, "hipMalloc(table): %s", hipGetErrorString(e));
-        job->int_table_cap = table_cap;
-        MR_HIP(hipMemsetAsync(job->int_table, 0xFF, table_cap * 4, job->stream));
-        MR_HIP(hipMemsetAsync(static_cast<uint8_t*>(job->int_table) + table_cap * 4, 0, table_cap * 16, job->stream));
+      {
+        // a new table region is laid out for table_cap slots: keys start as
+        // 0xFFFFFFFF, counts and values as 0 (a kept one is clean as a whole)
+        bool fresh = false;
+        st = dev_region(job, kRegTable, &job->int_table, &job->int_table_bytes, table_cap * kIntSlotBytes,
+                        table_cap * kIntSlotBytes, &fresh);
+        if (st != MR_OK) return st;
+        if (fresh) {
+          job->int_table_cap = table_cap;
+          MR_HIP(hipMemsetAsync(job->int_table, 0xFF, table_cap * 4, job->stream));
+          MR_HIP(hipMemsetAsync(static_cast<uint8_t*>(job->int_table) + table_cap * 4, 0, table_cap * 16, job->stream));
+        }
       }
       uint8_t* tb = static_cast<uint8_t*>(job->int_table);
       const uint64_t C = job->int_table_cap;
@@ -1123,14 +1307,10 @@ mr_status run_u32(mr_job* job, mr_map_kind kind, mr_reduce_op op, const void* d_
       MR_HIP(hipStreamSynchronize(job->stream));
       const uint64_t nc = hs.n_claimed;
       // records and sort scratch for nc keys
-      const uint64_t tiles = (nc + 2047) / 2048;
-      const uint64_t hn = 256 * std::max<uint64_t>(tiles, 1);
-      Carve c;
-      const uint64_t o_rk32 = c.take(4 * (nc + 1));
-      const uint64_t o_rk0 = c.take(8 * (nc + 1)), o_rv0 = c.take(8 * (nc + 1));
-      const uint64_t o_rk1 = c.take(8 * (nc + 1)), o_rv1 = c.take(8 * (nc + 1));
-      const uint64_t o_hist = c.take(4 * hn), o_ss = c.take(4 * (hn / 4096 + 2));
-      st = scratch(c.off);
+      const HashCarve hc = hash_carve(nc);
+      const uint64_t o_rk32 = hc.o_rk32, o_rk0 = hc.o_rk0, o_rv0 = hc.o_rv0, o_rk1 = hc.o_rk1, o_rv1 = hc.o_rv1,
+                     o_hist = hc.o_hist, o_ss = hc.o_ss;
+      st = scratch(hc.bytes);
       if (st != MR_OK) return st;
       uint8_t* sc = static_cast<uint8_t*>(job->int_scratch);
       L.rk32 = reinterpret_cast<uint32_t*>(sc + o_rk32);
@@ -1151,15 +1331,10 @@ mr_status run_u32(mr_job* job, mr_map_kind kind, mr_reduce_op op, const void* d_
       break;
     }
   } else {  // SORT
-    const uint64_t tiles = (n + 2047) / 2048;
-    const uint64_t hn = 256 * std::max<uint64_t>(tiles, 1);
-    Carve c;
-    const uint64_t o_rk0 = c.take(8 * (n + 1)), o_rv0 = c.take(8 * (n + 1));
-    const uint64_t o_rk1 = c.take(8 * (n + 1)), o_rv1 = c.take(8 * (n + 1));
-    const uint64_t o_hist = c.take(4 * hn), o_ss = c.take(4 * (std::max(hn, n) / 4096 + 2));
-    const uint64_t o_head = c.take(4 * (n + 1)), o_pos = c.take(4 * (n + 1)), o_hpos = c.take(4 * (n + 2));
-    const uint64_t o_ps = c.take(8 * (n / 4096 + 2));
-    st = scratch(c.off);
+    const SortCarve sc_ = sort_carve(n);
+    const uint64_t o_rk0 = sc_.o_rk0, o_rv0 = sc_.o_rv0, o_rk1 = sc_.o_rk1, o_rv1 = sc_.o_rv1, o_hist = sc_.o_hist,
+                   o_ss = sc_.o_ss, o_head = sc_.o_head, o_pos = sc_.o_pos, o_hpos = sc_.o_hpos, o_ps = sc_.o_ps;
+    st = scratch(sc_.bytes);
     if (st != MR_OK) return st;
     uint8_t* sc = static_cast<uint8_t*>(job->int_scratch);
     L.rk0 = reinterpret_cast<unsigned long long*>(sc + o_rk0);
@@ -1198,15 +1373,44 @@ mr_status run_u32(mr_job* job, mr_map_kind kind, mr_reduce_op op, const void* d_
 }
 
 
+// k-means scratch: centroid norms, the float64 re-check bound, the re-check
+// and tiny-coordinate counters, per-workgroup float64 sums and counts.
+struct KmCarve {
+  uint64_t o_cn, o_cmax, o_nr, o_ps, o_pc, bytes;
+};
+KmCarve km_carve(uint32_t k, uint32_t d, uint32_t G) {
+  KmCarve r;
+  Carve c;
+  r.o_cn = c.take(4ull * k);
+  r.o_cmax = c.take(8);
+  r.o_nr = c.take(16);
+  r.o_ps = c.take(8ull * G * k * d);
+  r.o_pc = c.take(4ull * G * k);
+  r.bytes = c.off;
+  return r;
+}
+uint32_t km_grid(uint64_t N, int n_cu, bool mfma) {
+  return mfma ? (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)n_cu * 3, (N + 127) / 128)) : 1u;
+}
+
 mr_status run_kmeans(mr_job* job, const void* d_input, uint64_t bytes, mr_output* out) {
   const uint32_t k = job->cfg.km_k, d = job->cfg.km_d;
-  if (!job->km_c || !k || !d) return fail(MR_ERR_INVALID_ARG, "the job was created without k-means centroids");
+  if (job->km_host.empty() || !k || !d) return fail(MR_ERR_INVALID_ARG, "the job was created without k-means centroids");
   if (bytes % (4ull * d)) return fail(MR_ERR_INVALID_ARG, "input length is not a multiple of 4 * d");
   const uint64_t N = bytes / (4ull * d);
   if (N >= (1ull << 31)) return fail(MR_ERR_UNSUPPORTED, "k-means inputs must have fewer than 2^31 points");
   if ((N && !out->assign) || !out->sums || !out->counts || !out->centroids)
     return fail(MR_ERR_INVALID_ARG, "k-means needs assign, sums, counts and centroids outputs");
   if ((uintptr_t)d_input % 4) return fail(MR_ERR_INVALID_ARG, "points must be 4-byte aligned");
+  {
+    bool fresh = false;
+    void* p = job->km_c;
+    const uint64_t cb = sizeof(float) * job->km_host.size();
+    mr_status st = dev_region(job, kRegKmC, &p, &job->km_c_bytes, cb, cb, &fresh);
+    if (st != MR_OK) return st;
+    job->km_c = static_cast<float*>(p);
+    if (fresh) MR_HIP(hipMemcpyAsync(job->km_c, job->km_host.data(), cb, hipMemcpyHostToDevice, job->stream));
+  }
   KmLaunch L{};
   L.X = static_cast<const float*>(d_input);
   L.N = N;
@@ -1214,11 +1418,10 @@ mr_status run_kmeans(mr_job* job, const void* d_input, uint64_t bytes, mr_output
   L.k = k;
   L.d = d;
   L.mfma = d == 32 && k == 64 && (uintptr_t)d_input % 16 == 0;
-  L.G = L.mfma ? (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)job->n_cu * 3, (N + 127) / 128)) : 1u;
-  Carve c;
-  const uint64_t o_cn = c.take(4ull * k), o_cmax = c.take(8), o_nr = c.take(16);  // rechecks, tiny flag
-  const uint64_t o_ps = c.take(8ull * L.G * k * d), o_pc = c.take(4ull * L.G * k);
-  mr_status st = ensure_ws(job, c.off);
+  L.G = km_grid(N, job->n_cu, L.mfma);
+  const KmCarve kc = km_carve(k, d, L.G);
+  const uint64_t o_cn = kc.o_cn, o_cmax = kc.o_cmax, o_nr = kc.o_nr, o_ps = kc.o_ps, o_pc = kc.o_pc;
+  mr_status st = ensure_ws(job, kc.bytes);
   if (st != MR_OK) return st;
   job->table_clean_bytes = 0;  // this scratch overwrites the word table region
   job->graph_valid = false;
@@ -1259,6 +1462,21 @@ mr_status run_kmeans(mr_job* job, const void* d_input, uint64_t bytes, mr_output
   return MR_OK;
 }
 
+// Bloom filter scratch: per (range, tile) counts, their scan, the total, the positions.
+struct BloomCarve {
+  uint64_t o_hist, o_sums, o_tot, o_part, bytes;
+};
+BloomCarve bloom_carve(const BloomPlan& b) {
+  BloomCarve r;
+  Carve c;
+  r.o_hist = c.take(4ull * std::max<uint64_t>(b.H, 1));
+  r.o_sums = c.take(4ull * scan_sums_count(b.H));
+  r.o_tot = c.take(8);
+  r.o_part = c.take(4ull * b.part_words);
+  r.bytes = c.off;
+  return r;
+}
+
 mr_status run_bloom(mr_job* job, mr_reduce_op op, const void* d_input, uint64_t bytes, uint64_t m, mr_output* out) {
   if (op != MR_REDUCE_COUNT) return fail(MR_ERR_UNSUPPORTED, "the Bloom filter takes MR_REDUCE_COUNT (bitwise OR)");
   const uint32_t k = job->cfg.bloom_k ? job->cfg.bloom_k : 20u;
@@ -1273,10 +1491,9 @@ mr_status run_bloom(mr_job* job, mr_reduce_op op, const void* d_input, uint64_t 
   if (!out->values) return fail(MR_ERR_INVALID_ARG, "the Bloom filter needs values (uint32 words)");
   if (out->cap_keys < b.n_words)
     return fail(MR_ERR_CAPACITY, "the Bloom filter needs %llu words", (unsigned long long)b.n_words);
-  Carve c;
-  const uint64_t o_hist = c.take(4ull * std::max<uint64_t>(b.H, 1)), o_sums = c.take(4ull * scan_sums_count(b.H));
-  const uint64_t o_tot = c.take(8), o_part = c.take(4ull * b.part_words);
-  mr_status st = ensure_ws(job, c.off);
+  const BloomCarve bc = bloom_carve(b);
+  const uint64_t o_hist = bc.o_hist, o_sums = bc.o_sums, o_tot = bc.o_tot, o_part = bc.o_part;
+  mr_status st = ensure_ws(job, bc.bytes);
   if (st != MR_OK) return st;
   job->table_clean_bytes = 0;  // this scratch overwrites the word table region
   job->graph_valid = false;
@@ -1310,6 +1527,14 @@ extern "C" mr_status mr_run(mr_job* job, mr_map_kind kind, mr_reduce_op op, cons
   ScopedDevice sd(job->device);
   out->stats = mr_stats{};
   out->status = MR_OK;
+  switch (kind) {
+    case MR_MAP_WORDS: arena_begin(job, kFamWords); break;
+    case MR_MAP_RGB_HIST: arena_begin(job, kFamRgb); break;
+    case MR_MAP_KMEANS: arena_begin(job, kFamKmeans); break;
+    case MR_MAP_BLOOM: arena_begin(job, kFamBloom); break;
+    case MR_MAP_LINKS: arena_begin(job, kFamLinks); break;
+    default: arena_begin(job, kFamU32); break;
+  }
   mr_status s;
   switch (kind) {
     case MR_MAP_WORDS: {
@@ -1339,6 +1564,8 @@ extern "C" mr_status mr_run(mr_job* job, mr_map_kind kind, mr_reduce_op op, cons
     default:
       return fail(MR_ERR_INVALID_ARG, "unknown map kind %d", (int)kind);
   }
+  out->stats.device_allocs = job->call_allocs;
+  out->stats.workspace_needed = job->cws_need;
   out->status = s;
   return s;
 }
@@ -1356,6 +1583,127 @@ extern "C" mr_status mr_rgb_hist_static(mr_job* job, const void* d_input, uint64
   const hipError_t e = rgb_static_enqueue(job->device, static_cast<const uint8_t*>(d_input), input_bytes, G,
                                           reinterpret_cast<unsigned long long*>(d_bins), job->stream);
   if (e != hipSuccess) return fail(MR_ERR_HIP, "mr_rgb_hist_static: %s", hipGetErrorString(e));
+  return MR_OK;
+}
+
+namespace {
+
+// Bytes of a sequence of regions carved as dev_region carves a caller workspace.
+struct RegionSum {
+  uint64_t off = 0;
+  void add(uint64_t bytes) { off = align_up(off, 256) + bytes; }
+};
+
+}  // namespace
+
+extern "C" mr_status mr_workspace_bytes(const mr_job_config* cfg, mr_map_kind kind, uint64_t n, uint64_t key_range,
+                                        uint64_t* out_bytes) {
+  if (!cfg || !out_bytes) return fail(MR_ERR_INVALID_ARG, "NULL argument");
+  int n_dev = 0;
+  if (hipGetDeviceCount(&n_dev) != hipSuccess || n_dev <= 0) return fail(MR_ERR_NO_DEVICE, "no HIP device");
+  if (cfg->device < 0 || cfg->device >= n_dev) return fail(MR_ERR_INVALID_ARG, "device %d out of range", cfg->device);
+  int n_cu = 0;
+  if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, cfg->device) != hipSuccess || n_cu <= 0)
+    return fail(MR_ERR_NO_DEVICE, "device query failed");
+  // a job with these settings (no device state) for the planning functions
+  mr_job tmp;
+  tmp.cfg = *cfg;
+  tmp.n_cu = n_cu;
+  RegionSum r;
+  switch (kind) {
+    case MR_MAP_WORDS: {
+      // the input's alignment may add a 16-byte chunk: plan at the worst one
+      std::vector<WordItem> items(1);
+      items[0] = WordItem{reinterpret_cast<const uint8_t*>(15), n, nullptr, 0, nullptr, initial_slots(&tmp, n, n)};
+      const uint64_t grid_cap = std::max<uint64_t>(1, (uint64_t)n_cu * eff_grid_pct(&tmp, n) / 100);
+      r.add(plan_words(items, false, flush_queue_cap(n, n_cu), grid_cap).c.off);
+      break;
+    }
+    case MR_MAP_RGB_HIST:
+      r.add(4ull * 768 * rgb_grid(n, n_cu));
+      break;
+    case MR_MAP_KMEANS: {
+      if (!cfg->km_k || !cfg->km_d) return fail(MR_ERR_INVALID_ARG, "k-means needs km_k and km_d");
+      const uint64_t N = n / (4ull * cfg->km_d);
+      r.add(4ull * cfg->km_k * cfg->km_d);
+      r.add(km_carve(cfg->km_k, cfg->km_d, km_grid(N, n_cu, cfg->km_d == 32 && cfg->km_k == 64)).bytes);
+      break;
+    }
+    case MR_MAP_BLOOM: {
+      const uint32_t k = cfg->bloom_k ? cfg->bloom_k : 20u, h = cfg->bloom_hashes ? cfg->bloom_hashes : 7u;
+      if (!key_range || key_range > (1ull << 29) || k > 32 || h > 8)
+        return fail(MR_ERR_INVALID_ARG, "the Bloom filter needs 1 <= key_range <= 2^29 bits, k <= 32, hashes <= 8");
+      const BloomPlan b = bloom_plan(n, k, h, key_range);
+      r.add(bloom_carve(b).bytes);
+      break;
+    }
+    case MR_MAP_U32_KEYS:
+    case MR_MAP_U32_KV: {
+      const uint32_t esz = kind == MR_MAP_U32_KV ? 8 : 4;
+      const uint64_t ne = n / esz;
+      // pairs are planned for SUM (the widest values), keys for COUNT
+      const uint32_t op = kind == MR_MAP_U32_KV ? (uint32_t)MR_REDUCE_SUM : (uint32_t)MR_REDUCE_COUNT;
+      const uint32_t G = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)n_cu * 2, (ne + 1023) / 1024));
+      r.add(sizeof(IntSmall));
+      std::vector<mr_strategy> cand;
+      if (cfg->strategy == MR_STRAT_LEARNED) {
+        r.add(4 * sel_floats());
+        for (mr_strategy c : {MR_STRAT_LDS_ARRAY, MR_STRAT_GLOBAL_ARRAY, MR_STRAT_HASH, MR_STRAT_SORT})
+          if (int_feasible(c, key_range, op)) cand.push_back(c);
+      } else if (cfg->strategy == MR_STRAT_RULE) {
+        cand.push_back(rule_strategy(key_range, op, eff_lds_array_bytes(&tmp, kind, n)));
+      } else {
+        cand.push_back(cfg->strategy);
+      }
+      uint64_t worst = 0;
+      for (mr_strategy c : cand) {
+        RegionSum t = r;
+        if (c == MR_STRAT_LDS_ARRAY || c == MR_STRAT_GLOBAL_ARRAY) {
+          t.add(key_range * 12 + 8);
+          t.add(dense_carve(c, ne, key_range, op, G).bytes);
+        } else if (c == MR_STRAT_HASH) {
+          t.add(int_table_slots(&tmp, kind, n, ne, key_range) * kIntSlotBytes);
+          t.add(hash_carve(key_range ? std::min(ne, key_range) : ne).bytes);
+        } else {
+          t.add(sort_carve(ne).bytes);
+        }
+        worst = std::max(worst, t.off);
+      }
+      r.off = worst;
+      break;
+    }
+    case MR_MAP_LINKS: {
+      const uint64_t cap = std::max<uint64_t>(4096, n / 512);
+      Carve c;
+      c.take(8);
+      c.take(4 * cap);
+      c.take(4 * cap);
+      c.take(4 * cap);
+      r.add(c.off);
+      std::vector<WordItem> items(1);
+      items[0] = WordItem{reinterpret_cast<const uint8_t*>(15), n, nullptr, 0, nullptr, initial_slots(&tmp, n, n)};
+      const uint64_t grid_cap = std::max<uint64_t>(1, (uint64_t)n_cu * eff_grid_pct(&tmp, n) / 100);
+      r.add(plan_words(items, true, 0, grid_cap).c.off);
+      // the file-list pass: at most one pair and one URL per marker
+      const uint64_t hw = links_hist_words(cap);
+      c.take(8 * cap);
+      c.take(8 * cap);
+      c.take(8 * cap);
+      c.take(8 * cap);
+      c.take(4 * std::max<uint64_t>(hw, 1));
+      c.take(4 * std::max(scan_sums_count(hw), scan_sums_count(cap)));
+      c.take(4 * cap);
+      c.take(8);
+      c.take(8);
+      c.take(8);
+      c.take(4 * (cap + 1));
+      r.add(c.off);
+      break;
+    }
+    default:
+      return fail(MR_ERR_INVALID_ARG, "unknown map kind %d", (int)kind);
+  }
+  *out_bytes = r.off;
   return MR_OK;
 }
 
@@ -1388,7 +1736,13 @@ extern "C" mr_status mr_batch_run(mr_job* job, const mr_batch_item* items, uint3
                     items[i].n_records, &outs[i], 0};
   }
   std::vector<mr_status> per(n_items, MR_OK);
-  return run_words(job, w, &per, GraphMode::kAlways);
+  arena_begin(job, kFamWords);
+  const mr_status st = run_words(job, w, &per, GraphMode::kAlways);
+  for (uint32_t i = 0; i < n_items; ++i) {
+    outs[i].stats.device_allocs = job->call_allocs;
+    outs[i].stats.workspace_needed = job->cws_need;
+  }
+  return st;
 }
 
 // ----------------------------------------------------------------------------
@@ -1407,7 +1761,28 @@ constexpr uint64_t kSelState = (kSelParams + MR_MLP_PARAMS + 63) / 64 * 64;  // 
 uint64_t sel_floats() { return kSelState + (feature_state_bytes() + 3) / 4; }
 
 mr_status sel_scratch(mr_job* job, uint64_t floats) {
-  return int_ensure(job, &job->sel_dev, &job->sel_dev_floats, floats, 4, -1);
+  bool fresh = false;
+  mr_status st = int_ensure(job, kRegSel, &job->sel_dev, &job->sel_dev_bytes, 4 * floats, -1, &fresh);
+  if (st != MR_OK) return st;
+  if (fresh) job->sel_uploaded = false;
+  return MR_OK;
+}
+
+// The selector region, with the loaded weights and normalisation in it.
+mr_status sel_upload(mr_job* job) {
+  mr_status st = sel_scratch(job, sel_floats());
+  if (st != MR_OK) return st;
+  if (!job->sel_loaded || job->sel_uploaded) return MR_OK;
+  float* dv = static_cast<float*>(job->sel_dev);
+  MR_HIP(hipMemcpyAsync(dv + kSelParams, job->sel_params.data(), 4 * MR_MLP_PARAMS, hipMemcpyHostToDevice, job->stream));
+  MR_HIP(hipMemcpyAsync(dv + kSelNorm, job->sel_mean.data(), 4 * MR_N_FEATURES, hipMemcpyHostToDevice, job->stream));
+  MR_HIP(hipMemcpyAsync(dv + kSelNorm + 16, job->sel_scale.data(), 4 * MR_N_FEATURES, hipMemcpyHostToDevice, job->stream));
+  MR_HIP(hipMemcpyAsync(dv + kSelNorm + 32, job->sel_lo.data(), 4 * MR_N_FEATURES, hipMemcpyHostToDevice, job->stream));
+  MR_HIP(hipMemcpyAsync(dv + kSelNorm + 48, job->sel_hi.data(), 4 * MR_N_FEATURES, hipMemcpyHostToDevice, job->stream));
+  // the host vectors stay unchanged until the copies are done: the next
+  // change of them (mr_selector_set) synchronises the stream first
+  job->sel_uploaded = true;
+  return MR_OK;
 }
 
 int feature_kind(mr_map_kind kind) {
@@ -1428,6 +1803,7 @@ extern "C" mr_status mr_job_features(mr_job* job, mr_map_kind kind, mr_reduce_op
   if (fk < 0) return fail(MR_ERR_UNSUPPORTED, "features exist for word and integer-key jobs");
   if (fk > 0 && (uintptr_t)d_input % 4) return fail(MR_ERR_INVALID_ARG, "integer input must be 4-byte aligned");
   ScopedDevice sd(job->device);
+  arena_begin(job, kFamFeatures);
   mr_status st = sel_scratch(job, sel_floats());
   if (st != MR_OK) return st;
   float* d = static_cast<float*>(job->sel_dev);
@@ -1449,22 +1825,138 @@ extern "C" mr_status mr_selector_set(mr_job* job, const float* params, const flo
   for (int i = 0; i < MR_N_FEATURES; ++i)
     if (!(feat_scale[i] > 0.f)) return fail(MR_ERR_INVALID_ARG, "feature scale %d must be positive", i);
   ScopedDevice sd(job->device);
+  MR_HIP(hipStreamSynchronize(job->stream));  // no copy of the previous weights is still reading them
   job->sel_params.assign(params, params + MR_MLP_PARAMS);
   job->sel_mean.assign(feat_mean, feat_mean + MR_N_FEATURES);
   job->sel_scale.assign(feat_scale, feat_scale + MR_N_FEATURES);
   job->sel_lo.assign(feat_lo, feat_lo + MR_N_FEATURES);
   job->sel_hi.assign(feat_hi, feat_hi + MR_N_FEATURES);
-  mr_status st = sel_scratch(job, sel_floats());
-  if (st != MR_OK) return st;
-  float* dv = static_cast<float*>(job->sel_dev);
-  MR_HIP(hipMemcpyAsync(dv + kSelParams, params, 4 * MR_MLP_PARAMS, hipMemcpyHostToDevice, job->stream));
-  MR_HIP(hipMemcpyAsync(dv + kSelNorm, feat_mean, 4 * MR_N_FEATURES, hipMemcpyHostToDevice, job->stream));
-  MR_HIP(hipMemcpyAsync(dv + kSelNorm + 16, feat_scale, 4 * MR_N_FEATURES, hipMemcpyHostToDevice, job->stream));
-  MR_HIP(hipMemcpyAsync(dv + kSelNorm + 32, feat_lo, 4 * MR_N_FEATURES, hipMemcpyHostToDevice, job->stream));
-  MR_HIP(hipMemcpyAsync(dv + kSelNorm + 48, feat_hi, 4 * MR_N_FEATURES, hipMemcpyHostToDevice, job->stream));
-  MR_HIP(hipStreamSynchronize(job->stream));
   job->sel_loaded = true;
+  job->sel_uploaded = false;  // copied to the device by the first call that uses them
   return MR_OK;
+}
+
+namespace {
+
+// Top-level members of a JSON object whose values are numbers or arrays of
+// numbers (other members are parsed and skipped). Enough for the selector
+// weights file; returns false on malformed text.
+struct JsonNumbers {
+  const char* p;
+  const char* end;
+  std::unordered_map<std::string, std::vector<double>> arrays;
+  void ws() {
+    while (p < end && (*p == ' ' || *p == '\n' || *p == '\r' || *p == '\t')) ++p;
+  }
+  bool str(std::string* out) {
+    if (p >= end || *p != '"') return false;
+    ++p;
+    while (p < end && *p != '"') {
+      if (*p == '\\') {
+        if (++p >= end) return false;
+      }
+      if (out) out->push_back(*p);
+      ++p;
+    }
+    if (p >= end) return false;
+    ++p;
+    return true;
+  }
+  bool number(double* v) {
+    char* e = nullptr;
+    const double x = std::strtod(p, &e);
+    if (e == p || e > end) return false;
+    p = e;
+    if (v) *v = x;
+    return true;
+  }
+  bool value(std::vector<double>* nums, int depth) {
+    ws();
+    if (p >= end || depth > 64) return false;
+    if (*p == '{') {
+      ++p;
+      ws();
+      if (p < end && *p == '}') return ++p, true;
+      for (;;) {
+        ws();
+        std::string key;
+        if (!str(&key)) return false;
+        ws();
+        if (p >= end || *p != ':') return false;
+        ++p;
+        std::vector<double> v;
+        const bool top = depth == 0;
+        if (!value(top ? &v : nullptr, depth + 1)) return false;
+        if (top && !v.empty()) arrays[key] = std::move(v);
+        ws();
+        if (p < end && *p == ',') { ++p; continue; }
+        if (p < end && *p == '}') return ++p, true;
+        return false;
+      }
+    }
+    if (*p == '[') {
+      ++p;
+      ws();
+      if (p < end && *p == ']') return ++p, true;
+      for (;;) {
+        ws();
+        if (p < end && (*p == '-' || (*p >= '0' && *p <= '9'))) {
+          double x;
+          if (!number(&x)) return false;
+          if (nums) nums->push_back(x);
+        } else if (!value(nullptr, depth + 1)) {
+          return false;
+        } else if (nums) {
+          nums = nullptr;  // not an array of numbers: not kept
+        }
+        ws();
+        if (p < end && *p == ',') { ++p; continue; }
+        if (p < end && *p == ']') return ++p, true;
+        return false;
+      }
+    }
+    if (*p == '"') return str(nullptr);
+    if (*p == '-' || (*p >= '0' && *p <= '9')) {
+      double x;
+      if (!number(&x)) return false;
+      if (nums) nums->push_back(x);
+      return true;
+    }
+    for (const char* w : {"true", "false", "null"}) {
+      const size_t n = std::strlen(w);
+      if ((size_t)(end - p) >= n && std::strncmp(p, w, n) == 0) return p += n, true;
+    }
+    return false;
+  }
+};
+
+}  // namespace
+
+extern "C" mr_status mr_selector_load(mr_job* job, const char* path) {
+  if (!job || !path) return fail(MR_ERR_INVALID_ARG, "NULL argument");
+  FILE* f = std::fopen(path, "rb");
+  if (!f) return fail(MR_ERR_INVALID_ARG, "cannot open selector weights %s", path);
+  std::string text;
+  char buf[65536];
+  size_t got;
+  while ((got = std::fread(buf, 1, sizeof buf, f)) > 0) text.append(buf, got);
+  std::fclose(f);
+  JsonNumbers j{text.c_str(), text.c_str() + text.size(), {}};
+  if (!j.value(nullptr, 0)) return fail(MR_ERR_INVALID_ARG, "selector weights %s: malformed JSON", path);
+  struct Need {
+    const char* key;
+    size_t n;
+  };
+  const Need need[] = {{"params", MR_MLP_PARAMS}, {"feat_mean", MR_N_FEATURES}, {"feat_scale", MR_N_FEATURES},
+                       {"feat_lo", MR_N_FEATURES}, {"feat_hi", MR_N_FEATURES}};
+  std::vector<float> a[5];
+  for (int i = 0; i < 5; ++i) {
+    auto it = j.arrays.find(need[i].key);
+    if (it == j.arrays.end() || it->second.size() != need[i].n)
+      return fail(MR_ERR_INVALID_ARG, "selector weights %s: \"%s\" must be %zu numbers", path, need[i].key, need[i].n);
+    a[i].assign(it->second.begin(), it->second.end());
+  }
+  return mr_selector_set(job, a[0].data(), a[1].data(), a[2].data(), a[3].data(), a[4].data());
 }
 
 // Network output for host features, computed by the forward kernel (batch of one).
@@ -1472,6 +1964,9 @@ extern "C" mr_status mr_selector_predict(mr_job* job, const float* feats, float*
   if (!job || !feats || !pred) return fail(MR_ERR_INVALID_ARG, "NULL argument");
   if (!job->sel_loaded) return fail(MR_ERR_INVALID_ARG, "no selector weights are loaded");
   ScopedDevice sd(job->device);
+  arena_begin(job, kFamPredict);
+  mr_status st = sel_upload(job);
+  if (st != MR_OK) return st;
   float x[16];
   for (int i = 0; i < MR_N_FEATURES; ++i) x[i] = (feats[i] - job->sel_mean[i]) / job->sel_scale[i];
   float* d = static_cast<float*>(job->sel_dev);
@@ -1497,10 +1992,11 @@ mr_status learned_strategy(mr_job* job, mr_map_kind kind, mr_reduce_op op, const
   uint32_t feas = 0;
   for (int i = 0; i < MR_N_STRATS; ++i)
     if (int_feasible(order[i], R, (uint32_t)op)) feas |= 1u << i;
-  uint64_t small_have = job->int_small ? 1 : 0;
-  mr_status st = int_ensure(job, &job->int_small, &small_have, 1, sizeof(IntSmall), 0);
+  mr_status st = int_ensure(job, kRegSmall, &job->int_small, &job->int_small_bytes, sizeof(IntSmall), 0);
   if (st != MR_OK) return st;
   IntSmall* sm = static_cast<IntSmall*>(job->int_small);
+  st = sel_upload(job);
+  if (st != MR_OK) return st;
   float* d = static_cast<float*>(job->sel_dev);
   MR_HIP(features_enqueue(static_cast<const uint8_t*>(d_input), bytes, fk, (int)op, R, (uint32_t)kLdsArrayBudget, d,
                           d + kSelState, job->stream));
@@ -1517,7 +2013,7 @@ mr_status learned_strategy(mr_job* job, mr_map_kind kind, mr_reduce_op op, const
 
 mr_status mlp_scratch(mr_job* job, uint32_t B) {
   const uint64_t need = (uint64_t)B * (4 + 64 + 64) + 64;
-  return int_ensure(job, &job->mlp_dev, &job->mlp_dev_floats, need, 4, -1);
+  return int_ensure(job, kRegMlp, &job->mlp_dev, &job->mlp_dev_bytes, 4 * need, -1);
 }
 
 }  // namespace
@@ -1536,6 +2032,7 @@ extern "C" mr_status mr_mlp_loss_backward(mr_job* job, const float* params, cons
   if (!job || !params || !loss || !grad || (B && (!X || !H1 || !H2 || !Y || !T || !M)))
     return fail(MR_ERR_INVALID_ARG, "NULL argument");
   ScopedDevice sd(job->device);
+  arena_begin(job, kFamMlp);
   mr_status st = mlp_scratch(job, B);
   if (st != MR_OK) return st;
   float* d = static_cast<float*>(job->mlp_dev);
@@ -1552,5 +2049,192 @@ extern "C" mr_status mr_mlp_adam(mr_job* job, float* params, const float* grad, 
   if (step == 0) return fail(MR_ERR_INVALID_ARG, "Adam steps count from 1");
   ScopedDevice sd(job->device);
   MR_HIP(adam_enqueue(params, grad, m, v, step, lr, beta1, beta2, eps, job->stream));
+  return MR_OK;
+}
+
+// ----------------------------------------------------------------------------
+// selector training: the whole loop on the device with the network kernels
+// ----------------------------------------------------------------------------
+
+namespace {
+
+// SplitMix64 (Steele, Lea and Flood, "Fast splittable pseudorandom number
+// generators", 2014): initialisation and shuffling of the training loop.
+struct SplitMix64 {
+  uint64_t x;
+  uint64_t next() {
+    uint64_t z = (x += 0x9E3779B97F4A7C15ULL);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+  }
+  double uniform() { return (next() >> 11) * (1.0 / 9007199254740992.0); }  // [0, 1)
+};
+
+mr_status write_selector_json(const char* path, const std::vector<float>& P, const float* mean, const float* scale,
+                              const float* lo, const float* hi, double mu, double sd) {
+  FILE* f = std::fopen(path, "wb");
+  if (!f) return fail(MR_ERR_INVALID_ARG, "cannot write %s", path);
+  auto arr = [&](const char* name, const float* a, size_t n, bool last) {
+    std::fprintf(f, "\"%s\": [", name);
+    for (size_t i = 0; i < n; ++i) std::fprintf(f, "%s%.9g", i ? ", " : "", (double)a[i]);
+    std::fprintf(f, "]%s", last ? "" : ", ");
+  };
+  std::fprintf(f, "{");
+  arr("params", P.data(), P.size(), false);
+  arr("feat_mean", mean, MR_N_FEATURES, false);
+  arr("feat_scale", scale, MR_N_FEATURES, false);
+  arr("feat_lo", lo, MR_N_FEATURES, false);
+  arr("feat_hi", hi, MR_N_FEATURES, false);
+  std::fprintf(f, "\"target_mu\": %.17g, \"target_sd\": %.17g, "
+                  "\"strategies\": [\"lds_array\", \"global_array\", \"hash\", \"sort\"]}", mu, sd);
+  const bool ok = std::fclose(f) == 0;
+  return ok ? MR_OK : fail(MR_ERR_INVALID_ARG, "writing %s failed", path);
+}
+
+}  // namespace
+
+extern "C" mr_status mr_selector_train(mr_job* job, const float* feats, const float* times, const uint8_t* feasible,
+                                       uint32_t n, const mr_train_config* tc, float* loss_out, const char* out_json) {
+  if (!job || !feats || !times || !feasible || !tc || n == 0) return fail(MR_ERR_INVALID_ARG, "NULL argument or no jobs");
+  const uint32_t epochs = tc->epochs ? tc->epochs : 500, B = tc->batch ? tc->batch : 64;
+  const float lr = tc->lr > 0.f ? tc->lr : 1e-3f, b1 = tc->beta1 > 0.f ? tc->beta1 : 0.9f;
+  const float b2 = tc->beta2 > 0.f ? tc->beta2 : 0.999f, eps = tc->eps > 0.f ? tc->eps : 1e-8f;
+  if (B > 4096 || b1 >= 1.f || b2 >= 1.f) return fail(MR_ERR_INVALID_ARG, "batch above 4096 or a beta not below 1");
+  const uint32_t F = MR_N_FEATURES, S = MR_N_STRATS;
+  // feature normalisation: mean and standard deviation (a constant feature keeps scale 1)
+  std::vector<double> mean(F, 0.0), var(F, 0.0);
+  for (uint32_t i = 0; i < n; ++i)
+    for (uint32_t f = 0; f < F; ++f) mean[f] += feats[(size_t)i * F + f];
+  for (uint32_t f = 0; f < F; ++f) mean[f] /= n;
+  for (uint32_t i = 0; i < n; ++i)
+    for (uint32_t f = 0; f < F; ++f) {
+      const double dlt = feats[(size_t)i * F + f] - mean[f];
+      var[f] += dlt * dlt;
+    }
+  std::vector<float> fmean(F), fscale(F), flo(F), fhi(F);
+  for (uint32_t f = 0; f < F; ++f) {
+    fmean[f] = (float)mean[f];
+    const double sdv = std::sqrt(var[f] / n);
+    fscale[f] = sdv < 1e-6 ? 1.f : (float)sdv;
+    double mn = feats[f], mx = feats[f];
+    for (uint32_t i = 1; i < n; ++i) {
+      mn = std::min<double>(mn, feats[(size_t)i * F + f]);
+      mx = std::max<double>(mx, feats[(size_t)i * F + f]);
+    }
+    // the range seen in training, widened by a tenth: outside it the rule decides
+    flo[f] = (float)(mn - 0.1 * (mx - mn) - 1e-3);
+    fhi[f] = (float)(mx + 0.1 * (mx - mn) + 1e-3);
+  }
+  // targets: log device times over the feasible containers, standardised with one mean and scale
+  double mu = 0.0, m2 = 0.0;
+  uint64_t nf = 0;
+  for (uint64_t i = 0; i < (uint64_t)n * S; ++i)
+    if (feasible[i]) {
+      if (!(times[i] > 0.f)) return fail(MR_ERR_INVALID_ARG, "a feasible time is not positive (job %llu)", (unsigned long long)(i / S));
+      mu += std::log((double)times[i]);
+      ++nf;
+    }
+  if (!nf) return fail(MR_ERR_INVALID_ARG, "no feasible container in any job");
+  mu /= nf;
+  for (uint64_t i = 0; i < (uint64_t)n * S; ++i)
+    if (feasible[i]) m2 += (std::log((double)times[i]) - mu) * (std::log((double)times[i]) - mu);
+  double sd = std::sqrt(m2 / nf);
+  if (!(sd > 0.0)) sd = 1.0;
+  // one row per job: normalised features, targets, mask
+  constexpr uint32_t kRow = MR_N_FEATURES + 2 * MR_N_STRATS;
+  std::vector<float> rows((size_t)n * kRow);
+  for (uint32_t i = 0; i < n; ++i) {
+    float* r = &rows[(size_t)i * kRow];
+    for (uint32_t f = 0; f < F; ++f) r[f] = (float)((feats[(size_t)i * F + f] - fmean[f]) / fscale[f]);
+    for (uint32_t k = 0; k < S; ++k) {
+      const bool ok = feasible[(size_t)i * S + k] != 0;
+      r[F + k] = ok ? (float)((std::log((double)times[(size_t)i * S + k]) - mu) / sd) : 0.f;
+      r[F + S + k] = ok ? 1.f : 0.f;
+    }
+  }
+  // He-uniform initialisation: weights U(-sqrt(6 / fan_in), +sqrt(6 / fan_in)), biases 0
+  SplitMix64 rng{tc->seed};
+  std::vector<float> P(MR_MLP_PARAMS, 0.f);
+  {
+    size_t o = 0;
+    const uint32_t dims[4] = {MR_N_FEATURES, 64, 64, MR_N_STRATS};
+    for (int l = 0; l < 3; ++l) {
+      const double lim = std::sqrt(6.0 / dims[l]);
+      for (uint32_t i = 0; i < dims[l] * dims[l + 1]; ++i) P[o++] = (float)((2.0 * rng.uniform() - 1.0) * lim);
+      o += dims[l + 1];
+    }
+  }
+  ScopedDevice sd_(job->device);
+  arena_begin(job, kFamTrain);
+  // device memory: parameters, gradient, moments, the epoch's shuffled rows,
+  // activations and backward scratch of one batch, per-batch losses
+  const uint32_t nb = (n + B - 1) / B;
+  Carve c;
+  const uint64_t o_p = c.take(4ull * MR_MLP_PARAMS), o_g = c.take(4ull * MR_MLP_PARAMS);
+  const uint64_t o_m = c.take(4ull * MR_MLP_PARAMS), o_v = c.take(4ull * MR_MLP_PARAMS);
+  const uint64_t o_x = c.take(4ull * n * F), o_t = c.take(4ull * n * S), o_k = c.take(4ull * n * S);
+  const uint64_t o_h1 = c.take(4ull * B * 64), o_h2 = c.take(4ull * B * 64), o_y = c.take(4ull * B * S);
+  const uint64_t o_dy = c.take(4ull * B * S), o_dz1 = c.take(4ull * B * 64), o_dz2 = c.take(4ull * B * 64);
+  const uint64_t o_loss = c.take(4ull * nb);
+  void* mem = nullptr;
+  uint64_t have = 0;
+  bool fresh = false;
+  mr_status st = dev_region(job, kRegTrain, &mem, &have, c.off, c.off, &fresh);
+  if (st != MR_OK) return st;
+  uint8_t* d = static_cast<uint8_t*>(mem);
+  auto F32 = [&](uint64_t o) { return reinterpret_cast<float*>(d + o); };
+  const hipStream_t s = job->stream;
+  mr_status result = MR_OK;
+  std::vector<float> X((size_t)n * F), T((size_t)n * S), M((size_t)n * S), losses(nb);
+  std::vector<uint32_t> perm(n);
+  for (uint32_t i = 0; i < n; ++i) perm[i] = i;
+  do {
+    hipError_t e = hipMemcpyAsync(F32(o_p), P.data(), 4ull * MR_MLP_PARAMS, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemsetAsync(F32(o_m), 0, 4ull * MR_MLP_PARAMS, s);
+    if (e == hipSuccess) e = hipMemsetAsync(F32(o_v), 0, 4ull * MR_MLP_PARAMS, s);
+    uint32_t step = 0;
+    for (uint32_t ep = 0; ep < epochs && e == hipSuccess; ++ep) {
+      // Fisher-Yates shuffle, then the rows in that order as split arrays
+      for (uint32_t i = n - 1; i > 0; --i) std::swap(perm[i], perm[(uint32_t)(rng.next() % (i + 1))]);
+      for (uint32_t i = 0; i < n; ++i) {
+        const float* r = &rows[(size_t)perm[i] * kRow];
+        std::memcpy(&X[(size_t)i * F], r, 4 * F);
+        std::memcpy(&T[(size_t)i * S], r + F, 4 * S);
+        std::memcpy(&M[(size_t)i * S], r + F + S, 4 * S);
+      }
+      e = hipMemcpyAsync(F32(o_x), X.data(), 4ull * n * F, hipMemcpyHostToDevice, s);
+      if (e == hipSuccess) e = hipMemcpyAsync(F32(o_t), T.data(), 4ull * n * S, hipMemcpyHostToDevice, s);
+      if (e == hipSuccess) e = hipMemcpyAsync(F32(o_k), M.data(), 4ull * n * S, hipMemcpyHostToDevice, s);
+      for (uint32_t b = 0; b < nb && e == hipSuccess; ++b) {
+        const uint32_t i0 = b * B, bs = std::min(B, n - i0);
+        const float* xb = F32(o_x) + (size_t)i0 * F;
+        const float* tb = F32(o_t) + (size_t)i0 * S;
+        const float* mb = F32(o_k) + (size_t)i0 * S;
+        e = mlp_forward_enqueue(F32(o_p), xb, bs, F32(o_h1), F32(o_h2), F32(o_y), s);
+        if (e == hipSuccess)
+          e = mlp_backward_enqueue(F32(o_p), xb, F32(o_h1), F32(o_h2), F32(o_y), tb, mb, bs, F32(o_dy), F32(o_dz1),
+                                   F32(o_dz2), F32(o_loss) + b, F32(o_g), s);
+        if (e == hipSuccess) e = adam_enqueue(F32(o_p), F32(o_g), F32(o_m), F32(o_v), ++step, lr, b1, b2, eps, s);
+      }
+      // the epoch's mean loss (batches weighted by their size); the host
+      // arrays are rewritten only after this synchronisation
+      if (e == hipSuccess) e = hipMemcpyAsync(losses.data(), F32(o_loss), 4ull * nb, hipMemcpyDeviceToHost, s);
+      if (e == hipSuccess) e = hipStreamSynchronize(s);
+      if (e == hipSuccess && loss_out) {
+        double tot = 0.0;
+        for (uint32_t b = 0; b < nb; ++b) tot += (double)losses[b] * std::min(B, n - b * B);
+        loss_out[ep] = (float)(tot / n);
+      }
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(P.data(), F32(o_p), 4ull * MR_MLP_PARAMS, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) result = fail(MR_ERR_HIP, "selector training: %s", hipGetErrorString(e));
+  } while (false);
+  if (job->cws == nullptr) (void)hipFree(mem);  // library memory of this call only
+  if (result != MR_OK) return result;
+  st = mr_selector_set(job, P.data(), fmean.data(), fscale.data(), flo.data(), fhi.data());
+  if (st != MR_OK) return st;
+  if (out_json) return write_selector_json(out_json, P, fmean.data(), fscale.data(), flo.data(), fhi.data(), mu, sd);
   return MR_OK;
 }

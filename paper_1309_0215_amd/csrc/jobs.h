@@ -11,7 +11,6 @@ enum : uint32_t {
   kFlagBadInput = 2u,    // malformed record offsets or a key outside the declared range
   kFlagSpin = 4u,        // a bounded wait expired (never expected)
   kFlagCapacity = 8u,    // an output buffer was too small (sizes still reported)
-  kFlagSortFallback = 16u,
   kFlagInternal = 32u,   // an internal invariant failed (reported as MR_ERR_HIP)
 };
 
@@ -28,7 +27,8 @@ struct JobState {
   uint32_t nb;                     // sort buckets
   uint32_t bucket_base;            // first global bucket of this job
   uint32_t rtile_base;             // first record tile of this job
-  uint32_t pad[2];
+  uint32_t sort_spills;            // sort buckets too large for LDS (sorted in global memory)
+  uint32_t pad;
 };
 
 static_assert(sizeof(JobState) % 8 == 0, "JobState is cleared as 32-bit words");

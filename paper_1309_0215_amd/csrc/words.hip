@@ -1329,7 +1329,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_buckets(const WordJob* __
       if (m <= blockDim.x) reg_bitonic(J, src, a, m);
       else soa_bitonic(J, src, a, m);
     } else {
-      if (threadIdx.x == 0) atomicOr(&J.st->flags, kFlagSortFallback);  // rare: sort the bucket in global memory
+      if (threadIdx.x == 0) atomicAdd(&J.st->sort_spills, 1u);  // rare: sort the bucket in global memory
       bitonic_sort(J, src, m);
     }
     if (!write) continue;

@@ -18,7 +18,6 @@ from __future__ import annotations
 
 import ctypes as C
 import json
-import math
 import os
 import time
 
@@ -161,67 +160,30 @@ def split(specs, n_train: int, seed: int = 0):
     return train, test
 
 
-def he_uniform(seed: int = 0) -> np.ndarray:
-    rng = np.random.default_rng(seed)
-    parts = []
-    for fan_in, fan_out in ((12, 64), (64, 64), (64, 4)):
-        lim = math.sqrt(6.0 / fan_in)
-        parts.append(rng.uniform(-lim, lim, size=fan_out * fan_in))
-        parts.append(np.zeros(fan_out))
-    return np.concatenate(parts).astype(np.float32)
-
-
 def train(torch, X, T, feas, epochs: int = 500, batch: int = 64, lr: float = 1e-3, seed: int = 0, log=None):
-    """Train on the GPU with the library's kernels. Returns (model dict, loss history)."""
+    """Train on the GPU with mr_selector_train (the library runs the whole
+    loop with its forward, backward and Adam kernels). Returns (model dict,
+    mean loss per epoch)."""
+    import tempfile
+
     from . import Job
     job = Job(device=0)
-    lib = job.lib
-    dev = "cuda:0"
-    mean = X.mean(0)
-    scale = X.std(0)
-    scale[scale < 1e-6] = 1.0
-    logt = np.log(np.where(feas, T, 1.0))
-    mu = float(logt[feas].mean())
-    sd = float(logt[feas].std() or 1.0)
-    Y = np.where(feas, (logt - mu) / sd, 0.0).astype(np.float32)
-    M = feas.astype(np.float32)
-    Xn = ((X - mean) / scale).astype(np.float32)
-    n = len(Xn)
-    P = torch.from_numpy(he_uniform(seed)).to(dev)
-    m = torch.zeros_like(P)
-    v = torch.zeros_like(P)
-    G = torch.zeros_like(P)
-    loss = torch.zeros(1, dtype=torch.float32, device=dev)
-    Xd, Yd, Md = (torch.from_numpy(a).to(dev) for a in (Xn, Y, M))
-    H1 = torch.empty(batch, 64, device=dev)
-    H2 = torch.empty(batch, 64, device=dev)
-    Yp = torch.empty(batch, 4, device=dev)
-    rng = np.random.default_rng(seed)
-    step = 0
-    hist = []
-    ptr = lambda t: t.data_ptr()  # noqa: E731
-    for ep in range(epochs):
-        perm = torch.from_numpy(rng.permutation(n)).to(dev)
-        tot = 0.0
-        for b0 in range(0, n, batch):
-            idx = perm[b0:b0 + batch]
-            B = int(idx.numel())
-            xb, yb, mb = Xd[idx].contiguous(), Yd[idx].contiguous(), Md[idx].contiguous()
-            L.check(lib.mr_mlp_forward(job.h, ptr(P), ptr(xb), B, ptr(H1), ptr(H2), ptr(Yp)), "forward")
-            L.check(lib.mr_mlp_loss_backward(job.h, ptr(P), ptr(xb), ptr(H1), ptr(H2), ptr(Yp), ptr(yb), ptr(mb), B,
-                                             ptr(loss), ptr(G)), "backward")
-            step += 1
-            L.check(lib.mr_mlp_adam(job.h, ptr(P), ptr(G), ptr(m), ptr(v), step, lr, 0.9, 0.999, 1e-8), "adam")
-            tot += float(loss.item()) * B
-        hist.append(tot / n)
-        if log and (ep % 100 == 0 or ep == epochs - 1):
-            log(f"epoch {ep}: loss {hist[-1]:.4f}")
-    lo = X.min(0) - 0.1 * (X.max(0) - X.min(0)) - 1e-3
-    hi = X.max(0) + 0.1 * (X.max(0) - X.min(0)) + 1e-3
-    model = {"params": P.cpu().numpy().tolist(), "feat_mean": mean.tolist(), "feat_scale": scale.tolist(),
-             "feat_lo": lo.tolist(), "feat_hi": hi.tolist(), "target_mu": mu, "target_sd": sd,
-             "strategies": STRAT_NAMES}
-    return model, hist
+    cfg = L.TrainConfig(epochs=epochs, batch=batch, lr=lr, beta1=0.9, beta2=0.999, eps=1e-8, seed=seed)
+    Xc = np.ascontiguousarray(X, np.float32)
+    Tc = np.ascontiguousarray(np.where(feas, T, 1.0), np.float32)
+    Fc = np.ascontiguousarray(feas, np.uint8)
+    hist = np.zeros(epochs, np.float32)
+    p = lambda a: a.ctypes.data_as(C.c_void_p)  # noqa: E731
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "selector_weights.json")
+        L.check(job.lib.mr_selector_train(job.h, p(Xc), p(Tc), p(Fc), len(Xc), C.byref(cfg), p(hist), path.encode()),
+                "mr_selector_train")
+        with open(path) as f:
+            model = json.load(f)
+    if log:
+        for ep in list(range(0, epochs, 100)) + [epochs - 1]:
+            log(f"epoch {ep}: loss {hist[ep]:.4f}")
+    return model, hist.tolist()
 
 
 def predict(torch, model, X) -> np.ndarray:

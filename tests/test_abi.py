@@ -52,16 +52,19 @@ def test_null_arguments_are_rejected_without_a_gpu():
     assert lib.mr_run(None, 0, 0, None, 0, None, 0, 0, None) == L.MR_ERR_INVALID_ARG
     assert b"NULL" in lib.mr_last_error()
     assert lib.mr_job_destroy(None) == L.MR_OK
+    assert lib.mr_workspace_bytes(None, 0, 0, 0, None) == L.MR_ERR_INVALID_ARG
+    assert lib.mr_selector_load(None, None) == L.MR_ERR_INVALID_ARG
 
 
 def test_struct_sizes_match_the_header():
     # sizes computed from the C declarations with the usual x86-64 alignment rules
     from paper_1309_0215_amd import _lib as L
-    assert C.sizeof(L.JobConfig) == 4 + 4 + 8 + 4 * 5 + 4 + 8 + 4 + 4 + 4 + 4 + 8 + 4 + 4 + 4 + 4
-    assert C.sizeof(L.Stats) == 4 + 4 + 8 + 8 + 4 + 4 + 4 + 4
+    assert C.sizeof(L.JobConfig) == 4 + 4 + 8 + 4 * 5 + 4 + 8 + 4 + 4 + 4 + 4 + 8 + 4 + 4 + 4 + 4 + 8 + 8
+    assert C.sizeof(L.Stats) == 4 + 4 + 8 + 8 + 4 + 4 + 4 + 4 + 4 + 4 + 8
     assert C.sizeof(L.Output) == 8 * 8 + 8 * 4 + 8 + C.sizeof(L.Stats) + 8 * 4
     assert C.sizeof(L.BatchItem) == 4 + 4 + 8 + 8 + 8 + 8 + 8
     assert C.sizeof(L.TuneEntry) == 4 + 4 + 8 + 8 + 4 * 4
+    assert C.sizeof(L.TrainConfig) == 4 * 6 + 8
 
 
 def test_product_path_does_not_import_the_oracle():
