@@ -286,11 +286,21 @@ typedef struct {
   uint64_t key_range;
 } mr_batch_item;
 
-/* Run many independent word-count jobs (MR_MAP_WORDS, MR_REDUCE_COUNT) in
- * one pass: one persistent map launch over a device work list of
+/* Run many independent jobs in one call (the start-up cost of many small
+ * jobs is what the paper's worker pool amortises, Section IV): word-count
+ * items (MR_MAP_WORDS, MR_REDUCE_COUNT) and integer-key items
+ * (MR_MAP_U32_KEYS, MR_MAP_U32_KV with any reduce op), in any mix.
+ * Word items: one persistent map launch over a device work list of
  * (job, tile) items, then batched compaction, sort and output, captured in a
- * HIP graph that is replayed while the batch layout is unchanged. outs[i]
- * receives job i's result exactly as mr_run would produce it, and
+ * HIP graph that is replayed while the batch layout is unchanged.
+ * Integer items: the container of each is decided first, for all of them at
+ * once: with MR_STRAT_LEARNED and weights loaded, the features and the
+ * network of every item run in one captured HIP graph (replayed while the
+ * items' inputs stay the same) and the choices are read back once; otherwise
+ * the rule or the forced container. Their containers then run one after
+ * another on the job's stream in regions sized for the largest item, and
+ * their states are read back once at the end.
+ * outs[i] receives item i's result exactly as mr_run would produce it, and
  * outs[i].status its status. Returns MR_OK, or the first failing status. */
 mr_status mr_batch_run(mr_job* job, const mr_batch_item* items, uint32_t n_items, mr_output* outs);
 

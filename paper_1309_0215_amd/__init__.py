@@ -245,6 +245,57 @@ class Job:
             keep.append(k)
         return items, outs, keep
 
+    def batch_prepare_mixed(self, entries):
+        """Item and output arrays of a batch of word-count and integer-key jobs.
+
+        Each entry is a dict: {"kind": "words", "data": uint8 tensor, "cap_keys",
+        "cap_bytes"} or {"kind": "u32" | "u32_kv", "data": int32 tensor (keys,
+        or interleaved (key, value) pairs), "op", "key_range", "cap_keys"}."""
+        torch = self.torch
+        dev = f"cuda:{self.device}"
+        n = len(entries)
+        items = (L.BatchItem * n)()
+        outs = (L.Output * n)()
+        keep = []
+        for i, e in enumerate(entries):
+            d = e["data"]
+            items[i].d_input, items[i].input_bytes = d.data_ptr(), int(d.numel()) * int(d.element_size())
+            if e["kind"] == "words":
+                items[i].kind, items[i].op = L.MAP_WORDS, L.REDUCE_COUNT
+                ck = e.get("cap_keys") or max(1024, min(int(d.numel()) // 2 + 1, 1 << 20))
+                cb = e.get("cap_bytes") or max(4096, min(int(d.numel()), 1 << 24))
+                o, k = self._word_out(ck, cb)
+            else:
+                items[i].kind = L.MAP_U32_KV if e["kind"] == "u32_kv" else L.MAP_U32_KEYS
+                items[i].op = e.get("op", L.REDUCE_COUNT)
+                items[i].key_range = e.get("key_range", 0)
+                ck = max(1, e["cap_keys"])
+                kt = torch.empty(ck, dtype=torch.int32, device=dev)
+                vt = torch.empty(ck, dtype=torch.int64 if items[i].op == L.REDUCE_SUM else torch.int32, device=dev)
+                o = L.Output()
+                o.keys, o.values, o.cap_keys = kt.data_ptr(), vt.data_ptr(), ck
+                k = (kt, vt)
+            outs[i] = o
+            keep.append(k)
+        return items, outs, keep
+
+    def batch_run(self, prepared, check: bool = True):
+        """One mr_batch_run over prepared items; returns the status (MR_OK unless check is False)."""
+        items, outs, keep = prepared
+        st = self.lib.mr_batch_run(self.h, items, len(keep), outs)
+        if check:
+            L.check(st, "mr_batch_run")
+        return st
+
+    @staticmethod
+    def batch_result(prepared, i):
+        """Result of item i of a run batch: WordsResult or U32Result."""
+        items, outs, keep = prepared
+        o, nk = outs[i], int(outs[i].n_keys)
+        if items[i].kind == L.MAP_WORDS:
+            return WordsResult(keep[i][0][:o.key_bytes_used], keep[i][1][:nk + 1], keep[i][2][:nk], _stats(o))
+        return U32Result(keep[i][0][:nk], keep[i][1][:nk], _stats(o))
+
     # -------------------------------------------------------------- histogram
     def rgb_hist(self, data, out=None):
         """768 bins (3 x 256, uint64 counts as int64) of interleaved RGB bytes.

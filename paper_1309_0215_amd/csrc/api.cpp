@@ -75,6 +75,10 @@ struct mr_job {
   std::vector<float> km_host;
   // batched graph cache: valid while nothing else has written the workspace
   hipGraphExec_t graph = nullptr;
+  // selection graph of a batch's integer items (features and network per item)
+  hipGraphExec_t sel_graph = nullptr;
+  uint64_t sel_graph_key = 0;
+  hipEvent_t ev_int0 = nullptr, ev_int1 = nullptr;  // around a batch's integer items
   uint64_t graph_key = 0;
   bool graph_valid = false;
   uint64_t plain_key = 0;  // launch-sequence identity of the last plain word pass
@@ -170,7 +174,9 @@ struct Carve {
 
 // Device regions of a job and the entry-point families that use them.
 enum RegionId { kRegWs = 1, kRegKmC, kRegSmall, kRegDense, kRegTable, kRegScratch, kRegSel, kRegMlp, kRegLink, kRegTrain };
-enum Family { kFamWords = 1, kFamRgb, kFamKmeans, kFamBloom, kFamU32, kFamLinks, kFamFeatures, kFamPredict, kFamMlp, kFamTrain };
+enum Family {
+  kFamWords = 1, kFamRgb, kFamKmeans, kFamBloom, kFamU32, kFamLinks, kFamFeatures, kFamPredict, kFamMlp, kFamTrain, kFamBatch
+};
 
 // Start of a call of `family`. With a caller workspace the call carves its
 // regions from offset 0; a region keeps its contents from the last call only
@@ -403,6 +409,9 @@ extern "C" mr_status mr_job_destroy(mr_job* job) {
   if (job->stream) (void)hipStreamSynchronize(job->stream);
   if (job->graph) (void)hipGraphExecDestroy(job->graph);
   if (job->rgb_graph) (void)hipGraphExecDestroy(job->rgb_graph);
+  if (job->sel_graph) (void)hipGraphExecDestroy(job->sel_graph);
+  if (job->ev_int0) (void)hipEventDestroy(job->ev_int0);
+  if (job->ev_int1) (void)hipEventDestroy(job->ev_int1);
   for (hipEvent_t e : job->rgb_ev)
     if (e) (void)hipEventDestroy(e);
   if (job->gstream) (void)hipStreamSynchronize(job->gstream);
@@ -1109,6 +1118,16 @@ mr_strategy rule_strategy(uint64_t R, uint32_t op, uint64_t lds_budget) {
 mr_status learned_strategy(mr_job* job, mr_map_kind kind, mr_reduce_op op, const void* d_input, uint64_t bytes,
                            uint64_t R, mr_strategy* s, bool* used);
 
+// Result sizes and status of an integer job from its state block.
+mr_status u32_finish(mr_job* job, mr_output* out, const IntSmall& hs) {
+  out->n_keys = hs.n_out;
+  out->key_bytes_used = 0;
+  job->int_last_distinct = hs.n_out;
+  if (hs.flags & kFlagBadInput) return fail(MR_ERR_INVALID_ARG, "a key is outside the declared key_range");
+  if (hs.n_out > out->cap_keys) return fail(MR_ERR_CAPACITY, "output needs %llu keys", (unsigned long long)hs.n_out);
+  return MR_OK;
+}
+
 // Scratch layouts of the integer-key containers (offsets in the scratch region).
 struct DenseCarve {  // LDS or global array over n elements and range R, G workgroups
   uint64_t o_blk = 0, o_cp = 0, o_vp = 0, o_ph = 0, o_ps = 0, o_pt = 0, o_pk = 0, bytes = 0;
@@ -1181,8 +1200,16 @@ uint64_t int_table_slots(const mr_job* job, mr_map_kind kind, uint64_t bytes, ui
   return std::max<uint64_t>(4096, next_pow2((uint64_t)std::ceil(std::min<uint64_t>(bound, 1ull << 24) / lf)));
 }
 
+// A batched integer item: the batch decides the container, gives the item
+// its own state slot and reads the states back once for all items.
+struct U32Ctx {
+  mr_strategy strat;   // the container to run
+  bool sel_used;       // the learned selector chose it
+  IntSmall* sm;        // this item's state (device)
+};
+
 mr_status run_u32(mr_job* job, mr_map_kind kind, mr_reduce_op op, const void* d_input, uint64_t bytes, uint64_t key_range,
-                  mr_output* out) {
+                  mr_output* out, const U32Ctx* ctx = nullptr) {
   const uint32_t esz = kind == MR_MAP_U32_KV ? 8 : 4;
   if (bytes % esz) return fail(MR_ERR_INVALID_ARG, "input length %llu is not a multiple of %u", (unsigned long long)bytes, esz);
   if (kind == MR_MAP_U32_KEYS && op != MR_REDUCE_COUNT) return fail(MR_ERR_UNSUPPORTED, "plain keys support COUNT only");
@@ -1194,8 +1221,8 @@ mr_status run_u32(mr_job* job, mr_map_kind kind, mr_reduce_op op, const void* d_
   if ((uintptr_t)d_input % 4) return fail(MR_ERR_INVALID_ARG, "integer input must be 4-byte aligned");
   const uint32_t o = (uint32_t)op;
 
-  mr_strategy strat = job->cfg.strategy;
-  bool sel_used = false;
+  mr_strategy strat = ctx ? ctx->strat : job->cfg.strategy;
+  bool sel_used = ctx ? ctx->sel_used : false;
   if (strat == MR_STRAT_LEARNED) {
     mr_status st = learned_strategy(job, kind, op, d_input, bytes, key_range, &strat, &sel_used);
     if (st != MR_OK) return st;
@@ -1205,9 +1232,13 @@ mr_status run_u32(mr_job* job, mr_map_kind kind, mr_reduce_op op, const void* d_
     return fail(MR_ERR_UNSUPPORTED, "strategy %d is infeasible for this job (key_range %llu)", (int)strat,
                 (unsigned long long)key_range);
 
-  mr_status st = int_ensure(job, kRegSmall, &job->int_small, &job->int_small_bytes, sizeof(IntSmall), 0);
-  if (st != MR_OK) return st;
-  IntSmall* sm = static_cast<IntSmall*>(job->int_small);
+  mr_status st = MR_OK;
+  IntSmall* sm = ctx ? ctx->sm : nullptr;
+  if (!sm) {
+    st = int_ensure(job, kRegSmall, &job->int_small, &job->int_small_bytes, sizeof(IntSmall), 0);
+    if (st != MR_OK) return st;
+    sm = static_cast<IntSmall*>(job->int_small);
+  }
 
   IntLaunch L{};
   L.in = static_cast<const uint32_t*>(d_input);
@@ -1240,7 +1271,7 @@ mr_status run_u32(mr_job* job, mr_map_kind kind, mr_reduce_op op, const void* d_
                   sizeof(IntSmall), (void*)job->stream, hipGetErrorString(e), hipGetErrorString(ea), (int)at.type);
     }
   }
-  MR_HIP(hipEventRecord(job->ev0, job->stream));
+  if (!ctx) MR_HIP(hipEventRecord(job->ev0, job->stream));
 
   if (strat == MR_STRAT_LDS_ARRAY || strat == MR_STRAT_GLOBAL_ARRAY) {
     // counts [R] then, 8-byte aligned, values [R]: 12 bytes per key plus alignment
@@ -1351,6 +1382,12 @@ mr_status run_u32(mr_job* job, mr_map_kind kind, mr_reduce_op op, const void* d_
     MR_HIP(int_enqueue_sort(L, job->stream));
     if (job->cfg.timing) MR_HIP(hipEventRecord(job->ev3, job->stream));
   }
+  out->stats.strategy_used = strat;
+  out->stats.selector_used = sel_used ? 1u : 0u;
+  out->stats.retries = retries;
+  out->stats.table_slots = table_cap;
+  out->stats.n_items = n;
+  if (ctx) return MR_OK;  // the batch reads the state back
   MR_HIP(hipEventRecord(job->ev1, job->stream));
   IntSmall hs;
   MR_HIP(hipMemcpyAsync(&hs, sm, sizeof hs, hipMemcpyDeviceToHost, job->stream));
@@ -1359,17 +1396,7 @@ mr_status run_u32(mr_job* job, mr_map_kind kind, mr_reduce_op op, const void* d_
   MR_HIP(hipEventElapsedTime(&ms, job->ev0, job->ev1));
   out->stats.gpu_ms = ms;
   if (job->cfg.timing) MR_HIP(hipEventElapsedTime(&out->stats.map_ms, job->ev2, job->ev3));
-  out->stats.strategy_used = strat;
-  out->stats.selector_used = sel_used ? 1u : 0u;
-  out->stats.retries = retries;
-  out->stats.table_slots = table_cap;
-  out->stats.n_items = n;
-  out->n_keys = hs.n_out;
-  out->key_bytes_used = 0;
-  job->int_last_distinct = hs.n_out;
-  if (hs.flags & kFlagBadInput) return fail(MR_ERR_INVALID_ARG, "a key is outside the declared key_range");
-  if (hs.n_out > out->cap_keys) return fail(MR_ERR_CAPACITY, "output needs %llu keys", (unsigned long long)hs.n_out);
-  return MR_OK;
+  return u32_finish(job, out, hs);
 }
 
 
@@ -1722,27 +1749,60 @@ extern "C" mr_status mr_tune_set(mr_job* job, const mr_tune_entry* entries, uint
   return MR_OK;
 }
 
+namespace {
+mr_status batch_ints_enqueue(mr_job* job, const mr_batch_item* items, const std::vector<uint32_t>& ii, mr_output* outs,
+                             std::vector<mr_status>& per);
+mr_status batch_ints_finish(mr_job* job, const std::vector<uint32_t>& ii, mr_output* outs, std::vector<mr_status>& per);
+}  // namespace
+
 extern "C" mr_status mr_batch_run(mr_job* job, const mr_batch_item* items, uint32_t n_items, mr_output* outs) {
   if (!job || (!items && n_items) || (!outs && n_items)) return fail(MR_ERR_INVALID_ARG, "NULL argument");
   if (n_items == 0) return MR_OK;
   ScopedDevice sd(job->device);
-  std::vector<WordItem> w(n_items);
+  std::vector<WordItem> w;
+  std::vector<uint32_t> wi, ii;
   for (uint32_t i = 0; i < n_items; ++i) {
-    if (items[i].kind != MR_MAP_WORDS || items[i].op != MR_REDUCE_COUNT)
-      return fail(MR_ERR_UNSUPPORTED, "mr_batch_run supports word-count items only (item %u)", i);
+    const mr_batch_item& it = items[i];
+    if (it.kind == MR_MAP_WORDS && it.op == MR_REDUCE_COUNT) {
+      wi.push_back(i);
+    } else if (it.kind == MR_MAP_U32_KEYS || it.kind == MR_MAP_U32_KV) {
+      if (it.d_record_offsets) return fail(MR_ERR_INVALID_ARG, "record offsets are only meaningful for words (item %u)", i);
+      ii.push_back(i);
+    } else {
+      return fail(MR_ERR_UNSUPPORTED, "mr_batch_run takes word-count and integer-key items (item %u)", i);
+    }
     outs[i].stats = mr_stats{};
     outs[i].status = MR_OK;
-    w[i] = WordItem{static_cast<const uint8_t*>(items[i].d_input), items[i].input_bytes, items[i].d_record_offsets,
-                    items[i].n_records, &outs[i], 0};
   }
+  for (uint32_t i : wi)
+    w.push_back(WordItem{static_cast<const uint8_t*>(items[i].d_input), items[i].input_bytes, items[i].d_record_offsets,
+                         items[i].n_records, &outs[i], 0});
   std::vector<mr_status> per(n_items, MR_OK);
-  arena_begin(job, kFamWords);
-  const mr_status st = run_words(job, w, &per, GraphMode::kAlways);
+  arena_begin(job, ii.empty() ? kFamWords : kFamBatch);
+  mr_status first = MR_OK;
+  // integer items first: the selection graph, then their containers on the
+  // stream; the word pass after them synchronises the stream once
+  if (!ii.empty()) {
+    first = batch_ints_enqueue(job, items, ii, outs, per);
+    if (first != MR_OK) return first;
+  }
+  if (!w.empty()) {
+    std::vector<mr_status> wper(w.size(), MR_OK);
+    const mr_status st = run_words(job, w, &wper, GraphMode::kAlways);
+    for (size_t k = 0; k < w.size(); ++k) per[wi[k]] = wper[k];
+    if (st != MR_OK && st != MR_ERR_CAPACITY && st != MR_ERR_INVALID_ARG) return st;
+  }
+  if (!ii.empty()) {
+    const mr_status st = batch_ints_finish(job, ii, outs, per);
+    if (st != MR_OK) return st;
+  }
   for (uint32_t i = 0; i < n_items; ++i) {
+    outs[i].status = per[i];
     outs[i].stats.device_allocs = job->call_allocs;
     outs[i].stats.workspace_needed = job->cws_need;
+    if (first == MR_OK && per[i] != MR_OK) first = per[i];
   }
-  return st;
+  return first;
 }
 
 // ----------------------------------------------------------------------------
@@ -2007,6 +2067,159 @@ mr_status learned_strategy(mr_job* job, mr_map_kind kind, mr_reduce_op op, const
   if (hs.choice >= 0 && hs.choice < MR_N_STRATS) {
     *s = order[hs.choice];
     *used = true;
+  }
+  return MR_OK;
+}
+
+// A batch's integer items. The containers are decided first: by the learned
+// selector for all items at once (features and network of every item in one
+// captured graph, replayed while the batch's inputs stay the same, then one
+// read-back of the choices), otherwise by the rule or the job's forced
+// container. The regions are then sized for the largest item and the items'
+// containers are enqueued one after another on the job's stream, each with
+// its own state block (hash-table items still read their key count back);
+// batch_ints_finish reads all states back once.
+mr_status batch_ints_enqueue(mr_job* job, const mr_batch_item* items, const std::vector<uint32_t>& ii, mr_output* outs,
+                             std::vector<mr_status>& per) {
+  const uint32_t ni = (uint32_t)ii.size();
+  const hipStream_t s = job->stream;
+  mr_status st = int_ensure(job, kRegSmall, &job->int_small, &job->int_small_bytes, sizeof(IntSmall) * ni, -1);
+  if (st != MR_OK) return st;
+  IntSmall* sm = static_cast<IntSmall*>(job->int_small);
+  MR_HIP(hipMemsetAsync(sm, 0, sizeof(IntSmall) * ni, s));
+  std::vector<mr_strategy> strat(ni, MR_STRAT_RULE);
+  std::vector<uint8_t> chosen(ni, 0);
+  for (uint32_t q = 0; q < ni; ++q) {
+    const mr_batch_item& it = items[ii[q]];
+    const uint32_t esz = it.kind == MR_MAP_U32_KV ? 8 : 4;
+    if (it.input_bytes % esz || (it.input_bytes && !it.d_input) || (uintptr_t)it.d_input % 4 ||
+        (it.kind == MR_MAP_U32_KEYS && it.op != MR_REDUCE_COUNT) || it.op > MR_REDUCE_MAX || it.key_range > (1ull << 32))
+      return fail(MR_ERR_INVALID_ARG, "integer item %u is malformed", ii[q]);
+  }
+  static const mr_strategy order[MR_N_STRATS] = {MR_STRAT_LDS_ARRAY, MR_STRAT_GLOBAL_ARRAY, MR_STRAT_HASH, MR_STRAT_SORT};
+  if (job->cfg.strategy == MR_STRAT_LEARNED && job->sel_loaded) {
+    // the selector region with one feature row per item after its own fields
+    st = sel_scratch(job, sel_floats() + 16ull * ni);
+    if (st != MR_OK) return st;
+    st = sel_upload(job);
+    if (st != MR_OK) return st;
+    float* d = static_cast<float*>(job->sel_dev);
+    float* rows = d + sel_floats();
+    uint64_t key = fnv_mix(fnv_mix(0xCBF29CE484222325ull, (uint64_t)d), (uint64_t)sm);
+    std::vector<uint32_t> feas(ni, 0);
+    for (uint32_t q = 0; q < ni; ++q) {
+      const mr_batch_item& it = items[ii[q]];
+      for (int k = 0; k < MR_N_STRATS; ++k)
+        if (int_feasible(order[k], it.key_range, (uint32_t)it.op)) feas[q] |= 1u << k;
+      for (uint64_t v : {(uint64_t)it.d_input, it.input_bytes, (uint64_t)it.kind, (uint64_t)it.op, it.key_range,
+                         (uint64_t)feas[q]})
+        key = fnv_mix(key, v);
+    }
+    if (!job->sel_graph || job->sel_graph_key != key) {
+      if (job->sel_graph) {
+        MR_HIP(hipGraphExecDestroy(job->sel_graph));
+        job->sel_graph = nullptr;
+      }
+      hipGraph_t g = nullptr;
+      const hipStream_t cs = job->gstream;
+      MR_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+      hipError_t e = hipSuccess;
+      for (uint32_t q = 0; q < ni && e == hipSuccess; ++q) {
+        const mr_batch_item& it = items[ii[q]];
+        e = features_enqueue(static_cast<const uint8_t*>(it.d_input), it.input_bytes, feature_kind(it.kind), (int)it.op,
+                             it.key_range, (uint32_t)kLdsArrayBudget, rows + 16ull * q, d + kSelState, cs);
+        if (e == hipSuccess) e = select_enqueue(rows + 16ull * q, d + kSelNorm, d + kSelParams, feas[q], &sm[q].choice, cs);
+      }
+      const hipError_t e2 = hipStreamEndCapture(cs, &g);
+      if (e == hipSuccess && e2 == hipSuccess) e = hipGraphInstantiate(&job->sel_graph, g, nullptr, nullptr, 0);
+      if (g) (void)hipGraphDestroy(g);
+      if (e != hipSuccess || e2 != hipSuccess)
+        return fail(MR_ERR_HIP, "selection graph: %s", hipGetErrorString(e != hipSuccess ? e : e2));
+      job->sel_graph_key = key;
+    }
+    MR_HIP(hipGraphLaunch(job->sel_graph, s));
+    std::vector<IntSmall> hs(ni);
+    MR_HIP(hipMemcpyAsync(hs.data(), sm, sizeof(IntSmall) * ni, hipMemcpyDeviceToHost, s));
+    MR_HIP(hipStreamSynchronize(s));
+    for (uint32_t q = 0; q < ni; ++q)
+      if (hs[q].choice >= 0 && hs[q].choice < MR_N_STRATS) {
+        strat[q] = order[hs[q].choice];
+        chosen[q] = 1;
+      }
+  } else if (job->cfg.strategy != MR_STRAT_LEARNED) {
+    for (uint32_t q = 0; q < ni; ++q) strat[q] = job->cfg.strategy;
+  }
+  // the rule for the items the selector left to it; the regions for the largest item
+  uint64_t dense_b = 0, dense_r = 0, table_s = 0, scratch_b = 0;
+  for (uint32_t q = 0; q < ni; ++q) {
+    const mr_batch_item& it = items[ii[q]];
+    const uint32_t op = (uint32_t)it.op;
+    const uint64_t n = it.input_bytes / (it.kind == MR_MAP_U32_KV ? 8 : 4);
+    if (strat[q] == MR_STRAT_RULE || strat[q] == MR_STRAT_LEARNED)
+      strat[q] = rule_strategy(it.key_range, op, eff_lds_array_bytes(job, it.kind, it.input_bytes));
+    if (!int_feasible(strat[q], it.key_range, op)) {
+      per[ii[q]] = fail(MR_ERR_UNSUPPORTED, "strategy %d is infeasible for item %u", (int)strat[q], ii[q]);
+      continue;
+    }
+    const uint32_t G = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)job->n_cu * 2, (n + 1023) / 1024));
+    if (strat[q] == MR_STRAT_LDS_ARRAY || strat[q] == MR_STRAT_GLOBAL_ARRAY) {
+      dense_r = std::max(dense_r, it.key_range);
+      dense_b = std::max(dense_b, it.key_range * 12 + 8);
+      scratch_b = std::max(scratch_b, dense_carve(strat[q], n, it.key_range, op, G).bytes);
+    } else if (strat[q] == MR_STRAT_HASH) {
+      table_s = std::max(table_s, int_table_slots(job, it.kind, it.input_bytes, n, it.key_range));
+      scratch_b = std::max(scratch_b, hash_carve(it.key_range ? std::min(n, it.key_range) : n).bytes);
+    } else {
+      scratch_b = std::max(scratch_b, sort_carve(n).bytes);
+    }
+  }
+  if (dense_b) {
+    bool fresh = false;
+    st = int_ensure(job, kRegDense, &job->int_dense, &job->int_dense_bytes, dense_b, 0, &fresh);
+    if (st != MR_OK) return st;
+    if (fresh) job->int_dense_R = dense_r;
+  }
+  if (table_s) {
+    bool fresh = false;
+    st = dev_region(job, kRegTable, &job->int_table, &job->int_table_bytes, table_s * kIntSlotBytes, table_s * kIntSlotBytes,
+                    &fresh);
+    if (st != MR_OK) return st;
+    if (fresh) {
+      job->int_table_cap = table_s;
+      MR_HIP(hipMemsetAsync(job->int_table, 0xFF, table_s * 4, s));
+      MR_HIP(hipMemsetAsync(static_cast<uint8_t*>(job->int_table) + table_s * 4, 0, table_s * 16, s));
+    }
+  }
+  if (scratch_b) {
+    st = int_ensure(job, kRegScratch, &job->int_scratch, &job->int_scratch_bytes, scratch_b, -1);
+    if (st != MR_OK) return st;
+  }
+  if (!job->ev_int0) MR_HIP(hipEventCreate(&job->ev_int0));
+  if (!job->ev_int1) MR_HIP(hipEventCreate(&job->ev_int1));
+  MR_HIP(hipEventRecord(job->ev_int0, s));
+  for (uint32_t q = 0; q < ni; ++q) {
+    if (per[ii[q]] != MR_OK) continue;
+    const mr_batch_item& it = items[ii[q]];
+    const U32Ctx ctx{strat[q], chosen[q] != 0, sm + q};
+    st = run_u32(job, it.kind, it.op, it.d_input, it.input_bytes, it.key_range, &outs[ii[q]], &ctx);
+    if (st == MR_ERR_HIP) return st;
+    per[ii[q]] = st;
+  }
+  MR_HIP(hipEventRecord(job->ev_int1, s));
+  return MR_OK;
+}
+
+mr_status batch_ints_finish(mr_job* job, const std::vector<uint32_t>& ii, mr_output* outs, std::vector<mr_status>& per) {
+  const uint32_t ni = (uint32_t)ii.size();
+  std::vector<IntSmall> hs(ni);
+  MR_HIP(hipMemcpyAsync(hs.data(), job->int_small, sizeof(IntSmall) * ni, hipMemcpyDeviceToHost, job->stream));
+  MR_HIP(hipStreamSynchronize(job->stream));
+  float ms = 0.f;
+  MR_HIP(hipEventElapsedTime(&ms, job->ev_int0, job->ev_int1));
+  for (uint32_t q = 0; q < ni; ++q) {
+    mr_output* o = &outs[ii[q]];
+    o->stats.gpu_ms = ms;
+    if (per[ii[q]] == MR_OK) per[ii[q]] = u32_finish(job, o, hs[q]);
   }
   return MR_OK;
 }
