@@ -352,3 +352,87 @@ def regret(times: np.ndarray, feasible: np.ndarray, chosen: np.ndarray) -> np.nd
     t = np.where(feasible, times, np.inf)
     best = t.min(axis=1)
     return times[np.arange(len(times)), chosen] / best - 1.0
+
+
+# ----------------------------------------------------------------------------
+# string hashing of the words, one character per step (Section III-C)
+# ----------------------------------------------------------------------------
+
+FNV64_BASIS = 0xCBF29CE484222325
+FNV64_PRIME = 0x100000001B3
+
+
+def fnv1a64(s: bytes) -> int:
+    """FNV-1a, 64 bits: for each byte, xor it in, then multiply by the prime (mod 2^64)."""
+    h = FNV64_BASIS
+    for b in s:
+        h = ((h ^ b) * FNV64_PRIME) & 0xFFFFFFFFFFFFFFFF
+    return h
+
+
+def word_spans(buf: np.ndarray) -> tuple[np.ndarray, np.ndarray]:
+    """(offsets, lengths) of the words of buf in input order: maximal runs of
+    bytes outside {09, 0A, 0B, 0C, 0D, 20}."""
+    b = np.asarray(buf, np.uint8)
+    sep = (b == 0x20) | ((b >= 0x09) & (b <= 0x0D))
+    word = np.concatenate([[False], ~sep, [False]])
+    d = np.diff(word.astype(np.int8))
+    starts = np.flatnonzero(d == 1)
+    ends = np.flatnonzero(d == -1)
+    return starts.astype(np.uint64), (ends - starts).astype(np.uint64)
+
+
+def word_hashes(buf: np.ndarray) -> np.ndarray:
+    """FNV-1a 64 of every word of buf, in input order (uint64)."""
+    raw = np.asarray(buf, np.uint8).tobytes()
+    offs, lens = word_spans(buf)
+    return np.array([fnv1a64(raw[o:o + l]) for o, l in zip(offs.tolist(), lens.tolist())], np.uint64)
+
+
+def stream_schedule(lengths, units: int):
+    """SIMDH-Stream: `units` lanes hash a stream of strings, one character per
+    lane per iteration (iterations numbered from 1), the terminator taking an
+    iteration of its own. A lane that meets its string's terminator takes the
+    next unprocessed string at the next iteration; lanes freed together take
+    the next strings in lane order. Returns [unit, first iteration, last
+    iteration] per string."""
+    n = len(lengths)
+    out = [None] * n
+    cur = [-1] * units
+    pos = [0] * units
+    nxt = 0
+    it = 0
+    while True:
+        it += 1
+        for u in range(units):
+            if cur[u] < 0 and nxt < n:
+                cur[u], pos[u] = nxt, 0
+                out[nxt] = [u, it, None]
+                nxt += 1
+        if all(c < 0 for c in cur):
+            break
+        for u in range(units):
+            c = cur[u]
+            if c < 0:
+                continue
+            if pos[u] == lengths[c]:  # the terminator: this string ends here
+                out[c][2] = it
+                cur[u] = -1
+            else:
+                pos[u] += 1
+    return out
+
+
+def padding_schedule(lengths, units: int):
+    """SIMDH-Padding: rounds of `units` consecutive strings; a round lasts as
+    many iterations as its longest string has characters, plus its
+    terminator; shorter strings are padded (their lanes idle). Returns
+    [unit, first iteration, last iteration] per string."""
+    out = []
+    start = 1
+    for r0 in range(0, len(lengths), units):
+        grp = lengths[r0:r0 + units]
+        for u, l in enumerate(grp):
+            out.append([u, start, start + int(l)])
+        start += int(max(grp)) + 1
+    return out
