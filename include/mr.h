@@ -275,6 +275,26 @@ mr_status mr_run(mr_job* job, mr_map_kind kind, mr_reduce_op op, const void* d_i
  * the 1024 rows of 32-bit counters cannot hold), MR_ERR_HIP. */
 mr_status mr_rgb_hist_static(mr_job* job, const void* d_input, uint64_t input_bytes, uint64_t* d_bins);
 
+/* FNV-1a 64 (basis 0xcbf29ce484222325, prime 0x100000001b3) of every word of
+ * d_input (words as for MR_MAP_WORDS, one record), in input order, hashed one
+ * character per lane per step as the string hashes of Section III-C:
+ * mode 0 = SIMDH-Padding (rounds of `units` consecutive words; a round lasts
+ * for its longest word, shorter ones padded), mode 1 = SIMDH-Stream (a lane
+ * takes the next word as soon as its own ends; lanes freed together take the
+ * next words in lane order, found from a ballot of the freed lanes and its
+ * prefix count). One wavefront of which `units` (1..64) lanes hash takes
+ * each block of `block` consecutive words (0 = 4096). A word's terminator
+ * takes a step of its own. Outputs (device): d_hashes uint64[cap_words];
+ * d_sched (optional, NULL = not written) uint32[cap_words][3] = lane, first
+ * and last step of each word, steps counted from 1 within its block; on
+ * return *n_words holds the number of words and *hash_ms (optional, host)
+ * the device time of the hashing kernel. Errors: MR_ERR_INVALID_ARG,
+ * MR_ERR_CAPACITY (more words than cap_words; *n_words is set),
+ * MR_ERR_UNSUPPORTED (inputs of 4 GiB or more), MR_ERR_HIP. */
+mr_status mr_hash_words(mr_job* job, const void* d_input, uint64_t input_bytes, uint32_t mode, uint32_t units,
+                        uint32_t block, uint64_t* d_hashes, uint32_t* d_sched, uint64_t cap_words, uint64_t* n_words,
+                        float* hash_ms);
+
 /* One item of a batch (device pointers as in mr_run). */
 typedef struct {
   mr_map_kind kind;

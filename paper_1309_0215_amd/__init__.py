@@ -296,6 +296,24 @@ class Job:
             return WordsResult(keep[i][0][:o.key_bytes_used], keep[i][1][:nk + 1], keep[i][2][:nk], _stats(o))
         return U32Result(keep[i][0][:nk], keep[i][1][:nk], _stats(o))
 
+    def hash_words(self, data, stream: bool = True, units: int = 64, block: int = 4096, schedule: bool = False):
+        """mr_hash_words: FNV-1a 64 of every word of a uint8 CUDA tensor, in
+        input order; returns (hashes as int64, schedule [n][3] int32 or None,
+        kernel ms)."""
+        torch = self.torch
+        dev = f"cuda:{self.device}"
+        nb = int(data.numel())
+        cap = nb // 2 + 1
+        h = torch.empty(cap, dtype=torch.int64, device=dev)
+        sch = torch.empty(cap, 3, dtype=torch.int32, device=dev) if schedule else None
+        n = C.c_uint64(0)
+        ms = C.c_float(0.0)
+        L.check(self.lib.mr_hash_words(self.h, _ptr(data), nb, 1 if stream else 0, units, block, h.data_ptr(),
+                                       None if sch is None else sch.data_ptr(), cap, C.byref(n), C.byref(ms)),
+                "mr_hash_words")
+        k = int(n.value)
+        return h[:k], (None if sch is None else sch[:k]), float(ms.value)
+
     # -------------------------------------------------------------- histogram
     def rgb_hist(self, data, out=None):
         """768 bins (3 x 256, uint64 counts as int64) of interleaved RGB bytes.

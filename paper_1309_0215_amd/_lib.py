@@ -27,7 +27,7 @@ EXPORTS = [
     "mr_status_str", "mr_last_error", "mr_job_create", "mr_job_destroy", "mr_run", "mr_batch_run",
     "mr_job_features", "mr_selector_set", "mr_selector_predict", "mr_mlp_forward", "mr_mlp_loss_backward",
     "mr_mlp_adam", "mr_tune_set", "mr_rgb_hist_static", "mr_workspace_bytes", "mr_selector_load",
-    "mr_selector_train",
+    "mr_selector_train", "mr_hash_words",
 ]
 
 
@@ -162,6 +162,8 @@ def load(required: bool = True):
     lib.mr_workspace_bytes.argtypes = [C.POINTER(JobConfig), C.c_int, U64, U64, C.POINTER(U64)]
     lib.mr_selector_load.restype = I32
     lib.mr_selector_load.argtypes = [P, C.c_char_p]
+    lib.mr_hash_words.restype = I32
+    lib.mr_hash_words.argtypes = [P, P, U64, U32, U32, U32, P, P, U64, C.POINTER(U64), C.POINTER(C.c_float)]
     lib.mr_selector_train.restype = I32
     lib.mr_selector_train.argtypes = [P, P, P, P, U32, C.POINTER(TrainConfig), P, C.c_char_p]
     if hasattr(lib, "mr_job_features"):

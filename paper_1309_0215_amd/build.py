@@ -18,7 +18,7 @@ LIB = os.path.join(HERE, "libmr.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["api.cpp", "words.hip", "hist.hip", "ints.hip", "kmeans.hip", "selector.hip", "bloom.hip", "links.hip"]
+SOURCES = ["api.cpp", "words.hip", "hist.hip", "ints.hip", "kmeans.hip", "selector.hip", "bloom.hip", "links.hip", "strhash.hip"]
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall", "-Wno-unused-function",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", os.path.join(HERE, "..", "include")]

@@ -173,9 +173,12 @@ struct Carve {
 };
 
 // Device regions of a job and the entry-point families that use them.
-enum RegionId { kRegWs = 1, kRegKmC, kRegSmall, kRegDense, kRegTable, kRegScratch, kRegSel, kRegMlp, kRegLink, kRegTrain };
+enum RegionId {
+  kRegWs = 1, kRegKmC, kRegSmall, kRegDense, kRegTable, kRegScratch, kRegSel, kRegMlp, kRegLink, kRegTrain, kRegHashList
+};
 enum Family {
-  kFamWords = 1, kFamRgb, kFamKmeans, kFamBloom, kFamU32, kFamLinks, kFamFeatures, kFamPredict, kFamMlp, kFamTrain, kFamBatch
+  kFamWords = 1, kFamRgb, kFamKmeans, kFamBloom, kFamU32, kFamLinks, kFamFeatures, kFamPredict, kFamMlp, kFamTrain, kFamBatch,
+  kFamHash
 };
 
 // Start of a call of `family`. With a caller workspace the call carves its
@@ -2450,4 +2453,61 @@ extern "C" mr_status mr_selector_train(mr_job* job, const float* feats, const fl
   if (st != MR_OK) return st;
   if (out_json) return write_selector_json(out_json, P, fmean.data(), fscale.data(), flo.data(), fhi.data(), mu, sd);
   return MR_OK;
+}
+
+// ----------------------------------------------------------------------------
+// word hashing one character per lane per step (SIMDH-Padding / SIMDH-Stream)
+// ----------------------------------------------------------------------------
+
+extern "C" mr_status mr_hash_words(mr_job* job, const void* d_input, uint64_t input_bytes, uint32_t mode, uint32_t units,
+                                   uint32_t block, uint64_t* d_hashes, uint32_t* d_sched, uint64_t cap_words,
+                                   uint64_t* n_words, float* hash_ms) {
+  if (!job || !n_words || (input_bytes && !d_input) || (cap_words && !d_hashes))
+    return fail(MR_ERR_INVALID_ARG, "NULL argument");
+  if (mode > 1 || units == 0 || units > 64) return fail(MR_ERR_INVALID_ARG, "mode must be 0 or 1 and units 1..64");
+  if (input_bytes >= (1ull << 32)) return fail(MR_ERR_UNSUPPORTED, "inputs must be below 4 GiB");
+  const uint64_t blk = block ? block : 4096;
+  ScopedDevice sd(job->device);
+  arena_begin(job, kFamHash);
+  const hipStream_t s = job->stream;
+  const uint8_t* in = static_cast<const uint8_t*>(d_input);
+  const uint64_t n_chunks = (input_bytes + 15) / 16;
+  Carve c;
+  const uint64_t o_cnt = c.take(4 * std::max<uint64_t>(n_chunks, 1)), o_sums = c.take(4 * scan_sums_count(n_chunks));
+  const uint64_t o_tot = c.take(8);
+  mr_status st = int_ensure(job, kRegScratch, &job->int_scratch, &job->int_scratch_bytes, c.off, -1);
+  if (st != MR_OK) return st;
+  uint8_t* sc = static_cast<uint8_t*>(job->int_scratch);
+  uint32_t* counts = reinterpret_cast<uint32_t*>(sc + o_cnt);
+  unsigned long long total = 0;
+  MR_HIP(hw_enqueue_list(in, input_bytes, counts, n_chunks, reinterpret_cast<uint32_t*>(sc + o_sums),
+                         reinterpret_cast<unsigned long long*>(sc + o_tot), s));
+  MR_HIP(hipMemcpyAsync(&total, sc + o_tot, 8, hipMemcpyDeviceToHost, s));
+  MR_HIP(hipStreamSynchronize(s));
+  *n_words = total;
+  if (total > cap_words) return fail(MR_ERR_CAPACITY, "the input has %llu words", (unsigned long long)total);
+  void* lst = nullptr;
+  uint64_t lst_have = 0;
+  bool fresh = false;
+  st = dev_region(job, kRegHashList, &lst, &lst_have, 8 * std::max<uint64_t>(total, 1), 8 * std::max<uint64_t>(total, 1),
+                  &fresh);
+  if (st != MR_OK) return st;
+  uint32_t* off = static_cast<uint32_t*>(lst);
+  uint32_t* len = off + total;
+  mr_status result = MR_OK;
+  do {
+    hipError_t e = hw_enqueue_words(in, input_bytes, counts, n_chunks, off, len, s);
+    if (e == hipSuccess) e = hipEventRecord(job->ev0, s);
+    if (e == hipSuccess)
+      e = hw_enqueue_hash(in, off, len, total, mode == 1, units, blk, reinterpret_cast<unsigned long long*>(d_hashes),
+                          d_sched, s);
+    if (e == hipSuccess) e = hipEventRecord(job->ev1, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, job->ev0, job->ev1);
+    if (e != hipSuccess) result = fail(MR_ERR_HIP, "mr_hash_words: %s", hipGetErrorString(e));
+    if (hash_ms) *hash_ms = ms;
+  } while (false);
+  if (!job->cws) (void)hipFree(lst);  // library memory of this call only
+  return result;
 }

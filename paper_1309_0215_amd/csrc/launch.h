@@ -203,4 +203,16 @@ hipError_t mlp_backward_enqueue(const float* P, const float* X, const float* H1,
 hipError_t adam_enqueue(float* P, const float* G, float* m, float* v, uint32_t step, float lr, float b1, float b2, float eps,
                         hipStream_t s);
 
+// Word hashing one character per lane per step (strhash.hip): word starts per
+// 16-byte chunk and their exclusive scan (counts[n_chunks] in place, total
+// = number of words); the word list (offsets, lengths, uint32); FNV-1a 64 of
+// every word with the padding or the stream schedule, `units` lanes per
+// wavefront, one wavefront per `block` words; sched optional ([word][3]).
+hipError_t hw_enqueue_list(const uint8_t* in, uint64_t n, uint32_t* counts, uint64_t n_chunks, uint32_t* scan_sums,
+                           unsigned long long* total, hipStream_t s);
+hipError_t hw_enqueue_words(const uint8_t* in, uint64_t n, const uint32_t* first, uint64_t n_chunks, uint32_t* off,
+                            uint32_t* len, hipStream_t s);
+hipError_t hw_enqueue_hash(const uint8_t* in, const uint32_t* off, const uint32_t* len, uint64_t n_words, bool stream,
+                           uint32_t units, uint64_t block, unsigned long long* hashes, uint32_t* sched, hipStream_t s);
+
 }  // namespace mr
