@@ -38,9 +38,34 @@ def time_steps(fn, steps, warmup, torch):
     return (time.perf_counter() - t0) * 1e3 / steps, outs
 
 
-def bench_rgb(torch, steps, warmup):
+def rep_stats(fn, reps, torch, scratch=None):
+    """Median, min and p95 (ms) of `reps` single runs of fn, each bracketed by
+    HIP events on torch's current stream (the stream the library's jobs run
+    on). With `scratch` (a 1 GiB device buffer) every rep is preceded by a
+    read and write of all of it, which evicts the L2 caches and the 256 MB
+    Infinity Cache (cold cache)."""
     import numpy as np
+    ms = []
+    for _ in range(reps):
+        if scratch is not None:
+            scratch.add_(1)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        b.synchronize()
+        ms.append(a.elapsed_time(b))
+    ms = np.array(ms)
+    return {"median_ms": float(np.median(ms)), "min_ms": float(ms.min()), "p95_ms": float(np.quantile(ms, 0.95)),
+            "reps": int(reps)}
 
+
+def bench_rgb(torch, steps, warmup, scratch):
+    """The headline step is the histogram through the allocation-free entry
+    point, enqueued step after step with no host synchronisation between
+    steps (the K steps are bracketed by synchronisations); the same job
+    through mr_run, which synchronises its stream before returning, is
+    reported beside it. Both give bit-identical bins (checked here)."""
     import gen
     from paper_1309_0215_amd import Job
     buf = gen.rgb(2)
@@ -48,22 +73,31 @@ def bench_rgb(torch, steps, warmup):
     d = torch.from_numpy(buf).to("cuda:0")
     job = Job(device=0, timing=1)
     out = torch.empty(768, dtype=torch.int64, device="cuda:0")  # one output buffer: repeated calls replay a graph
-    ms, outs = time_steps(lambda: job.rgb_hist(d, out=out)[1], steps, warmup, torch)
+    out_s = torch.empty(768, dtype=torch.int64, device="cuda:0")
+    ms, _ = time_steps(lambda: job.rgb_hist_static(d, out_s), steps, warmup, torch)
+    ms_sync, outs = time_steps(lambda: job.rgb_hist(d, out=out)[1], steps, warmup, torch)
+    assert torch.equal(out, out_s), "the allocation-free histogram differs from mr_run"
     map_ms = sum(o["map_ms"] for o in outs) / len(outs)
     gpu_ms = sum(o["gpu_ms"] for o in outs) / len(outs)
     gbs = n / (ms * 1e-3) / 1e9
-    res = {"bytes": n, "ms_per_step": ms, "gpu_ms": gpu_ms, "map_ms": map_ms, "GBps": gbs,
-           "hbm_frac": gbs / HBM_PEAK_GBS, "kernel_GBps": n / (map_ms * 1e-3) / 1e9}
+    warm = rep_stats(lambda: job.rgb_hist_static(d, out_s), 50, torch)
+    cold = rep_stats(lambda: job.rgb_hist_static(d, out_s), 50, torch, scratch)
+    res = {"bytes": n, "ms_per_step": ms, "GBps": gbs, "hbm_frac": gbs / HBM_PEAK_GBS,
+           "entry_point": "mr_rgb_hist_static, enqueued without host synchronisation between steps",
+           "mr_run_ms_per_step": ms_sync, "mr_run_GBps": n / (ms_sync * 1e-3) / 1e9,
+           "mr_run_gpu_ms": gpu_ms, "map_ms": map_ms, "kernel_GBps": n / (map_ms * 1e-3) / 1e9,
+           "warm_events": warm, "cold_events": cold,
+           "cold_median_GBps": n / (cold["median_ms"] * 1e-3) / 1e9}
     return res, buf
 
 
-def bench_words(torch, size, steps, warmup, seed=1):
+def bench_words(torch, size, steps, warmup, scratch, seed=1, combine=0):
     import gen
     from paper_1309_0215_amd import Job
     buf = gen.text(seed, size)
     d = torch.from_numpy(buf).to("cuda:0")
     from paper_1309_0215_amd import _lib as L
-    first = Job(device=0).words(d)  # sizes the output buffers
+    first = Job(device=0, wave_combine=combine).words(d)  # sizes the output buffers
 
     def run(job, steps_, warmup_):
         o, keep = job._word_out(len(first) + 16, int(first.key_bytes.numel()) + 64)
@@ -75,14 +109,20 @@ def bench_words(torch, size, steps, warmup, seed=1):
         return time_steps(step, steps_, warmup_, torch)
 
     # whole job, as a caller repeating it sees it (the repeat replays a captured graph)
-    ms, outs = run(Job(device=0), steps, warmup)
+    wjob = Job(device=0, wave_combine=combine)
+    ms, outs = run(wjob, steps, warmup)
     gpu_ms = sum(x[0] for x in outs) / len(outs)
+    o2, keep2 = wjob._word_out(len(first) + 16, int(first.key_bytes.numel()) + 64)
+    one = lambda: L.check(wjob.words_raw(d, o2), "words")  # noqa: E731
+    warm = rep_stats(one, 30, torch)
+    cold = rep_stats(one, 30, torch, scratch)
     # the map kernel alone (timed launches between events)
-    _, touts = run(Job(device=0, timing=1), steps, 2)
+    _, touts = run(Job(device=0, timing=1, wave_combine=combine), steps, 2)
     map_ms = sum(x[1] for x in touts) / len(touts)
     gbs = size / (ms * 1e-3) / 1e9
     return {"bytes": size, "distinct": len(first), "ms_per_step": ms, "gpu_ms": gpu_ms, "map_ms": map_ms, "GBps": gbs,
-            "hbm_frac": gbs / HBM_PEAK_GBS, "map_kernel_GBps": size / (map_ms * 1e-3) / 1e9}
+            "hbm_frac": gbs / HBM_PEAK_GBS, "map_kernel_GBps": size / (map_ms * 1e-3) / 1e9,
+            "warm_events": warm, "cold_events": cold, "cold_median_GBps": size / (cold["median_ms"] * 1e-3) / 1e9}
 
 
 def bench_kmeans(torch, steps, warmup):
@@ -143,55 +183,92 @@ def bench_batched(torch, reps=3):
             "outputs_identical": bool(same)}
 
 
-def bench_selector(torch, n_jobs=200):
-    """Held-out selector jobs: plain per-job rule vs learned vs batched word jobs + learned."""
+def bench_selector(torch, n_jobs=64):
+    """Held-out jobs of the selector set (mixed word and integer jobs): every
+    feasible container of every job is timed here, so the regret of the
+    learned selector and of the rule (time of the chosen container / time of
+    the best one - 1) comes from this run. Then jobs/s of plain per-job mr_run
+    with the rule, per-job mr_run with the learned selector, and the whole set
+    as one mr_batch_run with the learned selector; all three must give
+    identical outputs for every job."""
+    import numpy as np
+
     import gen
     from paper_1309_0215_amd import Job, _lib as L, selector as S
-    specs_all = S._specs(2000, 16)
+    model = json.load(open(S.WEIGHTS_PATH))
+    size_hi = int(model.get("meta", {}).get("size_hi_mib", 16))
+    specs_all = S._specs(2000, size_hi)
     _, test = S.split(specs_all, 1500)
     specs = [specs_all[i] for i in test[:n_jobs]]
     bufs = gen.job_inputs(specs)
-    dev = []
-    for s, b in zip(specs, bufs):
-        d = torch.from_numpy(b).to("cuda:0")
-        dev.append(d.view(torch.int32) if s.kind == "u32" else d)
     runner = S.Runner(torch)
-    model = S.load_model(runner.learned)
-    outs = [runner.outputs(s, d) for s, d in zip(specs, dev)]
-    words = [i for i, s in enumerate(specs) if s.kind == "words"]
-    ints = [i for i, s in enumerate(specs) if s.kind == "u32"]
+    S.load_model(runner.learned)
+    X, T = S.measure(runner, specs, bufs, reps=3)
+    feas = np.array([S.feasible(sp) for sp in specs])
+    dev = []
+    for sp, b in zip(specs, bufs):
+        d = torch.from_numpy(b).to("cuda:0")
+        dev.append(d.view(torch.int32) if sp.kind == "u32" else d)
+    outs = {name: [runner.outputs(sp, d) for sp, d in zip(specs, dev)] for name in ("rule", "learned")}
+    strat_used = {}
 
-    def plain():
-        for s, d, (o, _) in zip(specs, dev, outs):
-            L.check(runner.run(runner.rule, s, d, o)[0], "rule")
+    def per_job(name, job):
+        def run():
+            for i, (sp, d) in enumerate(zip(specs, dev)):
+                o = outs[name][i][0]
+                L.check(runner.run(job, sp, d, o)[0], name)
+                strat_used[(name, i)] = int(o.stats.strategy_used)
+        return run
 
-    def learned():
-        for s, d, (o, _) in zip(specs, dev, outs):
-            L.check(runner.run(runner.learned if s.kind == "u32" else runner.rule, s, d, o)[0], "learned")
-
-    bjob = Job(device=0)
-    prep = bjob.batch_prepare([dev[i] for i in words])
-
-    def batched_learned():
-        bjob.words_batch([dev[i] for i in words], prepared=prep)
-        for i in ints:
-            L.check(runner.run(runner.learned, specs[i], dev[i], outs[i][0])[0], "learned")
-
-    ms_plain, _ = time_steps(plain, 2, 1, torch)
-    ms_learn, _ = time_steps(learned, 2, 1, torch)
-    ms_bl, _ = time_steps(batched_learned, 2, 1, torch)
-    rep = model.get("meta", {}).get("report", {})
-    return {"jobs": len(specs), "word_jobs": len(words), "int_jobs": len(ints),
-            "bytes": int(sum(len(b) for b in bufs)),
+    bjob = Job(device=0, strategy=L.STRAT_LEARNED)
+    S.load_model(bjob)
+    ents = []
+    for sp, d, b in zip(specs, dev, bufs):
+        if sp.kind == "words":
+            ents.append({"kind": "words", "data": d, "cap_keys": min(len(b) // 2 + 1, sp.card + 16), "cap_bytes": len(b)})
+        else:
+            sumop = sp.op == "sum"
+            n = len(b) // (8 if sumop else 4)
+            ents.append({"kind": "u32_kv" if sumop else "u32", "data": d, "op": L.REDUCE_SUM if sumop else L.REDUCE_COUNT,
+                         "key_range": sp.card if sp.declare_range else 0, "cap_keys": max(1, min(n, sp.card))})
+    prep = bjob.batch_prepare_mixed(ents)
+    ms_plain, _ = time_steps(per_job("rule", runner.rule), 3, 1, torch)
+    ms_learn, _ = time_steps(per_job("learned", runner.learned), 3, 1, torch)
+    ms_batch, _ = time_steps(lambda: bjob.batch_run(prep), 3, 1, torch)
+    # identical outputs: plain rule, learned, batched learned
+    same = True
+    for i, sp in enumerate(specs):
+        r = Job.batch_result(prep, i)
+        for name in ("rule", "learned"):
+            o, keep = outs[name][i]
+            nk = int(o.n_keys)
+            if sp.kind == "words":
+                kb, ko, v = keep
+                same &= (torch.equal(kb[:o.key_bytes_used], r.key_bytes) and torch.equal(ko[:nk + 1], r.key_offsets)
+                         and torch.equal(v[:nk], r.values))
+            else:
+                k, v = keep
+                same &= torch.equal(k[:nk], r.keys) and torch.equal(v[:nk], r.values)
+    idx = {s_: j for j, s_ in enumerate(S.STRATS)}
+    ch_learned = np.array([idx[strat_used[("learned", i)]] for i in range(len(specs))])
+    ch_rule = np.array([idx[strat_used[("rule", i)]] for i in range(len(specs))])
+    r_l = S.regret(T, feas, ch_learned)
+    r_r = S.regret(T, feas, ch_rule)
+    ints = np.array([sp.kind == "u32" for sp in specs])
+    return {"jobs": len(specs), "word_jobs": int((~ints).sum()), "int_jobs": int(ints.sum()),
+            "bytes": int(sum(len(b) for b in bufs)), "size_range_mib": [1, size_hi],
             "plain_rule_jobs_per_s": len(specs) / (ms_plain * 1e-3),
             "learned_jobs_per_s": len(specs) / (ms_learn * 1e-3),
-            "batched_learned_jobs_per_s": len(specs) / (ms_bl * 1e-3),
-            "speedup_batched_learned_vs_plain": ms_plain / ms_bl,
-            "heldout_regret_learned_mean": rep.get("regret_learned_mean"),
-            "heldout_regret_rule_mean": rep.get("regret_rule_mean"),
-            "heldout_regret_learned_p95": rep.get("regret_learned_p95"),
-            "heldout_regret_rule_p95": rep.get("regret_rule_p95"),
-            "trained_on": "1,500 of 2,000 seeded jobs, sizes 1-16 MiB (measured by the runtime on this GPU model)"}
+            "batched_learned_jobs_per_s": len(specs) / (ms_batch * 1e-3),
+            "speedup_learned_vs_rule_per_job": ms_plain / ms_learn,
+            "speedup_batched_vs_per_job_learned": ms_learn / ms_batch,
+            "speedup_batched_learned_vs_plain_rule": ms_plain / ms_batch,
+            "regret_learned_mean": float(r_l.mean()), "regret_learned_p95": float(np.quantile(r_l, 0.95)),
+            "regret_rule_mean": float(r_r.mean()), "regret_rule_p95": float(np.quantile(r_r, 0.95)),
+            "regret_learned_int_mean": float(r_l[ints].mean()) if ints.any() else None,
+            "regret_rule_int_mean": float(r_r[ints].mean()) if ints.any() else None,
+            "outputs_identical": bool(same),
+            "regret_source": "container times measured in this run (median of 3 after a warm-up) on these held-out jobs"}
 
 
 def bench_hist16m(torch, steps=5):
@@ -292,19 +369,52 @@ def measured_traffic():
         return None
 
 
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline_rgb(buf):
+    """The C++ oracle on the host: one core over the whole 1 GiB input, and P
+    threads (the cores this process may use, at most 16) each over a
+    contiguous pixel-aligned part, bins added (the oracle call releases the
+    GIL). Each leg runs for about 10 s."""
+    import numpy as np
+    from concurrent.futures import ThreadPoolExecutor
+
     import oracle
     oracle.rgb(buf[:3 * 1024])  # load
     reps = 0
     t0 = time.perf_counter()
     while True:
-        oracle.rgb(buf)
+        ref = oracle.rgb(buf)
         reps += 1
-        if time.perf_counter() - t0 > 12.0 or reps >= 16:
+        if time.perf_counter() - t0 > 10.0 or reps >= 16:
             break
-    dt = (time.perf_counter() - t0) / reps
-    return {"value": len(buf) / dt / 1e9, "unit": "GB/s", "cores": 1, "kind": "oracle",
-            "sample": f"full 1 GiB input, {reps} pass(es) of the sequential C++ oracle"}
+    one = len(buf) / ((time.perf_counter() - t0) / reps) / 1e9
+    P = max(1, min(16, len(os.sched_getaffinity(0))))
+    px = len(buf) // 3
+    cuts = [3 * (px * k // P) for k in range(P + 1)]
+    parts = [buf[cuts[k]:cuts[k + 1]] for k in range(P)]
+    reps_p = 0
+    with ThreadPoolExecutor(P) as ex:
+        t0 = time.perf_counter()
+        while True:
+            tot = sum(ex.map(oracle.rgb, parts))
+            reps_p += 1
+            if time.perf_counter() - t0 > 10.0 or reps_p >= 200:
+                break
+        dt = (time.perf_counter() - t0) / reps_p
+    assert np.array_equal(tot, ref), "the parallel oracle legs disagree"
+    return {"value": len(buf) / dt / 1e9, "unit": "GB/s", "cores": P, "kind": "oracle",
+            "sample": f"full 1 GiB input: {reps_p} pass(es) of the C++ oracle on {P} threads over contiguous parts "
+                      f"(bins added); one core: {reps} pass(es)",
+            "single_core_value": one, "cpu_model": cpu_model()}
 
 
 def main():
@@ -314,6 +424,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--apps", default="rgb,words8,words512,kmeans,hist16m,bloom,links,batched,selector")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--wave-combine", type=int, default=0, help="word jobs: the wave-level combiner (0 or 1)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
@@ -322,16 +433,18 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     apps = set(args.apps.split(","))
 
+    scratch = torch.empty(1 << 30, dtype=torch.uint8, device="cuda:0")  # cold-cache reps read and write it
     log("rgb: generating 1 GiB")
-    rgb, rgb_buf = bench_rgb(torch, args.steps, args.warmup)
-    log(f"rgb: {rgb['GBps']:.1f} GB/s (kernel {rgb['kernel_GBps']:.1f} GB/s)")
+    rgb, rgb_buf = bench_rgb(torch, args.steps, args.warmup, scratch)
+    log(f"rgb: {rgb['GBps']:.1f} GB/s (mr_run {rgb['mr_run_GBps']:.1f}, kernel {rgb['kernel_GBps']:.1f}, "
+        f"cold median {rgb['cold_median_GBps']:.1f} GB/s)")
     per_app = {"rgb_histogram_1GiB": rgb}
     if "words8" in apps:
-        w = bench_words(torch, 8 << 20, args.steps, args.warmup)
+        w = bench_words(torch, 8 << 20, args.steps, args.warmup, scratch, combine=args.wave_combine)
         per_app["word_count_8MiB"] = w
         log(f"words 8 MiB: {w['GBps']:.1f} GB/s, map {w['map_kernel_GBps']:.1f} GB/s")
     if "words512" in apps:
-        w = bench_words(torch, 512 << 20, max(3, args.steps // 4), 2)
+        w = bench_words(torch, 512 << 20, max(3, args.steps // 4), 2, scratch, combine=args.wave_combine)
         per_app["word_count_512MiB"] = w
         log(f"words 512 MiB: {w['GBps']:.1f} GB/s, map {w['map_kernel_GBps']:.1f} GB/s")
 
@@ -347,8 +460,9 @@ def main():
     if "selector" in apps:
         sl = bench_selector(torch)
         per_app["selector_heldout_jobs"] = sl
-        log(f"selector: batched+learned {sl['batched_learned_jobs_per_s']:.0f} jobs/s vs plain rule "
-            f"{sl['plain_rule_jobs_per_s']:.0f} jobs/s")
+        log(f"selector: batched+learned {sl['batched_learned_jobs_per_s']:.0f} jobs/s, learned "
+            f"{sl['learned_jobs_per_s']:.0f}, plain rule {sl['plain_rule_jobs_per_s']:.0f} jobs/s; regret learned "
+            f"{sl['regret_learned_mean']:.3f} rule {sl['regret_rule_mean']:.3f}; identical {sl['outputs_identical']}")
 
     if "hist16m" in apps:
         h = bench_hist16m(torch)
@@ -392,7 +506,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "rgb_histogram_1GiB", "pixels": n // 3, "bytes": n,
                    "distribution": "3 clipped Gaussians, means 40/128/210, sd 25, seed 2",
-                   "output": "3x256 uint64 bins"},
+                   "output": "3x256 uint64 bins", "entry_point": "mr_rgb_hist_static"},
         "roofline": roof,
         "cpu_baseline": cpu,
         "per_app": per_app,

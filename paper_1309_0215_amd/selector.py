@@ -267,7 +267,7 @@ def main(argv=None):
     ap = argparse.ArgumentParser(description="train the reduce-strategy selector on measured timings")
     ap.add_argument("--n-jobs", type=int, default=2000)
     ap.add_argument("--n-train", type=int, default=1500)
-    ap.add_argument("--size-hi-mib", type=int, default=32)
+    ap.add_argument("--size-hi-mib", type=int, default=64)
     ap.add_argument("--epochs", type=int, default=500)
     ap.add_argument("--reps", type=int, default=2)
     ap.add_argument("--out", default="selector_out")
@@ -305,7 +305,8 @@ def main(argv=None):
     r_r = regret(T[test_idx], feas[test_idx], ch_rule)
     save_model(model, os.path.join(args.out, "selector_weights.json"),
                meta={"n_jobs": len(specs), "n_train": int(len(train_idx)), "size_hi_mib": args.size_hi_mib,
-                     "epochs": args.epochs, "final_loss": hist[-1]})
+                     "epochs": args.epochs, "final_loss": hist[-1],
+                     "command": "python -m paper_1309_0215_amd.selector " + " ".join(argv or sys.argv[1:])})
     # held-out jobs/s: rule-selected vs learned-selected, one mr_run per job, inputs resident
     load_model(runner.learned, os.path.join(args.out, "selector_weights.json"))
     tspecs = [specs[i] for i in test_idx]
@@ -331,6 +332,14 @@ def main(argv=None):
     }
     with open(os.path.join(args.out, "report.json"), "w") as f:
         json.dump(report, f, indent=1)
+    # the held-out jobs' features and measured container times: the table the
+    # regret test replays (learned choices from the device, rule choices as run)
+    heldout = {"features": np.round(X[test_idx], 6).tolist(), "times_ms": np.where(np.isfinite(T[test_idx]),
+                                                                                    T[test_idx], -1.0).round(6).tolist(),
+               "feasible": feas[test_idx].astype(int).tolist(), "rule_choice": ch_rule.tolist(),
+               "kind": [specs[i].kind for i in test_idx], "size_range_mib": [1, args.size_hi_mib]}
+    with open(os.path.join(args.out, "selector_heldout.json"), "w") as f:
+        json.dump(heldout, f)
     print(json.dumps(report))
 
 

@@ -291,3 +291,14 @@ def test_wave_combiner_records_and_hand_cases(torch):
     rng = np.random.default_rng(5)
     offs = np.concatenate([[0], np.sort(rng.integers(0, len(buf) + 1, 999)), [len(buf)]]).astype(np.int64)
     _check(job.words(_dev(torch, buf), _dev(torch, offs)), buf, offs.astype(np.uint64))
+
+
+def test_sort_spill_path(torch):
+    """About 2.7 M distinct words: more than the 1024 sort buckets of 2048
+    records hold in LDS, so buckets are sorted in global memory (counted in
+    stats.sort_spills); the output still equals the oracle's."""
+    from paper_1309_0215_amd import Job
+    buf = gen.text(91, 48 << 20, V=4_000_000, s=0.0, lmin=4, lmax=16)
+    res = Job(device=0).words(_dev(torch, buf))
+    assert res.stats["sort_spills"] > 0
+    _check(res, buf)
