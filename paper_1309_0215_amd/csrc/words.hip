@@ -114,9 +114,11 @@ MR_DEV int input_cmp(const uint8_t* in, uint64_t oa, uint64_t ob, uint64_t s, ui
 // three multiplies. It places the key in the LDS cache, and key_hash16
 // extends it for the global table.
 MR_DEV uint32_t lds_hash32(uint4 k, uint32_t len, uint32_t debug_hash) {
-  if (debug_hash) return len * 0x9E3779B1u;
-  const uint32_t a = (k.x ^ __builtin_amdgcn_alignbit(k.z, k.z, 16)) * 0x9E3779B1u;
-  const uint32_t b = (k.y ^ __builtin_amdgcn_alignbit(k.w, k.w, 16) ^ len) * 0x85EBCA77u;
+  // forced collisions (debug_hash): the key bytes are left out, so every key
+  // of one length gets one hash (a mask, not a branch, keeps the code straight)
+  const uint32_t keep = debug_hash ? 0u : ~0u;
+  const uint32_t a = ((k.x ^ __builtin_amdgcn_alignbit(k.z, k.z, 16)) & keep) * 0x9E3779B1u;
+  const uint32_t b = (((k.y ^ __builtin_amdgcn_alignbit(k.w, k.w, 16)) & keep) ^ len) * 0x85EBCA77u;
   uint32_t h = a ^ __builtin_amdgcn_alignbit(b, b, 15);
   h ^= h >> 16;
   h *= 0x7FEB352Du;
@@ -291,8 +293,10 @@ __global__ void k_words_prep(const WordJob* __restrict__ jobs, uint32_t n_jobs) 
 // Probe groups: 4 consecutive slots whose tags are read with one 16-byte LDS
 // load. A word visits at most kLdsGroups groups before it goes global.
 constexpr int kLdsGroups = 4;
-// Word descriptors a wave lists per round (more words take more rounds).
-constexpr uint32_t kListCap = 256;
+// Word descriptors a wave lists per round: a window's 992 owned bytes hold at
+// most 497 word starts (each but the first follows a separator), so one round
+// takes every window; record boundaries can add starts, which take more rounds.
+constexpr uint32_t kListCap = 512;
 
 template <int kSlotsLog2>
 struct LdsTable {
@@ -303,6 +307,16 @@ struct LdsTable {
   uint32_t off[kSlots];   // offset of one occurrence, for the global flush
 };
 
+
+// Zero exactly when the two 16-byte keys are equal. The final OR is one
+// three-input instruction the compiler cannot see through: written as plain
+// code, the OR of the XORs is turned into four compares whose results are
+// packed into a bit mask with 16-bit operations.
+MR_DEV uint32_t key_diff(uint4 a, uint4 b) {
+  uint32_t d;
+  asm("v_or3_b32 %0, %1, %2, %3" : "=v"(d) : "v"(a.x ^ b.x), "v"(a.y ^ b.y), "v"((a.z ^ b.z) | (a.w ^ b.w)));
+  return d;
+}
 
 // Bucketed linear probing: a group is searched for the key; a group with an
 // empty slot ends the search (slots fill in order and are never freed, so the
@@ -328,8 +342,7 @@ MR_DEV int lds_insert(LdsTable<L>& T, uint32_t* used, uint32_t limit, uint32_t t
     for (uint32_t rm = match & ready; rm; rm &= rm - 1u) {
       const uint32_t i = 4 * g + (uint32_t)__builtin_ctz(rm);
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");  // key bytes after the ready tag
-      const uint4 kk = T.key[i];
-      if (((kk.x ^ k.x) | (kk.y ^ k.y) | (kk.z ^ k.z) | (kk.w ^ k.w)) == 0u) {
+      if (key_diff(T.key[i], k) == 0u) {
         atomicAdd(&T.cnt[i], v);
         return 0;
       }
@@ -349,36 +362,6 @@ MR_DEV int lds_insert(LdsTable<L>& T, uint32_t* used, uint32_t limit, uint32_t t
     g = (g + 1) & kGroupMask;
   }
   return 2;
-}
-
-// The map's cache lookup, straight-line code for the whole wave. The map
-// places a key only in its home group (four slots): a key whose group filled
-// up before it came is not cached and goes to the global table, so every
-// lookup is one 16-byte tag read, and the keys that miss are the ones first
-// seen late, the colder ones. Returns 0 = counted (a ready slot holds the
-// key), 2 = not cached (the group is full without it), 3 = undecided (a free
-// slot to claim, a slot still being written, or a tag that matched another
-// key): the caller runs lds_insert on the home group.
-template <int L>
-MR_DEV int lds_probe_home(LdsTable<L>& T, uint32_t tg, uint32_t h, uint4 k, uint32_t v) {
-  constexpr uint32_t kGroupMask = LdsTable<L>::kSlots / 4 - 1;
-  const uint32_t g = h & kGroupMask;
-  const uint4 t4 = reinterpret_cast<const uint4*>(T.tag)[g];
-  const uint32_t tq = tg | 1u;
-  const uint32_t c = t4.x == tq ? 0u : (t4.y == tq ? 1u : (t4.z == tq ? 2u : (t4.w == tq ? 3u : 4u)));
-  const bool pend = t4.x == tg || t4.y == tg || t4.z == tg || t4.w == tg;
-  const bool empty = t4.x == 0u || t4.y == 0u || t4.z == 0u || t4.w == 0u;
-  if (c < 4u) {
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");  // key bytes after the ready tag
-    const uint32_t i = 4u * g + c;
-    const uint4 kk = T.key[i];
-    if (((kk.x ^ k.x) | (kk.y ^ k.y) | (kk.z ^ k.z) | (kk.w ^ k.w)) == 0u) {
-      atomicAdd(&T.cnt[i], v);
-      return 0;
-    }
-    return 3;
-  }
-  return (!pend && !empty) ? 2 : 3;
 }
 
 template <int L>
@@ -532,7 +515,10 @@ __global__ __launch_bounds__(kMapThreads) void k_words_map(const WordJob* __rest
   constexpr uint32_t kWaves = kMapThreads / kWave;
   __shared__ LdsTable<L> T;
   __shared__ uint4 stage[kWaves][kWave];
-  __shared__ uint32_t wlist[kWaves][kListCap];
+  __shared__ __attribute__((aligned(16))) uint16_t wlist[kWaves][kListCap];
+  // byte masks of the inline key lengths (entry n keeps bytes [0, n); the
+  // entries past 16 are all zero)
+  __shared__ __attribute__((aligned(16))) uint32_t s_kmask[64][4];
   constexpr uint32_t kBndWords = kWave * 16 / 32;  // boundary bits of the 1 KiB window
   __shared__ uint32_t bnd[kRecords ? kWaves : 1][kRecords ? kBndWords + 1 : 1];
   __shared__ uint32_t s_used;
@@ -540,6 +526,11 @@ __global__ __launch_bounds__(kMapThreads) void k_words_map(const WordJob* __rest
 
   for (uint32_t i = threadIdx.x; i < LdsTable<L>::kSlots; i += blockDim.x) T.tag[i] = 0u;
   for (uint32_t i = threadIdx.x; i < kFlushParts; i += blockDim.x) s_mfill[i] = 0u;
+  if (threadIdx.x < 256) {
+    const uint32_t n = threadIdx.x >> 2, w = threadIdx.x & 3u;
+    const int keep = n <= 16u ? (int)n - 4 * (int)w : 0;
+    s_kmask[n][w] = keep >= 4 ? ~0u : (keep <= 0 ? 0u : (1u << (8 * keep)) - 1u);
+  }
   if (threadIdx.x == 0) s_used = 0;
   __syncthreads();
 
@@ -564,21 +555,34 @@ __global__ __launch_bounds__(kMapThreads) void k_words_map(const WordJob* __rest
     const int64_t ci = (int64_t)((t - tile_base[jn]) * kMapTileChunks + wave * kOwnChunks) - 1 + (int64_t)lane;
     return (ci >= 0 && (uint64_t)ci < Jn.n_chunks) ? load_block(an0, an1, (Jn.chunk0 + (uint64_t)ci) * 16) : spaces4();
   };
-  // two tiles in flight ahead of the one being processed
-  uint4 nx1 = spaces4(), nx2 = spaces4();
-  if (t_begin < t_end) nx1 = load_part(t_begin);
-  if (t_begin + 1 < t_end) nx2 = load_part(t_begin + 1);
+  // The job's flags, read for the abort test. Every lane reads them at an
+  // address offset by a zero the compiler cannot see through, so the value
+  // stays in a vector register until the test reads its first lane: a value
+  // the compiler knows to be uniform is moved to a scalar register as soon as
+  // it is loaded, which waits for every load issued before it.
+  uint32_t zv;
+  asm("v_mov_b32 %0, 0" : "=v"(zv));
+  auto flags_of = [&](uint64_t t) -> uint32_t {
+    return __hip_atomic_load(gp(&jobs[find_job(tile_base, n_jobs, t)].st->flags + zv), __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+  };
+  // Tiles are prefetched two ahead into two register sets used in turn (the
+  // tile body below is emitted once for each), so that moving on to the next
+  // tile takes no register copy: copying a register whose load is still in
+  // flight waits for that load. For the same reason the flags for the next
+  // tile are read before its prefetch is issued and tested one tile later.
+  uint4 pa = spaces4(), pb = spaces4();
+  if (t_begin < t_end) pa = load_part(t_begin);
+  if (t_begin + 1 < t_end) pb = load_part(t_begin + 1);
+  uint32_t fl_next = t_begin < t_end ? flags_of(t_begin) : 0u;
 
-  for (uint64_t t = t_begin; t < t_end; ++t) {
-    const uint4 b0 = nx1;
-    nx1 = nx2;
-    if (t + 2 < t_end) nx2 = load_part(t + 2);
+  auto tile = [&](uint64_t t, uint4& buf) {
     const uint32_t j = find_job(tile_base, n_jobs, t);
     if ((int)j != cur) {
       // every wave meets this point at the same tile
       __syncthreads();
       if (cur >= 0) {
-        if (jobs[cur].queue) lds_flush_parts<L>(T, jobs[cur], &wlist[0][0], vlo, vhi, debug_hash);
+        if (jobs[cur].queue) lds_flush_parts<L>(T, jobs[cur], reinterpret_cast<uint32_t*>(&wlist[0][0]), vlo, vhi, debug_hash);
         else lds_flush<L>(T, jobs[cur], vlo, vhi, debug_hash);
         if (threadIdx.x == 0) s_used = 0;
         __syncthreads();
@@ -588,9 +592,7 @@ __global__ __launch_bounds__(kMapThreads) void k_words_map(const WordJob* __rest
       vhi = gp(jobs[j].st)->valid_hi;
     }
     const WordJob& J = jobs[j];
-    const bool abort =
-        (__hip_atomic_load(gp(&J.st->flags), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & (kFlagTableFull | kFlagBadInput)) != 0;
-    if (abort) continue;  // uniform over the wave
+    const uint32_t fl = fl_next;
     const uint64_t lt = t - tile_base[j];
     const uint64_t a0 = (uint64_t)J.in;
     // absolute address of the window's first byte (lane 0's chunk)
@@ -624,8 +626,12 @@ __global__ __launch_bounds__(kMapThreads) void k_words_map(const WordJob* __rest
     }
 
     // 1. the window into LDS; separator masks
-    ws[lane] = b0;
-    uint32_t sep = sep16(b0);
+    ws[lane] = buf;
+    uint32_t sep = sep16(buf);
+    // buf is free: the tile two ahead goes into it, after the flags for the next tile
+    if (t + 1 < t_end) fl_next = flags_of(t + 1);
+    if (t + 2 < t_end) buf = load_part(t + 2);
+    if (__builtin_amdgcn_readfirstlane(fl) & (kFlagTableFull | kFlagBadInput)) return;  // uniform over the wave
     // bytes outside the valid range count as separators (only windows that
     // reach past it need the per-lane check)
     if (win < a0 + vlo || win + 16ull * kWave > a0 + vhi) {
@@ -644,113 +650,159 @@ __global__ __launch_bounds__(kMapThreads) void k_words_map(const WordJob* __rest
     const uint32_t first = incl - n_mine;
     wave_sync();  // the window copy is complete
 
-    // 3. rounds of up to kListCap words, one word per lane
+    // 3. rounds of up to kListCap words, two words per lane per step.
+    // Descriptor: offset in the window << 6 | length, where 17..32 mark a word
+    // longer than 16 bytes (no end within the 16 bytes after its start; bit 31
+    // of the shifted end mask stands in for "no end", giving 32).
+    uint16_t* const wl = wlist[wave];
+    const uint32_t ends1 = (ends >> 1) | 0x80000000u;
+    const uint32_t lane16 = lane * 16u;
     for (uint32_t base = 0; base < total; base += kListCap) {
-      uint32_t p = first;
-      for (uint32_t m = starts; m; m &= m - 1u, ++p) {
-        if (p < base || p >= base + kListCap) continue;
-        const uint32_t s = __builtin_ctz(m);
-        const uint32_t after = ends & ~((2u << s) - 1u);
-        const uint32_t len = after ? (uint32_t)__builtin_ctz(after) - s : 32u;
-        wlist[wave][p - base] = ((lane * 16u + s) << 5) | (len <= 16u ? len : 31u);
+      {
+        uint32_t p = first - base;  // entries outside [0, kListCap) belong to other rounds
+        auto put = [&](uint32_t m) {
+          const uint32_t s = __builtin_ctz(m);
+          const uint32_t len = (uint32_t)__builtin_ctz(ends1 >> s) + 1u;
+          wl[p] = (uint16_t)(((lane16 + s) << 6) | len);
+        };
+        if (total <= kListCap) {  // uniform: the whole list fits this round
+          for (uint32_t m = starts; m; m &= m - 1u, ++p) put(m);
+        } else {
+          for (uint32_t m = starts; m; m &= m - 1u, ++p)
+            if (p < kListCap) put(m);
+        }
       }
       wave_sync();
       const uint32_t nr = (total - base) < kListCap ? (total - base) : kListCap;
-      // the word at list entry d: key bytes from the wave's copy of the window
-      auto key_at = [&](uint32_t d, uint4& k, uint32_t& len, uint32_t& o) {
-        o = (d >> 5) & 0x3FFu;
-        len = d & 31u;
-        // 16 bytes at any byte offset of the copy (LDS reads need no alignment
-        // here); o <= 62 * 16 + 15, so the read ends inside the wave's 1 KiB
-        const u32x4_u x = *reinterpret_cast<const u32x4_u*>(reinterpret_cast<const uint8_t*>(ws) + o);
-        k = make_uint4(keep_bytes(x[0], (int)len), keep_bytes(x[1], (int)len - 4), keep_bytes(x[2], (int)len - 8),
-                       keep_bytes(x[3], (int)len - 12));
-      };
-      // LDS inserts; the words the cache cannot take are marked (bit u: entry lane + 64 u)
-      constexpr uint32_t kPerLane = kListCap / kWave;
-      uint32_t missed = 0u;
-      uint32_t vcnt[kPerLane];
-#pragma unroll
-      for (uint32_t u = 0; u < kPerLane; ++u) {
-        vcnt[u] = 1u;
-        const uint32_t i = lane + u * kWave;
-        if (base + u * kWave >= total) break;  // uniform: no word left for any lane
-        const bool has = i < nr;
-        const uint32_t d = has ? wlist[wave][i] : 0u;
-        uint4 k;
-        uint32_t len, o;
-        key_at(d, k, len, o);
-        const bool inl = has && len <= 16u;
-        if (has && !inl) {
-          // a word longer than 16 bytes: measured, hashed and inserted from the input
-          const uint64_t off = (uint64_t)(win_off + o);
-          const uint64_t wl = word_length_slow(J, vlo, vhi, off);
-          g_insert<false>(J, vlo, vhi, off, wl, key_hash_global(J.in, off, wl, debug_hash), make_uint4(0, 0, 0, 0), 1u,
-                          debug_hash);
+      // a word the cache did not take goes to the job's miss queue (or the
+      // global table); a word longer than 16 bytes is measured, hashed and
+      // inserted from the input
+      auto miss = [&](bool lng, uint32_t off, uint32_t len, uint32_t h, uint4 k, uint32_t v) {
+        if (lng) {
+          const uint64_t wlen = word_length_slow(J, vlo, vhi, off);
+          g_insert<false>(J, vlo, vhi, off, wlen, key_hash_global(J.in, off, wlen, debug_hash), make_uint4(0, 0, 0, 0),
+                          1u, debug_hash);
+          return;
         }
-        const uint32_t h = lds_hash32(k, len, debug_hash);
-        uint32_t v = 1u;
-        if constexpr (kCombine) wave_combine_words(inl, h, len, k, v, 4);
-        const uint32_t tg = (h & 0xFFFFFFC0u) | (len << 1);
-        int r = (inl && v) ? lds_probe_home<L>(T, tg, h, k, v) : 0;
-        if (__ballot(r == 3)) {
-          if (r == 3) {
-            r = 1;
-            for (uint32_t spin = 0; r == 1; ++spin) {
-              r = lds_insert<L, 1>(T, &s_used, LdsTable<L>::kSlots, tg, h, k, win_off + o, v);
-              if (r == 1 && spin > (1u << 22)) {
-                __hip_atomic_fetch_or(gp(&J.st->flags), kFlagSpin, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                r = 0;
-              }
-            }
-          }
-        }
-        if (r == 2) missed |= 1u << u;
-        vcnt[u] = v;
-      }
-      // The misses of the whole round are packed to the front of the list and
-      // inserted globally one per lane: the wave then waits on one round of
-      // dependent global probes instead of one per list pass. A packed entry
-      // carries its count (above 1 after the combiner) in bits 16 and up.
-      uint32_t md[kPerLane];
-#pragma unroll
-      for (uint32_t u = 0; u < kPerLane; ++u)
-        md[u] = (missed >> u & 1u) ? ((wlist[wave][lane + u * kWave] & 0xFFFFu) | (vcnt[u] << 16)) : 0u;
-      const uint32_t n_m = __builtin_popcount(missed);
-      const uint32_t incl_m = wave_incl_scan(n_m);
-      const uint32_t total_m = (uint32_t)__builtin_amdgcn_readlane((int)incl_m, kWave - 1);
-      wave_sync();  // every lane has read its entries
-      uint32_t at = incl_m - n_m;
-#pragma unroll
-      for (uint32_t u = 0; u < kPerLane; ++u)
-        if (missed >> u & 1u) wlist[wave][at++] = md[u];
-      wave_sync();
-      for (uint32_t i = lane; i < total_m; i += kWave) {
-        uint4 k;
-        uint32_t len, o;
-        const uint32_t d = wlist[wave][i];
-        key_at(d, k, len, o);
-        const uint32_t off = win_off + o;
-        const uint64_t h = key_hash16(k, len, debug_hash);
+        const uint64_t h64 = hash_from32(h);
         if (J.mq) {
           // into this workgroup's sub-queue of the key's partition
-          const uint32_t q = (uint32_t)(h >> kFlushShift);
+          const uint32_t q = (uint32_t)(h64 >> kFlushShift);
           const uint32_t at = atomicAdd(&s_mfill[q], 1u);
           if (at < J.mq_cap) {
             FlushRec* dst = reinterpret_cast<FlushRec*>(J.mq) + ((uint64_t)q * J.mq_grid + blockIdx.x) * J.mq_cap + at;
             gstore16(&dst->k, k);
-            gstore16(&dst->off, make_uint4(off, len, d >> 16, 0u));
-            continue;
+            gstore16(&dst->off, make_uint4(off, len, v, 0u));
+            return;
           }
         }
-        g_insert<true>(J, vlo, vhi, off, len, h, k, d >> 16, debug_hash);
+        g_insert<true>(J, vlo, vhi, off, len, h64, k, v, debug_hash);
+      };
+      // the home-group lookup could not decide: the full insert, retried
+      // while a slot is being written
+      auto slow = [&](uint32_t tg, uint32_t h, uint4 k, uint32_t off, uint32_t v) -> int {
+        int r = 1;
+        for (uint32_t spin = 0; r == 1; ++spin) {
+          r = lds_insert<L, 1>(T, &s_used, LdsTable<L>::kSlots, tg, h, k, off, v);
+          if (r == 1 && spin > (1u << 22)) {
+            __hip_atomic_fetch_or(gp(&J.st->flags), kFlagSpin, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            r = 0;
+          }
+        }
+        return r;
+      };
+      constexpr uint32_t kGroupMask = LdsTable<L>::kSlots / 4 - 1;
+#pragma unroll 1
+      for (uint32_t i0 = 0; i0 < nr; i0 += 2 * kWave) {
+        // Straight-line code over the step's two words, so that the LDS reads
+        // of one overlap the arithmetic of the other. Key bytes come from the
+        // wave's copy of the window (16 bytes at any byte offset: LDS reads
+        // need no alignment here, and o <= 62 * 16 + 15 keeps the read inside
+        // the wave's 1 KiB), masked to the word's length.
+        uint4 k[2];
+        uint32_t h[2], len[2], o[2], v[2], slot[2];
+        bool has[2], inl[2];
+        int r[2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          const uint32_t i = i0 + lane + u * kWave;  // < kListCap: i0 <= kListCap - 128
+          has[u] = i < nr;
+          const uint32_t d0 = wl[i];
+          const uint32_t d = has[u] ? d0 : 0u;
+          o[u] = d >> 6;
+          len[u] = d & 63u;
+          const u32x4_u x = *reinterpret_cast<const u32x4_u*>(reinterpret_cast<const uint8_t*>(ws) + o[u]);
+          const uint4 mk = *reinterpret_cast<const uint4*>(s_kmask[len[u]]);
+          k[u] = make_uint4(x[0] & mk.x, x[1] & mk.y, x[2] & mk.z, x[3] & mk.w);
+          inl[u] = has[u] && len[u] <= 16u;
+          h[u] = lds_hash32(k[u], len[u], debug_hash);
+          v[u] = 1u;
+        }
+        if constexpr (kCombine) {
+          wave_combine_words(inl[0], h[0], len[0], k[0], v[0], 4);
+          wave_combine_words(inl[1], h[1], len[1], k[1], v[1], 4);
+        }
+        // home group: one 16-byte tag read each, then the key of the slot
+        // whose ready tag matches (read whether or not one does); the steps
+        // go over both words in turn, so that their LDS reads overlap
+        uint4 t4[2];
+        uint32_t c[2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          t4[u] = reinterpret_cast<const uint4*>(T.tag)[h[u] & kGroupMask];
+        }
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          // first slot with the ready tag (4: none); plain selects and bitwise
+          // logic, so that the compiler emits no branches here
+          const uint32_t tq = (h[u] & 0xFFFFFFC0u) | (len[u] << 1) | 1u;
+          const uint32_t c3 = t4[u].w == tq ? 3u : 4u;
+          const uint32_t c2 = t4[u].z == tq ? 2u : c3;
+          const uint32_t c1 = t4[u].y == tq ? 1u : c2;
+          c[u] = t4[u].x == tq ? 0u : c1;
+          slot[u] = 4u * (h[u] & kGroupMask) + (c[u] & 3u);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");  // key bytes after the ready tags
+        uint4 kk[2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) kk[u] = T.key[slot[u]];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          const uint32_t tg = (h[u] & 0xFFFFFFC0u) | (len[u] << 1);
+          const uint32_t kd = key_diff(kk[u], k[u]);
+          const bool go = inl[u] & (v[u] != 0u);
+          const bool hit = go & (c[u] < 4u) & (kd == 0u);
+          if (hit) atomicAdd(&T.cnt[slot[u]], v[u]);
+          // no ready slot with the key: undecided while the group has a free
+          // slot (tag 0), a slot with this tag still being written, or a
+          // ready slot whose tag matched another key
+          const uint4 t = t4[u];
+          const uint32_t free_min = min(min(t.x, t.y), min(t.z, t.w));
+          const uint32_t pend_min = min(min(t.x ^ tg, t.y ^ tg), min(t.z ^ tg, t.w ^ tg));
+          const bool undecided = (c[u] < 4u) | (free_min == 0u) | (pend_min == 0u);
+          r[u] = (go & !hit) ? (undecided ? 3 : 2) : 0;
+        }
+        if (__ballot(r[0] == 3 || r[1] == 3)) {
+#pragma unroll
+          for (int u = 0; u < 2; ++u)
+            if (r[u] == 3) r[u] = slow((h[u] & 0xFFFFFFC0u) | (len[u] << 1), h[u], k[u], win_off + o[u], v[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          const bool lng = has[u] && len[u] > 16u;
+          if (r[u] == 2 || lng) miss(lng, win_off + o[u], len[u], h[u], k[u], v[u]);
+        }
       }
       wave_sync();
     }
+  };
+  for (uint64_t t = t_begin; t < t_end; t += 2) {
+    tile(t, pa);
+    if (t + 1 < t_end) tile(t + 1, pb);
   }
   __syncthreads();
   if (cur >= 0) {
-    if (jobs[cur].queue) lds_flush_parts<L>(T, jobs[cur], &wlist[0][0], vlo, vhi, debug_hash);
+    if (jobs[cur].queue) lds_flush_parts<L>(T, jobs[cur], reinterpret_cast<uint32_t*>(&wlist[0][0]), vlo, vhi, debug_hash);
     else lds_flush<L>(T, jobs[cur], vlo, vhi, debug_hash);
   }
   // the miss sub-queue fills (every workgroup of a single job's map writes
