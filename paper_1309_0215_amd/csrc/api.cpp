@@ -483,20 +483,22 @@ struct WordsPlan {
   std::vector<uint64_t> slot_base, tile_base;
 };
 
-// Records per flush queue for a single job: at most one per LDS cache slot
-// that each of up to n_cu workgroups fills (3/4 of 4096), and at most one per
-// two input bytes, spread over the queues by hash, with slack; a full queue
-// sends its overflow to the global table directly.
-uint32_t flush_queue_cap(uint64_t n, int n_cu) {
-  const uint64_t recs = std::min<uint64_t>((uint64_t)n_cu * 3072, n / 2 + 1);
+// Records per flush queue of a batch of n_jobs jobs and n input bytes (the
+// queues are shared by the batch): a workgroup flushes its LDS cache (3/4 of
+// its 4096 slots filled, typically) once per job it meets, which is at most
+// n_cu + n_jobs flushes in all, and there is at most one record per two input
+// bytes; spread over the queues by hash, with slack. A full queue sends its
+// overflow to the global table directly.
+uint32_t flush_queue_cap(uint64_t n, int n_cu, uint64_t n_jobs) {
+  const uint64_t recs = std::min<uint64_t>(((uint64_t)n_cu + n_jobs) * 3072, n / 2 + 1);
   return (uint32_t)(recs * 3 / 2 / kFlushParts + 256);
 }
 
-// Records per miss sub-queue (one per map workgroup and partition) of a
-// single job: room for half the words of an input of mean word length 8
-// missing the LDS caches, spread evenly, so that a sub-queue rarely fills on
-// text whose cache misses stay below that; a full sub-queue sends its
-// overflow to the global table directly.
+// Records per miss sub-queue (one per map workgroup and partition, shared by
+// the jobs of a batch) for n input bytes: room for half the words of an
+// input of mean word length 8 missing the LDS caches, spread evenly, so that
+// a sub-queue rarely fills on text whose cache misses stay below that; a full
+// sub-queue sends its overflow to the global table directly.
 uint32_t miss_queue_cap(uint64_t n, uint32_t grid) {
   const uint64_t want = n / (16ull * grid * kFlushParts) + 1;
   return (uint32_t)std::min<uint64_t>(4096, std::max<uint64_t>(16, next_pow2(want)));
@@ -538,7 +540,9 @@ WordsPlan plan_words(const std::vector<WordItem>& items, bool slot_ranks, uint32
     p.qcap = qcap;
     p.o_queue = p.c.take(32ull * kFlushParts * qcap);
     p.o_qcnt = p.c.take(4ull * kFlushParts);
-    p.mq_cap = miss_queue_cap(items[0].n, p.grid);
+    uint64_t total_n = 0;
+    for (const WordItem& it : items) total_n += it.n;
+    p.mq_cap = miss_queue_cap(total_n, p.grid);
     p.o_mq = p.c.take(32ull * kFlushParts * p.grid * p.mq_cap);
     p.o_mqfill = p.c.take(4ull * kFlushParts * p.grid);
   }
@@ -576,8 +580,12 @@ uint64_t input_key(const uint8_t* in, uint64_t n) { return fnv_mix(fnv_mix(0xCBF
 mr_status words_pass(mr_job* job, std::vector<WordItem>& items, std::vector<JobState>& states, float* gpu_ms,
                      float* map_ms, GraphMode mode, LinkBufs* lb) {
   const uint32_t n = (uint32_t)items.size();
-  // single word jobs flush their LDS caches in two phases through partition queues
-  const uint32_t qcap = (n == 1 && !lb) ? flush_queue_cap(items[0].n, job->n_cu) : 0u;
+  // word jobs flush their LDS caches and send their cache misses through
+  // partition queues (shared by the jobs of a batch); the two-phase flush
+  // then sums them per partition
+  uint64_t total_n = 0;
+  for (const WordItem& it : items) total_n += it.n;
+  const uint32_t qcap = !lb ? flush_queue_cap(total_n, job->n_cu, n) : 0u;
   // tuned map parameters, looked up by the bytes this launch covers (a
   // batch by its total; each job's table load factor by its own size)
   uint64_t size_key = 0;
@@ -1646,7 +1654,7 @@ extern "C" mr_status mr_workspace_bytes(const mr_job_config* cfg, mr_map_kind ki
       std::vector<WordItem> items(1);
       items[0] = WordItem{reinterpret_cast<const uint8_t*>(15), n, nullptr, 0, nullptr, initial_slots(&tmp, n, n)};
       const uint64_t grid_cap = std::max<uint64_t>(1, (uint64_t)n_cu * eff_grid_pct(&tmp, n) / 100);
-      r.add(plan_words(items, false, flush_queue_cap(n, n_cu), grid_cap).c.off);
+      r.add(plan_words(items, false, flush_queue_cap(n, n_cu, 1), grid_cap).c.off);
       break;
     }
     case MR_MAP_RGB_HIST:

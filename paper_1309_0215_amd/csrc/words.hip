@@ -266,7 +266,7 @@ __global__ void k_words_prep(const WordJob* __restrict__ jobs, uint32_t n_jobs) 
   const uint32_t j = blockIdx.y;
   if (j >= n_jobs) return;
   const WordJob J = jobs[j];
-  if (J.qcnt && blockIdx.x == 0)
+  if (J.qcnt && j == 0 && blockIdx.x == 0)  // the queues are shared by the batch
     for (uint32_t p = threadIdx.x; p < kFlushParts; p += blockDim.x) J.qcnt[p] = 0u;
   if (!J.rec) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -324,9 +324,11 @@ MR_DEV uint32_t key_diff(uint4 a, uint4 b) {
 // table has reached its fill limit.
 // Returns 0 = counted, 1 = a matching slot is still being written or the
 // claim was lost (retry), 2 = not in the table and not inserted (go global).
+// With a job array (the summing of a batch's queues), a slot holds a key of
+// one job: equality takes the job index too.
 template <int L, int kGroups = kLdsGroups>
 MR_DEV int lds_insert(LdsTable<L>& T, uint32_t* used, uint32_t limit, uint32_t tg, uint32_t h, uint4 k, uint32_t off,
-                      uint32_t v = 1u) {
+                      uint32_t v = 1u, uint32_t* slot_job = nullptr, uint32_t job = 0u) {
   constexpr uint32_t kGroupMask = LdsTable<L>::kSlots / 4 - 1;
   uint32_t g = h & kGroupMask;
   for (int p = 0; p < kGroups; ++p) {
@@ -342,7 +344,7 @@ MR_DEV int lds_insert(LdsTable<L>& T, uint32_t* used, uint32_t limit, uint32_t t
     for (uint32_t rm = match & ready; rm; rm &= rm - 1u) {
       const uint32_t i = 4 * g + (uint32_t)__builtin_ctz(rm);
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");  // key bytes after the ready tag
-      if (key_diff(T.key[i], k) == 0u) {
+      if (key_diff(T.key[i], k) == 0u && (!slot_job || slot_job[i] == job)) {
         atomicAdd(&T.cnt[i], v);
         return 0;
       }
@@ -355,6 +357,7 @@ MR_DEV int lds_insert(LdsTable<L>& T, uint32_t* used, uint32_t limit, uint32_t t
       T.key[i] = k;
       T.off[i] = off;
       T.cnt[i] = v;
+      if (slot_job) slot_job[i] = job;
       __hip_atomic_store(&T.tag[i], tg | 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
       atomicAdd(used, 1u);
       return 0;
@@ -378,19 +381,21 @@ MR_DEV void lds_flush(LdsTable<L>& T, const WordJob& J, uint64_t vlo, uint64_t v
   }
 }
 
-// One record of a flush queue: an LDS cache entry (key bytes as loaded,
-// length, offset of an occurrence, count).
+// One record of a partition queue: key bytes as loaded, offset of an
+// occurrence, length, count, and the index of the job in its batch (the
+// queues of a batch are shared by its jobs).
 struct FlushRec {
   uint4 k;
-  uint32_t off, len, cnt, pad;
+  uint32_t off, len, cnt, job;
 };
 
 // Two-phase flush, first phase: the workgroup's cache entries go to the
-// job's queues by the top bits of their hash, with one global reservation per
-// queue; an entry that finds its queue full is inserted globally at once.
-// pc: LDS scratch [2 * kFlushParts]. Called by the whole workgroup.
+// partition queues by the top bits of their hash, with one global
+// reservation per queue; an entry that finds its queue full is inserted
+// globally at once. J is job `job` of the batch. pc: LDS scratch
+// [2 * kFlushParts]. Called by the whole workgroup.
 template <int L>
-MR_DEV void lds_flush_parts(LdsTable<L>& T, const WordJob& J, uint32_t* pc, uint64_t vlo, uint64_t vhi,
+MR_DEV void lds_flush_parts(LdsTable<L>& T, const WordJob& J, uint32_t job, uint32_t* pc, uint64_t vlo, uint64_t vhi,
                             uint32_t debug_hash) {
   for (uint32_t p = threadIdx.x; p < kFlushParts; p += blockDim.x) pc[p] = 0;
   __syncthreads();
@@ -417,7 +422,7 @@ MR_DEV void lds_flush_parts(LdsTable<L>& T, const WordJob& J, uint32_t* pc, uint
       if (at < J.qcap) {
         FlushRec* dst = &q[(uint64_t)p * J.qcap + at];
         gstore16(&dst->k, k);
-        gstore16(&dst->off, make_uint4(T.off[i], len, T.cnt[i], 0u));
+        gstore16(&dst->off, make_uint4(T.off[i], len, T.cnt[i], job));
       } else {
         g_insert<true>(J, vlo, vhi, T.off[i], len, h, k, T.cnt[i], debug_hash);
       }
@@ -582,7 +587,8 @@ __global__ __launch_bounds__(kMapThreads) void k_words_map(const WordJob* __rest
       // every wave meets this point at the same tile
       __syncthreads();
       if (cur >= 0) {
-        if (jobs[cur].queue) lds_flush_parts<L>(T, jobs[cur], reinterpret_cast<uint32_t*>(&wlist[0][0]), vlo, vhi, debug_hash);
+        if (jobs[cur].queue)
+          lds_flush_parts<L>(T, jobs[cur], (uint32_t)cur, reinterpret_cast<uint32_t*>(&wlist[0][0]), vlo, vhi, debug_hash);
         else lds_flush<L>(T, jobs[cur], vlo, vhi, debug_hash);
         if (threadIdx.x == 0) s_used = 0;
         __syncthreads();
@@ -692,7 +698,7 @@ __global__ __launch_bounds__(kMapThreads) void k_words_map(const WordJob* __rest
           if (at < J.mq_cap) {
             FlushRec* dst = reinterpret_cast<FlushRec*>(J.mq) + ((uint64_t)q * J.mq_grid + blockIdx.x) * J.mq_cap + at;
             gstore16(&dst->k, k);
-            gstore16(&dst->off, make_uint4(off, len, v, 0u));
+            gstore16(&dst->off, make_uint4(off, len, v, j));
             return;
           }
         }
@@ -802,66 +808,79 @@ __global__ __launch_bounds__(kMapThreads) void k_words_map(const WordJob* __rest
   }
   __syncthreads();
   if (cur >= 0) {
-    if (jobs[cur].queue) lds_flush_parts<L>(T, jobs[cur], reinterpret_cast<uint32_t*>(&wlist[0][0]), vlo, vhi, debug_hash);
+    if (jobs[cur].queue)
+          lds_flush_parts<L>(T, jobs[cur], (uint32_t)cur, reinterpret_cast<uint32_t*>(&wlist[0][0]), vlo, vhi, debug_hash);
     else lds_flush<L>(T, jobs[cur], vlo, vhi, debug_hash);
   }
-  // the miss sub-queue fills (every workgroup of a single job's map writes
-  // all of its entries, zero or not, so nothing needs clearing before)
+  // the miss sub-queue fills (the sub-queues are shared by the jobs of a
+  // batch; every workgroup writes all of its entries, zero or not, so
+  // nothing needs clearing before)
   const WordJob& J0 = jobs[0];
-  if (n_jobs == 1 && J0.mq)
+  if (J0.mq)
     for (uint32_t q = threadIdx.x; q < kFlushParts; q += blockDim.x) {
       const uint32_t f = s_mfill[q];
       J0.mq_fill[q * J0.mq_grid + blockIdx.x] = f < J0.mq_cap ? f : J0.mq_cap;
     }
 }
 
-// Two-phase flush, second phase: one workgroup per queue of job 0 sums the
-// queue's records by key in an LDS table and inserts each key globally once,
-// so the keys that every workgroup caches no longer meet on one global slot
+// Two-phase flush, second phase: one workgroup per partition sums the
+// records of its flush queue and of every map workgroup's miss sub-queue by
+// (job, key) in an LDS table and inserts each key into its job's table once,
+// so that the keys every workgroup meets no longer meet on one global slot
 // from every workgroup. Records that find the LDS table full are inserted
 // globally as they come.
 template <int L>
 __global__ __launch_bounds__(kMapThreads) void k_words_parts(const WordJob* __restrict__ jobs, uint32_t debug_hash) {
   __shared__ LdsTable<L> T;
+  __shared__ uint32_t s_job[LdsTable<L>::kSlots];
   __shared__ uint32_t s_used;
   constexpr uint32_t kLimit = LdsTable<L>::kSlots / 4 * 3;
-  const WordJob& J = jobs[0];
+  const WordJob& Q = jobs[0];  // the queues (shared by the jobs of a batch)
   const uint32_t p = blockIdx.x;
   for (uint32_t i = threadIdx.x; i < LdsTable<L>::kSlots; i += blockDim.x) T.tag[i] = 0u;
   if (threadIdx.x == 0) s_used = 0;
   __syncthreads();
-  const uint64_t vlo = gp(J.st)->valid_lo, vhi = gp(J.st)->valid_hi;
   // one record: summed into the LDS table, or inserted globally when it is full
   auto consume = [&](const FlushRec* rp) {
     const uint4 k = gload16(&rp->k);
-    const uint4 m = gload16(&rp->off);
-    const uint32_t h32 = lds_hash32(k, m.y, debug_hash);
+    const uint4 m = gload16(&rp->off);  // off, len, count, job
+    const uint32_t hk = lds_hash32(k, m.y, debug_hash);
+    // the LDS placement mixes in the job; the global table takes the key's own hash
+    const uint32_t h32 = hk ^ (m.w * 0x9E3779B1u);
     const uint32_t tg = (h32 & 0xFFFFFFC0u) | (m.y << 1);
     int r = 1;
     for (uint32_t spin = 0; r == 1; ++spin) {
-      r = lds_insert<L>(T, &s_used, kLimit, tg, h32, k, m.x, m.z);
+      r = lds_insert<L>(T, &s_used, kLimit, tg, h32, k, m.x, m.z, s_job, m.w);
       if (r == 1 && spin > (1u << 22)) {
-        __hip_atomic_fetch_or(gp(&J.st->flags), kFlagSpin, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_or(gp(&jobs[m.w].st->flags), kFlagSpin, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         r = 0;
       }
     }
-    if (r == 2) g_insert<true>(J, vlo, vhi, m.x, m.y, hash_from32(h32), k, m.z, debug_hash);
+    if (r == 2) g_insert<true>(jobs[m.w], 0, 0, m.x, m.y, hash_from32(hk), k, m.z, debug_hash);
   };
-  const uint32_t qn = *gp(&J.qcnt[p]);
-  const uint32_t n = qn < J.qcap ? qn : J.qcap;
-  const FlushRec* q = reinterpret_cast<const FlushRec*>(J.queue) + (uint64_t)p * J.qcap;
+  const uint32_t qn = *gp(&Q.qcnt[p]);
+  const uint32_t n = qn < Q.qcap ? qn : Q.qcap;
+  const FlushRec* q = reinterpret_cast<const FlushRec*>(Q.queue) + (uint64_t)p * Q.qcap;
   for (uint32_t r0 = threadIdx.x; r0 < n; r0 += blockDim.x) consume(&q[r0]);
-  if (J.mq) {
+  if (Q.mq) {
     // the map workgroups' miss sub-queues of this partition, one wave per sub-queue
     const uint32_t lane = lane_id();
-    for (uint32_t w = threadIdx.x / kWave; w < J.mq_grid; w += blockDim.x / kWave) {
-      const uint32_t nm = *gp(&J.mq_fill[p * J.mq_grid + w]);
-      const FlushRec* mq = reinterpret_cast<const FlushRec*>(J.mq) + ((uint64_t)p * J.mq_grid + w) * J.mq_cap;
+    for (uint32_t w = threadIdx.x / kWave; w < Q.mq_grid; w += blockDim.x / kWave) {
+      const uint32_t nm = *gp(&Q.mq_fill[p * Q.mq_grid + w]);
+      const FlushRec* mq = reinterpret_cast<const FlushRec*>(Q.mq) + ((uint64_t)p * Q.mq_grid + w) * Q.mq_cap;
       for (uint32_t i = lane; i < nm; i += kWave) consume(&mq[i]);
     }
   }
   __syncthreads();
-  lds_flush<L>(T, J, vlo, vhi, debug_hash);
+  // the summed keys into their jobs' tables
+  for (uint32_t i = threadIdx.x; i < LdsTable<L>::kSlots; i += blockDim.x) {
+    const uint32_t tg = T.tag[i];
+    if (tg & 1u) {
+      const uint32_t len = (tg >> 1) & 31u;
+      const uint4 k = T.key[i];
+      g_insert<true>(jobs[s_job[i]], 0, 0, T.off[i], len, key_hash16(k, len, debug_hash), k, T.cnt[i], debug_hash);
+    }
+  }
 }
 
 // ----------------------------------------------------------------------------
