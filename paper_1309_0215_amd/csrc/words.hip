@@ -960,6 +960,29 @@ __global__ __launch_bounds__(kCompactThreads) void k_words_compact(const WordJob
 // sample sort of the distinct keys (unsigned bytewise order, prefix first)
 // ----------------------------------------------------------------------------
 
+// A record read with two 16-byte global loads (records are 32-byte aligned).
+// A plain copy through a generic pointer becomes flat word loads, which may
+// alias LDS and therefore wait for each other around the LDS stores that
+// follow them.
+MR_DEV WRec load_wrec(const WRec* p) {
+  const uint4 a = gload16(p), b = gload16(reinterpret_cast<const uint8_t*>(p) + 16);
+  WRec r;
+  r.p[0] = a.x;
+  r.p[1] = a.y;
+  r.p[2] = a.z;
+  r.p[3] = a.w;
+  r.len = b.x;
+  r.off = b.y;
+  r.cnt = b.z;
+  r.pad = b.w;
+  return r;
+}
+
+MR_DEV void store_wrec(WRec* p, const WRec& r) {
+  gstore16(p, make_uint4(r.p[0], r.p[1], r.p[2], r.p[3]));
+  gstore16(reinterpret_cast<uint8_t*>(p) + 16, make_uint4(r.len, r.off, r.cnt, r.pad));
+}
+
 // Three-way compare of two records of the same job.
 MR_DEV int wrec_cmp(const WordJob& J, const WRec& a, const WRec& b) {
 #pragma unroll
@@ -1159,26 +1182,55 @@ MR_DEV void reg_bitonic(const WordJob& J, const WRec* recs, SoaKeys<CAP>& S, uin
 constexpr uint32_t kSortThreads = 1024;
 constexpr uint32_t kOversample = 4;
 
-// Plan the sort of every job: bucket counts and global bucket / record-tile bases.
-__global__ void k_sort_plan(const WordJob* __restrict__ jobs, uint32_t n_jobs, uint32_t* totals /*[2]*/) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  uint32_t bb = 0, rt = 0;
-  for (uint32_t j = 0; j < n_jobs; ++j) {
-    JobState* st = jobs[j].st;
-    const uint64_t n = st->n_recs;
-    uint32_t nb = 1;
-    if (n > kBucketCap) {
-      const uint64_t want = (n + 511) / 512;
-      nb = (uint32_t)(want < kMaxBuckets ? want : kMaxBuckets);
+// Plan the sort of every job: bucket counts and global bucket / record-tile
+// bases. One workgroup; the jobs are taken blockDim at a time, one per
+// thread, and the bases come from a workgroup scan of the counts.
+__global__ __launch_bounds__(kSortThreads) void k_sort_plan(const WordJob* __restrict__ jobs, uint32_t n_jobs,
+                                                             uint32_t* totals /*[2]*/) {
+  __shared__ uint32_t w_nb[kSortThreads / kWave], w_rt[kSortThreads / kWave];
+  const uint32_t lane = lane_id(), wv = threadIdx.x / kWave, nw = blockDim.x / kWave;
+  uint32_t carry_b = 0, carry_r = 0;
+  for (uint32_t base = 0; base < n_jobs; base += blockDim.x) {
+    const uint32_t j = base + threadIdx.x;
+    uint32_t nb = 0, rt = 0;
+    if (j < n_jobs) {
+      const uint64_t n = jobs[j].st->n_recs;
+      nb = 1;
+      if (n > kBucketCap) {
+        const uint64_t want = (n + 511) / 512;
+        nb = (uint32_t)(want < kMaxBuckets ? want : kMaxBuckets);
+      }
+      rt = (uint32_t)((n + kRecTile - 1) / kRecTile);
     }
-    st->nb = nb;
-    st->bucket_base = bb;
-    st->rtile_base = rt;
-    bb += nb;
-    rt += (uint32_t)((n + kRecTile - 1) / kRecTile);
+    const uint32_t inb = wave_incl_scan(nb), irt = wave_incl_scan(rt);
+    if (lane == kWave - 1) {
+      w_nb[wv] = inb;
+      w_rt[wv] = irt;
+    }
+    __syncthreads();
+    uint32_t pb = carry_b, pr = carry_r, tb = 0, tr = 0;
+    for (uint32_t q = 0; q < nw; ++q) {
+      if (q < wv) {
+        pb += w_nb[q];
+        pr += w_rt[q];
+      }
+      tb += w_nb[q];
+      tr += w_rt[q];
+    }
+    if (j < n_jobs) {
+      JobState* st = jobs[j].st;
+      st->nb = nb;
+      st->bucket_base = pb + inb - nb;
+      st->rtile_base = pr + irt - rt;
+    }
+    carry_b += tb;
+    carry_r += tr;
+    __syncthreads();
   }
-  totals[0] = bb;
-  totals[1] = rt;
+  if (threadIdx.x == 0) {
+    totals[0] = carry_b;
+    totals[1] = carry_r;
+  }
 }
 
 // Splitters of one job: sort an evenly spaced sample, keep every kOversample-th.
@@ -1205,13 +1257,13 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_splitters(const WordJob* 
   const WRec* recs = reinterpret_cast<const WRec*>(J.recs);
   for (uint32_t i = threadIdx.x; i < S; i += blockDim.x) {
     const uint32_t ix = (uint32_t)((uint64_t)i * n / S);
-    soa_load(smp, i, recs[ix], ix);
+    soa_load(smp, i, load_wrec(&recs[ix]), ix);
   }
   __syncthreads();
   if (S <= blockDim.x) reg_bitonic(J, recs, smp, S);
   else soa_bitonic(J, recs, smp, S);
   WRec* spl = reinterpret_cast<WRec*>(J.splitters);
-  for (uint32_t b = threadIdx.x; b + 1 < nb; b += blockDim.x) spl[b] = recs[smp.ix[(b + 1) * ov - 1]];
+  for (uint32_t b = threadIdx.x; b + 1 < nb; b += blockDim.x) store_wrec(&spl[b], load_wrec(&recs[smp.ix[(b + 1) * ov - 1]]));
 }
 
 // Bucket of each record: number of splitters strictly below it.
@@ -1249,16 +1301,16 @@ __global__ __launch_bounds__(256) void k_sort_count(const WordJob* __restrict__ 
     for (uint32_t b = threadIdx.x; b < nb; b += blockDim.x) {
       h_cnt[b] = 0;
       h_bytes[b] = 0;
-      if (b + 1 < nb) spl[b] = reinterpret_cast<const WRec*>(J.splitters)[b];
+      if (b + 1 < nb) spl[b] = load_wrec(reinterpret_cast<const WRec*>(J.splitters) + b);
     }
     __syncthreads();
     const WRec* recs = reinterpret_cast<const WRec*>(J.recs);
     for (uint32_t q = threadIdx.x; q < kRecTile; q += blockDim.x) {
       const uint64_t i = r0 + q;
       if (i >= n) break;
-      const WRec r = recs[i];
+      const WRec r = load_wrec(&recs[i]);
       const uint32_t b = nb > 1 ? bucket_of(J, spl, nb, r) : 0u;
-      J.rec_bucket[i] = b;
+      *gp(&J.rec_bucket[i]) = b;
       atomicAdd(&h_cnt[b], 1u);
       atomicAdd(&h_bytes[b], (unsigned long long)r.len);
     }
@@ -1352,7 +1404,7 @@ __global__ __launch_bounds__(256) void k_sort_scatter(const WordJob* __restrict_
 #pragma unroll
     for (uint32_t q = 0; q < kPer; ++q) {
       const uint64_t i = r0 + q * 256 + threadIdx.x;
-      bk[q] = i < n ? J.rec_bucket[i] : 0xFFFFFFFFu;
+      bk[q] = i < n ? *gp(&J.rec_bucket[i]) : 0xFFFFFFFFu;
       loc[q] = bk[q] != 0xFFFFFFFFu ? atomicAdd(&h_cnt[bk[q]], 1u) : 0u;
     }
     __syncthreads();
@@ -1362,7 +1414,7 @@ __global__ __launch_bounds__(256) void k_sort_scatter(const WordJob* __restrict_
 #pragma unroll
     for (uint32_t q = 0; q < kPer; ++q) {
       const uint64_t i = r0 + q * 256 + threadIdx.x;
-      if (bk[q] != 0xFFFFFFFFu) out[h_base[bk[q]] + loc[q]] = recs[i];
+      if (bk[q] != 0xFFFFFFFFu) store_wrec(&out[h_base[bk[q]] + loc[q]], load_wrec(&recs[i]));
     }
   }
 }
@@ -1376,12 +1428,19 @@ MR_DEV uint32_t find_bucket_job(const WordJob* jobs, uint32_t n_jobs, uint32_t g
   return lo;
 }
 
+// Output key bytes of a bucket staged in LDS before they are written out in
+// aligned 16-byte pieces (a bucket sorted in LDS whose keys are all inline).
+constexpr uint32_t kStageBytes = kBucketCap * 16 + 16;
+
 // Sort each bucket and write the job's outputs for it.
 __global__ __launch_bounds__(kSortThreads) void k_sort_buckets(const WordJob* __restrict__ jobs, uint32_t n_jobs, const uint32_t* totals,
-                                                                const uint32_t* bucket_cnt, const uint32_t* bucket_start,
+                                                                const uint32_t* bucket_cnt, const unsigned long long* bucket_bytes,
+                                                                const uint32_t* bucket_start,
                                                                 const unsigned long long* bucket_bstart) {
   __shared__ SoaKeys<kBucketCap> a;
   __shared__ uint64_t wsum[kSortThreads / kWave];
+  __shared__ __attribute__((aligned(16))) uint8_t ob[kStageBytes];
+  __shared__ uint32_t s_long;
   const uint32_t n_buckets = totals[0];
   for (uint32_t g = blockIdx.x; g < n_buckets; g += gridDim.x) {
     const uint32_t j = find_bucket_job(jobs, n_jobs, g);
@@ -1394,8 +1453,14 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_buckets(const WordJob* __
     __syncthreads();
     if (m == 0) continue;
     const bool in_lds = m <= kBucketCap;
+    if (threadIdx.x == 0) s_long = 0u;
+    __syncthreads();
     if (in_lds) {
-      for (uint32_t i = threadIdx.x; i < m; i += blockDim.x) soa_load(a, i, src[i], i);
+      for (uint32_t i = threadIdx.x; i < m; i += blockDim.x) {
+        const WRec r = load_wrec(&src[i]);
+        soa_load(a, i, r, i);
+        if (r.len > 16u) s_long = 1u;
+      }
       __syncthreads();
       if (m <= blockDim.x) reg_bitonic(J, src, a, m);
       else soa_bitonic(J, src, a, m);
@@ -1404,6 +1469,13 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_buckets(const WordJob* __
       bitonic_sort(J, src, m);
     }
     if (!write) continue;
+    // The bucket's key bytes are [y0, y0 + nbytes) of the output. Staged:
+    // byte y0 + e sits at ob[sh + e], where sh puts ob[0] at a 16-byte
+    // aligned output address.
+    const uint64_t nbytes = bucket_bytes[g];
+    uint8_t* const dst0 = J.out_key_bytes + y0;
+    const uint32_t sh = (uint32_t)((uintptr_t)dst0 & 15u);
+    const bool stage = in_lds && !s_long && nbytes + sh <= kStageBytes;
     // byte positions: exclusive scan of lengths in chunks of blockDim
     uint64_t carry = 0;
     for (uint32_t base = 0; base < m; base += blockDim.x) {
@@ -1426,13 +1498,18 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_buckets(const WordJob* __
       for (uint32_t q = 0; q < blockDim.x / kWave; ++q) tot += wsum[q];
       const uint64_t excl = carry + wpre + x - len;
       if (i < m) {
-        const WRec r = src[in_lds ? a.ix[i] : i];
+        const WRec r = load_wrec(&src[in_lds ? a.ix[i] : i]);
         const uint64_t o = y0 + excl;
         J.out_key_offsets[s0 + i] = o;
         J.out_values[s0 + i] = r.cnt;
         if (J.slot_rank) J.slot_rank[r.pad] = (uint32_t)(s0 + i);
-        if (r.len <= 16u) {
+        if (stage) {
           // the key is the big-endian prefix itself
+          uint8_t* const d = ob + sh + (uint32_t)excl;
+#pragma unroll
+          for (uint32_t b = 0; b < 16u; ++b)
+            if (b < r.len) d[b] = (uint8_t)(r.p[b >> 2] >> (24 - 8 * (b & 3)));
+        } else if (r.len <= 16u) {
 #pragma unroll
           for (uint32_t b = 0; b < 16u; ++b)
             if (b < r.len) J.out_key_bytes[o + b] = (uint8_t)(r.p[b >> 2] >> (24 - 8 * (b & 3)));
@@ -1448,6 +1525,22 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_buckets(const WordJob* __
         }
       }
       carry += tot;
+      __syncthreads();
+    }
+    if (stage) {
+      // 16-byte pieces wholly inside the bucket's range as one store each;
+      // the partial pieces at the two ends byte by byte (neighbouring
+      // buckets own the rest of them)
+      uint8_t* const base = dst0 - sh;  // 16-byte aligned
+      const uint32_t end = sh + (uint32_t)nbytes;
+      for (uint32_t c = threadIdx.x; c * 16u < end; c += blockDim.x) {
+        const uint32_t lo = c * 16u, hi = lo + 16u;
+        if (lo >= sh && hi <= end) {
+          gstore16(base + lo, *reinterpret_cast<const uint4*>(ob + lo));
+        } else {
+          for (uint32_t b = lo < sh ? sh : lo; b < (hi < end ? hi : end); ++b) base[b] = ob[b];
+        }
+      }
       __syncthreads();
     }
   }
@@ -1678,7 +1771,7 @@ hipError_t words_enqueue_reduce(const WordsLaunch& L, hipStream_t s) {
   const uint32_t cgrid = (uint32_t)(tiles < 4096 ? tiles : 4096);
   hipLaunchKernelGGL(k_words_compact, dim3(cgrid ? cgrid : 1), dim3(kCompactThreads), 0, s, L.jobs, L.n_jobs, L.total_slots,
                      item);
-  hipLaunchKernelGGL(k_sort_plan, dim3(1), dim3(64), 0, s, L.jobs, L.n_jobs, L.totals);
+  hipLaunchKernelGGL(k_sort_plan, dim3(1), dim3(kSortThreads), 0, s, L.jobs, L.n_jobs, L.totals);
   hipLaunchKernelGGL(k_sort_splitters, dim3(L.n_jobs), dim3(kSortThreads), 0, s, L.jobs, L.n_jobs, L.bucket_cnt,
                      L.bucket_bytes, L.bucket_fill);
   hipLaunchKernelGGL(k_sort_count, dim3(L.sort_grid), dim3(256), 0, s, L.jobs, L.n_jobs, L.totals, L.bucket_cnt, L.bucket_bytes);
@@ -1687,7 +1780,7 @@ hipError_t words_enqueue_reduce(const WordsLaunch& L, hipStream_t s) {
   hipLaunchKernelGGL(k_sort_scatter, dim3(L.sort_grid), dim3(256), 0, s, L.jobs, L.n_jobs, L.totals, L.bucket_start,
                      L.bucket_fill);
   hipLaunchKernelGGL(k_sort_buckets, dim3(L.sort_grid), dim3(kSortThreads), 0, s, L.jobs, L.n_jobs, L.totals, L.bucket_cnt,
-                     L.bucket_start, L.bucket_bstart);
+                     L.bucket_bytes, L.bucket_start, L.bucket_bstart);
   hipLaunchKernelGGL(k_words_finish, dim3(1), dim3(256), 0, s, L.jobs, L.n_jobs);
   return hipGetLastError();
 }
