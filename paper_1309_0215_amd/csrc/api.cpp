@@ -518,7 +518,8 @@ WordsPlan plan_words(const std::vector<WordItem>& items, bool slot_ranks, uint32
     p.total_tiles += (n_chunks + kMapTileChunks - 1) / kMapTileChunks;
   }
   p.tile_base[n] = p.total_tiles;
-  p.grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(p.total_tiles, grid_cap));
+  // (the summing kernel of the partition queues takes at most 1024 map workgroups)
+  p.grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(std::min<uint64_t>(p.total_tiles, grid_cap), 1024));
   // the table arena comes first so that its clean prefix survives layout changes
   p.o_tw = p.c.take(p.total_slots * 8);
   p.o_tc = p.c.take(p.total_slots * 4);

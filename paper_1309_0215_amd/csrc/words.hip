@@ -825,62 +825,134 @@ __global__ __launch_bounds__(kMapThreads) void k_words_map(const WordJob* __rest
 
 // Two-phase flush, second phase: one workgroup per partition sums the
 // records of its flush queue and of every map workgroup's miss sub-queue by
-// (job, key) in an LDS table and inserts each key into its job's table once,
+// (job, key) in an LDS table and inserts each summed key into its job's table,
 // so that the keys every workgroup meets no longer meet on one global slot
-// from every workgroup. Records that find the LDS table full are inserted
-// globally as they come.
+// from every workgroup. The records are taken in rounds of one per thread
+// (the next round's record is loaded meanwhile); after a round that leaves
+// the table more than half full, the table is flushed into the global tables
+// (one insert per summed key, all threads at once) and cleared, so records
+// never fall back to one global insert each. A round adds at most blockDim
+// keys, which keeps the table below three quarters full.
+constexpr uint32_t kMaxMapGrid = 1024;  // map workgroups (miss sub-queues per partition)
 template <int L>
 __global__ __launch_bounds__(kMapThreads) void k_words_parts(const WordJob* __restrict__ jobs, uint32_t debug_hash) {
+  constexpr uint32_t kSlots = LdsTable<L>::kSlots;
+  static_assert(kSlots / 2 + kMapThreads <= kSlots / 4 * 3, "a round cannot fill the table");
   __shared__ LdsTable<L> T;
-  __shared__ uint32_t s_job[LdsTable<L>::kSlots];
+  __shared__ uint32_t s_job[kSlots];
+  __shared__ uint32_t s_pre[kMaxMapGrid + 2];  // first record of each segment: flush queue, then sub-queue w
   __shared__ uint32_t s_used;
-  constexpr uint32_t kLimit = LdsTable<L>::kSlots / 4 * 3;
   const WordJob& Q = jobs[0];  // the queues (shared by the jobs of a batch)
   const uint32_t p = blockIdx.x;
-  for (uint32_t i = threadIdx.x; i < LdsTable<L>::kSlots; i += blockDim.x) T.tag[i] = 0u;
+  for (uint32_t i = threadIdx.x; i < kSlots; i += blockDim.x) T.tag[i] = 0u;
   if (threadIdx.x == 0) s_used = 0;
+  // exclusive prefix of the segment sizes (segment 0: the flush queue;
+  // segment 1 + w: map workgroup w's sub-queue), blockDim at a time
+  __shared__ uint32_t s_wsum[kMapThreads / kWave];
+  const uint32_t G = Q.mq ? Q.mq_grid : 0u;
+  const uint32_t lane = lane_id(), wv = threadIdx.x / kWave, nw = blockDim.x / kWave;
+  uint32_t carry = 0;
+  for (uint32_t b0 = 0; b0 <= G; b0 += blockDim.x) {
+    const uint32_t w = b0 + threadIdx.x;
+    uint32_t c = 0;
+    if (w == 0) {
+      const uint32_t qn = *gp(&Q.qcnt[p]);
+      c = qn < Q.qcap ? qn : Q.qcap;
+    } else if (w <= G) {
+      c = *gp(&Q.mq_fill[p * Q.mq_grid + (w - 1)]);
+    }
+    const uint32_t incl = wave_incl_scan(c);
+    if (lane == kWave - 1) s_wsum[wv] = incl;
+    __syncthreads();
+    uint32_t before = carry, all = 0;
+    for (uint32_t q = 0; q < nw; ++q) {
+      if (q < wv) before += s_wsum[q];
+      all += s_wsum[q];
+    }
+    if (w <= G) s_pre[w] = before + incl - c;
+    carry += all;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) s_pre[G + 1] = carry;
   __syncthreads();
-  // one record: summed into the LDS table, or inserted globally when it is full
-  auto consume = [&](const FlushRec* rp) {
-    const uint4 k = gload16(&rp->k);
-    const uint4 m = gload16(&rp->off);  // off, len, count, job
+  const uint32_t total = carry;
+  const FlushRec* fq = reinterpret_cast<const FlushRec*>(Q.queue) + (uint64_t)p * Q.qcap;
+  // record r of the partition: the last segment starting at or before it.
+  // A thread's records only move forward, so the search gallops on from its
+  // previous segment (steps 1, 2, 4, ...) and then bisects.
+  uint32_t seg = 0;
+  auto rec_at = [&](uint32_t r) -> const FlushRec* {
+    uint32_t lo = seg, hi = seg + 1, step = 1;  // s_pre[lo] <= r < total = s_pre[G + 1]
+    while (hi <= G && s_pre[hi] <= r) {
+      lo = hi;
+      step <<= 1;
+      hi = lo + step;
+    }
+    if (hi > G + 1) hi = G + 1;
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (s_pre[mid] <= r) lo = mid; else hi = mid;
+    }
+    seg = lo;
+    const uint32_t e = r - s_pre[seg];
+    if (seg == 0) return fq + e;
+    return reinterpret_cast<const FlushRec*>(Q.mq) + ((uint64_t)p * Q.mq_grid + (seg - 1)) * Q.mq_cap + e;
+  };
+  auto consume = [&](uint4 k, uint4 m) {  // m: off, len, count, job
     const uint32_t hk = lds_hash32(k, m.y, debug_hash);
     // the LDS placement mixes in the job; the global table takes the key's own hash
     const uint32_t h32 = hk ^ (m.w * 0x9E3779B1u);
     const uint32_t tg = (h32 & 0xFFFFFFC0u) | (m.y << 1);
     int r = 1;
     for (uint32_t spin = 0; r == 1; ++spin) {
-      r = lds_insert<L>(T, &s_used, kLimit, tg, h32, k, m.x, m.z, s_job, m.w);
+      r = lds_insert<L>(T, &s_used, kSlots, tg, h32, k, m.x, m.z, s_job, m.w);
       if (r == 1 && spin > (1u << 22)) {
         __hip_atomic_fetch_or(gp(&jobs[m.w].st->flags), kFlagSpin, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         r = 0;
       }
     }
+    // the key's probe groups are full (rare below three quarters load)
     if (r == 2) g_insert<true>(jobs[m.w], 0, 0, m.x, m.y, hash_from32(hk), k, m.z, debug_hash);
   };
-  const uint32_t qn = *gp(&Q.qcnt[p]);
-  const uint32_t n = qn < Q.qcap ? qn : Q.qcap;
-  const FlushRec* q = reinterpret_cast<const FlushRec*>(Q.queue) + (uint64_t)p * Q.qcap;
-  for (uint32_t r0 = threadIdx.x; r0 < n; r0 += blockDim.x) consume(&q[r0]);
-  if (Q.mq) {
-    // the map workgroups' miss sub-queues of this partition, one wave per sub-queue
-    const uint32_t lane = lane_id();
-    for (uint32_t w = threadIdx.x / kWave; w < Q.mq_grid; w += blockDim.x / kWave) {
-      const uint32_t nm = *gp(&Q.mq_fill[p * Q.mq_grid + w]);
-      const FlushRec* mq = reinterpret_cast<const FlushRec*>(Q.mq) + ((uint64_t)p * Q.mq_grid + w) * Q.mq_cap;
-      for (uint32_t i = lane; i < nm; i += kWave) consume(&mq[i]);
+  // the summed keys into their jobs' tables; the table is cleared
+  auto flush = [&]() {
+    for (uint32_t i = threadIdx.x; i < kSlots; i += blockDim.x) {
+      const uint32_t tg = T.tag[i];
+      if (tg & 1u) {
+        const uint32_t len = (tg >> 1) & 31u;
+        const uint4 k = T.key[i];
+        g_insert<true>(jobs[s_job[i]], 0, 0, T.off[i], len, key_hash16(k, len, debug_hash), k, T.cnt[i], debug_hash);
+      }
+      T.tag[i] = 0u;
+    }
+  };
+  uint4 nk = make_uint4(0, 0, 0, 0), nm = make_uint4(0, 0, 0, 0);
+  if (threadIdx.x < total) {
+    const FlushRec* rp = rec_at(threadIdx.x);
+    nk = gload16(&rp->k);
+    nm = gload16(&rp->off);
+  }
+  for (uint32_t base = 0; base < total; base += blockDim.x) {
+    const bool have = base + threadIdx.x < total;
+    const uint4 k = nk, m = nm;
+    const uint32_t nx = base + blockDim.x + threadIdx.x;
+    if (nx < total) {
+      const FlushRec* rp = rec_at(nx);
+      nk = gload16(&rp->k);
+      nm = gload16(&rp->off);
+    }
+    if (have) consume(k, m);
+    __syncthreads();
+    const bool full = s_used > kSlots / 2;  // uniform: read after the barrier
+    __syncthreads();
+    if (full) {
+      flush();
+      if (threadIdx.x == 0) s_used = 0;
+      __syncthreads();
     }
   }
   __syncthreads();
-  // the summed keys into their jobs' tables
-  for (uint32_t i = threadIdx.x; i < LdsTable<L>::kSlots; i += blockDim.x) {
-    const uint32_t tg = T.tag[i];
-    if (tg & 1u) {
-      const uint32_t len = (tg >> 1) & 31u;
-      const uint4 k = T.key[i];
-      g_insert<true>(jobs[s_job[i]], 0, 0, T.off[i], len, key_hash16(k, len, debug_hash), k, T.cnt[i], debug_hash);
-    }
-  }
+  flush();
 }
 
 // ----------------------------------------------------------------------------
