@@ -475,36 +475,35 @@ uint64_t initial_slots(const mr_job* job, uint64_t n, uint64_t size_key) {
 struct WordsPlan {
   Carve c;
   uint64_t o_jobs, o_tile_base, o_states, o_totals, o_bucket_cnt, o_bucket_bytes, o_bucket_start, o_bucket_bstart,
-      o_bucket_fill, o_tw, o_tc, o_recs, o_recs2, o_rbucket, o_spl, o_slot_rank = 0, o_queue = 0, o_qcnt = 0;
-  uint32_t qcap = 0;  // records per flush queue (0: no two-phase flush)
+      o_bucket_fill, o_tw, o_tc, o_recs, o_recs2, o_rbucket, o_spl, o_slot_rank = 0;
+  uint32_t n_parts = 0;  // partitions of the two-phase reduce (0: none)
   uint64_t o_mq = 0, o_mqfill = 0;
-  uint32_t mq_cap = 0, grid = 1;  // miss sub-queue records; map workgroups
+  uint32_t mq_cap = 0, grid = 1;  // records per sub-queue; map workgroups
   uint64_t total_slots = 0, total_tiles = 0;
   std::vector<uint64_t> slot_base, tile_base;
 };
 
-// Records per flush queue of a batch of n_jobs jobs and n input bytes (the
-// queues are shared by the batch): a workgroup flushes its LDS cache (3/4 of
-// its 4096 slots filled, typically) once per job it meets, which is at most
-// n_cu + n_jobs flushes in all, and there is at most one record per two input
-// bytes; spread over the queues by hash, with slack. A full queue sends its
+// Partitions of the two-phase reduce: 256. More partitions would let the
+// distinct keys of a partition fit one summing workgroup's LDS table on
+// high-cardinality inputs, but each map workgroup keeps one partly written
+// line open per partition, and with 4096 partitions those lines no longer
+// fit the L2 (measured on 512 MiB of text: map 575 -> 754 us).
+uint32_t word_parts(uint64_t) { return 256u; }
+
+// Records per sub-queue (one per map workgroup and partition, shared by the
+// jobs of a batch): room for half the words of an input of mean word length 8
+// missing the LDS caches, spread evenly, plus the entries of the caches the
+// workgroup flushes (3/4 of 4096 slots, once per job it meets: at most
+// n_jobs + grid flushes in all), with slack. A full sub-queue sends its
 // overflow to the global table directly.
-uint32_t flush_queue_cap(uint64_t n, int n_cu, uint64_t n_jobs) {
-  const uint64_t recs = std::min<uint64_t>(((uint64_t)n_cu + n_jobs) * 3072, n / 2 + 1);
-  return (uint32_t)(recs * 3 / 2 / kFlushParts + 256);
+uint32_t miss_queue_cap(uint64_t n, uint32_t grid, uint32_t parts, uint64_t n_jobs) {
+  const uint64_t misses = n / (16ull * grid * parts);
+  const uint64_t flushed = 3072ull * (n_jobs + grid) / ((uint64_t)grid * parts);
+  const uint64_t want = misses + flushed + 1;
+  return (uint32_t)std::min<uint64_t>(4096, std::max<uint64_t>(16, next_pow2(want + want / 2)));
 }
 
-// Records per miss sub-queue (one per map workgroup and partition, shared by
-// the jobs of a batch) for n input bytes: room for half the words of an
-// input of mean word length 8 missing the LDS caches, spread evenly, so that
-// a sub-queue rarely fills on text whose cache misses stay below that; a full
-// sub-queue sends its overflow to the global table directly.
-uint32_t miss_queue_cap(uint64_t n, uint32_t grid) {
-  const uint64_t want = n / (16ull * grid * kFlushParts) + 1;
-  return (uint32_t)std::min<uint64_t>(4096, std::max<uint64_t>(16, next_pow2(want)));
-}
-
-WordsPlan plan_words(const std::vector<WordItem>& items, bool slot_ranks, uint32_t qcap, uint64_t grid_cap) {
+WordsPlan plan_words(const std::vector<WordItem>& items, bool slot_ranks, bool queues, uint64_t grid_cap) {
   WordsPlan p;
   const uint32_t n = (uint32_t)items.size();
   p.slot_base.resize(n);
@@ -537,15 +536,13 @@ WordsPlan plan_words(const std::vector<WordItem>& items, bool slot_ranks, uint32
   p.o_rbucket = p.c.take(4 * p.total_slots);
   p.o_spl = p.c.take(sizeof(WRec) * (kMaxBuckets - 1) * (uint64_t)n);
   if (slot_ranks) p.o_slot_rank = p.c.take(4 * p.total_slots);
-  if (qcap) {
-    p.qcap = qcap;
-    p.o_queue = p.c.take(32ull * kFlushParts * qcap);
-    p.o_qcnt = p.c.take(4ull * kFlushParts);
+  if (queues) {
     uint64_t total_n = 0;
     for (const WordItem& it : items) total_n += it.n;
-    p.mq_cap = miss_queue_cap(total_n, p.grid);
-    p.o_mq = p.c.take(32ull * kFlushParts * p.grid * p.mq_cap);
-    p.o_mqfill = p.c.take(4ull * kFlushParts * p.grid);
+    p.n_parts = word_parts(total_n);
+    p.mq_cap = miss_queue_cap(total_n, p.grid, p.n_parts, n);
+    p.o_mq = p.c.take(32ull * p.n_parts * p.grid * p.mq_cap);
+    p.o_mqfill = p.c.take(4ull * p.n_parts * p.grid);
   }
   return p;
 }
@@ -581,12 +578,9 @@ uint64_t input_key(const uint8_t* in, uint64_t n) { return fnv_mix(fnv_mix(0xCBF
 mr_status words_pass(mr_job* job, std::vector<WordItem>& items, std::vector<JobState>& states, float* gpu_ms,
                      float* map_ms, GraphMode mode, LinkBufs* lb) {
   const uint32_t n = (uint32_t)items.size();
-  // word jobs flush their LDS caches and send their cache misses through
-  // partition queues (shared by the jobs of a batch); the two-phase flush
-  // then sums them per partition
-  uint64_t total_n = 0;
-  for (const WordItem& it : items) total_n += it.n;
-  const uint32_t qcap = !lb ? flush_queue_cap(total_n, job->n_cu, n) : 0u;
+  // word jobs send their cache misses and flushed cache entries through
+  // partition queues (shared by the jobs of a batch), summed per partition
+  const bool queues = lb == nullptr;
   // tuned map parameters, looked up by the bytes this launch covers (a
   // batch by its total; each job's table load factor by its own size)
   uint64_t size_key = 0;
@@ -597,7 +591,7 @@ mr_status words_pass(mr_job* job, std::vector<WordItem>& items, std::vector<JobS
   if (lds_log2 != 8 && lds_log2 != 10 && lds_log2 != 11 && lds_log2 != 12)
     return fail(MR_ERR_INVALID_ARG, "lds_slots must be 256, 1024, 2048 or 4096");
   const uint64_t grid_cap = std::max<uint64_t>(1, (uint64_t)job->n_cu * eff_grid_pct(job, size_key) / 100);
-  WordsPlan p = plan_words(items, lb != nullptr, qcap, grid_cap);
+  WordsPlan p = plan_words(items, lb != nullptr, queues, grid_cap);
   mr_status st = ensure_ws(job, p.c.off);
   if (st != MR_OK) return st;
   uint8_t* ws = job->ws;
@@ -690,13 +684,11 @@ mr_status words_pass(mr_job* job, std::vector<WordItem>& items, std::vector<JobS
     J.cap_key_bytes = it.out->cap_key_bytes;
     J.st = reinterpret_cast<JobState*>(ws + p.o_states) + j;
     J.slot_rank = lb ? reinterpret_cast<uint32_t*>(ws + p.o_slot_rank) + p.slot_base[j] : nullptr;
-    J.queue = p.qcap ? ws + p.o_queue : nullptr;
-    J.qcnt = p.qcap ? reinterpret_cast<uint32_t*>(ws + p.o_qcnt) : nullptr;
-    J.qcap = p.qcap;
     J.mq_cap = p.mq_cap;
     J.mq_grid = p.grid;
-    J.mq = p.qcap ? ws + p.o_mq : nullptr;
-    J.mq_fill = p.qcap ? reinterpret_cast<uint32_t*>(ws + p.o_mqfill) : nullptr;
+    J.mq = p.n_parts ? ws + p.o_mq : nullptr;
+    J.mq_fill = p.n_parts ? reinterpret_cast<uint32_t*>(ws + p.o_mqfill) : nullptr;
+    J.part_shift = p.n_parts ? 64u - (uint32_t)__builtin_ctz(p.n_parts) : 64u;
     any_rec |= it.rec != nullptr;
   }
   MR_HIP(hipMemcpyAsync(ws + p.o_jobs, hj.data(), sizeof(WordJob) * n, hipMemcpyHostToDevice, s));
@@ -711,7 +703,7 @@ mr_status words_pass(mr_job* job, std::vector<WordItem>& items, std::vector<JobS
   L.map_grid = p.grid;
   L.sort_grid = (uint32_t)std::max(1, job->n_cu * 2);
   L.lds_log2 = lds_log2;
-  L.flush_parts = p.qcap != 0;
+  L.n_parts = p.n_parts;
   L.debug_hash = job->cfg.debug_hash;
   L.any_records = any_rec;
   L.wave_combine = job->cfg.wave_combine != 0;
@@ -1655,7 +1647,7 @@ extern "C" mr_status mr_workspace_bytes(const mr_job_config* cfg, mr_map_kind ki
       std::vector<WordItem> items(1);
       items[0] = WordItem{reinterpret_cast<const uint8_t*>(15), n, nullptr, 0, nullptr, initial_slots(&tmp, n, n)};
       const uint64_t grid_cap = std::max<uint64_t>(1, (uint64_t)n_cu * eff_grid_pct(&tmp, n) / 100);
-      r.add(plan_words(items, false, flush_queue_cap(n, n_cu, 1), grid_cap).c.off);
+      r.add(plan_words(items, false, true, grid_cap).c.off);
       break;
     }
     case MR_MAP_RGB_HIST:
@@ -1722,7 +1714,7 @@ extern "C" mr_status mr_workspace_bytes(const mr_job_config* cfg, mr_map_kind ki
       std::vector<WordItem> items(1);
       items[0] = WordItem{reinterpret_cast<const uint8_t*>(15), n, nullptr, 0, nullptr, initial_slots(&tmp, n, n)};
       const uint64_t grid_cap = std::max<uint64_t>(1, (uint64_t)n_cu * eff_grid_pct(&tmp, n) / 100);
-      r.add(plan_words(items, true, 0, grid_cap).c.off);
+      r.add(plan_words(items, true, false, grid_cap).c.off);
       // the file-list pass: at most one pair and one URL per marker
       const uint64_t hw = links_hist_words(cap);
       c.take(8 * cap);

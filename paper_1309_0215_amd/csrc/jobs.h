@@ -57,26 +57,23 @@ struct WordJob {
   uint64_t cap_key_bytes;
   JobState* st;
   uint32_t* slot_rank;       // [cap] output rank of the key in each table slot, or NULL
-  // partition queues of the two-phase flush (single jobs), or NULL: the LDS
-  // caches are flushed into kFlushParts queues by key hash, and one
-  // workgroup per queue sums them before the global inserts
-  void* queue;               // records [kFlushParts][qcap]
-  uint32_t* qcnt;            // [kFlushParts] records claimed per queue
-  uint32_t qcap;
-  // LDS-cache misses of the word map (single jobs), or NULL: map workgroup w
-  // appends the words its cache cannot take to its own sub-queue of
-  // partition p (records [kFlushParts][mq_grid][mq_cap], positions from LDS
-  // counters, no global atomics) and stores the sub-queue's fill in
-  // mq_fill[p * mq_grid + w]; the queue-summing workgroup of partition p then
-  // adds them with the flushed cache entries
+  // partition queues of the two-phase reduce, or NULL. Map workgroup w
+  // appends the words its LDS cache cannot take, and its cache entries when
+  // it flushes the cache, to its own sub-queue of the key's partition
+  // (records [n_parts][mq_grid][mq_cap], positions from LDS counters, no
+  // global atomics; shared by the jobs of a batch) and stores the sub-queue's
+  // fill in mq_fill[p * mq_grid + w]; one workgroup per partition then sums
+  // the records by key. A key's partition is its 64-bit hash >> part_shift
+  // (n_parts = 2^(64 - part_shift)).
   uint32_t mq_cap;
   uint32_t mq_grid;
   void* mq;
   uint32_t* mq_fill;
+  uint32_t part_shift;
+  uint32_t pad;
 };
 
-constexpr uint32_t kFlushParts = 256;  // queues: the top 8 bits of the key hash
-constexpr uint32_t kFlushShift = 56;
+constexpr uint32_t kMaxWordParts = 4096;  // partitions of the two-phase reduce (top 8 to 12 hash bits)
 
 // Compacted table entry of a word, ordered by (p, len) then tail bytes.
 struct WRec {

@@ -26,7 +26,7 @@ struct WordsLaunch {
   unsigned long long* bucket_bstart;
   uint32_t* bucket_fill;
   JobState* states;           // device [n_jobs]
-  bool flush_parts;            // job 0 flushes its LDS caches through partition queues (two-phase)
+  uint32_t n_parts;            // partitions of the two-phase reduce through partition queues (0: none)
   // Reverse Index map instead of the word map (one job)
   bool links;
   uint32_t link_grid;

@@ -266,8 +266,6 @@ __global__ void k_words_prep(const WordJob* __restrict__ jobs, uint32_t n_jobs) 
   const uint32_t j = blockIdx.y;
   if (j >= n_jobs) return;
   const WordJob J = jobs[j];
-  if (J.qcnt && j == 0 && blockIdx.x == 0)  // the queues are shared by the batch
-    for (uint32_t p = threadIdx.x; p < kFlushParts; p += blockDim.x) J.qcnt[p] = 0u;
   if (!J.rec) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       J.st->valid_lo = 0;
@@ -293,10 +291,12 @@ __global__ void k_words_prep(const WordJob* __restrict__ jobs, uint32_t n_jobs) 
 // Probe groups: 4 consecutive slots whose tags are read with one 16-byte LDS
 // load. A word visits at most kLdsGroups groups before it goes global.
 constexpr int kLdsGroups = 4;
-// Word descriptors a wave lists per round: a window's 992 owned bytes hold at
-// most 497 word starts (each but the first follows a separator), so one round
-// takes every window; record boundaries can add starts, which take more rounds.
-constexpr uint32_t kListCap = 512;
+// Word descriptors a wave lists per round (a multiple of 128: two words per
+// lane per step). A window's 992 owned bytes hold at most 497 word starts
+// (each but the first follows a separator) and text of mean token length 8
+// about 120, so nearly every window takes one round; windows with more
+// starts, and record boundaries, which can add starts, take more rounds.
+constexpr uint32_t kListCap = 384;
 
 template <int kSlotsLog2>
 struct LdsTable {
@@ -320,15 +320,17 @@ MR_DEV uint32_t key_diff(uint4 a, uint4 b) {
 
 // Bucketed linear probing: a group is searched for the key; a group with an
 // empty slot ends the search (slots fill in order and are never freed, so the
-// key would have been placed there), and the key claims that slot unless the
-// table has reached its fill limit.
-// Returns 0 = counted, 1 = a matching slot is still being written or the
-// claim was lost (retry), 2 = not in the table and not inserted (go global).
+// key would have been placed there), and the key claims that slot.
+// Returns 0 = counted in a slot that held the key, 4 = counted in a slot the
+// key has just claimed, 1 = a matching slot is still being written or the
+// claim was lost (retry), 2 = not in the table and not inserted (its groups
+// are full: go global). The caller counts claims where it needs a fill level
+// (one shared LDS counter would serialise every claim of the workgroup).
 // With a job array (the summing of a batch's queues), a slot holds a key of
 // one job: equality takes the job index too.
 template <int L, int kGroups = kLdsGroups>
-MR_DEV int lds_insert(LdsTable<L>& T, uint32_t* used, uint32_t limit, uint32_t tg, uint32_t h, uint4 k, uint32_t off,
-                      uint32_t v = 1u, uint32_t* slot_job = nullptr, uint32_t job = 0u) {
+MR_DEV int lds_insert(LdsTable<L>& T, uint32_t tg, uint32_t h, uint4 k, uint32_t off, uint32_t v = 1u,
+                      uint32_t* slot_job = nullptr, uint32_t job = 0u) {
   constexpr uint32_t kGroupMask = LdsTable<L>::kSlots / 4 - 1;
   uint32_t g = h & kGroupMask;
   for (int p = 0; p < kGroups; ++p) {
@@ -351,7 +353,6 @@ MR_DEV int lds_insert(LdsTable<L>& T, uint32_t* used, uint32_t limit, uint32_t t
     }
     if (match & ~ready) return 1;  // a slot with the key's tag is still being written
     if (empty) {
-      if (*used >= limit) return 2;
       const uint32_t i = 4 * g + (uint32_t)__builtin_ctz(empty);  // slots fill in order: the first empty one
       if (atomicCAS(&T.tag[i], 0u, tg) != 0u) return 1;  // lost the slot: look again
       T.key[i] = k;
@@ -359,8 +360,7 @@ MR_DEV int lds_insert(LdsTable<L>& T, uint32_t* used, uint32_t limit, uint32_t t
       T.cnt[i] = v;
       if (slot_job) slot_job[i] = job;
       __hip_atomic_store(&T.tag[i], tg | 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
-      atomicAdd(used, 1u);
-      return 0;
+      return 4;
     }
     g = (g + 1) & kGroupMask;
   }
@@ -389,38 +389,26 @@ struct FlushRec {
   uint32_t off, len, cnt, job;
 };
 
-// Two-phase flush, first phase: the workgroup's cache entries go to the
-// partition queues by the top bits of their hash, with one global
-// reservation per queue; an entry that finds its queue full is inserted
-// globally at once. J is job `job` of the batch. pc: LDS scratch
-// [2 * kFlushParts]. Called by the whole workgroup.
+// Two-phase reduce, first phase, for the cache: every entry of the
+// workgroup's LDS cache goes to the workgroup's own sub-queue of its key's
+// partition, after the words the cache missed (positions from the LDS fill
+// counters mfill); an entry that finds its sub-queue full is inserted
+// globally at once. J is job `job` of the batch. The cache is cleared.
+// Called by the whole workgroup.
 template <int L>
-MR_DEV void lds_flush_parts(LdsTable<L>& T, const WordJob& J, uint32_t job, uint32_t* pc, uint64_t vlo, uint64_t vhi,
+MR_DEV void lds_flush_parts(LdsTable<L>& T, const WordJob& J, uint32_t job, uint32_t* mfill, uint64_t vlo, uint64_t vhi,
                             uint32_t debug_hash) {
-  for (uint32_t p = threadIdx.x; p < kFlushParts; p += blockDim.x) pc[p] = 0;
-  __syncthreads();
-  for (uint32_t i = threadIdx.x; i < LdsTable<L>::kSlots; i += blockDim.x) {
-    const uint32_t tg = T.tag[i];
-    if (tg & 1u) atomicAdd(&pc[key_hash16(T.key[i], (tg >> 1) & 31u, debug_hash) >> kFlushShift], 1u);
-  }
-  __syncthreads();
-  for (uint32_t p = threadIdx.x; p < kFlushParts; p += blockDim.x) {
-    const uint32_t c = pc[p];
-    pc[kFlushParts + p] = c ? __hip_atomic_fetch_add(gp(&J.qcnt[p]), c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
-    pc[p] = 0;
-  }
-  __syncthreads();
-  FlushRec* q = reinterpret_cast<FlushRec*>(J.queue);
+  FlushRec* const mq = reinterpret_cast<FlushRec*>(J.mq);
   for (uint32_t i = threadIdx.x; i < LdsTable<L>::kSlots; i += blockDim.x) {
     const uint32_t tg = T.tag[i];
     if (tg & 1u) {
       const uint32_t len = (tg >> 1) & 31u;
       const uint4 k = T.key[i];
       const uint64_t h = key_hash16(k, len, debug_hash);
-      const uint32_t p = (uint32_t)(h >> kFlushShift);
-      const uint32_t at = pc[kFlushParts + p] + atomicAdd(&pc[p], 1u);
-      if (at < J.qcap) {
-        FlushRec* dst = &q[(uint64_t)p * J.qcap + at];
+      const uint32_t q = (uint32_t)(h >> J.part_shift);
+      const uint32_t at = atomicAdd(&mfill[q], 1u);
+      if (at < J.mq_cap) {
+        FlushRec* dst = mq + ((uint64_t)q * J.mq_grid + blockIdx.x) * J.mq_cap + at;
         gstore16(&dst->k, k);
         gstore16(&dst->off, make_uint4(T.off[i], len, T.cnt[i], job));
       } else {
@@ -526,17 +514,15 @@ __global__ __launch_bounds__(kMapThreads) void k_words_map(const WordJob* __rest
   __shared__ __attribute__((aligned(16))) uint32_t s_kmask[64][4];
   constexpr uint32_t kBndWords = kWave * 16 / 32;  // boundary bits of the 1 KiB window
   __shared__ uint32_t bnd[kRecords ? kWaves : 1][kRecords ? kBndWords + 1 : 1];
-  __shared__ uint32_t s_used;
-  __shared__ uint32_t s_mfill[kFlushParts];  // this workgroup's miss sub-queue fills
+  __shared__ uint32_t s_mfill[kMaxWordParts];  // this workgroup's sub-queue fills
 
   for (uint32_t i = threadIdx.x; i < LdsTable<L>::kSlots; i += blockDim.x) T.tag[i] = 0u;
-  for (uint32_t i = threadIdx.x; i < kFlushParts; i += blockDim.x) s_mfill[i] = 0u;
+  for (uint32_t i = threadIdx.x; i < kMaxWordParts; i += blockDim.x) s_mfill[i] = 0u;
   if (threadIdx.x < 256) {
     const uint32_t n = threadIdx.x >> 2, w = threadIdx.x & 3u;
     const int keep = n <= 16u ? (int)n - 4 * (int)w : 0;
     s_kmask[n][w] = keep >= 4 ? ~0u : (keep <= 0 ? 0u : (1u << (8 * keep)) - 1u);
   }
-  if (threadIdx.x == 0) s_used = 0;
   __syncthreads();
 
   const uint64_t t_begin = total_tiles * blockIdx.x / gridDim.x;
@@ -587,10 +573,9 @@ __global__ __launch_bounds__(kMapThreads) void k_words_map(const WordJob* __rest
       // every wave meets this point at the same tile
       __syncthreads();
       if (cur >= 0) {
-        if (jobs[cur].queue)
-          lds_flush_parts<L>(T, jobs[cur], (uint32_t)cur, reinterpret_cast<uint32_t*>(&wlist[0][0]), vlo, vhi, debug_hash);
+        if (jobs[cur].mq)
+          lds_flush_parts<L>(T, jobs[cur], (uint32_t)cur, s_mfill, vlo, vhi, debug_hash);
         else lds_flush<L>(T, jobs[cur], vlo, vhi, debug_hash);
-        if (threadIdx.x == 0) s_used = 0;
         __syncthreads();
       }
       cur = (int)j;
@@ -693,7 +678,7 @@ __global__ __launch_bounds__(kMapThreads) void k_words_map(const WordJob* __rest
         const uint64_t h64 = hash_from32(h);
         if (J.mq) {
           // into this workgroup's sub-queue of the key's partition
-          const uint32_t q = (uint32_t)(h64 >> kFlushShift);
+          const uint32_t q = (uint32_t)(h64 >> J.part_shift);
           const uint32_t at = atomicAdd(&s_mfill[q], 1u);
           if (at < J.mq_cap) {
             FlushRec* dst = reinterpret_cast<FlushRec*>(J.mq) + ((uint64_t)q * J.mq_grid + blockIdx.x) * J.mq_cap + at;
@@ -709,7 +694,7 @@ __global__ __launch_bounds__(kMapThreads) void k_words_map(const WordJob* __rest
       auto slow = [&](uint32_t tg, uint32_t h, uint4 k, uint32_t off, uint32_t v) -> int {
         int r = 1;
         for (uint32_t spin = 0; r == 1; ++spin) {
-          r = lds_insert<L, 1>(T, &s_used, LdsTable<L>::kSlots, tg, h, k, off, v);
+          r = lds_insert<L, 1>(T, tg, h, k, off, v);
           if (r == 1 && spin > (1u << 22)) {
             __hip_atomic_fetch_or(gp(&J.st->flags), kFlagSpin, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             r = 0;
@@ -808,16 +793,16 @@ __global__ __launch_bounds__(kMapThreads) void k_words_map(const WordJob* __rest
   }
   __syncthreads();
   if (cur >= 0) {
-    if (jobs[cur].queue)
-          lds_flush_parts<L>(T, jobs[cur], (uint32_t)cur, reinterpret_cast<uint32_t*>(&wlist[0][0]), vlo, vhi, debug_hash);
+    if (jobs[cur].mq) lds_flush_parts<L>(T, jobs[cur], (uint32_t)cur, s_mfill, vlo, vhi, debug_hash);
     else lds_flush<L>(T, jobs[cur], vlo, vhi, debug_hash);
   }
-  // the miss sub-queue fills (the sub-queues are shared by the jobs of a
-  // batch; every workgroup writes all of its entries, zero or not, so
-  // nothing needs clearing before)
+  // the sub-queue fills, once every flushed entry has taken its place (the
+  // sub-queues are shared by the jobs of a batch; every workgroup writes all
+  // of its entries, zero or not, so nothing needs clearing before)
+  __syncthreads();
   const WordJob& J0 = jobs[0];
   if (J0.mq)
-    for (uint32_t q = threadIdx.x; q < kFlushParts; q += blockDim.x) {
+    for (uint32_t q = threadIdx.x; q < (1u << (64 - J0.part_shift)); q += blockDim.x) {
       const uint32_t f = s_mfill[q];
       J0.mq_fill[q * J0.mq_grid + blockIdx.x] = f < J0.mq_cap ? f : J0.mq_cap;
     }
@@ -840,27 +825,21 @@ __global__ __launch_bounds__(kMapThreads) void k_words_parts(const WordJob* __re
   static_assert(kSlots / 2 + kMapThreads <= kSlots / 4 * 3, "a round cannot fill the table");
   __shared__ LdsTable<L> T;
   __shared__ uint32_t s_job[kSlots];
-  __shared__ uint32_t s_pre[kMaxMapGrid + 2];  // first record of each segment: flush queue, then sub-queue w
+  __shared__ uint32_t s_pre[kMaxMapGrid + 1];  // first record of each segment (map workgroup w's sub-queue)
   __shared__ uint32_t s_used;
   const WordJob& Q = jobs[0];  // the queues (shared by the jobs of a batch)
   const uint32_t p = blockIdx.x;
   for (uint32_t i = threadIdx.x; i < kSlots; i += blockDim.x) T.tag[i] = 0u;
   if (threadIdx.x == 0) s_used = 0;
-  // exclusive prefix of the segment sizes (segment 0: the flush queue;
-  // segment 1 + w: map workgroup w's sub-queue), blockDim at a time
+  // exclusive prefix of the segment sizes (segment w: map workgroup w's
+  // sub-queue of this partition), blockDim at a time
   __shared__ uint32_t s_wsum[kMapThreads / kWave];
-  const uint32_t G = Q.mq ? Q.mq_grid : 0u;
+  const uint32_t G = Q.mq_grid;
   const uint32_t lane = lane_id(), wv = threadIdx.x / kWave, nw = blockDim.x / kWave;
   uint32_t carry = 0;
-  for (uint32_t b0 = 0; b0 <= G; b0 += blockDim.x) {
+  for (uint32_t b0 = 0; b0 < G; b0 += blockDim.x) {
     const uint32_t w = b0 + threadIdx.x;
-    uint32_t c = 0;
-    if (w == 0) {
-      const uint32_t qn = *gp(&Q.qcnt[p]);
-      c = qn < Q.qcap ? qn : Q.qcap;
-    } else if (w <= G) {
-      c = *gp(&Q.mq_fill[p * Q.mq_grid + (w - 1)]);
-    }
+    const uint32_t c = w < G ? *gp(&Q.mq_fill[p * Q.mq_grid + w]) : 0u;
     const uint32_t incl = wave_incl_scan(c);
     if (lane == kWave - 1) s_wsum[wv] = incl;
     __syncthreads();
@@ -869,43 +848,40 @@ __global__ __launch_bounds__(kMapThreads) void k_words_parts(const WordJob* __re
       if (q < wv) before += s_wsum[q];
       all += s_wsum[q];
     }
-    if (w <= G) s_pre[w] = before + incl - c;
+    if (w < G) s_pre[w] = before + incl - c;
     carry += all;
     __syncthreads();
   }
-  if (threadIdx.x == 0) s_pre[G + 1] = carry;
+  if (threadIdx.x == 0) s_pre[G] = carry;
   __syncthreads();
   const uint32_t total = carry;
-  const FlushRec* fq = reinterpret_cast<const FlushRec*>(Q.queue) + (uint64_t)p * Q.qcap;
   // record r of the partition: the last segment starting at or before it.
   // A thread's records only move forward, so the search gallops on from its
   // previous segment (steps 1, 2, 4, ...) and then bisects.
   uint32_t seg = 0;
   auto rec_at = [&](uint32_t r) -> const FlushRec* {
-    uint32_t lo = seg, hi = seg + 1, step = 1;  // s_pre[lo] <= r < total = s_pre[G + 1]
-    while (hi <= G && s_pre[hi] <= r) {
+    uint32_t lo = seg, hi = seg + 1, step = 1;  // s_pre[lo] <= r < total = s_pre[G]
+    while (hi < G && s_pre[hi] <= r) {
       lo = hi;
       step <<= 1;
       hi = lo + step;
     }
-    if (hi > G + 1) hi = G + 1;
+    if (hi > G) hi = G;
     while (hi - lo > 1) {
       const uint32_t mid = (lo + hi) >> 1;
       if (s_pre[mid] <= r) lo = mid; else hi = mid;
     }
     seg = lo;
-    const uint32_t e = r - s_pre[seg];
-    if (seg == 0) return fq + e;
-    return reinterpret_cast<const FlushRec*>(Q.mq) + ((uint64_t)p * Q.mq_grid + (seg - 1)) * Q.mq_cap + e;
+    return reinterpret_cast<const FlushRec*>(Q.mq) + ((uint64_t)p * Q.mq_grid + seg) * Q.mq_cap + (r - s_pre[seg]);
   };
-  auto consume = [&](uint4 k, uint4 m) {  // m: off, len, count, job
+  auto consume = [&](uint4 k, uint4 m) -> bool {  // m: off, len, count, job; true: claimed a slot
     const uint32_t hk = lds_hash32(k, m.y, debug_hash);
     // the LDS placement mixes in the job; the global table takes the key's own hash
     const uint32_t h32 = hk ^ (m.w * 0x9E3779B1u);
     const uint32_t tg = (h32 & 0xFFFFFFC0u) | (m.y << 1);
     int r = 1;
     for (uint32_t spin = 0; r == 1; ++spin) {
-      r = lds_insert<L>(T, &s_used, kSlots, tg, h32, k, m.x, m.z, s_job, m.w);
+      r = lds_insert<L>(T, tg, h32, k, m.x, m.z, s_job, m.w);
       if (r == 1 && spin > (1u << 22)) {
         __hip_atomic_fetch_or(gp(&jobs[m.w].st->flags), kFlagSpin, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         r = 0;
@@ -913,6 +889,7 @@ __global__ __launch_bounds__(kMapThreads) void k_words_parts(const WordJob* __re
     }
     // the key's probe groups are full (rare below three quarters load)
     if (r == 2) g_insert<true>(jobs[m.w], 0, 0, m.x, m.y, hash_from32(hk), k, m.z, debug_hash);
+    return r == 4;
   };
   // the summed keys into their jobs' tables; the table is cleared
   auto flush = [&]() {
@@ -941,7 +918,10 @@ __global__ __launch_bounds__(kMapThreads) void k_words_parts(const WordJob* __re
       nk = gload16(&rp->k);
       nm = gload16(&rp->off);
     }
-    if (have) consume(k, m);
+    const bool claimed = have && consume(k, m);
+    // the round's claims, one LDS add per wave
+    const uint32_t nc = popc64(__ballot(claimed));
+    if (lane == 0 && nc) atomicAdd(&s_used, nc);
     __syncthreads();
     const bool full = s_used > kSlots / 2;  // uniform: read after the barrier
     __syncthreads();
@@ -1833,7 +1813,7 @@ hipError_t words_enqueue_map(const WordsLaunch& L, hipStream_t s) {
   }
 #undef MR_MAP_CASE
 #undef MR_MAP_LAUNCH
-  if (L.flush_parts) hipLaunchKernelGGL((k_words_parts<12>), dim3(kFlushParts), dim3(kMapThreads), 0, s, L.jobs, L.debug_hash);
+  if (L.n_parts) hipLaunchKernelGGL((k_words_parts<12>), dim3(L.n_parts), dim3(kMapThreads), 0, s, L.jobs, L.debug_hash);
   return hipGetLastError();
 }
 
