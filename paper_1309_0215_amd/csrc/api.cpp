@@ -689,6 +689,11 @@ mr_status words_pass(mr_job* job, std::vector<WordItem>& items, std::vector<JobS
     J.mq = p.n_parts ? ws + p.o_mq : nullptr;
     J.mq_fill = p.n_parts ? reinterpret_cast<uint32_t*>(ws + p.o_mqfill) : nullptr;
     J.part_shift = p.n_parts ? 64u - (uint32_t)__builtin_ctz(p.n_parts) : 64u;
+    // large tables are split into one region per partition (not with forced
+    // hash collisions, which put every key of a length into one region)
+    J.region_log2 = (p.n_parts && !job->cfg.debug_hash && it.cap >= 256ull * p.n_parts)
+                        ? (uint32_t)__builtin_ctzll(it.cap) - (uint32_t)__builtin_ctz(p.n_parts)
+                        : 0u;
     any_rec |= it.rec != nullptr;
   }
   MR_HIP(hipMemcpyAsync(ws + p.o_jobs, hj.data(), sizeof(WordJob) * n, hipMemcpyHostToDevice, s));

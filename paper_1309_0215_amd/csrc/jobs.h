@@ -70,7 +70,11 @@ struct WordJob {
   void* mq;
   uint32_t* mq_fill;
   uint32_t part_shift;
-  uint32_t pad;
+  // 0, or log2 of the slots of one partition's region of the global table:
+  // a key of partition p then lives in slots [p << region_log2, (p + 1) <<
+  // region_log2) (probing wraps inside the region), so that in the summing
+  // kernel only partition p's workgroup writes region p
+  uint32_t region_log2;
 };
 
 constexpr uint32_t kMaxWordParts = 4096;  // partitions of the two-phase reduce (top 8 to 12 hash bits)

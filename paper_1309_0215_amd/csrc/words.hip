@@ -216,25 +216,32 @@ constexpr uint64_t kMaxProbe = 512;
 // Insert one key with value v. Inline keys (len <= 16) come with k; longer
 // keys are compared against the input at off. Returns false on a full table;
 // otherwise the key's slot goes to *slot_out when it is given. v = 0 claims
-// or finds the slot without touching its count.
-template <bool kInline>
+// or finds the slot without touching its count. kWorkgroup: the caller's
+// workgroup is the only writer of the key's table region while it runs (the
+// summing kernel of the partition queues), so workgroup-scope atomics do,
+// which complete in the L2 instead of at the device's coherence point.
+template <bool kInline, bool kWorkgroup = false>
 MR_DEV bool g_insert(const WordJob& J, uint64_t vlo, uint64_t vhi, uint64_t off, uint64_t len, uint64_t h, uint4 k,
                      uint32_t v, uint32_t debug_hash, uint64_t* slot_out = nullptr) {
+  constexpr int kScope = kWorkgroup ? __HIP_MEMORY_SCOPE_WORKGROUP : __HIP_MEMORY_SCOPE_AGENT;
   const uint64_t word = gword(off, len, h);
-  const uint64_t mask = J.cap - 1;
+  // the key's region of the table (the whole table, or its partition's region)
+  const uint64_t mask = J.region_log2 ? (1ull << J.region_log2) - 1 : J.cap - 1;
+  const uint64_t base = J.region_log2 ? (h >> J.part_shift) << J.region_log2 : 0ull;
   // (with every key forced onto one hash the whole table is one run)
   const uint64_t limit = (debug_hash || mask < kMaxProbe) ? mask : kMaxProbe;
-  uint64_t i = h & mask;
+  uint64_t r = h & mask;
   for (uint64_t p = 0; p <= limit; ++p) {
+    const uint64_t i = base + r;
     // A relaxed load may be stale only as 0 (slots are written once per run);
     // the CAS below then returns the current word.
     unsigned long long cur = __hip_atomic_load(gp(&J.tw[i]), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     if (cur == 0ull) {
       unsigned long long old = 0ull;
       __hip_atomic_compare_exchange_strong(gp(&J.tw[i]), &old, (unsigned long long)word, __ATOMIC_RELAXED,
-                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                                           __ATOMIC_RELAXED, kScope);
       if (old == 0ull) {
-        if (v) __hip_atomic_fetch_add(gp(&J.tc[i]), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (v) __hip_atomic_fetch_add(gp(&J.tc[i]), v, __ATOMIC_RELAXED, kScope);
         if (slot_out) *slot_out = i;
         return true;
       }
@@ -244,12 +251,12 @@ MR_DEV bool g_insert(const WordJob& J, uint64_t vlo, uint64_t vhi, uint64_t off,
       const uint64_t rep = cur >> 32;
       const bool eq = kInline ? rep_equals_inline(J, rep, k, (uint32_t)len) : rep_equals_global(J, vlo, vhi, rep, off, len);
       if (eq) {
-        if (v) __hip_atomic_fetch_add(gp(&J.tc[i]), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (v) __hip_atomic_fetch_add(gp(&J.tc[i]), v, __ATOMIC_RELAXED, kScope);
         if (slot_out) *slot_out = i;
         return true;
       }
     }
-    i = (i + 1) & mask;
+    r = (r + 1) & mask;
     if ((p & 255u) == 255u &&
         (__hip_atomic_load(gp(&J.st->flags), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kFlagTableFull))
       return false;
@@ -874,6 +881,12 @@ __global__ __launch_bounds__(kMapThreads) void k_words_parts(const WordJob* __re
     seg = lo;
     return reinterpret_cast<const FlushRec*>(Q.mq) + ((uint64_t)p * Q.mq_grid + seg) * Q.mq_cap + (r - s_pre[seg]);
   };
+  // a summed key into its job's table: with the table split into partition
+  // regions, this workgroup is the region's only writer
+  auto insert = [&](const WordJob& J, uint32_t off, uint32_t len, uint64_t h, uint4 k, uint32_t v) {
+    if (J.region_log2) g_insert<true, true>(J, 0, 0, off, len, h, k, v, debug_hash);
+    else g_insert<true>(J, 0, 0, off, len, h, k, v, debug_hash);
+  };
   auto consume = [&](uint4 k, uint4 m) -> bool {  // m: off, len, count, job; true: claimed a slot
     const uint32_t hk = lds_hash32(k, m.y, debug_hash);
     // the LDS placement mixes in the job; the global table takes the key's own hash
@@ -888,7 +901,7 @@ __global__ __launch_bounds__(kMapThreads) void k_words_parts(const WordJob* __re
       }
     }
     // the key's probe groups are full (rare below three quarters load)
-    if (r == 2) g_insert<true>(jobs[m.w], 0, 0, m.x, m.y, hash_from32(hk), k, m.z, debug_hash);
+    if (r == 2) insert(jobs[m.w], m.x, m.y, hash_from32(hk), k, m.z);
     return r == 4;
   };
   // the summed keys into their jobs' tables; the table is cleared
@@ -898,7 +911,7 @@ __global__ __launch_bounds__(kMapThreads) void k_words_parts(const WordJob* __re
       if (tg & 1u) {
         const uint32_t len = (tg >> 1) & 31u;
         const uint4 k = T.key[i];
-        g_insert<true>(jobs[s_job[i]], 0, 0, T.off[i], len, key_hash16(k, len, debug_hash), k, T.cnt[i], debug_hash);
+        insert(jobs[s_job[i]], T.off[i], len, key_hash16(k, len, debug_hash), k, T.cnt[i]);
       }
       T.tag[i] = 0u;
     }
