@@ -477,8 +477,8 @@ struct WordsPlan {
   uint64_t o_jobs, o_tile_base, o_states, o_totals, o_bucket_cnt, o_bucket_bytes, o_bucket_start, o_bucket_bstart,
       o_bucket_fill, o_tw, o_tc, o_recs, o_recs2, o_rbucket, o_spl, o_slot_rank = 0;
   uint32_t n_parts = 0;  // partitions of the two-phase reduce (0: none)
-  uint64_t o_mq = 0, o_mqfill = 0;
-  uint32_t mq_cap = 0, grid = 1;  // records per sub-queue; map workgroups
+  uint64_t o_mq = 0, o_mqfill = 0, o_sq = 0, o_sqfill = 0;
+  uint32_t mq_cap = 0, sq_cap = 0, grid = 1;  // records per 32-byte and 16-byte sub-queue; map workgroups
   uint64_t total_slots = 0, total_tiles = 0;
   std::vector<uint64_t> slot_base, tile_base;
 };
@@ -490,17 +490,18 @@ struct WordsPlan {
 // fit the L2 (measured on 512 MiB of text: map 575 -> 754 us).
 uint32_t word_parts(uint64_t) { return 256u; }
 
-// Records per sub-queue (one per map workgroup and partition, shared by the
-// jobs of a batch): room for half the words of an input of mean word length 8
-// missing the LDS caches, spread evenly, plus the entries of the caches the
-// workgroup flushes (3/4 of 4096 slots, once per job it meets: at most
-// n_jobs + grid flushes in all), with slack. A full sub-queue sends its
-// overflow to the global table directly.
+// Records per sub-queue of each kind (one per map workgroup and partition,
+// shared by the jobs of a batch): room for half the words of an input of mean
+// word length 8 missing the LDS caches, spread evenly, plus the entries of the
+// caches the workgroup flushes (3/4 of 4096 slots, once per job it meets: at
+// most n_jobs + grid flushes in all), with half again as slack; either kind
+// can take all of them. A full sub-queue sends its overflow to the global
+// table directly.
 uint32_t miss_queue_cap(uint64_t n, uint32_t grid, uint32_t parts, uint64_t n_jobs) {
   const uint64_t misses = n / (16ull * grid * parts);
   const uint64_t flushed = 3072ull * (n_jobs + grid) / ((uint64_t)grid * parts);
   const uint64_t want = misses + flushed + 1;
-  return (uint32_t)std::min<uint64_t>(4096, std::max<uint64_t>(16, next_pow2(want + want / 2)));
+  return (uint32_t)std::min<uint64_t>(6144, std::max<uint64_t>(16, want + want / 2));
 }
 
 WordsPlan plan_words(const std::vector<WordItem>& items, bool slot_ranks, bool queues, uint64_t grid_cap) {
@@ -540,9 +541,11 @@ WordsPlan plan_words(const std::vector<WordItem>& items, bool slot_ranks, bool q
     uint64_t total_n = 0;
     for (const WordItem& it : items) total_n += it.n;
     p.n_parts = word_parts(total_n);
-    p.mq_cap = miss_queue_cap(total_n, p.grid, p.n_parts, n);
+    p.mq_cap = p.sq_cap = miss_queue_cap(total_n, p.grid, p.n_parts, n);
     p.o_mq = p.c.take(32ull * p.n_parts * p.grid * p.mq_cap);
     p.o_mqfill = p.c.take(4ull * p.n_parts * p.grid);
+    p.o_sq = p.c.take(16ull * p.n_parts * p.grid * p.sq_cap);
+    p.o_sqfill = p.c.take(4ull * p.n_parts * p.grid);
   }
   return p;
 }
@@ -688,6 +691,9 @@ mr_status words_pass(mr_job* job, std::vector<WordItem>& items, std::vector<JobS
     J.mq_grid = p.grid;
     J.mq = p.n_parts ? ws + p.o_mq : nullptr;
     J.mq_fill = p.n_parts ? reinterpret_cast<uint32_t*>(ws + p.o_mqfill) : nullptr;
+    J.sq_cap = p.sq_cap;
+    J.sq = p.n_parts ? ws + p.o_sq : nullptr;
+    J.sq_fill = p.n_parts ? reinterpret_cast<uint32_t*>(ws + p.o_sqfill) : nullptr;
     J.part_shift = p.n_parts ? 64u - (uint32_t)__builtin_ctz(p.n_parts) : 64u;
     // large tables are split into one region per partition (not with forced
     // hash collisions, which put every key of a length into one region)

@@ -65,10 +65,16 @@ struct WordJob {
   // fill in mq_fill[p * mq_grid + w]; one workgroup per partition then sums
   // the records by key. A key's partition is its 64-bit hash >> part_shift
   // (n_parts = 2^(64 - part_shift)).
+  // Records of keys of up to 8 bytes (with counts below 4096 and job
+  // indices below 65536) take 16 bytes in a second set of sub-queues (sq,
+  // sq_fill, sq_cap, laid out alike); the others take 32 bytes in mq.
   uint32_t mq_cap;
   uint32_t mq_grid;
   void* mq;
   uint32_t* mq_fill;
+  void* sq;
+  uint32_t* sq_fill;
+  uint32_t sq_cap;
   uint32_t part_shift;
   // 0, or log2 of the slots of one partition's region of the global table:
   // a key of partition p then lives in slots [p << region_log2, (p + 1) <<
@@ -77,7 +83,7 @@ struct WordJob {
   uint32_t region_log2;
 };
 
-constexpr uint32_t kMaxWordParts = 4096;  // partitions of the two-phase reduce (top 8 to 12 hash bits)
+constexpr uint32_t kMaxWordParts = 256;  // partitions of the two-phase reduce (the top 8 hash bits)
 
 // Compacted table entry of a word, ordered by (p, len) then tail bytes.
 struct WRec {

@@ -299,11 +299,10 @@ __global__ void k_words_prep(const WordJob* __restrict__ jobs, uint32_t n_jobs) 
 // load. A word visits at most kLdsGroups groups before it goes global.
 constexpr int kLdsGroups = 4;
 // Word descriptors a wave lists per round (a multiple of 128: two words per
-// lane per step). A window's 992 owned bytes hold at most 497 word starts
-// (each but the first follows a separator) and text of mean token length 8
-// about 120, so nearly every window takes one round; windows with more
-// starts, and record boundaries, which can add starts, take more rounds.
-constexpr uint32_t kListCap = 384;
+// lane per step): a window's 992 owned bytes hold at most 497 word starts
+// (each but the first follows a separator), so one round takes every window;
+// record boundaries can add starts, which take more rounds.
+constexpr uint32_t kListCap = 512;
 
 template <int kSlotsLog2>
 struct LdsTable {
@@ -396,31 +395,44 @@ struct FlushRec {
   uint32_t off, len, cnt, job;
 };
 
+// Appends a record to this workgroup's sub-queue of partition q: 16 bytes
+// (key bytes 0..7, offset, length | count << 4 | job << 16) for a key of up
+// to 8 bytes with a count below 4096 and a job index below 65536, 32 bytes
+// otherwise; the positions come from the workgroup's LDS fill counters.
+// Returns false when that sub-queue is full (the caller inserts globally).
+MR_DEV bool queue_append(const WordJob& J, uint32_t* mfill, uint32_t* sfill, uint32_t q, uint4 k, uint32_t off, uint32_t len,
+                         uint32_t cnt, uint32_t job) {
+  const uint64_t sub = (uint64_t)q * J.mq_grid + blockIdx.x;
+  if (len <= 8u && cnt < 4096u && job < 65536u) {
+    const uint32_t at = atomicAdd(&sfill[q], 1u);
+    if (at >= J.sq_cap) return false;
+    gstore16(reinterpret_cast<uint4*>(J.sq) + sub * J.sq_cap + at, make_uint4(k.x, k.y, off, len | (cnt << 4) | (job << 16)));
+    return true;
+  }
+  const uint32_t at = atomicAdd(&mfill[q], 1u);
+  if (at >= J.mq_cap) return false;
+  FlushRec* dst = reinterpret_cast<FlushRec*>(J.mq) + sub * J.mq_cap + at;
+  gstore16(&dst->k, k);
+  gstore16(&dst->off, make_uint4(off, len, cnt, job));
+  return true;
+}
+
 // Two-phase reduce, first phase, for the cache: every entry of the
 // workgroup's LDS cache goes to the workgroup's own sub-queue of its key's
-// partition, after the words the cache missed (positions from the LDS fill
-// counters mfill); an entry that finds its sub-queue full is inserted
-// globally at once. J is job `job` of the batch. The cache is cleared.
-// Called by the whole workgroup.
+// partition, after the words the cache missed; an entry that finds its
+// sub-queue full is inserted globally at once. J is job `job` of the batch.
+// The cache is cleared. Called by the whole workgroup.
 template <int L>
-MR_DEV void lds_flush_parts(LdsTable<L>& T, const WordJob& J, uint32_t job, uint32_t* mfill, uint64_t vlo, uint64_t vhi,
-                            uint32_t debug_hash) {
-  FlushRec* const mq = reinterpret_cast<FlushRec*>(J.mq);
+MR_DEV void lds_flush_parts(LdsTable<L>& T, const WordJob& J, uint32_t job, uint32_t* mfill, uint32_t* sfill, uint64_t vlo,
+                            uint64_t vhi, uint32_t debug_hash) {
   for (uint32_t i = threadIdx.x; i < LdsTable<L>::kSlots; i += blockDim.x) {
     const uint32_t tg = T.tag[i];
     if (tg & 1u) {
       const uint32_t len = (tg >> 1) & 31u;
       const uint4 k = T.key[i];
       const uint64_t h = key_hash16(k, len, debug_hash);
-      const uint32_t q = (uint32_t)(h >> J.part_shift);
-      const uint32_t at = atomicAdd(&mfill[q], 1u);
-      if (at < J.mq_cap) {
-        FlushRec* dst = mq + ((uint64_t)q * J.mq_grid + blockIdx.x) * J.mq_cap + at;
-        gstore16(&dst->k, k);
-        gstore16(&dst->off, make_uint4(T.off[i], len, T.cnt[i], job));
-      } else {
+      if (!queue_append(J, mfill, sfill, (uint32_t)(h >> J.part_shift), k, T.off[i], len, T.cnt[i], job))
         g_insert<true>(J, vlo, vhi, T.off[i], len, h, k, T.cnt[i], debug_hash);
-      }
     }
     T.tag[i] = 0u;
   }
@@ -521,10 +533,13 @@ __global__ __launch_bounds__(kMapThreads) void k_words_map(const WordJob* __rest
   __shared__ __attribute__((aligned(16))) uint32_t s_kmask[64][4];
   constexpr uint32_t kBndWords = kWave * 16 / 32;  // boundary bits of the 1 KiB window
   __shared__ uint32_t bnd[kRecords ? kWaves : 1][kRecords ? kBndWords + 1 : 1];
-  __shared__ uint32_t s_mfill[kMaxWordParts];  // this workgroup's sub-queue fills
+  __shared__ uint32_t s_mfill[kMaxWordParts], s_sfill[kMaxWordParts];  // this workgroup's sub-queue fills
 
   for (uint32_t i = threadIdx.x; i < LdsTable<L>::kSlots; i += blockDim.x) T.tag[i] = 0u;
-  for (uint32_t i = threadIdx.x; i < kMaxWordParts; i += blockDim.x) s_mfill[i] = 0u;
+  for (uint32_t i = threadIdx.x; i < kMaxWordParts; i += blockDim.x) {
+    s_mfill[i] = 0u;
+    s_sfill[i] = 0u;
+  }
   if (threadIdx.x < 256) {
     const uint32_t n = threadIdx.x >> 2, w = threadIdx.x & 3u;
     const int keep = n <= 16u ? (int)n - 4 * (int)w : 0;
@@ -581,7 +596,7 @@ __global__ __launch_bounds__(kMapThreads) void k_words_map(const WordJob* __rest
       __syncthreads();
       if (cur >= 0) {
         if (jobs[cur].mq)
-          lds_flush_parts<L>(T, jobs[cur], (uint32_t)cur, s_mfill, vlo, vhi, debug_hash);
+          lds_flush_parts<L>(T, jobs[cur], (uint32_t)cur, s_mfill, s_sfill, vlo, vhi, debug_hash);
         else lds_flush<L>(T, jobs[cur], vlo, vhi, debug_hash);
         __syncthreads();
       }
@@ -683,17 +698,8 @@ __global__ __launch_bounds__(kMapThreads) void k_words_map(const WordJob* __rest
           return;
         }
         const uint64_t h64 = hash_from32(h);
-        if (J.mq) {
-          // into this workgroup's sub-queue of the key's partition
-          const uint32_t q = (uint32_t)(h64 >> J.part_shift);
-          const uint32_t at = atomicAdd(&s_mfill[q], 1u);
-          if (at < J.mq_cap) {
-            FlushRec* dst = reinterpret_cast<FlushRec*>(J.mq) + ((uint64_t)q * J.mq_grid + blockIdx.x) * J.mq_cap + at;
-            gstore16(&dst->k, k);
-            gstore16(&dst->off, make_uint4(off, len, v, j));
-            return;
-          }
-        }
+        // into this workgroup's sub-queue of the key's partition
+        if (J.mq && queue_append(J, s_mfill, s_sfill, (uint32_t)(h64 >> J.part_shift), k, off, len, v, j)) return;
         g_insert<true>(J, vlo, vhi, off, len, h64, k, v, debug_hash);
       };
       // the home-group lookup could not decide: the full insert, retried
@@ -800,7 +806,7 @@ __global__ __launch_bounds__(kMapThreads) void k_words_map(const WordJob* __rest
   }
   __syncthreads();
   if (cur >= 0) {
-    if (jobs[cur].mq) lds_flush_parts<L>(T, jobs[cur], (uint32_t)cur, s_mfill, vlo, vhi, debug_hash);
+    if (jobs[cur].mq) lds_flush_parts<L>(T, jobs[cur], (uint32_t)cur, s_mfill, s_sfill, vlo, vhi, debug_hash);
     else lds_flush<L>(T, jobs[cur], vlo, vhi, debug_hash);
   }
   // the sub-queue fills, once every flushed entry has taken its place (the
@@ -810,8 +816,9 @@ __global__ __launch_bounds__(kMapThreads) void k_words_map(const WordJob* __rest
   const WordJob& J0 = jobs[0];
   if (J0.mq)
     for (uint32_t q = threadIdx.x; q < (1u << (64 - J0.part_shift)); q += blockDim.x) {
-      const uint32_t f = s_mfill[q];
+      const uint32_t f = s_mfill[q], g = s_sfill[q];
       J0.mq_fill[q * J0.mq_grid + blockIdx.x] = f < J0.mq_cap ? f : J0.mq_cap;
+      J0.sq_fill[q * J0.mq_grid + blockIdx.x] = g < J0.sq_cap ? g : J0.sq_cap;
     }
 }
 
@@ -832,21 +839,22 @@ __global__ __launch_bounds__(kMapThreads) void k_words_parts(const WordJob* __re
   static_assert(kSlots / 2 + kMapThreads <= kSlots / 4 * 3, "a round cannot fill the table");
   __shared__ LdsTable<L> T;
   __shared__ uint32_t s_job[kSlots];
-  __shared__ uint32_t s_pre[kMaxMapGrid + 1];  // first record of each segment (map workgroup w's sub-queue)
+  // first record of each segment: map workgroup w's 32-byte sub-queue (w),
+  // then its 16-byte one (G + w)
+  __shared__ uint32_t s_pre[2 * kMaxMapGrid + 1];
   __shared__ uint32_t s_used;
   const WordJob& Q = jobs[0];  // the queues (shared by the jobs of a batch)
   const uint32_t p = blockIdx.x;
   for (uint32_t i = threadIdx.x; i < kSlots; i += blockDim.x) T.tag[i] = 0u;
   if (threadIdx.x == 0) s_used = 0;
-  // exclusive prefix of the segment sizes (segment w: map workgroup w's
-  // sub-queue of this partition), blockDim at a time
+  // exclusive prefix of the segment sizes, blockDim at a time
   __shared__ uint32_t s_wsum[kMapThreads / kWave];
-  const uint32_t G = Q.mq_grid;
+  const uint32_t G = Q.mq_grid, NS = 2 * G;
   const uint32_t lane = lane_id(), wv = threadIdx.x / kWave, nw = blockDim.x / kWave;
   uint32_t carry = 0;
-  for (uint32_t b0 = 0; b0 < G; b0 += blockDim.x) {
+  for (uint32_t b0 = 0; b0 < NS; b0 += blockDim.x) {
     const uint32_t w = b0 + threadIdx.x;
-    const uint32_t c = w < G ? *gp(&Q.mq_fill[p * Q.mq_grid + w]) : 0u;
+    const uint32_t c = w < G ? *gp(&Q.mq_fill[p * G + w]) : (w < NS ? *gp(&Q.sq_fill[p * G + (w - G)]) : 0u);
     const uint32_t incl = wave_incl_scan(c);
     if (lane == kWave - 1) s_wsum[wv] = incl;
     __syncthreads();
@@ -855,31 +863,45 @@ __global__ __launch_bounds__(kMapThreads) void k_words_parts(const WordJob* __re
       if (q < wv) before += s_wsum[q];
       all += s_wsum[q];
     }
-    if (w < G) s_pre[w] = before + incl - c;
+    if (w < NS) s_pre[w] = before + incl - c;
     carry += all;
     __syncthreads();
   }
-  if (threadIdx.x == 0) s_pre[G] = carry;
+  if (threadIdx.x == 0) s_pre[NS] = carry;
   __syncthreads();
   const uint32_t total = carry;
   // record r of the partition: the last segment starting at or before it.
   // A thread's records only move forward, so the search gallops on from its
   // previous segment (steps 1, 2, 4, ...) and then bisects.
+  // record r of the partition: the last segment starting at or before it.
+  // A thread's records only move forward, so the search gallops on from its
+  // previous segment (steps 1, 2, 4, ...) and then bisects. The record's two
+  // 16-byte halves are loaded (the second is zero for a 16-byte record; the
+  // caller decodes by `wide`).
   uint32_t seg = 0;
-  auto rec_at = [&](uint32_t r) -> const FlushRec* {
-    uint32_t lo = seg, hi = seg + 1, step = 1;  // s_pre[lo] <= r < total = s_pre[G]
-    while (hi < G && s_pre[hi] <= r) {
+  auto load_rec = [&](uint32_t r, uint4& a, uint4& b, bool& wide) {
+    uint32_t lo = seg, hi = seg + 1, step = 1;  // s_pre[lo] <= r < total = s_pre[NS]
+    while (hi < NS && s_pre[hi] <= r) {
       lo = hi;
       step <<= 1;
       hi = lo + step;
     }
-    if (hi > G) hi = G;
+    if (hi > NS) hi = NS;
     while (hi - lo > 1) {
       const uint32_t mid = (lo + hi) >> 1;
       if (s_pre[mid] <= r) lo = mid; else hi = mid;
     }
     seg = lo;
-    return reinterpret_cast<const FlushRec*>(Q.mq) + ((uint64_t)p * Q.mq_grid + seg) * Q.mq_cap + (r - s_pre[seg]);
+    const uint32_t e = r - s_pre[seg];
+    wide = seg < G;
+    if (wide) {
+      const FlushRec* rp = reinterpret_cast<const FlushRec*>(Q.mq) + ((uint64_t)p * G + seg) * Q.mq_cap + e;
+      a = gload16(&rp->k);
+      b = gload16(&rp->off);
+    } else {
+      a = gload16(reinterpret_cast<const uint4*>(Q.sq) + ((uint64_t)p * G + (seg - G)) * Q.sq_cap + e);
+      b = make_uint4(0, 0, 0, 0);
+    }
   };
   // a summed key into its job's table: with the table split into partition
   // regions, this workgroup is the region's only writer
@@ -916,21 +938,16 @@ __global__ __launch_bounds__(kMapThreads) void k_words_parts(const WordJob* __re
       T.tag[i] = 0u;
     }
   };
-  uint4 nk = make_uint4(0, 0, 0, 0), nm = make_uint4(0, 0, 0, 0);
-  if (threadIdx.x < total) {
-    const FlushRec* rp = rec_at(threadIdx.x);
-    nk = gload16(&rp->k);
-    nm = gload16(&rp->off);
-  }
+  uint4 na = make_uint4(0, 0, 0, 0), nb = make_uint4(0, 0, 0, 0);
+  bool nwide = true;
+  if (threadIdx.x < total) load_rec(threadIdx.x, na, nb, nwide);
   for (uint32_t base = 0; base < total; base += blockDim.x) {
     const bool have = base + threadIdx.x < total;
-    const uint4 k = nk, m = nm;
+    // this round's record as (key, {offset, length, count, job})
+    const uint4 k = nwide ? na : make_uint4(na.x, na.y, 0u, 0u);
+    const uint4 m = nwide ? nb : make_uint4(na.z, na.w & 15u, (na.w >> 4) & 0xFFFu, na.w >> 16);
     const uint32_t nx = base + blockDim.x + threadIdx.x;
-    if (nx < total) {
-      const FlushRec* rp = rec_at(nx);
-      nk = gload16(&rp->k);
-      nm = gload16(&rp->off);
-    }
+    if (nx < total) load_rec(nx, na, nb, nwide);
     const bool claimed = have && consume(k, m);
     // the round's claims, one LDS add per wave
     const uint32_t nc = popc64(__ballot(claimed));
