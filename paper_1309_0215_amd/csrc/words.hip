@@ -1102,224 +1102,189 @@ MR_DEV void bitonic_sort(const WordJob& J, WRec* a, uint32_t m) {
   }
 }
 
-// Keys of up to CAP records in LDS as separate arrays (prefix words, length,
-// record index): a compare-exchange reads consecutive words across threads
-// instead of 32-byte records, which keeps LDS accesses free of bank conflicts.
+// Keys of up to CAP records in LDS: 16-byte prefixes, lengths and record
+// indices in separate arrays (a search step reads one prefix and one length).
 template <uint32_t CAP>
-struct SoaKeys {
-  uint32_t k[4][CAP];
+struct LdsKeys {
+  uint4 k[CAP];
   uint32_t len[CAP];
-  uint32_t ix[CAP];  // record index in recs
+  uint32_t ix[CAP];  // record index
 };
 
-template <uint32_t CAP>
-MR_DEV void soa_load(SoaKeys<CAP>& S, uint32_t i, const WRec& r, uint32_t ix) {
-  S.k[0][i] = r.p[0];
-  S.k[1][i] = r.p[1];
-  S.k[2][i] = r.p[2];
-  S.k[3][i] = r.p[3];
-  S.len[i] = r.len;
-  S.ix[i] = ix;
+// a < b for keys given by their 16-byte prefixes (x the most significant
+// word) and lengths, read as 160-bit numbers: the borrow out of a - b, one
+// subtract-with-borrow per word, all in the vector unit. Keys longer than
+// 16 bytes with one prefix are ordered by the caller.
+MR_DEV bool lex_less(uint4 a, uint32_t al, uint4 b, uint32_t bl) {
+  uint32_t d, r;
+  uint64_t c;
+  asm("v_sub_co_u32_e64 %0, %2, %3, %4\n\t"
+      "v_subb_co_u32_e64 %0, %2, %5, %6, %2\n\t"
+      "v_subb_co_u32_e64 %0, %2, %7, %8, %2\n\t"
+      "v_subb_co_u32_e64 %0, %2, %9, %10, %2\n\t"
+      "v_subb_co_u32_e64 %0, %2, %11, %12, %2\n\t"
+      "v_cndmask_b32_e64 %1, 0, 1, %2"
+      : "=&v"(d), "=v"(r), "=&s"(c)
+      : "v"(al), "v"(bl), "v"(a.w), "v"(b.w), "v"(a.z), "v"(b.z), "v"(a.y), "v"(b.y), "v"(a.x), "v"(b.x));
+  return r != 0;
 }
 
-// Three-way compare of entries i and l (same order as wrec_cmp).
-template <uint32_t CAP>
-MR_DEV int soa_cmp(const WordJob& J, const WRec* recs, const SoaKeys<CAP>& S, uint32_t i, uint32_t l) {
+// Sort of entries [0, m) of K (m <= E * blockDim.x, m <= CAP) by merging.
+// At the level of runs of L entries, the entry at place i counts the entries
+// of its partner run below it by a binary search of that run; with its own
+// index in its run that gives its place in the merged run of 2L (the keys
+// are distinct). Each thread keeps E entries in registers and follows them
+// from place to place: every search reads K, a barrier, then every entry is
+// written to its new place. There are ceil(log2 m) levels and no padding.
+template <uint32_t E, uint32_t CAP>
+MR_DEV void merge_sort(const uint8_t* in, const WRec* recs, LdsKeys<CAP>& K, uint32_t m) {
+  const uint32_t T = blockDim.x, t = threadIdx.x;
+  uint4 xk[E];
+  uint32_t xl[E], xi[E], at[E];  // an entry's key, record and present place
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const uint32_t a = S.k[q][i], b = S.k[q][l];
-    if (a != b) return a < b ? -1 : 1;
-  }
-  const uint32_t la = S.len[i], lb = S.len[l];
-  if (la > 16u && lb > 16u) {
-    const int c = input_cmp(J.in, recs[S.ix[i]].off, recs[S.ix[l]].off, 16, la < lb ? la : lb);
-    if (c) return c;
-  }
-  return la < lb ? -1 : (la > lb ? 1 : 0);
-}
-
-template <uint32_t CAP>
-MR_DEV void soa_swap(SoaKeys<CAP>& S, uint32_t i, uint32_t l) {
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const uint32_t t = S.k[q][i];
-    S.k[q][i] = S.k[q][l];
-    S.k[q][l] = t;
-  }
-  uint32_t t = S.len[i];
-  S.len[i] = S.len[l];
-  S.len[l] = t;
-  t = S.ix[i];
-  S.ix[i] = S.ix[l];
-  S.ix[l] = t;
-}
-
-// Bitonic sort (all-ascending "flip" form) of entries [0, m), m <= CAP, by the
-// whole workgroup; indices >= m act as +infinity and are never touched.
-template <uint32_t CAP>
-MR_DEV void soa_bitonic(const WordJob& J, const WRec* recs, SoaKeys<CAP>& S, uint32_t m) {
-  uint32_t n = 1;
-  while (n < m) n <<= 1;
-  for (uint32_t k = 2; k <= n; k <<= 1) {
-    for (uint32_t jj = k >> 1; jj > 0; jj >>= 1) {
-      for (uint32_t t = threadIdx.x; t < n / 2; t += blockDim.x) {
-        const uint32_t i = ((t & ~(jj - 1)) << 1) | (t & (jj - 1));
-        const uint32_t l = (jj == (k >> 1)) ? (i ^ (k - 1)) : (i | jj);
-        if (l < m && soa_cmp(J, recs, S, i, l) > 0) soa_swap(S, i, l);
-      }
-      __syncthreads();
+  for (uint32_t e = 0; e < E; ++e) {
+    at[e] = e * T + t;
+    if (at[e] < m) {
+      xk[e] = K.k[at[e]];
+      xl[e] = K.len[at[e]];
+      xi[e] = K.ix[at[e]];
     }
   }
-}
-
-// The same sort with one entry per thread in registers, for m <= blockDim.x:
-// compare-exchange stages between lanes of one wave (partner distance < 64)
-// swap through shuffles with no barrier; only the stages with a farther
-// partner go through the LDS arrays (10 of the 55 stages of a 1024-entry
-// sort). The network and the order are those of soa_bitonic; entries past m
-// are +infinity. S holds the input and receives the sorted entries.
-constexpr uint32_t kRegPad = 0xFFFFFFFFu;  // index field of a padding entry
-
-MR_DEV int reg_cmp(const WordJob& J, const WRec* recs, const uint32_t (&a)[6], const uint32_t (&b)[6]) {
-  // a[0..3]: prefix words, a[4]: length, a[5]: record index (kRegPad: padding)
-  if (a[5] == kRegPad || b[5] == kRegPad) return (a[5] == kRegPad ? 1 : 0) - (b[5] == kRegPad ? 1 : 0);
+  for (uint32_t L = 1; L < m; L <<= 1) {
+    uint32_t dst[E];
 #pragma unroll
-  for (int q = 0; q < 4; ++q)
-    if (a[q] != b[q]) return a[q] < b[q] ? -1 : 1;
-  if (a[4] > 16u && b[4] > 16u) {
-    const int c = input_cmp(J.in, recs[a[5]].off, recs[b[5]].off, 16, a[4] < b[4] ? a[4] : b[4]);
-    if (c) return c;
-  }
-  return a[4] < b[4] ? -1 : (a[4] > b[4] ? 1 : 0);
-}
-
-template <uint32_t CAP>
-MR_DEV void reg_bitonic(const WordJob& J, const WRec* recs, SoaKeys<CAP>& S, uint32_t m) {
-  uint32_t n = 1;
-  while (n < m) n <<= 1;
-  const uint32_t t = threadIdx.x;
-  const bool act = t < n;
-  uint32_t a[6];
-  if (t < m) {
-    a[0] = S.k[0][t];
-    a[1] = S.k[1][t];
-    a[2] = S.k[2][t];
-    a[3] = S.k[3][t];
-    a[4] = S.len[t];
-    a[5] = S.ix[t];
-  } else {
-#pragma unroll
-    for (int q = 0; q < 6; ++q) a[q] = kRegPad;
-  }
-  __syncthreads();  // every entry is read before S is used for exchanges
-  for (uint32_t k = 2; k <= n; k <<= 1) {
-    for (uint32_t jj = k >> 1; jj > 0; jj >>= 1) {
-      const uint32_t x = jj == (k >> 1) ? (k - 1) : jj;  // partner: t ^ x
-      uint32_t b[6];
-      if (x < (uint32_t)kWave) {
-#pragma unroll
-        for (int q = 0; q < 6; ++q) b[q] = (uint32_t)__shfl_xor((int)a[q], (int)x);
-      } else {
-        if (act) {
-          S.k[0][t] = a[0];
-          S.k[1][t] = a[1];
-          S.k[2][t] = a[2];
-          S.k[3][t] = a[3];
-          S.len[t] = a[4];
-          S.ix[t] = a[5];
+    for (uint32_t e = 0; e < E; ++e) {
+      const uint32_t i = at[e];
+      dst[e] = i;
+      if (i < m) {
+        const uint32_t b0 = (i ^ L) & ~(L - 1);  // the partner run
+        const uint32_t blen = b0 >= m ? 0u : (m - b0 < L ? m - b0 : L);
+        uint32_t pos = 0;  // entries of the partner run below entry i
+        for (uint32_t step = L; step; step >>= 1) {
+          const uint32_t q = pos + step;
+          if (q <= blen) {
+            const uint32_t j = b0 + q - 1;
+            const uint4 bk = K.k[j];
+            const uint32_t bl = K.len[j];
+            bool below = lex_less(bk, bl, xk[e], xl[e]);
+            const uint32_t ml = bl < xl[e] ? bl : xl[e];
+            if (ml > 16u) {
+              // two keys longer than 16 bytes: when they share the prefix
+              // their bytes in the input decide (the empty asm keeps these
+              // compares inside the branch)
+              uint4 pk = bk;
+              asm volatile("" : "+v"(pk.x), "+v"(pk.y), "+v"(pk.z), "+v"(pk.w));
+              if (pk.x == xk[e].x && pk.y == xk[e].y && pk.z == xk[e].z && pk.w == xk[e].w) {
+                const int c = input_cmp(in, recs[K.ix[j]].off, recs[xi[e]].off, 16, ml);
+                below = c < 0 || (c == 0 && bl < xl[e]);
+              }
+            }
+            if (below) pos = q;
+          }
         }
-        __syncthreads();
-        if (act) {
-          const uint32_t p = t ^ x;
-          b[0] = S.k[0][p];
-          b[1] = S.k[1][p];
-          b[2] = S.k[2][p];
-          b[3] = S.k[3][p];
-          b[4] = S.len[p];
-          b[5] = S.ix[p];
-        }
-        __syncthreads();
-      }
-      if (act) {
-        // the lower index of the pair keeps the smaller entry
-        const int c = reg_cmp(J, recs, a, b);
-        if ((t & jj) == 0 ? c > 0 : c < 0) {
-#pragma unroll
-          for (int q = 0; q < 6; ++q) a[q] = b[q];
-        }
+        dst[e] = (i & ~(2 * L - 1)) + (i & (L - 1)) + pos;
       }
     }
+    __syncthreads();  // every search has read the previous order
+#pragma unroll
+    for (uint32_t e = 0; e < E; ++e) {
+      if (at[e] < m) {
+        K.k[dst[e]] = xk[e];
+        K.len[dst[e]] = xl[e];
+        K.ix[dst[e]] = xi[e];
+        at[e] = dst[e];
+      }
+    }
+    __syncthreads();
   }
-  if (t < m) {
-    S.k[0][t] = a[0];
-    S.k[1][t] = a[1];
-    S.k[2][t] = a[2];
-    S.k[3][t] = a[3];
-    S.len[t] = a[4];
-    S.ix[t] = a[5];
-  }
-  __syncthreads();
 }
 
 constexpr uint32_t kSortThreads = 1024;
+constexpr uint32_t kBucketKeys = 512;       // keys per sort bucket, on average
+constexpr uint32_t kBucketThreads = 1024;   // threads of a bucket's workgroup
 constexpr uint32_t kOversample = 4;
+constexpr uint32_t kMaxSamples = kMaxBuckets * kOversample;
+constexpr uint32_t kRankRows = kSortThreads / kWave;  // samples ranked per work item of k_sort_ranks (one per wave)
+constexpr uint32_t kRankJobs = 4;                     // batches of up to this many jobs take k_sort_ranks
 
-// Plan the sort of every job: bucket counts and global bucket / record-tile
-// bases. One workgroup; the jobs are taken blockDim at a time, one per
-// thread, and the bases come from a workgroup scan of the counts.
+// Samples per bucket of a job with nb > 1 buckets: 4 * kOversample while the
+// sample fits half of kMaxSamples, 2 * kOversample while it fits all of it,
+// else kOversample. The largest bucket sets the bucket sort's time, and more
+// samples keep it closer to the mean (a bucket larger than the workgroup
+// sorts twice the entries).
+MR_DEV uint32_t sample_ov(uint32_t nb) {
+  return nb * 4 * kOversample <= kMaxSamples / 2 ? 4 * kOversample
+                                                 : (nb * 2 * kOversample <= kMaxSamples ? 2 * kOversample : kOversample);
+}
+
+// Plan the sort of every job: bucket counts and global bucket, record-tile
+// and rank work-item bases. One workgroup; the jobs are taken blockDim at a
+// time, one per thread, and the bases come from a workgroup scan of the
+// counts.
 __global__ __launch_bounds__(kSortThreads) void k_sort_plan(const WordJob* __restrict__ jobs, uint32_t n_jobs,
                                                              uint32_t* totals /*[2]*/) {
-  __shared__ uint32_t w_nb[kSortThreads / kWave], w_rt[kSortThreads / kWave];
+  __shared__ uint32_t w_nb[kSortThreads / kWave], w_rt[kSortThreads / kWave], w_si[kSortThreads / kWave];
   const uint32_t lane = lane_id(), wv = threadIdx.x / kWave, nw = blockDim.x / kWave;
-  uint32_t carry_b = 0, carry_r = 0;
+  uint32_t carry_b = 0, carry_r = 0, carry_s = 0;
   for (uint32_t base = 0; base < n_jobs; base += blockDim.x) {
     const uint32_t j = base + threadIdx.x;
-    uint32_t nb = 0, rt = 0;
+    uint32_t nb = 0, rt = 0, si = 0;
     if (j < n_jobs) {
       const uint64_t n = jobs[j].st->n_recs;
       nb = 1;
       if (n > kBucketCap) {
-        const uint64_t want = (n + 511) / 512;
+        const uint64_t want = (n + kBucketKeys - 1) / kBucketKeys;
         nb = (uint32_t)(want < kMaxBuckets ? want : kMaxBuckets);
+        si = (nb * sample_ov(nb) + kRankRows - 1) / kRankRows;
       }
       rt = (uint32_t)((n + kRecTile - 1) / kRecTile);
     }
-    const uint32_t inb = wave_incl_scan(nb), irt = wave_incl_scan(rt);
+    const uint32_t inb = wave_incl_scan(nb), irt = wave_incl_scan(rt), isi = wave_incl_scan(si);
     if (lane == kWave - 1) {
       w_nb[wv] = inb;
       w_rt[wv] = irt;
+      w_si[wv] = isi;
     }
     __syncthreads();
-    uint32_t pb = carry_b, pr = carry_r, tb = 0, tr = 0;
+    uint32_t pb = carry_b, pr = carry_r, ps = carry_s, tb = 0, tr = 0, ts = 0;
     for (uint32_t q = 0; q < nw; ++q) {
       if (q < wv) {
         pb += w_nb[q];
         pr += w_rt[q];
+        ps += w_si[q];
       }
       tb += w_nb[q];
       tr += w_rt[q];
+      ts += w_si[q];
     }
     if (j < n_jobs) {
       JobState* st = jobs[j].st;
       st->nb = nb;
       st->bucket_base = pb + inb - nb;
       st->rtile_base = pr + irt - rt;
+      st->rank_base = ps + isi - si;
     }
     carry_b += tb;
     carry_r += tr;
+    carry_s += ts;
     __syncthreads();
   }
   if (threadIdx.x == 0) {
     totals[0] = carry_b;
     totals[1] = carry_r;
+    totals[2] = carry_s;
   }
 }
 
-// Splitters of one job: sort an evenly spaced sample, keep every kOversample-th.
+// Splitters of one job: its sample is S = nb * ov evenly spaced records,
+// sorted in LDS by the merge sort, and the splitter of bucket b is the
+// sample entry of rank (b + 1) * ov - 1. One workgroup per job (the jobs of
+// a batch run side by side); it also clears the job's bucket counters.
 __global__ __launch_bounds__(kSortThreads) void k_sort_splitters(const WordJob* __restrict__ jobs, uint32_t n_jobs,
                                                                   uint32_t* bucket_cnt, unsigned long long* bucket_bytes,
                                                                   uint32_t* bucket_fill) {
-  __shared__ SoaKeys<kMaxBuckets * kOversample> smp;
+  static_assert(kMaxSamples <= 4 * kSortThreads, "a sample takes at most four entries per thread");
+  __shared__ LdsKeys<kMaxSamples> smp;
   const uint32_t j = blockIdx.x;
   if (j >= n_jobs) return;
   const WordJob& J = jobs[j];
@@ -1332,20 +1297,102 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_splitters(const WordJob* 
   }
   if (nb <= 1) return;
   const uint64_t n = J.st->n_recs;
-  // twice the oversampling while the sample fits the array: the largest
-  // bucket, which sets the bucket sort's time, stays closer to the mean
-  const uint32_t ov = nb * 2 * kOversample <= kMaxBuckets * kOversample ? 2 * kOversample : kOversample;
-  const uint32_t S = nb * ov;
+  const uint32_t ov = sample_ov(nb), S = nb * ov;
   const WRec* recs = reinterpret_cast<const WRec*>(J.recs);
   for (uint32_t i = threadIdx.x; i < S; i += blockDim.x) {
     const uint32_t ix = (uint32_t)((uint64_t)i * n / S);
-    soa_load(smp, i, load_wrec(&recs[ix]), ix);
+    const WRec r = load_wrec(&recs[ix]);
+    smp.k[i] = make_uint4(r.p[0], r.p[1], r.p[2], r.p[3]);
+    smp.len[i] = r.len;
+    smp.ix[i] = ix;
   }
   __syncthreads();
-  if (S <= blockDim.x) reg_bitonic(J, recs, smp, S);
-  else soa_bitonic(J, recs, smp, S);
+  if (S <= blockDim.x) merge_sort<1>(J.in, recs, smp, S);
+  else if (S <= 2 * blockDim.x) merge_sort<2>(J.in, recs, smp, S);
+  else merge_sort<4>(J.in, recs, smp, S);
   WRec* spl = reinterpret_cast<WRec*>(J.splitters);
   for (uint32_t b = threadIdx.x; b + 1 < nb; b += blockDim.x) store_wrec(&spl[b], load_wrec(&recs[smp.ix[(b + 1) * ov - 1]]));
+}
+
+// Order of two keys by their 16-byte prefixes and lengths (plain compares,
+// no branches); `tie` marks two keys longer than 16 bytes with one prefix,
+// whose order needs their bytes in the input.
+MR_DEV void key_order(uint4 a, uint32_t al, uint4 b, uint32_t bl, bool& lt, bool& tie) {
+  const bool e0 = a.x == b.x, e1 = a.y == b.y, e2 = a.z == b.z, e3 = a.w == b.w;
+  lt = (a.x < b.x) | (e0 & ((a.y < b.y) | (e1 & ((a.z < b.z) | (e2 & ((a.w < b.w) | (e3 & (al < bl))))))));
+  tie = e0 & e1 & e2 & e3 & (al > 16u) & (bl > 16u);
+}
+
+// Work item g of k_sort_ranks: the job whose items hold it.
+MR_DEV uint32_t find_rank_job(const WordJob* jobs, uint32_t n_jobs, uint32_t g) {
+  uint32_t lo = 0, hi = n_jobs;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (jobs[mid].st->rank_base <= g) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+// The same splitters without a sort, for a batch of a few jobs: a single
+// sort of the sample would leave all but one CU idle. The keys are
+// distinct, so a sample's rank is the number of samples below it, found by
+// comparing it with every sample: work item g ranks kRankRows samples of one
+// job, one per wave, each lane taking every 64th sample and a ballot adding
+// up the lanes; the items of all jobs are spread over the grid. The grid
+// also clears every bucket's counters.
+__global__ __launch_bounds__(kSortThreads) void k_sort_ranks(const WordJob* __restrict__ jobs, uint32_t n_jobs,
+                                                              const uint32_t* totals, uint32_t* bucket_cnt,
+                                                              unsigned long long* bucket_bytes, uint32_t* bucket_fill) {
+  __shared__ uint4 ck[kMaxSamples];
+  __shared__ uint32_t cl[kMaxSamples];
+  const uint32_t n_buckets = totals[0];
+  for (uint32_t b = blockIdx.x * blockDim.x + threadIdx.x; b < n_buckets; b += gridDim.x * blockDim.x) {
+    bucket_cnt[b] = 0;
+    bucket_bytes[b] = 0;
+    bucket_fill[b] = 0;
+  }
+  const uint32_t items = totals[2];
+  const uint32_t lane = lane_id(), wv = threadIdx.x / kWave;
+  for (uint32_t g = blockIdx.x; g < items; g += gridDim.x) {
+    const uint32_t j = find_rank_job(jobs, n_jobs, g);
+    const WordJob& J = jobs[j];
+    const uint32_t nb = J.st->nb;
+    const uint64_t n = J.st->n_recs;
+    const uint32_t ov = sample_ov(nb), S = nb * ov;
+    const WRec* recs = reinterpret_cast<const WRec*>(J.recs);
+    __syncthreads();  // the previous item's reads of the sample are done
+    for (uint32_t i = threadIdx.x; i < S; i += blockDim.x) {
+      const WRec r = load_wrec(&recs[(uint64_t)i * n / S]);
+      ck[i] = make_uint4(r.p[0], r.p[1], r.p[2], r.p[3]);
+      cl[i] = r.len;
+    }
+    __syncthreads();
+    const uint32_t row = (g - J.st->rank_base) * kRankRows + wv;
+    if (row < S) {
+      const uint4 rk = ck[row];
+      const uint32_t rl = cl[row];
+      const uint64_t rix = (uint64_t)row * n / S;
+      uint32_t rank = 0;
+      for (uint32_t c0 = 0; c0 < S; c0 += kWave) {
+        const uint32_t c = c0 + lane;
+        bool below = false;
+        if (c < S) {
+          const uint32_t l = cl[c];
+          bool tie;
+          key_order(ck[c], l, rk, rl, below, tie);
+          if (tie) {  // rare: two long keys with one prefix
+            const int cc = input_cmp(J.in, recs[(uint64_t)c * n / S].off, recs[rix].off, 16, l < rl ? l : rl);
+            below = cc < 0 || (cc == 0 && l < rl);
+          }
+        }
+        rank += (uint32_t)__popcll(__ballot(below));
+      }
+      if (lane == 0 && (rank + 1) % ov == 0) {
+        const uint32_t b = (rank + 1) / ov - 1;
+        if (b + 1 < nb) store_wrec(&reinterpret_cast<WRec*>(J.splitters)[b], load_wrec(&recs[rix]));
+      }
+    }
+  }
 }
 
 // Bucket of each record: number of splitters strictly below it.
@@ -1512,15 +1559,16 @@ MR_DEV uint32_t find_bucket_job(const WordJob* jobs, uint32_t n_jobs, uint32_t g
 
 // Output key bytes of a bucket staged in LDS before they are written out in
 // aligned 16-byte pieces (a bucket sorted in LDS whose keys are all inline).
-constexpr uint32_t kStageBytes = kBucketCap * 16 + 16;
+constexpr uint32_t kStageBytes = 32512;  // with the sort arrays, under half the CU's LDS: two workgroups per CU
 
 // Sort each bucket and write the job's outputs for it.
-__global__ __launch_bounds__(kSortThreads) void k_sort_buckets(const WordJob* __restrict__ jobs, uint32_t n_jobs, const uint32_t* totals,
+__global__ __launch_bounds__(kBucketThreads) void k_sort_buckets(const WordJob* __restrict__ jobs, uint32_t n_jobs, const uint32_t* totals,
                                                                 const uint32_t* bucket_cnt, const unsigned long long* bucket_bytes,
                                                                 const uint32_t* bucket_start,
                                                                 const unsigned long long* bucket_bstart) {
-  __shared__ SoaKeys<kBucketCap> a;
-  __shared__ uint64_t wsum[kSortThreads / kWave];
+  static_assert(kBucketCap <= 4 * kBucketThreads, "a bucket sorted in LDS takes at most four entries per thread");
+  __shared__ LdsKeys<kBucketCap> a;
+  __shared__ uint64_t wsum[kBucketThreads / kWave];
   __shared__ __attribute__((aligned(16))) uint8_t ob[kStageBytes];
   __shared__ uint32_t s_long;
   const uint32_t n_buckets = totals[0];
@@ -1540,12 +1588,20 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_buckets(const WordJob* __
     if (in_lds) {
       for (uint32_t i = threadIdx.x; i < m; i += blockDim.x) {
         const WRec r = load_wrec(&src[i]);
-        soa_load(a, i, r, i);
+        a.k[i] = make_uint4(r.p[0], r.p[1], r.p[2], r.p[3]);
+        a.len[i] = r.len;
+        a.ix[i] = i;
         if (r.len > 16u) s_long = 1u;
       }
       __syncthreads();
-      if (m <= blockDim.x) reg_bitonic(J, src, a, m);
-      else soa_bitonic(J, src, a, m);
+      if (m <= blockDim.x) {
+        merge_sort<1>(J.in, src, a, m);
+      } else if constexpr (kBucketCap <= 2 * kBucketThreads) {
+        merge_sort<2>(J.in, src, a, m);
+      } else {
+        if (m <= 2 * blockDim.x) merge_sort<2>(J.in, src, a, m);
+        else merge_sort<4>(J.in, src, a, m);
+      }
     } else {
       if (threadIdx.x == 0) atomicAdd(&J.st->sort_spills, 1u);  // rare: sort the bucket in global memory
       bitonic_sort(J, src, m);
@@ -1854,14 +1910,18 @@ hipError_t words_enqueue_reduce(const WordsLaunch& L, hipStream_t s) {
   hipLaunchKernelGGL(k_words_compact, dim3(cgrid ? cgrid : 1), dim3(kCompactThreads), 0, s, L.jobs, L.n_jobs, L.total_slots,
                      item);
   hipLaunchKernelGGL(k_sort_plan, dim3(1), dim3(kSortThreads), 0, s, L.jobs, L.n_jobs, L.totals);
-  hipLaunchKernelGGL(k_sort_splitters, dim3(L.n_jobs), dim3(kSortThreads), 0, s, L.jobs, L.n_jobs, L.bucket_cnt,
-                     L.bucket_bytes, L.bucket_fill);
+  if (L.n_jobs <= kRankJobs)
+    hipLaunchKernelGGL(k_sort_ranks, dim3(L.sort_grid), dim3(kSortThreads), 0, s, L.jobs, L.n_jobs, L.totals,
+                       L.bucket_cnt, L.bucket_bytes, L.bucket_fill);
+  else
+    hipLaunchKernelGGL(k_sort_splitters, dim3(L.n_jobs), dim3(kSortThreads), 0, s, L.jobs, L.n_jobs, L.bucket_cnt,
+                       L.bucket_bytes, L.bucket_fill);
   hipLaunchKernelGGL(k_sort_count, dim3(L.sort_grid), dim3(256), 0, s, L.jobs, L.n_jobs, L.totals, L.bucket_cnt, L.bucket_bytes);
   hipLaunchKernelGGL(k_sort_scan, dim3(L.n_jobs), dim3(64), 0, s, L.jobs, L.n_jobs, L.bucket_cnt, L.bucket_bytes,
                      L.bucket_start, L.bucket_bstart);
   hipLaunchKernelGGL(k_sort_scatter, dim3(L.sort_grid), dim3(256), 0, s, L.jobs, L.n_jobs, L.totals, L.bucket_start,
                      L.bucket_fill);
-  hipLaunchKernelGGL(k_sort_buckets, dim3(L.sort_grid), dim3(kSortThreads), 0, s, L.jobs, L.n_jobs, L.totals, L.bucket_cnt,
+  hipLaunchKernelGGL(k_sort_buckets, dim3(L.sort_grid), dim3(kBucketThreads), 0, s, L.jobs, L.n_jobs, L.totals, L.bucket_cnt,
                      L.bucket_bytes, L.bucket_start, L.bucket_bstart);
   hipLaunchKernelGGL(k_words_finish, dim3(1), dim3(256), 0, s, L.jobs, L.n_jobs);
   return hipGetLastError();

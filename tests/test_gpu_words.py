@@ -293,6 +293,42 @@ def test_wave_combiner_records_and_hand_cases(torch):
     _check(job.words(_dev(torch, buf), _dev(torch, offs)), buf, offs.astype(np.uint64))
 
 
+def _shared_prefix_text(seed: int, n_long: int, n_short: int, n_tokens: int) -> np.ndarray:
+    # n_long distinct words of 17-40 bytes that all begin with the same 16
+    # bytes (their order is decided past the prefix, by the bytes in the
+    # input) and n_short distinct words of 1-12 bytes, in random order
+    rng = np.random.default_rng(seed)
+    pre = b"q" * 16
+    longs = {pre + bytes(rng.integers(97, 123, size=int(rng.integers(1, 25)), dtype=np.uint8)) for _ in range(n_long)}
+    shorts = {bytes(rng.integers(97, 123, size=int(rng.integers(1, 13)), dtype=np.uint8)) for _ in range(n_short)}
+    vocab = sorted(longs) + sorted(shorts)
+    pick = rng.integers(0, len(vocab), size=n_tokens)
+    return np.frombuffer(b" ".join(vocab[i] for i in pick) + b"\n", np.uint8).copy()
+
+
+@pytest.mark.parametrize("n_long,n_short", [(3_000, 30_000), (30_000, 70_000), (200_000, 400_000)])
+def test_long_keys_with_one_prefix(torch, n_long, n_short):
+    """Long keys that share their first 16 bytes are ordered by their input
+    bytes inside the register sorts of the splitter sample and of the buckets.
+    The sizes give sample sorts of one, two and four entries per thread and
+    buckets of more than 1024 records."""
+    from paper_1309_0215_amd import Job
+    buf = _shared_prefix_text(95, n_long, n_short, 3 * (n_long + n_short))
+    _check(Job(device=0).words(_dev(torch, buf)), buf)
+
+
+def test_long_keys_with_one_prefix_in_a_batch(torch):
+    """The same inputs as a batch of six jobs: batches of more than a few jobs
+    take their splitters from a merge sort of each job's sample (one
+    workgroup per job) instead of ranks, with the same order of long keys."""
+    from paper_1309_0215_amd import Job
+    sizes = [(3_000, 30_000), (30_000, 70_000), (200_000, 400_000), (100, 2_000), (20_000, 0), (1, 1)]
+    bufs = [_shared_prefix_text(96 + i, nl, ns, 3 * (nl + ns)) for i, (nl, ns) in enumerate(sizes)]
+    res = Job(device=0).words_batch([_dev(torch, b) for b in bufs])
+    for r, b in zip(res, bufs):
+        _check(r, b)
+
+
 def test_sort_spill_path(torch):
     """About 2.7 M distinct words: more than the 1024 sort buckets of 2048
     records hold in LDS, so buckets are sorted in global memory (counted in
