@@ -277,14 +277,20 @@ __global__ __launch_bounds__(kPartThreads) void k_part_count(IntIn in, uint64_t 
 }
 
 // Each tile is ordered by range in LDS first; then each wave writes whole
-// runs (one range's elements of the tile) as contiguous 2-byte entries.
+// runs (one range's elements of the tile) as contiguous 2-byte entries. The
+// range arrays take dynamic LDS sized by P (part_scatter_lds), so that for
+// P <= 1024 two workgroups fit a CU: one streams its tile while the other
+// scans its counts or writes its runs.
+constexpr uint32_t part_scatter_lds(uint32_t P) { return (2 * P + 1) * 4; }
+
 __global__ __launch_bounds__(kPartThreads) void k_part_scatter(IntIn in, uint64_t R, uint32_t P, uint32_t n_tiles,
                                                                const uint32_t* __restrict__ offs /* scanned hist */,
                                                                const unsigned long long* __restrict__ total,
                                                                uint16_t* __restrict__ part) {
-  __shared__ uint32_t lbase[kMaxParts + 1];  // start of each range's run in the staged tile (and the end)
-  __shared__ uint32_t lpos[kMaxParts];       // next free place of each range's run
-  __shared__ uint16_t sk[kPartTile];         // staged low bits, ordered by range
+  extern __shared__ uint32_t ranges[];
+  uint32_t* const lbase = ranges;         // [P + 1] start of each range's run in the staged tile (and the end)
+  uint32_t* const lpos = ranges + P + 1;  // [P] next free place of each range's run
+  __shared__ uint16_t sk[kPartTile];      // staged low bits, ordered by range
   __shared__ uint32_t wsum[kPartThreads / kWave];
   const uint32_t t = blockIdx.x;
   // this tile's count of range p, from the scanned counts (range-major, tile-minor)
@@ -977,7 +983,8 @@ hipError_t int_enqueue_global_array_parts(const IntLaunch& L, const PartPlan& pp
   hipLaunchKernelGGL(k_scan_blocks, dim3(pp.sb), dim3(256), 0, s, hist, pp.H, scan_sums);
   hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, s, scan_sums, pp.sb, total);
   hipLaunchKernelGGL(k_scan_apply, dim3(pp.sb), dim3(256), 0, s, hist, pp.H, scan_sums);
-  hipLaunchKernelGGL(k_part_scatter, dim3(pp.n_tiles), dim3(kPartThreads), 0, s, in, L.R, pp.P, pp.n_tiles, hist, total, part);
+  hipLaunchKernelGGL(k_part_scatter, dim3(pp.n_tiles), dim3(kPartThreads), part_scatter_lds(pp.P), s, in, L.R, pp.P, pp.n_tiles,
+                     hist, total, part);
   hipLaunchKernelGGL(k_part_fill, dim3(pp.P), dim3(1024), 0, s, part, hist, total, pp.P, pp.n_tiles, L.R, L.dcnt);
   return hipGetLastError();
 }
