@@ -1320,7 +1320,7 @@ mr_status run_u32(mr_job* job, mr_map_kind kind, mr_reduce_op op, const void* d_
       MR_HIP(int_enqueue_global_array(L, job->stream));
     }
     if (job->cfg.timing) MR_HIP(hipEventRecord(job->ev3, job->stream));
-    MR_HIP(int_enqueue_dense_out(L, true, job->stream));
+    MR_HIP(int_enqueue_dense_out(L, true, parts, job->stream));
   } else if (strat == MR_STRAT_HASH) {
     // capacity: distinct <= min(n, range); start from the last job's distinct count when larger inputs repeat
     table_cap = int_table_slots(job, kind, bytes, n, key_range);

@@ -204,6 +204,8 @@ constexpr uint32_t kPartKeys = 1u << kPartBits;  // keys per range: LDS counters
 constexpr uint32_t kMaxParts = 2048;             // ranges (key range up to 2^26)
 constexpr uint32_t kPartTile = 32768;            // elements per tile of the count and scatter passes
 constexpr uint32_t kPartThreads = 1024;
+constexpr uint32_t kCompTile = 2048;  // keys per block of the ordered compaction of dense arrays (256 threads x 8)
+static_assert(kPartKeys % kCompTile == 0, "a key range holds whole compaction blocks");
 
 // Element i of a tile: keys are read 4 at a time (one 16-byte load) when the
 // input is plain keys; pairs are read one by one.
@@ -354,9 +356,14 @@ __global__ __launch_bounds__(kPartThreads) void k_part_scatter(IntIn in, uint64_
   }
 }
 
+// One workgroup per key range counts the range's segment in LDS and writes
+// the range's counts once. It also counts the keys present in each of the
+// range's compaction blocks (blk), which the ordered compaction of the dense
+// array would otherwise count in a pass of its own.
 __global__ __launch_bounds__(1024) void k_part_fill(const uint16_t* __restrict__ part, const uint32_t* __restrict__ offs,
                                                     const unsigned long long* __restrict__ total, uint32_t P,
-                                                    uint32_t n_tiles, uint64_t R, uint32_t* __restrict__ dcnt) {
+                                                    uint32_t n_tiles, uint64_t R, uint32_t* __restrict__ dcnt,
+                                                    uint32_t* __restrict__ blk) {
   __shared__ uint32_t c[kPartKeys];
   const uint32_t p = blockIdx.x;
   for (uint32_t i = threadIdx.x; i < kPartKeys; i += blockDim.x) c[i] = 0;
@@ -393,15 +400,24 @@ __global__ __launch_bounds__(1024) void k_part_fill(const uint16_t* __restrict__
   }
   __syncthreads();
   const uint64_t key0 = (uint64_t)p * kPartKeys;
-  const uint64_t nk = R - key0 < kPartKeys ? R - key0 : kPartKeys;
+  const uint32_t nk = (uint32_t)(R - key0 < kPartKeys ? R - key0 : kPartKeys);
   for (uint32_t i = threadIdx.x; i < nk; i += blockDim.x) dcnt[key0 + i] = c[i];
+  // keys present per compaction block, one wave per block
+  const uint32_t lane = lane_id();
+  for (uint32_t b = threadIdx.x / kWave; b * kCompTile < nk; b += blockDim.x / kWave) {
+    const uint32_t q1 = (b + 1) * kCompTile < nk ? (b + 1) * kCompTile : nk;
+    uint32_t present = 0;
+    for (uint32_t q = b * kCompTile; q < q1; q += kWave) {
+      const uint32_t i = q + lane;
+      present += (uint32_t)__popcll(__ballot(i < q1 && c[i] != 0));
+    }
+    if (lane == 0) blk[key0 / kCompTile + b] = present;
+  }
 }
 
 // ----------------------------------------------------------------------------
 // ordered compaction of dense arrays: keys with count > 0, ascending
 // ----------------------------------------------------------------------------
-constexpr uint32_t kCompTile = 2048;  // keys per block (256 threads x 8)
-
 __global__ __launch_bounds__(256) void k_dense_count(const uint32_t* __restrict__ dcnt, uint32_t R, uint32_t* __restrict__ blk) {
   __shared__ uint32_t s;
   if (threadIdx.x == 0) s = 0;
@@ -985,14 +1001,15 @@ hipError_t int_enqueue_global_array_parts(const IntLaunch& L, const PartPlan& pp
   hipLaunchKernelGGL(k_scan_apply, dim3(pp.sb), dim3(256), 0, s, hist, pp.H, scan_sums);
   hipLaunchKernelGGL(k_part_scatter, dim3(pp.n_tiles), dim3(kPartThreads), part_scatter_lds(pp.P), s, in, L.R, pp.P, pp.n_tiles,
                      hist, total, part);
-  hipLaunchKernelGGL(k_part_fill, dim3(pp.P), dim3(1024), 0, s, part, hist, total, pp.P, pp.n_tiles, L.R, L.dcnt);
+  hipLaunchKernelGGL(k_part_fill, dim3(pp.P), dim3(1024), 0, s, part, hist, total, pp.P, pp.n_tiles, L.R, L.dcnt, L.blk);
   return hipGetLastError();
 }
 
 // Compaction of the dense arrays into the outputs; clears them when asked.
-hipError_t int_enqueue_dense_out(const IntLaunch& L, bool clear, hipStream_t s) {
+// blk_counted: the blocks' present keys are in L.blk already (partitioned fill).
+hipError_t int_enqueue_dense_out(const IntLaunch& L, bool clear, bool blk_counted, hipStream_t s) {
   const uint32_t nb = (uint32_t)((L.R + kCompTile - 1) / kCompTile);
-  hipLaunchKernelGGL(k_dense_count, dim3(nb ? nb : 1), dim3(256), 0, s, L.dcnt, L.R, L.blk);
+  if (!blk_counted) hipLaunchKernelGGL(k_dense_count, dim3(nb ? nb : 1), dim3(256), 0, s, L.dcnt, L.R, L.blk);
   hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, s, L.blk, nb, L.n_out);
   switch (L.op) {
     case 0: hipLaunchKernelGGL(k_dense_write<0>, dim3(nb ? nb : 1), dim3(256), 0, s, L.dcnt, L.dval, L.R, L.blk, L.out_keys, L.out_vals, L.cap, clear); break;

@@ -159,7 +159,7 @@ PartPlan part_plan(uint64_t n, uint64_t R);
 hipError_t int_enqueue_global_array_parts(const IntLaunch& L, const PartPlan& pp, uint32_t* hist, uint32_t* scan_sums,
                                           unsigned long long* total, uint16_t* part, hipStream_t s);
 hipError_t int_enqueue_global_array(const IntLaunch& L, hipStream_t s);
-hipError_t int_enqueue_dense_out(const IntLaunch& L, bool clear, hipStream_t s);
+hipError_t int_enqueue_dense_out(const IntLaunch& L, bool clear, bool blk_counted, hipStream_t s);
 hipError_t int_enqueue_hash_map(const IntLaunch& L, hipStream_t s);
 hipError_t int_enqueue_hash_out(const IntLaunch& L, uint64_t n_claimed_host, hipStream_t s);
 hipError_t int_enqueue_hash_sort_out(const IntLaunch& L, uint64_t n, hipStream_t s);
