@@ -1506,8 +1506,12 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scan(const WordJob* __res
     carry_b += tot_b;
     __syncthreads();
   }
-  if (threadIdx.x == 0 && (J.st->n_recs > J.cap_keys || J.st->key_bytes > J.cap_key_bytes))
-    atomicOr(&J.st->flags, kFlagCapacity);
+  // the outputs' capacity; when they hold the job, the final entry of its
+  // key offsets (the total of its key bytes)
+  if (threadIdx.x == 0) {
+    if (J.st->n_recs > J.cap_keys || J.st->key_bytes > J.cap_key_bytes) atomicOr(&J.st->flags, kFlagCapacity);
+    else if (J.out_key_offsets) J.out_key_offsets[J.st->n_recs] = J.st->key_bytes;
+  }
 }
 
 __global__ __launch_bounds__(256) void k_sort_scatter(const WordJob* __restrict__ jobs, uint32_t n_jobs, const uint32_t* totals,
@@ -1681,14 +1685,6 @@ __global__ __launch_bounds__(kBucketThreads) void k_sort_buckets(const WordJob* 
       }
       __syncthreads();
     }
-  }
-}
-
-// Final entry of each job's key offsets (the total number of key bytes).
-__global__ void k_words_finish(const WordJob* __restrict__ jobs, uint32_t n_jobs) {
-  for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < n_jobs; j += gridDim.x * blockDim.x) {
-    const WordJob& J = jobs[j];
-    if (J.out_key_offsets && !(J.st->flags & kFlagCapacity)) J.out_key_offsets[J.st->n_recs] = J.st->key_bytes;
   }
 }
 
@@ -1923,7 +1919,6 @@ hipError_t words_enqueue_reduce(const WordsLaunch& L, hipStream_t s) {
                      L.bucket_fill);
   hipLaunchKernelGGL(k_sort_buckets, dim3(L.sort_grid), dim3(kBucketThreads), 0, s, L.jobs, L.n_jobs, L.totals, L.bucket_cnt,
                      L.bucket_bytes, L.bucket_start, L.bucket_bstart);
-  hipLaunchKernelGGL(k_words_finish, dim3(1), dim3(256), 0, s, L.jobs, L.n_jobs);
   return hipGetLastError();
 }
 
