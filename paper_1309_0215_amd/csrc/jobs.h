@@ -28,7 +28,7 @@ struct JobState {
   uint32_t bucket_base;            // first global bucket of this job
   uint32_t rtile_base;             // first record tile of this job
   uint32_t sort_spills;            // sort buckets too large for LDS (sorted in global memory)
-  uint32_t rank_base;              // first work item of this job in k_sort_ranks
+  uint32_t pad;
 };
 
 static_assert(sizeof(JobState) % 8 == 0, "JobState is cleared as 32-bit words");

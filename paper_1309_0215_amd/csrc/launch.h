@@ -19,7 +19,7 @@ struct WordsLaunch {
   uint32_t debug_hash;
   bool any_records;
   bool wave_combine;          // merge equal words of a wave before the LDS cache (the wave-level combiner)
-  uint32_t* totals;           // device [3]: buckets, record tiles, rank work items
+  uint32_t* totals;           // device [2]: buckets, record tiles
   uint32_t* bucket_cnt;       // device [n_jobs * kMaxBuckets]
   unsigned long long* bucket_bytes;
   uint32_t* bucket_start;

@@ -1217,62 +1217,59 @@ MR_DEV uint32_t sample_ov(uint32_t nb) {
                                                  : (nb * 2 * kOversample <= kMaxSamples ? 2 * kOversample : kOversample);
 }
 
-// Plan the sort of every job: bucket counts and global bucket, record-tile
-// and rank work-item bases. One workgroup; the jobs are taken blockDim at a
-// time, one per thread, and the bases come from a workgroup scan of the
-// counts.
+// Sort plan of one job of n distinct keys: buckets, record tiles and rank
+// work items (the last only for jobs of more than one bucket).
+MR_DEV void job_plan(uint64_t n, uint32_t& nb, uint32_t& rt, uint32_t& si) {
+  nb = 1;
+  si = 0;
+  if (n > kBucketCap) {
+    const uint64_t want = (n + kBucketKeys - 1) / kBucketKeys;
+    nb = (uint32_t)(want < kMaxBuckets ? want : kMaxBuckets);
+    si = (nb * sample_ov(nb) + kRankRows - 1) / kRankRows;
+  }
+  rt = (uint32_t)((n + kRecTile - 1) / kRecTile);
+}
+
+// Plan the sort of every job: bucket counts and global bucket / record-tile
+// bases. One workgroup; the jobs are taken blockDim at a time, one per
+// thread, and the bases come from a workgroup scan of the counts.
 __global__ __launch_bounds__(kSortThreads) void k_sort_plan(const WordJob* __restrict__ jobs, uint32_t n_jobs,
                                                              uint32_t* totals /*[2]*/) {
-  __shared__ uint32_t w_nb[kSortThreads / kWave], w_rt[kSortThreads / kWave], w_si[kSortThreads / kWave];
+  __shared__ uint32_t w_nb[kSortThreads / kWave], w_rt[kSortThreads / kWave];
   const uint32_t lane = lane_id(), wv = threadIdx.x / kWave, nw = blockDim.x / kWave;
-  uint32_t carry_b = 0, carry_r = 0, carry_s = 0;
+  uint32_t carry_b = 0, carry_r = 0;
   for (uint32_t base = 0; base < n_jobs; base += blockDim.x) {
     const uint32_t j = base + threadIdx.x;
-    uint32_t nb = 0, rt = 0, si = 0;
-    if (j < n_jobs) {
-      const uint64_t n = jobs[j].st->n_recs;
-      nb = 1;
-      if (n > kBucketCap) {
-        const uint64_t want = (n + kBucketKeys - 1) / kBucketKeys;
-        nb = (uint32_t)(want < kMaxBuckets ? want : kMaxBuckets);
-        si = (nb * sample_ov(nb) + kRankRows - 1) / kRankRows;
-      }
-      rt = (uint32_t)((n + kRecTile - 1) / kRecTile);
-    }
-    const uint32_t inb = wave_incl_scan(nb), irt = wave_incl_scan(rt), isi = wave_incl_scan(si);
+    uint32_t nb = 0, rt = 0, si;
+    if (j < n_jobs) job_plan(jobs[j].st->n_recs, nb, rt, si);
+    const uint32_t inb = wave_incl_scan(nb), irt = wave_incl_scan(rt);
     if (lane == kWave - 1) {
       w_nb[wv] = inb;
       w_rt[wv] = irt;
-      w_si[wv] = isi;
     }
     __syncthreads();
-    uint32_t pb = carry_b, pr = carry_r, ps = carry_s, tb = 0, tr = 0, ts = 0;
+    uint32_t pb = carry_b, pr = carry_r, tb = 0, tr = 0;
     for (uint32_t q = 0; q < nw; ++q) {
       if (q < wv) {
         pb += w_nb[q];
         pr += w_rt[q];
-        ps += w_si[q];
       }
       tb += w_nb[q];
       tr += w_rt[q];
-      ts += w_si[q];
     }
     if (j < n_jobs) {
       JobState* st = jobs[j].st;
       st->nb = nb;
       st->bucket_base = pb + inb - nb;
       st->rtile_base = pr + irt - rt;
-      st->rank_base = ps + isi - si;
     }
     carry_b += tb;
     carry_r += tr;
-    carry_s += ts;
     __syncthreads();
   }
   if (threadIdx.x == 0) {
     totals[0] = carry_b;
     totals[1] = carry_r;
-    totals[2] = carry_s;
   }
 }
 
@@ -1323,40 +1320,62 @@ MR_DEV void key_order(uint4 a, uint32_t al, uint4 b, uint32_t bl, bool& lt, bool
   tie = e0 & e1 & e2 & e3 & (al > 16u) & (bl > 16u);
 }
 
-// Work item g of k_sort_ranks: the job whose items hold it.
-MR_DEV uint32_t find_rank_job(const WordJob* jobs, uint32_t n_jobs, uint32_t g) {
-  uint32_t lo = 0, hi = n_jobs;
-  while (hi - lo > 1) {
-    const uint32_t mid = (lo + hi) >> 1;
-    if (jobs[mid].st->rank_base <= g) lo = mid; else hi = mid;
-  }
-  return lo;
-}
 
 // The same splitters without a sort, for a batch of a few jobs: a single
 // sort of the sample would leave all but one CU idle. The keys are
 // distinct, so a sample's rank is the number of samples below it, found by
 // comparing it with every sample: work item g ranks kRankRows samples of one
 // job, one per wave, each lane taking every 64th sample and a ballot adding
-// up the lanes; the items of all jobs are spread over the grid. The grid
-// also clears every bucket's counters.
+// up the lanes; the items of all jobs are spread over the grid. The kernel
+// also plans the sort of its (at most kRankJobs) jobs, as k_sort_plan would:
+// every workgroup works the plan out for itself, workgroup 0 stores it for
+// the kernels that follow, and the grid clears every bucket's counters.
 __global__ __launch_bounds__(kSortThreads) void k_sort_ranks(const WordJob* __restrict__ jobs, uint32_t n_jobs,
-                                                              const uint32_t* totals, uint32_t* bucket_cnt,
+                                                              uint32_t* totals, uint32_t* bucket_cnt,
                                                               unsigned long long* bucket_bytes, uint32_t* bucket_fill) {
   __shared__ uint4 ck[kMaxSamples];
   __shared__ uint32_t cl[kMaxSamples];
-  const uint32_t n_buckets = totals[0];
+  __shared__ uint32_t s_nb[kRankJobs], s_rank_base[kRankJobs + 1], s_tot[3];
+  if (threadIdx.x == 0) {
+    uint32_t tb = 0, tr = 0, ts = 0;
+    for (uint32_t j = 0; j < n_jobs; ++j) {
+      uint32_t nb, rt, si;
+      job_plan(jobs[j].st->n_recs, nb, rt, si);
+      s_nb[j] = nb;
+      s_rank_base[j] = ts;
+      if (blockIdx.x == 0) {
+        JobState* st = jobs[j].st;
+        st->nb = nb;
+        st->bucket_base = tb;
+        st->rtile_base = tr;
+      }
+      tb += nb;
+      tr += rt;
+      ts += si;
+    }
+    s_rank_base[n_jobs] = ts;
+    s_tot[0] = tb;
+    s_tot[1] = tr;
+    s_tot[2] = ts;
+    if (blockIdx.x == 0) {
+      totals[0] = tb;
+      totals[1] = tr;
+    }
+  }
+  __syncthreads();
+  const uint32_t n_buckets = s_tot[0];
   for (uint32_t b = blockIdx.x * blockDim.x + threadIdx.x; b < n_buckets; b += gridDim.x * blockDim.x) {
     bucket_cnt[b] = 0;
     bucket_bytes[b] = 0;
     bucket_fill[b] = 0;
   }
-  const uint32_t items = totals[2];
+  const uint32_t items = s_tot[2];
   const uint32_t lane = lane_id(), wv = threadIdx.x / kWave;
   for (uint32_t g = blockIdx.x; g < items; g += gridDim.x) {
-    const uint32_t j = find_rank_job(jobs, n_jobs, g);
+    uint32_t j = 0;  // the job whose items hold g
+    while (j + 1 < n_jobs && s_rank_base[j + 1] <= g) ++j;
     const WordJob& J = jobs[j];
-    const uint32_t nb = J.st->nb;
+    const uint32_t nb = s_nb[j];
     const uint64_t n = J.st->n_recs;
     const uint32_t ov = sample_ov(nb), S = nb * ov;
     const WRec* recs = reinterpret_cast<const WRec*>(J.recs);
@@ -1367,7 +1386,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_ranks(const WordJob* __re
       cl[i] = r.len;
     }
     __syncthreads();
-    const uint32_t row = (g - J.st->rank_base) * kRankRows + wv;
+    const uint32_t row = (g - s_rank_base[j]) * kRankRows + wv;
     if (row < S) {
       const uint4 rk = ck[row];
       const uint32_t rl = cl[row];
@@ -1905,13 +1924,15 @@ hipError_t words_enqueue_reduce(const WordsLaunch& L, hipStream_t s) {
   const uint32_t cgrid = (uint32_t)(tiles < 4096 ? tiles : 4096);
   hipLaunchKernelGGL(k_words_compact, dim3(cgrid ? cgrid : 1), dim3(kCompactThreads), 0, s, L.jobs, L.n_jobs, L.total_slots,
                      item);
-  hipLaunchKernelGGL(k_sort_plan, dim3(1), dim3(kSortThreads), 0, s, L.jobs, L.n_jobs, L.totals);
-  if (L.n_jobs <= kRankJobs)
+  if (L.n_jobs <= kRankJobs) {
+    // plans the sort itself
     hipLaunchKernelGGL(k_sort_ranks, dim3(L.sort_grid), dim3(kSortThreads), 0, s, L.jobs, L.n_jobs, L.totals,
                        L.bucket_cnt, L.bucket_bytes, L.bucket_fill);
-  else
+  } else {
+    hipLaunchKernelGGL(k_sort_plan, dim3(1), dim3(kSortThreads), 0, s, L.jobs, L.n_jobs, L.totals);
     hipLaunchKernelGGL(k_sort_splitters, dim3(L.n_jobs), dim3(kSortThreads), 0, s, L.jobs, L.n_jobs, L.bucket_cnt,
                        L.bucket_bytes, L.bucket_fill);
+  }
   hipLaunchKernelGGL(k_sort_count, dim3(L.sort_grid), dim3(256), 0, s, L.jobs, L.n_jobs, L.totals, L.bucket_cnt, L.bucket_bytes);
   hipLaunchKernelGGL(k_sort_scan, dim3(L.n_jobs), dim3(64), 0, s, L.jobs, L.n_jobs, L.bucket_cnt, L.bucket_bytes,
                      L.bucket_start, L.bucket_bstart);
