@@ -1211,7 +1211,7 @@ constexpr uint32_t kRankJobs = 4;                     // batches of up to this m
 // sample fits half of kMaxSamples, 2 * kOversample while it fits all of it,
 // else kOversample. The largest bucket sets the bucket sort's time, and more
 // samples keep it closer to the mean (a bucket larger than the workgroup
-// sorts twice the entries).
+// takes two entries per thread and about twice the time).
 MR_DEV uint32_t sample_ov(uint32_t nb) {
   return nb * 4 * kOversample <= kMaxSamples / 2 ? 4 * kOversample
                                                  : (nb * 2 * kOversample <= kMaxSamples ? 2 * kOversample : kOversample);
