@@ -329,6 +329,18 @@ def test_long_keys_with_one_prefix_in_a_batch(torch):
         _check(r, b)
 
 
+def test_small_batch_of_multi_bucket_jobs(torch):
+    """Four jobs of 3,000 to 60,000 distinct words each: a batch this small
+    takes its splitters from sample ranks spread over all CUs, with the sort
+    planned inside that kernel, and its work items belong to several jobs."""
+    from paper_1309_0215_amd import Job
+    bufs = [gen.text(110 + i, size, V=V, s=0.8) for i, (size, V) in
+            enumerate(((1 << 20, 3_000), (3 << 20, 60_000), (2 << 20, 20_000), (1 << 19, 8_000)))]
+    res = Job(device=0).words_batch([_dev(torch, b) for b in bufs])
+    for r, b in zip(res, bufs):
+        _check(r, b)
+
+
 def test_sort_spill_path(torch):
     """About 2.7 M distinct words: more than the 1024 sort buckets of 2048
     records hold in LDS, so buckets are sorted in global memory (counted in
