@@ -47,6 +47,34 @@ def _check_assign(X, Cn, a, idx=None):
     return int((a[idx] != D.argmin(axis=1)).sum())
 
 
+def _check_assign_all(X, Cn, a, chunk=1 << 20):
+    """_check_assign over every point, for sizes where the direct form of
+    every distance takes minutes. Each point is screened with the expanded
+    float64 form |x|^2 - 2 x.c + |c|^2 (float32 inputs: the products are
+    exact, the 32-term sums round by less than 32 * 2^-53 of |x|^2 + 2|x||c|
+    + |c|^2), taken here with the margin m = 1e-12 (|x|^2 + max |c|^2), over
+    a hundred times that bound. A point whose distance to its assigned
+    centroid lies more than 3m inside the acceptance limit passes, more than
+    3m outside it fails; the others are decided by the oracle's direct form.
+    Returns the number of points so decided."""
+    C64 = np.asarray(Cn, np.float64)
+    cn = (C64 * C64).sum(axis=1)
+    near = []
+    for lo in range(0, len(X), chunk):
+        x = np.asarray(X[lo:lo + chunk], np.float64)
+        xn = (x * x).sum(axis=1)
+        De = xn[:, None] - 2.0 * (x @ C64.T) + cn[None, :]
+        lim = De.min(axis=1) * (1 + 1e-6) + 1e-12
+        dg = De[np.arange(len(x)), a[lo:lo + chunk]]
+        m = 1e-12 * (xn + cn.max())
+        assert not (dg > lim + 3 * m).any(), lo + np.flatnonzero(dg > lim + 3 * m)[:10]
+        near.append(lo + np.flatnonzero(np.abs(dg - lim) <= 3 * m))
+    idx = np.concatenate(near)
+    if len(idx):
+        _check_assign(X, Cn, a, idx)
+    return len(idx)
+
+
 def _check_update(X, Cn, a, s, c, cent):
     k = len(Cn)
     S64, n64, newC = oracle.kmeans_update(X, a, Cn)
@@ -137,15 +165,17 @@ def test_points_equal_to_centroids(torch):
 
 
 def test_full_config_16m(torch):
-    """The full 16,777,216-point step. Assignments of 2^20 points (the first
-    and the last 2^19, which hold the grid's ragged tail) are checked against
-    the oracle's direct form; counts and sums over all points."""
+    """The full 16,777,216-point step. The assignments of all points are
+    checked (the first and the last 2^19, which hold the grid's ragged tail,
+    against the oracle's direct form; every point through _check_assign_all),
+    the counts and sums over all points."""
     X, Cn = gen.kmeans(3)  # 16,777,216 x 32, k = 64, first 64 points
     a, s, c, cent, st = _run(torch, X, Cn)
     assert int(c.astype(np.int64).sum()) == len(X)
     half = 1 << 19
     idx = np.concatenate([np.arange(half), np.arange(len(X) - half, len(X))])
     _check_assign(X, Cn, a, idx)
+    print(f"points decided by the direct form: {_check_assign_all(X, Cn, a)}")
     # sums over all points in float64 with the GPU's assignments (bincount per dim)
     k, d = Cn.shape
     n64 = np.bincount(a, minlength=k)
