@@ -341,6 +341,21 @@ def test_small_batch_of_multi_bucket_jobs(torch):
         _check(r, b)
 
 
+def test_words_past_the_length_tag(torch):
+    """Words of 65,535 bytes and more: the table's 16-bit length tag
+    saturates, so equality needs the true lengths, and keys that share their
+    first 16 bytes are ordered by their bytes in the input (here words of one
+    letter repeated, differing only at the end or in length)."""
+    from paper_1309_0215_amd import Job
+    a = b"a"
+    words = [a * 70_000, a * 70_000, a * 69_999 + b"b", a * 100_000, a * 65_535, a * 65_536, a * 65_534,
+             a * 65_536, b"short", b"a", a * 17, a * 70_000]
+    rng = np.random.default_rng(9)
+    rng.shuffle(words)
+    buf = np.frombuffer(b" ".join(words) + b"\n", np.uint8).copy()
+    _check(Job(device=0).words(_dev(torch, buf)), buf)
+
+
 def test_sort_spill_path(torch):
     """About 2.7 M distinct words: more than the 1024 sort buckets of 2048
     records hold in LDS, so buckets are sorted in global memory (counted in
