@@ -164,6 +164,20 @@ def test_points_equal_to_centroids(torch):
     assert np.array_equal(a, np.arange(64))
 
 
+@pytest.mark.parametrize("d,k", [(32, 64), (5, 7)])
+def test_no_points(torch, d, k):
+    """An input of no points: every cluster is empty, so the counts and sums
+    are zero and every centroid stays where it was (the oracle's update of an
+    empty input gives the same)."""
+    rng = np.random.default_rng(8)
+    Cn = rng.standard_normal((k, d)).astype(np.float32)
+    X = np.zeros((0, d), np.float32)
+    a, s, c, cent, st = _run(torch, X, Cn)
+    assert len(a) == 0 and (c == 0).all() and (s == 0).all()
+    assert np.array_equal(cent, Cn)
+    _check_update(X, Cn, a, s, c, cent)
+
+
 def test_full_config_16m(torch):
     """The full 16,777,216-point step. The assignments of all points are
     checked (the first and the last 2^19, which hold the grid's ragged tail,
