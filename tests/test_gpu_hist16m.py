@@ -5,9 +5,10 @@ with atomics instead of per-worker local arrays, Section III-E).
 * 2^22 elements over 2^24 keys: every output (key, count) against the CPU
   oracle, with the rule's container (global array) and with the hash table
   and the sort forced.
-* The full 2^28 elements: the oracle's counts for 4096 sampled keys (the
-  oracle run on the elements holding those keys), the count total, and the
-  ordering and range of the output keys.
+* The full 2^28 elements: every one of the 2^24 bins against np.bincount.
+* Skewed inputs through the key-range partitions: most elements on one key
+  (one range's segment holds nearly all of them), keys on the range
+  boundaries, and an input of a single key.
 """
 import numpy as np
 import pytest
@@ -79,6 +80,26 @@ def test_pairs_count_and_ragged_range(torch):
     vals = np.arange(len(keys), dtype=np.uint32)
     d = lambda a: torch.from_numpy(a.view(np.int32)).to("cuda:0")  # noqa: E731
     res = Job(device=0).u32(d(keys), d(vals), op=0, key_range=Rr)
+    assert res.stats["strategy_used"] == GLOBAL_ARRAY
+    ek, ev = oracle.u32(keys)
+    assert np.array_equal(res.keys.cpu().numpy().view(np.uint32), ek)
+    assert np.array_equal(res.values.cpu().numpy().view(np.uint32).astype(np.uint64), ev)
+
+
+@pytest.mark.parametrize("share", [0.9, 1.0])
+def test_skewed_keys_through_the_partitions(torch, share):
+    """A share of the 2^22 elements on one key of the last 2^15-key range,
+    keys on both sides of every range boundary, the rest uniform."""
+    n = 1 << 22
+    rng = np.random.default_rng(26)
+    keys = gen.uniform_keys(26, n, R)
+    hot = rng.random(n) < share
+    keys[hot] = R - 5
+    if share < 1.0:
+        edges = np.arange(1, R >> 15, dtype=np.uint32) << 15
+        keys[:len(edges)] = edges
+        keys[len(edges):2 * len(edges)] = edges - 1
+    res = _run(torch, 0, keys)
     assert res.stats["strategy_used"] == GLOBAL_ARRAY
     ek, ev = oracle.u32(keys)
     assert np.array_equal(res.keys.cpu().numpy().view(np.uint32), ek)
