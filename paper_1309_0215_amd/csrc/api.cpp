@@ -1145,7 +1145,7 @@ mr_status u32_finish(mr_job* job, mr_output* out, const IntSmall& hs) {
 
 // Scratch layouts of the integer-key containers (offsets in the scratch region).
 struct DenseCarve {  // LDS or global array over n elements and range R, G workgroups
-  uint64_t o_blk = 0, o_cp = 0, o_vp = 0, o_ph = 0, o_ps = 0, o_pt = 0, o_pk = 0, bytes = 0;
+  uint64_t o_blk = 0, o_cp = 0, o_vp = 0, o_ph = 0, o_pk = 0, bytes = 0;
   bool parts = false;  // a large COUNT array filled by key-range partitions
   PartPlan pp;
 };
@@ -1162,10 +1162,8 @@ DenseCarve dense_carve(mr_strategy strat, uint64_t n, uint64_t R, uint32_t op, u
   d.pp = part_plan(n, R);
   d.parts = strat == MR_STRAT_GLOBAL_ARRAY && op == MR_REDUCE_COUNT && d.pp.usable;
   if (d.parts) {
-    d.o_ph = c.take(4 * d.pp.H);
-    d.o_ps = c.take(4ull * d.pp.sb + 4);
-    d.o_pt = c.take(8);
-    d.o_pk = c.take(2 * n);
+    d.o_ph = c.take(4 * d.pp.runs);
+    d.o_pk = c.take(2 * d.pp.part_elems);
   }
   d.bytes = c.off;
   return d;
@@ -1301,8 +1299,7 @@ mr_status run_u32(mr_job* job, mr_map_kind kind, mr_reduce_op op, const void* d_
     const DenseCarve dc = dense_carve(strat, n, key_range, o, L.G);
     const PartPlan& pp = dc.pp;
     const bool parts = dc.parts;
-    const uint64_t o_blk = dc.o_blk, o_cp = dc.o_cp, o_vp = dc.o_vp, o_ph = dc.o_ph, o_ps = dc.o_ps, o_pt = dc.o_pt,
-                   o_pk = dc.o_pk;
+    const uint64_t o_blk = dc.o_blk, o_cp = dc.o_cp, o_vp = dc.o_vp, o_ph = dc.o_ph, o_pk = dc.o_pk;
     st = scratch(dc.bytes);
     if (st != MR_OK) return st;
     uint8_t* sc = static_cast<uint8_t*>(job->int_scratch);
@@ -1313,9 +1310,8 @@ mr_status run_u32(mr_job* job, mr_map_kind kind, mr_reduce_op op, const void* d_
       L.val_part = sc + o_vp;
       MR_HIP(int_enqueue_lds_array(L, job->stream));
     } else if (parts) {
-      MR_HIP(int_enqueue_global_array_parts(L, pp, reinterpret_cast<uint32_t*>(sc + o_ph), reinterpret_cast<uint32_t*>(sc + o_ps),
-                                            reinterpret_cast<unsigned long long*>(sc + o_pt),
-                                            reinterpret_cast<uint16_t*>(sc + o_pk), job->stream));
+      MR_HIP(int_enqueue_global_array_tiles(L, pp, reinterpret_cast<uint32_t*>(sc + o_ph), reinterpret_cast<uint16_t*>(sc + o_pk),
+                                            job->stream));
     } else {
       MR_HIP(int_enqueue_global_array(L, job->stream));
     }

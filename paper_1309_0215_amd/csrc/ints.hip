@@ -193,16 +193,17 @@ __global__ __launch_bounds__(256) void k_global_array(IntIn in, uint32_t R, uint
 // global array over a large range, filled by key-range partitions (COUNT)
 //
 // Device-scope atomics run far below the load rate, so a large array is not
-// updated element by element. Instead: count the elements of every 2^14-key
-// range per tile, scan, scatter each element's low 14 bits into its range's
-// segment, then one workgroup per range counts its segment in an LDS array
-// and writes the range's counts once. Every array entry is written exactly
-// once; no global atomics on the array.
+// updated element by element. Instead each tile of elements is ordered by
+// 2^15-key range in LDS and written where it stands, as the elements' low 15
+// bits, with the start of each range's run in the tile; then one workgroup
+// per range counts that range's runs of every tile in an LDS array and
+// writes the range's counts once. Every array entry is written exactly once;
+// no global atomics on the array.
 // ----------------------------------------------------------------------------
 constexpr uint32_t kPartBits = 15;
 constexpr uint32_t kPartKeys = 1u << kPartBits;  // keys per range: LDS counters of one workgroup (128 KB)
 constexpr uint32_t kMaxParts = 2048;             // ranges (key range up to 2^26)
-constexpr uint32_t kPartTile = 32768;            // elements per tile of the count and scatter passes
+constexpr uint32_t kPartTile = 32768;            // elements per tile (a multiple of 8)
 constexpr uint32_t kPartThreads = 1024;
 constexpr uint32_t kCompTile = 2048;  // keys per block of the ordered compaction of dense arrays (256 threads x 8)
 static_assert(kPartKeys % kCompTile == 0, "a key range holds whole compaction blocks");
@@ -249,66 +250,40 @@ MR_DEV void for_tile_keys(const IntIn& in, uint64_t base, F&& f) {
   }
 }
 
-// Each workgroup counts kPartCountTiles consecutive tiles, one LDS row of
-// range counters per tile, so that the counts of one range over those tiles
-// are stored as one contiguous run (range-major order, as the scan wants):
-// one store per tile and range had cost about ten times the counts' bytes
-// in partial-line writes.
-constexpr uint32_t kPartCountTiles = 8;
+// Dynamic LDS of k_part_tile: the range arrays, sized by P, so that for
+// P <= 1024 two workgroups fit a CU (one streams its tile while the other
+// scans its counts or writes its row).
+constexpr uint32_t part_tile_lds(uint32_t P) { return (2 * P + 1) * 4; }
 
-__global__ __launch_bounds__(kPartThreads) void k_part_count(IntIn in, uint64_t R, uint32_t P, uint32_t n_tiles,
-                                                             uint32_t* __restrict__ hist /* [P][n_tiles] */,
-                                                             uint32_t* __restrict__ flags) {
-  __shared__ uint32_t h[kPartCountTiles][kMaxParts];
-  const uint32_t t0 = blockIdx.x * kPartCountTiles;
-  const uint32_t nt = n_tiles - t0 < kPartCountTiles ? n_tiles - t0 : kPartCountTiles;
-  for (uint32_t i = threadIdx.x; i < nt * P; i += blockDim.x) h[i / P][i % P] = 0;
-  __syncthreads();
-  bool bad = false;
-  for (uint32_t j = 0; j < nt; ++j)
-    for_tile_keys(in, (uint64_t)(t0 + j) * kPartTile, [&](uint32_t k) {
-      if (k < R) atomicAdd(&h[j][k >> kPartBits], 1u);
-      else bad = true;
-    });
-  __syncthreads();
-  for (uint32_t i = threadIdx.x; i < P * nt; i += blockDim.x) {
-    const uint32_t p = i / nt, j = i % nt;
-    hist[(uint64_t)p * n_tiles + t0 + j] = h[j][p];
-  }
-  if (bad) atomicOr(flags, kFlagBadInput);
-}
-
-// Each tile is ordered by range in LDS first; then each wave writes whole
-// runs (one range's elements of the tile) as contiguous 2-byte entries. The
-// range arrays take dynamic LDS sized by P (part_scatter_lds), so that for
-// P <= 1024 two workgroups fit a CU: one streams its tile while the other
-// scans its counts or writes its runs.
-constexpr uint32_t part_scatter_lds(uint32_t P) { return (2 * P + 1) * 4; }
-
-__global__ __launch_bounds__(kPartThreads) void k_part_scatter(IntIn in, uint64_t R, uint32_t P, uint32_t n_tiles,
-                                                               const uint32_t* __restrict__ offs /* scanned hist */,
-                                                               const unsigned long long* __restrict__ total,
-                                                               uint16_t* __restrict__ part) {
+// Tile t writes its elements' in-range offsets ordered by range to
+// part[t * kPartTile, ...) and the start of each range's run in the tile to
+// runs[t * (P + 1) + p] (entry P: the tile's element count), both as whole
+// contiguous rows.
+__global__ __launch_bounds__(kPartThreads) void k_part_tile(IntIn in, uint64_t R, uint32_t P, uint32_t* __restrict__ runs,
+                                                            uint16_t* __restrict__ part, uint32_t* __restrict__ flags) {
   extern __shared__ uint32_t ranges[];
-  uint32_t* const lbase = ranges;         // [P + 1] start of each range's run in the staged tile (and the end)
-  uint32_t* const lpos = ranges + P + 1;  // [P] next free place of each range's run
-  __shared__ uint16_t sk[kPartTile];      // staged low bits, ordered by range
+  uint32_t* const lbase = ranges;         // [P + 1] start of each range's run in the tile (and the end)
+  uint32_t* const lpos = ranges + P + 1;  // [P] counts, then the next free place of each range's run
+  __shared__ __attribute__((aligned(16))) uint16_t sk[kPartTile];  // staged offsets, ordered by range
   __shared__ uint32_t wsum[kPartThreads / kWave];
   const uint32_t t = blockIdx.x;
-  // this tile's count of range p, from the scanned counts (range-major, tile-minor)
-  auto tile_count = [&](uint32_t p) -> uint32_t {
-    const uint64_t at = (uint64_t)p * n_tiles + t;
-    const uint64_t next = at + 1 < (uint64_t)P * n_tiles ? (uint64_t)offs[at + 1] : *total;
-    return (uint32_t)(next - offs[at]);
-  };
-  // exclusive scan of the tile's range counts (P <= 2048: 2 per thread)
+  for (uint32_t q = threadIdx.x; q < P; q += blockDim.x) lpos[q] = 0u;
+  __syncthreads();
+  // 1. the tile's count of each range
+  bool bad = false;
+  for_tile_keys(in, (uint64_t)t * kPartTile, [&](uint32_t k) {
+    if (k < R) atomicAdd(&lpos[k >> kPartBits], 1u);
+    else bad = true;
+  });
+  if (bad) atomicOr(flags, kFlagBadInput);
+  __syncthreads();
+  // 2. run starts: exclusive scan of the counts (P <= kMaxParts: kPer per thread)
   constexpr uint32_t kPer = kMaxParts / kPartThreads;
-  uint32_t c[kPer], gb[kPer], sum = 0;  // this tile's count and global segment start per range
+  uint32_t c[kPer], sum = 0;
 #pragma unroll
   for (uint32_t q = 0; q < kPer; ++q) {
-    const uint32_t p = threadIdx.x * kPer + q;
-    c[q] = p < P ? tile_count(p) : 0u;
-    gb[q] = p < P ? offs[(uint64_t)p * n_tiles + t] : 0u;
+    const uint32_t r = threadIdx.x * kPer + q;
+    c[q] = r < P ? lpos[r] : 0u;
     sum += c[q];
   }
   const uint32_t lane = lane_id(), wv = threadIdx.x / kWave;
@@ -328,81 +303,101 @@ __global__ __launch_bounds__(kPartThreads) void k_part_scatter(IntIn in, uint64_
   uint32_t run = pre + incl - sum;
 #pragma unroll
   for (uint32_t q = 0; q < kPer; ++q) {
-    const uint32_t p = threadIdx.x * kPer + q;
-    if (p < P) {
-      lbase[p] = run;
-      lpos[p] = run;
+    const uint32_t r = threadIdx.x * kPer + q;
+    if (r < P) {
+      lbase[r] = run;
+      lpos[r] = run;
     }
     run += c[q];
   }
   if (threadIdx.x == 0) lbase[P] = m;
   __syncthreads();
+  uint32_t* const row = runs + (uint64_t)t * (P + 1);
+  for (uint32_t q = threadIdx.x; q <= P; q += blockDim.x) row[q] = lbase[q];
+  // 3. each element to its place (the tile is read again: keeping it in
+  // registers took one workgroup per CU instead of two, and was slower)
   for_tile_keys(in, (uint64_t)t * kPartTile, [&](uint32_t k) {
     if (k < R) sk[atomicAdd(&lpos[k >> kPartBits], 1u)] = (uint16_t)(k & (kPartKeys - 1));
   });
   __syncthreads();
-  // the run ends are lbase[p + 1]: lpos now holds the global segment starts,
-  // so that the write loop reads no global memory before its stores
-#pragma unroll
-  for (uint32_t q = 0; q < kPer; ++q) {
-    const uint32_t p = threadIdx.x * kPer + q;
-    if (p < P) lpos[p] = gb[q];
-  }
-  __syncthreads();
-  for (uint32_t p = wv; p < P; p += kPartThreads / kWave) {
-    const uint32_t b0 = lbase[p], b1 = lbase[p + 1];
-    uint16_t* dst = part + lpos[p];
-    for (uint32_t j = b0 + lane; j < b1; j += kWave) dst[j - b0] = sk[j];
+  // 4. the staged offsets as one row, eight per 16-byte store
+  uint16_t* const dst = part + (uint64_t)t * kPartTile;
+  for (uint32_t i = threadIdx.x; i * 8u < m; i += blockDim.x) {
+    if (i * 8u + 8u <= m) {
+      gstore16(dst + i * 8u, *reinterpret_cast<const uint4*>(&sk[i * 8u]));
+    } else {
+      for (uint32_t e = i * 8u; e < m; ++e) dst[e] = sk[e];
+    }
   }
 }
 
-// One workgroup per key range counts the range's segment in LDS and writes
-// the range's counts once. It also counts the keys present in each of the
-// range's compaction blocks (blk), which the ordered compaction of the dense
-// array would otherwise count in a pass of its own.
-__global__ __launch_bounds__(1024) void k_part_fill(const uint16_t* __restrict__ part, const uint32_t* __restrict__ offs,
-                                                    const unsigned long long* __restrict__ total, uint32_t P,
-                                                    uint32_t n_tiles, uint64_t R, uint32_t* __restrict__ dcnt,
-                                                    uint32_t* __restrict__ blk) {
+// One workgroup per key range counts the range's runs of every tile in LDS
+// (a thread takes whole tiles: it loads its tiles' run bounds together, then
+// a run's covering 16-byte pieces, up to kFillVecs at once, before it counts
+// them) and writes the range's counts once, with the present keys per
+// compaction block (the ordered compaction's first pass, done here).
+constexpr uint32_t kFillTilesPer = 8;  // tiles a thread takes at a time
+constexpr uint32_t kFillVecs = 12;     // 16-byte pieces of a run loaded before counting
+
+__global__ __launch_bounds__(1024) void k_part_fill_tiles(const uint16_t* __restrict__ part, const uint32_t* __restrict__ runs,
+                                                          uint32_t P, uint32_t n_tiles, uint64_t R,
+                                                          uint32_t* __restrict__ dcnt, uint32_t* __restrict__ blk) {
   __shared__ uint32_t c[kPartKeys];
   const uint32_t p = blockIdx.x;
   for (uint32_t i = threadIdx.x; i < kPartKeys; i += blockDim.x) c[i] = 0;
   __syncthreads();
-  const uint64_t start = offs[(uint64_t)p * n_tiles];
-  const uint64_t end = p + 1 < P ? offs[(uint64_t)(p + 1) * n_tiles] : *total;
-  // 8 entries per 16-byte load over the aligned middle, single entries at the ends
-  const uint64_t a0 = (start + 7) & ~7ull, a1 = end & ~7ull;
-  if (a0 < a1) {
-    const uint4* v = reinterpret_cast<const uint4*>(part + a0);
-    const uint64_t nv = (a1 - a0) / 8;
-    auto count8 = [&](const uint4& x) {
-      const uint32_t w[4] = {x.x, x.y, x.z, x.w};
+  auto count8 = [&](const uint4& x) {
+    const uint32_t w[4] = {x.x, x.y, x.z, x.w};
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        atomicAdd(&c[w[e] & 0xFFFFu], 1u);
-        atomicAdd(&c[w[e] >> 16], 1u);
-      }
-    };
-    // loads in batches of four per lane, issued before any of them is used
-    uint64_t q = threadIdx.x;
-    for (; q + 3 * blockDim.x < nv; q += 4 * blockDim.x) {
-      uint4 x[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) x[u] = gload16(v + q + u * blockDim.x);
-#pragma unroll
-      for (int u = 0; u < 4; ++u) count8(x[u]);
+    for (int e = 0; e < 4; ++e) {
+      atomicAdd(&c[w[e] & 0xFFFFu], 1u);
+      atomicAdd(&c[w[e] >> 16], 1u);
     }
-    for (; q < nv; q += blockDim.x) count8(gload16(v + q));
-    for (uint64_t j = start + threadIdx.x; j < a0; j += blockDim.x) atomicAdd(&c[part[j]], 1u);
-    for (uint64_t j = a1 + threadIdx.x; j < end; j += blockDim.x) atomicAdd(&c[part[j]], 1u);
-  } else {
-    for (uint64_t j = start + threadIdx.x; j < end; j += blockDim.x) atomicAdd(&c[part[j]], 1u);
+  };
+  for (uint32_t t0 = 0; t0 < n_tiles; t0 += kFillTilesPer * blockDim.x) {
+    uint32_t b0[kFillTilesPer], b1[kFillTilesPer];
+#pragma unroll
+    for (uint32_t u = 0; u < kFillTilesPer; ++u) {
+      const uint32_t t = t0 + u * blockDim.x + threadIdx.x;
+      b0[u] = b1[u] = 0u;
+      if (t < n_tiles) {
+        const uint32_t* row = runs + (uint64_t)t * (P + 1) + p;
+        b0[u] = *gp(row);
+        b1[u] = *gp(row + 1);
+      }
+    }
+#pragma unroll 1
+    for (uint32_t u = 0; u < kFillTilesPer; ++u) {
+      const uint16_t* src = part + (uint64_t)(t0 + u * blockDim.x + threadIdx.x) * kPartTile;
+      // the run [b0, b1) read as the aligned 16-byte pieces that cover it
+      // (inside the tile's row, whose length is a multiple of 8 entries),
+      // the entries outside it left out
+      const uint32_t lo = b0[u], hi = b1[u];
+      for (uint32_t v = lo & ~7u; v < hi; v += 8u * kFillVecs) {
+        uint4 x[kFillVecs];
+#pragma unroll
+        for (uint32_t q = 0; q < kFillVecs; ++q)
+          if (v + 8u * q < hi) x[q] = gload16(src + v + 8u * q);
+#pragma unroll
+        for (uint32_t q = 0; q < kFillVecs; ++q) {
+          const uint32_t e0 = v + 8u * q;
+          if (e0 >= hi) continue;
+          if (e0 >= lo && e0 + 8u <= hi) {
+            count8(x[q]);
+          } else {
+            const uint32_t w[4] = {x[q].x, x[q].y, x[q].z, x[q].w};
+#pragma unroll
+            for (uint32_t i = 0; i < 8u; ++i)
+              if (e0 + i >= lo && e0 + i < hi) atomicAdd(&c[(w[i >> 1] >> (16u * (i & 1u))) & 0xFFFFu], 1u);
+          }
+        }
+      }
+    }
   }
   __syncthreads();
   const uint64_t key0 = (uint64_t)p * kPartKeys;
   const uint32_t nk = (uint32_t)(R - key0 < kPartKeys ? R - key0 : kPartKeys);
   for (uint32_t i = threadIdx.x; i < nk; i += blockDim.x) dcnt[key0 + i] = c[i];
-  // keys present per compaction block, one wave per block
   const uint32_t lane = lane_id();
   for (uint32_t b = threadIdx.x / kWave; b * kCompTile < nk; b += blockDim.x / kWave) {
     const uint32_t q1 = (b + 1) * kCompTile < nk ? (b + 1) * kCompTile : nk;
@@ -985,23 +980,19 @@ PartPlan part_plan(uint64_t n, uint64_t R) {
   PartPlan pp{};
   pp.P = (uint32_t)((R + kPartKeys - 1) / kPartKeys);
   pp.n_tiles = (uint32_t)((n + kPartTile - 1) / kPartTile);
-  pp.H = (uint64_t)pp.P * pp.n_tiles;
-  pp.sb = (uint32_t)((pp.H + kScanTile - 1) / kScanTile);
+  pp.runs = (uint64_t)(pp.P + 1) * pp.n_tiles;
+  pp.part_elems = (uint64_t)pp.n_tiles * kPartTile;
   pp.usable = R > kPartKeys && pp.P <= kMaxParts && n >= (1ull << 20) && n < (1ull << 32);
   return pp;
 }
 
-hipError_t int_enqueue_global_array_parts(const IntLaunch& L, const PartPlan& pp, uint32_t* hist, uint32_t* scan_sums,
-                                          unsigned long long* total, uint16_t* part, hipStream_t s) {
+// The tile-major fill: runs [n_tiles][P + 1], part [n_tiles * kPartTile].
+hipError_t int_enqueue_global_array_tiles(const IntLaunch& L, const PartPlan& pp, uint32_t* runs, uint16_t* part,
+                                          hipStream_t s) {
   const IntIn in{L.in, L.n, L.kv};
-  hipLaunchKernelGGL(k_part_count, dim3((pp.n_tiles + kPartCountTiles - 1) / kPartCountTiles), dim3(kPartThreads), 0, s, in,
-                     L.R, pp.P, pp.n_tiles, hist, L.flags);
-  hipLaunchKernelGGL(k_scan_blocks, dim3(pp.sb), dim3(256), 0, s, hist, pp.H, scan_sums);
-  hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, s, scan_sums, pp.sb, total);
-  hipLaunchKernelGGL(k_scan_apply, dim3(pp.sb), dim3(256), 0, s, hist, pp.H, scan_sums);
-  hipLaunchKernelGGL(k_part_scatter, dim3(pp.n_tiles), dim3(kPartThreads), part_scatter_lds(pp.P), s, in, L.R, pp.P, pp.n_tiles,
-                     hist, total, part);
-  hipLaunchKernelGGL(k_part_fill, dim3(pp.P), dim3(1024), 0, s, part, hist, total, pp.P, pp.n_tiles, L.R, L.dcnt, L.blk);
+  hipLaunchKernelGGL(k_part_tile, dim3(pp.n_tiles), dim3(kPartThreads), part_tile_lds(pp.P), s, in, L.R, pp.P, runs, part,
+                     L.flags);
+  hipLaunchKernelGGL(k_part_fill_tiles, dim3(pp.P), dim3(1024), 0, s, part, runs, pp.P, pp.n_tiles, L.R, L.dcnt, L.blk);
   return hipGetLastError();
 }
 

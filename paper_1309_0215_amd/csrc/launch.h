@@ -150,14 +150,14 @@ hipError_t bloom_enqueue(const uint8_t* in, uint64_t n_bytes, uint32_t k, uint32
 // global array filled by key-range partitions (COUNT): plan and enqueue
 struct PartPlan {
   uint32_t P;        // key ranges of 2^15 keys
-  uint32_t n_tiles;  // tiles of the count and scatter passes
-  uint64_t H;        // P * n_tiles range counts
-  uint32_t sb;       // scan blocks over the counts
+  uint32_t n_tiles;  // tiles of elements
+  uint64_t runs;     // (P + 1) * n_tiles run starts
+  uint64_t part_elems;  // n_tiles * tile size: the in-range offsets, tile by tile
   bool usable;       // range, size and element count suit this fill
 };
 PartPlan part_plan(uint64_t n, uint64_t R);
-hipError_t int_enqueue_global_array_parts(const IntLaunch& L, const PartPlan& pp, uint32_t* hist, uint32_t* scan_sums,
-                                          unsigned long long* total, uint16_t* part, hipStream_t s);
+hipError_t int_enqueue_global_array_tiles(const IntLaunch& L, const PartPlan& pp, uint32_t* runs, uint16_t* part,
+                                          hipStream_t s);
 hipError_t int_enqueue_global_array(const IntLaunch& L, hipStream_t s);
 hipError_t int_enqueue_dense_out(const IntLaunch& L, bool clear, bool blk_counted, hipStream_t s);
 hipError_t int_enqueue_hash_map(const IntLaunch& L, hipStream_t s);
