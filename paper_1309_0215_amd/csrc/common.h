@@ -38,6 +38,7 @@ MR_DEV void gstore16(void* p, uint4 x) {
 }
 
 constexpr int kWave = 64;
+constexpr uint32_t kXcds = 8;  // accelerator complex dies; workgroups are dispatched to them in turn
 
 // ---------------------------------------------------------------------------
 // hashing (the hash only places keys; equality is always decided on full keys)

@@ -343,7 +343,11 @@ __global__ __launch_bounds__(1024) void k_part_fill_tiles(const uint16_t* __rest
                                                           uint32_t P, uint32_t n_tiles, uint64_t R,
                                                           uint32_t* __restrict__ dcnt, uint32_t* __restrict__ blk) {
   __shared__ uint32_t c[kPartKeys];
-  const uint32_t p = blockIdx.x;
+  // Workgroups are handed to the eight XCDs in turn; neighbouring ranges read
+  // neighbouring words of every tile's run-start row and share the 128-byte
+  // lines where their runs meet, so each XCD takes a contiguous block of
+  // ranges and its L2 serves those lines once.
+  const uint32_t p = (P % kXcds == 0u) ? (blockIdx.x % kXcds) * (P / kXcds) + blockIdx.x / kXcds : blockIdx.x;
   for (uint32_t i = threadIdx.x; i < kPartKeys; i += blockDim.x) c[i] = 0;
   __syncthreads();
   auto count8 = [&](const uint4& x) {
