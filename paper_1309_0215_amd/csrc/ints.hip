@@ -203,8 +203,9 @@ __global__ __launch_bounds__(256) void k_global_array(IntIn in, uint32_t R, uint
 constexpr uint32_t kPartBits = 15;
 constexpr uint32_t kPartKeys = 1u << kPartBits;  // keys per range: LDS counters of one workgroup (128 KB)
 constexpr uint32_t kMaxParts = 2048;             // ranges (key range up to 2^26)
-constexpr uint32_t kPartTile = 32768;            // elements per tile (a multiple of 8)
+constexpr uint32_t kPartTile = 16384;            // elements per tile (a multiple of 8)
 constexpr uint32_t kPartThreads = 1024;
+static_assert(kPartTile % (4 * kPartThreads) == 0, "a held tile is whole 16-byte vectors, the same number per thread");
 constexpr uint32_t kCompTile = 2048;  // keys per block of the ordered compaction of dense arrays (256 threads x 8)
 static_assert(kPartKeys % kCompTile == 0, "a key range holds whole compaction blocks");
 
@@ -269,12 +270,33 @@ __global__ __launch_bounds__(kPartThreads) void k_part_tile(IntIn in, uint64_t R
   const uint32_t t = blockIdx.x;
   for (uint32_t q = threadIdx.x; q < P; q += blockDim.x) lpos[q] = 0u;
   __syncthreads();
+  // A whole tile of aligned plain keys is held in registers between the count
+  // and the placing (four 16-byte vectors per thread); other tiles are read
+  // twice.
+  constexpr uint32_t kHeld = kPartTile / 4 / kPartThreads;
+  const bool held = !in.kv && ((uintptr_t)in.p & 15u) == 0 && (uint64_t)(t + 1) * kPartTile <= in.n &&
+                    blockDim.x == kPartThreads;
+  uint4 x[kHeld];
   // 1. the tile's count of each range
   bool bad = false;
-  for_tile_keys(in, (uint64_t)t * kPartTile, [&](uint32_t k) {
+  auto count = [&](uint32_t k) {
     if (k < R) atomicAdd(&lpos[k >> kPartBits], 1u);
     else bad = true;
-  });
+  };
+  if (held) {
+    const uint4* v = reinterpret_cast<const uint4*>(in.p + (uint64_t)t * kPartTile);
+#pragma unroll
+    for (uint32_t u = 0; u < kHeld; ++u) x[u] = gload16(v + threadIdx.x + u * kPartThreads);
+#pragma unroll
+    for (uint32_t u = 0; u < kHeld; ++u) {
+      count(x[u].x);
+      count(x[u].y);
+      count(x[u].z);
+      count(x[u].w);
+    }
+  } else {
+    for_tile_keys(in, (uint64_t)t * kPartTile, count);
+  }
   if (bad) atomicOr(flags, kFlagBadInput);
   __syncthreads();
   // 2. run starts: exclusive scan of the counts (P <= kMaxParts: kPer per thread)
@@ -314,11 +336,21 @@ __global__ __launch_bounds__(kPartThreads) void k_part_tile(IntIn in, uint64_t R
   __syncthreads();
   uint32_t* const row = runs + (uint64_t)t * (P + 1);
   for (uint32_t q = threadIdx.x; q <= P; q += blockDim.x) row[q] = lbase[q];
-  // 3. each element to its place (the tile is read again: keeping it in
-  // registers took one workgroup per CU instead of two, and was slower)
-  for_tile_keys(in, (uint64_t)t * kPartTile, [&](uint32_t k) {
+  // 3. each element to its place
+  auto place = [&](uint32_t k) {
     if (k < R) sk[atomicAdd(&lpos[k >> kPartBits], 1u)] = (uint16_t)(k & (kPartKeys - 1));
-  });
+  };
+  if (held) {
+#pragma unroll
+    for (uint32_t u = 0; u < kHeld; ++u) {
+      place(x[u].x);
+      place(x[u].y);
+      place(x[u].z);
+      place(x[u].w);
+    }
+  } else {
+    for_tile_keys(in, (uint64_t)t * kPartTile, place);
+  }
   __syncthreads();
   // 4. the staged offsets as one row, eight per 16-byte store
   uint16_t* const dst = part + (uint64_t)t * kPartTile;
