@@ -374,7 +374,7 @@ constexpr uint32_t kFillVecs = 12;     // 16-byte pieces of a run loaded before 
 __global__ __launch_bounds__(1024) void k_part_fill_tiles(const uint16_t* __restrict__ part, const uint32_t* __restrict__ runs,
                                                           uint32_t P, uint32_t n_tiles, uint64_t R,
                                                           uint32_t* __restrict__ dcnt, uint32_t* __restrict__ blk) {
-  __shared__ uint32_t c[kPartKeys];
+  __shared__ uint32_t c[kPartKeys + kWave / 2];  // the range's counters, then 32 sinks for entries outside a run
   // Workgroups are handed to the eight XCDs in turn; neighbouring ranges read
   // neighbouring words of every tile's run-start row and share the 128-byte
   // lines where their runs meet, so each XCD takes a contiguous block of
@@ -382,14 +382,7 @@ __global__ __launch_bounds__(1024) void k_part_fill_tiles(const uint16_t* __rest
   const uint32_t p = (P % kXcds == 0u) ? (blockIdx.x % kXcds) * (P / kXcds) + blockIdx.x / kXcds : blockIdx.x;
   for (uint32_t i = threadIdx.x; i < kPartKeys; i += blockDim.x) c[i] = 0;
   __syncthreads();
-  auto count8 = [&](const uint4& x) {
-    const uint32_t w[4] = {x.x, x.y, x.z, x.w};
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      atomicAdd(&c[w[e] & 0xFFFFu], 1u);
-      atomicAdd(&c[w[e] >> 16], 1u);
-    }
-  };
+  const uint32_t sink = kPartKeys + (threadIdx.x & (kWave / 2 - 1));
   for (uint32_t t0 = 0; t0 < n_tiles; t0 += kFillTilesPer * blockDim.x) {
     uint32_t b0[kFillTilesPer], b1[kFillTilesPer];
 #pragma unroll
@@ -407,7 +400,7 @@ __global__ __launch_bounds__(1024) void k_part_fill_tiles(const uint16_t* __rest
       const uint16_t* src = part + (uint64_t)(t0 + u * blockDim.x + threadIdx.x) * kPartTile;
       // the run [b0, b1) read as the aligned 16-byte pieces that cover it
       // (inside the tile's row, whose length is a multiple of 8 entries),
-      // the entries outside it left out
+      // the entries outside it counted in a sink
       const uint32_t lo = b0[u], hi = b1[u];
       for (uint32_t v = lo & ~7u; v < hi; v += 8u * kFillVecs) {
         uint4 x[kFillVecs];
@@ -418,13 +411,13 @@ __global__ __launch_bounds__(1024) void k_part_fill_tiles(const uint16_t* __rest
         for (uint32_t q = 0; q < kFillVecs; ++q) {
           const uint32_t e0 = v + 8u * q;
           if (e0 >= hi) continue;
-          if (e0 >= lo && e0 + 8u <= hi) {
-            count8(x[q]);
-          } else {
-            const uint32_t w[4] = {x[q].x, x[q].y, x[q].z, x[q].w};
+          // eight atomics whatever the piece's overlap with the run: an entry
+          // outside it goes to one of the sinks, spread over the banks
+          const uint32_t w[4] = {x[q].x, x[q].y, x[q].z, x[q].w};
 #pragma unroll
-            for (uint32_t i = 0; i < 8u; ++i)
-              if (e0 + i >= lo && e0 + i < hi) atomicAdd(&c[(w[i >> 1] >> (16u * (i & 1u))) & 0xFFFFu], 1u);
+          for (uint32_t i = 0; i < 8u; ++i) {
+            const uint32_t key = (w[i >> 1] >> (16u * (i & 1u))) & 0xFFFFu;
+            atomicAdd(&c[e0 + i - lo < hi - lo ? key : sink], 1u);
           }
         }
       }
