@@ -9,6 +9,8 @@ with atomics instead of per-worker local arrays, Section III-E).
 * Skewed inputs through the key-range partitions: most elements on one key
   (one range's segment holds nearly all of them), keys on the range
   boundaries, and an input of a single key.
+* Inputs off the fast tile path: a partial last tile, keys 4 bytes past a
+  16-byte boundary, and (key, value) pairs.
 """
 import numpy as np
 import pytest
@@ -102,5 +104,24 @@ def test_skewed_keys_through_the_partitions(torch, share):
     res = _run(torch, 0, keys)
     assert res.stats["strategy_used"] == GLOBAL_ARRAY
     ek, ev = oracle.u32(keys)
+    assert np.array_equal(res.keys.cpu().numpy().view(np.uint32), ek)
+    assert np.array_equal(res.values.cpu().numpy().view(np.uint32).astype(np.uint64), ev)
+
+
+@pytest.mark.parametrize("offset", [0, 1])
+def test_ragged_and_unaligned_inputs(torch, offset):
+    """Plain keys whose last 16K-element tile is partial (offset 0: the whole
+    tiles are held in registers, the last one is read twice), and the same
+    keys starting 4 bytes past a 16-byte boundary (offset 1: every tile takes
+    the path that reads it twice, one key at a time)."""
+    from paper_1309_0215_amd import Job
+    n = (1 << 22) + 77
+    keys = gen.uniform_keys(27, n + 1, R)
+    kt = torch.from_numpy(keys.view(np.int32)).to("cuda:0")
+    view = kt[offset:offset + n]
+    assert (view.data_ptr() % 16 == 0) == (offset == 0)
+    res = Job(device=0).u32(view, key_range=R)
+    assert res.stats["strategy_used"] == GLOBAL_ARRAY
+    ek, ev = oracle.u32(keys[offset:offset + n])
     assert np.array_equal(res.keys.cpu().numpy().view(np.uint32), ek)
     assert np.array_equal(res.values.cpu().numpy().view(np.uint32).astype(np.uint64), ev)
