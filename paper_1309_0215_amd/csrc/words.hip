@@ -269,10 +269,20 @@ MR_DEV bool g_insert(const WordJob& J, uint64_t vlo, uint64_t vhi, uint64_t off,
 // prep: validate record offsets and publish the valid byte range
 // ----------------------------------------------------------------------------
 
-__global__ void k_words_prep(const WordJob* __restrict__ jobs, uint32_t n_jobs) {
+// Without record offsets one block per job (blockIdx.y) clears the job's
+// state and publishes its whole input as the valid range: the state's only
+// writer here, so no separate clearing launch is needed. With them the states
+// are cleared by k_zero_states beforehand (the blocks of a job report bad
+// offsets into its flags).
+__global__ void k_words_prep(const WordJob* __restrict__ jobs, uint32_t n_jobs, uint32_t clear) {
   const uint32_t j = blockIdx.y;
   if (j >= n_jobs) return;
   const WordJob J = jobs[j];
+  if (clear) {
+    uint32_t* w = reinterpret_cast<uint32_t*>(J.st);
+    for (uint32_t i = threadIdx.x; i < (uint32_t)(sizeof(JobState) / 4); i += blockDim.x) w[i] = 0u;
+    __syncthreads();
+  }
   if (!J.rec) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       J.st->valid_lo = 0;
@@ -1867,17 +1877,18 @@ __global__ void k_zero_states(JobState* st, uint32_t n) {
 }
 
 hipError_t words_enqueue_zero_states(const WordsLaunch& L, hipStream_t s) {
-  hipLaunchKernelGGL(k_zero_states, dim3(1), dim3(256), 0, s, L.states, L.n_jobs);
+  // without record offsets the prep kernel clears each job's state itself
+  if (L.any_records) hipLaunchKernelGGL(k_zero_states, dim3(1), dim3(256), 0, s, L.states, L.n_jobs);
   return hipGetLastError();
 }
 
 hipError_t words_enqueue_prep(const WordsLaunch& L, hipStream_t s) {
   if (L.any_records) {
     dim3 g(64, L.n_jobs);
-    hipLaunchKernelGGL(k_words_prep, g, dim3(256), 0, s, L.jobs, L.n_jobs);
+    hipLaunchKernelGGL(k_words_prep, g, dim3(256), 0, s, L.jobs, L.n_jobs, 0u);
   } else {
     dim3 g(1, L.n_jobs);
-    hipLaunchKernelGGL(k_words_prep, g, dim3(64), 0, s, L.jobs, L.n_jobs);
+    hipLaunchKernelGGL(k_words_prep, g, dim3(64), 0, s, L.jobs, L.n_jobs, 1u);
   }
   return hipGetLastError();
 }
