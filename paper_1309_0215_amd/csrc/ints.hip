@@ -378,7 +378,8 @@ __global__ __launch_bounds__(1024) void k_part_fill_tiles(const uint16_t* __rest
   // Workgroups are handed to the eight XCDs in turn; neighbouring ranges read
   // neighbouring words of every tile's run-start row and share the 128-byte
   // lines where their runs meet, so each XCD takes a contiguous block of
-  // ranges and its L2 serves those lines once.
+  // ranges and its L2 serves those lines once. The map is a permutation of
+  // the ranges: another dispatch order costs cache hits, not correctness.
   const uint32_t p = (P % kXcds == 0u) ? (blockIdx.x % kXcds) * (P / kXcds) + blockIdx.x / kXcds : blockIdx.x;
   for (uint32_t i = threadIdx.x; i < kPartKeys; i += blockDim.x) c[i] = 0;
   __syncthreads();
