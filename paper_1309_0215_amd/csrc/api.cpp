@@ -926,8 +926,10 @@ mr_status run_links(mr_job* job, mr_reduce_op op, const void* d_input, uint64_t 
   }
   // file lists
   const uint64_t n = n_marks, nk = out->n_keys;
-  const uint32_t fb = bits_for(rec ? n_rec : 1), rb = bits_for(nk + 1);
-  const int sort_bits = (int)std::max<uint32_t>(8, (fb + rb + 7) / 8 * 8);
+  // key = rank * F + record, below n_keys * F; all ones in the sorted bits marks no link
+  const uint64_t F = rec ? std::max<uint64_t>(n_rec, 1) : 1;
+  const uint32_t kb = bits_for(nk * F + 1);
+  const int sort_bits = (int)std::max<uint32_t>(8, (kb + 7) / 8 * 8);
   const uint64_t hw = links_hist_words(n);
   Carve c2 = c;
   const uint64_t o_k0 = c2.take(8 * n), o_v0 = c2.take(8 * n), o_k1 = c2.take(8 * n), o_v1 = c2.take(8 * n);
@@ -956,7 +958,7 @@ mr_status run_links(mr_job* job, mr_reduce_op op, const void* d_input, uint64_t 
   P.n = n;
   P.slot_rank = lb.slot_rank;
   P.n_keys = nk;
-  P.file_bits = (int)fb;
+  P.file_mod = F;
   P.sort_bits = sort_bits;
   P.k0 = reinterpret_cast<unsigned long long*>(d + o_k0);
   P.v0 = reinterpret_cast<unsigned long long*>(d + o_v0);

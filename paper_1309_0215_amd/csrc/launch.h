@@ -49,8 +49,8 @@ struct LinksPost {
   uint64_t n;                   // pairs (markers)
   const uint32_t* slot_rank;    // output rank of the URL in each table slot
   uint64_t n_keys;              // distinct URLs
-  int file_bits;                // bits of a record index
-  int sort_bits;                // rank bits + file bits, a multiple of 8
+  uint64_t file_mod;            // sort key = rank * file_mod + record (file_mod: the record count, at least 1)
+  int sort_bits;                // key bits, a multiple of 8, with 2^sort_bits > n_keys * file_mod
   unsigned long long *k0, *v0, *k1, *v1;  // [n] each: sort keys, unused values, and their second buffers
   uint32_t* hist;               // radix histogram
   uint32_t* scan_sums;

@@ -25,15 +25,17 @@ __global__ void k_links_init(unsigned long long* total, unsigned long long* n_va
   }
 }
 
-// Sort key of each pair: (output rank of its URL) << file_bits | record; all
-// ones for a marker that starts no link (those sort last).
+// Sort key of each pair: (output rank of its URL) * file_mod + record, which
+// orders by rank and then record in fewer bits than a shifted rank when the
+// record count is not a power of two; all ones for a marker that starts no
+// link (those sort last: the sorted bits of a valid key are never all ones).
 __global__ __launch_bounds__(kLinksThreads) void k_links_rank(LinksPost P) {
   for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < P.n; i += (uint64_t)gridDim.x * blockDim.x) {
     const uint32_t slot = P.pair_slot[i];
     unsigned long long key = ~0ull;
     if (slot != ~0u) {
       const uint32_t rank = P.slot_rank[slot];
-      if (rank < P.n_keys) key = ((unsigned long long)rank << P.file_bits) | P.pair_file[i];
+      if (rank < P.n_keys) key = (unsigned long long)rank * P.file_mod + P.pair_file[i];
       else atomicOr(P.flags, kFlagInternal);  // every URL of the table has an output rank
     }
     P.k0[i] = key;
@@ -58,12 +60,11 @@ __global__ __launch_bounds__(kLinksThreads) void k_links_heads(const unsigned lo
 // offset and its first index among the sorted pairs. list_off[n_keys] = the
 // number of list entries, first[n_keys] = the number of links.
 __global__ __launch_bounds__(kLinksThreads) void k_links_write(const unsigned long long* __restrict__ k, uint64_t n,
-                                                               const uint32_t* __restrict__ pos, int file_bits,
+                                                               const uint32_t* __restrict__ pos, uint64_t file_mod,
                                                                const unsigned long long* __restrict__ total,
                                                                const unsigned long long* __restrict__ n_valid,
                                                                uint64_t n_keys, uint32_t* __restrict__ ids,
                                                                uint64_t* __restrict__ list_off, uint32_t* __restrict__ first) {
-  const unsigned long long fmask = (1ull << file_bits) - 1ull;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     list_off[n_keys] = *total;
     first[n_keys] = (uint32_t)*n_valid;
@@ -73,10 +74,11 @@ __global__ __launch_bounds__(kLinksThreads) void k_links_write(const unsigned lo
     if (x == ~0ull) continue;
     const unsigned long long prev = i ? k[i - 1] : ~0ull;
     if (i && x == prev) continue;
-    ids[pos[i]] = (uint32_t)(x & fmask);
-    if (i == 0 || (x >> file_bits) != (prev >> file_bits)) {
-      list_off[x >> file_bits] = pos[i];
-      first[x >> file_bits] = (uint32_t)i;
+    const unsigned long long rank = x / file_mod;
+    ids[pos[i]] = (uint32_t)(x - rank * file_mod);
+    if (i == 0 || rank != prev / file_mod) {
+      list_off[rank] = pos[i];
+      first[rank] = (uint32_t)i;
     }
   }
 }
@@ -110,7 +112,7 @@ hipError_t links_enqueue_rank_sort(const LinksPost& P, bool* sorted_in_1, hipStr
 hipError_t links_enqueue_write(const LinksPost& P, bool sorted_in_1, uint32_t* ids, uint64_t* list_off, uint32_t* counts,
                                hipStream_t s) {
   const unsigned long long* k = sorted_in_1 ? P.k1 : P.k0;
-  hipLaunchKernelGGL(k_links_write, dim3(links_grid(P.n)), dim3(kLinksThreads), 0, s, k, P.n, P.head, P.file_bits,
+  hipLaunchKernelGGL(k_links_write, dim3(links_grid(P.n)), dim3(kLinksThreads), 0, s, k, P.n, P.head, P.file_mod,
                      P.total, P.n_valid, P.n_keys, ids, list_off, P.first);
   if (P.n_keys)
     hipLaunchKernelGGL(k_links_counts, dim3(links_grid(P.n_keys)), dim3(kLinksThreads), 0, s, P.first, P.n_keys, counts);
