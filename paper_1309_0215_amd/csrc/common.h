@@ -66,6 +66,28 @@ MR_DEV uint64_t hash_u32(uint32_t k) { return fmix64((uint64_t)k * 0x9E3779B97F4
 // ---------------------------------------------------------------------------
 // separators: the six ASCII whitespace bytes 0x09..0x0D and 0x20
 // ---------------------------------------------------------------------------
+// Lane l receives lane l + 1's value (lane 63 keeps `fill`), and lane l
+// receives lane l - 1's value (lane 0 keeps `fill`): DPP whole-wave shifts.
+MR_DEV uint32_t from_next_lane(uint32_t v, uint32_t fill) {
+  return (uint32_t)__builtin_amdgcn_update_dpp((int)fill, (int)v, 0x130, 0xF, 0xF, false);  // wave_shl:1
+}
+MR_DEV uint32_t from_prev_lane(uint32_t v, uint32_t fill) {
+  return (uint32_t)__builtin_amdgcn_update_dpp((int)fill, (int)v, 0x138, 0xF, 0xF, false);  // wave_shr:1
+}
+
+// Inclusive prefix sum over the 64 lanes with DPP: shifts within rows of 16
+// lanes, then the last lane of row 0 (row 2) is broadcast into row 1 (row 3),
+// and the last lane of row 1 into rows 2 and 3. No LDS traffic.
+MR_DEV uint32_t wave_incl_scan(uint32_t x) {
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xF, 0xF, true);  // row_shr:1
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xF, 0xF, true);  // row_shr:2
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xF, 0xF, true);  // row_shr:4
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xF, 0xF, true);  // row_shr:8
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xA, 0xF, false);  // row_bcast:15
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xC, 0xF, false);  // row_bcast:31
+  return x;
+}
+
 MR_DEV bool is_sep_byte(uint32_t b) { return b == 0x20u || (b - 0x09u) < 5u; }
 
 // Separator flags of a little-endian word: bit 7 of byte i is set when byte i

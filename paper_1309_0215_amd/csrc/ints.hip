@@ -994,8 +994,63 @@ hipError_t int_enqueue_global_array(const IntLaunch& L, hipStream_t s) {
   return hipGetLastError();
 }
 
+// Exclusive scan of a[0, n) in place by one workgroup, for n up to
+// kScanOneMax: wave w takes a contiguous segment of whole 64-element steps.
+// Each wave sums its segment (coalesced loads), the 16 wave totals are
+// scanned in LDS, then each wave reads its segment again (from the cache)
+// and scans it kScanOneBatch steps at a time with DPP lane shifts (the
+// batch's scans are independent, so they overlap), adding a running carry.
+// One launch instead of the block sums, their scan and the apply.
+constexpr uint32_t kScanOneWaves = 16;
+constexpr uint32_t kScanOneSteps = 64;  // 64-element steps per wave at most
+constexpr uint32_t kScanOneBatch = 8;   // steps loaded and scanned together
+constexpr uint64_t kScanOneMax = (uint64_t)kScanOneWaves * kWave * kScanOneSteps;
+
+__global__ __launch_bounds__(kScanOneWaves * kWave) void k_scan_one(uint32_t* __restrict__ a, uint32_t n,
+                                                                   unsigned long long* total) {
+  __shared__ uint32_t ws[kScanOneWaves];
+  const uint32_t lane = lane_id(), wv = threadIdx.x / kWave;
+  const uint32_t steps = (n + kScanOneWaves * kWave - 1) / (kScanOneWaves * kWave);  // <= kScanOneSteps
+  const uint32_t b0 = wv * steps * kWave;
+  auto at = [&](uint32_t q) { return b0 + q * kWave + lane; };
+  uint32_t part = 0;
+  for (uint32_t q0 = 0; q0 < steps; q0 += kScanOneBatch) {
+    uint32_t v[kScanOneBatch];
+#pragma unroll
+    for (uint32_t u = 0; u < kScanOneBatch; ++u) v[u] = (q0 + u < steps && at(q0 + u) < n) ? a[at(q0 + u)] : 0u;
+#pragma unroll
+    for (uint32_t u = 0; u < kScanOneBatch; ++u) part += v[u];
+  }
+  const uint32_t wsum = wave_incl_scan(part);  // every lane takes part in the lane shifts
+  if (lane == kWave - 1) ws[wv] = wsum;
+  __syncthreads();
+  uint32_t carry = 0, all = 0;
+  for (uint32_t w = 0; w < kScanOneWaves; ++w) {
+    if (w < wv) carry += ws[w];
+    all += ws[w];
+  }
+  for (uint32_t q0 = 0; q0 < steps; q0 += kScanOneBatch) {
+    uint32_t v[kScanOneBatch];
+#pragma unroll
+    for (uint32_t u = 0; u < kScanOneBatch; ++u) v[u] = (q0 + u < steps && at(q0 + u) < n) ? a[at(q0 + u)] : 0u;
+#pragma unroll
+    for (uint32_t u = 0; u < kScanOneBatch; ++u) v[u] = wave_incl_scan(v[u]);
+#pragma unroll
+    for (uint32_t u = 0; u < kScanOneBatch; ++u) {
+      const uint32_t ex = from_prev_lane(v[u], 0u);  // exclusive within the step
+      if (q0 + u < steps && at(q0 + u) < n) a[at(q0 + u)] = carry + ex;
+      carry += (uint32_t)__builtin_amdgcn_readlane((int)v[u], kWave - 1);
+    }
+  }
+  if (threadIdx.x == 0 && total) *total = all;
+}
+
 // Exclusive scan of a[0, n) in place; the sum of all entries into *total.
 hipError_t scan_exclusive_u32(uint32_t* a, uint64_t n, uint32_t* sums, unsigned long long* total, hipStream_t s) {
+  if (n <= kScanOneMax) {
+    hipLaunchKernelGGL(k_scan_one, dim3(1), dim3(kScanOneWaves * kWave), 0, s, a, (uint32_t)n, total);
+    return hipGetLastError();
+  }
   const uint32_t sb = (uint32_t)((n + kScanTile - 1) / kScanTile);
   hipLaunchKernelGGL(k_scan_blocks, dim3(sb ? sb : 1), dim3(256), 0, s, a, n, sums);
   hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, s, sums, sb ? sb : 1, total);
@@ -1067,9 +1122,14 @@ hipError_t radix_sort64(unsigned long long* k0, unsigned long long* v0, unsigned
     unsigned long long *ki = in1 ? k1 : k0, *vi = in1 ? v1 : v0, *ko = in1 ? k0 : k1, *vo = in1 ? v0 : v1;
     if (n) {
       hipLaunchKernelGGL(k_radix_hist, dim3(n_tiles), dim3(256), 0, s, ki, n, sh, n_tiles, hist);
-      hipLaunchKernelGGL(k_scan_blocks, dim3(sb), dim3(256), 0, s, hist, hn, scan_sums);
-      hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, s, scan_sums, sb, (unsigned long long*)nullptr);
-      hipLaunchKernelGGL(k_scan_apply, dim3(sb), dim3(256), 0, s, hist, hn, scan_sums);
+      if (hn <= kScanOneMax) {
+        hipLaunchKernelGGL(k_scan_one, dim3(1), dim3(kScanOneWaves * kWave), 0, s, hist, (uint32_t)hn,
+                           (unsigned long long*)nullptr);
+      } else {
+        hipLaunchKernelGGL(k_scan_blocks, dim3(sb), dim3(256), 0, s, hist, hn, scan_sums);
+        hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, s, scan_sums, sb, (unsigned long long*)nullptr);
+        hipLaunchKernelGGL(k_scan_apply, dim3(sb), dim3(256), 0, s, hist, hn, scan_sums);
+      }
       hipLaunchKernelGGL(k_radix_scatter, dim3(n_tiles), dim3(256), 0, s, ki, vi, n, sh, n_tiles, hist, ko, vo);
     }
     in1 = !in1;

@@ -463,28 +463,6 @@ MR_DEV uint32_t sep16(uint4 b) { return sep_mask16(b.x, b.y, b.z, b.w); }
 // Four 32-bit words read at any byte address.
 typedef uint32_t u32x4_u __attribute__((ext_vector_type(4), aligned(1)));
 
-// Lane l receives lane l + 1's value (lane 63 keeps `fill`), and lane l
-// receives lane l - 1's value (lane 0 keeps `fill`): DPP whole-wave shifts.
-MR_DEV uint32_t from_next_lane(uint32_t v, uint32_t fill) {
-  return (uint32_t)__builtin_amdgcn_update_dpp((int)fill, (int)v, 0x130, 0xF, 0xF, false);  // wave_shl:1
-}
-MR_DEV uint32_t from_prev_lane(uint32_t v, uint32_t fill) {
-  return (uint32_t)__builtin_amdgcn_update_dpp((int)fill, (int)v, 0x138, 0xF, 0xF, false);  // wave_shr:1
-}
-
-// Inclusive prefix sum over the 64 lanes with DPP: shifts within rows of 16
-// lanes, then the last lane of row 0 (row 2) is broadcast into row 1 (row 3),
-// and the last lane of row 1 into rows 2 and 3. No LDS traffic.
-MR_DEV uint32_t wave_incl_scan(uint32_t x) {
-  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xF, 0xF, true);  // row_shr:1
-  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xF, 0xF, true);  // row_shr:2
-  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xF, 0xF, true);  // row_shr:4
-  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xF, 0xF, true);  // row_shr:8
-  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xA, 0xF, false);  // row_bcast:15
-  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xC, 0xF, false);  // row_bcast:31
-  return x;
-}
-
 // Wave-level combiner: `rounds` times, the first lane still holding a word
 // is the leader; every lane whose word equals the leader's (same LDS hash,
 // length and bytes) adds its count to the leader and drops out. `v` is this
