@@ -975,20 +975,22 @@ mr_status run_links(mr_job* job, mr_reduce_op op, const void* d_input, uint64_t 
   MR_HIP(hipEventRecord(job->ev0, job->stream));
   bool in1 = false;
   MR_HIP(links_enqueue_rank_sort(P, &in1, job->stream));
+  // the lists are written at once (entries past the capacity are skipped);
+  // their size and the error flag are checked after the one synchronisation
+  MR_HIP(links_enqueue_write(P, in1, out->list_ids, out->cap_list_ids, out->list_offsets,
+                             static_cast<uint32_t*>(out->values), job->stream));
   unsigned long long tv[2] = {0, 0};
   uint32_t flags = 0;
   MR_HIP(hipMemcpyAsync(&tv[0], P.total, 8, hipMemcpyDeviceToHost, job->stream));
   MR_HIP(hipMemcpyAsync(&tv[1], P.n_valid, 8, hipMemcpyDeviceToHost, job->stream));
   MR_HIP(hipMemcpyAsync(&flags, P.flags, 4, hipMemcpyDeviceToHost, job->stream));
+  MR_HIP(hipEventRecord(job->ev1, job->stream));
   MR_HIP(hipStreamSynchronize(job->stream));
   if (flags) return fail(MR_ERR_HIP, "internal error: a link's URL is missing from the sorted URLs");
   out->n_list_ids = tv[0];
   out->stats.n_items = tv[1];
   if (tv[0] > out->cap_list_ids)
     return fail(MR_ERR_CAPACITY, "the file lists need %llu entries", (unsigned long long)tv[0]);
-  MR_HIP(links_enqueue_write(P, in1, out->list_ids, out->list_offsets, static_cast<uint32_t*>(out->values), job->stream));
-  MR_HIP(hipEventRecord(job->ev1, job->stream));
-  MR_HIP(hipStreamSynchronize(job->stream));
   float ms = 0.f;
   MR_HIP(hipEventElapsedTime(&ms, job->ev0, job->ev1));
   out->stats.gpu_ms += ms;

@@ -61,8 +61,8 @@ struct LinksPost {
   uint32_t* first;              // [n_keys + 1] first sorted pair of each rank
 };
 hipError_t links_enqueue_rank_sort(const LinksPost& P, bool* sorted_in_1, hipStream_t s);
-hipError_t links_enqueue_write(const LinksPost& P, bool sorted_in_1, uint32_t* ids, uint64_t* list_off, uint32_t* counts,
-                               hipStream_t s);
+hipError_t links_enqueue_write(const LinksPost& P, bool sorted_in_1, uint32_t* ids, uint64_t cap_ids, uint64_t* list_off,
+                               uint32_t* counts, hipStream_t s);
 uint64_t links_hist_words(uint64_t n);
 hipError_t radix_sort64(unsigned long long* k0, unsigned long long* v0, unsigned long long* k1, unsigned long long* v1,
                         uint64_t n, int bits, uint32_t* hist, uint32_t* scan_sums, bool* result_in_1, hipStream_t s);

@@ -56,14 +56,15 @@ __global__ __launch_bounds__(kLinksThreads) void k_links_heads(const unsigned lo
 }
 
 // After the exclusive scan of the heads: each head writes its record into
-// the list at its position; the first head of a rank writes the rank's list
+// the list at its position (positions past cap_ids are skipped: the host
+// reports the capacity error after the launch); the first head of a rank writes the rank's list
 // offset and its first index among the sorted pairs. list_off[n_keys] = the
 // number of list entries, first[n_keys] = the number of links.
 __global__ __launch_bounds__(kLinksThreads) void k_links_write(const unsigned long long* __restrict__ k, uint64_t n,
                                                                const uint32_t* __restrict__ pos, uint64_t file_mod,
                                                                const unsigned long long* __restrict__ total,
                                                                const unsigned long long* __restrict__ n_valid,
-                                                               uint64_t n_keys, uint32_t* __restrict__ ids,
+                                                               uint64_t n_keys, uint32_t* __restrict__ ids, uint64_t cap_ids,
                                                                uint64_t* __restrict__ list_off, uint32_t* __restrict__ first) {
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     list_off[n_keys] = *total;
@@ -75,7 +76,7 @@ __global__ __launch_bounds__(kLinksThreads) void k_links_write(const unsigned lo
     const unsigned long long prev = i ? k[i - 1] : ~0ull;
     if (i && x == prev) continue;
     const unsigned long long rank = x / file_mod;
-    ids[pos[i]] = (uint32_t)(x - rank * file_mod);
+    if (pos[i] < cap_ids) ids[pos[i]] = (uint32_t)(x - rank * file_mod);
     if (i == 0 || rank != prev / file_mod) {
       list_off[rank] = pos[i];
       first[rank] = (uint32_t)i;
@@ -109,11 +110,11 @@ hipError_t links_enqueue_rank_sort(const LinksPost& P, bool* sorted_in_1, hipStr
   return scan_exclusive_u32(P.head, P.n, P.scan_sums, P.total, s);
 }
 
-hipError_t links_enqueue_write(const LinksPost& P, bool sorted_in_1, uint32_t* ids, uint64_t* list_off, uint32_t* counts,
-                               hipStream_t s) {
+hipError_t links_enqueue_write(const LinksPost& P, bool sorted_in_1, uint32_t* ids, uint64_t cap_ids, uint64_t* list_off,
+                               uint32_t* counts, hipStream_t s) {
   const unsigned long long* k = sorted_in_1 ? P.k1 : P.k0;
   hipLaunchKernelGGL(k_links_write, dim3(links_grid(P.n)), dim3(kLinksThreads), 0, s, k, P.n, P.head, P.file_mod,
-                     P.total, P.n_valid, P.n_keys, ids, list_off, P.first);
+                     P.total, P.n_valid, P.n_keys, ids, cap_ids, list_off, P.first);
   if (P.n_keys)
     hipLaunchKernelGGL(k_links_counts, dim3(links_grid(P.n_keys)), dim3(kLinksThreads), 0, s, P.first, P.n_keys, counts);
   return hipGetLastError();
