@@ -447,6 +447,7 @@ struct LinkBufs {
   uint32_t* pair_slot;
   uint32_t* pair_file;
   uint32_t* slot_rank;  // set by the pass: output rank of each table slot
+  unsigned long long h_n_marks;  // set by the pass: markers found (read back with the job states)
 };
 
 struct WordItem {
@@ -771,11 +772,15 @@ mr_status words_pass(mr_job* job, std::vector<WordItem>& items, std::vector<JobS
     MR_HIP(words_enqueue_reduce(L, s));
     MR_HIP(hipEventRecord(job->ev1, s));
   }
-  st = ensure_host_states(job, n);
+  // (with markers, their count comes back in the same round trip, in the
+  // pinned buffer's entry past the states)
+  st = ensure_host_states(job, n + (lb ? 1u : 0u));
   if (st != MR_OK) return st;
   MR_HIP(hipMemcpyAsync(job->h_states, ws + p.o_states, sizeof(JobState) * n, hipMemcpyDeviceToHost, s));
+  if (lb) MR_HIP(hipMemcpyAsync(&job->h_states[n], lb->n_marks, 8, hipMemcpyDeviceToHost, s));
   MR_HIP(hipStreamSynchronize(s));
   states.assign(job->h_states, job->h_states + n);
+  if (lb) std::memcpy(&lb->h_n_marks, &job->h_states[n], 8);
   float ms = 0.f;
   MR_HIP(hipEventElapsedTime(&ms, job->ev0, job->ev1));
   *gpu_ms = ms;
@@ -909,11 +914,11 @@ mr_status run_links(mr_job* job, mr_reduce_op op, const void* d_input, uint64_t 
     if (st != MR_OK) return st;
     uint8_t* d = static_cast<uint8_t*>(job->link_dev);
     lb = LinkBufs{reinterpret_cast<uint32_t*>(d + o_marks), reinterpret_cast<unsigned long long*>(d + o_n), cap,
-                  reinterpret_cast<uint32_t*>(d + o_slot), reinterpret_cast<uint32_t*>(d + o_file), nullptr};
+                  reinterpret_cast<uint32_t*>(d + o_slot), reinterpret_cast<uint32_t*>(d + o_file), nullptr, 0ull};
     items[0] = WordItem{static_cast<const uint8_t*>(d_input), bytes, rec, n_rec, out, 0};
     st = run_words(job, items, nullptr, GraphMode::kNever, &lb);
     if (st != MR_OK && st != MR_ERR_CAPACITY) return st;
-    MR_HIP(hipMemcpy(&n_marks, lb.n_marks, 8, hipMemcpyDeviceToHost));
+    n_marks = lb.h_n_marks;
     if (n_marks <= cap) break;
     if (attempt >= 2) return fail(MR_ERR_HIP, "marker list did not converge");
     cap = next_pow2(n_marks);
@@ -971,7 +976,6 @@ mr_status run_links(mr_job* job, mr_reduce_op op, const void* d_input, uint64_t 
   P.n_valid = reinterpret_cast<unsigned long long*>(d + o_val);
   P.flags = reinterpret_cast<uint32_t*>(d + o_fl);
   P.first = reinterpret_cast<uint32_t*>(d + o_first);
-  MR_HIP(hipMemsetAsync(P.flags, 0, 4, job->stream));
   MR_HIP(hipEventRecord(job->ev0, job->stream));
   bool in1 = false;
   MR_HIP(links_enqueue_rank_sort(P, &in1, job->stream));

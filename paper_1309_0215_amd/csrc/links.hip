@@ -18,10 +18,11 @@ namespace mr {
 constexpr uint32_t kLinksThreads = 256;
 constexpr uint32_t kLinksRadixTile = 2048;  // elements per tile of the radix sort in ints.hip
 
-__global__ void k_links_init(unsigned long long* total, unsigned long long* n_valid) {
+__global__ void k_links_init(unsigned long long* total, unsigned long long* n_valid, uint32_t* flags) {
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     *total = 0ull;
     *n_valid = 0ull;
+    *flags = 0u;
   }
 }
 
@@ -100,7 +101,7 @@ static uint32_t links_grid(uint64_t n) {
 
 hipError_t links_enqueue_rank_sort(const LinksPost& P, bool* sorted_in_1, hipStream_t s) {
   *sorted_in_1 = false;
-  hipLaunchKernelGGL(k_links_init, dim3(1), dim3(64), 0, s, P.total, P.n_valid);
+  hipLaunchKernelGGL(k_links_init, dim3(1), dim3(64), 0, s, P.total, P.n_valid, P.flags);
   if (!P.n) return hipGetLastError();
   hipLaunchKernelGGL(k_links_rank, dim3(links_grid(P.n)), dim3(kLinksThreads), 0, s, P);
   hipError_t e = radix_sort64(P.k0, P.v0, P.k1, P.v1, P.n, P.sort_bits, P.hist, P.scan_sums, sorted_in_1, s);
