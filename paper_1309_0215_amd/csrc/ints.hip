@@ -1086,7 +1086,8 @@ hipError_t int_enqueue_global_array_tiles(const IntLaunch& L, const PartPlan& pp
 hipError_t int_enqueue_dense_out(const IntLaunch& L, bool clear, bool blk_counted, hipStream_t s) {
   const uint32_t nb = (uint32_t)((L.R + kCompTile - 1) / kCompTile);
   if (!blk_counted) hipLaunchKernelGGL(k_dense_count, dim3(nb ? nb : 1), dim3(256), 0, s, L.dcnt, L.R, L.blk);
-  hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, s, L.blk, nb, L.n_out);
+  if (nb <= kScanOneMax) hipLaunchKernelGGL(k_scan_one, dim3(1), dim3(kScanOneWaves * kWave), 0, s, L.blk, nb, L.n_out);
+  else hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, s, L.blk, nb, L.n_out);
   switch (L.op) {
     case 0: hipLaunchKernelGGL(k_dense_write<0>, dim3(nb ? nb : 1), dim3(256), 0, s, L.dcnt, L.dval, L.R, L.blk, L.out_keys, L.out_vals, L.cap, clear); break;
     case 1: hipLaunchKernelGGL(k_dense_write<1>, dim3(nb ? nb : 1), dim3(256), 0, s, L.dcnt, L.dval, L.R, L.blk, L.out_keys, L.out_vals, L.cap, clear); break;
