@@ -743,13 +743,8 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const unsigned long long*
 #pragma unroll
     for (uint32_t e = 0; e < E; ++e) ones += (uint32_t)((k[e] >> (shift + bit)) & 1ull);
     const uint32_t zeros = E - ones;
-    // block exclusive scan of zeros
-    uint32_t inc = zeros;
-#pragma unroll
-    for (int o = 1; o < kWave; o <<= 1) {
-      const uint32_t t = __shfl_up(inc, o);
-      if (lane >= (uint32_t)o) inc += t;
-    }
+    // block exclusive scan of zeros (DPP lane shifts within the wave)
+    const uint32_t inc = wave_incl_scan(zeros);
     if (lane == kWave - 1) ws[wv] = inc;
     __syncthreads();
     uint32_t pre = 0, tot = 0;
