@@ -159,3 +159,15 @@ def test_mixed_kinds_on_one_job(torch):
         assert np.array_equal(h.cpu().numpy().astype(np.uint64), oracle.rgb(rgb))
         a, s, c, cent, st = j.kmeans(torch.from_numpy(X).cuda())
         assert int(c.sum()) == len(X)
+
+
+@pytest.mark.parametrize("n", [524_288, 524_289])
+def test_sort_at_the_one_workgroup_scan_limit(torch, n):
+    """The sort's digit histograms (256 digits x 2048-element tiles) are
+    scanned by one workgroup up to 65,536 entries: 524,288 pairs fill that
+    exactly (64 steps of 64 entries per wave), one more pair takes the
+    three-kernel scan."""
+    keys, vals = gen.u32_keys(31, n, 1 << 20, 1.0, with_values=True)
+    res = _run(torch, _job(STRATS["sort"]), keys, vals, "sum", 1 << 20)
+    assert res.stats["strategy_used"] == STRATS["sort"]
+    _check(res, keys, vals, "sum")
