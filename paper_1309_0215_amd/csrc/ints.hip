@@ -309,12 +309,7 @@ __global__ __launch_bounds__(kPartThreads) void k_part_tile(IntIn in, uint64_t R
     sum += c[q];
   }
   const uint32_t lane = lane_id(), wv = threadIdx.x / kWave;
-  uint32_t incl = sum;
-#pragma unroll
-  for (int o = 1; o < kWave; o <<= 1) {
-    const uint32_t y = (uint32_t)__shfl_up((int)incl, o);
-    if (lane >= (uint32_t)o) incl += y;
-  }
+  const uint32_t incl = wave_incl_scan(sum);
   if (lane == kWave - 1) wsum[wv] = incl;
   __syncthreads();
   uint32_t pre = 0, m = 0;
